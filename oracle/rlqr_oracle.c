@@ -1,0 +1,819 @@
+/*
+ * rlqr_oracle.c -- plain, slow FP64 CPU reference for dual-regularized LQR.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the oracle the GPU library is checked
+ * against. Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load it; the library never does. It shares no code with the
+ * HIP path.
+ *
+ * What it computes (arXiv 2509.16370, "Dual-Regularized Riccati Recursions
+ * for Interior-Point Optimal Control"):
+ *   - rlqr_oracle_seq: the sequential recursion of Section "Sequential
+ *     Algorithm" (Theorem "main-seq-theorem", the formulas for G, g, H, h,
+ *     K, k before eq. control-law, eq. value-fn-formulas, eqs. recover-x0,
+ *     recover-x, control-law and the y = P x + p rewriting at the end of the
+ *     proof), with Delta_i = delta * I.
+ *   - rlqr_oracle_par: the parallel algorithm of Section "Parallel
+ *     Algorithm" run serially: u-elimination (eqs. lqr-gpu-init-running,
+ *     lqr-gpu-init-terminal), reverse associative scan with the
+ *     single-inversion combine, p either from the scan's p-combine or from
+ *     the p-recurrence (Corollary "p-recurrence") as an affine reverse scan,
+ *     per-stage pivots and gains, and the forward affine-composition scan of
+ *     Section "Composing Affine Functions with Associative Scans".
+ *   - rlqr_oracle_residual: the stagewise residual of Section "Residual
+ *     Computation".
+ *
+ * Layout: row-major matrices, stage-stacked (see the C-ABI header). All
+ * arithmetic is double; loops are written out plainly, no blocking.
+ *
+ * Readings taken where the paper leaves a choice open:
+ *   - (I + delta P)^{-1} is applied through an unpivoted LDL^T of the
+ *     symmetric S_hat = I + delta P; its D entries are the state pivots of the
+ *     certificate (Section "Inertia Certification", inverse-free form).
+ *   - G_k is factored by unpivoted LDL^T; its D entries are the control pivots.
+ *   - W, G and P are symmetrized after being formed (the paper proves them
+ *     symmetric; rounding does not keep them so).
+ *   - The combine's single inverse (I + C P)^{-1} is applied by LU with
+ *     partial pivoting (the matrix is not symmetric; C may be singular).
+ *   - A pivot d is "zero" when |d| <= 1e3 * dim * eps64 * max|diag| of the
+ *     matrix being factored; the recursion then stops and returns 1.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_ZERO_PIVOT_FACTOR 1.0e3
+
+/* ------------------------------------------------------------ dense helpers */
+
+/* C[r x c] = A[r x k] * B[k x c] */
+static void mat_mul(int r, int k, int c, const double *A, const double *B, double *C) {
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < c; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += A[i * k + l] * B[l * c + j];
+      C[i * c + j] = s;
+    }
+}
+
+/* C[r x c] = A^T * B, A is [k x r], B is [k x c] */
+static void mat_tmul(int r, int k, int c, const double *A, const double *B, double *C) {
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < c; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += A[l * r + i] * B[l * c + j];
+      C[i * c + j] = s;
+    }
+}
+
+/* y[r] = A[r x c] x[c] */
+static void mat_vec(int r, int c, const double *A, const double *x, double *y) {
+  for (int i = 0; i < r; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < c; ++j) s += A[i * c + j] * x[j];
+    y[i] = s;
+  }
+}
+
+/* y[c] = A^T x, A is [r x c] */
+static void mat_tvec(int r, int c, const double *A, const double *x, double *y) {
+  for (int j = 0; j < c; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < r; ++i) s += A[i * c + j] * x[i];
+    y[j] = s;
+  }
+}
+
+static void symmetrize(int n, double *S) {
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double v = 0.5 * (S[i * n + j] + S[j * n + i]);
+      S[i * n + j] = v;
+      S[j * n + i] = v;
+    }
+}
+
+static double max_abs_diag(int n, const double *S) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s = fmax(s, fabs(S[i * n + i]));
+  return s;
+}
+
+/* Unpivoted LDL^T of symmetric S (n x n): unit lower L, diagonal D.
+ * Returns 0, or 1 when a pivot is zero in the sense stated above. */
+static int ldlt(int n, const double *S, double *L, double *D) {
+  double tol = ORACLE_ZERO_PIVOT_FACTOR * n * DBL_EPSILON * max_abs_diag(n, S);
+  for (int i = 0; i < n * n; ++i) L[i] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double d = S[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k] * D[k];
+    D[j] = d;
+    L[j * n + j] = 1.0;
+    if (!(fabs(d) > tol)) {
+      for (int k = j + 1; k < n; ++k) D[k] = NAN;
+      return 1;
+    }
+    for (int i = j + 1; i < n; ++i) {
+      double s = S[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k] * D[k];
+      L[i * n + j] = s / d;
+    }
+  }
+  return 0;
+}
+
+/* Solve (L D L^T) X = Bm in place; Bm is n x ncol row-major. */
+static void ldlt_solve(int n, int ncol, const double *L, const double *D, double *X) {
+  for (int c = 0; c < ncol; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = X[i * ncol + c];
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * X[k * ncol + c];
+      X[i * ncol + c] = s;
+    }
+    for (int i = 0; i < n; ++i) X[i * ncol + c] /= D[i];
+    for (int i = n - 1; i >= 0; --i) {
+      double s = X[i * ncol + c];
+      for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * X[k * ncol + c];
+      X[i * ncol + c] = s;
+    }
+  }
+}
+
+/* LU with partial pivoting of a general n x n matrix, in place. Returns 0 or 1 (singular). */
+static int lu_factor(int n, double *A, int *piv) {
+  for (int j = 0; j < n; ++j) {
+    int p = j;
+    double best = fabs(A[j * n + j]);
+    for (int i = j + 1; i < n; ++i)
+      if (fabs(A[i * n + j]) > best) { best = fabs(A[i * n + j]); p = i; }
+    piv[j] = p;
+    if (best == 0.0) return 1;
+    if (p != j)
+      for (int k = 0; k < n; ++k) { double t = A[j * n + k]; A[j * n + k] = A[p * n + k]; A[p * n + k] = t; }
+    for (int i = j + 1; i < n; ++i) {
+      double f = A[i * n + j] / A[j * n + j];
+      A[i * n + j] = f;
+      for (int k = j + 1; k < n; ++k) A[i * n + k] -= f * A[j * n + k];
+    }
+  }
+  return 0;
+}
+
+/* Solve A X = Bm with the LU above; Bm n x ncol row-major, in place. */
+static void lu_solve(int n, int ncol, const double *LU, const int *piv, double *X) {
+  for (int j = 0; j < n; ++j)
+    if (piv[j] != j)
+      for (int c = 0; c < ncol; ++c) {
+        double t = X[j * ncol + c]; X[j * ncol + c] = X[piv[j] * ncol + c]; X[piv[j] * ncol + c] = t;
+      }
+  for (int c = 0; c < ncol; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = X[i * ncol + c];
+      for (int k = 0; k < i; ++k) s -= LU[i * n + k] * X[k * ncol + c];
+      X[i * ncol + c] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = X[i * ncol + c];
+      for (int k = i + 1; k < n; ++k) s -= LU[i * n + k] * X[k * ncol + c];
+      X[i * ncol + c] = s / LU[i * n + i];
+    }
+  }
+}
+
+/* Solve A^T X = Bm with the LU of A (P A = L U  =>  A^T = U^T L^T P). */
+static void lu_solve_t(int n, int ncol, const double *LU, const int *piv, double *X) {
+  for (int c = 0; c < ncol; ++c) {
+    for (int i = 0; i < n; ++i) { /* U^T z = b */
+      double s = X[i * ncol + c];
+      for (int k = 0; k < i; ++k) s -= LU[k * n + i] * X[k * ncol + c];
+      X[i * ncol + c] = s / LU[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) { /* L^T w = z */
+      double s = X[i * ncol + c];
+      for (int k = i + 1; k < n; ++k) s -= LU[k * n + i] * X[k * ncol + c];
+      X[i * ncol + c] = s;
+    }
+  }
+  for (int j = n - 1; j >= 0; --j)
+    if (piv[j] != j)
+      for (int c = 0; c < ncol; ++c) {
+        double t = X[j * ncol + c]; X[j * ncol + c] = X[piv[j] * ncol + c]; X[piv[j] * ncol + c] = t;
+      }
+}
+
+static void fill_nan(double *p, size_t cnt) {
+  if (!p) return;
+  for (size_t i = 0; i < cnt; ++i) p[i] = NAN;
+}
+
+/* ------------------------------------------------------ sequential recursion */
+
+/*
+ * Sequential dual-regularized Riccati recursion (Section "Sequential
+ * Algorithm"). Inputs in the flat per-instance layout; optional outputs
+ * (pass NULL to skip): P (N+1) n n, p (N+1) n, K N m n, k N m,
+ * dS (N+1) n  = D of LDL^T(I + delta P_i)  (state pivots, i = 0..N),
+ * dG N m      = D of LDL^T(G_i)            (control pivots, i = 0..N-1).
+ * Returns 0, or 1 if a pivot was zero (solution then NaN).
+ */
+int rlqr_oracle_seq(int n, int m, int N, double delta,
+                    const double *Q, const double *M, const double *R,
+                    const double *A, const double *B,
+                    const double *q, const double *r, const double *c,
+                    double *x, double *u, double *y,
+                    double *Pout, double *pout, double *Kout, double *kout,
+                    double *dS, double *dG) {
+  const int nn = n * n, nm = n * m, mm = m * m;
+  double *P = malloc(sizeof(double) * (size_t)(N + 1) * nn);
+  double *p = malloc(sizeof(double) * (size_t)(N + 1) * n);
+  double *K = malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * nm);
+  double *kk = malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * m);
+  double *SL = malloc(sizeof(double) * (size_t)(N + 1) * nn); /* L of S_hat_i */
+  double *SD = malloc(sizeof(double) * (size_t)(N + 1) * n);  /* D of S_hat_i */
+  double *GD = malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * m);
+  double *Sh = malloc(sizeof(double) * nn), *W = malloc(sizeof(double) * nn);
+  double *WA = malloc(sizeof(double) * nn), *WB = malloc(sizeof(double) * nm);
+  double *G = malloc(sizeof(double) * mm), *GL = malloc(sizeof(double) * mm);
+  double *H = malloc(sizeof(double) * nm), *tmp = malloc(sizeof(double) * nn);
+  double *g = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * m);
+  double *v = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
+  int status = 0;
+
+  /* base case: P_N = Q_N, p_N = q_N */
+  memcpy(P + (size_t)N * nn, Q + (size_t)N * nn, sizeof(double) * nn);
+  memcpy(p + (size_t)N * n, q + (size_t)N * n, sizeof(double) * n);
+
+  for (int k = N - 1; k >= 0 && !status; --k) {
+    const double *Pn = P + (size_t)(k + 1) * nn, *pn = p + (size_t)(k + 1) * n;
+    const double *Ak = A + (size_t)k * nn, *Bk = B + (size_t)k * nm;
+    const double *Qk = Q + (size_t)k * nn, *Mk = M + (size_t)k * nm, *Rk = R + (size_t)k * mm;
+    const double *qk = q + (size_t)k * n, *rk = r + (size_t)k * m, *cn = c + (size_t)(k + 1) * n;
+
+    /* S_hat_{k+1} = I + delta P_{k+1}, factored */
+    for (int i = 0; i < nn; ++i) Sh[i] = delta * Pn[i];
+    for (int i = 0; i < n; ++i) Sh[i * n + i] += 1.0;
+    if (ldlt(n, Sh, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n)) { status = 1; break; }
+    /* W_{k+1} = P_{k+1} (I + delta P_{k+1})^{-1} = ((I + delta P)^{-1} P)^T */
+    memcpy(tmp, Pn, sizeof(double) * nn);
+    ldlt_solve(n, n, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n, tmp);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) W[i * n + j] = tmp[j * n + i];
+    symmetrize(n, W);
+
+    /* G_k = R_k + B^T W B,  H_k = B^T W A + M^T */
+    mat_mul(n, n, m, W, Bk, WB);
+    mat_tmul(m, n, m, Bk, WB, G);
+    for (int i = 0; i < mm; ++i) G[i] += Rk[i];
+    symmetrize(m, G);
+    mat_mul(n, n, n, W, Ak, WA);
+    mat_tmul(m, n, n, Bk, WA, H);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) H[i * n + j] += Mk[j * m + i];
+
+    /* g_{k+1} = p_{k+1} + W (c_{k+1} - delta p_{k+1}),  h_k = r_k + B^T g */
+    for (int i = 0; i < n; ++i) v[i] = cn[i] - delta * pn[i];
+    mat_vec(n, n, W, v, g);
+    for (int i = 0; i < n; ++i) g[i] += pn[i];
+    mat_tvec(n, m, Bk, g, h);
+    for (int i = 0; i < m; ++i) h[i] += rk[i];
+
+    /* K_k = -G^{-1} H,  k_k = -G^{-1} h */
+    if (ldlt(m, G, GL, GD + (size_t)k * m)) { status = 1; break; }
+    double *Kk = K + (size_t)k * nm, *kkk = kk + (size_t)k * m;
+    memcpy(Kk, H, sizeof(double) * nm);
+    ldlt_solve(m, n, GL, GD + (size_t)k * m, Kk);
+    for (int i = 0; i < nm; ++i) Kk[i] = -Kk[i];
+    memcpy(kkk, h, sizeof(double) * m);
+    ldlt_solve(m, 1, GL, GD + (size_t)k * m, kkk);
+    for (int i = 0; i < m; ++i) kkk[i] = -kkk[i];
+
+    /* P_k = A^T W A + Q + H^T K,  p_k = q + A^T g + H^T k */
+    double *Pk = P + (size_t)k * nn, *pk = p + (size_t)k * n;
+    mat_tmul(n, n, n, Ak, WA, Pk);
+    mat_tmul(n, m, n, H, Kk, tmp);
+    for (int i = 0; i < nn; ++i) Pk[i] += Qk[i] + tmp[i];
+    symmetrize(n, Pk);
+    mat_tvec(n, n, Ak, g, pk);
+    mat_tvec(m, n, H, kkk, w);
+    for (int i = 0; i < n; ++i) pk[i] += qk[i] + w[i];
+  }
+
+  if (!status) {
+    /* S_hat_0 = I + delta P_0 */
+    for (int i = 0; i < nn; ++i) Sh[i] = delta * P[i];
+    for (int i = 0; i < n; ++i) Sh[i * n + i] += 1.0;
+    if (ldlt(n, Sh, SL, SD)) status = 1;
+  }
+
+  if (!status) {
+    /* forward pass: x_0 = S_hat_0^{-1}(c_0 - delta p_0),
+       u_k = K_k x_k + k_k,
+       x_{k+1} = S_hat_{k+1}^{-1}(A x + B u + c_{k+1} - delta p_{k+1}),
+       y_k = P_k x_k + p_k */
+    for (int i = 0; i < n; ++i) x[i] = c[i] - delta * p[i];
+    ldlt_solve(n, 1, SL, SD, x);
+    for (int k = 0; k < N; ++k) {
+      const double *xk = x + (size_t)k * n;
+      double *uk = u + (size_t)k * m, *xn = x + (size_t)(k + 1) * n;
+      mat_vec(m, n, K + (size_t)k * nm, xk, uk);
+      for (int i = 0; i < m; ++i) uk[i] += kk[(size_t)k * m + i];
+      mat_vec(n, n, A + (size_t)k * nn, xk, v);
+      mat_vec(n, m, B + (size_t)k * nm, uk, w);
+      for (int i = 0; i < n; ++i)
+        xn[i] = v[i] + w[i] + c[(size_t)(k + 1) * n + i] - delta * p[(size_t)(k + 1) * n + i];
+      ldlt_solve(n, 1, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n, xn);
+    }
+    for (int k = 0; k <= N; ++k) {
+      mat_vec(n, n, P + (size_t)k * nn, x + (size_t)k * n, y + (size_t)k * n);
+      for (int i = 0; i < n; ++i) y[(size_t)k * n + i] += p[(size_t)k * n + i];
+    }
+  } else {
+    fill_nan(x, (size_t)(N + 1) * n); fill_nan(u, (size_t)N * m); fill_nan(y, (size_t)(N + 1) * n);
+  }
+
+  if (Pout) memcpy(Pout, P, sizeof(double) * (size_t)(N + 1) * nn);
+  if (pout) memcpy(pout, p, sizeof(double) * (size_t)(N + 1) * n);
+  if (Kout && N) memcpy(Kout, K, sizeof(double) * (size_t)N * nm);
+  if (kout && N) memcpy(kout, kk, sizeof(double) * (size_t)N * m);
+  if (dS) memcpy(dS, SD, sizeof(double) * (size_t)(N + 1) * n);
+  if (dG && N) memcpy(dG, GD, sizeof(double) * (size_t)N * m);
+
+  free(P); free(p); free(K); free(kk); free(SL); free(SD); free(GD);
+  free(Sh); free(W); free(WA); free(WB); free(G); free(GL); free(H); free(tmp);
+  free(g); free(h); free(v); free(w);
+  return status;
+}
+
+/* --------------------------------------------------------- parallel algorithm */
+
+/* Interval value-function element (P, p, A, C, c)_{i->j}. */
+typedef struct { double *P, *p, *A, *C, *c; } elem_t;
+
+static void elem_alloc(elem_t *e, int n) {
+  e->P = calloc((size_t)n * n, sizeof(double));
+  e->p = calloc((size_t)n, sizeof(double));
+  e->A = calloc((size_t)n * n, sizeof(double));
+  e->C = calloc((size_t)n * n, sizeof(double));
+  e->c = calloc((size_t)n, sizeof(double));
+}
+static void elem_free(elem_t *e) { free(e->P); free(e->p); free(e->A); free(e->C); free(e->c); }
+static void elem_copy(elem_t *d, const elem_t *s, int n) {
+  memcpy(d->P, s->P, sizeof(double) * n * n); memcpy(d->p, s->p, sizeof(double) * n);
+  memcpy(d->A, s->A, sizeof(double) * n * n); memcpy(d->C, s->C, sizeof(double) * n * n);
+  memcpy(d->c, s->c, sizeof(double) * n);
+}
+
+/*
+ * (i->j) combined with (j->k), eq. lqr-gpu-combo with the single-inversion
+ * form of P_{i->k}:  X = I + C_ij P_jk (one LU),
+ *   P_ik = A_ij^T P_jk X^{-1} A_ij + P_ij
+ *   p_ik = A_ij^T (I + P_jk C_ij)^{-1}(p_jk + P_jk c_ij) + p_ij,
+ *          with (I + P_jk C_ij)^{-1} = X^{-T} since P and C are symmetric
+ *   A_ik = A_jk X^{-1} A_ij
+ *   C_ik = A_jk X^{-1} C_ij A_jk^T + C_jk
+ *   c_ik = A_jk X^{-1}(c_ij - C_ij p_jk) + c_jk
+ * Returns 1 if X is singular.
+ */
+static int combine(int n, const elem_t *e1, const elem_t *e2, elem_t *o) {
+  const int nn = n * n;
+  double *X = malloc(sizeof(double) * nn), *T1 = malloc(sizeof(double) * nn);
+  double *T2 = malloc(sizeof(double) * nn), *v = malloc(sizeof(double) * n);
+  double *w = malloc(sizeof(double) * n);
+  int *piv = malloc(sizeof(int) * n);
+  int st = 0;
+  mat_mul(n, n, n, e1->C, e2->P, X);
+  for (int i = 0; i < n; ++i) X[i * n + i] += 1.0;
+  if (lu_factor(n, X, piv)) { st = 1; goto done; }
+  /* P_ik */
+  memcpy(T1, e1->A, sizeof(double) * nn);          /* X^{-1} A_ij */
+  lu_solve(n, n, X, piv, T1);
+  mat_mul(n, n, n, e2->P, T1, T2);                 /* P_jk X^{-1} A_ij */
+  mat_tmul(n, n, n, e1->A, T2, o->P);              /* A_ij^T (...) */
+  for (int i = 0; i < nn; ++i) o->P[i] += e1->P[i];
+  symmetrize(n, o->P);
+  /* A_ik = A_jk X^{-1} A_ij  (T1 = X^{-1} A_ij) */
+  mat_mul(n, n, n, e2->A, T1, o->A);
+  /* C_ik = A_jk X^{-1} C_ij A_jk^T + C_jk */
+  memcpy(T1, e1->C, sizeof(double) * nn);
+  lu_solve(n, n, X, piv, T1);                      /* X^{-1} C_ij */
+  mat_mul(n, n, n, e2->A, T1, T2);                 /* A_jk X^{-1} C_ij */
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < n; ++l) s += T2[i * n + l] * e2->A[j * n + l];
+      o->C[i * n + j] = s + e2->C[i * n + j];
+    }
+  symmetrize(n, o->C);
+  /* p_ik */
+  mat_vec(n, n, e2->P, e1->c, v);
+  for (int i = 0; i < n; ++i) v[i] += e2->p[i];
+  lu_solve_t(n, 1, X, piv, v);
+  mat_tvec(n, n, e1->A, v, o->p);
+  for (int i = 0; i < n; ++i) o->p[i] += e1->p[i];
+  /* c_ik */
+  mat_vec(n, n, e1->C, e2->p, v);
+  for (int i = 0; i < n; ++i) v[i] = e1->c[i] - v[i];
+  lu_solve(n, 1, X, piv, v);
+  mat_vec(n, n, e2->A, v, w);
+  for (int i = 0; i < n; ++i) o->c[i] = w[i] + e2->c[i];
+done:
+  free(X); free(T1); free(T2); free(v); free(w); free(piv);
+  return st;
+}
+
+/* Affine map v -> T v + t on R^n. */
+typedef struct { double *T, *t; } aff_t;
+
+/* outer o inner : v -> T_o (T_i v + t_i) + t_o. In the paper's notation
+ * f((a,B),(c,D)) = (D a + c, D B) with (a,B) = inner and (c,D) = outer. */
+static void aff_compose(int n, const aff_t *outer, const aff_t *inner, aff_t *o) {
+  double *T = malloc(sizeof(double) * n * n), *t = malloc(sizeof(double) * n);
+  mat_mul(n, n, n, outer->T, inner->T, T);
+  mat_vec(n, n, outer->T, inner->t, t);
+  for (int i = 0; i < n; ++i) t[i] += outer->t[i];
+  memcpy(o->T, T, sizeof(double) * n * n);
+  memcpy(o->t, t, sizeof(double) * n);
+  free(T); free(t);
+}
+
+/*
+ * Scans over L elements, run serially with a chosen bracketing:
+ *   bracketing 0: plain fold (one element at a time),
+ *   bracketing 1: Hillis-Steele rounds (distance 1, 2, 4, ...), every round
+ *                 reads only the previous round's values.
+ * Reverse scan of the interval elements: out_i = e_i (+) e_{i+1} (+) ... (+) e_{L-1}.
+ */
+static int reverse_scan_elems(int n, int L, elem_t *e, int bracketing) {
+  if (bracketing == 0) {
+    elem_t t; elem_alloc(&t, n);
+    for (int i = L - 2; i >= 0; --i) {
+      if (combine(n, &e[i], &e[i + 1], &t)) { elem_free(&t); return 1; }
+      elem_copy(&e[i], &t, n);
+    }
+    elem_free(&t);
+    return 0;
+  }
+  elem_t *old = malloc(sizeof(elem_t) * L);
+  for (int i = 0; i < L; ++i) elem_alloc(&old[i], n);
+  int st = 0;
+  for (int d = 1; d < L && !st; d *= 2) {
+    for (int i = 0; i < L; ++i) elem_copy(&old[i], &e[i], n);
+    for (int i = 0; i + d < L && !st; ++i) st = combine(n, &old[i], &old[i + d], &e[i]);
+  }
+  for (int i = 0; i < L; ++i) elem_free(&old[i]);
+  free(old);
+  return st;
+}
+
+/* Reverse scan of affine maps: out_i = F_i o F_{i+1} o ... o F_{L-1}. */
+static void reverse_scan_aff(int n, int L, aff_t *F, int bracketing) {
+  if (bracketing == 0) {
+    for (int i = L - 2; i >= 0; --i) aff_compose(n, &F[i], &F[i + 1], &F[i]);
+    return;
+  }
+  aff_t *old = malloc(sizeof(aff_t) * L);
+  for (int i = 0; i < L; ++i) { old[i].T = malloc(sizeof(double) * n * n); old[i].t = malloc(sizeof(double) * n); }
+  for (int d = 1; d < L; d *= 2) {
+    for (int i = 0; i < L; ++i) { memcpy(old[i].T, F[i].T, sizeof(double) * n * n); memcpy(old[i].t, F[i].t, sizeof(double) * n); }
+    for (int i = 0; i + d < L; ++i) aff_compose(n, &old[i], &old[i + d], &F[i]);
+  }
+  for (int i = 0; i < L; ++i) { free(old[i].T); free(old[i].t); }
+  free(old);
+}
+
+/* Forward scan of affine maps: out_i = F_i o F_{i-1} o ... o F_0. */
+static void forward_scan_aff(int n, int L, aff_t *F, int bracketing) {
+  if (bracketing == 0) {
+    for (int i = 1; i < L; ++i) aff_compose(n, &F[i], &F[i - 1], &F[i]);
+    return;
+  }
+  aff_t *old = malloc(sizeof(aff_t) * L);
+  for (int i = 0; i < L; ++i) { old[i].T = malloc(sizeof(double) * n * n); old[i].t = malloc(sizeof(double) * n); }
+  for (int d = 1; d < L; d *= 2) {
+    for (int i = 0; i < L; ++i) { memcpy(old[i].T, F[i].T, sizeof(double) * n * n); memcpy(old[i].t, F[i].t, sizeof(double) * n); }
+    for (int i = d; i < L; ++i) aff_compose(n, &old[i], &old[i - d], &F[i]);
+  }
+  for (int i = 0; i < L; ++i) { free(old[i].T); free(old[i].t); }
+  free(old);
+}
+
+/*
+ * Parallel dual-regularized Riccati, run serially (Section "Parallel Algorithm").
+ * bracketing: 0 fold, 1 Hillis-Steele rounds (applies to every scan).
+ * p_mode: 0 take p_i from the scan's p-combine, 1 recover p_i with the
+ *         p-recurrence (Corollary "p-recurrence") as a reverse affine scan.
+ * Same outputs as rlqr_oracle_seq. Requires every R_i to be invertible.
+ */
+int rlqr_oracle_par(int n, int m, int N, double delta,
+                    const double *Q, const double *M, const double *R,
+                    const double *A, const double *B,
+                    const double *q, const double *r, const double *c,
+                    int bracketing, int p_mode,
+                    double *x, double *u, double *y,
+                    double *Pout, double *pout, double *Kout, double *kout,
+                    double *dS, double *dG) {
+  const int nn = n * n, nm = n * m, mm = m * m, L = N + 1;
+  int status = 0;
+  elem_t *e = malloc(sizeof(elem_t) * L);
+  for (int i = 0; i < L; ++i) elem_alloc(&e[i], n);
+  double *Rf = malloc(sizeof(double) * mm), *RiMt = malloc(sizeof(double) * nm);
+  double *RiBt = malloc(sizeof(double) * nm), *Rir = malloc(sizeof(double) * m);
+  int *piv = malloc(sizeof(int) * (n > m ? n : m));
+
+  /* u-elimination: element (i -> i+1), eq. lqr-gpu-init-running */
+  for (int i = 0; i < N && !status; ++i) {
+    const double *Qi = Q + (size_t)i * nn, *Mi = M + (size_t)i * nm, *Ri = R + (size_t)i * mm;
+    const double *Ai = A + (size_t)i * nn, *Bi = B + (size_t)i * nm;
+    const double *qi = q + (size_t)i * n, *ri = r + (size_t)i * m, *cn = c + (size_t)(i + 1) * n;
+    memcpy(Rf, Ri, sizeof(double) * mm);
+    if (lu_factor(m, Rf, piv)) { status = 1; break; }
+    /* R^{-1} M^T  (m x n) */
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < n; ++b) RiMt[a * n + b] = Mi[b * m + a];
+    lu_solve(m, n, Rf, piv, RiMt);
+    /* R^{-1} B^T  (m x n) */
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < n; ++b) RiBt[a * n + b] = Bi[b * m + a];
+    lu_solve(m, n, Rf, piv, RiBt);
+    memcpy(Rir, ri, sizeof(double) * m);
+    lu_solve(m, 1, Rf, piv, Rir);
+    elem_t *ei = &e[i];
+    mat_mul(n, m, n, Mi, RiMt, ei->P);                 /* M R^{-1} M^T */
+    for (int a = 0; a < nn; ++a) ei->P[a] = Qi[a] - ei->P[a];
+    symmetrize(n, ei->P);
+    mat_vec(n, m, Mi, Rir, ei->p);
+    for (int a = 0; a < n; ++a) ei->p[a] = qi[a] - ei->p[a];
+    mat_mul(n, m, n, Bi, RiMt, ei->A);                 /* B R^{-1} M^T */
+    for (int a = 0; a < nn; ++a) ei->A[a] = Ai[a] - ei->A[a];
+    mat_mul(n, m, n, Bi, RiBt, ei->C);                 /* B R^{-1} B^T */
+    for (int a = 0; a < n; ++a) ei->C[a * n + a] += delta;
+    symmetrize(n, ei->C);
+    mat_vec(n, m, Bi, Rir, ei->c);
+    for (int a = 0; a < n; ++a) ei->c[a] = cn[a] - ei->c[a];
+  }
+  /* terminal element (N -> N+1), eq. lqr-gpu-init-terminal */
+  memcpy(e[N].P, Q + (size_t)N * nn, sizeof(double) * nn);
+  memcpy(e[N].p, q + (size_t)N * n, sizeof(double) * n);
+
+  double *P = malloc(sizeof(double) * (size_t)L * nn);
+  double *p = malloc(sizeof(double) * (size_t)L * n);
+  double *K = malloc(sizeof(double) * (size_t)(N ? N : 1) * nm);
+  double *kk = malloc(sizeof(double) * (size_t)(N ? N : 1) * m);
+  double *SL = malloc(sizeof(double) * (size_t)L * nn), *SD = malloc(sizeof(double) * (size_t)L * n);
+  double *Wn = malloc(sizeof(double) * (size_t)L * nn);   /* W_i, i = 1..N */
+  double *GD = malloc(sizeof(double) * (size_t)(N ? N : 1) * m);
+  double *GL = malloc(sizeof(double) * (size_t)(N ? N : 1) * mm);
+  double *Sh = malloc(sizeof(double) * nn), *tmp = malloc(sizeof(double) * nn);
+  double *G = malloc(sizeof(double) * mm), *H = malloc(sizeof(double) * nm);
+  double *WB = malloc(sizeof(double) * nm), *WA = malloc(sizeof(double) * nn);
+  double *v = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * m);
+
+  /* reverse scan: e_i (+) ... (+) e_N gives P_i = P_{i->N+1}, p_i = p_{i->N+1} */
+  if (!status) status = reverse_scan_elems(n, L, e, bracketing);
+  if (!status) {
+    for (int i = 0; i < L; ++i) {
+      memcpy(P + (size_t)i * nn, e[i].P, sizeof(double) * nn);
+      memcpy(p + (size_t)i * n, e[i].p, sizeof(double) * n);
+    }
+  }
+
+  /* per-stage pivots and feedback gains (independent over i) */
+  for (int i = 0; i <= N && !status; ++i) {
+    for (int a = 0; a < nn; ++a) Sh[a] = delta * P[(size_t)i * nn + a];
+    for (int a = 0; a < n; ++a) Sh[a * n + a] += 1.0;
+    if (ldlt(n, Sh, SL + (size_t)i * nn, SD + (size_t)i * n)) status = 1;
+  }
+  for (int i = 0; i < N && !status; ++i) {
+    const double *Pn = P + (size_t)(i + 1) * nn;
+    const double *Ai = A + (size_t)i * nn, *Bi = B + (size_t)i * nm, *Mi = M + (size_t)i * nm;
+    double *W = Wn + (size_t)(i + 1) * nn;
+    memcpy(tmp, Pn, sizeof(double) * nn);
+    ldlt_solve(n, n, SL + (size_t)(i + 1) * nn, SD + (size_t)(i + 1) * n, tmp);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) W[a * n + b] = tmp[b * n + a];
+    symmetrize(n, W);
+    mat_mul(n, n, m, W, Bi, WB);
+    mat_tmul(m, n, m, Bi, WB, G);
+    for (int a = 0; a < mm; ++a) G[a] += R[(size_t)i * mm + a];
+    symmetrize(m, G);
+    mat_mul(n, n, n, W, Ai, WA);
+    mat_tmul(m, n, n, Bi, WA, H);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < n; ++b) H[a * n + b] += Mi[b * m + a];
+    if (ldlt(m, G, GL + (size_t)i * mm, GD + (size_t)i * m)) { status = 1; break; }
+    double *Ki = K + (size_t)i * nm;
+    memcpy(Ki, H, sizeof(double) * nm);
+    ldlt_solve(m, n, GL + (size_t)i * mm, GD + (size_t)i * m, Ki);
+    for (int a = 0; a < nm; ++a) Ki[a] = -Ki[a];
+  }
+
+  if (!status && p_mode == 1) {
+    /* p-recurrence: p_i = q_i + K_i^T r_i + (A_i + B_i K_i)^T (p_{i+1} + W_{i+1}(c_{i+1} - delta p_{i+1}))
+       as the affine map p_{i+1} -> T_i p_{i+1} + t_i with
+       T_i = (A_i + B_i K_i)^T (I - delta W_{i+1}),
+       t_i = q_i + K_i^T r_i + (A_i + B_i K_i)^T W_{i+1} c_{i+1};
+       F_N is the constant map to q_N (T = 0, t = q_N). */
+    aff_t *F = malloc(sizeof(aff_t) * L);
+    double *Acl = malloc(sizeof(double) * nn), *ImW = malloc(sizeof(double) * nn);
+    for (int i = 0; i < L; ++i) { F[i].T = calloc((size_t)nn, sizeof(double)); F[i].t = calloc((size_t)n, sizeof(double)); }
+    for (int i = 0; i < N; ++i) {
+      const double *W = Wn + (size_t)(i + 1) * nn;
+      mat_mul(n, m, n, B + (size_t)i * nm, K + (size_t)i * nm, Acl);
+      for (int a = 0; a < nn; ++a) Acl[a] += A[(size_t)i * nn + a];
+      for (int a = 0; a < nn; ++a) ImW[a] = -delta * W[a];
+      for (int a = 0; a < n; ++a) ImW[a * n + a] += 1.0;
+      mat_tmul(n, n, n, Acl, ImW, F[i].T);
+      mat_vec(n, n, W, c + (size_t)(i + 1) * n, v);
+      mat_tvec(n, n, Acl, v, F[i].t);
+      mat_tvec(m, n, K + (size_t)i * nm, r + (size_t)i * m, w);
+      for (int a = 0; a < n; ++a) F[i].t[a] += q[(size_t)i * n + a] + w[a];
+    }
+    memcpy(F[N].t, q + (size_t)N * n, sizeof(double) * n);
+    reverse_scan_aff(n, L, F, bracketing);
+    for (int i = 0; i < L; ++i) memcpy(p + (size_t)i * n, F[i].t, sizeof(double) * n);
+    for (int i = 0; i < L; ++i) { free(F[i].T); free(F[i].t); }
+    free(F); free(Acl); free(ImW);
+  }
+
+  if (!status) {
+    /* k_i = -G_i^{-1}(r_i + B_i^T g_{i+1}),  g_{i+1} = p_{i+1} + W_{i+1}(c_{i+1} - delta p_{i+1}) */
+    for (int i = 0; i < N; ++i) {
+      const double *W = Wn + (size_t)(i + 1) * nn, *pn = p + (size_t)(i + 1) * n;
+      for (int a = 0; a < n; ++a) v[a] = c[(size_t)(i + 1) * n + a] - delta * pn[a];
+      mat_vec(n, n, W, v, w);
+      for (int a = 0; a < n; ++a) w[a] += pn[a];
+      mat_tvec(n, m, B + (size_t)i * nm, w, h);
+      for (int a = 0; a < m; ++a) h[a] += r[(size_t)i * m + a];
+      ldlt_solve(m, 1, GL + (size_t)i * mm, GD + (size_t)i * m, h);
+      for (int a = 0; a < m; ++a) kk[(size_t)i * m + a] = -h[a];
+    }
+    /* x_0 = S_hat_0^{-1}(c_0 - delta p_0); then x_{i+1} = F_i(x_i) with
+       F_i(x) = S_hat_{i+1}^{-1}(A_i + B_i K_i) x + S_hat_{i+1}^{-1}(B_i k_i + c_{i+1} - delta p_{i+1}),
+       composed by a forward affine scan and applied to x_0. */
+    for (int a = 0; a < n; ++a) x[a] = c[a] - delta * p[a];
+    ldlt_solve(n, 1, SL, SD, x);
+    if (N > 0) {
+      aff_t *F = malloc(sizeof(aff_t) * N);
+      for (int i = 0; i < N; ++i) {
+        F[i].T = malloc(sizeof(double) * nn); F[i].t = malloc(sizeof(double) * n);
+        mat_mul(n, m, n, B + (size_t)i * nm, K + (size_t)i * nm, F[i].T);
+        for (int a = 0; a < nn; ++a) F[i].T[a] += A[(size_t)i * nn + a];
+        ldlt_solve(n, n, SL + (size_t)(i + 1) * nn, SD + (size_t)(i + 1) * n, F[i].T);
+        mat_vec(n, m, B + (size_t)i * nm, kk + (size_t)i * m, F[i].t);
+        for (int a = 0; a < n; ++a)
+          F[i].t[a] += c[(size_t)(i + 1) * n + a] - delta * p[(size_t)(i + 1) * n + a];
+        ldlt_solve(n, 1, SL + (size_t)(i + 1) * nn, SD + (size_t)(i + 1) * n, F[i].t);
+      }
+      forward_scan_aff(n, N, F, bracketing);
+      for (int i = 0; i < N; ++i) {
+        mat_vec(n, n, F[i].T, x, v);
+        for (int a = 0; a < n; ++a) x[(size_t)(i + 1) * n + a] = v[a] + F[i].t[a];
+      }
+      for (int i = 0; i < N; ++i) { free(F[i].T); free(F[i].t); }
+      free(F);
+    }
+    for (int i = 0; i < N; ++i) {
+      mat_vec(m, n, K + (size_t)i * nm, x + (size_t)i * n, u + (size_t)i * m);
+      for (int a = 0; a < m; ++a) u[(size_t)i * m + a] += kk[(size_t)i * m + a];
+    }
+    for (int i = 0; i <= N; ++i) {
+      mat_vec(n, n, P + (size_t)i * nn, x + (size_t)i * n, y + (size_t)i * n);
+      for (int a = 0; a < n; ++a) y[(size_t)i * n + a] += p[(size_t)i * n + a];
+    }
+  } else {
+    fill_nan(x, (size_t)L * n); fill_nan(u, (size_t)N * m); fill_nan(y, (size_t)L * n);
+  }
+
+  if (Pout) memcpy(Pout, P, sizeof(double) * (size_t)L * nn);
+  if (pout) memcpy(pout, p, sizeof(double) * (size_t)L * n);
+  if (Kout && N) memcpy(Kout, K, sizeof(double) * (size_t)N * nm);
+  if (kout && N) memcpy(kout, kk, sizeof(double) * (size_t)N * m);
+  if (dS) memcpy(dS, SD, sizeof(double) * (size_t)L * n);
+  if (dG && N) memcpy(dG, GD, sizeof(double) * (size_t)N * m);
+
+  for (int i = 0; i < L; ++i) elem_free(&e[i]);
+  free(e); free(Rf); free(RiMt); free(RiBt); free(Rir); free(piv);
+  free(P); free(p); free(K); free(kk); free(SL); free(SD); free(Wn); free(GD); free(GL);
+  free(Sh); free(tmp); free(G); free(H); free(WB); free(WA); free(v); free(w); free(h);
+  return status;
+}
+
+/* Exposed for the associativity pin: one combine of two interval elements. */
+int rlqr_oracle_combine(int n,
+                        const double *P1, const double *p1, const double *A1, const double *C1, const double *c1,
+                        const double *P2, const double *p2, const double *A2, const double *C2, const double *c2,
+                        double *P, double *p, double *Ao, double *C, double *co) {
+  elem_t e1 = {(double *)P1, (double *)p1, (double *)A1, (double *)C1, (double *)c1};
+  elem_t e2 = {(double *)P2, (double *)p2, (double *)A2, (double *)C2, (double *)c2};
+  elem_t o; elem_alloc(&o, n);
+  int st = combine(n, &e1, &e2, &o);
+  memcpy(P, o.P, sizeof(double) * n * n); memcpy(p, o.p, sizeof(double) * n);
+  memcpy(Ao, o.A, sizeof(double) * n * n); memcpy(C, o.C, sizeof(double) * n * n);
+  memcpy(co, o.c, sizeof(double) * n);
+  elem_free(&o);
+  return st;
+}
+
+/* ------------------------------------------------------------------ residual */
+
+/*
+ * Residual of the first-order conditions at (x, u, y) (Section "Residual
+ * Computation"), written into res in this order:
+ *   stage blocks i = 0..N-1:  [Q_i x_i + M_i u_i + A_i^T y_{i+1} + q_i - y_i ;
+ *                              M_i^T x_i + R_i u_i + B_i^T y_{i+1} + r_i]   (n + m each)
+ *   terminal block:           Q_N x_N + q_N - y_N                          (n)
+ *   c_0 - delta y_0 - x_0                                                   (n)
+ *   A_i x_i + B_i u_i + c_{i+1} - delta y_{i+1} - x_{i+1}, i = 0..N-1       (n each)
+ * Length N(n+m) + n + (N+1)n.
+ */
+void rlqr_oracle_residual(int n, int m, int N, double delta,
+                          const double *Q, const double *M, const double *R,
+                          const double *A, const double *B,
+                          const double *q, const double *r, const double *c,
+                          const double *x, const double *u, const double *y,
+                          double *res) {
+  const int nn = n * n, nm = n * m, mm = m * m;
+  size_t o = 0;
+  for (int i = 0; i < N; ++i) {
+    const double *xi = x + (size_t)i * n, *ui = u + (size_t)i * m;
+    const double *yi = y + (size_t)i * n, *yn = y + (size_t)(i + 1) * n;
+    for (int a = 0; a < n; ++a) {
+      double s = q[(size_t)i * n + a] - yi[a];
+      for (int b = 0; b < n; ++b) s += Q[(size_t)i * nn + a * n + b] * xi[b];
+      for (int b = 0; b < m; ++b) s += M[(size_t)i * nm + a * m + b] * ui[b];
+      for (int b = 0; b < n; ++b) s += A[(size_t)i * nn + b * n + a] * yn[b];
+      res[o++] = s;
+    }
+    for (int a = 0; a < m; ++a) {
+      double s = r[(size_t)i * m + a];
+      for (int b = 0; b < n; ++b) s += M[(size_t)i * nm + b * m + a] * xi[b];
+      for (int b = 0; b < m; ++b) s += R[(size_t)i * mm + a * m + b] * ui[b];
+      for (int b = 0; b < n; ++b) s += B[(size_t)i * nm + b * m + a] * yn[b];
+      res[o++] = s;
+    }
+  }
+  for (int a = 0; a < n; ++a) {
+    double s = q[(size_t)N * n + a] - y[(size_t)N * n + a];
+    for (int b = 0; b < n; ++b) s += Q[(size_t)N * nn + a * n + b] * x[(size_t)N * n + b];
+    res[o++] = s;
+  }
+  for (int a = 0; a < n; ++a) res[o++] = c[a] - delta * y[a] - x[a];
+  for (int i = 0; i < N; ++i) {
+    const double *xi = x + (size_t)i * n, *ui = u + (size_t)i * m;
+    for (int a = 0; a < n; ++a) {
+      double s = c[(size_t)(i + 1) * n + a] - delta * y[(size_t)(i + 1) * n + a] - x[(size_t)(i + 1) * n + a];
+      for (int b = 0; b < n; ++b) s += A[(size_t)i * nn + a * n + b] * xi[b];
+      for (int b = 0; b < m; ++b) s += B[(size_t)i * nm + a * m + b] * ui[b];
+      res[o++] = s;
+    }
+  }
+}
+
+/* ------------------------------------------------------------- batch driver */
+
+/*
+ * Runs rlqr_oracle_seq over a packed batch (offsets are the exclusive
+ * prefix sums of the per-instance element counts, one int64[B+1] per array),
+ * instances spread over threads. status[b] receives the per-instance return.
+ * Returns the number of threads used.
+ */
+int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
+                          const double *delta,
+                          const double *Q, const double *M, const double *R,
+                          const double *A, const double *B,
+                          const double *q, const double *r, const double *c,
+                          const long long *oQ, const long long *oM, const long long *oR,
+                          const long long *oA, const long long *oB,
+                          const long long *oq, const long long *or_, const long long *oc,
+                          const long long *ox, const long long *ou, const long long *oy,
+                          double *x, double *u, double *y, int *status, int nthreads) {
+  int used = 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+  {
+#pragma omp single
+    used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 1)
+    for (int b = 0; b < batch; ++b)
+      status[b] = rlqr_oracle_seq(nx[b], nu[b], N[b], delta[b],
+                                  Q + oQ[b], M + oM[b], R + oR[b], A + oA[b], B + oB[b],
+                                  q + oq[b], r + or_[b], c + oc[b],
+                                  x + ox[b], u + ou[b], y + oy[b],
+                                  NULL, NULL, NULL, NULL, NULL, NULL);
+  }
+#else
+  (void)nthreads;
+  for (int b = 0; b < batch; ++b)
+    status[b] = rlqr_oracle_seq(nx[b], nu[b], N[b], delta[b],
+                                Q + oQ[b], M + oM[b], R + oR[b], A + oA[b], B + oB[b],
+                                q + oq[b], r + or_[b], c + oc[b],
+                                x + ox[b], u + ou[b], y + oy[b],
+                                NULL, NULL, NULL, NULL, NULL, NULL);
+#endif
+  return used;
+}

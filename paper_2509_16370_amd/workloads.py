@@ -1,0 +1,214 @@
+"""Seeded synthetic inputs for dual-regularized LQR problems.
+
+This module only draws random problem data and packs it into the flat layout
+that both the C-ABI library and the CPU oracle read. It holds none of the
+solver's arithmetic (no Riccati step, no residual, no pivot test), so the GPU
+path and the oracle can share it without sharing any of the method.
+
+Problem data follow the dual-regularized LQR definition (Section "Dual-Regularized
+LQR", Definition 1): stage blocks Q_i (n x n), M_i (n x m), R_i (m x m),
+q_i, r_i, dynamics A_i (n x n), B_i (n x m), offsets c_0 .. c_N and the
+regularization Delta_i = delta * I.
+
+Flat layout (per instance, instances packed one after another, float64):
+
+    Q : (N+1) * n * n     stage i is a row-major n x n block
+    M : N * n * m         row-major n x m (cost term x^T M u)
+    R : N * m * m
+    A : N * n * n
+    B : N * n * m
+    q : (N+1) * n
+    r : N * m
+    c : (N+1) * n         c[0] is the initial-state target c_0,
+                          c[i+1] the offset of the dynamics of step i
+    x : (N+1) * n,  u : N * m,  y : (N+1) * n      (solution)
+
+The element counts per instance are given by `counts(N, n, m)`; offsets are
+exclusive prefix sums of those counts over the batch.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+ARRAYS_LHS = ("Q", "M", "R", "A", "B")
+ARRAYS_RHS = ("q", "r", "c")
+ARRAYS_SOL = ("x", "u", "y")
+ALL_ARRAYS = ARRAYS_LHS + ARRAYS_RHS + ARRAYS_SOL
+
+
+def counts(N: int, n: int, m: int) -> Dict[str, int]:
+    """Number of float64 elements each array holds for one instance."""
+    return {
+        "Q": (N + 1) * n * n, "M": N * n * m, "R": N * m * m,
+        "A": N * n * n, "B": N * n * m,
+        "q": (N + 1) * n, "r": N * m, "c": (N + 1) * n,
+        "x": (N + 1) * n, "u": N * m, "y": (N + 1) * n,
+    }
+
+
+@dataclasses.dataclass
+class Instance:
+    """One dual-regularized LQR instance; arrays are stage-stacked."""
+    n: int
+    m: int
+    N: int
+    delta: float
+    Q: np.ndarray  # (N+1, n, n)
+    M: np.ndarray  # (N, n, m)
+    R: np.ndarray  # (N, m, m)
+    A: np.ndarray  # (N, n, n)
+    B: np.ndarray  # (N, n, m)
+    q: np.ndarray  # (N+1, n)
+    r: np.ndarray  # (N, m)
+    c: np.ndarray  # (N+1, n)
+    indefinite: bool = False
+
+
+def _rng(seed: Sequence[int]) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(seed))))
+
+
+def _haar_orthogonal(rng: np.random.Generator, N: int, n: int) -> np.ndarray:
+    g = rng.standard_normal((N, n, n))
+    qm, rm = np.linalg.qr(g)
+    s = np.sign(np.diagonal(rm, axis1=1, axis2=2))
+    s[s == 0] = 1.0
+    return qm * s[:, None, :]
+
+
+def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
+                  indefinite: bool = False) -> Instance:
+    """Draw one instance with the stage recipe of the small single-instance workload.
+
+    Recipe (all draws independent per stage, in this order):
+      A_i = 0.95 * Haar-orthogonal + 0.05 * N(0,1)/sqrt(n)
+      B_i ~ N(0,1)/sqrt(m)
+      Q_i = W W^T / n + 1e-2 I,  W ~ N(0,1)   (i = 0..N, Q_N by the same recipe)
+      R_i = V V^T / m + 1e-1 I,  V ~ N(0,1)
+      M_i ~ N(0, 0.01^2)
+      q_i ~ N(0,1) (i = 0..N),  r_i ~ N(0,1)
+      c_0 ~ N(0,1),  c_1..c_N ~ N(0, 0.1^2)
+    With indefinite=True every Q_i is shifted by -0.5 * lambda_max(Q_i) I.
+    """
+    rng = _rng(seed)
+    A = 0.95 * _haar_orthogonal(rng, N, n) + 0.05 * rng.standard_normal((N, n, n)) / np.sqrt(n)
+    B = rng.standard_normal((N, n, m)) / np.sqrt(m)
+    W = rng.standard_normal((N + 1, n, n))
+    Q = W @ np.swapaxes(W, 1, 2) / n + 1e-2 * np.eye(n)
+    V = rng.standard_normal((N, m, m))
+    R = V @ np.swapaxes(V, 1, 2) / m + 1e-1 * np.eye(m)
+    M = 0.01 * rng.standard_normal((N, n, m))
+    q = rng.standard_normal((N + 1, n))
+    r = rng.standard_normal((N, m))
+    c = np.empty((N + 1, n))
+    c[0] = rng.standard_normal(n)
+    c[1:] = 0.1 * rng.standard_normal((N, n))
+    if indefinite:
+        lmax = np.linalg.eigvalsh(Q)[:, -1]
+        Q = Q - 0.5 * lmax[:, None, None] * np.eye(n)
+    # exact symmetry of the symmetric blocks
+    Q = 0.5 * (Q + np.swapaxes(Q, 1, 2))
+    R = 0.5 * (R + np.swapaxes(R, 1, 2))
+    return Instance(n, m, N, float(delta), Q, M, R, A, B, q, r, c, indefinite)
+
+
+# ---------------------------------------------------------------- workloads
+
+def single_small(run: int = 0) -> List[Instance]:
+    """One instance, n=4, m=2, N=32, delta=1e-6."""
+    return [make_instance(4, 2, 32, 1e-6, (0, 0, run))]
+
+
+def batched_uniform(batch: int = 4096, n: int = 12, m: int = 4, N: int = 128,
+                    delta: float = 1e-8, run: int = 0) -> List[Instance]:
+    """Uniform batch (quadrotor-sized: n=12, m=4, N=128), per-instance seeds."""
+    return [make_instance(n, m, N, delta, (1, b, run)) for b in range(batch)]
+
+
+def batched_ragged(batch: int = 1024, delta: float = 1e-4, run: int = 0,
+                   n_choices=(8, 16, 32), m_choices=(2, 4, 8), N_range=(50, 1000),
+                   indefinite_frac: float = 0.2) -> List[Instance]:
+    """Ragged batch: N ~ U{50..1000}, n and m uniform over the choices,
+    round(0.2*batch) instances (seeded permutation) with indefinite Q."""
+    rng = _rng((2, 1 << 20, run))
+    Ns = rng.integers(N_range[0], N_range[1] + 1, size=batch)
+    ns = rng.choice(np.asarray(n_choices), size=batch)
+    ms = rng.choice(np.asarray(m_choices), size=batch)
+    n_indef = int(round(indefinite_frac * batch))
+    indef = np.zeros(batch, dtype=bool)
+    indef[rng.permutation(batch)[:n_indef]] = True
+    return [make_instance(int(ns[b]), int(ms[b]), int(Ns[b]), delta, (2, b, run),
+                          indefinite=bool(indef[b])) for b in range(batch)]
+
+
+def long_horizon(N: int = 16384, n: int = 64, m: int = 32, delta: float = 1e-6,
+                 run: int = 0) -> List[Instance]:
+    """One long-horizon instance (n=64, m=32, N=16384 at full size)."""
+    return [make_instance(n, m, N, delta, (3, 0, run))]
+
+
+# ---------------------------------------------------------------- packing
+
+@dataclasses.dataclass
+class Packed:
+    """A batch in the flat layout: shapes (int32) + one float64 array per name."""
+    N: np.ndarray
+    n: np.ndarray
+    m: np.ndarray
+    delta: np.ndarray
+    arrays: Dict[str, np.ndarray]
+    offsets: Dict[str, np.ndarray]  # name -> int64[B+1]
+
+    @property
+    def batch(self) -> int:
+        return int(self.N.shape[0])
+
+    def stage_count(self) -> int:
+        return int(self.N.sum())
+
+
+def layout_offsets(N, n, m) -> Dict[str, np.ndarray]:
+    N = np.asarray(N, dtype=np.int64)
+    n = np.asarray(n, dtype=np.int64)
+    m = np.asarray(m, dtype=np.int64)
+    per = {
+        "Q": (N + 1) * n * n, "M": N * n * m, "R": N * m * m,
+        "A": N * n * n, "B": N * n * m,
+        "q": (N + 1) * n, "r": N * m, "c": (N + 1) * n,
+        "x": (N + 1) * n, "u": N * m, "y": (N + 1) * n,
+    }
+    out = {}
+    for k, v in per.items():
+        o = np.zeros(len(N) + 1, dtype=np.int64)
+        np.cumsum(v, out=o[1:])
+        out[k] = o
+    return out
+
+
+def pack(instances: List[Instance]) -> Packed:
+    N = np.array([i.N for i in instances], dtype=np.int32)
+    n = np.array([i.n for i in instances], dtype=np.int32)
+    m = np.array([i.m for i in instances], dtype=np.int32)
+    delta = np.array([i.delta for i in instances], dtype=np.float64)
+    offs = layout_offsets(N, n, m)
+    arrays = {}
+    for name in ARRAYS_LHS + ARRAYS_RHS:
+        arrays[name] = np.concatenate(
+            [getattr(i, name).reshape(-1) for i in instances]).astype(np.float64)
+        assert arrays[name].shape[0] == offs[name][-1]
+    return Packed(N, n, m, delta, arrays, offs)
+
+
+def unpack_solution(p: Packed, x: np.ndarray, u: np.ndarray, y: np.ndarray):
+    """Split flat x, u, y into per-instance (N+1,n), (N,m), (N+1,n) arrays."""
+    out = []
+    for b in range(p.batch):
+        N, n, m = int(p.N[b]), int(p.n[b]), int(p.m[b])
+        ox, ou, oy = p.offsets["x"][b], p.offsets["u"][b], p.offsets["y"][b]
+        out.append((x[ox:ox + (N + 1) * n].reshape(N + 1, n),
+                    u[ou:ou + N * m].reshape(N, m),
+                    y[oy:oy + (N + 1) * n].reshape(N + 1, n)))
+    return out
