@@ -1,0 +1,181 @@
+/*
+ * rlqr.h -- C ABI of the MI355X dual-regularized LQR solver.
+ *
+ * The library solves batches of dual-regularized LQR problems (Definition in
+ * Section "Dual-Regularized LQR" of arXiv 2509.16370): for each instance it
+ * returns the unique solution (x, u, y) of the first-order conditions
+ *
+ *     [[P, C^T], [C, -Delta]] [x; y] = -[s; c]       (eq. primal-dual-linear-system)
+ *
+ * with the stagewise blocks of eq. optimal-control-specialization and
+ * Delta_i = delta * I for i = 0..N. The call split follows the paper's
+ * factorization / solve / residual callbacks (Section "Software
+ * Contributions"): one factorization serves any number of right-hand sides.
+ *
+ * Memory. Every array argument is a DEVICE pointer owned by the caller unless
+ * it is marked [host]. Scalars and matrices are float64, row-major. The handle
+ * owns its workspace, allocated once by rlqr_create; no other call allocates
+ * device memory.
+ *
+ * Layout of a batch (instances packed one after another; per instance the
+ * arrays are stage-stacked):
+ *     Q (N+1)*n*n   M N*n*m   R N*m*m   A N*n*n   B N*n*m
+ *     q (N+1)*n     r N*m     c (N+1)*n   (c[0] = c_0, c[i+1] offset of step i)
+ *     x (N+1)*n     u N*m     y (N+1)*n
+ *     residual  N*(n+m) + n + (N+1)*n  (order given at rlqr_residual)
+ * Instance b's block of array k starts at the exclusive prefix sum of the
+ * per-instance element counts; rlqr_layout_offsets returns those offsets.
+ *
+ * Streams. Calls are ordered on the given stream (a hipStream_t passed as
+ * void*; NULL means the default stream) and return before the GPU finishes.
+ * A handle must not be used from two streams at once.
+ *
+ * Errors. Whole-call failures return a negative rlqr_status and leave outputs
+ * untouched; no call aborts or throws. Per-instance outcomes are reported in
+ * inst_status (RLQR_INST_*).
+ */
+#ifndef RLQR_H
+#define RLQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlqr_handle rlqr_handle;
+typedef void *rlqr_stream; /* hipStream_t */
+
+typedef enum {
+  RLQR_OK = 0,
+  RLQR_E_INVALID = -1,     /* bad argument: NULL pointer, shape out of range, unknown mode */
+  RLQR_E_NOMEM = -2,       /* workspace allocation failed */
+  RLQR_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  RLQR_E_STATE = -4,       /* call order: solve/inertia/residual before factor */
+  RLQR_E_UNSUPPORTED = -5  /* mode not available for these shapes */
+} rlqr_status;
+
+typedef enum {
+  /* Sequential recursion (Section "Sequential Algorithm"), every product and
+     pivot in float64. */
+  RLQR_SEQ_FP64 = 0,
+  /* Sequential recursion with float32 matrix products and float64 pivot
+     factorizations; rlqr_solve refines against the float64 residual. */
+  RLQR_SEQ_MIXED = 1
+} rlqr_mode;
+
+/* per-instance outcome written by rlqr_solve */
+enum {
+  RLQR_INST_OK = 0,             /* solved to rel_tol, pivot certificate holds  */
+  RLQR_INST_NOT_PD = 1,         /* solved to rel_tol, certificate fails (wrong inertia) */
+  RLQR_INST_SINGULAR = 2,       /* a pivot is zero; x, u, y are NaN             */
+  RLQR_INST_NOT_CONVERGED = 3   /* relative residual above rel_tol after max_refine steps */
+};
+
+/* array identifiers for rlqr_layout_offsets */
+enum {
+  RLQR_ARR_Q = 0, RLQR_ARR_M, RLQR_ARR_R, RLQR_ARR_A, RLQR_ARR_B,
+  RLQR_ARR_q, RLQR_ARR_r, RLQR_ARR_c, RLQR_ARR_x, RLQR_ARR_u, RLQR_ARR_y,
+  RLQR_ARR_RES, RLQR_ARR_COUNT
+};
+
+typedef struct {
+  int32_t batch;        /* number of instances B >= 0                          */
+  const int32_t *N;     /* [host][B] horizon, N >= 0                            */
+  const int32_t *nx;    /* [host][B] state size n, 1 <= n                       */
+  const int32_t *nu;    /* [host][B] control size m, 1 <= m; n <= 64, n + m <= 96 */
+} rlqr_shape;
+
+typedef struct {        /* left-hand side: stage blocks and regularization       */
+  const double *Q, *M, *R, *A, *B;
+  const double *delta;  /* [B] delta_b >= 0; Delta_i = delta_b * I, i = 0..N    */
+} rlqr_lhs;
+
+typedef struct { const double *q, *r, *c; } rlqr_rhs;   /* s = (q_0, r_0, ..., q_N), c */
+typedef struct { double *x, *u, *y; } rlqr_sol;
+
+/* Largest n and n + m the kernels accept. */
+#define RLQR_MAX_NX 64
+#define RLQR_MAX_NXU 96
+
+/*
+ * Create a handle for a fixed batch of shapes and one mode; allocates the
+ * factor workspace (the only allocation the library makes). The shape arrays
+ * are copied. *workspace_bytes (may be NULL) receives the device bytes held.
+ * Errors: RLQR_E_INVALID (NULL h/s, batch < 0, a shape out of range, unknown
+ * mode), RLQR_E_NOMEM, RLQR_E_HIP. On error *h is set to NULL.
+ */
+rlqr_status rlqr_create(rlqr_handle **h, const rlqr_shape *s, rlqr_mode mode,
+                        size_t *workspace_bytes);
+
+/* Write the B+1 exclusive prefix offsets (in float64 elements) of array `array`
+ * (RLQR_ARR_*) to off [host]. Errors: RLQR_E_INVALID. */
+rlqr_status rlqr_layout_offsets(const rlqr_handle *h, int32_t array, int64_t *off);
+
+/*
+ * Factor the left-hand side: the backward Riccati recursion of Section
+ * "Sequential Algorithm" (S_hat_{k+1} = I + delta P_{k+1}, W_{k+1} =
+ * P_{k+1} S_hat_{k+1}^{-1}, G_k = R_k + B_k^T W B_k, H_k = B_k^T W A_k + M_k^T,
+ * K_k = -G_k^{-1} H_k, P_k = A_k^T W A_k + Q_k + H_k^T K_k, P_N = Q_N) for every
+ * instance, recording the pivots of S_hat_i (i = 0..N) and G_i (i = 0..N-1)
+ * for the certificate. The lhs arrays must stay valid and unchanged until the
+ * last rlqr_solve/rlqr_residual on this factorization, which re-read them.
+ * Errors: RLQR_E_INVALID (NULL pointer), RLQR_E_HIP.
+ */
+rlqr_status rlqr_factor(rlqr_handle *h, const rlqr_lhs *lhs, rlqr_stream st);
+
+/*
+ * Solve for one right-hand side with the current factorization: backward
+ * vector pass (g, h, k_k, p_k), forward rollout x_0 = S_hat_0^{-1}(c_0 -
+ * delta p_0), u_k = K_k x_k + k_k, x_{k+1} = S_hat_{k+1}^{-1}(A_k x_k + B_k u_k
+ * + c_{k+1} - delta p_{k+1}), y_k = P_k x_k + p_k (Theorem "main-seq-theorem").
+ * Then up to max_refine steps of iterative refinement against the float64
+ * residual of Section "Residual Computation": z <- z + solve(residual),
+ * per instance until ||residual||_inf <= rel_tol * ||[s; c]||_inf.
+ * inst_status [B] (RLQR_INST_*) and inst_relres [B] (final relative residual)
+ * may be NULL. Errors: RLQR_E_INVALID, RLQR_E_STATE (no factorization),
+ * RLQR_E_HIP.
+ */
+rlqr_status rlqr_solve(rlqr_handle *h, const rlqr_rhs *rhs, rlqr_sol *out,
+                       double rel_tol, int32_t max_refine,
+                       int32_t *inst_status, double *inst_relres, rlqr_stream st);
+
+/*
+ * Pivot certificate of Theorem "riccati-inertia-certification-theorem":
+ * pd_verdict[b] = 1 iff every pivot of every S_hat_i and G_i is positive, i.e.
+ * iff the KKT matrix has inertia (N(n+m)+n, (N+1)n, 0). first_bad[b] is the
+ * first failing pivot in elimination order (S_hat_N, G_{N-1}, S_hat_{N-1},
+ * ..., G_0, S_hat_0), coded 2i for S_hat_i and 2i+1 for G_i, or -1.
+ * inertia[3b..3b+2] = (0, (N+1)n, 0) + the sign counts of all pivots; a pivot
+ * with |d| <= 1e3 * dim * eps64 * max|diag| of its matrix counts as zero.
+ * Any output pointer may be NULL. Errors: RLQR_E_STATE, RLQR_E_HIP.
+ */
+rlqr_status rlqr_pivot_inertia(rlqr_handle *h, int32_t *pd_verdict, int32_t *first_bad,
+                               int64_t *inertia, rlqr_stream st);
+
+/*
+ * Float64 residual of the first-order conditions at z = (x, u, y) (Section
+ * "Residual Computation"), written per instance in this order:
+ *   for i < N: Q_i x_i + M_i u_i + A_i^T y_{i+1} + q_i - y_i      (n)
+ *              M_i^T x_i + R_i u_i + B_i^T y_{i+1} + r_i          (m)
+ *   Q_N x_N + q_N - y_N                                            (n)
+ *   c_0 - delta y_0 - x_0                                          (n)
+ *   for i < N: A_i x_i + B_i u_i + c_{i+1} - delta y_{i+1} - x_{i+1} (n)
+ * res may be NULL (then only inst_relres); inst_relres [B] receives
+ * ||res||_inf / ||[s; c]||_inf and may be NULL. Uses the lhs of the last
+ * rlqr_factor. Errors: RLQR_E_INVALID, RLQR_E_STATE, RLQR_E_HIP.
+ */
+rlqr_status rlqr_residual(rlqr_handle *h, const rlqr_rhs *rhs, const rlqr_sol *z,
+                          double *res, double *inst_relres, rlqr_stream st);
+
+/* Release the handle and its workspace (waits for the device). NULL is a no-op. */
+void rlqr_destroy(rlqr_handle *h);
+
+/* Static description of a status code. */
+const char *rlqr_status_string(rlqr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLQR_H */

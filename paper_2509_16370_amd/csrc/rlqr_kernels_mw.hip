@@ -1,0 +1,717 @@
+// rlqr_kernels_mw.hip -- the sequential dual-regularized Riccati recursion for
+// larger stages (n + m > 16): one workgroup of NW wavefronts per instance.
+//
+// Same per-stage algebra as the one-wavefront kernels (Section "Sequential
+// Algorithm" of arXiv 2509.16370): sweep S_hat = I + delta P, W = -P X,
+// T = W [A B], Z = [A B]^T T + Hessian, sweep the control pivots of Z. The
+// state tiles (P, X = -S_hat^{-1}, W) are NX x NX with NX = 16 TX >= n; the
+// stage tiles (Z) are NZ x NZ with NZ = 16 TZ >= n + m. Every tile is split in
+// 16 x 16 blocks dealt round-robin to the wavefronts; Z blocks are numbered so
+// that the state block (I, J), I, J < TX, of Z has the index of block (I, J)
+// of the state tiles -- the wavefront that owns a block of Z_xx therefore
+// also owns the same block of P for the next stage.
+//
+// Pivot sweeps broadcast each pivot column through LDS with one workgroup
+// barrier per pivot. Workspace per stage: TZ^2 + TX^2 blocks (Z, then X).
+#include "rlqr_device.h"
+#include "rlqr_internal.h"
+
+namespace rlqr {
+
+template <int TX, int TZ>
+__device__ __forceinline__ void zmap(int z, int& I, int& J) {
+  if (z < TX * TX) {
+    I = z / TX;
+    J = z % TX;
+    return;
+  }
+  int e = z - TX * TX;
+  if (TZ > TX && e < TX * (TZ - TX)) {
+    I = e / (TZ - TX);
+    J = TX + e % (TZ - TX);
+    return;
+  }
+  e -= TX * (TZ - TX);
+  I = TX + e / TZ;
+  J = e % TZ;
+}
+
+// C block (I, J) = op(A) * B over KB 16-blocks of the inner dimension.
+template <typename T, bool TRANS_A, int KB>
+__device__ __forceinline__ typename AccT<T>::type gemm_blk(const T* sa, int lda, const T* sb, int ldb,
+                                                           int I, int J, int lane) {
+  typename AccT<T>::type acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 16 * kb + 4 * kk + kq;
+      const T av = TRANS_A ? sa[k * lda + 16 * I + i] : sa[(16 * I + i) * lda + k];
+      const T bv = sb[k * ldb + 16 * J + i];
+      acc = mfma16(av, bv, acc);
+    }
+  }
+  return acc;
+}
+
+template <typename TL, typename T>
+__device__ __forceinline__ void blk_to_lds(T* s, int ld, int I, int J, const double (&X)[4], int lane) {
+  const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) s[(16 * I + trow<TL>(grp, v)) * ld + 16 * J + col] = (T)X[v];
+}
+
+// max over the workgroup of a per-lane value (all threads get the result)
+template <int NW>
+__device__ __forceinline__ double wg_max(double v, double* red, int w, int lane) {
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+// Symmetric sweep of pivots j0..j1-1 over a tile whose owned blocks are
+// X[t] at block coordinates (bi[t], bj[t]) (valid if ok[t]). colbuf holds
+// 2 x 16*TT doubles. Same update rules (and exact symmetry) as sweep16.
+template <typename TL, int C, int TT>
+__device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], const int (&bj)[C],
+                                         const bool (&ok)[C], int j0, int j1, int lane, double* colbuf,
+                                         PivStats& ps, int code, double tol, double scale) {
+  const int col = lane & 15, grp = lane >> 4;
+  for (int j = j0; j < j1; ++j) {
+    double* cb = colbuf + 16 * TT * (j & 1);
+    const int jb = j >> 4, jj = j & 15;
+#pragma unroll
+    for (int t = 0; t < C; ++t)
+      if (ok[t] && bj[t] == jb && col == jj) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cb[16 * bi[t] + trow<TL>(grp, v)] = X[t][v];
+      }
+    __syncthreads();
+    const double d = cb[j];
+    const bool zero = !(fabs(d) > tol);
+    if (zero) ps.nzero++;
+    else if (d > 0) ps.npos++;
+    else ps.nneg++;
+    if ((zero || d < 0) && ps.first_bad < 0) ps.first_bad = code;
+    ps.minrel = fmin(ps.minrel, fabs(d) / scale);
+    const double rd = zero ? 0.0 : 1.0 / d;
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      if (!ok[t]) continue;
+      const int c = 16 * bj[t] + col;
+      const double cc = cb[c];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * bi[t] + trow<TL>(grp, v);
+        const double ci = cb[r];
+        double x;
+        if (r == j && c == j) x = -rd;
+        else if (r == j) x = cc * rd;
+        else if (c == j) x = ci * rd;
+        else x = __fma_rn(-(ci * cc), rd, X[t][v]);
+        X[t][v] = x;
+      }
+    }
+  }
+}
+
+template <int C, typename TL>
+__device__ __forceinline__ double diag_max(const double (&X)[C][4], const int (&bi)[C], const int (&bj)[C],
+                                           const bool (&ok)[C], int lo, int hi, int lane) {
+  const int col = lane & 15, grp = lane >> 4;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < C; ++t) {
+    if (!ok[t]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * bi[t] + trow<TL>(grp, v), c = 16 * bj[t] + col;
+      if (r == c && r >= lo && r < hi) s = fmax(s, fabs(X[t][v]));
+    }
+  }
+  return s;
+}
+
+template <typename TG, int TX, int TZ, int NW>
+struct MwCfg {
+  static constexpr int NX = 16 * TX, NZ = 16 * TZ;
+  static constexpr int LDX = NX + 1, LDZ = NZ + 1;
+  static constexpr int CX = (TX * TX + NW - 1) / NW;
+  static constexpr int CZ = (TZ * TZ + NW - 1) / NW;
+  static constexpr int CT = (TX * TZ + NW - 1) / NW;
+  static constexpr int NAB = (NX * NZ + 64 * NW - 1) / (64 * NW);
+  static constexpr int BYTES_P = (int)sizeof(TG) * NX * LDX;
+  static constexpr int BYTES_X = (int)sizeof(TG) * NX * LDZ;
+  static constexpr int BYTES_D = 8 * NZ * LDZ;
+  static constexpr int BYTES_U0 = BYTES_P + BYTES_X > BYTES_D ? BYTES_P + BYTES_X : BYTES_D;
+  static constexpr int BYTES_U = (BYTES_U0 + 15) / 16 * 16;
+  static constexpr int BYTES_AB = (int)sizeof(TG) * NX * LDZ;
+  static constexpr int BLOCKS_PER_STAGE = TZ * TZ + TX * TX;
+};
+
+template <typename TG, int TX, int TZ, int NW>
+__global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
+  using C = MwCfg<TG, TX, TZ, NW>;
+  constexpr int NX = C::NX, NZ = C::NZ, LDX = C::LDX, LDZ = C::LDZ;
+  constexpr int CX = C::CX, CZ = C::CZ, CT = C::CT, NAB = C::NAB;
+  const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
+  if (a.run && !a.run[b]) return;
+  const InstMeta mt = a.meta[b];
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const double delta = a.delta[b];
+  const double* __restrict__ Qg = a.Q + mt.oQ;
+  const double* __restrict__ Mg = a.M + mt.oM;
+  const double* __restrict__ Rg = a.R + mt.oR;
+  const double* __restrict__ Ag = a.A + mt.oA;
+  const double* __restrict__ Bg = a.B + mt.oB;
+  TG* __restrict__ ws = reinterpret_cast<TG*>(a.ws) + mt.ows;
+  constexpr int64_t STAGE = (int64_t)C::BLOCKS_PER_STAGE * 256;
+  auto ztile = [&](int i) { return ws + (int64_t)i * STAGE; };
+  auto xtile = [&](int i) { return ws + (int64_t)i * STAGE + (int64_t)TZ * TZ * 256; };
+
+  __shared__ __align__(16) unsigned char smem[C::BYTES_U + C::BYTES_AB];
+  __shared__ double colbuf[2 * NZ];
+  __shared__ double red[NW];
+  TG* sP = reinterpret_cast<TG*>(smem);
+  TG* sX = reinterpret_cast<TG*>(smem + C::BYTES_P);
+  double* sD = reinterpret_cast<double*>(smem);
+  TG* sAB = reinterpret_cast<TG*>(smem + C::BYTES_U);
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  int xi[CX], xj[CX], zi[CZ], zj[CZ], ti[CT], tj[CT];
+  bool xo[CX], zo[CZ], to[CT];
+#pragma unroll
+  for (int t = 0; t < CX; ++t) {
+    const int bx = w + NW * t;
+    xo[t] = bx < TX * TX;
+    xi[t] = bx / TX;
+    xj[t] = bx % TX;
+  }
+#pragma unroll
+  for (int t = 0; t < CZ; ++t) {
+    const int bz = w + NW * t;
+    zo[t] = bz < TZ * TZ;
+    zmap<TX, TZ>(zo[t] ? bz : 0, zi[t], zj[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int bt = w + NW * t;
+    to[t] = bt < TX * TZ;
+    ti[t] = bt / TZ;
+    tj[t] = bt % TZ;
+  }
+
+  PivStats ps;
+  ps.init();
+  const double eps = 2.220446049250313e-16;
+
+  auto load_ab = [&](double (&o)[NAB], int k) {
+    const double* A = Ag + (int64_t)k * n * n;
+    const double* B = Bg + (int64_t)k * n * m;
+#pragma unroll
+    for (int t = 0; t < NAB; ++t) {
+      const int e = tid + 64 * NW * t, r = e / NZ, c = e % NZ;
+      double v = 0.0;
+      if (e < NX * NZ && r < n) {
+        if (c < n) v = A[r * n + c];
+        else if (c < n + m) v = B[r * m + (c - n)];
+      }
+      o[t] = v;
+    }
+  };
+  auto load_h = [&](double (&o)[CZ][4], int k) {
+    const double* Q = Qg + (int64_t)k * n * n;
+    const double* M = Mg + (int64_t)k * n * m;
+    const double* R = Rg + (int64_t)k * m * m;
+#pragma unroll
+    for (int t = 0; t < CZ; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * zi[t] + trow<TG>(grp, v), c = 16 * zj[t] + col;
+        double x = 0.0;
+        if (zo[t]) {
+          if (r < n) {
+            if (c < n) x = Q[r * n + c];
+            else if (c < n + m) x = M[r * m + (c - n)];
+          } else if (r < n + m) {
+            if (c < n) x = M[c * m + (r - n)];
+            else if (c < n + m) x = R[(r - n) * m + (c - n)];
+          }
+        }
+        o[t][v] = x;
+      }
+  };
+  auto store_ab = [&](const double (&o)[NAB]) {
+#pragma unroll
+    for (int t = 0; t < NAB; ++t) {
+      const int e = tid + 64 * NW * t;
+      if (e < NX * NZ) sAB[(e / NZ) * LDZ + (e % NZ)] = (TG)o[t];
+    }
+  };
+
+  // P_N = Q_N
+  double P[CX][4];
+  {
+    const double* QN = Qg + (int64_t)N * n * n;
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+        P[t][v] = (xo[t] && r < n && c < n) ? QN[r * n + c] : 0.0;
+      }
+    TG* zt = ztile(N);
+#pragma unroll
+    for (int t = 0; t < CZ; ++t) {
+      if (!zo[t]) continue;
+      const int bz = w + NW * t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        zt[(int64_t)bz * 256 + v * 64 + lane] = (TG)((t < CX && bz < TX * TX) ? P[t < CX ? t : 0][v] : 0.0);
+    }
+  }
+
+  double ab[NAB], H[CZ][4];
+  if (N > 0) {
+    load_ab(ab, N - 1);
+    load_h(H, N - 1);
+  }
+
+  for (int k = N - 1; k >= 0; --k) {
+    __syncthreads();
+    store_ab(ab);
+    double Hc[CZ][4];
+#pragma unroll
+    for (int t = 0; t < CZ; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Hc[t][v] = H[t][v];
+    if (k >= 1) {
+      load_ab(ab, k - 1);
+      load_h(H, k - 1);
+    }
+    // X = I + delta P_{k+1}, swept -> -S_hat^{-1}
+    double X[CX][4];
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+        X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + delta * P[t][v];
+      }
+    {
+      const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
+      sweep_mw<TG, CX, TX>(X, xi, xj, xo, 0, n, lane, colbuf, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
+    }
+    {
+      TG* xt = xtile(k + 1);
+#pragma unroll
+      for (int t = 0; t < CX; ++t)
+        if (xo[t])
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xt[(int64_t)(w + NW * t) * 256 + v * 64 + lane] = (TG)X[t][v];
+    }
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t]) {
+        blk_to_lds<TG>(sP, LDX, xi[t], xj[t], P[t], lane);
+        blk_to_lds<TG>(sX, LDX, xi[t], xj[t], X[t], lane);
+      }
+    __syncthreads();
+    // W = -P X, symmetrized through sD (sD overlaps sP/sX: barrier between)
+    double W[CX][4];
+#pragma unroll
+    for (int t = 0; t < CX; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[t][v] = 0.0;
+      if (!xo[t]) continue;
+      auto acc = gemm_blk<TG, false, TX>(sP, LDX, sX, LDX, xi[t], xj[t], lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[t][v] = -(double)acc[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t]) blk_to_lds<TG>(sD, LDX, xi[t], xj[t], W[t], lane);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+        if (xo[t]) W[t][v] = 0.5 * (W[t][v] + sD[c * LDX + r]);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t]) blk_to_lds<TG>(sP, LDX, xi[t], xj[t], W[t], lane);
+    __syncthreads();
+    // T = W [A B]  (NX x NZ)
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      if (!to[t]) continue;
+      auto acc = gemm_blk<TG, false, TX>(sP, LDX, sAB, LDZ, ti[t], tj[t], lane);
+      double Tb[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tb[v] = (double)acc[v];
+      blk_to_lds<TG>(sX, LDZ, ti[t], tj[t], Tb, lane);
+    }
+    __syncthreads();
+    // Z = [A B]^T T + Hessian, symmetrized
+    double Z[CZ][4];
+#pragma unroll
+    for (int t = 0; t < CZ; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Z[t][v] = 0.0;
+      if (!zo[t]) continue;
+      auto acc = gemm_blk<TG, true, TX>(sAB, LDZ, sX, LDZ, zi[t], zj[t], lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Z[t][v] = (double)acc[v] + Hc[t][v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CZ; ++t)
+      if (zo[t]) blk_to_lds<TG>(sD, LDZ, zi[t], zj[t], Z[t], lane);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CZ; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * zi[t] + trow<TG>(grp, v), c = 16 * zj[t] + col;
+        if (zo[t]) Z[t][v] = 0.5 * (Z[t][v] + sD[c * LDZ + r]);
+      }
+    {
+      const double sc = wg_max<NW>(diag_max<CZ, TG>(Z, zi, zj, zo, n, n + m, lane), red, w, lane);
+      sweep_mw<TG, CZ, TZ>(Z, zi, zj, zo, n, n + m, lane, colbuf, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
+    }
+    {
+      TG* zt = ztile(k);
+#pragma unroll
+      for (int t = 0; t < CZ; ++t)
+        if (zo[t])
+#pragma unroll
+          for (int v = 0; v < 4; ++v) zt[(int64_t)(w + NW * t) * 256 + v * 64 + lane] = (TG)Z[t][v];
+    }
+    // P_k = Z_xx (same owner, same slot)
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+        P[t][v] = (xo[t] && r < n && c < n) ? Z[t < CZ ? t : 0][v] : 0.0;
+      }
+  }
+  // S_hat_0
+  {
+    double X[CX][4];
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+        X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + delta * P[t][v];
+      }
+    const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
+    sweep_mw<TG, CX, TX>(X, xi, xj, xo, 0, n, lane, colbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
+    TG* xt = xtile(0);
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t])
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xt[(int64_t)(w + NW * t) * 256 + v * 64 + lane] = (TG)X[t][v];
+  }
+  if (tid == 0) {
+    FactorInfo fi;
+    fi.verdict = (ps.first_bad < 0) ? 1 : 0;
+    fi.first_bad = ps.first_bad;
+    fi.singular = ps.nzero > 0 ? 1 : 0;
+    fi.pad = 0;
+    fi.npos = ps.npos;
+    fi.nneg = ps.nneg + (int64_t)(N + 1) * n;
+    fi.nzero = ps.nzero;
+    fi.minrel = ps.minrel;
+    a.info[b] = fi;
+  }
+}
+
+// ------------------------------------------------------------------ solve
+
+// y[c] = sum_r Tile[r][c] vec[r] over a tile of TR x TC blocks owned
+// round-robin (blocks at (bi[t], bj[t])); vec and out in LDS; red is
+// TR x 16 TC doubles. Deterministic: block-row partials are summed in order.
+template <typename TL, int Cn, int TR, int TC>
+__device__ __forceinline__ void tmatvec_mw(const double (&X)[Cn][4], const int (&bi)[Cn], const int (&bj)[Cn],
+                                           const bool (&ok)[Cn], const double* vec, double* out, double* red,
+                                           int tid, int lane) {
+  const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < Cn; ++t) {
+    if (!ok[t]) continue;  // wave-uniform
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s += X[t][v] * vec[16 * bi[t] + trow<TL>(grp, v)];
+    s = group_sum(s);
+    if (grp == 0) red[bi[t] * 16 * TC + 16 * bj[t] + col] = s;
+  }
+  __syncthreads();
+  if (tid < 16 * TC) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < TR; ++i) s += red[i * 16 * TC + tid];
+    out[tid] = s;
+  }
+  __syncthreads();
+}
+
+template <typename TG, int TX, int TZ, int NW>
+__global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
+  using C = MwCfg<TG, TX, TZ, NW>;
+  constexpr int NZ = C::NZ, CX = C::CX, CZ = C::CZ, CT = C::CT;
+  const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  if (a.run && !a.run[b]) return;
+  if (tid == 0) {
+    a.resmax[b] = 0ull;
+    a.bmax[b] = 0ull;
+  }
+  const InstMeta mt = a.meta[b];
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const double delta = a.delta[b];
+  const double* __restrict__ Ag = a.A + mt.oA;
+  const double* __restrict__ Bg = a.B + mt.oB;
+  const TG* __restrict__ ws = reinterpret_cast<const TG*>(a.ws) + mt.ows;
+  constexpr int64_t STAGE = (int64_t)C::BLOCKS_PER_STAGE * 256;
+  auto ztile = [&](int i) { return ws + (int64_t)i * STAGE; };
+  auto xtile = [&](int i) { return ws + (int64_t)i * STAGE + (int64_t)TZ * TZ * 256; };
+  double* __restrict__ pg = a.pk + mt.opk;
+  double* __restrict__ kg = a.pk + mt.opk + (int64_t)(N + 1) * n;
+  const double *qb, *rb, *cb;
+  int64_t qs, rs;
+  const bool accum = a.corr != nullptr;
+  if (accum) {
+    const double* res = a.corr + mt.ores;
+    qb = res; qs = n + m;
+    rb = res + n; rs = n + m;
+    cb = res + (int64_t)N * (n + m) + n;
+  } else {
+    qb = a.q + mt.oq; qs = n;
+    rb = a.r + mt.or_; rs = m;
+    cb = a.c + mt.oc;
+  }
+  double* __restrict__ xg = a.x + mt.ox;
+  double* __restrict__ ug = a.u + mt.ou;
+  double* __restrict__ yg = a.y + mt.oy;
+  if (a.info[b].singular) {
+    if (!accum) {
+      const double nanv = __builtin_nan("");
+      for (int i = tid; i < (N + 1) * n; i += 64 * NW) { xg[i] = nanv; yg[i] = nanv; }
+      for (int i = tid; i < N * m; i += 64 * NW) ug[i] = nanv;
+    }
+    return;
+  }
+
+  __shared__ double s0[NZ], s1[NZ], s2[NZ];
+  __shared__ double red[TZ * NZ];
+
+  int xi[CX], xj[CX], zi[CZ], zj[CZ], ai[CT], aj[CT], ati[CT], atj[CT];
+  bool xo[CX], zo[CZ], ao[CT];
+#pragma unroll
+  for (int t = 0; t < CX; ++t) {
+    const int bx = w + NW * t;
+    xo[t] = bx < TX * TX; xi[t] = bx / TX; xj[t] = bx % TX;
+  }
+#pragma unroll
+  for (int t = 0; t < CZ; ++t) {
+    const int bz = w + NW * t;
+    zo[t] = bz < TZ * TZ;
+    zmap<TX, TZ>(zo[t] ? bz : 0, zi[t], zj[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int bt = w + NW * t;
+    ao[t] = bt < TX * TZ;
+    ai[t] = bt / TZ; aj[t] = bt % TZ;      // block of [A B]   (TX x TZ)
+    ati[t] = bt % TZ; atj[t] = bt / TZ;    // block of [A B]^T (TZ x TX)
+  }
+  auto load_tile = [&](auto& R, const TG* g, auto& ok, int cnt) {
+    for (int t = 0; t < cnt; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        R[t][v] = ok[t] ? (double)g[(int64_t)(w + NW * t) * 256 + v * 64 + lane] : 0.0;
+  };
+  // [A B] block (rows state, cols n+m) in tile layout, or its transpose
+  auto load_ab = [&](double (&R)[CT][4], int k, bool trans) {
+    const double* A = Ag + (int64_t)k * n * n;
+    const double* B = Bg + (int64_t)k * n * m;
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = trans ? 16 * ati[t] + trow<TG>(grp, v) : 16 * ai[t] + trow<TG>(grp, v);
+        const int cc = trans ? 16 * atj[t] + col : 16 * aj[t] + col;
+        const int r = trans ? cc : rr, c = trans ? rr : cc;  // element [A B][r][c]
+        double x = 0.0;
+        if (ao[t] && r < n) {
+          if (c < n) x = A[r * n + c];
+          else if (c < n + m) x = B[r * m + (c - n)];
+        }
+        R[t][v] = x;
+      }
+  };
+  const bool xr = tid < n, ur = tid >= n && tid < n + m;
+
+  // backward vector pass; s0/s1/s2 hold vectors of length NZ
+  double p = xr ? qb[(int64_t)N * qs + tid] : 0.0;  // threads tid < NZ carry vector entries
+  if (xr) pg[(int64_t)N * n + tid] = p;
+  double Zp[CZ][4];
+  load_tile(Zp, ztile(N), zo, CZ);
+  for (int k = N - 1; k >= 0; --k) {
+    double Zk[CZ][4], Xn[CX][4], AB[CT][4];
+    load_tile(Zk, ztile(k), zo, CZ);
+    load_tile(Xn, xtile(k + 1), xo, CX);
+    load_ab(AB, k, false);
+    const double ck = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+    const double qk = xr ? qb[(int64_t)k * qs + tid] : 0.0;
+    const double rk = ur ? rb[(int64_t)k * rs + (tid - n)] : 0.0;
+    __syncthreads();
+    if (tid < NZ) s0[tid] = xr ? ck : 0.0;
+    __syncthreads();
+    tmatvec_mw<TG, CZ, TZ, TZ>(Zp, zi, zj, zo, s0, s1, red, tid, lane);   // s1 = Z_{k+1} c (x rows = P c)
+    if (tid < NZ) s2[tid] = xr ? p + s1[tid] : 0.0;                      // v
+    __syncthreads();
+    tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s2, s1, red, tid, lane);   // s1 = -S_hat^{-1} v
+    if (tid < NZ) s0[tid] = xr ? -s1[tid] : 0.0;                          // g
+    __syncthreads();
+    tmatvec_mw<TG, CT, TX, TZ>(AB, ai, aj, ao, s0, s1, red, tid, lane);   // s1 = [A^T g; B^T g]
+    const double abg = tid < NZ ? s1[tid] : 0.0;
+    if (tid < NZ) s2[tid] = ur ? rk + abg : 0.0;                          // h
+    __syncthreads();
+    tmatvec_mw<TG, CZ, TZ, TZ>(Zk, zi, zj, zo, s2, s1, red, tid, lane);   // s1 = [-K^T h; -G^{-1} h]
+    if (xr) {
+      p = qk + abg - s1[tid];
+      pg[(int64_t)k * n + tid] = p;
+    }
+    if (ur) kg[(int64_t)k * m + (tid - n)] = s1[tid];
+#pragma unroll
+    for (int t = 0; t < CZ; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zp[t][v] = Zk[t][v];
+  }
+  __syncthreads();
+
+  // forward rollout
+  double x;
+  {
+    double X0[CX][4];
+    load_tile(X0, xtile(0), xo, CX);
+    const double p0 = xr ? pg[tid] : 0.0;
+    if (tid < NZ) s0[tid] = xr ? cb[tid] - delta * p0 : 0.0;
+    __syncthreads();
+    tmatvec_mw<TG, CX, TX, TX>(X0, xi, xj, xo, s0, s1, red, tid, lane);
+    x = xr ? -s1[tid] : 0.0;
+  }
+  for (int k = 0; k < N; ++k) {
+    double Zk[CZ][4], Xn[CX][4], ABt[CT][4];
+    load_tile(Zk, ztile(k), zo, CZ);
+    load_tile(Xn, xtile(k + 1), xo, CX);
+    load_ab(ABt, k, true);
+    const double pk = xr ? pg[(int64_t)k * n + tid] : 0.0;
+    const double kk = ur ? kg[(int64_t)k * m + (tid - n)] : 0.0;
+    const double pn = xr ? pg[(int64_t)(k + 1) * n + tid] : 0.0;
+    const double cn = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+    __syncthreads();
+    if (tid < NZ) s0[tid] = xr ? x : 0.0;
+    __syncthreads();
+    tmatvec_mw<TG, CZ, TZ, TZ>(Zk, zi, zj, zo, s0, s1, red, tid, lane);  // [P x; -K x]
+    double uk = 0.0;
+    if (xr) {
+      const double yk = s1[tid] + pk;
+      const int64_t i = (int64_t)k * n + tid;
+      yg[i] = accum ? yg[i] + yk : yk;
+      xg[i] = accum ? xg[i] + x : x;
+    }
+    if (ur) {
+      uk = kk - s1[tid];
+      const int64_t i = (int64_t)k * m + (tid - n);
+      ug[i] = accum ? ug[i] + uk : uk;
+    }
+    if (tid < NZ) s2[tid] = xr ? x : (ur ? uk : 0.0);
+    __syncthreads();
+    tmatvec_mw<TG, CT, TZ, TX>(ABt, ati, atj, ao, s2, s1, red, tid, lane); // [A B] z
+    if (tid < NZ) s0[tid] = xr ? s1[tid] + cn - delta * pn : 0.0;
+    __syncthreads();
+    tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s0, s1, red, tid, lane);
+    x = xr ? -s1[tid] : 0.0;
+  }
+  {
+    double ZN[CZ][4];
+    load_tile(ZN, ztile(N), zo, CZ);
+    const double pN = xr ? pg[(int64_t)N * n + tid] : 0.0;
+    __syncthreads();
+    if (tid < NZ) s0[tid] = xr ? x : 0.0;
+    __syncthreads();
+    tmatvec_mw<TG, CZ, TZ, TZ>(ZN, zi, zj, zo, s0, s1, red, tid, lane);
+    if (xr) {
+      const int64_t i = (int64_t)N * n + tid;
+      const double yN = s1[tid] + pN;
+      yg[i] = accum ? yg[i] + yN : yN;
+      xg[i] = accum ? xg[i] + x : x;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <typename TG, int TX, int TZ, int NW>
+static hipError_t launch_mw_pair(bool factor, const void* args, int nblocks, hipStream_t st) {
+  if (factor)
+    hipLaunchKernelGGL((k_factor_mw<TG, TX, TZ, NW>), dim3(nblocks), dim3(64 * NW), 0, st,
+                       *reinterpret_cast<const FactorArgs*>(args));
+  else
+    hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW>), dim3(nblocks), dim3(64 * NW), 0, st,
+                       *reinterpret_cast<const SolveArgs*>(args));
+  return hipGetLastError();
+}
+
+template <typename TG>
+static hipError_t launch_mw_t(int cls, bool factor, const void* args, int nblocks, hipStream_t st) {
+  switch (cls) {
+    case TILE_X1_Z2: return launch_mw_pair<TG, 1, 2, 4>(factor, args, nblocks, st);
+    case TILE_X2_Z2: return launch_mw_pair<TG, 2, 2, 4>(factor, args, nblocks, st);
+    case TILE_X2_Z3: return launch_mw_pair<TG, 2, 3, 4>(factor, args, nblocks, st);
+    case TILE_X3_Z3: return launch_mw_pair<TG, 3, 3, 9>(factor, args, nblocks, st);
+    case TILE_X4_Z4: return launch_mw_pair<TG, 4, 4, 16>(factor, args, nblocks, st);
+    case TILE_X4_Z6: return launch_mw_pair<TG, 4, 6, 16>(factor, args, nblocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  return fp32 ? launch_mw_t<float>(cls, true, &a, nblocks, st) : launch_mw_t<double>(cls, true, &a, nblocks, st);
+}
+
+hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  return fp32 ? launch_mw_t<float>(cls, false, &a, nblocks, st) : launch_mw_t<double>(cls, false, &a, nblocks, st);
+}
+
+int tile_blocks_per_stage(int cls) {
+  switch (cls) {
+    case TILE_16: return 2;
+    case TILE_X1_Z2: return 4 + 1;
+    case TILE_X2_Z2: return 4 + 4;
+    case TILE_X2_Z3: return 9 + 4;
+    case TILE_X3_Z3: return 9 + 9;
+    case TILE_X4_Z4: return 16 + 16;
+    case TILE_X4_Z6: return 36 + 16;
+  }
+  return 0;
+}
+
+}  // namespace rlqr

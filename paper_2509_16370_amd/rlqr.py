@@ -1,0 +1,231 @@
+"""Thin Python binding of the rlqr C ABI (include/rlqr.h).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+librlqr.so. torch tensors provide device memory and the stream. The functions
+rlqr_create, rlqr_factor, rlqr_solve, rlqr_pivot_inertia, rlqr_residual and
+rlqr_destroy carry the C names; `Solver` wraps one handle.
+
+If librlqr.so is missing this module raises at import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librlqr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "(the solver has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+RLQR_OK, RLQR_E_INVALID, RLQR_E_NOMEM, RLQR_E_HIP, RLQR_E_STATE, RLQR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+RLQR_SEQ_FP64, RLQR_SEQ_MIXED = 0, 1
+INST_OK, INST_NOT_PD, INST_SINGULAR, INST_NOT_CONVERGED = 0, 1, 2, 3
+ARRAYS = ("Q", "M", "R", "A", "B", "q", "r", "c", "x", "u", "y", "res")
+MODES = {"fp64": RLQR_SEQ_FP64, "mixed": RLQR_SEQ_MIXED}
+MAX_NXU = 16
+
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("N", _i32p), ("nx", _i32p), ("nu", _i32p)]
+
+
+class _Lhs(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("Q", "M", "R", "A", "B", "delta")]
+
+
+class _Rhs(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("q", "r", "c")]
+
+
+class _Sol(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("x", "u", "y")]
+
+
+_lib.rlqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_size_t)]
+_lib.rlqr_layout_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+_lib.rlqr_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), _vp]
+_lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
+                            ctypes.c_int32, _vp, _vp, _vp]
+_lib.rlqr_pivot_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.rlqr_residual.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), _vp, _vp, _vp]
+_lib.rlqr_destroy.argtypes = [_vp]
+_lib.rlqr_destroy.restype = None
+_lib.rlqr_status_string.argtypes = [ctypes.c_int]
+_lib.rlqr_status_string.restype = ctypes.c_char_p
+for _f in ("rlqr_create", "rlqr_layout_offsets", "rlqr_factor", "rlqr_solve",
+           "rlqr_pivot_inertia", "rlqr_residual"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("rlqr_create", "rlqr_layout_offsets", "rlqr_factor", "rlqr_solve",
+            "rlqr_pivot_inertia", "rlqr_residual", "rlqr_destroy", "rlqr_status_string")
+
+
+class RlqrError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {_lib.rlqr_status_string(code).decode()} ({code})")
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != RLQR_OK:
+        raise RlqrError(code, where)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ------------------------------------------------------------- C-named calls
+
+def rlqr_create(N: Sequence[int], nx: Sequence[int], nu: Sequence[int], mode: int):
+    """Returns (handle, workspace_bytes)."""
+    N = np.ascontiguousarray(N, dtype=np.int32)
+    nx = np.ascontiguousarray(nx, dtype=np.int32)
+    nu = np.ascontiguousarray(nu, dtype=np.int32)
+    shape = _Shape(len(N), N.ctypes.data_as(_i32p), nx.ctypes.data_as(_i32p), nu.ctypes.data_as(_i32p))
+    h = _vp()
+    ws = ctypes.c_size_t(0)
+    _check(_lib.rlqr_create(ctypes.byref(h), ctypes.byref(shape), int(mode), ctypes.byref(ws)), "rlqr_create")
+    return h, int(ws.value)
+
+
+def rlqr_layout_offsets(h, array: int, batch: int) -> np.ndarray:
+    off = np.zeros(batch + 1, dtype=np.int64)
+    _check(_lib.rlqr_layout_offsets(h, int(array), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+           "rlqr_layout_offsets")
+    return off
+
+
+def rlqr_factor(h, Q, M, R, A, B, delta, stream=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+    _check(_lib.rlqr_factor(h, ctypes.byref(lhs), _stream(stream)), "rlqr_factor")
+
+
+def rlqr_solve(h, q, r, c, x, u, y, rel_tol, max_refine, inst_status=None, inst_relres=None, stream=None):
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
+    _check(_lib.rlqr_solve(h, ctypes.byref(rhs), ctypes.byref(sol), float(rel_tol), int(max_refine),
+                           _ptr(inst_status), _ptr(inst_relres), _stream(stream)), "rlqr_solve")
+
+
+def rlqr_pivot_inertia(h, verdict=None, first_bad=None, inertia=None, stream=None):
+    _check(_lib.rlqr_pivot_inertia(h, _ptr(verdict), _ptr(first_bad), _ptr(inertia), _stream(stream)),
+           "rlqr_pivot_inertia")
+
+
+def rlqr_residual(h, q, r, c, x, u, y, res=None, inst_relres=None, stream=None):
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
+    _check(_lib.rlqr_residual(h, ctypes.byref(rhs), ctypes.byref(sol), _ptr(res), _ptr(inst_relres),
+                              _stream(stream)), "rlqr_residual")
+
+
+def rlqr_destroy(h):
+    _lib.rlqr_destroy(h)
+
+
+# ------------------------------------------------------------- convenience
+
+class Solver:
+    """One handle over a fixed batch of shapes; tensors are torch CUDA float64."""
+
+    def __init__(self, N, nx, nu, mode: str = "fp64", device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.N = np.asarray(N, dtype=np.int32)
+        self.nx = np.asarray(nx, dtype=np.int32)
+        self.nu = np.asarray(nu, dtype=np.int32)
+        self.batch = int(self.N.shape[0])
+        self.mode = mode
+        with torch.cuda.device(self.device):
+            self.handle, self.workspace_bytes = rlqr_create(self.N, self.nx, self.nu, MODES[mode])
+        self.offsets = {name: rlqr_layout_offsets(self.handle, i, self.batch) for i, name in enumerate(ARRAYS)}
+        self._lhs = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.rlqr_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self.handle = None
+
+    def size(self, name: str) -> int:
+        return int(self.offsets[name][-1])
+
+    def empty(self, name: str):
+        return self.torch.empty(max(self.size(name), 1), dtype=self.torch.float64, device=self.device)
+
+    def factor(self, lhs: Dict[str, "torch.Tensor"], stream=None):
+        for k in ("Q", "M", "R", "A", "B"):
+            t = lhs[k]
+            assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() >= self.size(k), k
+        assert lhs["delta"].numel() >= self.batch and lhs["delta"].dtype == self.torch.float64
+        self._lhs = lhs  # the library re-reads the lhs during refinement: keep it alive
+        rlqr_factor(self.handle, *(lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")), stream=stream)
+
+    def solve(self, rhs, out=None, rel_tol: float = 1e-8, max_refine: int = 0, stream=None):
+        torch = self.torch
+        for k in ("q", "r", "c"):
+            t = rhs[k]
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() >= self.size(k), k
+        if out is None:
+            out = {k: self.empty(k) for k in ("x", "u", "y")}
+        status = torch.empty(max(self.batch, 1), dtype=torch.int32, device=self.device)
+        relres = torch.empty(max(self.batch, 1), dtype=torch.float64, device=self.device)
+        rlqr_solve(self.handle, rhs["q"], rhs["r"], rhs["c"], out["x"], out["u"], out["y"],
+                   rel_tol, max_refine, status, relres, stream=stream)
+        return out, status, relres
+
+    def pivot_inertia(self, stream=None):
+        torch = self.torch
+        verdict = torch.empty(max(self.batch, 1), dtype=torch.int32, device=self.device)
+        first_bad = torch.empty(max(self.batch, 1), dtype=torch.int32, device=self.device)
+        inertia = torch.empty(max(3 * self.batch, 1), dtype=torch.int64, device=self.device)
+        rlqr_pivot_inertia(self.handle, verdict, first_bad, inertia, stream=stream)
+        return verdict, first_bad, inertia.view(-1, 3) if self.batch else inertia
+
+    def residual(self, rhs, sol, stream=None):
+        torch = self.torch
+        res = self.empty("res")
+        relres = torch.empty(max(self.batch, 1), dtype=torch.float64, device=self.device)
+        rlqr_residual(self.handle, rhs["q"], rhs["r"], rhs["c"], sol["x"], sol["u"], sol["y"],
+                      res, relres, stream=stream)
+        return res, relres
+
+
+def to_device(packed, device="cuda:0"):
+    """Copy a workloads.Packed batch to device tensors (lhs, rhs dicts)."""
+    import torch
+    dev = torch.device(device)
+
+    def t(a):  # never hand the library a NULL pointer for an empty array
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        return torch.from_numpy(a if a.size else np.zeros(1)).to(dev)
+    lhs = {k: t(packed.arrays[k]) for k in ("Q", "M", "R", "A", "B")}
+    lhs["delta"] = t(packed.delta)
+    rhs = {k: t(packed.arrays[k]) for k in ("q", "r", "c")}
+    return lhs, rhs

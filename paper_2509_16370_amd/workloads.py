@@ -212,3 +212,34 @@ def unpack_solution(p: Packed, x: np.ndarray, u: np.ndarray, y: np.ndarray):
                     u[ou:ou + N * m].reshape(N, m),
                     y[oy:oy + (N + 1) * n].reshape(N + 1, n)))
     return out
+
+
+# ---------------------------------------------------------------- parallel packing
+
+def _pack_chunk(specs):
+    p = pack([make_instance(*s) for s in specs])
+    return p.N, p.n, p.m, p.delta, p.arrays
+
+
+def uniform_specs(batch=4096, n=12, m=4, N=128, delta=1e-8, run=0, cfg_id=1):
+    """Specs (n, m, N, delta, seed) of `batched_uniform`, for `pack_parallel`."""
+    return [(n, m, N, delta, (cfg_id, b, run)) for b in range(batch)]
+
+
+def pack_parallel(specs, workers: int = 8) -> Packed:
+    """Generate and pack instances given as make_instance argument tuples, in
+    worker processes; identical to pack([make_instance(*s) for s in specs])."""
+    import concurrent.futures as cf
+    workers = max(1, min(workers, len(specs)))
+    if workers == 1 or len(specs) < 64:
+        return pack([make_instance(*s) for s in specs])
+    chunk = (len(specs) + workers - 1) // workers
+    parts = [specs[i:i + chunk] for i in range(0, len(specs), chunk)]
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(_pack_chunk, parts))
+    N = np.concatenate([r[0] for r in res])
+    n = np.concatenate([r[1] for r in res])
+    m = np.concatenate([r[2] for r in res])
+    delta = np.concatenate([r[3] for r in res])
+    arrays = {k: np.concatenate([r[4][k] for r in res]) for k in ARRAYS_LHS + ARRAYS_RHS}
+    return Packed(N, n, m, delta, arrays, layout_offsets(N, n, m))
