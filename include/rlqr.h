@@ -62,7 +62,18 @@ typedef enum {
   RLQR_SEQ_FP64 = 0,
   /* Sequential recursion with float32 matrix products and float64 pivot
      factorizations; rlqr_solve refines against the float64 residual. */
-  RLQR_SEQ_MIXED = 1
+  RLQR_SEQ_MIXED = 1,
+  /* Parallel-in-time (Section "Parallel Algorithm"): the horizon is cut into
+     segments of L stages; the reverse associative scan of the interval
+     value-function elements (eqs. lqr-gpu-init-running, lqr-gpu-combo), in
+     float32, gives the cost-to-go at every segment start, and all segments
+     then run the recursion of RLQR_SEQ_MIXED at once. The solve runs the
+     segments in parallel as well and joins them through each segment's
+     transfer matrix (the product of its closed-loop maps
+     F_i = S_hat_{i+1}^{-1}(A_i + B_i K_i)), then refines against the float64
+     residual. Instances whose scan or pivots fall outside the float32 guard
+     band are factored in float64 by the sequential recursion. */
+  RLQR_SCAN_FP32 = 2
 } rlqr_mode;
 
 /* per-instance outcome written by rlqr_solve */
@@ -99,6 +110,14 @@ typedef struct { double *x, *u, *y; } rlqr_sol;
 #define RLQR_MAX_NX 64
 #define RLQR_MAX_NXU 96
 
+/* Launch tuning fixed at create. */
+typedef struct {
+  int32_t scan_chunk;  /* RLQR_SCAN_FP32: stages per segment L >= 1; 0 picks L
+                          from the batch (about two segments per compute unit).
+                          An instance with N <= L is one segment and skips the
+                          scan. Ignored by the sequential modes. */
+} rlqr_tuning;
+
 /*
  * Create a handle for a fixed batch of shapes and one mode; allocates the
  * factor workspace (the only allocation the library makes). The shape arrays
@@ -108,6 +127,15 @@ typedef struct { double *x, *u, *y; } rlqr_sol;
  */
 rlqr_status rlqr_create(rlqr_handle **h, const rlqr_shape *s, rlqr_mode mode,
                         size_t *workspace_bytes);
+
+/* rlqr_create with explicit tuning (t may be NULL: defaults). Errors as
+ * rlqr_create, plus RLQR_E_INVALID for scan_chunk < 0. */
+rlqr_status rlqr_create_tuned(rlqr_handle **h, const rlqr_shape *s, rlqr_mode mode,
+                              const rlqr_tuning *t, size_t *workspace_bytes);
+
+/* The tuning in effect (scan_chunk resolved when it was 0) [host].
+ * Errors: RLQR_E_INVALID. */
+rlqr_status rlqr_get_tuning(const rlqr_handle *h, rlqr_tuning *t);
 
 /* Write the B+1 exclusive prefix offsets (in float64 elements) of array `array`
  * (RLQR_ARR_*) to off [host]. Errors: RLQR_E_INVALID. */

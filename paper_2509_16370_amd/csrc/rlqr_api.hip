@@ -1,14 +1,17 @@
 // rlqr_api.hip -- host side of the C ABI declared in include/rlqr.h.
 //
 // Owns the handle: shape metadata, packed-layout offsets, the factorization
-// workspace (two 16 x 16 tiles per stage and instance) and the per-instance
-// flags that steer the mixed-precision path:
+// workspace and the per-instance flags that steer the precision of each
+// instance:
 //   flag64[b]  instance uses the float64 factorization (always in RLQR_SEQ_FP64;
-//              in RLQR_SEQ_MIXED when a pivot falls inside the guard band or
-//              refinement in float32 did not converge)
+//              otherwise when a pivot falls inside the guard band, the scan
+//              failed, or refinement from float32 tiles did not converge)
 //   conv[b]    refinement converged
+// Work is cut into segments (SegDesc): in the sequential modes one segment
+// per instance; in RLQR_SCAN_FP32 the horizon of an instance is cut into
+// segments of L stages whose boundary cost-to-go comes from the scan.
 // All launches are asynchronous on the caller's stream; no call after
-// rlqr_create allocates memory, synchronizes or copies to the host.
+// rlqr_create allocates memory or synchronizes with the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,11 +30,30 @@ namespace {
 // instance to the float64 factorization, so the certificate is decided in float64.
 constexpr double kGuard = 1.0e-4;
 
+// element tile size of the scan for state size n (16, 32 or 64 rows)
+inline int scan_tx(int n) { return n <= 16 ? 1 : (n <= 32 ? 2 : 4); }
+inline int scan_group(int n) { return n <= 16 ? 0 : (n <= 32 ? 1 : 2); }
+
+struct SegList {
+  SegDesc* d = nullptr;
+  int count = 0;
+};
+
+// Instances of one element tile size that take part in the scan.
+struct ScanGroup {
+  int tx = 0, tw = 0, ninst = 0, maxN = 0, maxchunks = 0;
+  int32_t* insts = nullptr;
+  int64_t *eoff = nullptr, *aoff = nullptr;
+  float* elems = nullptr;
+  float* aggr[2] = {nullptr, nullptr};
+};
+
 }  // namespace
 
 struct rlqr_handle {
   int B = 0;
   rlqr_mode mode = RLQR_SEQ_FP64;
+  int chunk = 0;  // scan mode: stages per segment
   std::vector<int32_t> N, n, m;
   std::vector<int64_t> off[RLQR_ARR_COUNT];
   int64_t total_stage_blocks = 0;  // sum of N_b + 1
@@ -39,16 +61,33 @@ struct rlqr_handle {
 
   InstMeta* meta = nullptr;
   int64_t* stage_off = nullptr;
-  int32_t* blk_inst = nullptr;  // residual block -> instance
+  int32_t* blk_inst = nullptr;  // residual slot -> instance
   void* ws64 = nullptr;   // float64 tiles
-  void* ws32 = nullptr;   // float32 tiles (mixed mode)
+  void* ws32 = nullptr;   // float32 tiles (mixed and scan modes)
   double* pk = nullptr;   // p_i / k_i scratch
   double* res[2] = {nullptr, nullptr};  // residual vectors (ping-pong between passes)
   FactorInfo* info = nullptr;
-  int32_t* fused = nullptr;  // instance's solve kernel computes its residual itself
-  // instances grouped by tile class: device id lists and counts
+
+  // one segment per instance, by tile class (factor); instance lists (solve)
+  SegList whole[TILE_CLASSES];
   int32_t* list[TILE_CLASSES] = {};
   int count[TILE_CLASSES] = {};
+  int32_t* whole_off = nullptr;   // [B + 1]: b
+  SegStats* whole_stats = nullptr;
+
+  // scan mode
+  SegList fseg[TILE_CLASSES];     // every segment (factor)
+  SegList sseg[TILE_CLASSES];     // segments of multi-segment instances (solve, transfer)
+  int32_t* seg_off = nullptr;     // [B + 1]
+  SegStats* seg_stats = nullptr;
+  ScanGroup grp[3];
+  int32_t* multi_list = nullptr;  // instances with two or more segments
+  int nmulti = 0;
+  int32_t* multi = nullptr;       // [B] 1 if the instance has two or more segments
+  int32_t* bad = nullptr;         // [B] scan failed
+  int32_t* run1 = nullptr;        // [B] float32 run mask of single-segment instances
+  double *psi = nullptr, *plo = nullptr, *xhi = nullptr;
+
   unsigned long long *resmax = nullptr, *bmax = nullptr;
   int32_t *flag64 = nullptr, *conv = nullptr, *run32 = nullptr, *run64 = nullptr,
           *runres = nullptr, *fb = nullptr, *status = nullptr;
@@ -78,6 +117,17 @@ static void release(rlqr_handle* h) {
   h->allocs.clear();
 }
 
+template <typename T>
+static bool upload(T* dst, const std::vector<T>& src) {
+  if (src.empty()) return true;
+  return hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+#define RLQR_TRY(x)                           \
+  do {                                        \
+    if ((x) != hipSuccess) return RLQR_E_HIP; \
+  } while (0)
+
 extern "C" {
 
 const char* rlqr_status_string(rlqr_status s) {
@@ -92,11 +142,13 @@ const char* rlqr_status_string(rlqr_status s) {
   return "unknown status";
 }
 
-rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, size_t* workspace_bytes) {
+rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, const rlqr_tuning* tune,
+                              size_t* workspace_bytes) {
   if (!hp) return RLQR_E_INVALID;
   *hp = nullptr;
   if (!s || s->batch < 0) return RLQR_E_INVALID;
-  if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED) return RLQR_E_INVALID;
+  if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED && mode != RLQR_SCAN_FP32) return RLQR_E_INVALID;
+  if (tune && tune->scan_chunk < 0) return RLQR_E_INVALID;
   const int B = s->batch;
   if (B > 0 && (!s->N || !s->nx || !s->nu)) return RLQR_E_INVALID;
   for (int b = 0; b < B; ++b) {
@@ -111,20 +163,36 @@ rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, s
   h->N.assign(s->N, s->N + B);
   h->n.assign(s->nx, s->nx + B);
   h->m.assign(s->nu, s->nu + B);
+  const bool scan = mode == RLQR_SCAN_FP32;
+
+  // segment length: about two segments per compute unit over the whole batch
+  int64_t total_elems = 0;
+  for (int b = 0; b < B; ++b) total_elems += h->N[b] + 1;
+  int L = tune && tune->scan_chunk > 0 ? tune->scan_chunk : (int)std::min<int64_t>(
+                                                                std::max<int64_t>((total_elems + 511) / 512, 8), 1 << 20);
+  h->chunk = L;
+
   for (auto& o : h->off) o.assign(B + 1, 0);
   std::vector<InstMeta> meta(B);
   std::vector<int64_t> stage_off(B + 1, 0);
-  std::vector<int32_t> cls(B), fused(B);
+  std::vector<int32_t> cls(B), nseg(B, 1), seg_off(B + 1, 0), whole_off(B + 1, 0), multi(B, 0), multi_list;
   std::vector<std::vector<int32_t>> lists(TILE_CLASSES);
-  int64_t ws_elems = 0, pk_elems = 0;
+  int64_t ws_elems = 0, pk_elems = 0, vec_elems = 0, psi_elems = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t N = h->N[b], n = h->n[b], m = h->m[b];
     const int64_t cnt[RLQR_ARR_COUNT] = {(N + 1) * n * n, N * n * m, N * m * m, N * n * n, N * n * m,
                                          (N + 1) * n,     N * m,     (N + 1) * n, (N + 1) * n, N * m,
                                          (N + 1) * n,     N * (n + m) + n + (N + 1) * n};
     for (int k = 0; k < RLQR_ARR_COUNT; ++k) h->off[k][b + 1] = h->off[k][b] + cnt[k];
+    cls[b] = tile_class((int)n, (int)m);
+    lists[cls[b]].push_back(b);
+    if (scan && N > L) nseg[b] = (int)((N + L - 1) / L);
+    if (nseg[b] > 1) {
+      multi[b] = 1;
+      multi_list.push_back(b);
+    }
     InstMeta& mt = meta[b];
-    mt.N = (int32_t)N; mt.n = (int32_t)n; mt.m = (int32_t)m; mt.pad = 0;
+    mt.N = (int32_t)N; mt.n = (int32_t)n; mt.m = (int32_t)m; mt.nseg = nseg[b];
     mt.oQ = h->off[RLQR_ARR_Q][b]; mt.oM = h->off[RLQR_ARR_M][b]; mt.oR = h->off[RLQR_ARR_R][b];
     mt.oA = h->off[RLQR_ARR_A][b]; mt.oB = h->off[RLQR_ARR_B][b];
     mt.oq = h->off[RLQR_ARR_q][b]; mt.or_ = h->off[RLQR_ARR_r][b]; mt.oc = h->off[RLQR_ARR_c][b];
@@ -132,17 +200,44 @@ rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, s
     mt.ores = h->off[RLQR_ARR_RES][b];
     mt.ows = ws_elems;
     mt.opk = pk_elems;
-    cls[b] = tile_class((int)n, (int)m);
-    fused[b] = cls[b] == TILE_16 ? 1 : 0;
-    lists[cls[b]].push_back(b);
+    mt.ovec = vec_elems;
+    mt.opsi = psi_elems;
     ws_elems += (N + 1) * tile_blocks_per_stage(cls[b]) * 256;
     pk_elems += (N + 1) * n + N * m;
+    if (nseg[b] > 1) {
+      vec_elems += nseg[b] * n;
+      psi_elems += (int64_t)nseg[b] * 2 * n * n;
+    }
     stage_off[b + 1] = stage_off[b] + N + 1;
+    seg_off[b + 1] = seg_off[b] + nseg[b];
+    whole_off[b + 1] = b + 1;
   }
   h->total_stage_blocks = stage_off[B];
   std::vector<int32_t> blk_inst(h->total_stage_blocks > 0 ? h->total_stage_blocks : 1, 0);
   for (int b = 0; b < B; ++b)
     for (int64_t i = stage_off[b]; i < stage_off[b + 1]; ++i) blk_inst[i] = b;
+
+  // scan groups: instances with two or more segments, by element tile size
+  std::vector<int32_t> g_insts[3];
+  std::vector<int64_t> g_eoff[3], g_aoff[3], inst_aoff(B, 0);
+  int64_t g_elem[3] = {0, 0, 0}, g_aggr[3] = {0, 0, 0};
+  for (int b = 0; b < B; ++b) {
+    if (nseg[b] < 2) continue;
+    const int g = scan_group(h->n[b]);
+    ScanGroup& G = h->grp[g];
+    const int N = h->N[b], n = h->n[b], m = h->m[b];
+    const int nch = (N + 1 + L - 1) / L;
+    G.tx = scan_tx(n);
+    G.tw = std::max(G.tw, (m + 2 * n + 15) / 16);
+    G.maxN = std::max(G.maxN, N);
+    G.maxchunks = std::max(G.maxchunks, nch);
+    g_insts[g].push_back(b);
+    g_eoff[g].push_back(g_elem[g]);
+    g_aoff[g].push_back(g_aggr[g]);
+    inst_aoff[b] = g_aggr[g];
+    g_elem[g] += N + 1;
+    g_aggr[g] += nch;
+  }
 
   rlqr_status st = RLQR_OK;
   auto A = [&](void** p, size_t bytes) {
@@ -152,15 +247,20 @@ rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, s
   A((void**)&h->stage_off, sizeof(int64_t) * (size_t)(B + 1));
   A((void**)&h->blk_inst, sizeof(int32_t) * blk_inst.size());
   A(&h->ws64, sizeof(double) * (size_t)ws_elems);
-  if (mode == RLQR_SEQ_MIXED) A(&h->ws32, sizeof(float) * (size_t)ws_elems);
+  if (mode != RLQR_SEQ_FP64) A(&h->ws32, sizeof(float) * (size_t)ws_elems);
   A((void**)&h->pk, sizeof(double) * (size_t)pk_elems);
   A((void**)&h->res[0], sizeof(double) * (size_t)h->off[RLQR_ARR_RES][B]);
   A((void**)&h->res[1], sizeof(double) * (size_t)h->off[RLQR_ARR_RES][B]);
   A((void**)&h->info, sizeof(FactorInfo) * (size_t)B);
-  A((void**)&h->fused, sizeof(int32_t) * (size_t)B);
+  A((void**)&h->whole_off, sizeof(int32_t) * (size_t)(B + 1));
+  A((void**)&h->whole_stats, sizeof(SegStats) * (size_t)B);
   for (int c = 0; c < TILE_CLASSES; ++c) {
     h->count[c] = (int)lists[c].size();
-    if (h->count[c] > 0) A((void**)&h->list[c], sizeof(int32_t) * lists[c].size());
+    h->whole[c].count = h->count[c];
+    if (h->count[c] > 0) {
+      A((void**)&h->list[c], sizeof(int32_t) * lists[c].size());
+      A((void**)&h->whole[c].d, sizeof(SegDesc) * lists[c].size());
+    }
   }
   A((void**)&h->resmax, sizeof(unsigned long long) * (size_t)B);
   A((void**)&h->bmax, sizeof(unsigned long long) * (size_t)B);
@@ -168,19 +268,88 @@ rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, s
   for (auto pp : i32s) A((void**)pp, sizeof(int32_t) * (size_t)B);
   A((void**)&h->lastrel, sizeof(double) * (size_t)B);
   A((void**)&h->relres, sizeof(double) * (size_t)B);
+  if (scan) {
+    A((void**)&h->seg_off, sizeof(int32_t) * (size_t)(B + 1));
+    A((void**)&h->seg_stats, sizeof(SegStats) * (size_t)std::max(seg_off[B], 1));
+    A((void**)&h->multi, sizeof(int32_t) * (size_t)B);
+    A((void**)&h->bad, sizeof(int32_t) * (size_t)B);
+    A((void**)&h->run1, sizeof(int32_t) * (size_t)B);
+    h->nmulti = (int)multi_list.size();
+    if (h->nmulti > 0) {
+      A((void**)&h->multi_list, sizeof(int32_t) * multi_list.size());
+      A((void**)&h->psi, sizeof(double) * (size_t)psi_elems);
+      A((void**)&h->plo, sizeof(double) * (size_t)vec_elems);
+      A((void**)&h->xhi, sizeof(double) * (size_t)vec_elems);
+    }
+    for (int g = 0; g < 3; ++g) {
+      ScanGroup& G = h->grp[g];
+      G.ninst = (int)g_insts[g].size();
+      if (G.ninst == 0) continue;
+      const size_t elem = 3ull * (16 * G.tx) * (16 * G.tx);
+      A((void**)&G.insts, sizeof(int32_t) * (size_t)G.ninst);
+      A((void**)&G.eoff, sizeof(int64_t) * (size_t)G.ninst);
+      A((void**)&G.aoff, sizeof(int64_t) * (size_t)G.ninst);
+      A((void**)&G.elems, sizeof(float) * elem * (size_t)g_elem[g]);
+      A((void**)&G.aggr[0], sizeof(float) * elem * (size_t)g_aggr[g]);
+      A((void**)&G.aggr[1], sizeof(float) * elem * (size_t)g_aggr[g]);
+    }
+  }
+  // segment descriptors (device pointers into the scan buffers are known now)
+  std::vector<std::vector<SegDesc>> whole_d(TILE_CLASSES), fseg_d(TILE_CLASSES), sseg_d(TILE_CLASSES);
+  if (st == RLQR_OK) {
+    for (int b = 0; b < B; ++b) {
+      SegDesc d{};
+      d.inst = b; d.lo = 0; d.hi = h->N[b]; d.p0_ld = 0; d.gidx = b; d.s = 0; d.P0 = nullptr;
+      whole_d[cls[b]].push_back(d);
+      if (!scan) continue;
+      const int N = h->N[b];
+      const ScanGroup* G = nseg[b] > 1 ? &h->grp[scan_group(h->n[b])] : nullptr;
+      for (int s2 = 0; s2 < nseg[b]; ++s2) {
+        SegDesc e{};
+        e.inst = b;
+        e.lo = s2 * L;
+        e.hi = nseg[b] > 1 ? std::min(e.lo + L, N) : N;
+        e.gidx = seg_off[b] + s2;
+        e.s = s2;
+        e.P0 = nullptr;
+        e.p0_ld = 0;
+        if (G && e.hi < N) {
+          const int NX = 16 * G->tx;
+          const int rb = scan_result_buffer(G->maxchunks);
+          e.P0 = G->aggr[rb] + (size_t)(inst_aoff[b] + s2 + 1) * 3 * NX * NX;
+          e.p0_ld = NX;
+        }
+        fseg_d[cls[b]].push_back(e);
+        if (nseg[b] > 1) sseg_d[cls[b]].push_back(e);
+      }
+    }
+    for (int c = 0; c < TILE_CLASSES; ++c) {
+      if (!scan) break;
+      h->fseg[c].count = (int)fseg_d[c].size();
+      h->sseg[c].count = (int)sseg_d[c].size();
+      if (h->fseg[c].count > 0) A((void**)&h->fseg[c].d, sizeof(SegDesc) * fseg_d[c].size());
+      if (h->sseg[c].count > 0) A((void**)&h->sseg[c].d, sizeof(SegDesc) * sseg_d[c].size());
+    }
+  }
   if (st == RLQR_OK && B > 0) {
-    if (hipMemcpy(h->meta, meta.data(), sizeof(InstMeta) * B, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->stage_off, stage_off.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->blk_inst, blk_inst.data(), sizeof(int32_t) * blk_inst.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->fused, fused.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess)
-      st = RLQR_E_HIP;
-    for (int c = 0; c < TILE_CLASSES && st == RLQR_OK; ++c)
-      if (h->count[c] > 0 &&
-          hipMemcpy(h->list[c], lists[c].data(), sizeof(int32_t) * lists[c].size(), hipMemcpyHostToDevice) != hipSuccess)
-        st = RLQR_E_HIP;
+    bool ok = upload(h->meta, meta) && upload(h->stage_off, stage_off) && upload(h->blk_inst, blk_inst) &&
+              upload(h->whole_off, whole_off);
+    for (int c = 0; c < TILE_CLASSES && ok; ++c) {
+      if (h->count[c] > 0) ok = upload(h->list[c], lists[c]) && upload(h->whole[c].d, whole_d[c]);
+      if (ok && scan && h->fseg[c].count > 0) ok = upload(h->fseg[c].d, fseg_d[c]);
+      if (ok && scan && h->sseg[c].count > 0) ok = upload(h->sseg[c].d, sseg_d[c]);
+    }
+    if (ok && scan) {
+      ok = upload(h->seg_off, seg_off) && upload(h->multi, multi);
+      if (ok && h->nmulti > 0) ok = upload(h->multi_list, multi_list);
+      for (int g = 0; g < 3 && ok; ++g)
+        if (h->grp[g].ninst > 0)
+          ok = upload(h->grp[g].insts, g_insts[g]) && upload(h->grp[g].eoff, g_eoff[g]) &&
+               upload(h->grp[g].aoff, g_aoff[g]);
+    }
     std::vector<int32_t> f(B, mode == RLQR_SEQ_FP64 ? 1 : 0);
-    if (st == RLQR_OK && hipMemcpy(h->flag64, f.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess)
-      st = RLQR_E_HIP;
+    if (ok) ok = upload(h->flag64, f);
+    if (!ok) st = RLQR_E_HIP;
   }
   if (st != RLQR_OK) {
     release(h);
@@ -192,34 +361,75 @@ rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, s
   return RLQR_OK;
 }
 
+rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, size_t* workspace_bytes) {
+  return rlqr_create_tuned(hp, s, mode, nullptr, workspace_bytes);
+}
+
+rlqr_status rlqr_get_tuning(const rlqr_handle* h, rlqr_tuning* t) {
+  if (!h || !t) return RLQR_E_INVALID;
+  t->scan_chunk = h->chunk;
+  return RLQR_OK;
+}
+
 rlqr_status rlqr_layout_offsets(const rlqr_handle* h, int32_t array, int64_t* off) {
   if (!h || !off || array < 0 || array >= RLQR_ARR_COUNT) return RLQR_E_INVALID;
   std::memcpy(off, h->off[array].data(), sizeof(int64_t) * (h->B + 1));
   return RLQR_OK;
 }
 
-static FactorArgs factor_args(rlqr_handle* h, void* ws, const int32_t* run) {
-  FactorArgs a{};
-  a.meta = h->meta; a.list = nullptr; a.run = run;
-  a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
-  a.ws = ws; a.info = h->info;
-  return a;
+}  // extern "C"
+
+// One factor launch per tile class over the given segment lists, then the
+// per-instance merge of the segments' pivot statistics.
+static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const int32_t* off, SegStats* stats,
+                                  void* ws, const int32_t* run, bool fp32, hipStream_t st) {
+  for (int c = 0; c < TILE_CLASSES; ++c) {
+    if (lists[c].count == 0) continue;
+    FactorArgs a{};
+    a.meta = h->meta; a.segs = lists[c].d; a.run = run;
+    a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
+    a.ws = ws; a.stats = stats;
+    hipError_t e = (c == TILE_16) ? launch_factor(a, lists[c].count, fp32, st)
+                                  : launch_factor_mw(c, a, lists[c].count, fp32, st);
+    if (e != hipSuccess) return e;
+  }
+  MergeArgs m{};
+  m.batch = h->B; m.meta = h->meta; m.seg_off = off; m.run = run; m.stats = stats; m.info = h->info;
+  return launch_merge(m, st);
 }
 
-// one factor launch per tile class
-static hipError_t factor_all(rlqr_handle* h, void* ws, const int32_t* run, bool fp32, hipStream_t st) {
+static hipError_t factor_whole(rlqr_handle* h, void* ws, const int32_t* run, bool fp32, hipStream_t st) {
+  return factor_segments(h, h->whole, h->whole_off, h->whole_stats, ws, run, fp32, st);
+}
+
+// Scan mode: elements, chunk reduce and suffix scan per group, then every
+// segment factored from its boundary cost-to-go, then the transfer matrices.
+static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
+  hipError_t e = launch_fill_i32(h->bad, h->B, 0, st);
+  if (e != hipSuccess) return e;
+  for (int g = 0; g < 3; ++g) {
+    ScanGroup& G = h->grp[g];
+    if (G.ninst == 0) continue;
+    ScanArgs a{};
+    a.meta = h->meta; a.insts = G.insts; a.eoff = G.eoff; a.aoff = G.aoff;
+    a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
+    a.elems = G.elems; a.aggr[0] = G.aggr[0]; a.aggr[1] = G.aggr[1];
+    a.chunk = h->chunk; a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
+    if ((e = launch_scan_elements(a, G.ninst, G.tx, G.tw, st)) != hipSuccess) return e;
+    if ((e = launch_scan_tree(a, G.ninst, G.tx, st)) != hipSuccess) return e;
+  }
+  if ((e = factor_segments(h, h->fseg, h->seg_off, h->seg_stats, h->ws32, nullptr, true, st)) != hipSuccess)
+    return e;
   for (int c = 0; c < TILE_CLASSES; ++c) {
-    if (h->count[c] == 0) continue;
-    FactorArgs a = factor_args(h, ws, run);
-    a.list = h->list[c];
-    hipError_t e = (c == TILE_16) ? launch_factor(a, h->count[c], fp32, st)
-                                  : launch_factor_mw(c, a, h->count[c], fp32, st);
-    if (e != hipSuccess) return e;
+    if (h->sseg[c].count == 0) continue;
+    TransferArgs t{};
+    t.meta = h->meta; t.segs = h->sseg[c].d; t.A = h->lhs.A; t.B = h->lhs.B; t.ws = h->ws32; t.psi = h->psi;
+    if ((e = launch_transfer(c, t, h->sseg[c].count, st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_stream stv) {
+extern "C" rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_stream stv) {
   if (!h || !lhs) return RLQR_E_INVALID;
   if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || !lhs->delta)) return RLQR_E_INVALID;
   h->lhs = *lhs;
@@ -227,23 +437,25 @@ rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_stream stv) {
   if (h->B == 0) return RLQR_OK;
   hipStream_t st = (hipStream_t)stv;
   if (h->mode == RLQR_SEQ_FP64) {
-    if (factor_all(h, h->ws64, nullptr, false, st) != hipSuccess) return RLQR_E_HIP;
+    RLQR_TRY(factor_whole(h, h->ws64, nullptr, false, st));
     return RLQR_OK;
   }
-  // mixed: float32 products everywhere, then float64 for instances whose pivots
-  // fall inside the guard band
-  if (factor_all(h, h->ws32, nullptr, true, st) != hipSuccess) return RLQR_E_HIP;
+  // float32 products everywhere, then float64 for instances whose pivots fall
+  // inside the guard band (or whose scan failed)
+  if (h->mode == RLQR_SEQ_MIXED) RLQR_TRY(factor_whole(h, h->ws32, nullptr, true, st));
+  else RLQR_TRY(factor_scan(h, st));
   MaskArgs m{};
   m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
-  if (launch_masks(m, st) != hipSuccess) return RLQR_E_HIP;
-  if (factor_all(h, h->ws64, h->flag64, false, st) != hipSuccess) return RLQR_E_HIP;
+  m.bad = h->mode == RLQR_SCAN_FP32 ? h->bad : nullptr;
+  RLQR_TRY(launch_masks(m, st));
+  RLQR_TRY(factor_whole(h, h->ws64, h->flag64, false, st));
   return RLQR_OK;
 }
 
 static SolveArgs solve_args(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
-                            const double* corr, double* res_out) {
+                            const double* corr) {
   SolveArgs a{};
-  a.meta = h->meta; a.list = nullptr; a.run = run;
+  a.meta = h->meta; a.run = run;
   a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
   a.ws = fp32 ? h->ws32 : h->ws64;
   a.info = h->info;
@@ -251,8 +463,7 @@ static SolveArgs solve_args(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, 
   a.corr = corr;
   a.x = out->x; a.u = out->u; a.y = out->y;
   a.pk = h->pk;
-  a.res_out = res_out;
-  a.resmax = h->resmax; a.bmax = h->bmax;
+  a.plo = h->plo; a.xhi = h->xhi;
   return a;
 }
 
@@ -276,17 +487,13 @@ static CheckArgs check_args(rlqr_handle* h, int final_pass, double tol, const in
   return a;
 }
 
-#define RLQR_TRY(x)                        \
-  do {                                     \
-    if ((x) != hipSuccess) return RLQR_E_HIP; \
-  } while (0)
-
-// one solve launch per tile class and precision; run masks select instances
-static rlqr_status solve_launch(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
-                                const double* corr, double* res_out, hipStream_t st) {
+// Whole-instance solves, one launch per tile class; run masks select instances.
+// skip (scan mode) leaves the multi-segment instances to the segment solve.
+static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
+                               const double* corr, hipStream_t st) {
   for (int c = 0; c < TILE_CLASSES; ++c) {
     if (h->count[c] == 0) continue;
-    SolveArgs a = solve_args(h, rhs, out, fp32, run, corr, res_out);
+    SolveArgs a = solve_args(h, rhs, out, fp32, run, corr);
     a.list = h->list[c];
     hipError_t e = (c == TILE_16) ? launch_solve(a, h->count[c], fp32, st)
                                   : launch_solve_mw(c, a, h->count[c], fp32, st);
@@ -295,9 +502,32 @@ static rlqr_status solve_launch(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* o
   return RLQR_OK;
 }
 
+// Scan mode: the segments of multi-segment instances in three phases joined
+// by the boundary chains (see k_solve_mw and k_chain).
+static rlqr_status solve_segments(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, const int32_t* run,
+                                  const double* corr, hipStream_t st) {
+  if (h->nmulti == 0) return RLQR_OK;
+  for (int phase = 1; phase <= 3; ++phase) {
+    for (int c = 0; c < TILE_CLASSES; ++c) {
+      if (h->sseg[c].count == 0) continue;
+      SolveArgs a = solve_args(h, rhs, out, true, run, corr);
+      a.segs = h->sseg[c].d;
+      a.phase = phase;
+      RLQR_TRY(launch_seg_solve(c, a, h->sseg[c].count, st));
+    }
+    if (phase < 3) {
+      ChainArgs ch{};
+      ch.meta = h->meta; ch.insts = h->multi_list; ch.run = run; ch.psi = h->psi;
+      ch.vec = phase == 1 ? h->plo : h->xhi;
+      ch.forward = phase == 2 ? 1 : 0;
+      RLQR_TRY(launch_chain(ch, h->nmulti, st));
+    }
+  }
+  return RLQR_OK;
+}
+
 // Pass p of the refinement: solve (p == 0) or correct (p > 0) every
-// instance not yet converged, then its residual (fused for one-wavefront
-// instances, a separate kernel for the others) and the convergence check.
+// instance not yet converged, then its residual and the convergence check.
 static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, int pass, double tol,
                               const int32_t* run64_override, hipStream_t st) {
   const double* corr = pass == 0 ? nullptr : h->res[(pass - 1) & 1];
@@ -314,22 +544,27 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
     r32 = h->run32; r64 = h->run64; rres = h->runres;
   }
   rlqr_status s;
-  if (h->mode == RLQR_SEQ_MIXED && !run64_override)
-    if ((s = solve_launch(h, rhs, out, true, r32, corr, res_out, st)) != RLQR_OK) return s;
-  if ((s = solve_launch(h, rhs, out, false, r64, corr, res_out, st)) != RLQR_OK) return s;
-  bool any_unfused = false;
-  for (int c = 1; c < TILE_CLASSES; ++c) any_unfused |= h->count[c] > 0;
-  if (any_unfused) {
-    ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
-    ra.skip = h->fused;
-    RLQR_TRY(launch_residual(ra, h->total_stage_blocks, st));
+  if (h->mode != RLQR_SEQ_FP64 && !run64_override) {
+    if (h->mode == RLQR_SCAN_FP32) {
+      // single-segment instances take the whole-instance kernels
+      MaskArgs m{};
+      m.batch = h->B; m.kind = 4; m.run32 = h->run32; m.multi = h->multi; m.run1 = h->run1;
+      RLQR_TRY(launch_masks(m, st));
+      if ((s = solve_whole(h, rhs, out, true, h->run1, corr, st)) != RLQR_OK) return s;
+      if ((s = solve_segments(h, rhs, out, r32, corr, st)) != RLQR_OK) return s;
+    } else if ((s = solve_whole(h, rhs, out, true, r32, corr, st)) != RLQR_OK) {
+      return s;
+    }
   }
+  if ((s = solve_whole(h, rhs, out, false, r64, corr, st)) != RLQR_OK) return s;
+  ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
+  RLQR_TRY(launch_residual(ra, h->total_stage_blocks, st));
   RLQR_TRY(launch_check(check_args(h, 0, tol, rres), st));
   return RLQR_OK;
 }
 
-rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, double rel_tol, int32_t max_refine,
-                       int32_t* inst_status, double* inst_relres, rlqr_stream stv) {
+extern "C" rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, double rel_tol,
+                                  int32_t max_refine, int32_t* inst_status, double* inst_relres, rlqr_stream stv) {
   if (!h || !rhs || !out) return RLQR_E_INVALID;
   if (!h->factored) return RLQR_E_STATE;
   if (h->B == 0) return RLQR_OK;
@@ -339,16 +574,19 @@ rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, doubl
   rlqr_status s;
 
   RLQR_TRY(launch_fill_i32(h->conv, h->B, 0, st));
+  // per-instance residual maxima start at zero (the check kernel clears resmax after each pass)
+  RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->resmax), 2 * h->B, 0, st));
+  RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->bmax), 2 * h->B, 0, st));
   for (int pass = 0; pass <= max_refine; ++pass)
     if ((s = solve_pass(h, rhs, out, pass, rel_tol, nullptr, st)) != RLQR_OK) return s;
   RLQR_TRY(launch_check(check_args(h, 1, rel_tol, nullptr), st));
 
-  if (h->mode == RLQR_SEQ_MIXED) {
+  if (h->mode != RLQR_SEQ_FP64) {
     // instances that did not converge from float32 tiles: redo them in float64
     MaskArgs m{};
     m.batch = h->B; m.kind = 2; m.flag64 = h->flag64; m.conv = h->conv; m.status = h->status; m.fb = h->fb;
     RLQR_TRY(launch_masks(m, st));
-    RLQR_TRY(factor_all(h, h->ws64, h->fb, false, st));
+    RLQR_TRY(factor_whole(h, h->ws64, h->fb, false, st));
     const int extra = std::min<int32_t>(max_refine, 2);
     for (int pass = 0; pass <= extra; ++pass) {
       if (pass > 0) {
@@ -367,8 +605,8 @@ rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, doubl
   return RLQR_OK;
 }
 
-rlqr_status rlqr_pivot_inertia(rlqr_handle* h, int32_t* pd_verdict, int32_t* first_bad, int64_t* inertia,
-                               rlqr_stream stv) {
+extern "C" rlqr_status rlqr_pivot_inertia(rlqr_handle* h, int32_t* pd_verdict, int32_t* first_bad, int64_t* inertia,
+                                          rlqr_stream stv) {
   if (!h) return RLQR_E_INVALID;
   if (!h->factored) return RLQR_E_STATE;
   InertiaArgs a{};
@@ -377,8 +615,8 @@ rlqr_status rlqr_pivot_inertia(rlqr_handle* h, int32_t* pd_verdict, int32_t* fir
   return RLQR_OK;
 }
 
-rlqr_status rlqr_residual(rlqr_handle* h, const rlqr_rhs* rhs, const rlqr_sol* z, double* res,
-                          double* inst_relres, rlqr_stream stv) {
+extern "C" rlqr_status rlqr_residual(rlqr_handle* h, const rlqr_rhs* rhs, const rlqr_sol* z, double* res,
+                                     double* inst_relres, rlqr_stream stv) {
   if (!h || !rhs || !z) return RLQR_E_INVALID;
   if (!h->factored) return RLQR_E_STATE;
   if (h->B == 0) return RLQR_OK;
@@ -399,10 +637,8 @@ rlqr_status rlqr_residual(rlqr_handle* h, const rlqr_rhs* rhs, const rlqr_sol* z
   return RLQR_OK;
 }
 
-void rlqr_destroy(rlqr_handle* h) {
+extern "C" void rlqr_destroy(rlqr_handle* h) {
   if (!h) return;
   release(h);
   delete h;
 }
-
-}  // extern "C"

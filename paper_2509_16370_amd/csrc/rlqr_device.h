@@ -89,6 +89,14 @@ __device__ __forceinline__ double wave_max(double v) {
 // Every update is written so that exact symmetry is preserved bit for bit.
 // colbuf: 2 x 16 doubles of LDS (double-buffered pivot column).
 // code: certificate code shared by all pivots of the block. TL selects the row map.
+// LDS ordering inside a one-wavefront workgroup: the LDS unit executes one
+// wavefront's instructions in order, so a compiler-level barrier suffices.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename TL>
 __device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane,
                                         double* colbuf, PivStats& ps, int code,
@@ -100,7 +108,7 @@ __device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane
 #pragma unroll
       for (int v = 0; v < 4; ++v) cb[trow<TL>(grp, v)] = X[v];
     }
-    __syncthreads();
+    wave_sync();
     const double d = uniform(cb[j]);
     const double cc = cb[col];
     double ci[4];
@@ -123,6 +131,27 @@ __device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane
       X[v] = (r == j) ? onrow : offrow;
     }
   }
+}
+
+// Block numbering of a stage tile Z (NZ = 16 TZ) in the multi-wavefront
+// kernels: the TX x TX state blocks first (row-major, numbered like the blocks
+// of the state tiles), then the (x, u) blocks, then the u block-rows.
+template <int TX, int TZ>
+__device__ __forceinline__ void zmap(int z, int& I, int& J) {
+  if (z < TX * TX) {
+    I = z / TX;
+    J = z % TX;
+    return;
+  }
+  int e = z - TX * TX;
+  if (TZ > TX && e < TX * (TZ - TX)) {
+    I = e / (TZ - TX);
+    J = TX + e % (TZ - TX);
+    return;
+  }
+  e -= TX * (TZ - TX);
+  I = TX + e / TZ;
+  J = e % TZ;
 }
 
 }  // namespace rlqr

@@ -9,9 +9,12 @@ namespace rlqr {
 
 // Per-instance metadata: shape and element offsets into every packed array
 // (ows in workspace elements, opk in float64 elements of the p/k scratch).
+// Scan mode only: nseg stage segments, ovec the first boundary vector (n
+// float64 per segment), opsi the first transfer matrix pair (2 n^2 float64
+// per segment).
 struct InstMeta {
-  int32_t N, n, m, pad;
-  int64_t oQ, oM, oR, oA, oB, oq, or_, oc, ox, ou, oy, ores, ows, opk;
+  int32_t N, n, m, nseg;
+  int64_t oQ, oM, oR, oA, oB, oq, or_, oc, ox, ou, oy, ores, ows, opk, ovec, opsi;
 };
 
 // Certificate bookkeeping written by the factor kernels.
@@ -21,18 +24,89 @@ struct FactorInfo {
   double minrel;  // min |pivot| / max|diag| over all pivots
 };
 
+// A stage range [lo, hi) of one instance run by one factor workgroup. The
+// recursion starts from P_hi: Q_N when hi == N, else the float32 tile P0
+// (row-major, stride 16 * TX) produced by the parallel scan.
+struct SegDesc {
+  int32_t inst, lo, hi, p0_ld;  // p0_ld: row stride of P0
+  int32_t gidx, s;              // index of this segment's SegStats; segment number in its instance
+  const float* P0;
+};
+
+// Pivot bookkeeping of one segment, merged per instance by k_merge_stats.
+struct SegStats {
+  int32_t first_bad, nzero;
+  int32_t npos, nneg;
+  double minrel;
+};
+
 struct FactorArgs {
   const InstMeta* meta;
-  const int32_t* list;    // block -> instance (NULL: identity)
+  const SegDesc* segs;    // block -> segment
   const int32_t* run;     // if set, only instances with run[b] != 0 are touched
   const double *Q, *M, *R, *A, *B, *delta;
   void* ws;
+  SegStats* stats;        // one per segment (indexed like segs)
+};
+
+struct MergeArgs {
+  int batch;
+  const InstMeta* meta;
+  const int32_t* seg_off;    // exclusive prefix of segments per instance (global segment order)
+  const int32_t* run;
+  const SegStats* stats;
   FactorInfo* info;
 };
 
+// Parallel-in-time scan over a list of instances (blockIdx.y indexes the list).
+struct ScanArgs {
+  const InstMeta* meta;
+  const int32_t* insts;    // instances handled by this launch
+  const int64_t* eoff;     // per instance: element offset (in elements) into elems
+  const int64_t* aoff;     // per instance: chunk-aggregate offset (in elements) into aggr
+  const double *Q, *M, *R, *A, *B, *delta;
+  float* elems;            // N + 1 interval elements per instance
+  float* aggr[2];          // chunk aggregates, ping-pong
+  const float* aggr_in;
+  float* aggr_out;
+  int chunk, dist, maxN, maxchunks;
+  int32_t* bad;            // per instance: set when the scan cannot be used
+};
+hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tw, hipStream_t st);
+hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, hipStream_t st);
+int scan_result_buffer(int maxchunks);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t st);
+
+// Transfer matrix of a segment [lo, hi): Psi = F_{hi-1} ... F_lo with
+// F_k = S_hat_{k+1}^{-1} (A_k + B_k K_k), from the float32 factor tiles.
+struct TransferArgs {
+  const InstMeta* meta;
+  const SegDesc* segs;
+  const double *A, *B;
+  const void* ws;          // float32 factor tiles
+  double* psi;             // per segment: Psi (row-major n x n), then Psi^T
+};
+hipError_t launch_transfer(int cls, const TransferArgs& a, int nblocks, hipStream_t st);
+
+// Sequential pass over the segment boundaries of each instance (one
+// wavefront per instance): backward p_lo(s) += Psi_s^T p_lo(s+1), or forward
+// xhi(s) += Psi_s xhi(s-1).
+struct ChainArgs {
+  const InstMeta* meta;
+  const int32_t* insts;
+  const int32_t* run;
+  const double* psi;
+  double* vec;
+  int forward;
+};
+hipError_t launch_chain(const ChainArgs& a, int ninst, hipStream_t st);
+
 struct SolveArgs {
   const InstMeta* meta;
-  const int32_t* list;
+  const int32_t* list;    // whole-instance solves: block -> instance
+  const SegDesc* segs;    // segment solves: block -> segment
+  int phase;              // segment solves: 1, 2 or 3 (see k_solve_mw)
+  double *plo, *xhi;      // segment boundary vectors (n per segment, at InstMeta::ovec)
   const int32_t* run;     // if set, only instances with run[b] != 0 are touched
   const double *Q, *M, *R, *A, *B, *delta;
   const void* ws;
@@ -41,14 +115,14 @@ struct SolveArgs {
   const double* corr;       // if set: correction pass, right-hand side = this residual, z += dz
   double *x, *u, *y;
   double* pk;               // p_i / k_i scratch
-  double* res_out;          // residual of the resulting z (fused kernels), may be NULL
-  unsigned long long *resmax, *bmax;  // written by fused kernels
 };
+hipError_t launch_seg_solve(int cls, const SolveArgs& a, int nblocks, hipStream_t st);
 
 struct ResidualArgs {
   int batch;
   const InstMeta* meta;
-  const int32_t* blk_inst;   // block -> instance (one block per stage i = 0..N of each instance)
+  const int32_t* blk_inst;   // slot -> instance (one slot per stage i = 0..N of each instance)
+  int64_t total_slots;
   const int64_t* stage_off;  // exclusive prefix of N_b + 1
   const int32_t* run;
   const int32_t* skip;       // if set, instances with skip[b] != 0 are left alone
@@ -107,11 +181,14 @@ hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t st);
 
 struct MaskArgs {
   int batch;
-  int kind;               // 0: run masks, 1: guard band, 2: pick fallback instances, 3: fallback run mask
+  int kind;               // 0: run masks, 1: guard band, 2: pick fallback instances, 3: fallback run mask,
+                          // 4: single-segment float32 run mask
   double guard;
   const FactorInfo* info;
   const int32_t* status;
-  int32_t *flag64, *conv, *run32, *run64, *runres, *fb;
+  const int32_t* bad;     // kind 1: instances whose scan failed also go to float64
+  const int32_t* multi;   // kind 4: instances with two or more segments
+  int32_t *flag64, *conv, *run32, *run64, *runres, *fb, *run1;
 };
 hipError_t launch_masks(const MaskArgs& a, hipStream_t st);
 

@@ -119,12 +119,82 @@ __device__ __forceinline__ double diag_scale(const double (&X)[4], int lo, int h
 
 // ------------------------------------------------------------------ factor
 
+// Raw stage blocks [Q_k | M_k | R_k | A_k | B_k | 0] staged in LDS by direct
+// global-to-LDS copies (no registers hold the data in flight). STG_MAX covers
+// n + m <= 16 (2n^2 + 2nm + m^2 <= 512) plus the zero cell.
+constexpr int STG_MAX = 520;
+typedef __attribute__((address_space(1))) const void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+// Copy L doubles from global src to LDS dst, 64 dwords per instruction.
+__device__ __forceinline__ void dma_block(const double* src, double* dst, int L, int lane) {
+  const int dw = 2 * L;
+  for (int j = 0; j < dw; j += 64)
+    if (j + lane < dw)
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(reinterpret_cast<const char*>(src) + 4 * (j + lane)),
+                                       (lvoid_t*)(reinterpret_cast<char*>(dst) + 4 * j), 4, 0, 0);
+}
+
+__device__ __forceinline__ void dma_stage(double* stg, const double* Q, const double* M, const double* R,
+                                          const double* A, const double* B, int n, int m, int lane) {
+  const int nn = n * n, nm = n * m, mm = m * m;
+  dma_block(Q, stg, nn, lane);
+  dma_block(M, stg + nn, nm, lane);
+  dma_block(R, stg + nn + nm, mm, lane);
+  dma_block(A, stg + nn + nm + mm, nn, lane);
+  dma_block(B, stg + 2 * nn + nm + mm, nm, lane);
+}
+
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
+
+// staging index of [A B][i][j] (zero cell outside the n x (n+m) block)
+__device__ __forceinline__ int stg_ab(int i, int j, int n, int m) {
+  const int oA = n * n + n * m + m * m, oB = oA + n * n, oZ = oB + n * m;
+  return (i < n && j < n) ? oA + i * n + j : ((i < n && j < n + m) ? oB + i * m + (j - n) : oZ);
+}
+// staging index of the Hessian [[Q, M], [M^T, R]][r][c]
+__device__ __forceinline__ int stg_hess(int r, int c, int n, int m) {
+  const int nn = n * n, nm = n * m, oZ = 2 * nn + 2 * nm + m * m;
+  const bool rx = r < n, ru = r >= n && r < n + m, cx = c < n, cu = c >= n && c < n + m;
+  return (rx && cx) ? r * n + c
+       : (rx && cu) ? nn + r * m + (c - n)
+       : (ru && cx) ? nn + c * m + (r - n)
+       : (ru && cu) ? nn + nm + (r - n) * m + (c - n) : oZ;
+}
+
+// T = W [A B] (op A from LDS tile, op B from the staged blocks) and
+// Z = [A B]^T T (op A from the staged blocks, op B from LDS tile).
+template <typename T>
+__device__ __forceinline__ typename AccT<T>::type gemm_w_ab(const T* sw, const double* stg, int n, int m, int lane) {
+  typename AccT<T>::type acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * kk + kq;
+    acc = mfma16(sw[i * LD + k], (T)stg[stg_ab(k, i, n, m)], acc);
+  }
+  return acc;
+}
+template <typename T>
+__device__ __forceinline__ typename AccT<T>::type gemm_abt_t(const double* stg, const T* st, int n, int m, int lane) {
+  typename AccT<T>::type acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * kk + kq;
+    acc = mfma16((T)stg[stg_ab(k, i, n, m)], st[k * LD + i], acc);
+  }
+  return acc;
+}
+
 template <typename TG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_factor16(FactorArgs a) {
-  const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
+  const SegDesc sd = a.segs[blockIdx.x];
+  const int b = sd.inst;
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
+  const int klo = sd.lo, khi = sd.hi;
   const double delta = a.delta[b];
   const double* __restrict__ Qg = a.Q + mt.oQ;
   const double* __restrict__ Mg = a.M + mt.oM;
@@ -134,17 +204,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   TG* __restrict__ ws = reinterpret_cast<TG*>(a.ws) + mt.ows;  // tiles: Z_i at 2i, X_i at 2i+1
 
   const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
-  __shared__ TG sP[NT * LD], sX[NT * LD], sAB[NT * LD];
-  __shared__ double sD[NT * LD];
+  // work region: sP (P, then W) and sX (X, then T); the float64
+  // symmetrization scratch sD overlays the start of the region. Safe inside
+  // one wavefront: LDS accesses complete in program order.
+  constexpr int TILE_T = NT * LD;
+  constexpr int REGION = (2 * TILE_T * (int)sizeof(TG) > TILE_T * 8) ? 2 * TILE_T * (int)sizeof(TG) : TILE_T * 8;
+  __shared__ __align__(16) unsigned char work[REGION];
+  __shared__ __align__(16) double stg[STG_MAX];
   __shared__ double colbuf[32];
+  TG* sP = reinterpret_cast<TG*>(work);
+  TG* sX = sP + TILE_T;
+  double* sD = reinterpret_cast<double*>(work);
 
   PivStats ps;
   ps.init();
   const double eps = 2.220446049250313e-16;
+  const int oZ = 2 * n * n + 2 * n * m + m * m;
 
-  // P_N = Q_N
+  // P_hi: Q_N at the top of the horizon, else the boundary tile of the scan
   double P[4];
-  {
+  if (sd.P0 == nullptr) {
     const double* QN = Qg + (int64_t)N * n * n;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -153,28 +232,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const double x = QN[in ? r * n + col : 0];
       P[v] = in ? x : 0.0;
     }
-  }
-  tile_store(ws + (int64_t)(2 * N) * 256, P, lane);
-
-  double H[4], abn[4], Hn[4];
-  if (N > 0) {
-    const int k = N - 1;
-    double ab[4];
-    load_ab_rowmajor(ab, Ag + (int64_t)k * n * n, Bg + (int64_t)k * n * m, n, m, lane);
+  } else {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) sAB[((lane + 64 * t) >> 4) * LD + ((lane + 64 * t) & 15)] = (TG)ab[t];
-    load_hess<TG>(H, Qg + (int64_t)k * n * n, Mg + (int64_t)k * n * m, Rg + (int64_t)k * m * m, n, m, lane);
-  }
-  __syncthreads();
-
-  for (int k = N - 1; k >= 0; --k) {
-    // prefetch the stage blocks of step k-1
-    if (k >= 1) {
-      load_ab_rowmajor(abn, Ag + (int64_t)(k - 1) * n * n, Bg + (int64_t)(k - 1) * n * m, n, m, lane);
-      load_hess<TG>(Hn, Qg + (int64_t)(k - 1) * n * n, Mg + (int64_t)(k - 1) * n * m,
-                Rg + (int64_t)(k - 1) * m * m, n, m, lane);
+    for (int v = 0; v < 4; ++v) {
+      const int r = trow<TG>(grp, v);
+      const bool in = r < n && col < n;
+      const float x = sd.P0[in ? r * sd.p0_ld + col : 0];
+      P[v] = in ? (double)x : 0.0;
     }
-    // X = I + delta P_{k+1}; sweep -> -S_hat_{k+1}^{-1}
+  }
+  if (khi == N) tile_store(ws + (int64_t)(2 * N) * 256, P, lane);
+  if (khi > klo) {
+    const int k = khi - 1;
+    dma_stage(stg, Qg + (int64_t)k * n * n, Mg + (int64_t)k * n * m, Rg + (int64_t)k * m * m,
+              Ag + (int64_t)k * n * n, Bg + (int64_t)k * n * m, n, m, lane);
+  }
+
+  for (int k = khi - 1; k >= klo; --k) {
+    // X = I + delta P_{k+1}; sweep -> -S_hat_{k+1}^{-1}  (no stage data needed)
     double X[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
@@ -185,36 +260,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     tile_store(ws + (int64_t)(2 * (k + 1) + 1) * 256, X, lane);
     tile_to_lds<TG>(sP, P, lane);
     tile_to_lds<TG>(sX, X, lane);
-    __syncthreads();
-    // W = -P X, symmetrized
+    wave_sync();
+    // W = -P X, symmetrized (sD overlays sP)
     double W[4];
     {
       auto acc = gemm16<TG, false>(sP, sX, lane);
       acc_to_regs<TG>(W, acc, -1.0);
     }
+    wave_sync();
     tile_to_lds<TG>(sD, W, lane);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int v = 0; v < 4; ++v) W[v] = 0.5 * (W[v] + sD[col * LD + trow<TG>(grp, v)]);
+    wave_sync();
     tile_to_lds<TG>(sP, W, lane);
-    __syncthreads();
+    // the stage blocks of step k must have landed
+    wait_vmem();
+    if (k == khi - 1 && lane == 0) stg[oZ] = 0.0;
+    wave_sync();
+    double H[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) H[v] = stg[stg_hess(trow<TG>(grp, v), col, n, m)];
     // T = W [A B]
     double T[4];
     {
-      auto acc = gemm16<TG, false>(sP, sAB, lane);
+      auto acc = gemm_w_ab<TG>(sP, stg, n, m, lane);
       acc_to_regs<TG>(T, acc, 1.0);
     }
     tile_to_lds<TG>(sX, T, lane);
-    __syncthreads();
+    wave_sync();
     // Z = [A B]^T T + Hess, symmetrized
     double Z[4];
     {
-      auto acc = gemm16<TG, true>(sAB, sX, lane);
+      auto acc = gemm_abt_t<TG>(stg, sX, n, m, lane);
 #pragma unroll
       for (int v = 0; v < 4; ++v) Z[v] = (double)acc[v] + H[v];
     }
+    // the staged blocks are no longer read: fetch step k-1's
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): reads of stg returned
+    wave_sync();
+    if (k > klo)
+      dma_stage(stg, Qg + (int64_t)(k - 1) * n * n, Mg + (int64_t)(k - 1) * n * m, Rg + (int64_t)(k - 1) * m * m,
+                Ag + (int64_t)(k - 1) * n * n, Bg + (int64_t)(k - 1) * n * m, n, m, lane);
     tile_to_lds<TG>(sD, Z, lane);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int v = 0; v < 4; ++v) Z[v] = 0.5 * (Z[v] + sD[col * LD + trow<TG>(grp, v)]);
     // sweep the control block: G_k pivots
@@ -225,17 +314,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     tile_store(ws + (int64_t)(2 * k) * 256, Z, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) P[v] = (trow<TG>(grp, v) < n && col < n) ? Z[v] : 0.0;
-    __syncthreads();
-    if (k >= 1) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) sAB[((lane + 64 * t) >> 4) * LD + ((lane + 64 * t) & 15)] = (TG)abn[t];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) H[v] = Hn[v];
-      __syncthreads();
-    }
+    wave_sync();
   }
   // S_hat_0
-  {
+  if (klo == 0) {
     double X[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
@@ -244,16 +326,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     tile_store(ws + (int64_t)1 * 256, X, lane);
   }
   if (lane == 0) {
-    FactorInfo fi;
-    fi.verdict = (ps.first_bad < 0) ? 1 : 0;
-    fi.first_bad = ps.first_bad;
-    fi.singular = ps.nzero > 0 ? 1 : 0;
-    fi.pad = 0;
-    fi.npos = ps.npos;
-    fi.nneg = ps.nneg + (int64_t)(N + 1) * n;
-    fi.nzero = ps.nzero;
-    fi.minrel = ps.minrel;
-    a.info[b] = fi;
+    SegStats st;
+    st.first_bad = ps.first_bad;
+    st.nzero = ps.nzero;
+    st.npos = ps.npos;
+    st.nneg = ps.nneg;
+    st.minrel = ps.minrel;
+    a.stats[sd.gidx] = st;
   }
 }
 
@@ -270,14 +349,6 @@ __device__ __forceinline__ double tmatvec(const double (&X)[4], const double* ve
   return group_sum(s);
 }
 
-// LDS ordering inside a one-wavefront workgroup: the LDS unit executes one
-// wavefront's instructions in order, so a compiler-level barrier suffices.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // masked vector element load: v[i] if ok else 0. A masked-off lane reads the
 // zero below instead (an empty block may sit at the end of an array).
 __device__ double g_zero = 0.0;
@@ -287,14 +358,11 @@ __device__ __forceinline__ double ld_or0(const double* __restrict__ v, int64_t i
   return ok ? x : 0.0;
 }
 
-// Solve pass. Backward vector pass and forward rollout (see the file header),
-// with the float64 residual of Section "Residual Computation" evaluated on the
-// fly: at step k the rows of stage k-1 are completed (they need y_k and x_k).
+// Solve pass: backward vector pass and forward rollout (see the file header).
 // corr == NULL: solve K z = -b and write z.  corr != NULL: solve for the
-// correction with right-hand side corr (the previous residual), add it to z.
-// Either way the residual of the resulting z against the original b is
-// written to res_out (if set) and its infinity norm and ||b||_inf to
-// resmax/bmax.
+// correction with right-hand side corr (the previous residual) and add it to
+// z. The tiles and stage blocks of the next step are loaded one step ahead
+// so that the dependent chain does not wait on memory.
 template <typename TG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_solve16(SolveArgs a) {
   const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
@@ -303,34 +371,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
   const double delta = a.delta[b];
-  const double* __restrict__ Qg = a.Q + mt.oQ;
-  const double* __restrict__ Mg = a.M + mt.oM;
-  const double* __restrict__ Rg = a.R + mt.oR;
   const double* __restrict__ Ag = a.A + mt.oA;
   const double* __restrict__ Bg = a.B + mt.oB;
   const TG* __restrict__ ws = reinterpret_cast<const TG*>(a.ws) + mt.ows;
   double* __restrict__ pg = a.pk + mt.opk;                        // p_i at i*n
   double* __restrict__ kg = a.pk + mt.opk + (int64_t)(N + 1) * n;  // k_i at i*m
-  const double* __restrict__ q0 = a.q + mt.oq;
-  const double* __restrict__ r0 = a.r + mt.or_;
-  const double* __restrict__ c0 = a.c + mt.oc;
   const double *qb, *rb, *cb;
   int64_t qs, rs;
-  if (a.corr) {
+  const bool acc = a.corr != nullptr;
+  if (acc) {
     const double* res = a.corr + mt.ores;
     qb = res; qs = n + m;
     rb = res + n; rs = n + m;
     cb = res + (int64_t)N * (n + m) + n;
   } else {
-    qb = q0; qs = n;
-    rb = r0; rs = m;
-    cb = c0;
+    qb = a.q + mt.oq; qs = n;
+    rb = a.r + mt.or_; rs = m;
+    cb = a.c + mt.oc;
   }
   double* __restrict__ xg = a.x + mt.ox;
   double* __restrict__ ug = a.u + mt.ou;
   double* __restrict__ yg = a.y + mt.oy;
-  double* __restrict__ rg = a.res_out ? a.res_out + mt.ores : nullptr;
-  const bool acc = a.corr != nullptr;
 
   if (a.info[b].singular) {
     if (!acc) {
@@ -341,28 +402,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     return;
   }
 
-  __shared__ double sv[6][16];
+  __shared__ double sv[2][16];
   const bool xr = col < n, ur = (col >= n) && (col < n + m);
   const bool own = grp == 0;  // lanes 0..15 write outputs
 
-  // ---- backward vector pass
+  // ---- backward vector pass (k = N-1 .. 0), one step of lookahead
   double p = ld_or0(qb, (int64_t)N * qs + col, xr);
   if (own && xr) pg[(int64_t)N * n + col] = p;
-  double Zp[4];
+  double Zp[4], Zk[4], Xn[4], ab[4];
   tile_load(Zp, ws + (int64_t)(2 * N) * 256, lane);
-  for (int k = N - 1; k >= 0; --k) {
-    double Zk[4], Xn[4], ab[4];
-    tile_load(Zk, ws + (int64_t)(2 * k) * 256, lane);
-    tile_load(Xn, ws + (int64_t)(2 * (k + 1) + 1) * 256, lane);
-    {
-      const double* A = Ag + (int64_t)k * n * n;
-      const double* B = Bg + (int64_t)k * n * m;
+  if (N > 0) {
+    tile_load(Zk, ws + (int64_t)(2 * (N - 1)) * 256, lane);
+    tile_load(Xn, ws + (int64_t)(2 * N + 1) * 256, lane);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) ab[v] = ab_elem(A, B, n, m, trow<TG>(grp, v), col);
-    }
+    for (int v = 0; v < 4; ++v)
+      ab[v] = ab_elem(Ag + (int64_t)(N - 1) * n * n, Bg + (int64_t)(N - 1) * n * m, n, m, trow<TG>(grp, v), col);
+  }
+  for (int k = N - 1; k >= 0; --k) {
     const double ck = ld_or0(cb, (int64_t)(k + 1) * n + col, xr);
     const double qk = ld_or0(qb, (int64_t)k * qs + col, xr);
     const double rk = ld_or0(rb, (int64_t)k * rs + (col - n), ur);
+    // next step's operands
+    double Zk1[4], Xn1[4], ab1[4];
+    const int k1 = k > 0 ? k - 1 : 0;
+    tile_load(Zk1, ws + (int64_t)(2 * k1) * 256, lane);
+    tile_load(Xn1, ws + (int64_t)(2 * (k1 + 1) + 1) * 256, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      ab1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, trow<TG>(grp, v), col);
     wave_sync();
     if (own) sv[0][col] = ck;
     wave_sync();
@@ -370,26 +437,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     if (own) sv[1][col] = vv;
     wave_sync();
     const double g = -tmatvec<TG>(Xn, sv[1], lane);                  // S_hat^{-1} v
-    if (own) sv[2][col] = xr ? g : 0.0;
+    if (own) sv[0][col] = xr ? g : 0.0;
     wave_sync();
-    const double abg = tmatvec<TG>(ab, sv[2], lane);                 // [A^T g; B^T g]
+    const double abg = tmatvec<TG>(ab, sv[0], lane);                 // [A^T g; B^T g]
     const double h = ur ? rk + abg : 0.0;
-    if (own) sv[3][col] = h;
+    if (own) sv[1][col] = h;
     wave_sync();
-    const double zh = tmatvec<TG>(Zk, sv[3], lane);                  // [-K^T h; -G^{-1} h]
+    const double zh = tmatvec<TG>(Zk, sv[1], lane);                  // [-K^T h; -G^{-1} h]
     p = xr ? qk + abg - zh : 0.0;
     if (own) {
       if (xr) pg[(int64_t)k * n + col] = p;
       if (ur) kg[(int64_t)k * m + (col - n)] = zh;
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Zp[v] = Zk[v];
+    for (int v = 0; v < 4; ++v) {
+      Zp[v] = Zk[v];
+      Zk[v] = Zk1[v];
+      Xn[v] = Xn1[v];
+      ab[v] = ab1[v];
+    }
   }
   __syncthreads();  // p/k written by lanes 0..15 are read by all lanes below
 
-  // ---- forward rollout with the fused residual
-  double rmax = 0.0, bmax = 0.0;
-  double x;  // correction state x_k
+  // ---- forward rollout (k = 0 .. N-1), one step of lookahead
+  double x;
   {
     double X0[4];
     tile_load(X0, ws + (int64_t)1 * 256, lane);
@@ -400,129 +471,65 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     wave_sync();
     x = xr ? -tmatvec<TG>(X0, sv[0], lane) : 0.0;
   }
-  // totals of the previous stage, kept for its residual rows
-  double xtp = 0.0, utp = 0.0, ytp = 0.0, wtp = 0.0, q0p = 0.0, r0p = 0.0;
-  double Hp[4] = {0, 0, 0, 0}, abp[4] = {0, 0, 0, 0};
-  for (int k = 0; k <= N; ++k) {
-    const bool last = (k == N);
-    double Zk[4], Xn[4], abt[4], ab[4], Hk[4];
-    tile_load(Zk, ws + (int64_t)(2 * k) * 256, lane);
-    const int kn = last ? k : k + 1;
-    tile_load(Xn, ws + (int64_t)(2 * kn + 1) * 256, lane);
-    const int ks = last ? (k > 0 ? k - 1 : 0) : k;  // stage blocks (unused on the last step)
-    {
-      const double* A = Ag + (int64_t)ks * n * n;
-      const double* B = Bg + (int64_t)ks * n * m;
+  double abt[4];
+  tile_load(Zk, ws, lane);
+  tile_load(Xn, ws + (int64_t)(2 * (N > 0 ? 1 : 0) + 1) * 256, lane);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = trow<TG>(grp, v);
-        abt[v] = (!last && N > 0) ? ab_elem(A, B, n, m, col, j) : 0.0;   // [A B][col][j]
-        ab[v] = (!last && N > 0) ? ab_elem(A, B, n, m, j, col) : 0.0;    // [A B][j][col]
-      }
-      if (!last && N > 0) {
-        load_hess<TG>(Hk, Qg + (int64_t)k * n * n, Mg + (int64_t)k * n * m, Rg + (int64_t)k * m * m, n, m, lane);
-      } else {
-        // terminal block Q_N for the last row group
-        const double* QN = Qg + (int64_t)N * n * n;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = trow<TG>(grp, v);
-          Hk[v] = ld_or0(QN, r * n + col, r < n && xr);
-        }
-      }
-    }
+  for (int v = 0; v < 4; ++v)
+    abt[v] = N > 0 ? ab_elem(Ag, Bg, n, m, col, trow<TG>(grp, v)) : 0.0;  // [A B][col][j]
+  for (int k = 0; k < N; ++k) {
     const double pk = ld_or0(pg, (int64_t)k * n + col, xr);
-    const double kk = ld_or0(kg, (int64_t)k * m + (col - n), ur && !last);
-    const double pn = ld_or0(pg, (int64_t)kn * n + col, xr && !last);
-    const double cn = ld_or0(cb, (int64_t)kn * n + col, xr && !last);
-    const double q0k = ld_or0(q0, (int64_t)k * n + col, xr);
-    const double r0k = ld_or0(r0, (int64_t)k * m + (col - n), ur && !last);
-    const double c0k = ld_or0(c0, (int64_t)k * n + col, xr);
+    const double kk = ld_or0(kg, (int64_t)k * m + (col - n), ur);
+    const double pn = ld_or0(pg, (int64_t)(k + 1) * n + col, xr);
+    const double cn = ld_or0(cb, (int64_t)(k + 1) * n + col, xr);
     const double xold = acc ? ld_or0(xg, (int64_t)k * n + col, xr) : 0.0;
     const double yold = acc ? ld_or0(yg, (int64_t)k * n + col, xr) : 0.0;
-    const double uold = acc ? ld_or0(ug, (int64_t)k * m + (col - n), ur && !last) : 0.0;
-
-    // phase A: [P_k x; -K_k x] for the chain, Hess_{k-1} z_{k-1} for the residual
+    const double uold = acc ? ld_or0(ug, (int64_t)k * m + (col - n), ur) : 0.0;
+    double Zk1[4], Xn1[4], abt1[4];
+    const int k1 = k + 1 < N ? k + 1 : k;
+    tile_load(Zk1, ws + (int64_t)(2 * (k + 1)) * 256, lane);  // tile 2N exists (P_N)
+    tile_load(Xn1, ws + (int64_t)(2 * (k1 + 1) + 1) * 256, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      abt1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, col, trow<TG>(grp, v));
     wave_sync();
-    if (own) {
-      sv[0][col] = xr ? x : 0.0;
-      sv[1][col] = xr ? xtp : (ur ? utp : 0.0);
-    }
+    if (own) sv[0][col] = xr ? x : 0.0;
     wave_sync();
-    const double zx = tmatvec<TG>(Zk, sv[0], lane);
-    const double h1 = tmatvec<TG>(Hp, sv[1], lane);
-    const double yk = xr ? zx + pk : 0.0;
-    const double uk = (ur && !last) ? kk - zx : 0.0;
-    const double xt = x + xold, yt = yk + yold, ut = uk + uold;
+    const double zx = tmatvec<TG>(Zk, sv[0], lane);   // [P_k x; -K_k x]
+    const double uk = ur ? kk - zx : 0.0;
     if (own) {
       if (xr) {
-        yg[(int64_t)k * n + col] = yt;
-        xg[(int64_t)k * n + col] = xt;
+        yg[(int64_t)k * n + col] = zx + pk + yold;
+        xg[(int64_t)k * n + col] = x + xold;
       }
-      if (ur && !last) ug[(int64_t)k * m + (col - n)] = ut;
-    }
-    // phase B: [A B] z for the chain (correction) and for the totals,
-    // [A_{k-1} B_{k-1}]^T y_k for the residual of stage k-1
-    wave_sync();
-    if (own) {
-      sv[2][col] = xr ? x : (ur ? uk : 0.0);
-      sv[3][col] = xr ? yt : 0.0;
-      sv[4][col] = xr ? xt : (ur ? ut : 0.0);
+      if (ur) ug[(int64_t)k * m + (col - n)] = uk + uold;
+      sv[1][col] = xr ? x : (ur ? uk : 0.0);
     }
     wave_sync();
-    const double w = tmatvec<TG>(abt, sv[2], lane);
-    const double h2 = tmatvec<TG>(abp, sv[3], lane);
-    const double wt = acc ? tmatvec<TG>(abt, sv[4], lane) : w;
-    // residual rows of stage k-1 (x-row, u-row, dynamics row)
-    if (k > 0) {
-      const double rx = h1 + h2 + q0p - ytp;        // x rows
-      const double ru = h1 + h2 + r0p;              // u rows
-      const double rd = wtp + c0k - delta * yt - xt;  // dynamics row of step k-1
-      if (own) {
-        const int64_t base = (int64_t)(k - 1) * (n + m);
-        if (xr) {
-          if (rg) rg[base + col] = rx;
-          if (rg) rg[(int64_t)N * (n + m) + n + (int64_t)k * n + col] = rd;
-          rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
-        }
-        if (ur) {
-          if (rg) rg[base + col] = ru;
-          rmax = fmax(rmax, fabs(ru));
-        }
-      }
-    } else if (own && xr) {  // initial-state row c_0 - delta y_0 - x_0
-      const double ri = c0k - delta * yt - xt;
-      if (rg) rg[(int64_t)N * (n + m) + n + col] = ri;
-      rmax = fmax(rmax, fabs(ri));
-    }
-    if (own) bmax = fmax(bmax, fmax(fabs(q0k), fmax(fabs(r0k), fabs(c0k))));
-    if (last) {
-      // terminal row Q_N x_N + q_N - y_N
-      wave_sync();
-      if (own) sv[5][col] = xr ? xt : 0.0;
-      wave_sync();
-      const double rt = tmatvec<TG>(Hk, sv[5], lane) + q0k - yt;
-      if (own && xr) {
-        if (rg) rg[(int64_t)N * (n + m) + col] = rt;
-        rmax = fmax(rmax, fabs(rt));
-      }
-      break;
-    }
-    // phase C: x_{k+1} = S_hat_{k+1}^{-1}(A x + B u + c_{k+1} - delta p_{k+1})
-    wave_sync();
+    const double w = tmatvec<TG>(abt, sv[1], lane);   // A x + B u
     if (own) sv[0][col] = xr ? w + cn - delta * pn : 0.0;
     wave_sync();
     x = xr ? -tmatvec<TG>(Xn, sv[0], lane) : 0.0;
-    // keep this stage for its residual rows
-    xtp = xt; utp = ut; ytp = yt; wtp = wt; q0p = q0k; r0p = r0k;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { Hp[v] = Hk[v]; abp[v] = ab[v]; }
+    for (int v = 0; v < 4; ++v) {
+      Zk[v] = Zk1[v];
+      Xn[v] = Xn1[v];
+      abt[v] = abt1[v];
+    }
   }
-  rmax = wave_max(rmax);
-  bmax = wave_max(bmax);
-  if (lane == 0) {
-    a.resmax[b] = (unsigned long long)__double_as_longlong(rmax);
-    a.bmax[b] = (unsigned long long)__double_as_longlong(bmax);
+  {
+    // y_N = P_N x_N + p_N  (Zk now holds tile 2N)
+    const double pN = ld_or0(pg, (int64_t)N * n + col, xr);
+    const double xold = acc ? ld_or0(xg, (int64_t)N * n + col, xr) : 0.0;
+    const double yold = acc ? ld_or0(yg, (int64_t)N * n + col, xr) : 0.0;
+    wave_sync();
+    if (own) sv[0][col] = xr ? x : 0.0;
+    wave_sync();
+    const double yN = tmatvec<TG>(Zk, sv[0], lane) + pN;
+    if (own && xr) {
+      yg[(int64_t)N * n + col] = yN + yold;
+      xg[(int64_t)N * n + col] = x + xold;
+    }
   }
 }
 
@@ -533,57 +540,154 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// One block of 64 lanes per (instance, stage i = 0..N); stage N also covers
-// the terminal row and the c_0 row. Rows are spread over the lanes.
-__global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
-  const int64_t gblk = blockIdx.x;
-  const int b = a.blk_inst[gblk];
-  if (a.run && !a.run[b]) return;
-  if (a.skip && a.skip[b]) return;
-  if (a.info && a.info[b].singular) return;
-  const int i = (int)(gblk - a.stage_off[b]);
-  const InstMeta mt = a.meta[b];
+// Residual of Section "Residual Computation", float64, fully parallel over
+// (instance, stage): a fixed grid of one-wavefront blocks strides over the
+// stage slots i = 0..N of every instance (slot N also carries the terminal
+// row and the c_0 row). For n + m <= 16 a slot is three tile-vector
+// products on register tiles (Hessian [[Q, M], [M^T, R]], [A B] and its
+// transpose) -- the same scheme as the solve; larger stages use one lane per
+// row. Per-instance maxima use 64-bit atomic max (order-independent).
+__device__ __forceinline__ void residual_slot_tiles(const ResidualArgs& a, const InstMeta& mt, int b, int i,
+                                                    double* sv, double& rmax, double& bmax, int lane) {
   const int N = mt.N, n = mt.n, m = mt.m;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool xr = col < n, ur = col >= n && col < n + m, own = grp == 0;
   const double delta = a.delta[b];
-  const double* Q = a.Q + mt.oQ; const double* M = a.M + mt.oM; const double* R = a.R + mt.oR;
-  const double* A = a.A + mt.oA; const double* B = a.B + mt.oB;
   const double* q = a.q + mt.oq; const double* r = a.r + mt.or_; const double* c = a.c + mt.oc;
   const double* x = a.x + mt.ox; const double* u = a.u + mt.ou; const double* y = a.y + mt.oy;
   double* res = a.res ? a.res + mt.ores : nullptr;
-  const int nn = n * n, nm = n * m, mm = m * m;
-  double rmax = 0.0, bmax = 0.0;
   if (i < N) {
-    const double* Qi = Q + (int64_t)i * nn; const double* Mi = M + (int64_t)i * nm;
-    const double* Ri = R + (int64_t)i * mm; const double* Ai = A + (int64_t)i * nn;
-    const double* Bi = B + (int64_t)i * nm;
+    const int ks = i;
+    const double* Qi = a.Q + mt.oQ + (int64_t)ks * n * n;
+    const double* Mi = a.M + mt.oM + (int64_t)ks * n * m;
+    const double* Ri = a.R + mt.oR + (int64_t)ks * m * m;
+    const double* Ai = a.A + mt.oA + (int64_t)ks * n * n;
+    const double* Bi = a.B + mt.oB + (int64_t)ks * n * m;
+    double H[4], ab[4], abt[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 4 * grp + v;
+      H[v] = hess_elem(Qi, Mi, Ri, n, m, j, col);
+      ab[v] = ab_elem(Ai, Bi, n, m, j, col);    // [A B][j][col]
+      abt[v] = ab_elem(Ai, Bi, n, m, col, j);   // [A B][col][j]
+    }
+    const double xi = ld_or0(x, (int64_t)i * n + col, xr);
+    const double ui = ld_or0(u, (int64_t)i * m + (col - n), ur);
+    const double yi = ld_or0(y, (int64_t)i * n + col, xr);
+    const double yn = ld_or0(y, (int64_t)(i + 1) * n + col, xr);
+    const double xn = ld_or0(x, (int64_t)(i + 1) * n + col, xr);
+    const double qi = ld_or0(q, (int64_t)i * n + col, xr);
+    const double ri = ld_or0(r, (int64_t)i * m + (col - n), ur);
+    const double cn = ld_or0(c, (int64_t)(i + 1) * n + col, xr);
+    wave_sync();
+    if (own) {
+      sv[col] = xr ? xi : (ur ? ui : 0.0);
+      sv[16 + col] = xr ? yn : 0.0;
+    }
+    wave_sync();
+    double h = 0.0, g = 0.0, w = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 4 * grp + v;
+      h += H[v] * sv[j];          // Hess z
+      g += ab[v] * sv[16 + j];    // [A B]^T y_{i+1}
+      w += abt[v] * sv[j];        // [A B] z
+    }
+    h = group_sum(h);
+    g = group_sum(g);
+    w = group_sum(w);
+    if (own) {
+      const int64_t base = (int64_t)i * (n + m);
+      if (xr) {
+        const double rx = h + g + qi - yi;
+        const double rd = w + cn - delta * yn - xn;
+        if (res) {
+          res[base + col] = rx;
+          res[(int64_t)N * (n + m) + 2 * n + (int64_t)i * n + col] = rd;
+        }
+        rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
+        bmax = fmax(bmax, fmax(fabs(qi), fabs(cn)));
+      }
+      if (ur) {
+        const double ru = h + g + ri;
+        if (res) res[base + col] = ru;
+        rmax = fmax(rmax, fabs(ru));
+        bmax = fmax(bmax, fabs(ri));
+      }
+    }
+  } else {
+    const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
+    double Hq[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 4 * grp + v;
+      Hq[v] = ld_or0(QN, j * n + col, j < n && xr);
+    }
+    const double xN = ld_or0(x, (int64_t)N * n + col, xr);
+    const double yN = ld_or0(y, (int64_t)N * n + col, xr);
+    const double qN = ld_or0(q, (int64_t)N * n + col, xr);
+    const double c0 = ld_or0(c, col, xr);
+    const double x0 = ld_or0(x, col, xr);
+    const double y0 = ld_or0(y, col, xr);
+    wave_sync();
+    if (own) sv[col] = xr ? xN : 0.0;
+    wave_sync();
+    double h = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h += Hq[v] * sv[4 * grp + v];
+    h = group_sum(h);
+    if (own && xr) {
+      const double rt = h + qN - yN;
+      const double ri = c0 - delta * y0 - x0;
+      if (res) {
+        res[(int64_t)N * (n + m) + col] = rt;
+        res[(int64_t)N * (n + m) + n + col] = ri;
+      }
+      rmax = fmax(rmax, fmax(fabs(rt), fabs(ri)));
+      bmax = fmax(bmax, fmax(fabs(qN), fabs(c0)));
+    }
+  }
+}
+
+__device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const InstMeta& mt, int b, int i,
+                                                   double& rmax, double& bmax, int lane) {
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const int nn = n * n, nm = n * m, mm = m * m;
+  const double delta = a.delta[b];
+  const double* q = a.q + mt.oq; const double* r = a.r + mt.or_; const double* c = a.c + mt.oc;
+  const double* x = a.x + mt.ox; const double* u = a.u + mt.ou; const double* y = a.y + mt.oy;
+  double* res = a.res ? a.res + mt.ores : nullptr;
+  if (i < N) {
+    const double* Q = a.Q + mt.oQ + (int64_t)i * nn; const double* M = a.M + mt.oM + (int64_t)i * nm;
+    const double* R = a.R + mt.oR + (int64_t)i * mm; const double* A = a.A + mt.oA + (int64_t)i * nn;
+    const double* B = a.B + mt.oB + (int64_t)i * nm;
     const double* xi = x + (int64_t)i * n; const double* ui = u + (int64_t)i * m;
-    const double* yi = y + (int64_t)i * n; const double* yn = y + (int64_t)(i + 1) * n;
-    const double* xn = x + (int64_t)(i + 1) * n;
-    for (int row = threadIdx.x; row < 2 * n + m; row += 64) {
-      double s, bv;
+    const double* yn = y + (int64_t)(i + 1) * n;
+    for (int row = lane; row < 2 * n + m; row += 64) {
+      double s = 0.0, bv;
       int64_t out;
-      if (row < n) {           // x-row
+      if (row < n) {
         const int a0 = row;
+        for (int j = 0; j < n; ++j) s = fma(Q[a0 * n + j], xi[j], s);
+        for (int j = 0; j < m; ++j) s = fma(M[a0 * m + j], ui[j], s);
+        for (int j = 0; j < n; ++j) s = fma(A[j * n + a0], yn[j], s);
         bv = q[(int64_t)i * n + a0];
-        s = bv - yi[a0];
-        for (int j = 0; j < n; ++j) s += Qi[a0 * n + j] * xi[j];
-        for (int j = 0; j < m; ++j) s += Mi[a0 * m + j] * ui[j];
-        for (int j = 0; j < n; ++j) s += Ai[j * n + a0] * yn[j];
+        s += bv - y[(int64_t)i * n + a0];
         out = (int64_t)i * (n + m) + a0;
-      } else if (row < n + m) { // u-row
+      } else if (row < n + m) {
         const int a0 = row - n;
+        for (int j = 0; j < n; ++j) s = fma(M[j * m + a0], xi[j], s);
+        for (int j = 0; j < m; ++j) s = fma(R[a0 * m + j], ui[j], s);
+        for (int j = 0; j < n; ++j) s = fma(B[j * m + a0], yn[j], s);
         bv = r[(int64_t)i * m + a0];
-        s = bv;
-        for (int j = 0; j < n; ++j) s += Mi[j * m + a0] * xi[j];
-        for (int j = 0; j < m; ++j) s += Ri[a0 * m + j] * ui[j];
-        for (int j = 0; j < n; ++j) s += Bi[j * m + a0] * yn[j];
+        s += bv;
         out = (int64_t)i * (n + m) + n + a0;
-      } else {                  // dynamics row of step i
+      } else {
         const int a0 = row - n - m;
+        for (int j = 0; j < n; ++j) s = fma(A[a0 * n + j], xi[j], s);
+        for (int j = 0; j < m; ++j) s = fma(B[a0 * m + j], ui[j], s);
         bv = c[(int64_t)(i + 1) * n + a0];
-        s = bv - delta * yn[a0] - xn[a0];
-        for (int j = 0; j < n; ++j) s += Ai[a0 * n + j] * xi[j];
-        for (int j = 0; j < m; ++j) s += Bi[a0 * m + j] * ui[j];
+        s += bv - delta * yn[a0] - x[(int64_t)(i + 1) * n + a0];
         out = (int64_t)N * (n + m) + 2 * n + (int64_t)i * n + a0;
       }
       if (res) res[out] = s;
@@ -591,15 +695,15 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
       bmax = fmax(bmax, fabs(bv));
     }
   } else {
-    const double* QN = Q + (int64_t)N * nn;
-    const double* xN = x + (int64_t)N * n; const double* yN = y + (int64_t)N * n;
-    for (int row = threadIdx.x; row < 2 * n; row += 64) {
-      double s, bv;
+    const double* QN = a.Q + mt.oQ + (int64_t)N * nn;
+    const double* xN = x + (int64_t)N * n;
+    for (int row = lane; row < 2 * n; row += 64) {
+      double s = 0.0, bv;
       int64_t out;
       if (row < n) {
+        for (int j = 0; j < n; ++j) s = fma(QN[row * n + j], xN[j], s);
         bv = q[(int64_t)N * n + row];
-        s = bv - yN[row];
-        for (int j = 0; j < n; ++j) s += QN[row * n + j] * xN[j];
+        s += bv - y[(int64_t)N * n + row];
         out = (int64_t)N * (n + m) + row;
       } else {
         const int a0 = row - n;
@@ -612,11 +716,27 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
       bmax = fmax(bmax, fabs(bv));
     }
   }
-  rmax = wave_max(rmax);
-  bmax = wave_max(bmax);
-  if (threadIdx.x == 0) {
-    atomic_max_nonneg(a.resmax + b, rmax);
-    atomic_max_nonneg(a.bmax + b, bmax);
+}
+
+__global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
+  __shared__ double sv[32];
+  const int lane = threadIdx.x;
+  for (int64_t g = blockIdx.x; g < a.total_slots; g += gridDim.x) {
+    const int b = a.blk_inst[g];
+    if (a.run && !a.run[b]) continue;
+    if (a.skip && a.skip[b]) continue;
+    if (a.info && a.info[b].singular) continue;
+    const InstMeta mt = a.meta[b];
+    const int i = (int)(g - a.stage_off[b]);
+    double rmax = 0.0, bmax = 0.0;
+    if (mt.n + mt.m <= 16) residual_slot_tiles(a, mt, b, i, sv, rmax, bmax, lane);
+    else residual_slot_rows(a, mt, b, i, rmax, bmax, lane);
+    rmax = wave_max(rmax);
+    bmax = wave_max(bmax);
+    if (lane == 0) {
+      atomic_max_nonneg(a.resmax + b, rmax);
+      atomic_max_nonneg(a.bmax + b, bmax);
+    }
   }
 }
 
@@ -669,7 +789,7 @@ __global__ void k_masks(MaskArgs a) {
     a.runres[b] = (!c) ? 1 : 0;
   } else if (a.kind == 1) {
     const FactorInfo fi = a.info[b];
-    a.flag64[b] = (fi.singular || !(fi.minrel >= a.guard)) ? 1 : 0;
+    a.flag64[b] = (fi.singular || !(fi.minrel >= a.guard) || (a.bad && a.bad[b])) ? 1 : 0;
   } else if (a.kind == 2) {
     const int f = (!a.flag64[b] && a.status[b] == RLQR_INST_NOT_CONVERGED) ? 1 : 0;
     a.fb[b] = f;
@@ -677,9 +797,47 @@ __global__ void k_masks(MaskArgs a) {
       a.flag64[b] = 1;
       a.conv[b] = 0;
     }
-  } else {
+  } else if (a.kind == 3) {
     a.run64[b] = (a.fb[b] && !a.conv[b]) ? 1 : 0;
+  } else {
+    a.run1[b] = (a.run32[b] && !a.multi[b]) ? 1 : 0;
   }
+}
+
+// Per-instance certificate from its segments (global segment order). The
+// first failing pivot in elimination order has the largest code.
+__global__ void k_merge_stats(MergeArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.batch) return;
+  if (a.run && !a.run[b]) return;
+  int first_bad = -1, nzero = 0;
+  long long npos = 0, nneg = 0;
+  double minrel = 1.0e300;
+  for (int s = a.seg_off[b]; s < a.seg_off[b + 1]; ++s) {
+    const SegStats st = a.stats[s];
+    first_bad = max(first_bad, st.first_bad);
+    nzero += st.nzero;
+    npos += st.npos;
+    nneg += st.nneg;
+    minrel = fmin(minrel, st.minrel);
+  }
+  const InstMeta mt = a.meta[b];
+  FactorInfo fi;
+  fi.verdict = first_bad < 0 ? 1 : 0;
+  fi.first_bad = first_bad;
+  fi.singular = nzero > 0 ? 1 : 0;
+  fi.pad = 0;
+  fi.npos = npos;
+  fi.nneg = nneg + (long long)(mt.N + 1) * mt.n;
+  fi.nzero = nzero;
+  fi.minrel = minrel;
+  a.info[b] = fi;
+}
+
+hipError_t launch_merge(const MergeArgs& a, hipStream_t st) {
+  if (a.batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_stats, dim3((a.batch + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 __global__ void k_inertia(InertiaArgs a) {
@@ -724,9 +882,12 @@ hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const ResidualArgs& a, int64_t nblocks, hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)nblocks), dim3(64), 0, st, a);
+hipError_t launch_residual(const ResidualArgs& a, int64_t nslots, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  ResidualArgs b = a;
+  b.total_slots = nslots;
+  const int64_t grid = nslots < 8192 ? nslots : 8192;  // 32 one-wavefront blocks per CU
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)grid), dim3(64), 0, st, b);
   return hipGetLastError();
 }
 

@@ -18,24 +18,6 @@
 
 namespace rlqr {
 
-template <int TX, int TZ>
-__device__ __forceinline__ void zmap(int z, int& I, int& J) {
-  if (z < TX * TX) {
-    I = z / TX;
-    J = z % TX;
-    return;
-  }
-  int e = z - TX * TX;
-  if (TZ > TX && e < TX * (TZ - TX)) {
-    I = e / (TZ - TX);
-    J = TX + e % (TZ - TX);
-    return;
-  }
-  e -= TX * (TZ - TX);
-  I = TX + e / TZ;
-  J = e % TZ;
-}
-
 // C block (I, J) = op(A) * B over KB 16-blocks of the inner dimension.
 template <typename T, bool TRANS_A, int KB>
 __device__ __forceinline__ typename AccT<T>::type gemm_blk(const T* sa, int lda, const T* sb, int ldb,
@@ -160,10 +142,12 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   using C = MwCfg<TG, TX, TZ, NW>;
   constexpr int NX = C::NX, NZ = C::NZ, LDX = C::LDX, LDZ = C::LDZ;
   constexpr int CX = C::CX, CZ = C::CZ, CT = C::CT, NAB = C::NAB;
-  const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
+  const SegDesc sd = a.segs[blockIdx.x];
+  const int b = sd.inst;
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
+  const int klo = sd.lo, khi = sd.hi;
   const double delta = a.delta[b];
   const double* __restrict__ Qg = a.Q + mt.oQ;
   const double* __restrict__ Mg = a.M + mt.oM;
@@ -255,7 +239,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     }
   };
 
-  // P_N = Q_N
+  // P_hi: Q_N at the top of the horizon, else the boundary tile of the scan
   double P[CX][4];
   {
     const double* QN = Qg + (int64_t)N * n * n;
@@ -264,8 +248,11 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
-        P[t][v] = (xo[t] && r < n && c < n) ? QN[r * n + c] : 0.0;
+        const bool in = xo[t] && r < n && c < n;
+        P[t][v] = !in ? 0.0 : (sd.P0 ? (double)sd.P0[r * sd.p0_ld + c] : QN[r * n + c]);
       }
+  }
+  if (khi == N) {
     TG* zt = ztile(N);
 #pragma unroll
     for (int t = 0; t < CZ; ++t) {
@@ -278,12 +265,12 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   }
 
   double ab[NAB], H[CZ][4];
-  if (N > 0) {
-    load_ab(ab, N - 1);
-    load_h(H, N - 1);
+  if (khi > klo) {
+    load_ab(ab, khi - 1);
+    load_h(H, khi - 1);
   }
 
-  for (int k = N - 1; k >= 0; --k) {
+  for (int k = khi - 1; k >= klo; --k) {
     __syncthreads();
     store_ab(ab);
     double Hc[CZ][4];
@@ -291,7 +278,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     for (int t = 0; t < CZ; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) Hc[t][v] = H[t][v];
-    if (k >= 1) {
+    if (k > klo) {
       load_ab(ab, k - 1);
       load_h(H, k - 1);
     }
@@ -407,7 +394,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       }
   }
   // S_hat_0
-  {
+  if (klo == 0) {
     double X[CX][4];
 #pragma unroll
     for (int t = 0; t < CX; ++t)
@@ -426,16 +413,13 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         for (int v = 0; v < 4; ++v) xt[(int64_t)(w + NW * t) * 256 + v * 64 + lane] = (TG)X[t][v];
   }
   if (tid == 0) {
-    FactorInfo fi;
-    fi.verdict = (ps.first_bad < 0) ? 1 : 0;
-    fi.first_bad = ps.first_bad;
-    fi.singular = ps.nzero > 0 ? 1 : 0;
-    fi.pad = 0;
-    fi.npos = ps.npos;
-    fi.nneg = ps.nneg + (int64_t)(N + 1) * n;
-    fi.nzero = ps.nzero;
-    fi.minrel = ps.minrel;
-    a.info[b] = fi;
+    SegStats st;
+    st.first_bad = ps.first_bad;
+    st.nzero = ps.nzero;
+    st.npos = ps.npos;
+    st.nneg = ps.nneg;
+    st.minrel = ps.minrel;
+    a.stats[sd.gidx] = st;
   }
 }
 
@@ -468,19 +452,32 @@ __device__ __forceinline__ void tmatvec_mw(const double (&X)[Cn][4], const int (
   __syncthreads();
 }
 
-template <typename TG, int TX, int TZ, int NW>
+// Solve pass over the stages [lo, hi) of one instance. SEG == false: the whole
+// horizon (lo = 0, hi = N): backward vector pass from p_N = q_N, forward
+// rollout from x_0 = S_hat_0^{-1}(c_0 - delta p_0), x, u, y written.
+// SEG == true (scan mode; p_k and x_k are affine in the segment's boundary
+// values through the transfer matrix Psi of the segment):
+//   phase 1: backward from p_hi = 0 (q_N on the last segment); p_lo -> plo
+//   phase 2: backward from the true p_hi (the next segment's plo), p_k and
+//            k_k written; forward from x_lo = 0 (x_0 on the first segment);
+//            x_hi -> xhi
+//   phase 3: forward from the true x_lo (the previous segment's xhi), x, u, y
+//            written (x_N, y_N by the last segment)
+template <typename TG, int TX, int TZ, int NW, bool SEG>
 __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   using C = MwCfg<TG, TX, TZ, NW>;
   constexpr int NZ = C::NZ, CX = C::CX, CZ = C::CZ, CT = C::CT;
-  const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
+  SegDesc sd;
+  if (SEG) sd = a.segs[blockIdx.x];
+  const int b = SEG ? sd.inst : (a.list ? a.list[blockIdx.x] : (int)blockIdx.x);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   if (a.run && !a.run[b]) return;
-  if (tid == 0) {
-    a.resmax[b] = 0ull;
-    a.bmax[b] = 0ull;
-  }
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
+  const int lo = SEG ? sd.lo : 0, hi = SEG ? sd.hi : N;
+  const int phase = SEG ? a.phase : 0;
+  const bool do_bwd = !SEG || phase <= 2, do_fwd = !SEG || phase >= 2;
+  const bool write_pk = !SEG || phase == 2, write_z = !SEG || phase == 3;
   const double delta = a.delta[b];
   const double* __restrict__ Ag = a.A + mt.oA;
   const double* __restrict__ Bg = a.B + mt.oB;
@@ -507,10 +504,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   double* __restrict__ ug = a.u + mt.ou;
   double* __restrict__ yg = a.y + mt.oy;
   if (a.info[b].singular) {
-    if (!accum) {
+    if (!accum && write_z) {
       const double nanv = __builtin_nan("");
-      for (int i = tid; i < (N + 1) * n; i += 64 * NW) { xg[i] = nanv; yg[i] = nanv; }
-      for (int i = tid; i < N * m; i += 64 * NW) ug[i] = nanv;
+      const int x1 = hi == N ? N + 1 : hi;
+      for (int i = lo * n + tid; i < x1 * n; i += 64 * NW) { xg[i] = nanv; yg[i] = nanv; }
+      for (int i = lo * m + tid; i < hi * m; i += 64 * NW) ug[i] = nanv;
     }
     return;
   }
@@ -565,48 +563,55 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   };
   const bool xr = tid < n, ur = tid >= n && tid < n + m;
 
-  // backward vector pass; s0/s1/s2 hold vectors of length NZ
-  double p = xr ? qb[(int64_t)N * qs + tid] : 0.0;  // threads tid < NZ carry vector entries
-  if (xr) pg[(int64_t)N * n + tid] = p;
-  double Zp[CZ][4];
-  load_tile(Zp, ztile(N), zo, CZ);
-  for (int k = N - 1; k >= 0; --k) {
-    double Zk[CZ][4], Xn[CX][4], AB[CT][4];
-    load_tile(Zk, ztile(k), zo, CZ);
-    load_tile(Xn, xtile(k + 1), xo, CX);
-    load_ab(AB, k, false);
-    const double ck = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
-    const double qk = xr ? qb[(int64_t)k * qs + tid] : 0.0;
-    const double rk = ur ? rb[(int64_t)k * rs + (tid - n)] : 0.0;
-    __syncthreads();
-    if (tid < NZ) s0[tid] = xr ? ck : 0.0;
-    __syncthreads();
-    tmatvec_mw<TG, CZ, TZ, TZ>(Zp, zi, zj, zo, s0, s1, red, tid, lane);   // s1 = Z_{k+1} c (x rows = P c)
-    if (tid < NZ) s2[tid] = xr ? p + s1[tid] : 0.0;                      // v
-    __syncthreads();
-    tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s2, s1, red, tid, lane);   // s1 = -S_hat^{-1} v
-    if (tid < NZ) s0[tid] = xr ? -s1[tid] : 0.0;                          // g
-    __syncthreads();
-    tmatvec_mw<TG, CT, TX, TZ>(AB, ai, aj, ao, s0, s1, red, tid, lane);   // s1 = [A^T g; B^T g]
-    const double abg = tid < NZ ? s1[tid] : 0.0;
-    if (tid < NZ) s2[tid] = ur ? rk + abg : 0.0;                          // h
-    __syncthreads();
-    tmatvec_mw<TG, CZ, TZ, TZ>(Zk, zi, zj, zo, s2, s1, red, tid, lane);   // s1 = [-K^T h; -G^{-1} h]
-    if (xr) {
-      p = qk + abg - s1[tid];
-      pg[(int64_t)k * n + tid] = p;
+  // ---- backward vector pass over k = hi-1 .. lo; threads tid < NZ carry vector entries
+  if (do_bwd) {
+    double p;
+    if (hi == N) p = xr ? qb[(int64_t)N * qs + tid] : 0.0;
+    else if (phase == 1) p = 0.0;
+    else p = xr ? a.plo[mt.ovec + (int64_t)(sd.s + 1) * n + tid] : 0.0;
+    if (write_pk && xr) pg[(int64_t)hi * n + tid] = p;
+    double Zp[CZ][4];
+    load_tile(Zp, ztile(hi), zo, CZ);
+    for (int k = hi - 1; k >= lo; --k) {
+      double Zk[CZ][4], Xn[CX][4], AB[CT][4];
+      load_tile(Zk, ztile(k), zo, CZ);
+      load_tile(Xn, xtile(k + 1), xo, CX);
+      load_ab(AB, k, false);
+      const double ck = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+      const double qk = xr ? qb[(int64_t)k * qs + tid] : 0.0;
+      const double rk = ur ? rb[(int64_t)k * rs + (tid - n)] : 0.0;
+      __syncthreads();
+      if (tid < NZ) s0[tid] = xr ? ck : 0.0;
+      __syncthreads();
+      tmatvec_mw<TG, CZ, TZ, TZ>(Zp, zi, zj, zo, s0, s1, red, tid, lane);   // s1 = Z_{k+1} c (x rows = P c)
+      if (tid < NZ) s2[tid] = xr ? p + s1[tid] : 0.0;                      // v
+      __syncthreads();
+      tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s2, s1, red, tid, lane);   // s1 = -S_hat^{-1} v
+      if (tid < NZ) s0[tid] = xr ? -s1[tid] : 0.0;                          // g
+      __syncthreads();
+      tmatvec_mw<TG, CT, TX, TZ>(AB, ai, aj, ao, s0, s1, red, tid, lane);   // s1 = [A^T g; B^T g]
+      const double abg = tid < NZ ? s1[tid] : 0.0;
+      if (tid < NZ) s2[tid] = ur ? rk + abg : 0.0;                          // h
+      __syncthreads();
+      tmatvec_mw<TG, CZ, TZ, TZ>(Zk, zi, zj, zo, s2, s1, red, tid, lane);   // s1 = [-K^T h; -G^{-1} h]
+      if (xr) {
+        p = qk + abg - s1[tid];
+        if (write_pk) pg[(int64_t)k * n + tid] = p;
+      }
+      if (ur && write_pk) kg[(int64_t)k * m + (tid - n)] = s1[tid];
+#pragma unroll
+      for (int t = 0; t < CZ; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Zp[t][v] = Zk[t][v];
     }
-    if (ur) kg[(int64_t)k * m + (tid - n)] = s1[tid];
-#pragma unroll
-    for (int t = 0; t < CZ; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Zp[t][v] = Zk[t][v];
+    if (SEG && phase == 1 && xr) a.plo[mt.ovec + (int64_t)sd.s * n + tid] = p;
+    __syncthreads();
   }
-  __syncthreads();
+  if (!do_fwd) return;
 
-  // forward rollout
+  // ---- forward rollout over k = lo .. hi-1
   double x;
-  {
+  if (lo == 0) {
     double X0[CX][4];
     load_tile(X0, xtile(0), xo, CX);
     const double p0 = xr ? pg[tid] : 0.0;
@@ -614,8 +619,12 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     __syncthreads();
     tmatvec_mw<TG, CX, TX, TX>(X0, xi, xj, xo, s0, s1, red, tid, lane);
     x = xr ? -s1[tid] : 0.0;
+  } else if (phase == 2) {
+    x = 0.0;
+  } else {
+    x = xr ? a.xhi[mt.ovec + (int64_t)(sd.s - 1) * n + tid] : 0.0;
   }
-  for (int k = 0; k < N; ++k) {
+  for (int k = lo; k < hi; ++k) {
     double Zk[CZ][4], Xn[CX][4], ABt[CT][4];
     load_tile(Zk, ztile(k), zo, CZ);
     load_tile(Xn, xtile(k + 1), xo, CX);
@@ -629,7 +638,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     __syncthreads();
     tmatvec_mw<TG, CZ, TZ, TZ>(Zk, zi, zj, zo, s0, s1, red, tid, lane);  // [P x; -K x]
     double uk = 0.0;
-    if (xr) {
+    if (xr && write_z) {
       const double yk = s1[tid] + pk;
       const int64_t i = (int64_t)k * n + tid;
       yg[i] = accum ? yg[i] + yk : yk;
@@ -638,7 +647,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     if (ur) {
       uk = kk - s1[tid];
       const int64_t i = (int64_t)k * m + (tid - n);
-      ug[i] = accum ? ug[i] + uk : uk;
+      if (write_z) ug[i] = accum ? ug[i] + uk : uk;
     }
     if (tid < NZ) s2[tid] = xr ? x : (ur ? uk : 0.0);
     __syncthreads();
@@ -648,7 +657,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s0, s1, red, tid, lane);
     x = xr ? -s1[tid] : 0.0;
   }
-  {
+  if (SEG && phase == 2) {
+    if (xr) a.xhi[mt.ovec + (int64_t)sd.s * n + tid] = x;
+    return;
+  }
+  if (hi == N) {
     double ZN[CZ][4];
     load_tile(ZN, ztile(N), zo, CZ);
     const double pN = xr ? pg[(int64_t)N * n + tid] : 0.0;
@@ -673,7 +686,7 @@ static hipError_t launch_mw_pair(bool factor, const void* args, int nblocks, hip
     hipLaunchKernelGGL((k_factor_mw<TG, TX, TZ, NW>), dim3(nblocks), dim3(64 * NW), 0, st,
                        *reinterpret_cast<const FactorArgs*>(args));
   else
-    hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW>), dim3(nblocks), dim3(64 * NW), 0, st,
+    hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false>), dim3(nblocks), dim3(64 * NW), 0, st,
                        *reinterpret_cast<const SolveArgs*>(args));
   return hipGetLastError();
 }
@@ -699,6 +712,28 @@ hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32
 hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   return fp32 ? launch_mw_t<float>(cls, false, &a, nblocks, st) : launch_mw_t<double>(cls, false, &a, nblocks, st);
+}
+
+// Segment solves (scan mode, float32 tiles); the one-wavefront class uses the
+// same kernel with a single 16 x 16 block (its workspace layout is identical).
+template <int TX, int TZ, int NW>
+static hipError_t launch_seg_t(const SolveArgs& a, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_solve_mw<float, TX, TZ, NW, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_solve(int cls, const SolveArgs& a, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (cls) {
+    case TILE_16: return launch_seg_t<1, 1, 1>(a, nblocks, st);
+    case TILE_X1_Z2: return launch_seg_t<1, 2, 4>(a, nblocks, st);
+    case TILE_X2_Z2: return launch_seg_t<2, 2, 4>(a, nblocks, st);
+    case TILE_X2_Z3: return launch_seg_t<2, 3, 4>(a, nblocks, st);
+    case TILE_X3_Z3: return launch_seg_t<3, 3, 9>(a, nblocks, st);
+    case TILE_X4_Z4: return launch_seg_t<4, 4, 16>(a, nblocks, st);
+    case TILE_X4_Z6: return launch_seg_t<4, 6, 16>(a, nblocks, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 int tile_blocks_per_stage(int cls) {

@@ -1,0 +1,696 @@
+// rlqr_scan.hip -- parallel-in-time pieces of the dual-regularized Riccati
+// solver (Section "Parallel Algorithm" of arXiv 2509.16370), float32 products.
+//
+// Interval value-function elements e = (P, A, C) (eqs. lqr-gpu-init-running,
+// lqr-gpu-init-terminal) are stored per element as three NX x NX float32
+// tiles, row-major with stride NX, zero outside n x n:
+//     P at 0, A at NX^2, C at 2 NX^2.
+// The combine (i->j) (+) (j->k) is the single-inversion form of eq.
+// lqr-gpu-combo with X = I + C_ij P_jk inverted by Gauss-Jordan elimination
+// with partial pivoting; p and c are not carried (the p-recurrence recovers p,
+// as the paper recommends).
+#include "rlqr_device.h"
+#include "rlqr_internal.h"
+
+namespace rlqr {
+
+// ------------------------------------------------------------ block helpers
+
+// C block (I, J) = op(A) * B, KB 16-blocks of inner dimension, float32 LDS operands.
+template <bool TRANS_A, int KB>
+__device__ __forceinline__ f4 sgemm_blk(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
+  f4 acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 16 * kb + 4 * kk + kq;
+      const float av = TRANS_A ? sa[k * lda + 16 * I + i] : sa[(16 * I + i) * lda + k];
+      const float bv = sb[k * ldb + 16 * J + i];
+      acc = mfma16(av, bv, acc);
+    }
+  return acc;
+}
+// same with op(B) = B^T
+template <int KB>
+__device__ __forceinline__ f4 sgemm_blk_bt(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
+  f4 acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 16 * kb + 4 * kk + kq;
+      const float av = sa[(16 * I + i) * lda + k];
+      const float bv = sb[(16 * J + i) * ldb + k];
+      acc = mfma16(av, bv, acc);
+    }
+  return acc;
+}
+
+// accumulator element (v) of block (I, J): row 16 I + 4 grp + v, column 16 J + col
+__device__ __forceinline__ int arow(int I, int grp, int v) { return 16 * I + 4 * grp + v; }
+
+// ------------------------------------------------------------ combine
+
+template <int TX, int NW>
+struct ScanCfg {
+  static constexpr int NX = 16 * TX, LDX = NX + 1, LDW = 2 * NX + 1;
+  static constexpr int NB = TX * TX;                   // blocks of a state tile
+  static constexpr int CB = (NB + NW - 1) / NW;        // blocks per wavefront
+  static constexpr int TILE = NX * LDX;                // floats of an LDS tile
+  static constexpr int ELEM = 3 * NX * NX;             // floats of a stored element
+};
+
+// LDS working set of one combine
+template <int TX, int NW>
+struct ScanLds {
+  using C = ScanCfg<TX, NW>;
+  float P1[C::TILE], A1[C::TILE], C1[C::TILE];  // accumulated (i -> j)
+  float P2[C::TILE], A2[C::TILE];               // next (j -> k)
+  float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
+  float YA[C::TILE], YC[C::TILE];
+  float rowbuf[2 * C::NX], colbuf[C::NX];
+  int piv;
+};
+
+// copy an element's P, A (and C if withC) from global into LDS tiles
+template <int TX, int NW>
+__device__ __forceinline__ void load_elem(float* P, float* A, float* Cc, const float* __restrict__ e, int tid) {
+  using C = ScanCfg<TX, NW>;
+  for (int x = tid; x < C::NX * C::NX; x += 64 * NW) {
+    const int r = x / C::NX, c = x % C::NX;
+    P[r * C::LDX + c] = e[x];
+    A[r * C::LDX + c] = e[C::NX * C::NX + x];
+    if (Cc) Cc[r * C::LDX + c] = e[2 * C::NX * C::NX + x];
+  }
+}
+template <int TX, int NW>
+__device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P, const float* A, const float* Cc, int tid) {
+  using C = ScanCfg<TX, NW>;
+  for (int x = tid; x < C::NX * C::NX; x += 64 * NW) {
+    const int r = x / C::NX, c = x % C::NX;
+    e[x] = P[r * C::LDX + c];
+    e[C::NX * C::NX + x] = A[r * C::LDX + c];
+    e[2 * C::NX * C::NX + x] = Cc[r * C::LDX + c];
+  }
+}
+
+// acc (P1, A1, C1 in LDS) <- acc (+) next (P2, A2 in LDS, C2 in global).
+// Returns false if X = I + C1 P2 is singular (no pivot above tol).
+template <int TX, int NW>
+__device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid) {
+  using C = ScanCfg<TX, NW>;
+  constexpr int NX = C::NX, LDX = C::LDX, LDW = C::LDW, CB = C::CB;
+  const int w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  bool ok = true;
+  // X = I + C1 P2, W = [X | I]
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+    f4 acc = sgemm_blk<false, TX>(s.C1, LDX, s.P2, LDX, I, J, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      s.W[r * LDW + c] = acc[v] + (r == c ? 1.0f : 0.0f);
+      s.W[r * LDW + NX + c] = (r == c) ? 1.0f : 0.0f;
+    }
+  }
+  __syncthreads();
+  // Gauss-Jordan with partial pivoting on the first n pivots
+  for (int j = 0; j < n; ++j) {
+    if (w == 0) {
+      const float a = (lane < NX && lane >= j) ? fabsf(s.W[lane * LDW + j]) : -1.0f;
+      float best = a;
+      int bi = lane;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const float ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const int p = bi;
+      // swap rows j and p, then publish the scaled pivot row and column j
+      for (int c = lane; c < 2 * NX; c += 64) {
+        const float vj = s.W[j * LDW + c], vp = s.W[p * LDW + c];
+        s.W[j * LDW + c] = vp;
+        s.W[p * LDW + c] = vj;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const float d = s.W[j * LDW + j];
+      const float rd = (best > 0.0f) ? 1.0f / d : 0.0f;
+      if (lane == 0 && !(best > 0.0f)) s.piv = -1;
+      for (int c = lane; c < 2 * NX; c += 64) s.rowbuf[c] = s.W[j * LDW + c] * rd;
+      if (lane < NX) s.colbuf[lane] = s.W[lane * LDW + j];
+    }
+    __syncthreads();
+    for (int x = tid; x < NX * 2 * NX; x += 64 * NW) {
+      const int r = x / (2 * NX), c = x % (2 * NX);
+      const float rv = s.rowbuf[c];
+      s.W[r * LDW + c] = (r == j) ? rv : fmaf(-s.colbuf[r], rv, s.W[r * LDW + c]);
+    }
+    __syncthreads();
+  }
+  if (s.piv < 0) ok = false;
+  // Y_A = X^{-1} A1, Y_C = X^{-1} C1
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+    f4 ya = sgemm_blk<false, TX>(s.W + NX, LDW, s.A1, LDX, I, J, lane);
+    f4 yc = sgemm_blk<false, TX>(s.W + NX, LDW, s.C1, LDX, I, J, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      s.YA[r * LDX + c] = ya[v];
+      s.YC[r * LDX + c] = yc[v];
+    }
+  }
+  __syncthreads();
+  // T1 = P2 Y_A (into W left half), T2 = Y_C A2^T (into W right half)
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+    f4 t1 = sgemm_blk<false, TX>(s.P2, LDX, s.YA, LDX, I, J, lane);
+    f4 t2 = sgemm_blk_bt<TX>(s.YC, LDX, s.A2, LDX, I, J, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      s.W[r * LDW + c] = t1[v];
+      s.W[r * LDW + NX + c] = t2[v];
+    }
+  }
+  __syncthreads();
+  // P = A1^T T1 + P1,  A = A2 Y_A,  C = A2 T2 + C2
+  float Pn[CB][4], An[CB][4], Cn[CB][4];
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+    f4 pa = sgemm_blk<true, TX>(s.A1, LDX, s.W, LDW, I, J, lane);
+    f4 aa = sgemm_blk<false, TX>(s.A2, LDX, s.YA, LDX, I, J, lane);
+    f4 ca = sgemm_blk<false, TX>(s.A2, LDX, s.W + NX, LDW, I, J, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      Pn[t][v] = pa[v] + s.P1[r * LDX + c];
+      An[t][v] = aa[v];
+      Cn[t][v] = ca[v] + C2g[r * NX + c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      s.P1[r * LDX + c] = Pn[t][v];
+      s.A1[r * LDX + c] = An[t][v];
+      s.C1[r * LDX + c] = Cn[t][v];
+    }
+  }
+  __syncthreads();
+  // symmetrize P and C (the products keep them symmetric only up to rounding)
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      Pn[t][v] = 0.5f * (s.P1[r * LDX + c] + s.P1[c * LDX + r]);
+      Cn[t][v] = 0.5f * (s.C1[r * LDX + c] + s.C1[c * LDX + r]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    const int bx = w + NW * t;
+    if (bx >= C::NB) break;
+    const int I = bx / TX, J = bx % TX;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = arow(I, grp, v), c = 16 * J + col;
+      s.P1[r * LDX + c] = Pn[t][v];
+      s.C1[r * LDX + c] = Cn[t][v];
+    }
+  }
+  __syncthreads();
+  return ok;
+}
+
+// ------------------------------------------------------------ kernels
+
+// u-elimination (eq. lqr-gpu-init-running) for stage i = blockIdx.x of
+// instance `inst`: sweep the R block of the symmetric matrix
+//     [[R, M^T, B^T], [M, Q, 0], [B, 0, -delta I]]      (order u, x, z)
+// which leaves Q - M R^{-1} M^T in the (x, x) block, -B R^{-1} M^T in the
+// (z, x) block and -(delta I + B R^{-1} B^T) in the (z, z) block. Element i
+// is (P, A, C) = (Q - M R^{-1} M^T, A - B R^{-1} M^T, delta I + B R^{-1} B^T);
+// block N holds the terminal element (Q_N, 0, 0). The sweep is float64.
+template <int TX, int TW, int NW>
+__global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
+  constexpr int NX = 16 * TX, NWD = 16 * TW, CW = (TW * TW + NW - 1) / NW;
+  const int b = a.insts[blockIdx.y];
+  const InstMeta mt = a.meta[b];
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const int i = blockIdx.x;
+  if (i > N) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  float* __restrict__ e = a.elems + (a.eoff[blockIdx.y] + i) * 3 * NX * NX;
+  // zero the padding of the element tiles (rows or columns >= n)
+  for (int x = tid; x < NX * NX; x += 64 * NW) {
+    const int r = x / NX, c = x % NX;
+    if (r >= n || c >= n) {
+      e[x] = 0.0f;
+      e[NX * NX + x] = 0.0f;
+      e[2 * NX * NX + x] = 0.0f;
+    }
+  }
+  if (i == N) {  // terminal element
+    const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
+    for (int x = tid; x < n * n; x += 64 * NW) {
+      const int r = x / n, c = x % n;
+      e[r * NX + c] = (float)QN[x];
+      e[NX * NX + r * NX + c] = 0.0f;
+      e[2 * NX * NX + r * NX + c] = 0.0f;
+    }
+    return;
+  }
+  const double delta = a.delta[b];
+  const double* Q = a.Q + mt.oQ + (int64_t)i * n * n;
+  const double* M = a.M + mt.oM + (int64_t)i * n * m;
+  const double* R = a.R + mt.oR + (int64_t)i * m * m;
+  const double* A = a.A + mt.oA + (int64_t)i * n * n;
+  const double* B = a.B + mt.oB + (int64_t)i * n * m;
+  __shared__ double colbuf[2 * NWD];
+  __shared__ double red[NW];
+  int bi[CW], bj[CW];
+  bool ok[CW];
+  double X[CW][4];
+  const int D = m + 2 * n;
+#pragma unroll
+  for (int t = 0; t < CW; ++t) {
+    const int bz = w + NW * t;
+    ok[t] = bz < TW * TW;
+    bi[t] = ok[t] ? bz / TW : 0;
+    bj[t] = ok[t] ? bz % TW : 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
+      double x = 0.0;
+      if (ok[t] && r < D && c < D) {
+        const int rb = r < m ? 0 : (r < m + n ? 1 : 2), cbk = c < m ? 0 : (c < m + n ? 1 : 2);
+        const int rr = rb == 0 ? r : (rb == 1 ? r - m : r - m - n);
+        const int cc = cbk == 0 ? c : (cbk == 1 ? c - m : c - m - n);
+        if (rb == 0 && cbk == 0) x = R[rr * m + cc];
+        else if (rb == 0 && cbk == 1) x = M[cc * m + rr];
+        else if (rb == 0 && cbk == 2) x = B[cc * m + rr];
+        else if (rb == 1 && cbk == 0) x = M[rr * m + cc];
+        else if (rb == 1 && cbk == 1) x = Q[rr * n + cc];
+        else if (rb == 2 && cbk == 0) x = B[rr * m + cc];
+        else if (rb == 2 && cbk == 2) x = (rr == cc) ? -delta : 0.0;
+      }
+      X[t][v] = x;
+    }
+  }
+  // sweep the R block (pivots 0..m-1); a zero pivot makes the instance unfit for the scan
+  double sc = 0.0;
+#pragma unroll
+  for (int t = 0; t < CW; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
+      if (ok[t] && r == c && r < m) sc = fmax(sc, fabs(X[t][v]));
+    }
+  sc = wave_max(sc);
+  __syncthreads();
+  if (lane == 0) red[w] = sc;
+  __syncthreads();
+  sc = red[0];
+  for (int q = 1; q < NW; ++q) sc = fmax(sc, red[q]);
+  PivStats ps;
+  ps.init();
+  for (int j = 0; j < m; ++j) {
+    double* cb = colbuf + NWD * (j & 1);
+    const int jb = j >> 4, jj = j & 15;
+#pragma unroll
+    for (int t = 0; t < CW; ++t)
+      if (ok[t] && bj[t] == jb && col == jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cb[16 * bi[t] + 4 * grp + v] = X[t][v];
+    __syncthreads();
+    const double d = cb[j];
+    const bool zero = !(fabs(d) > 1.0e3 * m * 2.220446049250313e-16 * sc);
+    ps.nzero += zero ? 1 : 0;
+    const double rd = zero ? 0.0 : 1.0 / d;
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+      if (!ok[t]) continue;
+      const int c = 16 * bj[t] + col;
+      const double cc = cb[c];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * bi[t] + 4 * grp + v;
+        const double ci = cb[r];
+        const double gen = __fma_rn(-(ci * cc), rd, X[t][v]);
+        X[t][v] = (r == j) ? ((c == j) ? -rd : cc * rd) : ((c == j) ? ci * rd : gen);
+      }
+    }
+  }
+  if (ps.nzero && tid == 0) a.bad[b] = 1;
+  // scatter the blocks of interest into the element
+#pragma unroll
+  for (int t = 0; t < CW; ++t) {
+    if (!ok[t]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
+      if (c < m || c >= m + n || r < m || r >= D) continue;  // only columns x
+      const int cx = c - m;
+      if (r < m + n) {
+        const int rx = r - m;
+        e[rx * NX + cx] = (float)X[t][v];                                  // P
+      } else {
+        const int rz = r - m - n;
+        e[NX * NX + rz * NX + cx] = (float)(A[rz * n + cx] + X[t][v]);     // A
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
+      if (r >= m + n && r < D && c >= m + n && c < D)
+        e[2 * NX * NX + (r - m - n) * NX + (c - m - n)] = (float)(-X[t][v]);  // C
+    }
+  }
+}
+
+// Fold the elements of chunk c = blockIdx.x (elements [c L, min(c L + L, N + 1)))
+// into one aggregate, left to right: acc = acc (+) e_next.
+template <int TX, int NW>
+__global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
+  using C = ScanCfg<TX, NW>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  ScanLds<TX, NW>& s = *reinterpret_cast<ScanLds<TX, NW>*>(smem);
+  const int b = a.insts[blockIdx.y];
+  const InstMeta mt = a.meta[b];
+  const int N = mt.N, n = mt.n;
+  const int c = blockIdx.x, L = a.chunk;
+  const int e0 = c * L, e1 = min(e0 + L, N + 1);
+  if (e0 > N) return;
+  const float* elems = a.elems + a.eoff[blockIdx.y] * C::ELEM;
+  const int tid = threadIdx.x;
+  if (tid == 0) s.piv = 0;
+  load_elem<TX, NW>(s.P1, s.A1, s.C1, elems + (int64_t)e0 * C::ELEM, tid);
+  __syncthreads();
+  bool ok = true;
+  for (int k = e0 + 1; k < e1; ++k) {
+    const float* en = elems + (int64_t)k * C::ELEM;
+    load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
+    __syncthreads();
+    ok &= combine<TX, NW>(s, en + 2 * C::NX * C::NX, n, tid);
+  }
+  store_elem<TX, NW>(a.aggr_out + (a.aoff[blockIdx.y] + c) * C::ELEM, s.P1, s.A1, s.C1, tid);
+  if (!ok && tid == 0) a.bad[b] = 1;
+}
+
+// One Hillis-Steele level of the reverse scan over chunk aggregates:
+// out[c] = in[c] (+) in[c + d] for c + d < NC, else out[c] = in[c].
+template <int TX, int NW>
+__global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
+  using C = ScanCfg<TX, NW>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  ScanLds<TX, NW>& s = *reinterpret_cast<ScanLds<TX, NW>*>(smem);
+  const int b = a.insts[blockIdx.y];
+  const InstMeta mt = a.meta[b];
+  const int n = mt.n;
+  const int nch = (mt.N + 1 + a.chunk - 1) / a.chunk;
+  const int c = blockIdx.x, d = a.dist;
+  if (c >= nch) return;
+  const float* in = a.aggr_in + a.aoff[blockIdx.y] * C::ELEM;
+  float* out = a.aggr_out + a.aoff[blockIdx.y] * C::ELEM;
+  const int tid = threadIdx.x;
+  if (tid == 0) s.piv = 0;
+  load_elem<TX, NW>(s.P1, s.A1, s.C1, in + (int64_t)c * C::ELEM, tid);
+  __syncthreads();
+  if (c + d < nch) {
+    const float* en = in + (int64_t)(c + d) * C::ELEM;
+    load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
+    __syncthreads();
+    if (!combine<TX, NW>(s, en + 2 * C::NX * C::NX, n, tid) && tid == 0) a.bad[b] = 1;
+  }
+  store_elem<TX, NW>(out + (int64_t)c * C::ELEM, s.P1, s.A1, s.C1, tid);
+}
+
+template <int TX, int NW>
+static size_t scan_lds_bytes() { return sizeof(ScanLds<TX, NW>); }
+
+template <int TX, int TW, int NW>
+static hipError_t launch_scan_init_t(const ScanArgs& a, int ninst, hipStream_t st) {
+  hipLaunchKernelGGL((k_scan_init<TX, TW, NW>), dim3(a.maxN + 1, ninst), dim3(64 * NW), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int TX, int NW>
+static hipError_t launch_scan_tree_t(ScanArgs a, int ninst, hipStream_t st) {
+  const size_t lds = scan_lds_bytes<TX, NW>();
+  hipError_t e = hipFuncSetAttribute((const void*)k_scan_reduce<TX, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_scan_level<TX, NW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  a.aggr_out = a.aggr[0];
+  hipLaunchKernelGGL((k_scan_reduce<TX, NW>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int cur = 0;
+  for (int d = 1; d < a.maxchunks; d *= 2) {
+    a.aggr_in = a.aggr[cur];
+    a.aggr_out = a.aggr[cur ^ 1];
+    a.dist = d;
+    hipLaunchKernelGGL((k_scan_level<TX, NW>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    cur ^= 1;
+  }
+  return hipSuccess;
+}
+
+// Dispatch on the state tile size (tx = NX / 16) and the tile count tw of
+// the u-elimination matrix (m + 2n rows): n <= 16 gives m + 2n <= 112, n <= 32
+// gives <= 128, n <= 64 gives <= 160.
+hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tw, hipStream_t st) {
+  if (ninst <= 0) return hipSuccess;
+  if (ninst > 65535) return hipErrorInvalidValue;  // grid y limit
+  if (tx == 1) {
+    if (tw <= 2) return launch_scan_init_t<1, 2, 4>(a, ninst, st);
+    if (tw <= 4) return launch_scan_init_t<1, 4, 8>(a, ninst, st);
+    if (tw <= 7) return launch_scan_init_t<1, 7, 16>(a, ninst, st);
+  } else if (tx == 2) {
+    if (tw <= 4) return launch_scan_init_t<2, 4, 8>(a, ninst, st);
+    if (tw <= 6) return launch_scan_init_t<2, 6, 12>(a, ninst, st);
+    if (tw <= 8) return launch_scan_init_t<2, 8, 16>(a, ninst, st);
+  } else if (tx == 4) {
+    if (tw <= 6) return launch_scan_init_t<4, 6, 12>(a, ninst, st);
+    if (tw <= 8) return launch_scan_init_t<4, 8, 16>(a, ninst, st);
+    if (tw <= 10) return launch_scan_init_t<4, 10, 16>(a, ninst, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// the ping-pong buffer holding the finished suffix scan
+int scan_result_buffer(int maxchunks) {
+  int cur = 0;
+  for (int d = 1; d < maxchunks; d *= 2) cur ^= 1;
+  return cur;
+}
+
+hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, hipStream_t st) {
+  if (ninst <= 0) return hipSuccess;
+  if (ninst > 65535) return hipErrorInvalidValue;  // grid y limit
+  if (tx == 1) return launch_scan_tree_t<1, 4>(a, ninst, st);
+  if (tx == 2) return launch_scan_tree_t<2, 4>(a, ninst, st);
+  if (tx == 4) return launch_scan_tree_t<4, 16>(a, ninst, st);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ segment transfer
+
+// Psi = F_{hi-1} ... F_lo for the segment [lo, hi) of blockIdx.x, with
+// F_k = S_hat_{k+1}^{-1} (A_k + B_k K_k) taken from the float32 factor tiles
+// (Z_k holds -K_k in its (u, x) block, X_{k+1} holds -S_hat_{k+1}^{-1}).
+// Per stage: V = [Psi; K Psi], T = [A B] V, Psi <- -X T, float32 MFMA.
+// The last segment of an instance is skipped: no boundary chain uses it.
+template <int TX, int TZ, int NW>
+__global__ __launch_bounds__(64 * NW) void k_transfer(TransferArgs a) {
+  constexpr int NX = 16 * TX, NZ = 16 * TZ, LX = NX + 1, LZ = NZ + 1;
+  constexpr int CB = (TX * TX + NW - 1) / NW, CV = (TZ * TX + NW - 1) / NW;
+  constexpr int STAGE = (TZ * TZ + TX * TX) * 256;
+  const SegDesc sd = a.segs[blockIdx.x];
+  const InstMeta mt = a.meta[sd.inst];
+  const int N = mt.N, n = mt.n, m = mt.m;
+  if (sd.hi >= N) return;
+  const float* __restrict__ ws = reinterpret_cast<const float*>(a.ws) + mt.ows;
+  const double* __restrict__ Ag = a.A + mt.oA;
+  const double* __restrict__ Bg = a.B + mt.oB;
+  __shared__ float sPsi[NX * LX], sX[NX * LX], sT[NX * LX];
+  __shared__ float sK[NZ * LX], sV[NZ * LX];
+  __shared__ float sAB[NX * LZ];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  for (int x = tid; x < NX * LX; x += 64 * NW) {
+    const int r = x / LX, c = x % LX;
+    sPsi[x] = (r == c && r < n) ? 1.0f : 0.0f;
+  }
+  for (int x = tid; x < NZ * LX; x += 64 * NW) sK[x] = 0.0f;
+  for (int x = tid; x < NX * LZ; x += 64 * NW) sAB[x] = 0.0f;
+  __syncthreads();
+  for (int k = sd.lo; k < sd.hi; ++k) {
+    // K_k = -(Z_k)_ux from the (u, x) entries of the stage tile
+    const float* zt = ws + (int64_t)k * STAGE;
+    for (int x = tid; x < TZ * TZ * 256; x += 64 * NW) {
+      const int bz = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+      int I, J;
+      zmap<TX, TZ>(bz, I, J);
+      const int r = 16 * I + 4 * (l >> 4) + v, c = 16 * J + (l & 15);
+      if (r >= n && r < n + m && c < n) sK[r * LX + c] = -zt[x];
+    }
+    const float* xt = ws + (int64_t)(k + 1) * STAGE + TZ * TZ * 256;
+    for (int x = tid; x < TX * TX * 256; x += 64 * NW) {
+      const int bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+      const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
+      sX[r * LX + c] = (r < n && c < n) ? xt[x] : 0.0f;
+    }
+    const double* A = Ag + (int64_t)k * n * n;
+    const double* B = Bg + (int64_t)k * n * m;
+    for (int x = tid; x < n * (n + m); x += 64 * NW) {
+      const int r = x / (n + m), c = x % (n + m);
+      sAB[r * LZ + c] = (float)(c < n ? A[r * n + c] : B[r * m + (c - n)]);
+    }
+    __syncthreads();
+    // V = K Psi (rows n .. n+m-1) + Psi (rows < n)
+#pragma unroll
+    for (int t = 0; t < CV; ++t) {
+      const int bv = w + NW * t;
+      if (bv >= TZ * TX) break;
+      const int I = bv / TX, J = bv % TX;
+      f4 acc = sgemm_blk<false, TX>(sK, LX, sPsi, LX, I, J, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = arow(I, grp, v), c = 16 * J + col;
+        sV[r * LX + c] = acc[v] + (r < NX ? sPsi[r * LX + c] : 0.0f);
+      }
+    }
+    __syncthreads();
+    // T = [A B] V
+#pragma unroll
+    for (int t = 0; t < CB; ++t) {
+      const int bx = w + NW * t;
+      if (bx >= TX * TX) break;
+      const int I = bx / TX, J = bx % TX;
+      f4 acc = sgemm_blk<false, TZ>(sAB, LZ, sV, LX, I, J, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sT[arow(I, grp, v) * LX + 16 * J + col] = acc[v];
+    }
+    __syncthreads();
+    // Psi = -X T
+#pragma unroll
+    for (int t = 0; t < CB; ++t) {
+      const int bx = w + NW * t;
+      if (bx >= TX * TX) break;
+      const int I = bx / TX, J = bx % TX;
+      f4 acc = sgemm_blk<false, TX>(sX, LX, sT, LX, I, J, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sPsi[arow(I, grp, v) * LX + 16 * J + col] = -acc[v];
+    }
+    __syncthreads();
+  }
+  double* out = a.psi + mt.opsi + (int64_t)sd.s * 2 * n * n;
+  for (int x = tid; x < n * n; x += 64 * NW) {
+    const int r = x / n, c = x % n;
+    out[x] = (double)sPsi[r * LX + c];
+    out[n * n + c * n + r] = (double)sPsi[r * LX + c];
+  }
+}
+
+template <int TX, int TZ, int NW>
+static hipError_t launch_transfer_t(const TransferArgs& a, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_transfer<TX, TZ, NW>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(int cls, const TransferArgs& a, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (cls) {
+    case TILE_16: return launch_transfer_t<1, 1, 1>(a, nblocks, st);
+    case TILE_X1_Z2: return launch_transfer_t<1, 2, 2>(a, nblocks, st);
+    case TILE_X2_Z2: return launch_transfer_t<2, 2, 4>(a, nblocks, st);
+    case TILE_X2_Z3: return launch_transfer_t<2, 3, 4>(a, nblocks, st);
+    case TILE_X3_Z3: return launch_transfer_t<3, 3, 9>(a, nblocks, st);
+    case TILE_X4_Z4: return launch_transfer_t<4, 4, 16>(a, nblocks, st);
+    case TILE_X4_Z6: return launch_transfer_t<4, 6, 16>(a, nblocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Boundary chain of one instance (blockIdx.x indexes the list), one wavefront;
+// lane i < n owns entry i. Backward: p_lo(s) += Psi_s^T p_lo(s+1) for
+// s = S-2 .. 0 (p_lo(S-1) is exact: it starts from q_N). Forward:
+// xhi(s) += Psi_s xhi(s-1) for s = 1 .. S-2 (xhi(0) is exact: it starts from x_0).
+__global__ __launch_bounds__(64) void k_chain(ChainArgs a) {
+  const int b = a.insts[blockIdx.x];
+  if (a.run && !a.run[b]) return;
+  const InstMeta mt = a.meta[b];
+  const int n = mt.n, S = mt.nseg, lane = threadIdx.x;
+  if (S < 2) return;
+  __shared__ double sv[64];
+  double* vec = a.vec + mt.ovec;
+  const double* psi = a.psi + mt.opsi;
+  const int64_t n2 = (int64_t)n * n;
+  const bool own = lane < n;
+  if (!a.forward) {
+    double cur = own ? vec[(int64_t)(S - 1) * n + lane] : 0.0;
+    for (int s = S - 2; s >= 0; --s) {
+      sv[lane] = cur;
+      wave_sync();
+      const double* P = psi + (int64_t)s * 2 * n2;  // Psi_s[j][i] at j n + i
+      double acc = own ? vec[(int64_t)s * n + lane] : 0.0;
+      if (own)
+        for (int j = 0; j < n; ++j) acc = fma(P[(int64_t)j * n + lane], sv[j], acc);
+      if (own) vec[(int64_t)s * n + lane] = acc;
+      cur = acc;
+      wave_sync();
+    }
+  } else {
+    double cur = own ? vec[lane] : 0.0;
+    for (int s = 1; s <= S - 2; ++s) {
+      sv[lane] = cur;
+      wave_sync();
+      const double* PT = psi + (int64_t)s * 2 * n2 + n2;  // Psi_s[i][j] at j n + i
+      double acc = own ? vec[(int64_t)s * n + lane] : 0.0;
+      if (own)
+        for (int j = 0; j < n; ++j) acc = fma(PT[(int64_t)j * n + lane], sv[j], acc);
+      if (own) vec[(int64_t)s * n + lane] = acc;
+      cur = acc;
+      wave_sync();
+    }
+  }
+}
+
+hipError_t launch_chain(const ChainArgs& a, int ninst, hipStream_t st) {
+  if (ninst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chain, dim3(ninst), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace rlqr

@@ -2,8 +2,9 @@
 
 Argument marshalling only: every step of the solve runs in the HIP kernels of
 librlqr.so. torch tensors provide device memory and the stream. The functions
-rlqr_create, rlqr_factor, rlqr_solve, rlqr_pivot_inertia, rlqr_residual and
-rlqr_destroy carry the C names; `Solver` wraps one handle.
+rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_solve,
+rlqr_pivot_inertia, rlqr_residual and rlqr_destroy carry the C names; `Solver`
+wraps one handle.
 
 If librlqr.so is missing this module raises at import: there is no fallback.
 """
@@ -26,11 +27,10 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 RLQR_OK, RLQR_E_INVALID, RLQR_E_NOMEM, RLQR_E_HIP, RLQR_E_STATE, RLQR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-RLQR_SEQ_FP64, RLQR_SEQ_MIXED = 0, 1
+RLQR_SEQ_FP64, RLQR_SEQ_MIXED, RLQR_SCAN_FP32 = 0, 1, 2
 INST_OK, INST_NOT_PD, INST_SINGULAR, INST_NOT_CONVERGED = 0, 1, 2, 3
 ARRAYS = ("Q", "M", "R", "A", "B", "q", "r", "c", "x", "u", "y", "res")
-MODES = {"fp64": RLQR_SEQ_FP64, "mixed": RLQR_SEQ_MIXED}
-MAX_NXU = 16
+MODES = {"fp64": RLQR_SEQ_FP64, "mixed": RLQR_SEQ_MIXED, "scan": RLQR_SCAN_FP32}
 
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -52,8 +52,15 @@ class _Sol(ctypes.Structure):
     _fields_ = [(k, _vp) for k in ("x", "u", "y")]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("scan_chunk", ctypes.c_int32)]
+
+
 _lib.rlqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes.c_int,
                              ctypes.POINTER(ctypes.c_size_t)]
+_lib.rlqr_create_tuned.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes.c_int,
+                                   ctypes.POINTER(_Tuning), ctypes.POINTER(ctypes.c_size_t)]
+_lib.rlqr_get_tuning.argtypes = [_vp, ctypes.POINTER(_Tuning)]
 _lib.rlqr_layout_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
 _lib.rlqr_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), _vp]
 _lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
@@ -64,12 +71,12 @@ _lib.rlqr_destroy.argtypes = [_vp]
 _lib.rlqr_destroy.restype = None
 _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
-for _f in ("rlqr_create", "rlqr_layout_offsets", "rlqr_factor", "rlqr_solve",
-           "rlqr_pivot_inertia", "rlqr_residual"):
+for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
+           "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("rlqr_create", "rlqr_layout_offsets", "rlqr_factor", "rlqr_solve",
-            "rlqr_pivot_inertia", "rlqr_residual", "rlqr_destroy", "rlqr_status_string")
+EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
+            "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_destroy", "rlqr_status_string")
 
 
 class RlqrError(RuntimeError):
@@ -98,16 +105,36 @@ def _stream(stream) -> Optional[int]:
 
 # ------------------------------------------------------------- C-named calls
 
+def _shape(N, nx, nu):
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (N, nx, nu)]
+    shape = _Shape(len(arrs[0]), *(a.ctypes.data_as(_i32p) for a in arrs))
+    return shape, arrs  # keep the arrays alive for the call
+
+
 def rlqr_create(N: Sequence[int], nx: Sequence[int], nu: Sequence[int], mode: int):
     """Returns (handle, workspace_bytes)."""
-    N = np.ascontiguousarray(N, dtype=np.int32)
-    nx = np.ascontiguousarray(nx, dtype=np.int32)
-    nu = np.ascontiguousarray(nu, dtype=np.int32)
-    shape = _Shape(len(N), N.ctypes.data_as(_i32p), nx.ctypes.data_as(_i32p), nu.ctypes.data_as(_i32p))
+    shape, _keep = _shape(N, nx, nu)
     h = _vp()
     ws = ctypes.c_size_t(0)
     _check(_lib.rlqr_create(ctypes.byref(h), ctypes.byref(shape), int(mode), ctypes.byref(ws)), "rlqr_create")
     return h, int(ws.value)
+
+
+def rlqr_create_tuned(N, nx, nu, mode: int, scan_chunk: int = 0):
+    """Returns (handle, workspace_bytes)."""
+    shape, _keep = _shape(N, nx, nu)
+    h = _vp()
+    ws = ctypes.c_size_t(0)
+    t = _Tuning(int(scan_chunk))
+    _check(_lib.rlqr_create_tuned(ctypes.byref(h), ctypes.byref(shape), int(mode), ctypes.byref(t),
+                                  ctypes.byref(ws)), "rlqr_create_tuned")
+    return h, int(ws.value)
+
+
+def rlqr_get_tuning(h) -> Dict[str, int]:
+    t = _Tuning(0)
+    _check(_lib.rlqr_get_tuning(h, ctypes.byref(t)), "rlqr_get_tuning")
+    return {"scan_chunk": int(t.scan_chunk)}
 
 
 def rlqr_layout_offsets(h, array: int, batch: int) -> np.ndarray:
@@ -150,7 +177,7 @@ def rlqr_destroy(h):
 class Solver:
     """One handle over a fixed batch of shapes; tensors are torch CUDA float64."""
 
-    def __init__(self, N, nx, nu, mode: str = "fp64", device: str = "cuda:0"):
+    def __init__(self, N, nx, nu, mode: str = "fp64", device: str = "cuda:0", scan_chunk: int = 0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -160,7 +187,9 @@ class Solver:
         self.batch = int(self.N.shape[0])
         self.mode = mode
         with torch.cuda.device(self.device):
-            self.handle, self.workspace_bytes = rlqr_create(self.N, self.nx, self.nu, MODES[mode])
+            self.handle, self.workspace_bytes = rlqr_create_tuned(self.N, self.nx, self.nu, MODES[mode],
+                                                                  scan_chunk)
+        self.tuning = rlqr_get_tuning(self.handle)
         self.offsets = {name: rlqr_layout_offsets(self.handle, i, self.batch) for i, name in enumerate(ARRAYS)}
         self._lhs = None
 

@@ -1,0 +1,165 @@
+"""GPU parity of the parallel-in-time mode (RLQR_SCAN_FP32) against the FP64 oracle.
+
+The scan mode cuts each horizon into segments of L stages. The segment
+boundaries get their cost-to-go from the float32 reverse scan, every segment
+runs the float32-product recursion, and the solve joins the segments through
+their transfer matrices; refinement against the float64 residual then brings
+every instance to the requested tolerance. The gates are the ones of the
+sequential modes: relative KKT residual <= rel_tol for every instance,
+element-wise 1e-7 * max(1, |z|) against the oracle (cond(K) of these
+instances is below ~1e4), identical verdicts, first failing pivots and
+inertia. Small L (1 to 8 stages) forces many segments per instance so that
+the scan, the boundary chains and the ragged segment tails are all exercised
+at sizes the oracle finishes quickly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_16370_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2509_16370_amd import rlqr
+    return rlqr
+
+
+def run(rl, insts, mode="scan", chunk=0, rel_tol=1e-8, max_refine=3):
+    import torch
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=chunk)
+    s.factor(lhs)
+    out, status, relres = s.solve(rhs, rel_tol=rel_tol, max_refine=max_refine)
+    verdict, first_bad, inertia = s.pivot_inertia()
+    torch.cuda.synchronize()
+    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
+    B = packed.batch
+    return dict(sols=sols, status=status.cpu().numpy()[:B], relres=relres.cpu().numpy()[:B],
+                verdict=verdict.cpu().numpy()[:B], first_bad=first_bad.cpu().numpy()[:B],
+                inertia=inertia.cpu().numpy().reshape(-1, 3)[:B], solver=s)
+
+
+def compare(sol, ref, tol):
+    scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y") if ref[k].size))
+    err = max(np.abs(a - ref[k]).max() if a.size else 0.0 for a, k in zip(sol, ("x", "u", "y")))
+    assert err <= tol * scale, f"max|gpu - oracle| = {err:.3e}, scale {scale:.3e}"
+
+
+def check_against_oracle(rl, insts, res, tol=1e-7, rel_tol=1e-8):
+    for b, inst in enumerate(insts):
+        ref = oracle.seq(inst)
+        if ref["status"]:
+            assert res["status"][b] == rl.INST_SINGULAR, b
+            continue
+        ov, ofb, oin = oracle.certificate(inst, ref["dS"], ref["dG"])
+        where = (b, inst.n, inst.m, inst.N, inst.delta)
+        assert res["verdict"][b] == int(ov), where
+        assert res["first_bad"][b] == ofb, where
+        if ov:
+            assert tuple(res["inertia"][b]) == oin, where
+        assert res["relres"][b] <= rel_tol, (where, res["relres"][b])
+        assert res["status"][b] == (rl.INST_OK if ov else rl.INST_NOT_PD), where
+        if ov:
+            compare(res["sols"][b], ref, tol)
+
+
+def _ragged(seed, count, shapes):
+    rng = np.random.default_rng(seed)
+    insts = []
+    for i in range(count):
+        n, m = shapes[int(rng.integers(len(shapes)))]
+        N = int(rng.choice([0, 1, 2, 5, 17, 33, 64]))
+        delta = float(rng.choice([0.0, 1e-8, 1e-4, 1e-1]))
+        insts.append(wl.make_instance(n, m, N, delta, (70, seed, i), indefinite=bool(rng.random() < 0.2)))
+    return insts
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 8])
+def test_scan_small_stages_match_oracle(rl, chunk):
+    """One-wavefront stage tiles (n + m <= 16), element tiles of 16."""
+    print(f"[gpu] scan small stages chunk={chunk}", flush=True)
+    shapes = [(1, 1), (2, 1), (4, 2), (7, 3), (12, 4), (15, 1), (8, 8)]
+    insts = _ragged(1, 40, shapes)
+    res = run(rl, insts, chunk=chunk)
+    assert res["solver"].tuning["scan_chunk"] == chunk
+    check_against_oracle(rl, insts, res)
+
+
+@pytest.mark.parametrize("chunk", [2, 5])
+def test_scan_multiwave_classes_match_oracle(rl, chunk):
+    """Every multi-wavefront tile class and all three element tile sizes."""
+    print(f"[gpu] scan multi-wavefront classes chunk={chunk}", flush=True)
+    shapes = [(10, 12), (20, 10), (24, 20), (40, 6), (50, 14), (64, 32), (17, 3), (33, 2)]
+    insts = []
+    for ci, (n, m) in enumerate(shapes):
+        for j, (N, delta, indef) in enumerate([(0, 1e-6, False), (3, 0.0, False), (11, 1e-2, True), (23, 1e-6, False)]):
+            insts.append(wl.make_instance(n, m, N, delta, (71, ci, j), indefinite=indef))
+    res = run(rl, insts, chunk=chunk)
+    check_against_oracle(rl, insts, res)
+
+
+def test_scan_default_chunk_and_single_segment_instances(rl):
+    """Automatic L; instances with N <= L stay one segment and skip the scan,
+    the others are cut; both kinds in one batch."""
+    print("[gpu] scan default chunk", flush=True)
+    insts = [wl.make_instance(12, 4, N, 1e-6, (72, i, 0)) for i, N in enumerate([0, 4, 8, 9, 40, 300])]
+    res = run(rl, insts, chunk=0)
+    L = res["solver"].tuning["scan_chunk"]
+    assert L >= 1
+    check_against_oracle(rl, insts, res)
+
+
+def test_scan_agrees_with_sequential_modes(rl):
+    """Same batch through all three modes: identical certificates, solutions
+    within the refined tolerance of each other."""
+    print("[gpu] scan vs sequential modes", flush=True)
+    insts = _ragged(3, 24, [(4, 2), (12, 4), (20, 10)])
+    a = run(rl, insts, mode="fp64")
+    b = run(rl, insts, mode="scan", chunk=4)
+    assert np.array_equal(a["verdict"], b["verdict"])
+    assert np.array_equal(a["first_bad"], b["first_bad"])
+    ok = a["verdict"] == 1
+    assert np.array_equal(a["inertia"][ok], b["inertia"][ok])
+    for i in np.nonzero(ok)[0]:
+        ref = dict(zip(("x", "u", "y"), a["sols"][i]))
+        compare(b["sols"][i], ref, 1e-7)
+
+
+def test_scan_deterministic(rl):
+    print("[gpu] scan determinism", flush=True)
+    insts = _ragged(4, 12, [(4, 2), (24, 20)])
+    a = run(rl, insts, chunk=3)
+    b = run(rl, insts, chunk=3)
+    for sa, sb in zip(a["sols"], b["sols"]):
+        for va, vb in zip(sa, sb):
+            assert np.array_equal(va, vb, equal_nan=True)
+
+
+def test_scan_long_horizon_reduced(rl):
+    """The long-horizon shape (n = 64, m = 32, delta = 1e-6) at N = 512 with
+    32-stage segments, refined to 1e-10 as the long-horizon workload asks."""
+    print("[gpu] scan long horizon N=512", flush=True)
+    inst = wl.make_instance(64, 32, 512, 1e-6, (73, 0, 0))
+    res = run(rl, [inst], chunk=32, rel_tol=1e-10, max_refine=6)
+    check_against_oracle(rl, [inst], res, tol=1e-8, rel_tol=1e-10)
+
+
+def test_scan_long_horizon_full_size(rl):
+    """N = 16384, n = 64, m = 32 in the launch configuration the benchmark
+    times (automatic L). The oracle's own float64 residual of the returned z
+    must be <= 1e-10 relative; certificate and solution against the oracle's
+    sequential solve (about 20 s on one host core)."""
+    print("[gpu] scan long horizon N=16384", flush=True)
+    inst = wl.long_horizon()[0]
+    res = run(rl, [inst], chunk=0, rel_tol=1e-10, max_refine=6)
+    x, u, y = res["sols"][0]
+    rel = oracle.rel_residual(inst, x, u, y)
+    assert rel <= 1e-10, rel
+    assert res["relres"][0] <= 1e-10
+    check_against_oracle(rl, [inst], res, tol=1e-7, rel_tol=1e-10)
