@@ -110,12 +110,19 @@ typedef struct { double *x, *u, *y; } rlqr_sol;
 #define RLQR_MAX_NX 64
 #define RLQR_MAX_NXU 96
 
-/* Launch tuning fixed at create. */
+/* Launch tuning fixed at create (an autotuner fills the per-instance arrays
+   bucket by bucket). */
 typedef struct {
-  int32_t scan_chunk;  /* RLQR_SCAN_FP32: stages per segment L >= 1; 0 picks L
-                          from the batch (about two segments per compute unit).
-                          An instance with N <= L is one segment and skips the
-                          scan. Ignored by the sequential modes. */
+  int32_t scan_chunk;          /* RLQR_SCAN_FP32: stages per segment L >= 1; 0 picks L
+                                  from the batch (about two segments per compute unit).
+                                  An instance with N <= L is one segment and skips the
+                                  scan. Ignored by the sequential modes. */
+  const int32_t *inst_chunk;   /* [host][B] or NULL. RLQR_SCAN_FP32: per-instance L
+                                  (>= 1), or 0 for one segment (the sequential float32
+                                  recursion of RLQR_SEQ_MIXED); overrides scan_chunk. */
+  const int32_t *inst_fp64;    /* [host][B] or NULL. RLQR_SEQ_MIXED and RLQR_SCAN_FP32:
+                                  1 = factor and solve this instance in float64 only
+                                  (no float32 attempt). */
 } rlqr_tuning;
 
 /*
@@ -133,8 +140,8 @@ rlqr_status rlqr_create(rlqr_handle **h, const rlqr_shape *s, rlqr_mode mode,
 rlqr_status rlqr_create_tuned(rlqr_handle **h, const rlqr_shape *s, rlqr_mode mode,
                               const rlqr_tuning *t, size_t *workspace_bytes);
 
-/* The tuning in effect (scan_chunk resolved when it was 0) [host].
- * Errors: RLQR_E_INVALID. */
+/* The tuning in effect (scan_chunk resolved when it was 0; the per-instance
+ * pointers are returned NULL) [host]. Errors: RLQR_E_INVALID. */
 rlqr_status rlqr_get_tuning(const rlqr_handle *h, rlqr_tuning *t);
 
 /* Write the B+1 exclusive prefix offsets (in float64 elements) of array `array`
@@ -196,6 +203,26 @@ rlqr_status rlqr_pivot_inertia(rlqr_handle *h, int32_t *pd_verdict, int32_t *fir
  */
 rlqr_status rlqr_residual(rlqr_handle *h, const rlqr_rhs *rhs, const rlqr_sol *z,
                           double *res, double *inst_relres, rlqr_stream st);
+
+/*
+ * Capture rlqr_factor followed by rlqr_solve (same arguments as those calls)
+ * on stream st into a HIP graph owned by the handle, for callers that repeat
+ * the same solve on new values in the same buffers (a Newton iteration, a
+ * serving loop): one graph launch then replaces the whole launch sequence of
+ * the batch. Nothing executes during capture. A replay reads the arrays
+ * behind the captured pointers as they are at replay time; every pointer must
+ * stay valid while the graph may be launched. A new capture replaces the
+ * previous graph. st must be a created stream (not NULL: the legacy default
+ * stream cannot be captured). Errors: RLQR_E_INVALID, RLQR_E_HIP (capture or
+ * instantiation failed; the handle keeps no graph).
+ */
+rlqr_status rlqr_graph_capture(rlqr_handle *h, const rlqr_lhs *lhs, const rlqr_rhs *rhs,
+                               rlqr_sol *out, double rel_tol, int32_t max_refine,
+                               int32_t *inst_status, double *inst_relres, rlqr_stream st);
+
+/* Launch the captured graph on st (any stream). Errors: RLQR_E_INVALID,
+ * RLQR_E_STATE (nothing captured), RLQR_E_HIP. */
+rlqr_status rlqr_graph_launch(rlqr_handle *h, rlqr_stream st);
 
 /* Release the handle and its workspace (waits for the device). NULL is a no-op. */
 void rlqr_destroy(rlqr_handle *h);

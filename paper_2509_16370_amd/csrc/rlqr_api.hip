@@ -56,12 +56,11 @@ struct rlqr_handle {
   int chunk = 0;  // scan mode: stages per segment
   std::vector<int32_t> N, n, m;
   std::vector<int64_t> off[RLQR_ARR_COUNT];
-  int64_t total_stage_blocks = 0;  // sum of N_b + 1
   size_t bytes = 0;
 
   InstMeta* meta = nullptr;
-  int64_t* stage_off = nullptr;
-  int32_t* blk_inst = nullptr;  // residual slot -> instance
+  ResChunk* chunks = nullptr;     // residual work units
+  int64_t nchunks = 0;
   void* ws64 = nullptr;   // float64 tiles
   void* ws32 = nullptr;   // float32 tiles (mixed and scan modes)
   double* pk = nullptr;   // p_i / k_i scratch
@@ -93,6 +92,12 @@ struct rlqr_handle {
           *runres = nullptr, *fb = nullptr, *status = nullptr;
   double *lastrel = nullptr, *relres = nullptr;
 
+  int32_t* pref32 = nullptr;     // [B] float32 attempt allowed (mixed and scan modes)
+  bool any_pref64 = false;
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
   rlqr_lhs lhs{};
   bool factored = false;
   std::vector<void*> allocs;
@@ -110,9 +115,17 @@ static rlqr_status dev_alloc(rlqr_handle* h, void** p, size_t bytes) {
   return RLQR_OK;
 }
 
+static void drop_graph(rlqr_handle* h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+}
+
 static void release(rlqr_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
+  drop_graph(h);
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
 }
@@ -168,13 +181,21 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   // segment length: about two segments per compute unit over the whole batch
   int64_t total_elems = 0;
   for (int b = 0; b < B; ++b) total_elems += h->N[b] + 1;
-  int L = tune && tune->scan_chunk > 0 ? tune->scan_chunk : (int)std::min<int64_t>(
-                                                                std::max<int64_t>((total_elems + 511) / 512, 8), 1 << 20);
+  const int L = tune && tune->scan_chunk > 0 ? tune->scan_chunk : (int)std::min<int64_t>(
+                                                                      std::max<int64_t>((total_elems + 511) / 512, 8), 1 << 20);
   h->chunk = L;
+  std::vector<int32_t> Lb(B, L), pref64(B, 0);
+  if (tune && tune->inst_chunk)
+    for (int b = 0; b < B; ++b) {
+      if (tune->inst_chunk[b] < 0) { delete h; return RLQR_E_INVALID; }
+      Lb[b] = tune->inst_chunk[b] > 0 ? tune->inst_chunk[b] : std::max(h->N[b], 1);
+    }
+  if (tune && tune->inst_fp64 && mode != RLQR_SEQ_FP64)
+    for (int b = 0; b < B; ++b) pref64[b] = tune->inst_fp64[b] ? 1 : 0;
+  for (int b = 0; b < B; ++b) h->any_pref64 = h->any_pref64 || pref64[b];
 
   for (auto& o : h->off) o.assign(B + 1, 0);
   std::vector<InstMeta> meta(B);
-  std::vector<int64_t> stage_off(B + 1, 0);
   std::vector<int32_t> cls(B), nseg(B, 1), seg_off(B + 1, 0), whole_off(B + 1, 0), multi(B, 0), multi_list;
   std::vector<std::vector<int32_t>> lists(TILE_CLASSES);
   int64_t ws_elems = 0, pk_elems = 0, vec_elems = 0, psi_elems = 0;
@@ -186,13 +207,14 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     for (int k = 0; k < RLQR_ARR_COUNT; ++k) h->off[k][b + 1] = h->off[k][b] + cnt[k];
     cls[b] = tile_class((int)n, (int)m);
     lists[cls[b]].push_back(b);
-    if (scan && N > L) nseg[b] = (int)((N + L - 1) / L);
+    if (scan && !pref64[b] && N > Lb[b]) nseg[b] = (int)((N + Lb[b] - 1) / Lb[b]);
     if (nseg[b] > 1) {
       multi[b] = 1;
       multi_list.push_back(b);
     }
     InstMeta& mt = meta[b];
     mt.N = (int32_t)N; mt.n = (int32_t)n; mt.m = (int32_t)m; mt.nseg = nseg[b];
+    mt.chunk = Lb[b]; mt.pad = 0;
     mt.oQ = h->off[RLQR_ARR_Q][b]; mt.oM = h->off[RLQR_ARR_M][b]; mt.oR = h->off[RLQR_ARR_R][b];
     mt.oA = h->off[RLQR_ARR_A][b]; mt.oB = h->off[RLQR_ARR_B][b];
     mt.oq = h->off[RLQR_ARR_q][b]; mt.or_ = h->off[RLQR_ARR_r][b]; mt.oc = h->off[RLQR_ARR_c][b];
@@ -208,14 +230,14 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
       vec_elems += nseg[b] * n;
       psi_elems += (int64_t)nseg[b] * 2 * n * n;
     }
-    stage_off[b + 1] = stage_off[b] + N + 1;
     seg_off[b + 1] = seg_off[b] + nseg[b];
     whole_off[b + 1] = b + 1;
   }
-  h->total_stage_blocks = stage_off[B];
-  std::vector<int32_t> blk_inst(h->total_stage_blocks > 0 ? h->total_stage_blocks : 1, 0);
+  std::vector<ResChunk> chunks;
   for (int b = 0; b < B; ++b)
-    for (int64_t i = stage_off[b]; i < stage_off[b + 1]; ++i) blk_inst[i] = b;
+    for (int i0 = 0; i0 <= h->N[b]; i0 += RES_CHUNK)
+      chunks.push_back(ResChunk{b, i0, std::min(i0 + RES_CHUNK, h->N[b] + 1), 0});
+  h->nchunks = (int64_t)chunks.size();
 
   // scan groups: instances with two or more segments, by element tile size
   std::vector<int32_t> g_insts[3];
@@ -226,7 +248,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     const int g = scan_group(h->n[b]);
     ScanGroup& G = h->grp[g];
     const int N = h->N[b], n = h->n[b], m = h->m[b];
-    const int nch = (N + 1 + L - 1) / L;
+    const int nch = (N + 1 + Lb[b] - 1) / Lb[b];
     G.tx = scan_tx(n);
     G.tw = std::max(G.tw, (m + 2 * n + 15) / 16);
     G.maxN = std::max(G.maxN, N);
@@ -244,8 +266,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     if (st == RLQR_OK) st = dev_alloc(h, p, bytes);
   };
   A((void**)&h->meta, sizeof(InstMeta) * (size_t)B);
-  A((void**)&h->stage_off, sizeof(int64_t) * (size_t)(B + 1));
-  A((void**)&h->blk_inst, sizeof(int32_t) * blk_inst.size());
+  A((void**)&h->chunks, sizeof(ResChunk) * std::max<size_t>(chunks.size(), 1));
   A(&h->ws64, sizeof(double) * (size_t)ws_elems);
   if (mode != RLQR_SEQ_FP64) A(&h->ws32, sizeof(float) * (size_t)ws_elems);
   A((void**)&h->pk, sizeof(double) * (size_t)pk_elems);
@@ -268,6 +289,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   for (auto pp : i32s) A((void**)pp, sizeof(int32_t) * (size_t)B);
   A((void**)&h->lastrel, sizeof(double) * (size_t)B);
   A((void**)&h->relres, sizeof(double) * (size_t)B);
+  if (mode != RLQR_SEQ_FP64) A((void**)&h->pref32, sizeof(int32_t) * (size_t)B);
   if (scan) {
     A((void**)&h->seg_off, sizeof(int32_t) * (size_t)(B + 1));
     A((void**)&h->seg_stats, sizeof(SegStats) * (size_t)std::max(seg_off[B], 1));
@@ -307,8 +329,8 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
       for (int s2 = 0; s2 < nseg[b]; ++s2) {
         SegDesc e{};
         e.inst = b;
-        e.lo = s2 * L;
-        e.hi = nseg[b] > 1 ? std::min(e.lo + L, N) : N;
+        e.lo = s2 * Lb[b];
+        e.hi = nseg[b] > 1 ? std::min(e.lo + Lb[b], N) : N;
         e.gidx = seg_off[b] + s2;
         e.s = s2;
         e.P0 = nullptr;
@@ -332,8 +354,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     }
   }
   if (st == RLQR_OK && B > 0) {
-    bool ok = upload(h->meta, meta) && upload(h->stage_off, stage_off) && upload(h->blk_inst, blk_inst) &&
-              upload(h->whole_off, whole_off);
+    bool ok = upload(h->meta, meta) && upload(h->chunks, chunks) && upload(h->whole_off, whole_off);
     for (int c = 0; c < TILE_CLASSES && ok; ++c) {
       if (h->count[c] > 0) ok = upload(h->list[c], lists[c]) && upload(h->whole[c].d, whole_d[c]);
       if (ok && scan && h->fseg[c].count > 0) ok = upload(h->fseg[c].d, fseg_d[c]);
@@ -348,7 +369,14 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
                upload(h->grp[g].aoff, g_aoff[g]);
     }
     std::vector<int32_t> f(B, mode == RLQR_SEQ_FP64 ? 1 : 0);
+    for (int b = 0; b < B; ++b) f[b] = f[b] || pref64[b];
     if (ok) ok = upload(h->flag64, f);
+    if (ok && mode != RLQR_SEQ_FP64) {
+      std::vector<int32_t> p32(B);
+      for (int b = 0; b < B; ++b) p32[b] = pref64[b] ? 0 : 1;
+      ok = upload(h->pref32, p32);
+    }
+    if (ok && scan && scan_prepare() != hipSuccess) ok = false;
     if (!ok) st = RLQR_E_HIP;
   }
   if (st != RLQR_OK) {
@@ -368,6 +396,8 @@ rlqr_status rlqr_create(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode mode, s
 rlqr_status rlqr_get_tuning(const rlqr_handle* h, rlqr_tuning* t) {
   if (!h || !t) return RLQR_E_INVALID;
   t->scan_chunk = h->chunk;
+  t->inst_chunk = nullptr;
+  t->inst_fp64 = nullptr;
   return RLQR_OK;
 }
 
@@ -414,11 +444,12 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
     a.meta = h->meta; a.insts = G.insts; a.eoff = G.eoff; a.aoff = G.aoff;
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
     a.elems = G.elems; a.aggr[0] = G.aggr[0]; a.aggr[1] = G.aggr[1];
-    a.chunk = h->chunk; a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
+    a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
     if ((e = launch_scan_elements(a, G.ninst, G.tx, G.tw, st)) != hipSuccess) return e;
     if ((e = launch_scan_tree(a, G.ninst, G.tx, st)) != hipSuccess) return e;
   }
-  if ((e = factor_segments(h, h->fseg, h->seg_off, h->seg_stats, h->ws32, nullptr, true, st)) != hipSuccess)
+  const int32_t* run32 = h->any_pref64 ? h->pref32 : nullptr;
+  if ((e = factor_segments(h, h->fseg, h->seg_off, h->seg_stats, h->ws32, run32, true, st)) != hipSuccess)
     return e;
   for (int c = 0; c < TILE_CLASSES; ++c) {
     if (h->sseg[c].count == 0) continue;
@@ -442,11 +473,12 @@ extern "C" rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_str
   }
   // float32 products everywhere, then float64 for instances whose pivots fall
   // inside the guard band (or whose scan failed)
-  if (h->mode == RLQR_SEQ_MIXED) RLQR_TRY(factor_whole(h, h->ws32, nullptr, true, st));
+  if (h->mode == RLQR_SEQ_MIXED) RLQR_TRY(factor_whole(h, h->ws32, h->any_pref64 ? h->pref32 : nullptr, true, st));
   else RLQR_TRY(factor_scan(h, st));
   MaskArgs m{};
   m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
   m.bad = h->mode == RLQR_SCAN_FP32 ? h->bad : nullptr;
+  m.pref32 = h->any_pref64 ? h->pref32 : nullptr;
   RLQR_TRY(launch_masks(m, st));
   RLQR_TRY(factor_whole(h, h->ws64, h->flag64, false, st));
   return RLQR_OK;
@@ -470,7 +502,7 @@ static SolveArgs solve_args(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, 
 static ResidualArgs residual_args(rlqr_handle* h, const rlqr_rhs* rhs, const rlqr_sol* z, double* res,
                                   const int32_t* run) {
   ResidualArgs a{};
-  a.batch = h->B; a.meta = h->meta; a.blk_inst = h->blk_inst; a.stage_off = h->stage_off;
+  a.batch = h->B; a.meta = h->meta; a.chunks = h->chunks; a.nchunks = h->nchunks;
   a.run = run; a.skip = nullptr; a.info = h->info;
   a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
   a.q = rhs->q; a.r = rhs->r; a.c = rhs->c;
@@ -558,7 +590,7 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
   }
   if ((s = solve_whole(h, rhs, out, false, r64, corr, st)) != RLQR_OK) return s;
   ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
-  RLQR_TRY(launch_residual(ra, h->total_stage_blocks, st));
+  RLQR_TRY(launch_residual(ra, st));
   RLQR_TRY(launch_check(check_args(h, 0, tol, rres), st));
   return RLQR_OK;
 }
@@ -627,13 +659,54 @@ extern "C" rlqr_status rlqr_residual(rlqr_handle* h, const rlqr_rhs* rhs, const 
   RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->bmax), 2 * h->B, 0, st));
   ResidualArgs a = residual_args(h, rhs, z, res, nullptr);
   a.info = nullptr;  // evaluate every instance at the given z, singular ones included
-  RLQR_TRY(launch_residual(a, h->total_stage_blocks, st));
+  RLQR_TRY(launch_residual(a, st));
   if (inst_relres) {
     CheckArgs c = check_args(h, 1, 0.0, nullptr);
     c.plain = 1;
     c.relres = inst_relres;
     RLQR_TRY(launch_check(c, st));
   }
+  return RLQR_OK;
+}
+
+extern "C" rlqr_status rlqr_graph_capture(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_rhs* rhs, rlqr_sol* out,
+                                          double rel_tol, int32_t max_refine, int32_t* inst_status,
+                                          double* inst_relres, rlqr_stream stv) {
+  if (!h || !lhs || !rhs || !out || !stv) return RLQR_E_INVALID;
+  if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || !lhs->delta || !rhs->q || !rhs->r ||
+                   !rhs->c || !out->x || !out->u || !out->y))
+    return RLQR_E_INVALID;
+  if (!(rel_tol >= 0.0) || max_refine < 0) return RLQR_E_INVALID;
+  hipStream_t st = (hipStream_t)stv;
+  drop_graph(h);
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return RLQR_E_HIP;
+  }
+  rlqr_status s = rlqr_factor(h, lhs, stv);
+  if (s == RLQR_OK) s = rlqr_solve(h, rhs, out, rel_tol, max_refine, inst_status, inst_relres, stv);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (s != RLQR_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return s != RLQR_OK ? s : RLQR_E_HIP;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return RLQR_E_HIP;
+  }
+  h->graph = g;
+  h->graph_exec = x;
+  return RLQR_OK;
+}
+
+extern "C" rlqr_status rlqr_graph_launch(rlqr_handle* h, rlqr_stream stv) {
+  if (!h) return RLQR_E_INVALID;
+  if (!h->graph_exec) return RLQR_E_STATE;
+  RLQR_TRY(hipGraphLaunch(h->graph_exec, (hipStream_t)stv));
   return RLQR_OK;
 }
 

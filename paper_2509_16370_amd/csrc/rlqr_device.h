@@ -81,14 +81,6 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Symmetric pivot sweep (Gauss-Jordan on a symmetric tile) over pivots
-// j0 .. j1-1 of the tile X held in registers (accumulator layout, float64).
-// Sweeping a block S of a symmetric matrix [[X_SS, X_ST], [X_TS, X_TT]] turns
-// it into [[-X_SS^{-1}, X_SS^{-1} X_ST], [X_TS X_SS^{-1}, X_TT - X_TS X_SS^{-1} X_ST]].
-// The pivots met are the D entries of the unpivoted LDL^T of X_SS.
-// Every update is written so that exact symmetry is preserved bit for bit.
-// colbuf: 2 x 16 doubles of LDS (double-buffered pivot column).
-// code: certificate code shared by all pivots of the block. TL selects the row map.
 // LDS ordering inside a one-wavefront workgroup: the LDS unit executes one
 // wavefront's instructions in order, so a compiler-level barrier suffices.
 __device__ __forceinline__ void wave_sync() {
@@ -97,40 +89,117 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename TL>
-__device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane,
-                                        double* colbuf, PivStats& ps, int code,
-                                        double tol, double scale) {
-  const int col = lane & 15, grp = lane >> 4;
-  for (int j = j0; j < j1; ++j) {
-    double* cb = colbuf + 16 * (j & 1);
-    if (col == j) {
+// 1 / d by Newton-Raphson from the hardware estimate: each step
+// r <- r + r (1 - d r) squares the relative error, so two steps from the
+// estimate reach float64 unit roundoff (within one ulp of the rounded quotient).
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __fma_rn(-d, r, 1.0);
+  r = __fma_rn(r, e, r);
+  e = __fma_rn(-d, r, 1.0);
+  return __fma_rn(r, e, r);
+}
+
+// value of lane J of each 16-lane row, for every lane of that row (DPP row broadcast)
+template <int J>
+__device__ __forceinline__ double row_bcast(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x150 + J, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + J, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// x of lane `src` (a wave-uniform lane index), moved to scalar registers
+__device__ __forceinline__ double lane_value(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// max over the 16 lanes of each row (DPP row rotations), then over the rows
+__device__ __forceinline__ double wave_max_rows(double s) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) cb[trow<TL>(grp, v)] = X[v];
+  for (int k = 1; k < 16; k <<= 1) {
+    const long long b = __double_as_longlong(s);
+    int lo, hi;
+    switch (k) {
+      case 1: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x121, 0xf, 0xf, false);
+              hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x121, 0xf, 0xf, false); break;
+      case 2: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x122, 0xf, 0xf, false);
+              hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x122, 0xf, 0xf, false); break;
+      case 4: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x124, 0xf, 0xf, false);
+              hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x124, 0xf, 0xf, false); break;
+      default: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x128, 0xf, 0xf, false);
+               hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x128, 0xf, 0xf, false); break;
     }
-    wave_sync();
-    const double d = uniform(cb[j]);
-    const double cc = cb[col];
-    double ci[4];
+    s = fmax(s, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo));
+  }
+  return fmax(fmax(lane_value(s, 0), lane_value(s, 16)), fmax(lane_value(s, 32), lane_value(s, 48)));
+}
+
+// One pivot J of the symmetric sweep (see sweep16). Row J of the tile sits in
+// row group GJ, register VJ; column J of row group g sits in lane 16 g + J.
+template <typename TL, int J>
+__device__ __forceinline__ void sweep_pivot(double (&X)[4], int lane, double tol, double& dsave) {
+  constexpr bool F32 = trow<TL>(1, 0) == 4;
+  constexpr int GJ = F32 ? (J >> 2) : (J & 3);
+  constexpr int VJ = F32 ? (J & 3) : (J >> 2);
+  const int col = lane & 15, grp = lane >> 4;
+  const double d = lane_value(X[VJ], 16 * GJ + J);        // X[J][J]
+  const double cc = __shfl(X[VJ], 16 * GJ + col);          // X[J][col] = X[col][J]
+  double ci[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ci[v] = cb[trow<TL>(grp, v)];
-    const bool zero = !(fabs(d) > tol);
-    ps.nzero += zero ? 1 : 0;
-    ps.npos += (!zero && d > 0) ? 1 : 0;
-    ps.nneg += (!zero && d < 0) ? 1 : 0;
-    ps.first_bad = ((zero || d < 0) && ps.first_bad < 0) ? code : ps.first_bad;
-    ps.minrel = fmin(ps.minrel, fabs(d) / scale);
-    const double rd = zero ? 0.0 : 1.0 / d;
-    const double ccr = cc * rd;
+  for (int v = 0; v < 4; ++v) ci[v] = row_bcast<J>(X[v]);  // X[row(v)][J]
+  const bool nz = fabs(d) > tol;
+  dsave = (lane == J) ? d : dsave;
+  const double rd = nz ? recip(d) : 0.0;
+  const bool cj = col == J;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = trow<TL>(grp, v);
-      const double gen = __fma_rn(-(ci[v] * cc), rd, X[v]);
-      const double onrow = (col == j) ? -rd : ccr;
-      const double offrow = (col == j) ? ci[v] * rd : gen;
-      X[v] = (r == j) ? onrow : offrow;
+  for (int v = 0; v < 4; ++v) {
+    const double gen = __fma_rn(-(ci[v] * cc), rd, X[v]);
+    const double colv = ci[v] * rd;
+    if (v == VJ) {
+      const double rowv = cj ? -rd : cc * rd;
+      X[v] = (grp == GJ) ? rowv : (cj ? colv : gen);
+    } else {
+      X[v] = cj ? colv : gen;
     }
   }
+}
+
+// Symmetric pivot sweep (Gauss-Jordan on a symmetric tile) over pivots
+// j0 .. j1-1 of the tile X held in registers (accumulator layout, float64).
+// Sweeping a block S of a symmetric matrix [[X_SS, X_ST], [X_TS, X_TT]] turns
+// it into [[-X_SS^{-1}, X_SS^{-1} X_ST], [X_TS X_SS^{-1}, X_TT - X_TS X_SS^{-1} X_ST]].
+// The pivots met are the D entries of the unpivoted LDL^T of X_SS.
+// Every update is written so that exact symmetry is preserved bit for bit
+// (the product ci * cc is formed before the scaling). The pivot column moves
+// between lanes by DPP row broadcasts, the pivot row by one ds_bpermute; the
+// pivots are counted once per sweep from a ballot.
+// code: certificate code shared by all pivots of the block. TL selects the row map.
+template <typename TL>
+__device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane, PivStats& ps, int code,
+                                        double tol, double scale) {
+  double dsave = 1.0;
+#define RLQR_PIVOT(J) \
+  if (J >= j0 && J < j1) sweep_pivot<TL, J>(X, lane, tol, dsave);
+  RLQR_PIVOT(0) RLQR_PIVOT(1) RLQR_PIVOT(2) RLQR_PIVOT(3) RLQR_PIVOT(4) RLQR_PIVOT(5) RLQR_PIVOT(6)
+  RLQR_PIVOT(7) RLQR_PIVOT(8) RLQR_PIVOT(9) RLQR_PIVOT(10) RLQR_PIVOT(11) RLQR_PIVOT(12) RLQR_PIVOT(13)
+  RLQR_PIVOT(14) RLQR_PIVOT(15)
+#undef RLQR_PIVOT
+  const bool mine = lane >= j0 && lane < j1;
+  const bool zero = mine && !(fabs(dsave) > tol);
+  const bool pos = mine && !zero && dsave > 0;
+  const bool neg = mine && !zero && dsave < 0;
+  const int nz = __popcll(__ballot(zero)), np = __popcll(__ballot(pos)), nn = __popcll(__ballot(neg));
+  ps.nzero += nz;
+  ps.npos += np;
+  ps.nneg += nn;
+  ps.first_bad = ((nz + nn) > 0 && ps.first_bad < 0) ? code : ps.first_bad;
+  // smallest |pivot| of the sweep (lanes 0..15 hold the pivots)
+  const double dmin = -wave_max_rows(mine ? -fabs(dsave) : -1.0e300);
+  if (j1 > j0) ps.minrel = fmin(ps.minrel, dmin / scale);
 }
 
 // Block numbering of a stage tile Z (NZ = 16 TZ) in the multi-wavefront

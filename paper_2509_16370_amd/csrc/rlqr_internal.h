@@ -14,6 +14,7 @@ namespace rlqr {
 // per segment).
 struct InstMeta {
   int32_t N, n, m, nseg;
+  int32_t chunk, pad;  // scan mode: stages per segment and per scan chunk
   int64_t oQ, oM, oR, oA, oB, oq, or_, oc, ox, ou, oy, ores, ows, opk, ovec, opsi;
 };
 
@@ -69,12 +70,13 @@ struct ScanArgs {
   float* aggr[2];          // chunk aggregates, ping-pong
   const float* aggr_in;
   float* aggr_out;
-  int chunk, dist, maxN, maxchunks;
+  int dist, maxN, maxchunks;
   int32_t* bad;            // per instance: set when the scan cannot be used
 };
 hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tw, hipStream_t st);
 hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, hipStream_t st);
 int scan_result_buffer(int maxchunks);
+hipError_t scan_prepare();  // once per device before the first scan launch
 hipError_t launch_merge(const MergeArgs& a, hipStream_t st);
 
 // Transfer matrix of a segment [lo, hi): Psi = F_{hi-1} ... F_lo with
@@ -118,12 +120,17 @@ struct SolveArgs {
 };
 hipError_t launch_seg_solve(int cls, const SolveArgs& a, int nblocks, hipStream_t st);
 
+// RES_CHUNK consecutive stage slots [i0, i1) of one instance (slots 0..N)
+constexpr int RES_CHUNK = 16;
+struct ResChunk {
+  int32_t inst, i0, i1, pad;
+};
+
 struct ResidualArgs {
   int batch;
   const InstMeta* meta;
-  const int32_t* blk_inst;   // slot -> instance (one slot per stage i = 0..N of each instance)
-  int64_t total_slots;
-  const int64_t* stage_off;  // exclusive prefix of N_b + 1
+  const ResChunk* chunks;
+  int64_t nchunks;
   const int32_t* run;
   const int32_t* skip;       // if set, instances with skip[b] != 0 are left alone
   const FactorInfo* info;
@@ -174,7 +181,7 @@ hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, h
 hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st);
 hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st);
 hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, hipStream_t st);
-hipError_t launch_residual(const ResidualArgs& a, int64_t nblocks, hipStream_t st);
+hipError_t launch_residual(const ResidualArgs& a, hipStream_t st);
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 hipError_t launch_inertia(const InertiaArgs& a, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t st);
@@ -187,6 +194,7 @@ struct MaskArgs {
   const FactorInfo* info;
   const int32_t* status;
   const int32_t* bad;     // kind 1: instances whose scan failed also go to float64
+  const int32_t* pref32;  // kind 1: if set, instances with pref32[b] == 0 always use float64
   const int32_t* multi;   // kind 4: instances with two or more segments
   int32_t *flag64, *conv, *run32, *run64, *runres, *fb, *run1;
 };

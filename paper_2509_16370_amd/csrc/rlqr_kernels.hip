@@ -114,7 +114,7 @@ __device__ __forceinline__ double diag_scale(const double (&X)[4], int lo, int h
     const int r = trow<TL>(grp, v);
     if (r == c && r >= lo && r < hi) s = fmax(s, fabs(X[v]));
   }
-  return wave_max(s);
+  return wave_max_rows(s);
 }
 
 // ------------------------------------------------------------------ factor
@@ -211,7 +211,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   constexpr int REGION = (2 * TILE_T * (int)sizeof(TG) > TILE_T * 8) ? 2 * TILE_T * (int)sizeof(TG) : TILE_T * 8;
   __shared__ __align__(16) unsigned char work[REGION];
   __shared__ __align__(16) double stg[STG_MAX];
-  __shared__ double colbuf[32];
   TG* sP = reinterpret_cast<TG*>(work);
   TG* sX = sP + TILE_T;
   double* sD = reinterpret_cast<double*>(work);
@@ -255,7 +254,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
     {
       const double sc = diag_scale<TG>(X, 0, n, lane);
-      sweep16<TG>(X, 0, n, lane, colbuf, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
+      sweep16<TG>(X, 0, n, lane, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
     }
     tile_store(ws + (int64_t)(2 * (k + 1) + 1) * 256, X, lane);
     tile_to_lds<TG>(sP, P, lane);
@@ -309,7 +308,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // sweep the control block: G_k pivots
     {
       const double sc = diag_scale<TG>(Z, n, n + m, lane);
-      sweep16<TG>(Z, n, n + m, lane, colbuf, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
+      sweep16<TG>(Z, n, n + m, lane, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
     }
     tile_store(ws + (int64_t)(2 * k) * 256, Z, lane);
 #pragma unroll
@@ -322,7 +321,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
     const double sc = diag_scale<TG>(X, 0, n, lane);
-    sweep16<TG>(X, 0, n, lane, colbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
+    sweep16<TG>(X, 0, n, lane, ps, 0, 1.0e3 * n * eps * sc, sc);
     tile_store(ws + (int64_t)1 * 256, X, lane);
   }
   if (lane == 0) {
@@ -540,112 +539,128 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// Residual of Section "Residual Computation", float64, fully parallel over
-// (instance, stage): a fixed grid of one-wavefront blocks strides over the
-// stage slots i = 0..N of every instance (slot N also carries the terminal
-// row and the c_0 row). For n + m <= 16 a slot is three tile-vector
-// products on register tiles (Hessian [[Q, M], [M^T, R]], [A B] and its
-// transpose) -- the same scheme as the solve; larger stages use one lane per
-// row. Per-instance maxima use 64-bit atomic max (order-independent).
-__device__ __forceinline__ void residual_slot_tiles(const ResidualArgs& a, const InstMeta& mt, int b, int i,
-                                                    double* sv, double& rmax, double& bmax, int lane) {
+// Residual of Section "Residual Computation", float64, parallel over
+// (instance, chunk of stages): one wavefront walks RES_CHUNK consecutive
+// stage slots i of one instance (slot N carries the terminal row and the c_0
+// row) and keeps the instance's maxima in registers, so each chunk issues one
+// pair of 64-bit atomic max operations (order-independent). For n + m <= 16 a
+// slot is three tile-vector products on register tiles (Hessian
+// [[Q, M], [M^T, R]], [A B] and its transpose), with the operands of the next
+// slot loaded while the current one is reduced; larger stages use one lane
+// per row.
+struct ResOps {
+  double H[4], ab[4], abt[4];
+  double xi, ui, yi, yn, xn, qi, ri, cn;
+};
+
+__device__ __forceinline__ void res_load(const ResidualArgs& a, const InstMeta& mt, int i, int lane, ResOps& o) {
+  const int n = mt.n, m = mt.m;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool xr = col < n, ur = col >= n && col < n + m;
+  const double* Qi = a.Q + mt.oQ + (int64_t)i * n * n;
+  const double* Mi = a.M + mt.oM + (int64_t)i * n * m;
+  const double* Ri = a.R + mt.oR + (int64_t)i * m * m;
+  const double* Ai = a.A + mt.oA + (int64_t)i * n * n;
+  const double* Bi = a.B + mt.oB + (int64_t)i * n * m;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = 4 * grp + v;
+    o.H[v] = hess_elem(Qi, Mi, Ri, n, m, j, col);
+    o.ab[v] = ab_elem(Ai, Bi, n, m, j, col);    // [A B][j][col]
+    o.abt[v] = ab_elem(Ai, Bi, n, m, col, j);   // [A B][col][j]
+  }
+  o.xi = ld_or0(a.x + mt.ox, (int64_t)i * n + col, xr);
+  o.ui = ld_or0(a.u + mt.ou, (int64_t)i * m + (col - n), ur);
+  o.yi = ld_or0(a.y + mt.oy, (int64_t)i * n + col, xr);
+  o.yn = ld_or0(a.y + mt.oy, (int64_t)(i + 1) * n + col, xr);
+  o.xn = ld_or0(a.x + mt.ox, (int64_t)(i + 1) * n + col, xr);
+  o.qi = ld_or0(a.q + mt.oq, (int64_t)i * n + col, xr);
+  o.ri = ld_or0(a.r + mt.or_, (int64_t)i * m + (col - n), ur);
+  o.cn = ld_or0(a.c + mt.oc, (int64_t)(i + 1) * n + col, xr);
+}
+
+__device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMeta& mt, double delta, int i,
+                                            const ResOps& o, double* sv, double& rmax, double& bmax, int lane) {
   const int N = mt.N, n = mt.n, m = mt.m;
   const int col = lane & 15, grp = lane >> 4;
   const bool xr = col < n, ur = col >= n && col < n + m, own = grp == 0;
-  const double delta = a.delta[b];
-  const double* q = a.q + mt.oq; const double* r = a.r + mt.or_; const double* c = a.c + mt.oc;
-  const double* x = a.x + mt.ox; const double* u = a.u + mt.ou; const double* y = a.y + mt.oy;
   double* res = a.res ? a.res + mt.ores : nullptr;
-  if (i < N) {
-    const int ks = i;
-    const double* Qi = a.Q + mt.oQ + (int64_t)ks * n * n;
-    const double* Mi = a.M + mt.oM + (int64_t)ks * n * m;
-    const double* Ri = a.R + mt.oR + (int64_t)ks * m * m;
-    const double* Ai = a.A + mt.oA + (int64_t)ks * n * n;
-    const double* Bi = a.B + mt.oB + (int64_t)ks * n * m;
-    double H[4], ab[4], abt[4];
+  wave_sync();
+  if (own) {
+    sv[col] = xr ? o.xi : (ur ? o.ui : 0.0);
+    sv[16 + col] = xr ? o.yn : 0.0;
+  }
+  wave_sync();
+  double h = 0.0, g = 0.0, w = 0.0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = 4 * grp + v;
-      H[v] = hess_elem(Qi, Mi, Ri, n, m, j, col);
-      ab[v] = ab_elem(Ai, Bi, n, m, j, col);    // [A B][j][col]
-      abt[v] = ab_elem(Ai, Bi, n, m, col, j);   // [A B][col][j]
-    }
-    const double xi = ld_or0(x, (int64_t)i * n + col, xr);
-    const double ui = ld_or0(u, (int64_t)i * m + (col - n), ur);
-    const double yi = ld_or0(y, (int64_t)i * n + col, xr);
-    const double yn = ld_or0(y, (int64_t)(i + 1) * n + col, xr);
-    const double xn = ld_or0(x, (int64_t)(i + 1) * n + col, xr);
-    const double qi = ld_or0(q, (int64_t)i * n + col, xr);
-    const double ri = ld_or0(r, (int64_t)i * m + (col - n), ur);
-    const double cn = ld_or0(c, (int64_t)(i + 1) * n + col, xr);
-    wave_sync();
-    if (own) {
-      sv[col] = xr ? xi : (ur ? ui : 0.0);
-      sv[16 + col] = xr ? yn : 0.0;
-    }
-    wave_sync();
-    double h = 0.0, g = 0.0, w = 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = 4 * grp + v;
-      h += H[v] * sv[j];          // Hess z
-      g += ab[v] * sv[16 + j];    // [A B]^T y_{i+1}
-      w += abt[v] * sv[j];        // [A B] z
-    }
-    h = group_sum(h);
-    g = group_sum(g);
-    w = group_sum(w);
-    if (own) {
-      const int64_t base = (int64_t)i * (n + m);
-      if (xr) {
-        const double rx = h + g + qi - yi;
-        const double rd = w + cn - delta * yn - xn;
-        if (res) {
-          res[base + col] = rx;
-          res[(int64_t)N * (n + m) + 2 * n + (int64_t)i * n + col] = rd;
-        }
-        rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
-        bmax = fmax(bmax, fmax(fabs(qi), fabs(cn)));
-      }
-      if (ur) {
-        const double ru = h + g + ri;
-        if (res) res[base + col] = ru;
-        rmax = fmax(rmax, fabs(ru));
-        bmax = fmax(bmax, fabs(ri));
-      }
-    }
-  } else {
-    const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
-    double Hq[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = 4 * grp + v;
-      Hq[v] = ld_or0(QN, j * n + col, j < n && xr);
-    }
-    const double xN = ld_or0(x, (int64_t)N * n + col, xr);
-    const double yN = ld_or0(y, (int64_t)N * n + col, xr);
-    const double qN = ld_or0(q, (int64_t)N * n + col, xr);
-    const double c0 = ld_or0(c, col, xr);
-    const double x0 = ld_or0(x, col, xr);
-    const double y0 = ld_or0(y, col, xr);
-    wave_sync();
-    if (own) sv[col] = xr ? xN : 0.0;
-    wave_sync();
-    double h = 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) h += Hq[v] * sv[4 * grp + v];
-    h = group_sum(h);
-    if (own && xr) {
-      const double rt = h + qN - yN;
-      const double ri = c0 - delta * y0 - x0;
+  for (int v = 0; v < 4; ++v) {
+    const int j = 4 * grp + v;
+    h += o.H[v] * sv[j];          // Hess z
+    g += o.ab[v] * sv[16 + j];    // [A B]^T y_{i+1}
+    w += o.abt[v] * sv[j];        // [A B] z
+  }
+  h = group_sum(h);
+  g = group_sum(g);
+  w = group_sum(w);
+  if (own) {
+    const int64_t base = (int64_t)i * (n + m);
+    if (xr) {
+      const double rx = h + g + o.qi - o.yi;
+      const double rd = w + o.cn - delta * o.yn - o.xn;
       if (res) {
-        res[(int64_t)N * (n + m) + col] = rt;
-        res[(int64_t)N * (n + m) + n + col] = ri;
+        res[base + col] = rx;
+        res[(int64_t)N * (n + m) + 2 * n + (int64_t)i * n + col] = rd;
       }
-      rmax = fmax(rmax, fmax(fabs(rt), fabs(ri)));
-      bmax = fmax(bmax, fmax(fabs(qN), fabs(c0)));
+      rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
+      bmax = fmax(bmax, fmax(fabs(o.qi), fabs(o.cn)));
     }
+    if (ur) {
+      const double ru = h + g + o.ri;
+      if (res) res[base + col] = ru;
+      rmax = fmax(rmax, fabs(ru));
+      bmax = fmax(bmax, fabs(o.ri));
+    }
+  }
+}
+
+// slot N of an instance with n + m <= 16: terminal row and c_0 row
+__device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMeta& mt, double delta, double* sv,
+                                             double& rmax, double& bmax, int lane) {
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool xr = col < n, own = grp == 0;
+  const double* q = a.q + mt.oq; const double* c = a.c + mt.oc;
+  const double* x = a.x + mt.ox; const double* y = a.y + mt.oy;
+  double* res = a.res ? a.res + mt.ores : nullptr;
+  const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
+  double Hq[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = 4 * grp + v;
+    Hq[v] = ld_or0(QN, j * n + col, j < n && xr);
+  }
+  const double xN = ld_or0(x, (int64_t)N * n + col, xr);
+  const double yN = ld_or0(y, (int64_t)N * n + col, xr);
+  const double qN = ld_or0(q, (int64_t)N * n + col, xr);
+  const double c0 = ld_or0(c, col, xr);
+  const double x0 = ld_or0(x, col, xr);
+  const double y0 = ld_or0(y, col, xr);
+  wave_sync();
+  if (own) sv[col] = xr ? xN : 0.0;
+  wave_sync();
+  double h = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) h += Hq[v] * sv[4 * grp + v];
+  h = group_sum(h);
+  if (own && xr) {
+    const double rt = h + qN - yN;
+    const double ri = c0 - delta * y0 - x0;
+    if (res) {
+      res[(int64_t)N * (n + m) + col] = rt;
+      res[(int64_t)N * (n + m) + n + col] = ri;
+    }
+    rmax = fmax(rmax, fmax(fabs(rt), fabs(ri)));
+    bmax = fmax(bmax, fmax(fabs(qN), fabs(c0)));
   }
 }
 
@@ -721,16 +736,30 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
 __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
   __shared__ double sv[32];
   const int lane = threadIdx.x;
-  for (int64_t g = blockIdx.x; g < a.total_slots; g += gridDim.x) {
-    const int b = a.blk_inst[g];
+  for (int64_t g = blockIdx.x; g < a.nchunks; g += gridDim.x) {
+    const ResChunk ch = a.chunks[g];
+    const int b = ch.inst;
     if (a.run && !a.run[b]) continue;
     if (a.skip && a.skip[b]) continue;
     if (a.info && a.info[b].singular) continue;
     const InstMeta mt = a.meta[b];
-    const int i = (int)(g - a.stage_off[b]);
+    const double delta = a.delta[b];
     double rmax = 0.0, bmax = 0.0;
-    if (mt.n + mt.m <= 16) residual_slot_tiles(a, mt, b, i, sv, rmax, bmax, lane);
-    else residual_slot_rows(a, mt, b, i, rmax, bmax, lane);
+    if (mt.n + mt.m <= 16) {
+      const int iend = min(ch.i1, mt.N);  // stage slots i < N
+      ResOps o0, o1;
+      if (ch.i0 < iend) res_load(a, mt, ch.i0, lane, o0);
+      for (int i = ch.i0; i < iend; i += 2) {
+        if (i + 1 < iend) res_load(a, mt, i + 1, lane, o1);
+        res_compute(a, mt, delta, i, o0, sv, rmax, bmax, lane);
+        if (i + 1 >= iend) break;
+        if (i + 2 < iend) res_load(a, mt, i + 2, lane, o0);
+        res_compute(a, mt, delta, i + 1, o1, sv, rmax, bmax, lane);
+      }
+      if (ch.i1 > mt.N) res_terminal(a, mt, delta, sv, rmax, bmax, lane);
+    } else {
+      for (int i = ch.i0; i < ch.i1; ++i) residual_slot_rows(a, mt, b, i, rmax, bmax, lane);
+    }
     rmax = wave_max(rmax);
     bmax = wave_max(bmax);
     if (lane == 0) {
@@ -789,7 +818,8 @@ __global__ void k_masks(MaskArgs a) {
     a.runres[b] = (!c) ? 1 : 0;
   } else if (a.kind == 1) {
     const FactorInfo fi = a.info[b];
-    a.flag64[b] = (fi.singular || !(fi.minrel >= a.guard) || (a.bad && a.bad[b])) ? 1 : 0;
+    const bool fp64_only = a.pref32 && !a.pref32[b];
+    a.flag64[b] = (fp64_only || fi.singular || !(fi.minrel >= a.guard) || (a.bad && a.bad[b])) ? 1 : 0;
   } else if (a.kind == 2) {
     const int f = (!a.flag64[b] && a.status[b] == RLQR_INST_NOT_CONVERGED) ? 1 : 0;
     a.fb[b] = f;
@@ -882,12 +912,10 @@ hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const ResidualArgs& a, int64_t nslots, hipStream_t st) {
-  if (nslots <= 0) return hipSuccess;
-  ResidualArgs b = a;
-  b.total_slots = nslots;
-  const int64_t grid = nslots < 8192 ? nslots : 8192;  // 32 one-wavefront blocks per CU
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)grid), dim3(64), 0, st, b);
+hipError_t launch_residual(const ResidualArgs& a, hipStream_t st) {
+  if (a.nchunks <= 0) return hipSuccess;
+  const int64_t grid = a.nchunks < (1 << 20) ? a.nchunks : (1 << 20);
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
                                          const bool (&ok)[C], int j0, int j1, int lane, double* colbuf,
                                          PivStats& ps, int code, double tol, double scale) {
   const int col = lane & 15, grp = lane >> 4;
+  double dmin = 1.0e300;
   for (int j = j0; j < j1; ++j) {
     double* cb = colbuf + 16 * TT * (j & 1);
     const int jb = j >> 4, jj = j & 15;
@@ -81,8 +82,8 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
     else if (d > 0) ps.npos++;
     else ps.nneg++;
     if ((zero || d < 0) && ps.first_bad < 0) ps.first_bad = code;
-    ps.minrel = fmin(ps.minrel, fabs(d) / scale);
-    const double rd = zero ? 0.0 : 1.0 / d;
+    dmin = fmin(dmin, fabs(d));
+    const double rd = zero ? 0.0 : recip(d);
 #pragma unroll
     for (int t = 0; t < C; ++t) {
       if (!ok[t]) continue;
@@ -101,6 +102,7 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
       }
     }
   }
+  if (j1 > j0) ps.minrel = fmin(ps.minrel, dmin / scale);
 }
 
 template <int C, typename TL>
@@ -467,7 +469,7 @@ template <typename TG, int TX, int TZ, int NW, bool SEG>
 __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   using C = MwCfg<TG, TX, TZ, NW>;
   constexpr int NZ = C::NZ, CX = C::CX, CZ = C::CZ, CT = C::CT;
-  SegDesc sd;
+  SegDesc sd{};
   if (SEG) sd = a.segs[blockIdx.x];
   const int b = SEG ? sd.inst : (a.list ? a.list[blockIdx.x] : (int)blockIdx.x);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
@@ -569,7 +571,8 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     if (hi == N) p = xr ? qb[(int64_t)N * qs + tid] : 0.0;
     else if (phase == 1) p = 0.0;
     else p = xr ? a.plo[mt.ovec + (int64_t)(sd.s + 1) * n + tid] : 0.0;
-    if (write_pk && xr) pg[(int64_t)hi * n + tid] = p;
+    // p_hi belongs to the next segment (hi < N): only the last segment writes p_N
+    if (write_pk && xr && hi == N) pg[(int64_t)hi * n + tid] = p;
     double Zp[CZ][4];
     load_tile(Zp, ztile(hi), zo, CZ);
     for (int k = hi - 1; k >= lo; --k) {
@@ -631,7 +634,10 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     load_ab(ABt, k, true);
     const double pk = xr ? pg[(int64_t)k * n + tid] : 0.0;
     const double kk = ur ? kg[(int64_t)k * m + (tid - n)] : 0.0;
-    const double pn = xr ? pg[(int64_t)(k + 1) * n + tid] : 0.0;
+    // p_{k+1}; at a segment end (k + 1 == hi < N) the boundary value of the chain
+    const bool pbound = SEG && k + 1 == hi && hi < N;
+    const double* pnp = pbound ? a.plo + mt.ovec + (int64_t)(sd.s + 1) * n : pg + (int64_t)(k + 1) * n;
+    const double pn = xr ? pnp[tid] : 0.0;
     const double cn = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
     __syncthreads();
     if (tid < NZ) s0[tid] = xr ? x : 0.0;

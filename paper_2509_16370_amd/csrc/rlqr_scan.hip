@@ -356,7 +356,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
     const double d = cb[j];
     const bool zero = !(fabs(d) > 1.0e3 * m * 2.220446049250313e-16 * sc);
     ps.nzero += zero ? 1 : 0;
-    const double rd = zero ? 0.0 : 1.0 / d;
+    const double rd = zero ? 0.0 : recip(d);
 #pragma unroll
     for (int t = 0; t < CW; ++t) {
       if (!ok[t]) continue;
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
   const int b = a.insts[blockIdx.y];
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n;
-  const int c = blockIdx.x, L = a.chunk;
+  const int c = blockIdx.x, L = mt.chunk;
   const int e0 = c * L, e1 = min(e0 + L, N + 1);
   if (e0 > N) return;
   const float* elems = a.elems + a.eoff[blockIdx.y] * C::ELEM;
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
   const int b = a.insts[blockIdx.y];
   const InstMeta mt = a.meta[b];
   const int n = mt.n;
-  const int nch = (mt.N + 1 + a.chunk - 1) / a.chunk;
+  const int nch = (mt.N + 1 + mt.chunk - 1) / mt.chunk;
   const int c = blockIdx.x, d = a.dist;
   if (c >= nch) return;
   const float* in = a.aggr_in + a.aoff[blockIdx.y] * C::ELEM;
@@ -464,14 +464,29 @@ static hipError_t launch_scan_init_t(const ScanArgs& a, int ninst, hipStream_t s
   return hipGetLastError();
 }
 
+// The tree kernels use more than 64 KB of dynamic LDS; the limit is raised
+// once (scan_prepare, at handle creation) so that no launch path makes a
+// non-stream call (a launch sequence may be captured into a graph).
 template <int TX, int NW>
-static hipError_t launch_scan_tree_t(ScanArgs a, int ninst, hipStream_t st) {
+static hipError_t scan_prepare_t() {
   const size_t lds = scan_lds_bytes<TX, NW>();
   hipError_t e = hipFuncSetAttribute((const void*)k_scan_reduce<TX, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_scan_level<TX, NW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_scan_level<TX, NW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t scan_prepare() {
+  hipError_t e = scan_prepare_t<1, 4>();
+  if (e == hipSuccess) e = scan_prepare_t<2, 4>();
+  if (e == hipSuccess) e = scan_prepare_t<4, 16>();
+  return e;
+}
+
+template <int TX, int NW>
+static hipError_t launch_scan_tree_t(ScanArgs a, int ninst, hipStream_t st) {
+  const size_t lds = scan_lds_bytes<TX, NW>();
+  hipError_t e;
   a.aggr_out = a.aggr[0];
   hipLaunchKernelGGL((k_scan_reduce<TX, NW>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -53,7 +53,7 @@ class _Sol(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("scan_chunk", ctypes.c_int32)]
+    _fields_ = [("scan_chunk", ctypes.c_int32), ("inst_chunk", _i32p), ("inst_fp64", _i32p)]
 
 
 _lib.rlqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes.c_int,
@@ -61,6 +61,9 @@ _lib.rlqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes
 _lib.rlqr_create_tuned.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes.c_int,
                                    ctypes.POINTER(_Tuning), ctypes.POINTER(ctypes.c_size_t)]
 _lib.rlqr_get_tuning.argtypes = [_vp, ctypes.POINTER(_Tuning)]
+_lib.rlqr_graph_capture.argtypes = [_vp, ctypes.POINTER(_Lhs), ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol),
+                                    ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]
+_lib.rlqr_graph_launch.argtypes = [_vp, _vp]
 _lib.rlqr_layout_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
 _lib.rlqr_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), _vp]
 _lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
@@ -72,11 +75,12 @@ _lib.rlqr_destroy.restype = None
 _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
 for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-           "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual"):
+           "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-            "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_destroy", "rlqr_status_string")
+            "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
+            "rlqr_destroy", "rlqr_status_string")
 
 
 class RlqrError(RuntimeError):
@@ -120,12 +124,15 @@ def rlqr_create(N: Sequence[int], nx: Sequence[int], nu: Sequence[int], mode: in
     return h, int(ws.value)
 
 
-def rlqr_create_tuned(N, nx, nu, mode: int, scan_chunk: int = 0):
-    """Returns (handle, workspace_bytes)."""
+def rlqr_create_tuned(N, nx, nu, mode: int, scan_chunk: int = 0, inst_chunk=None, inst_fp64=None):
+    """Returns (handle, workspace_bytes). inst_chunk / inst_fp64: optional per-instance arrays."""
     shape, _keep = _shape(N, nx, nu)
     h = _vp()
     ws = ctypes.c_size_t(0)
-    t = _Tuning(int(scan_chunk))
+    ic = None if inst_chunk is None else np.ascontiguousarray(inst_chunk, dtype=np.int32)
+    i64 = None if inst_fp64 is None else np.ascontiguousarray(inst_fp64, dtype=np.int32)
+    t = _Tuning(int(scan_chunk), ic.ctypes.data_as(_i32p) if ic is not None else None,
+                i64.ctypes.data_as(_i32p) if i64 is not None else None)
     _check(_lib.rlqr_create_tuned(ctypes.byref(h), ctypes.byref(shape), int(mode), ctypes.byref(t),
                                   ctypes.byref(ws)), "rlqr_create_tuned")
     return h, int(ws.value)
@@ -168,6 +175,20 @@ def rlqr_residual(h, q, r, c, x, u, y, res=None, inst_relres=None, stream=None):
                               _stream(stream)), "rlqr_residual")
 
 
+def rlqr_graph_capture(h, Q, M, R, A, B, delta, q, r, c, x, u, y, rel_tol, max_refine,
+                       inst_status=None, inst_relres=None, stream=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
+    _check(_lib.rlqr_graph_capture(h, ctypes.byref(lhs), ctypes.byref(rhs), ctypes.byref(sol), float(rel_tol),
+                                   int(max_refine), _ptr(inst_status), _ptr(inst_relres), _stream(stream)),
+           "rlqr_graph_capture")
+
+
+def rlqr_graph_launch(h, stream=None):
+    _check(_lib.rlqr_graph_launch(h, _stream(stream)), "rlqr_graph_launch")
+
+
 def rlqr_destroy(h):
     _lib.rlqr_destroy(h)
 
@@ -177,7 +198,8 @@ def rlqr_destroy(h):
 class Solver:
     """One handle over a fixed batch of shapes; tensors are torch CUDA float64."""
 
-    def __init__(self, N, nx, nu, mode: str = "fp64", device: str = "cuda:0", scan_chunk: int = 0):
+    def __init__(self, N, nx, nu, mode: str = "fp64", device: str = "cuda:0", scan_chunk: int = 0,
+                 inst_chunk=None, inst_fp64=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -188,7 +210,7 @@ class Solver:
         self.mode = mode
         with torch.cuda.device(self.device):
             self.handle, self.workspace_bytes = rlqr_create_tuned(self.N, self.nx, self.nu, MODES[mode],
-                                                                  scan_chunk)
+                                                                  scan_chunk, inst_chunk, inst_fp64)
         self.tuning = rlqr_get_tuning(self.handle)
         self.offsets = {name: rlqr_layout_offsets(self.handle, i, self.batch) for i, name in enumerate(ARRAYS)}
         self._lhs = None
@@ -228,6 +250,24 @@ class Solver:
         rlqr_solve(self.handle, rhs["q"], rhs["r"], rhs["c"], out["x"], out["u"], out["y"],
                    rel_tol, max_refine, status, relres, stream=stream)
         return out, status, relres
+
+    def capture(self, lhs, rhs, out, rel_tol: float = 1e-8, max_refine: int = 0, stream=None):
+        """Capture factor + solve on `stream` (a torch.cuda.Stream, not the default
+        stream) into the handle's graph; returns (status, relres) tensors that each
+        replay refreshes."""
+        torch = self.torch
+        self._lhs = lhs
+        self._graph_args = (lhs, rhs, out)
+        status = torch.empty(max(self.batch, 1), dtype=torch.int32, device=self.device)
+        relres = torch.empty(max(self.batch, 1), dtype=torch.float64, device=self.device)
+        self._graph_out = (status, relres)
+        rlqr_graph_capture(self.handle, *(lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")),
+                           rhs["q"], rhs["r"], rhs["c"], out["x"], out["u"], out["y"], rel_tol, max_refine,
+                           status, relres, stream=stream)
+        return status, relres
+
+    def replay(self, stream=None):
+        rlqr_graph_launch(self.handle, stream=stream)
 
     def pivot_inertia(self, stream=None):
         torch = self.torch

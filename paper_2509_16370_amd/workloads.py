@@ -243,3 +243,77 @@ def pack_parallel(specs, workers: int = 8) -> Packed:
     delta = np.concatenate([r[3] for r in res])
     arrays = {k: np.concatenate([r[4][k] for r in res]) for k in ARRAYS_LHS + ARRAYS_RHS}
     return Packed(N, n, m, delta, arrays, layout_offsets(N, n, m))
+
+
+# ---------------------------------------------------------------- constrained trajectory problems
+
+@dataclasses.dataclass
+class TrajectorySet:
+    """Constrained trajectory problems sharing one model (no solver arithmetic here).
+
+    For each problem b: minimize
+        sum_{i<N} 1/2 wx |x_i - goal_b|^2 + 1/2 wu |u_i|^2 + 1/2 wN |x_N - goal_b|^2
+    subject to x_0 = x0_b, x_{i+1} = x_i + dt * tanh(A x_i + B u_i),
+    a_j^T x_i <= xmax (j = 1, 2; every stage i = 0..N) and |u_i| <= umax (componentwise).
+    """
+    n: int
+    m: int
+    N: int
+    dt: float
+    A: np.ndarray      # (n, n)
+    B: np.ndarray      # (n, m)
+    a: np.ndarray      # (2, n) unit normals of the state half-spaces
+    x0: np.ndarray     # (batch, n)
+    goal: np.ndarray   # (batch, n)
+    wx: float = 1.0
+    wu: float = 0.1
+    wN: float = 10.0
+    xmax: float = 1.5
+    umax: float = 1.0
+
+    @property
+    def batch(self) -> int:
+        return int(self.x0.shape[0])
+
+    def take(self, ids) -> "TrajectorySet":
+        ids = np.asarray(ids)
+        return dataclasses.replace(self, x0=self.x0[ids].copy(), goal=self.goal[ids].copy())
+
+
+def trajectory_model(n: int = 12, m: int = 4, seed: int = 0):
+    """Shared model: A = -I + 0.5 (W - W^T) / sqrt(n) with W ~ N(0,1) (a damped
+    rotation, so the uncontrolled flow is stable), B ~ N(0,1)/sqrt(m), and two
+    seeded unit normals a_1, a_2 of the state half-spaces."""
+    rng = _rng((4, 0, seed))
+    W = rng.standard_normal((n, n))
+    A = -np.eye(n) + 0.5 * (W - W.T) / np.sqrt(n)
+    B = rng.standard_normal((n, m)) / np.sqrt(m)
+    a = rng.standard_normal((2, n))
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    return A, B, a
+
+
+def trajectory_problems(count: int, N: int = 256, n: int = 12, m: int = 4, dt: float = 0.05,
+                        stream: int = 0, model_seed: int = 0, margin: float = 0.1,
+                        xmax: float = 0.5) -> TrajectorySet:
+    """`count` (x0, goal) pairs. x0 ~ N(0, 0.5^2 I); goal = -A^{-1} B u_g with
+    u_g ~ U(-0.5, 0.5)^m, a steady state of the dynamics held by an admissible
+    control; both rejection-sampled so that a_j^T v <= xmax - margin. Streams:
+    0 = evaluation pairs, 1 = training pairs (disjoint seed streams)."""
+    A, B, a = trajectory_model(n, m, model_seed)
+    Ainv_B = np.linalg.solve(A, B)
+    x0 = np.empty((count, n))
+    goal = np.empty((count, n))
+    for b in range(count):  # problem b depends only on (stream, model_seed, b)
+        rng = _rng((4, 2 + stream, model_seed, b))
+        while True:
+            v = 0.5 * rng.standard_normal(n)
+            if (a @ v <= xmax - margin).all():
+                x0[b] = v
+                break
+        while True:
+            v = -Ainv_B @ rng.uniform(-0.5, 0.5, m)
+            if (a @ v <= xmax - margin).all():
+                goal[b] = v
+                break
+    return TrajectorySet(n, m, N, dt, A, B, a, x0, goal, xmax=xmax)
