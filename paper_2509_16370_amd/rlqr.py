@@ -298,3 +298,96 @@ def to_device(packed, device="cuda:0"):
     lhs["delta"] = t(packed.delta)
     rhs = {k: t(packed.arrays[k]) for k in ("q", "r", "c")}
     return lhs, rhs
+
+
+# ------------------------------------------------------------- interior-point driver (include/ripm.h)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _IpmProblem(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("N", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("wx", ctypes.c_double), ("wu", ctypes.c_double),
+                ("wN", ctypes.c_double), ("xmax", ctypes.c_double), ("umax", ctypes.c_double),
+                ("A", _dp), ("B", _dp), ("a", _dp), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("lqr_mode", ctypes.c_int32)]
+
+
+_lib.ripm_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_IpmProblem), ctypes.POINTER(ctypes.c_size_t)]
+_lib.ripm_start.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.ripm_iterate.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _vp]
+_lib.ripm_solve.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp]
+_lib.ripm_solution.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.ripm_destroy.argtypes = [_vp]
+_lib.ripm_destroy.restype = None
+for _f in ("ripm_create", "ripm_start", "ripm_iterate", "ripm_solve", "ripm_solution"):
+    getattr(_lib, _f).restype = ctypes.c_int
+IPM_EXPORTED = ("ripm_create", "ripm_start", "ripm_iterate", "ripm_solve", "ripm_solution", "ripm_destroy")
+
+IPM_ETA = 1.0e3
+
+
+class IPM:
+    """Batched regularized interior-point driver over a workloads.TrajectorySet."""
+
+    def __init__(self, ts, lqr: str = "mixed", eta: float = IPM_ETA, tol: float = 1e-6, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.ts = ts
+        self.device = torch.device(device)
+        self.N, self.n, self.m = ts.N, ts.n, ts.m
+        self.ng = 2 + 2 * ts.m
+        self.batch = ts.batch
+        self._model = [np.ascontiguousarray(v, dtype=np.float64) for v in (ts.A, ts.B, ts.a)]
+        p = _IpmProblem(self.batch, ts.N, ts.n, ts.m, ts.dt, ts.wx, ts.wu, ts.wN, ts.xmax, ts.umax,
+                        *(v.ctypes.data_as(_dp) for v in self._model), float(eta), float(tol), MODES[lqr])
+        self.handle = _vp()
+        ws = ctypes.c_size_t(0)
+        with torch.cuda.device(self.device):
+            _check(_lib.ripm_create(ctypes.byref(self.handle), ctypes.byref(p), ctypes.byref(ws)), "ripm_create")
+        self.workspace_bytes = int(ws.value)
+        self.x0 = torch.from_numpy(np.ascontiguousarray(ts.x0, dtype=np.float64)).to(self.device)
+        self.goal = torch.from_numpy(np.ascontiguousarray(ts.goal, dtype=np.float64)).to(self.device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.ripm_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def warm_size(self) -> int:
+        N, n, m, ng = self.N, self.n, self.m, self.ng
+        return (N + 1) * n * 2 + N * m + (N + 1) * ng
+
+    def start(self, warm=None, stream=None):
+        """warm: None (cold) or a float64 device tensor [batch, warm_size()] of x, u, y, log z."""
+        if warm is not None:
+            assert warm.dtype == self.torch.float64 and warm.is_cuda and warm.is_contiguous()
+            assert warm.numel() == self.batch * self.warm_size()
+        _check(_lib.ripm_start(self.handle, _ptr(self.x0), _ptr(self.goal), _ptr(warm), _stream(stream)),
+               "ripm_start")
+
+    def iterate(self, stream=None) -> int:
+        act = ctypes.c_int32(0)
+        _check(_lib.ripm_iterate(self.handle, ctypes.byref(act), _stream(stream)), "ripm_iterate")
+        return int(act.value)
+
+    def solve(self, max_iter: int = 200, stream=None):
+        iters = np.zeros(self.batch, dtype=np.int32)
+        conv = np.zeros(self.batch, dtype=np.int32)
+        _check(_lib.ripm_solve(self.handle, int(max_iter), iters.ctypes.data, conv.ctypes.data, _stream(stream)),
+               "ripm_solve")
+        return iters, conv
+
+    def solution(self, stream=None):
+        torch = self.torch
+        B, N, n, m, ng = self.batch, self.N, self.n, self.m, self.ng
+        x = torch.empty(B, N + 1, n, dtype=torch.float64, device=self.device)
+        u = torch.empty(B, N, m, dtype=torch.float64, device=self.device)
+        y = torch.empty(B, N + 1, n, dtype=torch.float64, device=self.device)
+        z = torch.empty(B, N + 1, ng, dtype=torch.float64, device=self.device)
+        _check(_lib.ripm_solution(self.handle, _ptr(x), _ptr(u), _ptr(y), _ptr(z), _stream(stream)), "ripm_solution")
+        return x, u, y, z

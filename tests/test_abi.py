@@ -9,12 +9,13 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rlqr.h")
+IPM_HEADER = os.path.join(ROOT, "include", "ripm.h")
 
 
-def _declared():
-    src = open(HEADER).read()
+def _declared(path=HEADER, prefix="rlqr_"):
+    src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rlqr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -26,6 +27,43 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
     assert set(rlqr.EXPORTED) == set(names)
+
+
+def test_library_exports_every_ipm_symbol():
+    from paper_2509_16370_amd import rlqr
+    names = _declared(IPM_HEADER, "ripm_")
+    assert set(names) == set(rlqr.IPM_EXPORTED)
+    lib = ctypes.CDLL(rlqr.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_ipm_create_rejects_bad_problems():
+    from paper_2509_16370_amd import rlqr
+    lib = rlqr._lib
+    assert lib.ripm_create(None, None, None) == rlqr.RLQR_E_INVALID
+    A = np.eye(3); B = np.ones((3, 1)); a = np.ones((2, 3))
+    dp = rlqr._dp
+    good = dict(batch=2, N=4, n=3, m=1, dt=0.05, wx=1.0, wu=0.1, wN=10.0, xmax=0.5, umax=1.0, eta=1e3, tol=1e-6,
+                lqr_mode=1)
+    for bad in (dict(batch=0), dict(N=0), dict(n=30, m=3), dict(eta=0.0), dict(lqr_mode=2), dict(umax=-1.0)):
+        kw = dict(good, **bad)
+        p = rlqr._IpmProblem(kw["batch"], kw["N"], kw["n"], kw["m"], kw["dt"], kw["wx"], kw["wu"], kw["wN"],
+                             kw["xmax"], kw["umax"], A.ctypes.data_as(dp), B.ctypes.data_as(dp), a.ctypes.data_as(dp),
+                             kw["eta"], kw["tol"], kw["lqr_mode"])
+        h = rlqr._vp()
+        assert lib.ripm_create(ctypes.byref(h), ctypes.byref(p), None) == rlqr.RLQR_E_INVALID, bad
+    lib.ripm_destroy(None)
+
+
+def test_tuned_create_rejects_negative_segment_lengths():
+    from paper_2509_16370_amd import rlqr
+    with pytest.raises(rlqr.RlqrError) as e:
+        rlqr.rlqr_create_tuned([8], [3], [2], rlqr.RLQR_SCAN_FP32, scan_chunk=-1)
+    assert e.value.code == rlqr.RLQR_E_INVALID
+    with pytest.raises(rlqr.RlqrError) as e:
+        rlqr.rlqr_create_tuned([8, 9], [3, 3], [2, 2], rlqr.RLQR_SCAN_FP32, inst_chunk=[4, -2])
+    assert e.value.code == rlqr.RLQR_E_INVALID
 
 
 def test_status_strings():
@@ -57,6 +95,9 @@ def test_null_arguments_rejected():
     assert lib.rlqr_solve(None, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_pivot_inertia(None, None, None, None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_residual(None, None, None, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_graph_capture(None, None, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_graph_launch(None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_get_tuning(None, None) == rlqr.RLQR_E_INVALID
     lib.rlqr_destroy(None)
 
 
