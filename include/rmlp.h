@@ -55,6 +55,10 @@ rlqr_status rmlp_mse(int32_t dtype, int32_t M, int32_t N, const float *pred, con
 rlqr_status rmlp_adam(int32_t dtype, int64_t count, float *w, void *wq, const float *g, float *m, float *v,
                       float lr, float beta1, float beta2, float eps, int32_t t, rlqr_stream st);
 
+/* Y = X * scale + shift per column (M x N, ld = N; scale, shift [N]); Y may be X. */
+rlqr_status rmlp_affine_cols(int32_t M, int32_t N, const float *X, const float *scale, const float *shift, float *Y,
+                             rlqr_stream st);
+
 /* y = x converted to dtype (count elements). */
 rlqr_status rmlp_cast(int32_t dtype, int64_t count, const float *x, void *y, rlqr_stream st);
 

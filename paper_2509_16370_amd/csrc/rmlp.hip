@@ -202,6 +202,13 @@ __global__ void k_cast(int64_t n, const float* x, void* y) {
   if (i < n) Op<T>::store(y, i, x[i]);
 }
 
+__global__ void k_affine_cols(int64_t total, int N, const float* X, const float* scale, const float* shift, float* Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int j = (int)(i % N);
+  Y[i] = X[i] * scale[j] + shift[j];
+}
+
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -278,6 +285,17 @@ rlqr_status rmlp_adam(int32_t dtype, int64_t count, float* w, void* wq, const fl
   else
     hipLaunchKernelGGL(k_adam<uint16_t>, dim3(blocks(count)), dim3(256), 0, st, count, w, wq, g, m, v, lr, beta1,
                        beta2, eps, c1, c2);
+  RMLP_TRY(hipGetLastError());
+  return RLQR_OK;
+}
+
+rlqr_status rmlp_affine_cols(int32_t M, int32_t N, const float* X, const float* scale, const float* shift, float* Y,
+                             rlqr_stream stv) {
+  if (M < 0 || N < 0) return RLQR_E_INVALID;
+  if (M == 0 || N == 0) return RLQR_OK;
+  if (!X || !scale || !shift || !Y) return RLQR_E_INVALID;
+  const int64_t total = (int64_t)M * N;
+  hipLaunchKernelGGL(k_affine_cols, dim3(blocks(total)), dim3(256), 0, (hipStream_t)stv, total, N, X, scale, shift, Y);
   RMLP_TRY(hipGetLastError());
   return RLQR_OK;
 }

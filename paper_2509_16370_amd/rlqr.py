@@ -391,3 +391,56 @@ class IPM:
         z = torch.empty(B, N + 1, ng, dtype=torch.float64, device=self.device)
         _check(_lib.ripm_solution(self.handle, _ptr(x), _ptr(u), _ptr(y), _ptr(z), _stream(stream)), "ripm_solution")
         return x, u, y, z
+
+
+# ------------------------------------------------------------- network kernels (include/rmlp.h)
+
+RMLP_F32, RMLP_BF16 = 0, 1
+RMLP_ACT_NONE, RMLP_ACT_TANH = 0, 1
+_lib.rmlp_gemm.argtypes = [ctypes.c_int32] * 6 + [_vp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_float,
+                                                  ctypes.c_float, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+_lib.rmlp_tanh_backward.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.rmlp_colsum.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+_lib.rmlp_mse.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.rmlp_adam.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp]
+_lib.rmlp_affine_cols.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]
+_lib.rmlp_cast.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp]
+for _f in ("rmlp_gemm", "rmlp_tanh_backward", "rmlp_colsum", "rmlp_mse", "rmlp_adam", "rmlp_affine_cols", "rmlp_cast"):
+    getattr(_lib, _f).restype = ctypes.c_int
+MLP_EXPORTED = ("rmlp_gemm", "rmlp_tanh_backward", "rmlp_colsum", "rmlp_mse", "rmlp_adam", "rmlp_affine_cols",
+                "rmlp_cast")
+
+
+def rmlp_gemm(dtype, transA, transB, M, N, K, A, lda, B, ldb, alpha, beta, C, ldc, bias=None, act=0, Cq=None,
+              stream=None):
+    _check(_lib.rmlp_gemm(dtype, int(transA), int(transB), M, N, K, _ptr(A), lda, _ptr(B), ldb, float(alpha),
+                          float(beta), _ptr(C), ldc, _ptr(bias), act, _ptr(Cq), _stream(stream)), "rmlp_gemm")
+
+
+def rmlp_tanh_backward(dtype, count, dh, h, dpre, dpreq=None, stream=None):
+    _check(_lib.rmlp_tanh_backward(dtype, count, _ptr(dh), _ptr(h), _ptr(dpre), _ptr(dpreq), _stream(stream)),
+           "rmlp_tanh_backward")
+
+
+def rmlp_colsum(M, N, X, ldx, out, stream=None):
+    _check(_lib.rmlp_colsum(M, N, _ptr(X), ldx, _ptr(out), _stream(stream)), "rmlp_colsum")
+
+
+def rmlp_mse(dtype, M, N, pred, target, dpred, dpredq, loss, stream=None):
+    _check(_lib.rmlp_mse(dtype, M, N, _ptr(pred), _ptr(target), _ptr(dpred), _ptr(dpredq), _ptr(loss),
+                         _stream(stream)), "rmlp_mse")
+
+
+def rmlp_adam(dtype, count, w, wq, g, m, v, lr, beta1, beta2, eps, t, stream=None):
+    _check(_lib.rmlp_adam(dtype, count, _ptr(w), _ptr(wq), _ptr(g), _ptr(m), _ptr(v), float(lr), float(beta1),
+                          float(beta2), float(eps), int(t), _stream(stream)), "rmlp_adam")
+
+
+def rmlp_affine_cols(M, N, X, scale, shift, Y, stream=None):
+    _check(_lib.rmlp_affine_cols(M, N, _ptr(X), _ptr(scale), _ptr(shift), _ptr(Y), _stream(stream)),
+           "rmlp_affine_cols")
+
+
+def rmlp_cast(dtype, count, x, y, stream=None):
+    _check(_lib.rmlp_cast(dtype, count, _ptr(x), _ptr(y), _stream(stream)), "rmlp_cast")

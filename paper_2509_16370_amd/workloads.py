@@ -295,17 +295,18 @@ def trajectory_model(n: int = 12, m: int = 4, seed: int = 0):
 
 def trajectory_problems(count: int, N: int = 256, n: int = 12, m: int = 4, dt: float = 0.05,
                         stream: int = 0, model_seed: int = 0, margin: float = 0.1,
-                        xmax: float = 0.5) -> TrajectorySet:
+                        xmax: float = 0.5, first: int = 0) -> TrajectorySet:
     """`count` (x0, goal) pairs. x0 ~ N(0, 0.5^2 I); goal = -A^{-1} B u_g with
     u_g ~ U(-0.5, 0.5)^m, a steady state of the dynamics held by an admissible
     control; both rejection-sampled so that a_j^T v <= xmax - margin. Streams:
-    0 = evaluation pairs, 1 = training pairs (disjoint seed streams)."""
+    0 = evaluation pairs, 1 = training pairs (disjoint seed streams). Problems
+    first .. first + count - 1 of the stream are returned."""
     A, B, a = trajectory_model(n, m, model_seed)
     Ainv_B = np.linalg.solve(A, B)
     x0 = np.empty((count, n))
     goal = np.empty((count, n))
     for b in range(count):  # problem b depends only on (stream, model_seed, b)
-        rng = _rng((4, 2 + stream, model_seed, b))
+        rng = _rng((4, 2 + stream, model_seed, first + b))
         while True:
             v = 0.5 * rng.standard_normal(n)
             if (a @ v <= xmax - margin).all():

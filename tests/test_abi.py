@@ -38,6 +38,28 @@ def test_library_exports_every_ipm_symbol():
         assert hasattr(lib, name), name
 
 
+def test_library_exports_every_network_kernel_symbol():
+    from paper_2509_16370_amd import rlqr
+    names = _declared(os.path.join(ROOT, "include", "rmlp.h"), "rmlp_")
+    assert set(names) == set(rlqr.MLP_EXPORTED)
+    lib = ctypes.CDLL(rlqr.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_network_kernels_reject_bad_arguments():
+    from paper_2509_16370_amd import rlqr
+    lib = rlqr._lib
+    assert lib.rmlp_gemm(5, 0, 0, 4, 4, 4, None, 4, None, 4, 1.0, 0.0, None, 4, None, 0, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_gemm(0, 0, 0, -1, 4, 4, None, 4, None, 4, 1.0, 0.0, None, 4, None, 0, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_gemm(0, 0, 0, 4, 4, 4, None, 4, None, 4, 1.0, 0.0, None, 4, None, 0, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_gemm(0, 0, 0, 4, 4, 4, None, 4, None, 4, 1.0, 0.0, None, 4, None, 3, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_mse(0, 0, 4, None, None, None, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_adam(0, 10, None, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 0, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_cast(2, 10, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rmlp_gemm(0, 0, 0, 0, 4, 4, None, 4, None, 4, 1.0, 0.0, None, 4, None, 0, None, None) == rlqr.RLQR_OK
+
+
 def test_ipm_create_rejects_bad_problems():
     from paper_2509_16370_amd import rlqr
     lib = rlqr._lib
