@@ -14,6 +14,12 @@ not counted.
 Prints ONE JSON line. `value` is the mixed path; the plain float64 path, the
 roofline of the dominant kernel (the factorization) and the CPU oracle
 baseline are reported beside it.
+
+Other workloads (--workload): long_horizon (one instance, n=64, m=32,
+N=16384, delta=1e-6, refined to 1e-10; the parallel-in-time scan against the
+float64 sequential recursion) and batched_ragged (1024 instances,
+N ~ U{50..1000}, n in {8,16,32}, m in {2,4,8}, 20% indefinite Q, delta=1e-4;
+the autotuned single-graph launch against the float64 sequential path).
 """
 import argparse
 import json
@@ -39,21 +45,35 @@ def factor_algorithmic_bytes(n, m, elem_bytes):
     return lhs + handoff
 
 
-def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine):
-    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
-    out = {k: s.empty(k) for k in ("x", "u", "y")}
+def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_tol=REL_TOL, chunk=0, plan=None):
     stream = torch.cuda.current_stream()
+    if plan is not None:  # autotuned: one handle, one graph launch per step
+        from paper_2509_16370_amd import tune
+        tb = tune.TunedBatch(packed, plan, lhs, rhs, rel_tol=rel_tol, max_refine=max_refine)
+        s = tb.solver
 
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        s.factor(lhs)
-        if ev:
-            ev[1].record(stream)
-        res = s.solve(rhs, out=out, rel_tol=REL_TOL, max_refine=max_refine)
-        if ev:
-            ev[2].record(stream)
-        return res
+        def step(ev=None):
+            if ev:
+                ev[0].record(stream)
+                ev[1].record(stream)
+            out, st, rr = tb.run()
+            if ev:
+                ev[2].record(stream)
+            return out, st, rr
+    else:
+        s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=chunk)
+        out = {k: s.empty(k) for k in ("x", "u", "y")}
+
+        def step(ev=None):
+            if ev:
+                ev[0].record(stream)
+            s.factor(lhs)
+            if ev:
+                ev[1].record(stream)
+            res = s.solve(rhs, out=out, rel_tol=rel_tol, max_refine=max_refine)
+            if ev:
+                ev[2].record(stream)
+            return res
 
     for _ in range(warmup):
         step()
@@ -68,7 +88,7 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine):
     solve_ms = [e[1].elapsed_time(e[2]) for e in evs]
     status = status.cpu().numpy()[:packed.batch]
     relres = relres.cpu().numpy()[:packed.batch]
-    ok = (relres <= REL_TOL) & ((status == rl.INST_OK) | (status == rl.INST_NOT_PD))
+    ok = (relres <= rel_tol) & ((status == rl.INST_OK) | (status == rl.INST_NOT_PD))
     stages = int(packed.N[ok].sum())
     ms_per_step = 1e3 * wall / steps
     import numpy as np
@@ -82,11 +102,12 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine):
         median_relres=float(np.median(relres)),
         status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
         workspace_bytes=s.workspace_bytes,
+        tuning=s.tuning,
     )
 
 
-def cpu_baseline(packed, seconds_target=10.0):
-    """The FP64 oracle, as it stands, over the same batch on the host cores."""
+def cpu_baseline(packed, seconds_target=10.0, sample=None):
+    """The FP64 oracle, as it stands, over the same batch (or the named sample) on the host cores."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
@@ -101,10 +122,39 @@ def cpu_baseline(packed, seconds_target=10.0):
             break
     t = float(np.median(times))
     stages = int(packed.N.sum())
+    what = sample or f"full batch ({packed.batch} instances, {stages} stages)"
     return dict(value=stages / t, unit="stage-solves/s", cores=int(used), kind="oracle",
-                sample=f"full batch ({packed.batch} instances, {stages} stages), median of {len(times)} runs "
-                       f"of the sequential FP64 oracle, instances spread over {used} threads",
+                sample=f"{what}, median of {len(times)} runs of the sequential FP64 oracle, instances spread "
+                       f"over {used} threads",
                 seconds=t)
+
+
+def scan_factor_flops(n, m):
+    """Algorithmic flops per stage of the parallel-in-time factorization:
+    one interval combine (single inversion of I + C P and six n x n products,
+    about 16.7 n^3), the segment recursion (6.3 n^3 + 6 n^2 m + 4 n m^2 + m^3/3)
+    and the transfer-matrix product (4 n^3 + 2 n^2 m)."""
+    return 16.7 * n ** 3 + 6.3 * n ** 3 + 6 * n * n * m + 4 * n * m * m + m ** 3 / 3 + 4 * n ** 3 + 2 * n * n * m
+
+
+def load_counters(name):
+    """HBM traffic per launch from a committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.split("=", 1) for line in open(path).read().splitlines() if "=" in line and not line.startswith("#"))
+    srcs = kv.get("sources", "").split(",")
+    h = hashlib.sha256()
+    for f in srcs:
+        fp = os.path.join(ROOT, f.strip())
+        if not os.path.exists(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    if h.hexdigest() != kv.get("source_sha256", "").strip():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def main():
@@ -112,12 +162,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched_uniform",
+                    choices=["batched_uniform", "long_horizon", "batched_ragged"])
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--delta", type=float, default=1e-8)
     ap.add_argument("--max-refine", type=int, default=3)
-    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--modes", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="launch one plain 1 GiB float32 copy kernel (rmlp_cast) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batch is "
@@ -130,27 +184,88 @@ def main():
     from paper_2509_16370_amd import workloads as wl
     from paper_2509_16370_amd import rlqr as rl
 
-    n, m, N = 12, 4, 128
+    wk = args.workload
     t0 = time.perf_counter()
-    packed = wl.pack_parallel(wl.uniform_specs(batch=args.batch, n=n, m=m, N=N, delta=args.delta),
-                              workers=args.workers)
-    print(f"[bench] generated {args.batch} instances in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
-          flush=True)
+    rel_tol, max_refine = REL_TOL, args.max_refine
+    if wk == "batched_uniform":
+        n, m, N = 12, 4, 128
+        packed = wl.pack_parallel(wl.uniform_specs(batch=args.batch, n=n, m=m, N=N, delta=args.delta),
+                                  workers=args.workers)
+        modes = (args.modes or "fp64,mixed").split(",")
+        head = "mixed"
+        desc = (f"batched uniform dual-regularized LQR: {args.batch} instances, n={n}, m={m}, N={N}, "
+                f"delta={args.delta:g}, refined to {REL_TOL:g} relative KKT residual")
+        cfg = {"batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta}
+    elif wk == "long_horizon":
+        inst = wl.long_horizon()[0]
+        packed = wl.pack([inst])
+        rel_tol, max_refine = 1e-10, 6
+        modes = (args.modes or "fp64,scan").split(",")
+        head = "scan"
+        desc = ("single long-horizon dual-regularized LQR: n=64, m=32, N=16384, delta=1e-6, "
+                "refined to 1e-10 relative KKT residual; parallel-in-time scan vs float64 sequential")
+        cfg = {"batch": 1, "nx": 64, "nu": 32, "N": 16384, "delta": 1e-6}
+    else:
+        insts = wl.batched_ragged()
+        packed = wl.pack(insts)
+        args.delta = 1e-4
+        modes = (args.modes or "fp64,mixed,tuned").split(",")
+        head = "tuned"
+        desc = ("batched ragged dual-regularized LQR: 1024 instances, N ~ U{50..1000}, n in {8,16,32}, "
+                "m in {2,4,8}, 20% indefinite Q, delta=1e-4, refined to 1e-8; autotuned single-graph launch")
+        cfg = {"batch": packed.batch, "stages": int(packed.N.sum()), "delta": 1e-4}
+    print(f"[bench] generated {wk} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     lhs, rhs = rl.to_device(packed, "cuda:0")
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        cnt = 1 << 28
+        src = torch.ones(cnt, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        rl.rmlp_cast(rl.RMLP_F32, cnt, src, dst)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {cnt * 4} bytes read, {cnt * 4} bytes written", file=sys.stderr, flush=True)
+        del src, dst
 
-    modes = [md for md in args.modes.split(",") if md]
     results = {}
     for mode in modes:
-        results[mode] = run_mode(torch, rl, packed, lhs, rhs, mode, args.steps, args.warmup, args.max_refine)
+        steps, warmup = args.steps, args.warmup
+        if wk == "long_horizon" and mode != "scan":  # the sequential float64 recursion takes seconds per step
+            steps, warmup = max(1, args.steps // 10), 1
+        plan = None
+        if mode == "tuned":
+            from paper_2509_16370_amd import tune
+            t1 = time.perf_counter()
+            plan = tune.tune(packed, rel_tol=rel_tol, max_refine=max_refine, reps=2)
+            print(f"[bench] tuned {len(plan)} buckets in {time.perf_counter() - t1:.1f}s: "
+                  + ", ".join(f"{k}: {c.key()}" for k, c in plan.items()), file=sys.stderr, flush=True)
+        results[mode] = run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_tol=rel_tol,
+                                 plan=plan)
+        if plan is not None:
+            results[mode]["plan"] = {f"{k[0]},{k[1]}": c.key() for k, c in plan.items()}
         print(f"[bench] {mode}: {json.dumps(results[mode])}", file=sys.stderr, flush=True)
 
-    head = "mixed" if "mixed" in results else modes[0]
+    head = head if head in results else modes[0]
     r = results[head]
-    units = args.batch * N
-    elem = 4 if head == "mixed" else 8
-    alg_bytes = factor_algorithmic_bytes(n, m, elem) * units
-    achieved = alg_bytes / (r["factor_ms"] * 1e-3) / 1e9
+    if wk == "long_horizon":
+        flops = scan_factor_flops(64, 32) * 16384
+        achieved = flops / (r["factor_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "rlqr_factor (scan elements, chunk reduce, scan tree, segment recursion, transfer)",
+                "bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3,
+                "traffic": None, "algorithmic_flops_per_stage": scan_factor_flops(64, 32),
+                "launch_ms": r["factor_ms"]}
+        dtype = "f32+f64"
+    else:
+        elem = 8 if head == "fp64" else 4
+        alg_bytes = float(sum(factor_algorithmic_bytes(int(packed.n[b]), int(packed.m[b]), elem) * int(packed.N[b])
+                              for b in range(packed.batch)))
+        achieved = alg_bytes / (r["factor_ms"] * 1e-3) / 1e9
+        kern = "k_factor16<float>" if wk == "batched_uniform" else "rlqr_factor (all tile classes)"
+        traffic = load_counters("k_factor16_float.batched_uniform.counters.txt") if wk == "batched_uniform" else None
+        roof = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": r["factor_ms"]}
+        dtype = "f64" if head == "fp64" else "f32+f64"
+    cfg.update({"workload": desc, "rel_tol": rel_tol, "max_refine": max_refine, "path": head})
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -162,31 +277,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {
-            "workload": f"batched uniform dual-regularized LQR: {args.batch} instances, n={n}, m={m}, "
-                        f"N={N}, delta={args.delta:g}, refined to {REL_TOL:g} relative KKT residual",
-            "batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta,
-            "rel_tol": REL_TOL, "max_refine": args.max_refine, "path": head,
-        },
+        "config": cfg,
         "modes": results,
-        "roofline": {
-            "kernel": "k_factor16<float>" if head == "mixed" else "k_factor16<double>",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "algorithmic_bytes_per_stage": factor_algorithmic_bytes(n, m, elem),
-            "launch_ms": r["factor_ms"],
-        },
+        "roofline": roof,
     }
-    if "fp64" in results and "mixed" in results:
-        line["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
+    if "fp64" in results:
+        line[f"{head}_over_fp64"] = results[head]["value"] / results["fp64"]["value"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(packed)
+        if wk == "long_horizon":
+            line["cpu_baseline"] = cpu_baseline(wl.pack([wl.make_instance(64, 32, 2048, 1e-6, (3, 0, 0))]),
+                                                sample="one instance of the long-horizon shape at N=2048")
+        else:
+            line["cpu_baseline"] = cpu_baseline(packed)
     print(json.dumps(line), flush=True)
 
 

@@ -41,7 +41,7 @@ struct SegList {
 
 // Instances of one element tile size that take part in the scan.
 struct ScanGroup {
-  int tx = 0, tw = 0, ninst = 0, maxN = 0, maxchunks = 0;
+  int tx = 0, tm = 0, ninst = 0, maxN = 0, maxchunks = 0;
   int32_t* insts = nullptr;
   int64_t *eoff = nullptr, *aoff = nullptr;
   float* elems = nullptr;
@@ -250,7 +250,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     const int N = h->N[b], n = h->n[b], m = h->m[b];
     const int nch = (N + 1 + Lb[b] - 1) / Lb[b];
     G.tx = scan_tx(n);
-    G.tw = std::max(G.tw, (m + 2 * n + 15) / 16);
+    G.tm = std::max(G.tm, (m + 15) / 16);
     G.maxN = std::max(G.maxN, N);
     G.maxchunks = std::max(G.maxchunks, nch);
     g_insts[g].push_back(b);
@@ -445,7 +445,7 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
     a.elems = G.elems; a.aggr[0] = G.aggr[0]; a.aggr[1] = G.aggr[1];
     a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
-    if ((e = launch_scan_elements(a, G.ninst, G.tx, G.tw, st)) != hipSuccess) return e;
+    if ((e = launch_scan_elements(a, G.ninst, G.tx, G.tm, st)) != hipSuccess) return e;
     if ((e = launch_scan_tree(a, G.ninst, G.tx, st)) != hipSuccess) return e;
   }
   const int32_t* run32 = h->any_pref64 ? h->pref32 : nullptr;

@@ -548,27 +548,14 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
 // [[Q, M], [M^T, R]], [A B] and its transpose), with the operands of the next
 // slot loaded while the current one is reduced; larger stages use one lane
 // per row.
-struct ResOps {
-  double H[4], ab[4], abt[4];
+struct ResVec {
   double xi, ui, yi, yn, xn, qi, ri, cn;
 };
 
-__device__ __forceinline__ void res_load(const ResidualArgs& a, const InstMeta& mt, int i, int lane, ResOps& o) {
+__device__ __forceinline__ void res_load_vec(const ResidualArgs& a, const InstMeta& mt, int i, int lane, ResVec& o) {
   const int n = mt.n, m = mt.m;
-  const int col = lane & 15, grp = lane >> 4;
+  const int col = lane & 15;
   const bool xr = col < n, ur = col >= n && col < n + m;
-  const double* Qi = a.Q + mt.oQ + (int64_t)i * n * n;
-  const double* Mi = a.M + mt.oM + (int64_t)i * n * m;
-  const double* Ri = a.R + mt.oR + (int64_t)i * m * m;
-  const double* Ai = a.A + mt.oA + (int64_t)i * n * n;
-  const double* Bi = a.B + mt.oB + (int64_t)i * n * m;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int j = 4 * grp + v;
-    o.H[v] = hess_elem(Qi, Mi, Ri, n, m, j, col);
-    o.ab[v] = ab_elem(Ai, Bi, n, m, j, col);    // [A B][j][col]
-    o.abt[v] = ab_elem(Ai, Bi, n, m, col, j);   // [A B][col][j]
-  }
   o.xi = ld_or0(a.x + mt.ox, (int64_t)i * n + col, xr);
   o.ui = ld_or0(a.u + mt.ou, (int64_t)i * m + (col - n), ur);
   o.yi = ld_or0(a.y + mt.oy, (int64_t)i * n + col, xr);
@@ -579,8 +566,20 @@ __device__ __forceinline__ void res_load(const ResidualArgs& a, const InstMeta& 
   o.cn = ld_or0(a.c + mt.oc, (int64_t)(i + 1) * n + col, xr);
 }
 
+__device__ __forceinline__ void res_stage_dma(const ResidualArgs& a, const InstMeta& mt, int i, double* stg,
+                                              int lane) {
+  const int n = mt.n, m = mt.m;
+  dma_stage(stg, a.Q + mt.oQ + (int64_t)i * n * n, a.M + mt.oM + (int64_t)i * n * m,
+            a.R + mt.oR + (int64_t)i * m * m, a.A + mt.oA + (int64_t)i * n * n,
+            a.B + mt.oB + (int64_t)i * n * m, n, m, lane);
+}
+
+// Residual rows of stage i < N from the staged blocks (Hessian, [A B], [A B]^T
+// read at the per-lane staging indices) and the stage vectors.
 __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMeta& mt, double delta, int i,
-                                            const ResOps& o, double* sv, double& rmax, double& bmax, int lane) {
+                                            const double* stg, const int (&iH)[4], const int (&iAB)[4],
+                                            const int (&iABT)[4], const ResVec& o, double* sv, double& rmax,
+                                            double& bmax, int lane) {
   const int N = mt.N, n = mt.n, m = mt.m;
   const int col = lane & 15, grp = lane >> 4;
   const bool xr = col < n, ur = col >= n && col < n + m, own = grp == 0;
@@ -595,9 +594,9 @@ __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMet
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int j = 4 * grp + v;
-    h += o.H[v] * sv[j];          // Hess z
-    g += o.ab[v] * sv[16 + j];    // [A B]^T y_{i+1}
-    w += o.abt[v] * sv[j];        // [A B] z
+    h += stg[iH[v]] * sv[j];          // Hess z
+    g += stg[iAB[v]] * sv[16 + j];    // [A B]^T y_{i+1}
+    w += stg[iABT[v]] * sv[j];        // [A B] z
   }
   h = group_sum(h);
   g = group_sum(g);
@@ -735,7 +734,11 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
 
 __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
   __shared__ double sv[32];
-  const int lane = threadIdx.x;
+  // two distinct staging arrays: a direct global-to-LDS copy into one never
+  // aliases the reads of the other, so no wait is inserted before the reads
+  __shared__ __align__(16) double stgA[STG_MAX];
+  __shared__ __align__(16) double stgB[STG_MAX];
+  const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
   for (int64_t g = blockIdx.x; g < a.nchunks; g += gridDim.x) {
     const ResChunk ch = a.chunks[g];
     const int b = ch.inst;
@@ -743,18 +746,49 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
     if (a.skip && a.skip[b]) continue;
     if (a.info && a.info[b].singular) continue;
     const InstMeta mt = a.meta[b];
+    const int n = mt.n, m = mt.m;
     const double delta = a.delta[b];
     double rmax = 0.0, bmax = 0.0;
-    if (mt.n + mt.m <= 16) {
+    if (n + m <= 16) {
+      int iH[4], iAB[4], iABT[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 4 * grp + v;
+        iH[v] = stg_hess(j, col, n, m);
+        iAB[v] = stg_ab(j, col, n, m);
+        iABT[v] = stg_ab(col, j, n, m);
+      }
+      const int oZ = 2 * n * n + 2 * n * m + m * m;
       const int iend = min(ch.i1, mt.N);  // stage slots i < N
-      ResOps o0, o1;
-      if (ch.i0 < iend) res_load(a, mt, ch.i0, lane, o0);
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): earlier reads of the staging arrays returned
+      wave_sync();
+      if (lane == 0) {
+        stgA[oZ] = 0.0;
+        stgB[oZ] = 0.0;
+      }
+      ResVec v0, v1;
+      if (ch.i0 < iend) {
+        res_stage_dma(a, mt, ch.i0, stgA, lane);
+        res_load_vec(a, mt, ch.i0, lane, v0);
+      }
       for (int i = ch.i0; i < iend; i += 2) {
-        if (i + 1 < iend) res_load(a, mt, i + 1, lane, o1);
-        res_compute(a, mt, delta, i, o0, sv, rmax, bmax, lane);
+        wait_vmem();
+        wave_sync();
+        if (i + 1 < iend) {
+          res_stage_dma(a, mt, i + 1, stgB, lane);
+          res_load_vec(a, mt, i + 1, lane, v1);
+        }
+        res_compute(a, mt, delta, i, stgA, iH, iAB, iABT, v0, sv, rmax, bmax, lane);
         if (i + 1 >= iend) break;
-        if (i + 2 < iend) res_load(a, mt, i + 2, lane, o0);
-        res_compute(a, mt, delta, i + 1, o1, sv, rmax, bmax, lane);
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgA returned before it is refilled
+        wait_vmem();
+        wave_sync();
+        if (i + 2 < iend) {
+          res_stage_dma(a, mt, i + 2, stgA, lane);
+          res_load_vec(a, mt, i + 2, lane, v0);
+        }
+        res_compute(a, mt, delta, i + 1, stgB, iH, iAB, iABT, v1, sv, rmax, bmax, lane);
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgB returned before it is refilled
       }
       if (ch.i1 > mt.N) res_terminal(a, mt, delta, sv, rmax, bmax, lane);
     } else {

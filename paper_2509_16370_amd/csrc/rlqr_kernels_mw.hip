@@ -44,84 +44,6 @@ __device__ __forceinline__ void blk_to_lds(T* s, int ld, int I, int J, const dou
   for (int v = 0; v < 4; ++v) s[(16 * I + trow<TL>(grp, v)) * ld + 16 * J + col] = (T)X[v];
 }
 
-// max over the workgroup of a per-lane value (all threads get the result)
-template <int NW>
-__device__ __forceinline__ double wg_max(double v, double* red, int w, int lane) {
-  v = wave_max(v);
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double s = red[0];
-#pragma unroll
-  for (int i = 1; i < NW; ++i) s = fmax(s, red[i]);
-  return s;
-}
-
-// Symmetric sweep of pivots j0..j1-1 over a tile whose owned blocks are
-// X[t] at block coordinates (bi[t], bj[t]) (valid if ok[t]). colbuf holds
-// 2 x 16*TT doubles. Same update rules (and exact symmetry) as sweep16.
-template <typename TL, int C, int TT>
-__device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], const int (&bj)[C],
-                                         const bool (&ok)[C], int j0, int j1, int lane, double* colbuf,
-                                         PivStats& ps, int code, double tol, double scale) {
-  const int col = lane & 15, grp = lane >> 4;
-  double dmin = 1.0e300;
-  for (int j = j0; j < j1; ++j) {
-    double* cb = colbuf + 16 * TT * (j & 1);
-    const int jb = j >> 4, jj = j & 15;
-#pragma unroll
-    for (int t = 0; t < C; ++t)
-      if (ok[t] && bj[t] == jb && col == jj) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cb[16 * bi[t] + trow<TL>(grp, v)] = X[t][v];
-      }
-    __syncthreads();
-    const double d = cb[j];
-    const bool zero = !(fabs(d) > tol);
-    if (zero) ps.nzero++;
-    else if (d > 0) ps.npos++;
-    else ps.nneg++;
-    if ((zero || d < 0) && ps.first_bad < 0) ps.first_bad = code;
-    dmin = fmin(dmin, fabs(d));
-    const double rd = zero ? 0.0 : recip(d);
-#pragma unroll
-    for (int t = 0; t < C; ++t) {
-      if (!ok[t]) continue;
-      const int c = 16 * bj[t] + col;
-      const double cc = cb[c];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * bi[t] + trow<TL>(grp, v);
-        const double ci = cb[r];
-        double x;
-        if (r == j && c == j) x = -rd;
-        else if (r == j) x = cc * rd;
-        else if (c == j) x = ci * rd;
-        else x = __fma_rn(-(ci * cc), rd, X[t][v]);
-        X[t][v] = x;
-      }
-    }
-  }
-  if (j1 > j0) ps.minrel = fmin(ps.minrel, dmin / scale);
-}
-
-template <int C, typename TL>
-__device__ __forceinline__ double diag_max(const double (&X)[C][4], const int (&bi)[C], const int (&bj)[C],
-                                           const bool (&ok)[C], int lo, int hi, int lane) {
-  const int col = lane & 15, grp = lane >> 4;
-  double s = 0.0;
-#pragma unroll
-  for (int t = 0; t < C; ++t) {
-    if (!ok[t]) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * bi[t] + trow<TL>(grp, v), c = 16 * bj[t] + col;
-      if (r == c && r >= lo && r < hi) s = fmax(s, fabs(X[t][v]));
-    }
-  }
-  return s;
-}
-
 template <typename TG, int TX, int TZ, int NW>
 struct MwCfg {
   static constexpr int NX = 16 * TX, NZ = 16 * TZ;

@@ -255,15 +255,18 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
 // ------------------------------------------------------------ kernels
 
 // u-elimination (eq. lqr-gpu-init-running) for stage i = blockIdx.x of
-// instance `inst`: sweep the R block of the symmetric matrix
-//     [[R, M^T, B^T], [M, Q, 0], [B, 0, -delta I]]      (order u, x, z)
-// which leaves Q - M R^{-1} M^T in the (x, x) block, -B R^{-1} M^T in the
-// (z, x) block and -(delta I + B R^{-1} B^T) in the (z, z) block. Element i
-// is (P, A, C) = (Q - M R^{-1} M^T, A - B R^{-1} M^T, delta I + B R^{-1} B^T);
-// block N holds the terminal element (Q_N, 0, 0). The sweep is float64.
-template <int TX, int TW, int NW>
+// instance insts[blockIdx.y]. With S = [M^T | B^T] (m x 2n) the element is
+//     P = Q - M R^{-1} M^T,   A = A - B R^{-1} M^T,   C = delta I + B R^{-1} B^T,
+// i.e. the blocks of T - S^T R^{-1} S for T = [[Q, 0], [0, -delta I]]. R is
+// swept in float64 (its pivots decide whether the scan can be used: a zero
+// pivot marks the instance bad); Y = (-R^{-1}) S and S^T Y are float32 MFMA
+// products. Block N holds the terminal element (Q_N, 0, 0).
+template <int TX, int TM, int NW>
 __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
-  constexpr int NX = 16 * TX, NWD = 16 * TW, CW = (TW * TW + NW - 1) / NW;
+  constexpr int NX = 16 * TX, NM = 16 * TM, LDM = NM + 1, LDS2 = 2 * NX + 1;
+  constexpr int CR = (TM * TM + NW - 1) / NW;            // R blocks per wavefront
+  constexpr int CY = (TM * 2 * TX + NW - 1) / NW;        // Y blocks per wavefront
+  constexpr int CW = (3 * TX * TX + NW - 1) / NW;        // output blocks per wavefront
   const int b = a.insts[blockIdx.y];
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
@@ -271,22 +274,13 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
   if (i > N) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   float* __restrict__ e = a.elems + (a.eoff[blockIdx.y] + i) * 3 * NX * NX;
-  // zero the padding of the element tiles (rows or columns >= n)
-  for (int x = tid; x < NX * NX; x += 64 * NW) {
-    const int r = x / NX, c = x % NX;
-    if (r >= n || c >= n) {
-      e[x] = 0.0f;
-      e[NX * NX + x] = 0.0f;
-      e[2 * NX * NX + x] = 0.0f;
-    }
-  }
   if (i == N) {  // terminal element
     const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
-    for (int x = tid; x < n * n; x += 64 * NW) {
-      const int r = x / n, c = x % n;
-      e[r * NX + c] = (float)QN[x];
-      e[NX * NX + r * NX + c] = 0.0f;
-      e[2 * NX * NX + r * NX + c] = 0.0f;
+    for (int x = tid; x < NX * NX; x += 64 * NW) {
+      const int r = x / NX, c = x % NX;
+      e[x] = (r < n && c < n) ? (float)QN[r * n + c] : 0.0f;
+      e[NX * NX + x] = 0.0f;
+      e[2 * NX * NX + x] = 0.0f;
     }
     return;
   }
@@ -296,104 +290,82 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
   const double* R = a.R + mt.oR + (int64_t)i * m * m;
   const double* A = a.A + mt.oA + (int64_t)i * n * n;
   const double* B = a.B + mt.oB + (int64_t)i * n * m;
-  __shared__ double colbuf[2 * NWD];
+  __shared__ float sRi[NM * LDM];     // -R^{-1}
+  __shared__ float sS[NM * LDS2];     // S = [M^T | B^T], columns x at 0.., z at NX..
+  __shared__ float sY[NM * LDS2];     // Y = -R^{-1} S
+  __shared__ double colbuf[2 * NM];
   __shared__ double red[NW];
-  int bi[CW], bj[CW];
-  bool ok[CW];
-  double X[CW][4];
-  const int D = m + 2 * n;
+  // S, zero-padded
+  for (int x = tid; x < NM * 2 * NX; x += 64 * NW) {
+    const int k = x / (2 * NX), j = x % (2 * NX);
+    float v = 0.0f;
+    if (k < m) {
+      if (j < n) v = (float)M[j * m + k];
+      else if (j >= NX && j < NX + n) v = (float)B[(j - NX) * m + k];
+    }
+    sS[k * LDS2 + j] = v;
+  }
+  // R in register blocks (rows 16 bi + 4 grp + v), identity-padded, swept in float64
+  int ri[CR], rj[CR];
+  bool ro[CR];
+  double X[CR][4];
 #pragma unroll
-  for (int t = 0; t < CW; ++t) {
+  for (int t = 0; t < CR; ++t) {
     const int bz = w + NW * t;
-    ok[t] = bz < TW * TW;
-    bi[t] = ok[t] ? bz / TW : 0;
-    bj[t] = ok[t] ? bz % TW : 0;
+    ro[t] = bz < TM * TM;
+    ri[t] = ro[t] ? bz / TM : 0;
+    rj[t] = ro[t] ? bz % TM : 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
-      double x = 0.0;
-      if (ok[t] && r < D && c < D) {
-        const int rb = r < m ? 0 : (r < m + n ? 1 : 2), cbk = c < m ? 0 : (c < m + n ? 1 : 2);
-        const int rr = rb == 0 ? r : (rb == 1 ? r - m : r - m - n);
-        const int cc = cbk == 0 ? c : (cbk == 1 ? c - m : c - m - n);
-        if (rb == 0 && cbk == 0) x = R[rr * m + cc];
-        else if (rb == 0 && cbk == 1) x = M[cc * m + rr];
-        else if (rb == 0 && cbk == 2) x = B[cc * m + rr];
-        else if (rb == 1 && cbk == 0) x = M[rr * m + cc];
-        else if (rb == 1 && cbk == 1) x = Q[rr * n + cc];
-        else if (rb == 2 && cbk == 0) x = B[rr * m + cc];
-        else if (rb == 2 && cbk == 2) x = (rr == cc) ? -delta : 0.0;
-      }
-      X[t][v] = x;
+      const int r = 16 * ri[t] + trow<float>(grp, v), c = 16 * rj[t] + col;
+      X[t][v] = !ro[t] ? 0.0 : ((r < m && c < m) ? R[r * m + c] : (r == c ? 1.0 : 0.0));
     }
   }
-  // sweep the R block (pivots 0..m-1); a zero pivot makes the instance unfit for the scan
-  double sc = 0.0;
-#pragma unroll
-  for (int t = 0; t < CW; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
-      if (ok[t] && r == c && r < m) sc = fmax(sc, fabs(X[t][v]));
-    }
-  sc = wave_max(sc);
-  __syncthreads();
-  if (lane == 0) red[w] = sc;
-  __syncthreads();
-  sc = red[0];
-  for (int q = 1; q < NW; ++q) sc = fmax(sc, red[q]);
   PivStats ps;
   ps.init();
-  for (int j = 0; j < m; ++j) {
-    double* cb = colbuf + NWD * (j & 1);
-    const int jb = j >> 4, jj = j & 15;
-#pragma unroll
-    for (int t = 0; t < CW; ++t)
-      if (ok[t] && bj[t] == jb && col == jj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cb[16 * bi[t] + 4 * grp + v] = X[t][v];
-    __syncthreads();
-    const double d = cb[j];
-    const bool zero = !(fabs(d) > 1.0e3 * m * 2.220446049250313e-16 * sc);
-    ps.nzero += zero ? 1 : 0;
-    const double rd = zero ? 0.0 : recip(d);
-#pragma unroll
-    for (int t = 0; t < CW; ++t) {
-      if (!ok[t]) continue;
-      const int c = 16 * bj[t] + col;
-      const double cc = cb[c];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * bi[t] + 4 * grp + v;
-        const double ci = cb[r];
-        const double gen = __fma_rn(-(ci * cc), rd, X[t][v]);
-        X[t][v] = (r == j) ? ((c == j) ? -rd : cc * rd) : ((c == j) ? ci * rd : gen);
-      }
-    }
+  {
+    const double sc = wg_max<NW>(diag_max<CR, float>(X, ri, rj, ro, 0, m, lane), red, w, lane);
+    sweep_mw<float, CR, TM>(X, ri, rj, ro, 0, m, lane, colbuf, ps, 0, 1.0e3 * m * 2.220446049250313e-16 * sc, sc);
   }
   if (ps.nzero && tid == 0) a.bad[b] = 1;
-  // scatter the blocks of interest into the element
+#pragma unroll
+  for (int t = 0; t < CR; ++t)
+    if (ro[t])
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * ri[t] + trow<float>(grp, v), c = 16 * rj[t] + col;
+        sRi[r * LDM + c] = (r < m && c < m) ? (float)X[t][v] : 0.0f;
+      }
+  __syncthreads();
+  // Y = (-R^{-1}) S  (TM x 2TX blocks, inner TM)
+#pragma unroll
+  for (int t = 0; t < CY; ++t) {
+    const int by = w + NW * t;
+    if (by >= TM * 2 * TX) break;
+    const int I = by / (2 * TX), J = by % (2 * TX);
+    f4 acc = sgemm_blk<false, TM>(sRi, LDM, sS, LDS2, I, J, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sY[arow(I, grp, v) * LDS2 + 16 * J + col] = acc[v];
+  }
+  __syncthreads();
+  // S^T Y = -S^T R^{-1} S: blocks xx (P), zx (A), zz (C)
 #pragma unroll
   for (int t = 0; t < CW; ++t) {
-    if (!ok[t]) continue;
+    const int bo = w + NW * t;
+    if (bo >= 3 * TX * TX) break;
+    const int part = bo / (TX * TX), I = (bo % (TX * TX)) / TX, J = bo % TX;
+    const int rowblk = part == 0 ? I : TX + I;          // rows of S^T: x (0..) or z (NX..)
+    const int colblk = part == 2 ? TX + J : J;          // columns of Y: x or z
+    f4 acc = sgemm_blk<true, TM>(sS, LDS2, sY, LDS2, rowblk, colblk, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
-      if (c < m || c >= m + n || r < m || r >= D) continue;  // only columns x
-      const int cx = c - m;
-      if (r < m + n) {
-        const int rx = r - m;
-        e[rx * NX + cx] = (float)X[t][v];                                  // P
-      } else {
-        const int rz = r - m - n;
-        e[NX * NX + rz * NX + cx] = (float)(A[rz * n + cx] + X[t][v]);     // A
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * bi[t] + 4 * grp + v, c = 16 * bj[t] + col;
-      if (r >= m + n && r < D && c >= m + n && c < D)
-        e[2 * NX * NX + (r - m - n) * NX + (c - m - n)] = (float)(-X[t][v]);  // C
+      const int r = 16 * I + 4 * grp + v, c = 16 * J + col;
+      const bool in = r < n && c < n;
+      float val = 0.0f;
+      if (part == 0) val = in ? (float)(Q[r * n + c] + (double)acc[v]) : 0.0f;             // P
+      else if (part == 1) val = in ? (float)(A[r * n + c] + (double)acc[v]) : 0.0f;        // A
+      else val = in ? (float)((r == c ? delta : 0.0) - (double)acc[v]) : 0.0f;             // C
+      e[part * NX * NX + r * NX + c] = val;
     }
   }
 }
@@ -458,9 +430,9 @@ __global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
 template <int TX, int NW>
 static size_t scan_lds_bytes() { return sizeof(ScanLds<TX, NW>); }
 
-template <int TX, int TW, int NW>
+template <int TX, int TM, int NW>
 static hipError_t launch_scan_init_t(const ScanArgs& a, int ninst, hipStream_t st) {
-  hipLaunchKernelGGL((k_scan_init<TX, TW, NW>), dim3(a.maxN + 1, ninst), dim3(64 * NW), 0, st, a);
+  hipLaunchKernelGGL((k_scan_init<TX, TM, NW>), dim3(a.maxN + 1, ninst), dim3(64 * NW), 0, st, a);
   return hipGetLastError();
 }
 
@@ -502,24 +474,23 @@ static hipError_t launch_scan_tree_t(ScanArgs a, int ninst, hipStream_t st) {
   return hipSuccess;
 }
 
-// Dispatch on the state tile size (tx = NX / 16) and the tile count tw of
-// the u-elimination matrix (m + 2n rows): n <= 16 gives m + 2n <= 112, n <= 32
-// gives <= 128, n <= 64 gives <= 160.
-hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tw, hipStream_t st) {
+// Dispatch on the state tile size (tx = NX / 16) and the control tile count
+// tm = ceil(m / 16): n <= 16 allows m <= 95, n <= 32 allows m <= 79, n <= 64 allows m <= 63.
+hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tm, hipStream_t st) {
   if (ninst <= 0) return hipSuccess;
   if (ninst > 65535) return hipErrorInvalidValue;  // grid y limit
   if (tx == 1) {
-    if (tw <= 2) return launch_scan_init_t<1, 2, 4>(a, ninst, st);
-    if (tw <= 4) return launch_scan_init_t<1, 4, 8>(a, ninst, st);
-    if (tw <= 7) return launch_scan_init_t<1, 7, 16>(a, ninst, st);
+    if (tm <= 1) return launch_scan_init_t<1, 1, 4>(a, ninst, st);
+    if (tm <= 2) return launch_scan_init_t<1, 2, 4>(a, ninst, st);
+    if (tm <= 6) return launch_scan_init_t<1, 6, 8>(a, ninst, st);
   } else if (tx == 2) {
-    if (tw <= 4) return launch_scan_init_t<2, 4, 8>(a, ninst, st);
-    if (tw <= 6) return launch_scan_init_t<2, 6, 12>(a, ninst, st);
-    if (tw <= 8) return launch_scan_init_t<2, 8, 16>(a, ninst, st);
+    if (tm <= 1) return launch_scan_init_t<2, 1, 8>(a, ninst, st);
+    if (tm <= 2) return launch_scan_init_t<2, 2, 8>(a, ninst, st);
+    if (tm <= 5) return launch_scan_init_t<2, 5, 8>(a, ninst, st);
   } else if (tx == 4) {
-    if (tw <= 6) return launch_scan_init_t<4, 6, 12>(a, ninst, st);
-    if (tw <= 8) return launch_scan_init_t<4, 8, 16>(a, ninst, st);
-    if (tw <= 10) return launch_scan_init_t<4, 10, 16>(a, ninst, st);
+    if (tm <= 1) return launch_scan_init_t<4, 1, 16>(a, ninst, st);
+    if (tm <= 2) return launch_scan_init_t<4, 2, 16>(a, ninst, st);
+    if (tm <= 4) return launch_scan_init_t<4, 4, 16>(a, ninst, st);
   }
   return hipErrorInvalidValue;
 }
@@ -658,53 +629,71 @@ hipError_t launch_transfer(int cls, const TransferArgs& a, int nblocks, hipStrea
   return hipErrorInvalidValue;
 }
 
-// Boundary chain of one instance (blockIdx.x indexes the list), one wavefront;
-// lane i < n owns entry i. Backward: p_lo(s) += Psi_s^T p_lo(s+1) for
-// s = S-2 .. 0 (p_lo(S-1) is exact: it starts from q_N). Forward:
-// xhi(s) += Psi_s xhi(s-1) for s = 1 .. S-2 (xhi(0) is exact: it starts from x_0).
-__global__ __launch_bounds__(64) void k_chain(ChainArgs a) {
+// Boundary chain of one instance (blockIdx.x indexes the list). Backward:
+// p_lo(s) += Psi_s^T p_lo(s+1) for s = S-2 .. 0 (p_lo(S-1) is exact: it starts
+// from q_N). Forward: xhi(s) += Psi_s xhi(s-1) for s = 1 .. S-2 (xhi(0) is
+// exact: it starts from x_0). Thread (i, q) = (t & 63, t >> 6) forms the
+// partial sum of entry i over columns 16q .. 16q+15; the four partials are
+// added in order (deterministic). The matrix entries of the next step are
+// loaded into registers while the current step is reduced, so the dependent
+// chain does not wait on memory.
+__global__ __launch_bounds__(256) void k_chain(ChainArgs a) {
   const int b = a.insts[blockIdx.x];
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
-  const int n = mt.n, S = mt.nseg, lane = threadIdx.x;
-  if (S < 2) return;
-  __shared__ double sv[64];
+  const int n = mt.n, S = mt.nseg;
+  if (S < (a.forward ? 3 : 2)) return;  // forward: s = 1 .. S-2; backward: s = S-2 .. 0
+  __shared__ double sv[64], part[4][64];
+  const int t = threadIdx.x, i = t & 63, q = t >> 6;
   double* vec = a.vec + mt.ovec;
-  const double* psi = a.psi + mt.opsi;
   const int64_t n2 = (int64_t)n * n;
-  const bool own = lane < n;
-  if (!a.forward) {
-    double cur = own ? vec[(int64_t)(S - 1) * n + lane] : 0.0;
-    for (int s = S - 2; s >= 0; --s) {
-      sv[lane] = cur;
-      wave_sync();
-      const double* P = psi + (int64_t)s * 2 * n2;  // Psi_s[j][i] at j n + i
-      double acc = own ? vec[(int64_t)s * n + lane] : 0.0;
-      if (own)
-        for (int j = 0; j < n; ++j) acc = fma(P[(int64_t)j * n + lane], sv[j], acc);
-      if (own) vec[(int64_t)s * n + lane] = acc;
-      cur = acc;
-      wave_sync();
+  // column block of this thread: j = 16 q + jj < n
+  const int j0 = 16 * q;
+  const bool row_ok = i < n;
+  const int fwd = a.forward;
+  // matrix of step s: backward uses Psi_s (entry [j][i] at j n + i), forward Psi_s^T (same index)
+  auto mat = [&](int s2) { return a.psi + mt.opsi + (int64_t)s2 * 2 * n2 + (fwd ? n2 : 0); };
+  const int s_first = fwd ? 1 : S - 2, s_last = fwd ? S - 2 : 0, ds = fwd ? 1 : -1;
+  if (t < 64) sv[t] = (t < n) ? vec[(int64_t)(fwd ? 0 : S - 1) * n + t] : 0.0;
+  double pv[16];
+  {
+    const double* P = mat(s_first);
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = j0 + jj;
+      pv[jj] = (row_ok && j < n) ? P[(int64_t)j * n + i] : 0.0;
     }
-  } else {
-    double cur = own ? vec[lane] : 0.0;
-    for (int s = 1; s <= S - 2; ++s) {
-      sv[lane] = cur;
-      wave_sync();
-      const double* PT = psi + (int64_t)s * 2 * n2 + n2;  // Psi_s[i][j] at j n + i
-      double acc = own ? vec[(int64_t)s * n + lane] : 0.0;
-      if (own)
-        for (int j = 0; j < n; ++j) acc = fma(PT[(int64_t)j * n + lane], sv[j], acc);
-      if (own) vec[(int64_t)s * n + lane] = acc;
-      cur = acc;
-      wave_sync();
+  }
+  __syncthreads();
+  for (int s2 = s_first;; s2 += ds) {
+    double acc = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) acc = fma(pv[jj], sv[j0 + jj], acc);
+    const bool more = s2 != s_last;
+    const double own = (q == 0 && row_ok) ? vec[(int64_t)s2 * n + i] : 0.0;
+    if (more) {
+      const double* P = mat(s2 + ds);
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = j0 + jj;
+        pv[jj] = (row_ok && j < n) ? P[(int64_t)j * n + i] : 0.0;
+      }
     }
+    part[q][i] = acc;
+    __syncthreads();
+    if (q == 0) {
+      const double v = own + ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i]));
+      if (row_ok) vec[(int64_t)s2 * n + i] = v;
+      sv[i] = row_ok ? v : 0.0;
+    }
+    __syncthreads();
+    if (!more) break;
   }
 }
 
 hipError_t launch_chain(const ChainArgs& a, int ninst, hipStream_t st) {
   if (ninst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chain, dim3(ninst), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(k_chain, dim3(ninst), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
