@@ -235,7 +235,7 @@ def main():
         if mode == "tuned":
             from paper_2509_16370_amd import tune
             t1 = time.perf_counter()
-            plan = tune.tune(packed, rel_tol=rel_tol, max_refine=max_refine, reps=2)
+            plan = tune.tune_batch(packed, lhs, rhs, rel_tol=rel_tol, max_refine=max_refine, reps=2)
             print(f"[bench] tuned {len(plan)} buckets in {time.perf_counter() - t1:.1f}s: "
                   + ", ".join(f"{k}: {c.key()}" for k, c in plan.items()), file=sys.stderr, flush=True)
         results[mode] = run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_tol=rel_tol,

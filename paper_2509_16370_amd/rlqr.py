@@ -24,6 +24,13 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
         "(the solver has no CPU fallback)")
 
+# torch first: its HIP runtime is loaded under the name libamdhip64.so, which
+# does not match the SONAME (libamdhip64.so.7) of a runtime loaded earlier
+# through this library's dependency, so the opposite order puts two HIP
+# runtimes in the process (device pointers of one are foreign to the other).
+# Loaded in this order, the library binds to torch's runtime.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 RLQR_OK, RLQR_E_INVALID, RLQR_E_NOMEM, RLQR_E_HIP, RLQR_E_STATE, RLQR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5

@@ -1,14 +1,21 @@
 """Autotuner and graph driver for batched, ragged launches.
 
-Instances are grouped into buckets by (n, m). For each bucket the tuner times
-the candidate paths on that bucket's instances -- float64 sequential, the
-float32-product sequential recursion, and the parallel-in-time scan with
-segment lengths L -- each carried to the requested relative KKT residual,
-and keeps the fastest candidate that brings every instance of the bucket to
-the tolerance. The choices become per-instance tuning arrays of ONE handle in
-RLQR_SCAN_FP32 mode (`inst_fp64` = 1 for the float64 path, `inst_chunk` = 0
-for one segment, L for the scan), so the whole ragged batch is one handle and
-its factor + solve + refinement is captured into one HIP graph.
+Instances are grouped into buckets by (n, m); each bucket takes one of the
+candidate paths -- float64 sequential, the float32-product sequential
+recursion, or the parallel-in-time scan with segment length L -- carried to
+the requested relative KKT residual. The choices become per-instance tuning
+arrays of ONE handle in RLQR_SCAN_FP32 mode (`inst_fp64` = 1 for the float64
+path, `inst_chunk` = 0 for one segment, L for the scan), so the whole ragged
+batch is one handle and its factor + solve + refinement is captured into one
+HIP graph.
+
+Buckets share launches (one launch per tile class covers every bucket of that
+class), so a bucket's best path depends on the others: the tuner starts from
+all-float64 and does coordinate descent over the buckets, timing the whole
+batch's graph for every candidate of one bucket with the others fixed, and
+keeps a change only if it shortens the batch and every instance still
+reaches the tolerance (`tune_batch`). `tune` (buckets timed on their own) is
+kept as the cheaper first guess.
 
 Host-side orchestration only: every step of the solve runs in the library's
 HIP kernels.
@@ -115,6 +122,56 @@ def tune(packed: wl.Packed, rel_tol: float = 1e-8, max_refine: int = 3, reps: in
             if best is None or c.ms < best.ms:
                 best = c
         plan[bk] = best
+    return plan
+
+
+def time_plan(packed, plan, lhs, rhs, rel_tol, max_refine, reps, device="cuda:0") -> float:
+    """Median graph-launch time of the whole batch under `plan` (inf if an
+    instance misses the tolerance)."""
+    import torch
+    from . import rlqr as rl
+    tb = TunedBatch(packed, plan, lhs, rhs, rel_tol=rel_tol, max_refine=max_refine, device=device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for r in range(reps + 1):
+        ev[0].record(tb.stream)
+        tb.solver.replay(stream=tb.stream)
+        ev[1].record(tb.stream)
+        tb.stream.synchronize()
+        if r:
+            times.append(ev[0].elapsed_time(ev[1]))
+    st = tb.status.cpu().numpy()[:packed.batch]
+    rr = tb.relres.cpu().numpy()[:packed.batch]
+    solved = (st == rl.INST_OK) | (st == rl.INST_NOT_PD)
+    del tb
+    if np.any(st == rl.INST_NOT_CONVERGED) or not np.all((rr <= rel_tol) | ~solved):
+        return float("inf")
+    return float(np.median(times))
+
+
+def tune_batch(packed: wl.Packed, lhs, rhs, rel_tol: float = 1e-8, max_refine: int = 3, reps: int = 2,
+               lengths=(32, 128), rounds: int = 1, device: str = "cuda:0", log=None) -> Dict[Bucket, Choice]:
+    """Coordinate descent over the buckets with whole-batch timing (see module doc)."""
+    bks = buckets(packed)
+    work = {bk: float(sum(int(packed.N[b]) * (bk[0] + bk[1]) ** 3 for b in ids)) for bk, ids in bks.items()}
+    plan = {bk: Choice("fp64") for bk in bks}
+    best = time_plan(packed, plan, lhs, rhs, rel_tol, max_refine, reps, device)
+    if log:
+        log(f"[tune] all-fp64: {best:.3f} ms")
+    for _ in range(rounds):
+        for bk in sorted(bks, key=lambda k: -work[k]):
+            Nmax = int(packed.N[bks[bk]].max())
+            for c in candidates(bk[0], bk[1], Nmax, lengths):
+                if c.key() == plan[bk].key():
+                    continue
+                trial = dict(plan)
+                trial[bk] = c
+                t = time_plan(packed, trial, lhs, rhs, rel_tol, max_refine, reps, device)
+                if log:
+                    log(f"[tune] bucket {bk} -> {c.key()}: {t:.3f} ms (best {best:.3f})")
+                if t < 0.98 * best:
+                    best, plan = t, trial
+                    plan[bk].ms = t
     return plan
 
 

@@ -132,3 +132,18 @@ def test_layout_offsets_formula_matches_workloads():
         c = wl.counts(N[b], n[b], m[b])
         for k, v in c.items():
             assert off[k][b + 1] - off[k][b] == v
+
+
+def test_package_binds_to_a_single_hip_runtime():
+    """Importing the binding before torch must leave exactly one HIP runtime
+    mapped in the process once torch is loaded too."""
+    import subprocess
+    import sys
+    code = ("import paper_2509_16370_amd.rlqr\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
