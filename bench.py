@@ -16,8 +16,8 @@ roofline of the dominant kernel (the factorization) and the CPU oracle
 baseline are reported beside it.
 
 Other workloads (--workload): long_horizon (one instance, n=64, m=32,
-N=16384, delta=1e-6, refined to 1e-10; the parallel-in-time scan against the
-float64 sequential recursion) and batched_ragged (1024 instances,
+N=16384, delta=1e-6, refined to 1e-10; the parallel-in-time scan, with float32
+and with bfloat16 combine products, against the float64 sequential recursion) and batched_ragged (1024 instances,
 N ~ U{50..1000}, n in {8,16,32}, m in {2,4,8}, 20% indefinite Q, delta=1e-4;
 the autotuned single-graph launch against the float64 sequential path).
 """
@@ -200,7 +200,7 @@ def main():
         inst = wl.long_horizon()[0]
         packed = wl.pack([inst])
         rel_tol, max_refine = 1e-10, 6
-        modes = (args.modes or "fp64,scan").split(",")
+        modes = (args.modes or "fp64,scan,scan_bf16").split(",")
         head = "scan"
         desc = ("single long-horizon dual-regularized LQR: n=64, m=32, N=16384, delta=1e-6, "
                 "refined to 1e-10 relative KKT residual; parallel-in-time scan vs float64 sequential")
@@ -229,7 +229,7 @@ def main():
     results = {}
     for mode in modes:
         steps, warmup = args.steps, args.warmup
-        if wk == "long_horizon" and mode != "scan":  # the sequential float64 recursion takes seconds per step
+        if wk == "long_horizon" and mode == "fp64":  # the sequential float64 recursion takes seconds per step
             steps, warmup = max(1, args.steps // 10), 1
         plan = None
         if mode == "tuned":

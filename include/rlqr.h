@@ -73,7 +73,13 @@ typedef enum {
      F_i = S_hat_{i+1}^{-1}(A_i + B_i K_i)), then refines against the float64
      residual. Instances whose scan or pivots fall outside the float32 guard
      band are factored in float64 by the sequential recursion. */
-  RLQR_SCAN_FP32 = 2
+  RLQR_SCAN_FP32 = 2,
+  /* RLQR_SCAN_FP32 with bfloat16 operands (float32 accumulation) in the
+     matrix products of the scan combine (eq. lqr-gpu-combo); the inversion of
+     I + C P, the segment recursion, the pivots and the refinement are as in
+     RLQR_SCAN_FP32. The boundary cost-to-go carries bfloat16 rounding, so
+     rlqr_solve typically needs more refinement steps. */
+  RLQR_SCAN_BF16 = 3
 } rlqr_mode;
 
 /* per-instance outcome written by rlqr_solve */
@@ -113,14 +119,14 @@ typedef struct { double *x, *u, *y; } rlqr_sol;
 /* Launch tuning fixed at create (an autotuner fills the per-instance arrays
    bucket by bucket). */
 typedef struct {
-  int32_t scan_chunk;          /* RLQR_SCAN_FP32: stages per segment L >= 1; 0 picks L
+  int32_t scan_chunk;          /* RLQR_SCAN_*: stages per segment L >= 1; 0 picks L
                                   from the batch (about two segments per compute unit).
                                   An instance with N <= L is one segment and skips the
                                   scan. Ignored by the sequential modes. */
-  const int32_t *inst_chunk;   /* [host][B] or NULL. RLQR_SCAN_FP32: per-instance L
+  const int32_t *inst_chunk;   /* [host][B] or NULL. RLQR_SCAN_*: per-instance L
                                   (>= 1), or 0 for one segment (the sequential float32
                                   recursion of RLQR_SEQ_MIXED); overrides scan_chunk. */
-  const int32_t *inst_fp64;    /* [host][B] or NULL. RLQR_SEQ_MIXED and RLQR_SCAN_FP32:
+  const int32_t *inst_fp64;    /* [host][B] or NULL. RLQR_SEQ_MIXED and RLQR_SCAN_*:
                                   1 = factor and solve this instance in float64 only
                                   (no float32 attempt). */
 } rlqr_tuning;

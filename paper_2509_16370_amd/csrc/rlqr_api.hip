@@ -8,7 +8,7 @@
 //              failed, or refinement from float32 tiles did not converge)
 //   conv[b]    refinement converged
 // Work is cut into segments (SegDesc): in the sequential modes one segment
-// per instance; in RLQR_SCAN_FP32 the horizon of an instance is cut into
+// per instance; in the scan modes the horizon of an instance is cut into
 // segments of L stages whose boundary cost-to-go comes from the scan.
 // All launches are asynchronous on the caller's stream; no call after
 // rlqr_create allocates memory or synchronizes with the host.
@@ -103,6 +103,8 @@ struct rlqr_handle {
   std::vector<void*> allocs;
 };
 
+static bool is_scan(rlqr_mode m) { return m == RLQR_SCAN_FP32 || m == RLQR_SCAN_BF16; }
+
 static rlqr_status dev_alloc(rlqr_handle* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (hipMalloc(p, bytes) != hipSuccess) {
@@ -160,7 +162,8 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   if (!hp) return RLQR_E_INVALID;
   *hp = nullptr;
   if (!s || s->batch < 0) return RLQR_E_INVALID;
-  if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED && mode != RLQR_SCAN_FP32) return RLQR_E_INVALID;
+  if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED && mode != RLQR_SCAN_FP32 && mode != RLQR_SCAN_BF16)
+    return RLQR_E_INVALID;
   if (tune && tune->scan_chunk < 0) return RLQR_E_INVALID;
   const int B = s->batch;
   if (B > 0 && (!s->N || !s->nx || !s->nu)) return RLQR_E_INVALID;
@@ -176,7 +179,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   h->N.assign(s->N, s->N + B);
   h->n.assign(s->nx, s->nx + B);
   h->m.assign(s->nu, s->nu + B);
-  const bool scan = mode == RLQR_SCAN_FP32;
+  const bool scan = is_scan(mode);
 
   // segment length: about two segments per compute unit over the whole batch
   int64_t total_elems = 0;
@@ -446,7 +449,7 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
     a.elems = G.elems; a.aggr[0] = G.aggr[0]; a.aggr[1] = G.aggr[1];
     a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
     if ((e = launch_scan_elements(a, G.ninst, G.tx, G.tm, st)) != hipSuccess) return e;
-    if ((e = launch_scan_tree(a, G.ninst, G.tx, st)) != hipSuccess) return e;
+    if ((e = launch_scan_tree(a, G.ninst, G.tx, h->mode == RLQR_SCAN_BF16, st)) != hipSuccess) return e;
   }
   const int32_t* run32 = h->any_pref64 ? h->pref32 : nullptr;
   if ((e = factor_segments(h, h->fseg, h->seg_off, h->seg_stats, h->ws32, run32, true, st)) != hipSuccess)
@@ -477,7 +480,7 @@ extern "C" rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_str
   else RLQR_TRY(factor_scan(h, st));
   MaskArgs m{};
   m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
-  m.bad = h->mode == RLQR_SCAN_FP32 ? h->bad : nullptr;
+  m.bad = is_scan(h->mode) ? h->bad : nullptr;
   m.pref32 = h->any_pref64 ? h->pref32 : nullptr;
   RLQR_TRY(launch_masks(m, st));
   RLQR_TRY(factor_whole(h, h->ws64, h->flag64, false, st));
@@ -577,7 +580,7 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
   }
   rlqr_status s;
   if (h->mode != RLQR_SEQ_FP64 && !run64_override) {
-    if (h->mode == RLQR_SCAN_FP32) {
+    if (is_scan(h->mode)) {
       // single-segment instances take the whole-instance kernels
       MaskArgs m{};
       m.batch = h->B; m.kind = 4; m.run32 = h->run32; m.multi = h->multi; m.run1 = h->run1;

@@ -74,7 +74,7 @@ struct ScanArgs {
   int32_t* bad;            // per instance: set when the scan cannot be used
 };
 hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tm, hipStream_t st);
-hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, hipStream_t st);
+hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, bool bf16, hipStream_t st);
 int scan_result_buffer(int maxchunks);
 hipError_t scan_prepare();  // once per device before the first scan launch
 hipError_t launch_merge(const MergeArgs& a, hipStream_t st);

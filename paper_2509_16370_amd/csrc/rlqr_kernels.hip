@@ -417,10 +417,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     for (int v = 0; v < 4; ++v)
       ab[v] = ab_elem(Ag + (int64_t)(N - 1) * n * n, Bg + (int64_t)(N - 1) * n * m, n, m, trow<TG>(grp, v), col);
   }
+  double ck = 0.0, qk = 0.0, rk = 0.0;
+  if (N > 0) {
+    ck = ld_or0(cb, (int64_t)N * n + col, xr);
+    qk = ld_or0(qb, (int64_t)(N - 1) * qs + col, xr);
+    rk = ld_or0(rb, (int64_t)(N - 1) * rs + (col - n), ur);
+  }
   for (int k = N - 1; k >= 0; --k) {
-    const double ck = ld_or0(cb, (int64_t)(k + 1) * n + col, xr);
-    const double qk = ld_or0(qb, (int64_t)k * qs + col, xr);
-    const double rk = ld_or0(rb, (int64_t)k * rs + (col - n), ur);
     // next step's operands
     double Zk1[4], Xn1[4], ab1[4];
     const int k1 = k > 0 ? k - 1 : 0;
@@ -429,6 +432,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       ab1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, trow<TG>(grp, v), col);
+    const double ck1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
+    const double qk1 = ld_or0(qb, (int64_t)k1 * qs + col, xr);
+    const double rk1 = ld_or0(rb, (int64_t)k1 * rs + (col - n), ur);
     wave_sync();
     if (own) sv[0][col] = ck;
     wave_sync();
@@ -455,6 +461,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       Xn[v] = Xn1[v];
       ab[v] = ab1[v];
     }
+    ck = ck1;
+    qk = qk1;
+    rk = rk1;
   }
   __syncthreads();  // p/k written by lanes 0..15 are read by all lanes below
 
@@ -476,14 +485,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
   for (int v = 0; v < 4; ++v)
     abt[v] = N > 0 ? ab_elem(Ag, Bg, n, m, col, trow<TG>(grp, v)) : 0.0;  // [A B][col][j]
+  // step k's vectors, loaded one step ahead like the tiles
+  double pk = 0.0, kk = 0.0, pn = 0.0, cn = 0.0, xold = 0.0, yold = 0.0, uold = 0.0;
+  if (N > 0) {
+    pk = ld_or0(pg, col, xr);
+    kk = ld_or0(kg, col - n, ur);
+    pn = ld_or0(pg, (int64_t)n + col, xr);
+    cn = ld_or0(cb, (int64_t)n + col, xr);
+    if (acc) {
+      xold = ld_or0(xg, col, xr);
+      yold = ld_or0(yg, col, xr);
+      uold = ld_or0(ug, col - n, ur);
+    }
+  }
   for (int k = 0; k < N; ++k) {
-    const double pk = ld_or0(pg, (int64_t)k * n + col, xr);
-    const double kk = ld_or0(kg, (int64_t)k * m + (col - n), ur);
-    const double pn = ld_or0(pg, (int64_t)(k + 1) * n + col, xr);
-    const double cn = ld_or0(cb, (int64_t)(k + 1) * n + col, xr);
-    const double xold = acc ? ld_or0(xg, (int64_t)k * n + col, xr) : 0.0;
-    const double yold = acc ? ld_or0(yg, (int64_t)k * n + col, xr) : 0.0;
-    const double uold = acc ? ld_or0(ug, (int64_t)k * m + (col - n), ur) : 0.0;
     double Zk1[4], Xn1[4], abt1[4];
     const int k1 = k + 1 < N ? k + 1 : k;
     tile_load(Zk1, ws + (int64_t)(2 * (k + 1)) * 256, lane);  // tile 2N exists (P_N)
@@ -491,6 +506,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       abt1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, col, trow<TG>(grp, v));
+    const double pk1 = ld_or0(pg, (int64_t)k1 * n + col, xr);
+    const double kk1 = ld_or0(kg, (int64_t)k1 * m + (col - n), ur);
+    const double pn1 = ld_or0(pg, (int64_t)(k1 + 1) * n + col, xr);
+    const double cn1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
+    const double xold1 = acc ? ld_or0(xg, (int64_t)k1 * n + col, xr) : 0.0;
+    const double yold1 = acc ? ld_or0(yg, (int64_t)k1 * n + col, xr) : 0.0;
+    const double uold1 = acc ? ld_or0(ug, (int64_t)k1 * m + (col - n), ur) : 0.0;
     wave_sync();
     if (own) sv[0][col] = xr ? x : 0.0;
     wave_sync();
@@ -515,6 +537,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       Xn[v] = Xn1[v];
       abt[v] = abt1[v];
     }
+    pk = pk1; kk = kk1; pn = pn1; cn = cn1;
+    xold = xold1; yold = yold1; uold = uold1;
   }
   {
     // y_N = P_N x_N + p_N  (Zk now holds tile 2N)

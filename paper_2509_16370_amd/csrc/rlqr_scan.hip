@@ -1,5 +1,7 @@
 // rlqr_scan.hip -- parallel-in-time pieces of the dual-regularized Riccati
-// solver (Section "Parallel Algorithm" of arXiv 2509.16370), float32 products.
+// solver (Section "Parallel Algorithm" of arXiv 2509.16370), float32 products;
+// the combine's products optionally take bfloat16 operands (float32
+// accumulation, RLQR_SCAN_BF16).
 //
 // Interval value-function elements e = (P, A, C) (eqs. lqr-gpu-init-running,
 // lqr-gpu-init-terminal) are stored per element as three NX x NX float32
@@ -47,6 +49,66 @@ __device__ __forceinline__ f4 sgemm_blk_bt(const float* sa, int lda, const float
       acc = mfma16(av, bv, acc);
     }
   return acc;
+}
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16 bits, round to nearest even (a NaN stays a quiet NaN)
+__device__ __forceinline__ short bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (short)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// The same block products with bfloat16 operands and float32 accumulation:
+// one 16x16x16 MFMA per 16-block of the inner dimension, lane l holding
+// op(A)[i][4 kq .. 4 kq + 3] and B[4 kq .. 4 kq + 3][j] (i, j = l & 15, kq = l >> 4).
+template <bool TRANS_A, int KB>
+__device__ __forceinline__ f4 bgemm_blk(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
+  f4 acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    s4 av, bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 16 * kb + 4 * kq + j;
+      av[j] = bf16_bits(TRANS_A ? sa[k * lda + 16 * I + i] : sa[(16 * I + i) * lda + k]);
+      bv[j] = bf16_bits(sb[k * ldb + 16 * J + i]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+template <int KB>
+__device__ __forceinline__ f4 bgemm_blk_bt(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
+  f4 acc = {0, 0, 0, 0};
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    s4 av, bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 16 * kb + 4 * kq + j;
+      av[j] = bf16_bits(sa[(16 * I + i) * lda + k]);
+      bv[j] = bf16_bits(sb[(16 * J + i) * ldb + k]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// operand precision of the combine's products: float32 or bfloat16
+template <bool BF, bool TRANS_A, int KB>
+__device__ __forceinline__ f4 cgemm(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
+  if constexpr (BF) return bgemm_blk<TRANS_A, KB>(sa, lda, sb, ldb, I, J, lane);
+  else return sgemm_blk<TRANS_A, KB>(sa, lda, sb, ldb, I, J, lane);
+}
+template <bool BF, int KB>
+__device__ __forceinline__ f4 cgemm_bt(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
+  if constexpr (BF) return bgemm_blk_bt<KB>(sa, lda, sb, ldb, I, J, lane);
+  else return sgemm_blk_bt<KB>(sa, lda, sb, ldb, I, J, lane);
 }
 
 // accumulator element (v) of block (I, J): row 16 I + 4 grp + v, column 16 J + col
@@ -99,7 +161,7 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
 
 // acc (P1, A1, C1 in LDS) <- acc (+) next (P2, A2 in LDS, C2 in global).
 // Returns false if X = I + C1 P2 is singular (no pivot above tol).
-template <int TX, int NW>
+template <int TX, int NW, bool BF>
 __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid) {
   using C = ScanCfg<TX, NW>;
   constexpr int NX = C::NX, LDX = C::LDX, LDW = C::LDW, CB = C::CB;
@@ -111,7 +173,7 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
     const int bx = w + NW * t;
     if (bx >= C::NB) break;
     const int I = bx / TX, J = bx % TX;
-    f4 acc = sgemm_blk<false, TX>(s.C1, LDX, s.P2, LDX, I, J, lane);
+    f4 acc = cgemm<BF, false, TX>(s.C1, LDX, s.P2, LDX, I, J, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
@@ -163,8 +225,8 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
     const int bx = w + NW * t;
     if (bx >= C::NB) break;
     const int I = bx / TX, J = bx % TX;
-    f4 ya = sgemm_blk<false, TX>(s.W + NX, LDW, s.A1, LDX, I, J, lane);
-    f4 yc = sgemm_blk<false, TX>(s.W + NX, LDW, s.C1, LDX, I, J, lane);
+    f4 ya = cgemm<BF, false, TX>(s.W + NX, LDW, s.A1, LDX, I, J, lane);
+    f4 yc = cgemm<BF, false, TX>(s.W + NX, LDW, s.C1, LDX, I, J, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
@@ -179,8 +241,8 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
     const int bx = w + NW * t;
     if (bx >= C::NB) break;
     const int I = bx / TX, J = bx % TX;
-    f4 t1 = sgemm_blk<false, TX>(s.P2, LDX, s.YA, LDX, I, J, lane);
-    f4 t2 = sgemm_blk_bt<TX>(s.YC, LDX, s.A2, LDX, I, J, lane);
+    f4 t1 = cgemm<BF, false, TX>(s.P2, LDX, s.YA, LDX, I, J, lane);
+    f4 t2 = cgemm_bt<BF, TX>(s.YC, LDX, s.A2, LDX, I, J, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
@@ -196,9 +258,9 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
     const int bx = w + NW * t;
     if (bx >= C::NB) break;
     const int I = bx / TX, J = bx % TX;
-    f4 pa = sgemm_blk<true, TX>(s.A1, LDX, s.W, LDW, I, J, lane);
-    f4 aa = sgemm_blk<false, TX>(s.A2, LDX, s.YA, LDX, I, J, lane);
-    f4 ca = sgemm_blk<false, TX>(s.A2, LDX, s.W + NX, LDW, I, J, lane);
+    f4 pa = cgemm<BF, true, TX>(s.A1, LDX, s.W, LDW, I, J, lane);
+    f4 aa = cgemm<BF, false, TX>(s.A2, LDX, s.YA, LDX, I, J, lane);
+    f4 ca = cgemm<BF, false, TX>(s.A2, LDX, s.W + NX, LDW, I, J, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
@@ -372,7 +434,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
 
 // Fold the elements of chunk c = blockIdx.x (elements [c L, min(c L + L, N + 1)))
 // into one aggregate, left to right: acc = acc (+) e_next.
-template <int TX, int NW>
+template <int TX, int NW, bool BF>
 __global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
   using C = ScanCfg<TX, NW>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -393,7 +455,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
     const float* en = elems + (int64_t)k * C::ELEM;
     load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
     __syncthreads();
-    ok &= combine<TX, NW>(s, en + 2 * C::NX * C::NX, n, tid);
+    ok &= combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid);
   }
   store_elem<TX, NW>(a.aggr_out + (a.aoff[blockIdx.y] + c) * C::ELEM, s.P1, s.A1, s.C1, tid);
   if (!ok && tid == 0) a.bad[b] = 1;
@@ -401,7 +463,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
 
 // One Hillis-Steele level of the reverse scan over chunk aggregates:
 // out[c] = in[c] (+) in[c + d] for c + d < NC, else out[c] = in[c].
-template <int TX, int NW>
+template <int TX, int NW, bool BF>
 __global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
   using C = ScanCfg<TX, NW>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -422,7 +484,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
     const float* en = in + (int64_t)(c + d) * C::ELEM;
     load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
     __syncthreads();
-    if (!combine<TX, NW>(s, en + 2 * C::NX * C::NX, n, tid) && tid == 0) a.bad[b] = 1;
+    if (!combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid) && tid == 0) a.bad[b] = 1;
   }
   store_elem<TX, NW>(out + (int64_t)c * C::ELEM, s.P1, s.A1, s.C1, tid);
 }
@@ -439,35 +501,39 @@ static hipError_t launch_scan_init_t(const ScanArgs& a, int ninst, hipStream_t s
 // The tree kernels use more than 64 KB of dynamic LDS; the limit is raised
 // once (scan_prepare, at handle creation) so that no launch path makes a
 // non-stream call (a launch sequence may be captured into a graph).
-template <int TX, int NW>
+template <int TX, int NW, bool BF>
 static hipError_t scan_prepare_t() {
   const size_t lds = scan_lds_bytes<TX, NW>();
-  hipError_t e = hipFuncSetAttribute((const void*)k_scan_reduce<TX, NW>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_scan_reduce<TX, NW, BF>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_scan_level<TX, NW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipFuncSetAttribute((const void*)k_scan_level<TX, NW, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
 }
 
 hipError_t scan_prepare() {
-  hipError_t e = scan_prepare_t<1, 4>();
-  if (e == hipSuccess) e = scan_prepare_t<2, 4>();
-  if (e == hipSuccess) e = scan_prepare_t<4, 16>();
+  hipError_t e = scan_prepare_t<1, 4, false>();
+  if (e == hipSuccess) e = scan_prepare_t<2, 4, false>();
+  if (e == hipSuccess) e = scan_prepare_t<4, 16, false>();
+  if (e == hipSuccess) e = scan_prepare_t<1, 4, true>();
+  if (e == hipSuccess) e = scan_prepare_t<2, 4, true>();
+  if (e == hipSuccess) e = scan_prepare_t<4, 16, true>();
   return e;
 }
 
-template <int TX, int NW>
+template <int TX, int NW, bool BF>
 static hipError_t launch_scan_tree_t(ScanArgs a, int ninst, hipStream_t st) {
   const size_t lds = scan_lds_bytes<TX, NW>();
   hipError_t e;
   a.aggr_out = a.aggr[0];
-  hipLaunchKernelGGL((k_scan_reduce<TX, NW>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
+  hipLaunchKernelGGL((k_scan_reduce<TX, NW, BF>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int d = 1; d < a.maxchunks; d *= 2) {
     a.aggr_in = a.aggr[cur];
     a.aggr_out = a.aggr[cur ^ 1];
     a.dist = d;
-    hipLaunchKernelGGL((k_scan_level<TX, NW>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
+    hipLaunchKernelGGL((k_scan_level<TX, NW, BF>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
@@ -502,12 +568,18 @@ int scan_result_buffer(int maxchunks) {
   return cur;
 }
 
-hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, hipStream_t st) {
+hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, bool bf16, hipStream_t st) {
   if (ninst <= 0) return hipSuccess;
   if (ninst > 65535) return hipErrorInvalidValue;  // grid y limit
-  if (tx == 1) return launch_scan_tree_t<1, 4>(a, ninst, st);
-  if (tx == 2) return launch_scan_tree_t<2, 4>(a, ninst, st);
-  if (tx == 4) return launch_scan_tree_t<4, 16>(a, ninst, st);
+  if (bf16) {
+    if (tx == 1) return launch_scan_tree_t<1, 4, true>(a, ninst, st);
+    if (tx == 2) return launch_scan_tree_t<2, 4, true>(a, ninst, st);
+    if (tx == 4) return launch_scan_tree_t<4, 16, true>(a, ninst, st);
+  } else {
+    if (tx == 1) return launch_scan_tree_t<1, 4, false>(a, ninst, st);
+    if (tx == 2) return launch_scan_tree_t<2, 4, false>(a, ninst, st);
+    if (tx == 4) return launch_scan_tree_t<4, 16, false>(a, ninst, st);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -34,10 +34,10 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 RLQR_OK, RLQR_E_INVALID, RLQR_E_NOMEM, RLQR_E_HIP, RLQR_E_STATE, RLQR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-RLQR_SEQ_FP64, RLQR_SEQ_MIXED, RLQR_SCAN_FP32 = 0, 1, 2
+RLQR_SEQ_FP64, RLQR_SEQ_MIXED, RLQR_SCAN_FP32, RLQR_SCAN_BF16 = 0, 1, 2, 3
 INST_OK, INST_NOT_PD, INST_SINGULAR, INST_NOT_CONVERGED = 0, 1, 2, 3
 ARRAYS = ("Q", "M", "R", "A", "B", "q", "r", "c", "x", "u", "y", "res")
-MODES = {"fp64": RLQR_SEQ_FP64, "mixed": RLQR_SEQ_MIXED, "scan": RLQR_SCAN_FP32}
+MODES = {"fp64": RLQR_SEQ_FP64, "mixed": RLQR_SEQ_MIXED, "scan": RLQR_SCAN_FP32, "scan_bf16": RLQR_SCAN_BF16}
 
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)

@@ -178,7 +178,9 @@ class WarmStart:
         self.batch = batch
         self.mean = self.std = None
 
-    def fit(self, F, T, epochs=20, lr=1e-3, seed=0, log=None):
+    def fit(self, F, T, epochs=20, lr=1e-3, lr_min=1e-5, seed=0, log=None):
+        """Adam on minibatches of the standardized targets; the step size
+        follows a cosine from lr down to lr_min over the epochs."""
         torch = self.torch
         # per-output standardization constants of the training targets
         Tn = T.cpu().numpy().astype(np.float64)
@@ -194,17 +196,18 @@ class WarmStart:
         Mtot = F.shape[0]
         history = []
         for ep in range(epochs):
+            lr_ep = lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * ep / max(epochs, 1)))
             perm = torch.from_numpy(rng.permutation(Mtot)).to(F.device)
             tot, cnt = 0.0, 0
             for s in range(0, Mtot - self.batch + 1, self.batch):
                 idx = perm[s:s + self.batch]
                 loss = self.net.loss_and_grads(F[idx].contiguous(), Ts[idx].contiguous())
-                self.net.adam(lr=lr)
+                self.net.adam(lr=lr_ep)
                 tot += float(loss) if (s // self.batch) % 50 == 0 else 0.0
                 cnt += 1 if (s // self.batch) % 50 == 0 else 0
             history.append(tot / max(cnt, 1))
             if log:
-                log(f"[train] epoch {ep}: sampled loss {history[-1]:.4e}")
+                log(f"[train] epoch {ep}: lr {lr_ep:.2e}, sampled loss {history[-1]:.4e}")
         return history
 
     def predict(self, F):

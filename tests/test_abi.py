@@ -101,6 +101,7 @@ def test_status_strings():
     ([4], [3], [0], 0),      # m < 1
     ([-1], [3], [2], 0),     # N < 0
     ([4], [3], [2], 7),      # unknown mode
+    ([4], [3], [2], 4),      # unknown mode
 ])
 def test_create_rejects_bad_shapes(N, nx, nu, mode):
     from paper_2509_16370_amd import rlqr

@@ -1,4 +1,4 @@
-"""GPU parity of the parallel-in-time mode (RLQR_SCAN_FP32) against the FP64 oracle.
+"""GPU parity of the parallel-in-time modes (RLQR_SCAN_FP32, RLQR_SCAN_BF16) against the FP64 oracle.
 
 The scan mode cuts each horizon into segments of L stages. The segment
 boundaries get their cost-to-go from the float32 reverse scan, every segment
@@ -163,3 +163,23 @@ def test_scan_long_horizon_full_size(rl):
     assert rel <= 1e-10, rel
     assert res["relres"][0] <= 1e-10
     check_against_oracle(rl, [inst], res, tol=1e-7, rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("chunk,shapes", [(3, [(1, 1), (4, 2), (12, 4), (8, 8)]),
+                                          (5, [(20, 10), (40, 6), (64, 32), (17, 3)])])
+def test_scan_bf16_products_match_oracle(rl, chunk, shapes):
+    """RLQR_SCAN_BF16: bfloat16 operands in the scan combine's products. The
+    boundary cost-to-go carries bfloat16 rounding; refinement against the
+    float64 residual must still bring every instance to 1e-8, with the
+    certificate decided exactly as by the oracle."""
+    print(f"[gpu] scan bf16 chunk={chunk}", flush=True)
+    insts = _ragged(5 + chunk, 24, shapes)
+    res = run(rl, insts, mode="scan_bf16", chunk=chunk, max_refine=10)
+    check_against_oracle(rl, insts, res)
+
+
+def test_scan_bf16_long_horizon_reduced(rl):
+    print("[gpu] scan bf16 long horizon N=512", flush=True)
+    inst = wl.make_instance(64, 32, 512, 1e-6, (73, 0, 0))
+    res = run(rl, [inst], mode="scan_bf16", chunk=32, rel_tol=1e-10, max_refine=10)
+    check_against_oracle(rl, [inst], res, tol=1e-8, rel_tol=1e-10)
