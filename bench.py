@@ -5,7 +5,8 @@ residual, mixed precision vs plain float64, on one MI355X.
 Workload: a uniform batch of 4096 independent instances, n=12, m=4, N=128
 (quadrotor-sized), delta=1e-8, generated with the seeded recipe of
 paper_2509_16370_amd.workloads; inputs are resident in HBM before timing.
-One step = rlqr_factor + rlqr_solve (backward/forward passes, float64
+One step = rlqr_factor_rhs + rlqr_solve (the factorization with the solve's
+backward vector pass in its stage loop, then the forward rollout, float64
 residual and iterative refinement until every instance reaches
 ||K z + b||_inf <= 1e-8 ||b||_inf). A stage-solve is one stage of one
 instance carried through that step; instances that miss the tolerance are
@@ -36,13 +37,16 @@ HBM_PEAK_GBS = 8000.0
 REL_TOL = 1e-8
 
 
-def factor_algorithmic_bytes(n, m, elem_bytes):
+def factor_algorithmic_bytes(n, m, elem_bytes, with_rhs=True):
     """Per stage: read Q, M, R, A, B (float64) and write the minimal
     factorization a solve needs -- K (m x n), the symmetric P and S_hat^{-1}
-    (n(n+1)/2 each) and the symmetric G^{-1} (m(m+1)/2) -- in the working precision."""
+    (n(n+1)/2 each) and the symmetric G^{-1} (m(m+1)/2) -- in the working
+    precision; with the right-hand side (rlqr_factor_rhs) also read q, r, c
+    and write p, k (float64)."""
     lhs = 8 * (n * n + n * m + m * m + n * n + n * m)
     handoff = elem_bytes * (m * n + n * (n + 1) + m * (m + 1) // 2)
-    return lhs + handoff
+    vec = 8 * ((2 * n + m) + (n + m)) if with_rhs else 0
+    return lhs + handoff + vec
 
 
 def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_tol=REL_TOL, chunk=0, plan=None):
@@ -67,7 +71,7 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_t
         def step(ev=None):
             if ev:
                 ev[0].record(stream)
-            s.factor(lhs)
+            s.factor(lhs, rhs)  # rlqr_factor_rhs: the solve's backward vector pass rides in the factor
             if ev:
                 ev[1].record(stream)
             res = s.solve(rhs, out=out, rel_tol=rel_tol, max_refine=max_refine)
@@ -165,6 +169,9 @@ def main():
     ap.add_argument("--workload", default="batched_uniform",
                     choices=["batched_uniform", "long_horizon", "batched_ragged"])
     ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--nx", type=int, default=12, help="batched_uniform: state size")
+    ap.add_argument("--nu", type=int, default=4, help="batched_uniform: control size")
+    ap.add_argument("--horizon", type=int, default=128, help="batched_uniform: N")
     ap.add_argument("--delta", type=float, default=1e-8)
     ap.add_argument("--max-refine", type=int, default=3)
     ap.add_argument("--modes", default=None)
@@ -188,7 +195,7 @@ def main():
     t0 = time.perf_counter()
     rel_tol, max_refine = REL_TOL, args.max_refine
     if wk == "batched_uniform":
-        n, m, N = 12, 4, 128
+        n, m, N = args.nx, args.nu, args.horizon
         packed = wl.pack_parallel(wl.uniform_specs(batch=args.batch, n=n, m=m, N=N, delta=args.delta),
                                   workers=args.workers)
         modes = (args.modes or "fp64,mixed").split(",")
@@ -259,8 +266,14 @@ def main():
         alg_bytes = float(sum(factor_algorithmic_bytes(int(packed.n[b]), int(packed.m[b]), elem) * int(packed.N[b])
                               for b in range(packed.batch)))
         achieved = alg_bytes / (r["factor_ms"] * 1e-3) / 1e9
-        kern = "k_factor16<float>" if wk == "batched_uniform" else "rlqr_factor (all tile classes)"
-        traffic = load_counters("k_factor16_float.batched_uniform.counters.txt") if wk == "batched_uniform" else None
+        default_uniform = wk == "batched_uniform" and (args.nx, args.nu, args.horizon, args.batch) == (12, 4, 128, 4096)
+        if wk == "batched_uniform":
+            kern = ("k_factor16<%s>" if args.nx + args.nu <= 16 else "k_factor_mw<%s>") % (
+                "double" if head == "fp64" else "float")
+        else:
+            kern = "rlqr_factor (all tile classes)"
+        traffic = (load_counters("k_factor16_float.batched_uniform.counters.txt")
+                   if default_uniform and head == "mixed" else None)
         roof = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": r["factor_ms"]}

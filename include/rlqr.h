@@ -167,6 +167,20 @@ rlqr_status rlqr_layout_offsets(const rlqr_handle *h, int32_t array, int64_t *of
 rlqr_status rlqr_factor(rlqr_handle *h, const rlqr_lhs *lhs, rlqr_stream st);
 
 /*
+ * rlqr_factor for a caller who already knows the right-hand side it will
+ * solve next: in the sequential modes the backward vector pass of the solve
+ * (p_k, k_k of Theorem "main-seq-theorem") runs inside the factorization's
+ * stage loop for the instances with n + m <= 16, so the next rlqr_solve with
+ * the same rhs pointers starts those instances at the forward rollout.
+ * Results are identical to rlqr_factor followed by rlqr_solve. The rhs arrays
+ * must keep their contents until that rlqr_solve; any other rlqr_solve (other
+ * pointers, or a second call) runs the full passes. In the scan modes this is
+ * rlqr_factor. Errors: as rlqr_factor, and RLQR_E_INVALID for a NULL rhs
+ * array when the batch is not empty.
+ */
+rlqr_status rlqr_factor_rhs(rlqr_handle *h, const rlqr_lhs *lhs, const rlqr_rhs *rhs, rlqr_stream st);
+
+/*
  * Solve for one right-hand side with the current factorization: backward
  * vector pass (g, h, k_k, p_k), forward rollout x_0 = S_hat_0^{-1}(c_0 -
  * delta p_0), u_k = K_k x_k + k_k, x_{k+1} = S_hat_{k+1}^{-1}(A_k x_k + B_k u_k

@@ -711,7 +711,7 @@ rlqr_status ripm_iterate(ripm_handle* h, int32_t* active, rlqr_stream stv) {
   for (int round = 0; round < 60; ++round) {
     hipLaunchKernelGGL(k_ipm_build, stages, dim3(256), 0, st, a);
     IPM_TRY(hipGetLastError());
-    if ((s = rlqr_factor(h->lqr, &lhs, stv)) != RLQR_OK) return s;
+    if ((s = rlqr_factor_rhs(h->lqr, &lhs, &rhs, stv)) != RLQR_OK) return s;
     if ((s = rlqr_pivot_inertia(h->lqr, h->verdict, nullptr, nullptr, stv)) != RLQR_OK) return s;
     hipLaunchKernelGGL(k_ipm_zero, dim3(1), dim3(1), 0, st, h->counter);
     hipLaunchKernelGGL(k_ipm_rho, small, dim3(256), 0, st, a);

@@ -54,6 +54,8 @@ struct rlqr_handle {
   int B = 0;
   rlqr_mode mode = RLQR_SEQ_FP64;
   int chunk = 0;  // scan mode: stages per segment
+  int shape16 = SHAPE_ANY;  // fixed stage shape shared by every one-wavefront instance
+  int shape_all = SHAPE_ANY;  // fixed stage shape shared by every instance of the batch
   std::vector<int32_t> N, n, m;
   std::vector<int64_t> off[RLQR_ARR_COUNT];
   size_t bytes = 0;
@@ -100,6 +102,8 @@ struct rlqr_handle {
 
   rlqr_lhs lhs{};
   bool factored = false;
+  bool pk_fused = false;  // pk holds the backward vector pass for pk_rhs (rlqr_factor_rhs)
+  rlqr_rhs pk_rhs{};
   std::vector<void*> allocs;
 };
 
@@ -235,6 +239,17 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     }
     seg_off[b + 1] = seg_off[b] + nseg[b];
     whole_off[b + 1] = b + 1;
+  }
+  // one fixed-shape kernel serves the one-wavefront class if all its instances share the shape
+  {
+    int sn = -1, sm = -1;
+    bool same = true;
+    for (int b : lists[TILE_16]) {
+      if (sn < 0) { sn = h->n[b]; sm = h->m[b]; }
+      same = same && h->n[b] == sn && h->m[b] == sm;
+    }
+    h->shape16 = (sn > 0 && same) ? fixed_shape(sn, sm) : SHAPE_ANY;
+    h->shape_all = (B > 0 && (int)lists[TILE_16].size() == B) ? h->shape16 : SHAPE_ANY;
   }
   std::vector<ResChunk> chunks;
   for (int b = 0; b < B; ++b)
@@ -415,14 +430,18 @@ rlqr_status rlqr_layout_offsets(const rlqr_handle* h, int32_t array, int64_t* of
 // One factor launch per tile class over the given segment lists, then the
 // per-instance merge of the segments' pivot statistics.
 static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const int32_t* off, SegStats* stats,
-                                  void* ws, const int32_t* run, bool fp32, hipStream_t st) {
+                                  void* ws, const int32_t* run, bool fp32, hipStream_t st,
+                                  const rlqr_rhs* rhs = nullptr) {
   for (int c = 0; c < TILE_CLASSES; ++c) {
     if (lists[c].count == 0) continue;
     FactorArgs a{};
     a.meta = h->meta; a.segs = lists[c].d; a.run = run;
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
     a.ws = ws; a.stats = stats;
-    hipError_t e = (c == TILE_16) ? launch_factor(a, lists[c].count, fp32, st)
+    if (rhs && c == TILE_16) {
+      a.q = rhs->q; a.r = rhs->r; a.c = rhs->c; a.pk = h->pk;
+    }
+    hipError_t e = (c == TILE_16) ? launch_factor(a, lists[c].count, fp32, h->shape16, st)
                                   : launch_factor_mw(c, a, lists[c].count, fp32, st);
     if (e != hipSuccess) return e;
   }
@@ -431,8 +450,9 @@ static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const in
   return launch_merge(m, st);
 }
 
-static hipError_t factor_whole(rlqr_handle* h, void* ws, const int32_t* run, bool fp32, hipStream_t st) {
-  return factor_segments(h, h->whole, h->whole_off, h->whole_stats, ws, run, fp32, st);
+static hipError_t factor_whole(rlqr_handle* h, void* ws, const int32_t* run, bool fp32, hipStream_t st,
+                               const rlqr_rhs* rhs = nullptr) {
+  return factor_segments(h, h->whole, h->whole_off, h->whole_stats, ws, run, fp32, st, rhs);
 }
 
 // Scan mode: elements, chunk reduce and suffix scan per group, then every
@@ -463,28 +483,45 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
   return hipSuccess;
 }
 
-extern "C" rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_stream stv) {
+static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_rhs* rhs, hipStream_t st) {
   if (!h || !lhs) return RLQR_E_INVALID;
   if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || !lhs->delta)) return RLQR_E_INVALID;
+  if (rhs && h->B > 0 && (!rhs->q || !rhs->r || !rhs->c)) return RLQR_E_INVALID;
   h->lhs = *lhs;
   h->factored = true;
+  h->pk_fused = false;
   if (h->B == 0) return RLQR_OK;
-  hipStream_t st = (hipStream_t)stv;
+  if (is_scan(h->mode)) rhs = nullptr;  // the segment recursions do not carry the vector pass
   if (h->mode == RLQR_SEQ_FP64) {
-    RLQR_TRY(factor_whole(h, h->ws64, nullptr, false, st));
-    return RLQR_OK;
+    RLQR_TRY(factor_whole(h, h->ws64, nullptr, false, st, rhs));
+  } else {
+    // float32 products everywhere, then float64 for instances whose pivots fall
+    // inside the guard band (or whose scan failed)
+    if (h->mode == RLQR_SEQ_MIXED)
+      RLQR_TRY(factor_whole(h, h->ws32, h->any_pref64 ? h->pref32 : nullptr, true, st, rhs));
+    else
+      RLQR_TRY(factor_scan(h, st));
+    MaskArgs m{};
+    m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
+    m.bad = is_scan(h->mode) ? h->bad : nullptr;
+    m.pref32 = h->any_pref64 ? h->pref32 : nullptr;
+    RLQR_TRY(launch_masks(m, st));
+    RLQR_TRY(factor_whole(h, h->ws64, h->flag64, false, st, rhs));
   }
-  // float32 products everywhere, then float64 for instances whose pivots fall
-  // inside the guard band (or whose scan failed)
-  if (h->mode == RLQR_SEQ_MIXED) RLQR_TRY(factor_whole(h, h->ws32, h->any_pref64 ? h->pref32 : nullptr, true, st));
-  else RLQR_TRY(factor_scan(h, st));
-  MaskArgs m{};
-  m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
-  m.bad = is_scan(h->mode) ? h->bad : nullptr;
-  m.pref32 = h->any_pref64 ? h->pref32 : nullptr;
-  RLQR_TRY(launch_masks(m, st));
-  RLQR_TRY(factor_whole(h, h->ws64, h->flag64, false, st));
+  if (rhs) {
+    h->pk_fused = true;
+    h->pk_rhs = *rhs;
+  }
   return RLQR_OK;
+}
+
+extern "C" rlqr_status rlqr_factor(rlqr_handle* h, const rlqr_lhs* lhs, rlqr_stream stv) {
+  return factor_impl(h, lhs, nullptr, (hipStream_t)stv);
+}
+
+extern "C" rlqr_status rlqr_factor_rhs(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_rhs* rhs, rlqr_stream stv) {
+  if (!rhs) return RLQR_E_INVALID;
+  return factor_impl(h, lhs, rhs, (hipStream_t)stv);
 }
 
 static SolveArgs solve_args(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
@@ -525,12 +562,13 @@ static CheckArgs check_args(rlqr_handle* h, int final_pass, double tol, const in
 // Whole-instance solves, one launch per tile class; run masks select instances.
 // skip (scan mode) leaves the multi-segment instances to the segment solve.
 static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
-                               const double* corr, hipStream_t st) {
+                               const double* corr, hipStream_t st, bool fwd_only = false) {
   for (int c = 0; c < TILE_CLASSES; ++c) {
     if (h->count[c] == 0) continue;
     SolveArgs a = solve_args(h, rhs, out, fp32, run, corr);
     a.list = h->list[c];
-    hipError_t e = (c == TILE_16) ? launch_solve(a, h->count[c], fp32, st)
+    a.fwd_only = (fwd_only && c == TILE_16) ? 1 : 0;
+    hipError_t e = (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, st)
                                   : launch_solve_mw(c, a, h->count[c], fp32, st);
     if (e != hipSuccess) return RLQR_E_HIP;
   }
@@ -564,7 +602,7 @@ static rlqr_status solve_segments(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol*
 // Pass p of the refinement: solve (p == 0) or correct (p > 0) every
 // instance not yet converged, then its residual and the convergence check.
 static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, int pass, double tol,
-                              const int32_t* run64_override, hipStream_t st) {
+                              const int32_t* run64_override, hipStream_t st, bool fwd_only = false) {
   const double* corr = pass == 0 ? nullptr : h->res[(pass - 1) & 1];
   double* res_out = h->res[pass & 1];
   const int32_t *r32 = nullptr, *r64 = nullptr, *rres = nullptr;
@@ -587,13 +625,13 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
       RLQR_TRY(launch_masks(m, st));
       if ((s = solve_whole(h, rhs, out, true, h->run1, corr, st)) != RLQR_OK) return s;
       if ((s = solve_segments(h, rhs, out, r32, corr, st)) != RLQR_OK) return s;
-    } else if ((s = solve_whole(h, rhs, out, true, r32, corr, st)) != RLQR_OK) {
+    } else if ((s = solve_whole(h, rhs, out, true, r32, corr, st, fwd_only)) != RLQR_OK) {
       return s;
     }
   }
-  if ((s = solve_whole(h, rhs, out, false, r64, corr, st)) != RLQR_OK) return s;
+  if ((s = solve_whole(h, rhs, out, false, r64, corr, st, fwd_only)) != RLQR_OK) return s;
   ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
-  RLQR_TRY(launch_residual(ra, st));
+  RLQR_TRY(launch_residual(ra, h->shape_all, st));
   RLQR_TRY(launch_check(check_args(h, 0, tol, rres), st));
   return RLQR_OK;
 }
@@ -612,8 +650,11 @@ extern "C" rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol*
   // per-instance residual maxima start at zero (the check kernel clears resmax after each pass)
   RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->resmax), 2 * h->B, 0, st));
   RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->bmax), 2 * h->B, 0, st));
+  // the first pass may start at the forward rollout (rlqr_factor_rhs with these rhs arrays)
+  const bool fused = h->pk_fused && h->pk_rhs.q == rhs->q && h->pk_rhs.r == rhs->r && h->pk_rhs.c == rhs->c;
+  h->pk_fused = false;  // the passes below overwrite pk
   for (int pass = 0; pass <= max_refine; ++pass)
-    if ((s = solve_pass(h, rhs, out, pass, rel_tol, nullptr, st)) != RLQR_OK) return s;
+    if ((s = solve_pass(h, rhs, out, pass, rel_tol, nullptr, st, fused && pass == 0)) != RLQR_OK) return s;
   RLQR_TRY(launch_check(check_args(h, 1, rel_tol, nullptr), st));
 
   if (h->mode != RLQR_SEQ_FP64) {
@@ -662,7 +703,7 @@ extern "C" rlqr_status rlqr_residual(rlqr_handle* h, const rlqr_rhs* rhs, const 
   RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->bmax), 2 * h->B, 0, st));
   ResidualArgs a = residual_args(h, rhs, z, res, nullptr);
   a.info = nullptr;  // evaluate every instance at the given z, singular ones included
-  RLQR_TRY(launch_residual(a, st));
+  RLQR_TRY(launch_residual(a, h->shape_all, st));
   if (inst_relres) {
     CheckArgs c = check_args(h, 1, 0.0, nullptr);
     c.plain = 1;
@@ -686,7 +727,7 @@ extern "C" rlqr_status rlqr_graph_capture(rlqr_handle* h, const rlqr_lhs* lhs, c
     (void)hipGetLastError();
     return RLQR_E_HIP;
   }
-  rlqr_status s = rlqr_factor(h, lhs, stv);
+  rlqr_status s = rlqr_factor_rhs(h, lhs, rhs, stv);
   if (s == RLQR_OK) s = rlqr_solve(h, rhs, out, rel_tol, max_refine, inst_status, inst_relres, stv);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(st, &g);

@@ -154,17 +154,17 @@ __device__ __forceinline__ void sweep_pivot(double (&X)[4], int lane, double tol
   const bool nz = fabs(d) > tol;
   dsave = (lane == J) ? d : dsave;
   const double rd = nz ? recip(d) : 0.0;
+  // One formula for every element but row J: X - ci cc' / d with X zeroed in
+  // column J and cc' = -1 there, so column J becomes ci / d (the same
+  // rounding as ci * rd); row J is cc' / d (cc / d, and -1/d at (J, J)).
   const bool cj = col == J;
+  const double ccs = cj ? -1.0 : cc;
+  const double keep = cj ? 0.0 : 1.0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double gen = __fma_rn(-(ci[v] * cc), rd, X[v]);
-    const double colv = ci[v] * rd;
-    if (v == VJ) {
-      const double rowv = cj ? -rd : cc * rd;
-      X[v] = (grp == GJ) ? rowv : (cj ? colv : gen);
-    } else {
-      X[v] = cj ? colv : gen;
-    }
+    const double gen = __fma_rn(-(ci[v] * ccs), rd, X[v] * keep);
+    if (v == VJ) X[v] = (grp == GJ) ? ccs * rd : gen;
+    else X[v] = gen;
   }
 }
 

@@ -48,6 +48,10 @@ struct FactorArgs {
   const double *Q, *M, *R, *A, *B, *delta;
   void* ws;
   SegStats* stats;        // one per segment (indexed like segs)
+  // optional right-hand side (one-wavefront kernels, whole instances): the
+  // backward vector pass is run inside the stage loop and p_i / k_i written to pk
+  const double *q, *r, *c;
+  double* pk;
 };
 
 struct MergeArgs {
@@ -117,6 +121,7 @@ struct SolveArgs {
   const double* corr;       // if set: correction pass, right-hand side = this residual, z += dz
   double *x, *u, *y;
   double* pk;               // p_i / k_i scratch
+  int fwd_only;             // whole-instance one-wavefront solves: p_i / k_i already in pk (fused factor)
 };
 hipError_t launch_seg_solve(int cls, const SolveArgs& a, int nblocks, hipStream_t st);
 
@@ -177,11 +182,22 @@ inline int tile_class(int n, int m) {
 }
 int tile_blocks_per_stage(int cls);  // 16x16 blocks of workspace per stage
 
-hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, hipStream_t st);
+// Stage shapes of the one-wavefront kernels compiled with n and m fixed (the
+// paper's cart-pole / acrobot and quad-pendulum sizes and a quadrotor); a
+// launch over instances that all share one of them takes the fixed-shape
+// kernel, any other launch the general one (SHAPE_ANY).
+enum { SHAPE_ANY = 0, SHAPE_4_1, SHAPE_8_2, SHAPE_12_4 };
+inline int fixed_shape(int n, int m) {
+  if (n == 4 && m == 1) return SHAPE_4_1;
+  if (n == 8 && m == 2) return SHAPE_8_2;
+  if (n == 12 && m == 4) return SHAPE_12_4;
+  return SHAPE_ANY;
+}
+hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, int shape, hipStream_t st);
 hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st);
 hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st);
-hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, hipStream_t st);
-hipError_t launch_residual(const ResidualArgs& a, hipStream_t st);
+hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, int shape, hipStream_t st);
+hipError_t launch_residual(const ResidualArgs& a, int shape, hipStream_t st);
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 hipError_t launch_inertia(const InertiaArgs& a, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t st);

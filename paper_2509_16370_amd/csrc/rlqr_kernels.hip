@@ -117,7 +117,67 @@ __device__ __forceinline__ double diag_scale(const double (&X)[4], int lo, int h
   return wave_max_rows(s);
 }
 
+// ------------------------------------------------------------------ tile-vector helpers
+
+// y[c] = sum_r Tile[r][c] * vec[r] for the register tile (rows trow<TL>),
+// vec in LDS; result replicated over the four lane groups.
+template <typename TL>
+__device__ __forceinline__ double tmatvec(const double (&X)[4], const double* vec, int lane) {
+  const int grp = lane >> 4;
+  double s = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) s += X[v] * vec[trow<TL>(grp, v)];
+  return group_sum(s);
+}
+
+// tmatvec of the tile as stored (each element rounded to TL first)
+template <typename TL>
+__device__ __forceinline__ double tmatvec_r(const double (&X)[4], const double* vec, int lane) {
+  const int grp = lane >> 4;
+  double s = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) s += (double)(TL)X[v] * vec[trow<TL>(grp, v)];
+  return group_sum(s);
+}
+
+// masked vector element load: v[i] if ok else 0. A masked-off lane reads the
+// zero below instead (an empty block may sit at the end of an array).
+__device__ double g_zero = 0.0;
+__device__ __forceinline__ double ld_or0(const double* __restrict__ v, int64_t i, bool ok) {
+  const double* p = ok ? v + i : &g_zero;
+  const double x = *p;
+  return ok ? x : 0.0;
+}
+
 // ------------------------------------------------------------------ factor
+
+// One step k of the backward vector pass (Theorem "main-seq-theorem"):
+//   g = S_hat_{k+1}^{-1} (p_{k+1} + P_{k+1} c_{k+1}),  h = r_k + B_k^T g,
+//   k_k = -G_k^{-1} h,  p_k = q_k + A_k^T g + K_k^T h
+// from the tiles Zp = Z_{k+1} (P_{k+1}), Xn = X_{k+1} = -S_hat_{k+1}^{-1},
+// Zk = Z_k and ab = [A_k B_k] (all in the register layout trow<TG>); p holds
+// p_{k+1} on entry and p_k on exit (x lanes), the return value is k_k (u lanes).
+template <typename TG>
+__device__ __forceinline__ double bwd_vec_step(const double (&Zp)[4], const double (&Xn)[4], const double (&ab)[4],
+                                               const double (&Zk)[4], double& p, double ck, double qk, double rk,
+                                               double (*sv)[16], bool xr, bool ur, bool own, int col, int lane) {
+  wave_sync();
+  if (own) sv[0][col] = ck;
+  wave_sync();
+  const double vv = xr ? p + tmatvec<TG>(Zp, sv[0], lane) : 0.0;  // p + P_{k+1} c_{k+1}
+  if (own) sv[1][col] = vv;
+  wave_sync();
+  const double g = -tmatvec<TG>(Xn, sv[1], lane);                  // S_hat^{-1} v
+  if (own) sv[0][col] = xr ? g : 0.0;
+  wave_sync();
+  const double abg = tmatvec<TG>(ab, sv[0], lane);                 // [A^T g; B^T g]
+  const double h = ur ? rk + abg : 0.0;
+  if (own) sv[1][col] = h;
+  wave_sync();
+  const double zh = tmatvec<TG>(Zk, sv[1], lane);                  // [-K^T h; -G^{-1} h]
+  p = xr ? qk + abg - zh : 0.0;
+  return zh;
+}
 
 // Raw stage blocks [Q_k | M_k | R_k | A_k | B_k | 0] staged in LDS by direct
 // global-to-LDS copies (no registers hold the data in flight). STG_MAX covers
@@ -187,13 +247,15 @@ __device__ __forceinline__ typename AccT<T>::type gemm_abt_t(const double* stg, 
   return acc;
 }
 
-template <typename TG>
+// SN, SM > 0: stage shape fixed at compile time (every instance of the launch
+// has n = SN, m = SM); 0: taken from the instance.
+template <typename TG, int SN, int SM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_factor16(FactorArgs a) {
   const SegDesc sd = a.segs[blockIdx.x];
   const int b = sd.inst;
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
-  const int N = mt.N, n = mt.n, m = mt.m;
+  const int N = mt.N, n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
   const int klo = sd.lo, khi = sd.hi;
   const double delta = a.delta[b];
   const double* __restrict__ Qg = a.Q + mt.oQ;
@@ -219,6 +281,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   ps.init();
   const double eps = 2.220446049250313e-16;
   const int oZ = 2 * n * n + 2 * n * m + m * m;
+
+  // with a right-hand side (whole instances only): the backward vector pass
+  // of the solve rides along, on the stage's tiles rounded as stored, so p_k
+  // and k_k are those the solve's own backward pass would compute
+  const bool vec = a.q != nullptr;
+  const bool xr = col < n, ur = col >= n && col < n + m, own = grp == 0;
+  __shared__ double sv[2][16];
+  const double* __restrict__ qg = a.q + mt.oq;
+  const double* __restrict__ rg = a.r + mt.or_;
+  const double* __restrict__ cg = a.c + mt.oc;
+  double* __restrict__ pg = a.pk + mt.opk;
+  double* __restrict__ kg = a.pk + mt.opk + (int64_t)(N + 1) * n;
+  double pv = 0.0;
+  if (vec) {
+    pv = ld_or0(qg, (int64_t)N * n + col, xr);
+    if (own && xr) pg[(int64_t)N * n + col] = pv;
+  }
 
   // P_hi: Q_N at the top of the horizon, else the boundary tile of the scan
   double P[4];
@@ -248,15 +327,37 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 
   for (int k = khi - 1; k >= klo; --k) {
+    // the lane index, opaque to the compiler once per stage: the per-pivot
+    // lane masks of the sweeps are then recomputed inside the stage (one
+    // compare each) instead of being hoisted out of the loop, where sixteen
+    // of them per sweep exhaust the scalar registers
+    int lane_s = lane;
+    asm volatile("" : "+v"(lane_s));
+    double ck = 0.0, qk = 0.0, rk = 0.0;
+    if (vec) {
+      ck = ld_or0(cg, (int64_t)(k + 1) * n + col, xr);
+      qk = ld_or0(qg, (int64_t)k * n + col, xr);
+      rk = ld_or0(rg, (int64_t)k * m + (col - n), ur);
+    }
     // X = I + delta P_{k+1}; sweep -> -S_hat_{k+1}^{-1}  (no stage data needed)
     double X[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
     {
-      const double sc = diag_scale<TG>(X, 0, n, lane);
-      sweep16<TG>(X, 0, n, lane, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
+      const double sc = diag_scale<TG>(X, 0, n, lane_s);
+      sweep16<TG>(X, 0, n, lane_s, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
     }
     tile_store(ws + (int64_t)(2 * (k + 1) + 1) * 256, X, lane);
+    if (vec) {  // vector pass, first part: g = S_hat_{k+1}^{-1} (p_{k+1} + P_{k+1} c_{k+1})
+      wave_sync();
+      if (own) sv[0][col] = ck;
+      wave_sync();
+      const double vv = xr ? pv + tmatvec_r<TG>(P, sv[0], lane) : 0.0;
+      if (own) sv[1][col] = vv;
+      wave_sync();
+      const double g = -tmatvec_r<TG>(X, sv[1], lane);
+      if (own) sv[0][col] = xr ? g : 0.0;
+    }
     tile_to_lds<TG>(sP, P, lane);
     tile_to_lds<TG>(sX, X, lane);
     wave_sync();
@@ -295,6 +396,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
       for (int v = 0; v < 4; ++v) Z[v] = (double)acc[v] + H[v];
     }
+    double abg = 0.0;
+    if (vec) {  // second part: [A^T g; B^T g] from the staged blocks, h = r_k + B^T g
+      wave_sync();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) abg += stg[stg_ab(trow<TG>(grp, v), col, n, m)] * sv[0][trow<TG>(grp, v)];
+      abg = group_sum(abg);
+      if (own) sv[1][col] = ur ? rk + abg : 0.0;
+    }
     // the staged blocks are no longer read: fetch step k-1's
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): reads of stg returned
     wave_sync();
@@ -307,10 +416,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     for (int v = 0; v < 4; ++v) Z[v] = 0.5 * (Z[v] + sD[col * LD + trow<TG>(grp, v)]);
     // sweep the control block: G_k pivots
     {
-      const double sc = diag_scale<TG>(Z, n, n + m, lane);
-      sweep16<TG>(Z, n, n + m, lane, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
+      const double sc = diag_scale<TG>(Z, n, n + m, lane_s);
+      sweep16<TG>(Z, n, n + m, lane_s, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
     }
     tile_store(ws + (int64_t)(2 * k) * 256, Z, lane);
+    if (vec) {  // third part: k_k = -G_k^{-1} h, p_k = q_k + A^T g + K_k^T h
+      wave_sync();
+      const double zh = tmatvec_r<TG>(Z, sv[1], lane);
+      pv = xr ? qk + abg - zh : 0.0;
+      if (own) {
+        if (xr) pg[(int64_t)k * n + col] = pv;
+        if (ur) kg[(int64_t)k * m + (col - n)] = zh;
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) P[v] = (trow<TG>(grp, v) < n && col < n) ? Z[v] : 0.0;
     wave_sync();
@@ -337,38 +455,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
 // ------------------------------------------------------------------ solve
 
-// y[c] = sum_r Tile[r][c] * vec[r] for the register tile (rows trow<TL>),
-// vec in LDS; result replicated over the four lane groups.
-template <typename TL>
-__device__ __forceinline__ double tmatvec(const double (&X)[4], const double* vec, int lane) {
-  const int grp = lane >> 4;
-  double s = 0.0;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) s += X[v] * vec[trow<TL>(grp, v)];
-  return group_sum(s);
-}
-
-// masked vector element load: v[i] if ok else 0. A masked-off lane reads the
-// zero below instead (an empty block may sit at the end of an array).
-__device__ double g_zero = 0.0;
-__device__ __forceinline__ double ld_or0(const double* __restrict__ v, int64_t i, bool ok) {
-  const double* p = ok ? v + i : &g_zero;
-  const double x = *p;
-  return ok ? x : 0.0;
-}
-
 // Solve pass: backward vector pass and forward rollout (see the file header).
 // corr == NULL: solve K z = -b and write z.  corr != NULL: solve for the
 // correction with right-hand side corr (the previous residual) and add it to
 // z. The tiles and stage blocks of the next step are loaded one step ahead
 // so that the dependent chain does not wait on memory.
-template <typename TG>
+template <typename TG, int SN, int SM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_solve16(SolveArgs a) {
   const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
-  const int N = mt.N, n = mt.n, m = mt.m;
+  const int N = mt.N, n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
   const double delta = a.delta[b];
   const double* __restrict__ Ag = a.A + mt.oA;
   const double* __restrict__ Bg = a.B + mt.oB;
@@ -406,64 +504,54 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   const bool own = grp == 0;  // lanes 0..15 write outputs
 
   // ---- backward vector pass (k = N-1 .. 0), one step of lookahead
-  double p = ld_or0(qb, (int64_t)N * qs + col, xr);
-  if (own && xr) pg[(int64_t)N * n + col] = p;
-  double Zp[4], Zk[4], Xn[4], ab[4];
-  tile_load(Zp, ws + (int64_t)(2 * N) * 256, lane);
-  if (N > 0) {
-    tile_load(Zk, ws + (int64_t)(2 * (N - 1)) * 256, lane);
-    tile_load(Xn, ws + (int64_t)(2 * N + 1) * 256, lane);
+  // (already done by the factorization when fwd_only is set)
+  double Zk[4], Xn[4];
+  if (!a.fwd_only) {
+    double p = ld_or0(qb, (int64_t)N * qs + col, xr);
+    if (own && xr) pg[(int64_t)N * n + col] = p;
+    double Zp[4], ab[4];
+    tile_load(Zp, ws + (int64_t)(2 * N) * 256, lane);
+    if (N > 0) {
+      tile_load(Zk, ws + (int64_t)(2 * (N - 1)) * 256, lane);
+      tile_load(Xn, ws + (int64_t)(2 * N + 1) * 256, lane);
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      ab[v] = ab_elem(Ag + (int64_t)(N - 1) * n * n, Bg + (int64_t)(N - 1) * n * m, n, m, trow<TG>(grp, v), col);
-  }
-  double ck = 0.0, qk = 0.0, rk = 0.0;
-  if (N > 0) {
-    ck = ld_or0(cb, (int64_t)N * n + col, xr);
-    qk = ld_or0(qb, (int64_t)(N - 1) * qs + col, xr);
-    rk = ld_or0(rb, (int64_t)(N - 1) * rs + (col - n), ur);
-  }
-  for (int k = N - 1; k >= 0; --k) {
-    // next step's operands
-    double Zk1[4], Xn1[4], ab1[4];
-    const int k1 = k > 0 ? k - 1 : 0;
-    tile_load(Zk1, ws + (int64_t)(2 * k1) * 256, lane);
-    tile_load(Xn1, ws + (int64_t)(2 * (k1 + 1) + 1) * 256, lane);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      ab1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, trow<TG>(grp, v), col);
-    const double ck1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
-    const double qk1 = ld_or0(qb, (int64_t)k1 * qs + col, xr);
-    const double rk1 = ld_or0(rb, (int64_t)k1 * rs + (col - n), ur);
-    wave_sync();
-    if (own) sv[0][col] = ck;
-    wave_sync();
-    const double vv = xr ? p + tmatvec<TG>(Zp, sv[0], lane) : 0.0;  // p + P_{k+1} c_{k+1}
-    if (own) sv[1][col] = vv;
-    wave_sync();
-    const double g = -tmatvec<TG>(Xn, sv[1], lane);                  // S_hat^{-1} v
-    if (own) sv[0][col] = xr ? g : 0.0;
-    wave_sync();
-    const double abg = tmatvec<TG>(ab, sv[0], lane);                 // [A^T g; B^T g]
-    const double h = ur ? rk + abg : 0.0;
-    if (own) sv[1][col] = h;
-    wave_sync();
-    const double zh = tmatvec<TG>(Zk, sv[1], lane);                  // [-K^T h; -G^{-1} h]
-    p = xr ? qk + abg - zh : 0.0;
-    if (own) {
-      if (xr) pg[(int64_t)k * n + col] = p;
-      if (ur) kg[(int64_t)k * m + (col - n)] = zh;
+      for (int v = 0; v < 4; ++v)
+        ab[v] = ab_elem(Ag + (int64_t)(N - 1) * n * n, Bg + (int64_t)(N - 1) * n * m, n, m, trow<TG>(grp, v), col);
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Zp[v] = Zk[v];
-      Zk[v] = Zk1[v];
-      Xn[v] = Xn1[v];
-      ab[v] = ab1[v];
+    double ck = 0.0, qk = 0.0, rk = 0.0;
+    if (N > 0) {
+      ck = ld_or0(cb, (int64_t)N * n + col, xr);
+      qk = ld_or0(qb, (int64_t)(N - 1) * qs + col, xr);
+      rk = ld_or0(rb, (int64_t)(N - 1) * rs + (col - n), ur);
     }
-    ck = ck1;
-    qk = qk1;
-    rk = rk1;
+    for (int k = N - 1; k >= 0; --k) {
+      // next step's operands
+      double Zk1[4], Xn1[4], ab1[4];
+      const int k1 = k > 0 ? k - 1 : 0;
+      tile_load(Zk1, ws + (int64_t)(2 * k1) * 256, lane);
+      tile_load(Xn1, ws + (int64_t)(2 * (k1 + 1) + 1) * 256, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        ab1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, trow<TG>(grp, v), col);
+      const double ck1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
+      const double qk1 = ld_or0(qb, (int64_t)k1 * qs + col, xr);
+      const double rk1 = ld_or0(rb, (int64_t)k1 * rs + (col - n), ur);
+      const double zh = bwd_vec_step<TG>(Zp, Xn, ab, Zk, p, ck, qk, rk, sv, xr, ur, own, col, lane);
+      if (own) {
+        if (xr) pg[(int64_t)k * n + col] = p;
+        if (ur) kg[(int64_t)k * m + (col - n)] = zh;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Zp[v] = Zk[v];
+        Zk[v] = Zk1[v];
+        Xn[v] = Xn1[v];
+        ab[v] = ab1[v];
+      }
+      ck = ck1;
+      qk = qk1;
+      rk = rk1;
+    }
   }
   __syncthreads();  // p/k written by lanes 0..15 are read by all lanes below
 
@@ -576,8 +664,8 @@ struct ResVec {
   double xi, ui, yi, yn, xn, qi, ri, cn;
 };
 
-__device__ __forceinline__ void res_load_vec(const ResidualArgs& a, const InstMeta& mt, int i, int lane, ResVec& o) {
-  const int n = mt.n, m = mt.m;
+__device__ __forceinline__ void res_load_vec(const ResidualArgs& a, const InstMeta& mt, int n, int m, int i, int lane,
+                                             ResVec& o) {
   const int col = lane & 15;
   const bool xr = col < n, ur = col >= n && col < n + m;
   o.xi = ld_or0(a.x + mt.ox, (int64_t)i * n + col, xr);
@@ -590,9 +678,8 @@ __device__ __forceinline__ void res_load_vec(const ResidualArgs& a, const InstMe
   o.cn = ld_or0(a.c + mt.oc, (int64_t)(i + 1) * n + col, xr);
 }
 
-__device__ __forceinline__ void res_stage_dma(const ResidualArgs& a, const InstMeta& mt, int i, double* stg,
-                                              int lane) {
-  const int n = mt.n, m = mt.m;
+__device__ __forceinline__ void res_stage_dma(const ResidualArgs& a, const InstMeta& mt, int n, int m, int i,
+                                              double* stg, int lane) {
   dma_stage(stg, a.Q + mt.oQ + (int64_t)i * n * n, a.M + mt.oM + (int64_t)i * n * m,
             a.R + mt.oR + (int64_t)i * m * m, a.A + mt.oA + (int64_t)i * n * n,
             a.B + mt.oB + (int64_t)i * n * m, n, m, lane);
@@ -600,11 +687,11 @@ __device__ __forceinline__ void res_stage_dma(const ResidualArgs& a, const InstM
 
 // Residual rows of stage i < N from the staged blocks (Hessian, [A B], [A B]^T
 // read at the per-lane staging indices) and the stage vectors.
-__device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMeta& mt, double delta, int i,
-                                            const double* stg, const int (&iH)[4], const int (&iAB)[4],
+__device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMeta& mt, int n, int m, double delta,
+                                            int i, const double* stg, const int (&iH)[4], const int (&iAB)[4],
                                             const int (&iABT)[4], const ResVec& o, double* sv, double& rmax,
                                             double& bmax, int lane) {
-  const int N = mt.N, n = mt.n, m = mt.m;
+  const int N = mt.N;
   const int col = lane & 15, grp = lane >> 4;
   const bool xr = col < n, ur = col >= n && col < n + m, own = grp == 0;
   double* res = a.res ? a.res + mt.ores : nullptr;
@@ -647,9 +734,9 @@ __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMet
 }
 
 // slot N of an instance with n + m <= 16: terminal row and c_0 row
-__device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMeta& mt, double delta, double* sv,
-                                             double& rmax, double& bmax, int lane) {
-  const int N = mt.N, n = mt.n, m = mt.m;
+__device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMeta& mt, int n, int m, double delta,
+                                             double* sv, double& rmax, double& bmax, int lane) {
+  const int N = mt.N;
   const int col = lane & 15, grp = lane >> 4;
   const bool xr = col < n, own = grp == 0;
   const double* q = a.q + mt.oq; const double* c = a.c + mt.oc;
@@ -756,6 +843,8 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
   }
 }
 
+// SN, SM > 0: every instance of the batch has n = SN, m = SM (n + m <= 16).
+template <int SN, int SM>
 __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
   __shared__ double sv[32];
   // two distinct staging arrays: a direct global-to-LDS copy into one never
@@ -770,7 +859,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
     if (a.skip && a.skip[b]) continue;
     if (a.info && a.info[b].singular) continue;
     const InstMeta mt = a.meta[b];
-    const int n = mt.n, m = mt.m;
+    const int n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
     const double delta = a.delta[b];
     double rmax = 0.0, bmax = 0.0;
     if (n + m <= 16) {
@@ -792,29 +881,29 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
       }
       ResVec v0, v1;
       if (ch.i0 < iend) {
-        res_stage_dma(a, mt, ch.i0, stgA, lane);
-        res_load_vec(a, mt, ch.i0, lane, v0);
+        res_stage_dma(a, mt, n, m, ch.i0, stgA, lane);
+        res_load_vec(a, mt, n, m, ch.i0, lane, v0);
       }
       for (int i = ch.i0; i < iend; i += 2) {
         wait_vmem();
         wave_sync();
         if (i + 1 < iend) {
-          res_stage_dma(a, mt, i + 1, stgB, lane);
-          res_load_vec(a, mt, i + 1, lane, v1);
+          res_stage_dma(a, mt, n, m, i + 1, stgB, lane);
+          res_load_vec(a, mt, n, m, i + 1, lane, v1);
         }
-        res_compute(a, mt, delta, i, stgA, iH, iAB, iABT, v0, sv, rmax, bmax, lane);
+        res_compute(a, mt, n, m, delta, i, stgA, iH, iAB, iABT, v0, sv, rmax, bmax, lane);
         if (i + 1 >= iend) break;
         __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgA returned before it is refilled
         wait_vmem();
         wave_sync();
         if (i + 2 < iend) {
-          res_stage_dma(a, mt, i + 2, stgA, lane);
-          res_load_vec(a, mt, i + 2, lane, v0);
+          res_stage_dma(a, mt, n, m, i + 2, stgA, lane);
+          res_load_vec(a, mt, n, m, i + 2, lane, v0);
         }
-        res_compute(a, mt, delta, i + 1, stgB, iH, iAB, iABT, v1, sv, rmax, bmax, lane);
+        res_compute(a, mt, n, m, delta, i + 1, stgB, iH, iAB, iABT, v1, sv, rmax, bmax, lane);
         __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgB returned before it is refilled
       }
-      if (ch.i1 > mt.N) res_terminal(a, mt, delta, sv, rmax, bmax, lane);
+      if (ch.i1 > mt.N) res_terminal(a, mt, n, m, delta, sv, rmax, bmax, lane);
     } else {
       for (int i = ch.i0; i < ch.i1; ++i) residual_slot_rows(a, mt, b, i, rmax, bmax, lane);
     }
@@ -952,28 +1041,53 @@ __global__ void k_fill_i32(int32_t* p, int count, int32_t v) {
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
-  if (fp32_products)
-    hipLaunchKernelGGL(k_factor16<float>, dim3(nblocks), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_factor16<double>, dim3(nblocks), dim3(64), 0, st, a);
+template <typename TG, int SN, int SM>
+static hipError_t launch_factor_t(const FactorArgs& a, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_factor16<TG, SN, SM>), dim3(nblocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
-
-hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, hipStream_t st) {
+template <typename TG>
+static hipError_t launch_factor_s(const FactorArgs& a, int nblocks, int shape, hipStream_t st) {
+  switch (shape) {
+    case SHAPE_4_1: return launch_factor_t<TG, 4, 1>(a, nblocks, st);
+    case SHAPE_8_2: return launch_factor_t<TG, 8, 2>(a, nblocks, st);
+    case SHAPE_12_4: return launch_factor_t<TG, 12, 4>(a, nblocks, st);
+    default: return launch_factor_t<TG, 0, 0>(a, nblocks, st);
+  }
+}
+hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, int shape, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (fp32_tiles)
-    hipLaunchKernelGGL(k_solve16<float>, dim3(nblocks), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_solve16<double>, dim3(nblocks), dim3(64), 0, st, a);
-  return hipGetLastError();
+  return fp32_products ? launch_factor_s<float>(a, nblocks, shape, st) : launch_factor_s<double>(a, nblocks, shape, st);
 }
 
-hipError_t launch_residual(const ResidualArgs& a, hipStream_t st) {
+template <typename TG, int SN, int SM>
+static hipError_t launch_solve_t(const SolveArgs& a, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_solve16<TG, SN, SM>), dim3(nblocks), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+template <typename TG>
+static hipError_t launch_solve_s(const SolveArgs& a, int nblocks, int shape, hipStream_t st) {
+  switch (shape) {
+    case SHAPE_4_1: return launch_solve_t<TG, 4, 1>(a, nblocks, st);
+    case SHAPE_8_2: return launch_solve_t<TG, 8, 2>(a, nblocks, st);
+    case SHAPE_12_4: return launch_solve_t<TG, 12, 4>(a, nblocks, st);
+    default: return launch_solve_t<TG, 0, 0>(a, nblocks, st);
+  }
+}
+hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, int shape, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  return fp32_tiles ? launch_solve_s<float>(a, nblocks, shape, st) : launch_solve_s<double>(a, nblocks, shape, st);
+}
+
+hipError_t launch_residual(const ResidualArgs& a, int shape, hipStream_t st) {
   if (a.nchunks <= 0) return hipSuccess;
-  const int64_t grid = a.nchunks < (1 << 20) ? a.nchunks : (1 << 20);
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)grid), dim3(64), 0, st, a);
+  const dim3 grid((unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20)));
+  switch (shape) {
+    case SHAPE_4_1: hipLaunchKernelGGL((k_residual<4, 1>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_8_2: hipLaunchKernelGGL((k_residual<8, 2>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_12_4: hipLaunchKernelGGL((k_residual<12, 4>), grid, dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_residual<0, 0>), grid, dim3(64), 0, st, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -2,9 +2,9 @@
 
 Argument marshalling only: every step of the solve runs in the HIP kernels of
 librlqr.so. torch tensors provide device memory and the stream. The functions
-rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_solve,
-rlqr_pivot_inertia, rlqr_residual and rlqr_destroy carry the C names; `Solver`
-wraps one handle.
+rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_factor_rhs,
+rlqr_solve, rlqr_pivot_inertia, rlqr_residual and rlqr_destroy carry the C
+names; `Solver` wraps one handle.
 
 If librlqr.so is missing this module raises at import: there is no fallback.
 """
@@ -73,6 +73,7 @@ _lib.rlqr_graph_capture.argtypes = [_vp, ctypes.POINTER(_Lhs), ctypes.POINTER(_R
 _lib.rlqr_graph_launch.argtypes = [_vp, _vp]
 _lib.rlqr_layout_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
 _lib.rlqr_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), _vp]
+_lib.rlqr_factor_rhs.argtypes = [_vp, ctypes.POINTER(_Lhs), ctypes.POINTER(_Rhs), _vp]
 _lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
                             ctypes.c_int32, _vp, _vp, _vp]
 _lib.rlqr_pivot_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -82,11 +83,11 @@ _lib.rlqr_destroy.restype = None
 _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
 for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-           "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch"):
+           "rlqr_factor_rhs", "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-            "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
+            "rlqr_factor_rhs", "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
             "rlqr_destroy", "rlqr_status_string")
 
 
@@ -163,6 +164,12 @@ def rlqr_factor(h, Q, M, R, A, B, delta, stream=None):
     _check(_lib.rlqr_factor(h, ctypes.byref(lhs), _stream(stream)), "rlqr_factor")
 
 
+def rlqr_factor_rhs(h, Q, M, R, A, B, delta, q, r, c, stream=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    _check(_lib.rlqr_factor_rhs(h, ctypes.byref(lhs), ctypes.byref(rhs), _stream(stream)), "rlqr_factor_rhs")
+
+
 def rlqr_solve(h, q, r, c, x, u, y, rel_tol, max_refine, inst_status=None, inst_relres=None, stream=None):
     rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
     sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
@@ -237,13 +244,22 @@ class Solver:
     def empty(self, name: str):
         return self.torch.empty(max(self.size(name), 1), dtype=self.torch.float64, device=self.device)
 
-    def factor(self, lhs: Dict[str, "torch.Tensor"], stream=None):
+    def factor(self, lhs: Dict[str, "torch.Tensor"], rhs: Optional[Dict[str, "torch.Tensor"]] = None, stream=None):
+        """rlqr_factor, or rlqr_factor_rhs when the next solve's rhs is given."""
         for k in ("Q", "M", "R", "A", "B"):
             t = lhs[k]
             assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() >= self.size(k), k
         assert lhs["delta"].numel() >= self.batch and lhs["delta"].dtype == self.torch.float64
         self._lhs = lhs  # the library re-reads the lhs during refinement: keep it alive
-        rlqr_factor(self.handle, *(lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")), stream=stream)
+        args = [lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")]
+        if rhs is None:
+            rlqr_factor(self.handle, *args, stream=stream)
+            return
+        for k in ("q", "r", "c"):
+            t = rhs[k]
+            assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() >= self.size(k), k
+        self._rhs = rhs
+        rlqr_factor_rhs(self.handle, *args, rhs["q"], rhs["r"], rhs["c"], stream=stream)
 
     def solve(self, rhs, out=None, rel_tol: float = 1e-8, max_refine: int = 0, stream=None):
         torch = self.torch

@@ -30,12 +30,12 @@ def rl():
     return rlqr
 
 
-def run(rl, insts, mode, rel_tol=1e-8, max_refine=3):
+def run(rl, insts, mode, rel_tol=1e-8, max_refine=3, fused=False):
     import torch
     packed = wl.pack(insts)
     lhs, rhs = rl.to_device(packed)
     s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
-    s.factor(lhs)
+    s.factor(lhs, rhs if fused else None)
     out, status, relres = s.solve(rhs, rel_tol=rel_tol, max_refine=max_refine)
     verdict, first_bad, inertia = s.pivot_inertia()
     torch.cuda.synchronize()
@@ -128,6 +128,69 @@ def test_random_ragged_batch_matches_oracle(rl, mode):
         oracle_rel = oracle.rel_residual(inst, ref["x"], ref["u"], ref["y"])
         if ov and oracle_rel < 1e-12:
             compare(inst, res["sols"][b], ref, 1e-10 if mode == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "scan"])
+@pytest.mark.parametrize("shape", [(4, 1), (8, 2), (12, 4)])
+def test_fixed_shape_kernels_match_oracle(rl, mode, shape):
+    """A batch whose one-wavefront instances all share one of the stage shapes
+    compiled with n and m fixed takes those kernels; ragged N (including 0
+    and 1), deltas from 0 to 0.1 and indefinite instances."""
+    n, m = shape
+    print(f"[gpu] fixed shape n={n} m={m} mode={mode}", flush=True)
+    rng = np.random.default_rng(n * 10 + m)
+    insts = []
+    for i in range(20):
+        N = int(rng.choice([0, 1, 2, 7, 31, 64, 130]))
+        delta = float(rng.choice([0.0, 1e-8, 1e-4, 1e-1]))
+        insts.append(wl.make_instance(n, m, N, delta, (57, n * 10 + m, i), indefinite=bool(rng.random() < 0.2)))
+    res = run(rl, insts, mode)
+    for b, inst in enumerate(insts):
+        ref = oracle.seq(inst)
+        if ref["status"]:
+            assert res["status"][b] == rl.INST_SINGULAR
+            continue
+        ov, ofb, oin = oracle.certificate(inst, ref["dS"], ref["dG"])
+        assert res["verdict"][b] == int(ov), b
+        assert res["first_bad"][b] == ofb, b
+        if ov:
+            assert tuple(res["inertia"][b]) == oin, b
+        assert res["relres"][b] <= 1e-8, (b, res["relres"][b])
+        assert res["status"][b] == (rl.INST_OK if ov else rl.INST_NOT_PD), b
+        oracle_rel = oracle.rel_residual(inst, ref["x"], ref["u"], ref["y"])
+        if ov and oracle_rel < 1e-12:
+            compare(inst, res["sols"][b], ref, 1e-10 if mode == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "scan"])
+@pytest.mark.parametrize("uniform", [False, True])
+def test_factor_rhs_matches_factor_then_solve(rl, mode, uniform):
+    """rlqr_factor_rhs (the backward vector pass inside the factorization's
+    stage loop) gives the results of rlqr_factor + rlqr_solve: a ragged batch
+    mixing one-wavefront and multi-wavefront instances, and a uniform
+    quadrotor-shaped batch (fixed-shape kernels); both against the oracle."""
+    print(f"[gpu] factor_rhs mode={mode} uniform={uniform}", flush=True)
+    if uniform:
+        insts = [wl.make_instance(12, 4, N, d, (58, i, 0), indefinite=(i % 5 == 4))
+                 for i, (N, d) in enumerate([(0, 1e-8), (1, 1e-4), (9, 0.0), (40, 1e-8), (128, 1e-8),
+                                             (128, 1e-4), (77, 1e-1), (128, 1e-8), (3, 1.0), (64, 1e-6)])]
+    else:
+        insts = _random_batch(6, count=24) + [wl.make_instance(n, m, N, 1e-6, (59, n, N))
+                                              for n, m, N in [(20, 10, 9), (33, 5, 17), (24, 20, 0)]]
+    a = run(rl, insts, mode)
+    b = run(rl, insts, mode, fused=True)
+    for k in ("status", "verdict", "first_bad"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.all((b["relres"] <= 1e-8) | ~(a["relres"] <= 1e-8)), (a["relres"], b["relres"])
+    for i, inst in enumerate(insts):
+        if a["status"][i] == rl.INST_SINGULAR:
+            continue
+        ref = dict(zip(("x", "u", "y"), a["sols"][i]))
+        compare(inst, b["sols"][i], ref, 1e-12 if mode == "fp64" else 1e-8)
+        oref = oracle.seq(inst)
+        ov = oracle.certificate(inst, oref["dS"], oref["dG"])[0]
+        if ov and oracle.rel_residual(inst, oref["x"], oref["u"], oref["y"]) < 1e-12:
+            compare(inst, b["sols"][i], oref, 1e-10 if mode == "fp64" else 1e-7)
 
 
 def test_fp64_unrefined_is_accurate(rl):
