@@ -103,6 +103,9 @@ struct rlqr_handle {
   rlqr_lhs lhs{};
   bool factored = false;
   bool pk_fused = false;  // pk holds the backward vector pass for pk_rhs (rlqr_factor_rhs)
+  int32_t* resfuse = nullptr;        // [B] residual computed by the one-wavefront solve (n + m <= 16, one segment)
+  ResChunk* chunks_nf = nullptr;     // residual chunks of the other instances
+  int64_t nchunks_nf = 0;
   rlqr_rhs pk_rhs{};
   std::vector<void*> allocs;
 };
@@ -251,11 +254,18 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     h->shape16 = (sn > 0 && same) ? fixed_shape(sn, sm) : SHAPE_ANY;
     h->shape_all = (B > 0 && (int)lists[TILE_16].size() == B) ? h->shape16 : SHAPE_ANY;
   }
-  std::vector<ResChunk> chunks;
-  for (int b = 0; b < B; ++b)
-    for (int i0 = 0; i0 <= h->N[b]; i0 += RES_CHUNK)
-      chunks.push_back(ResChunk{b, i0, std::min(i0 + RES_CHUNK, h->N[b] + 1), 0});
+  std::vector<ResChunk> chunks, chunks_nf;
+  std::vector<int32_t> resfuse(B, 0);
+  for (int b = 0; b < B; ++b) {
+    resfuse[b] = (cls[b] == TILE_16 && nseg[b] == 1) ? 1 : 0;
+    for (int i0 = 0; i0 <= h->N[b]; i0 += RES_CHUNK) {
+      const ResChunk ch{b, i0, std::min(i0 + RES_CHUNK, h->N[b] + 1), 0};
+      chunks.push_back(ch);
+      if (!resfuse[b]) chunks_nf.push_back(ch);
+    }
+  }
   h->nchunks = (int64_t)chunks.size();
+  h->nchunks_nf = (int64_t)chunks_nf.size();
 
   // scan groups: instances with two or more segments, by element tile size
   std::vector<int32_t> g_insts[3];
@@ -285,6 +295,8 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   };
   A((void**)&h->meta, sizeof(InstMeta) * (size_t)B);
   A((void**)&h->chunks, sizeof(ResChunk) * std::max<size_t>(chunks.size(), 1));
+  A((void**)&h->chunks_nf, sizeof(ResChunk) * std::max<size_t>(chunks_nf.size(), 1));
+  A((void**)&h->resfuse, sizeof(int32_t) * std::max<size_t>((size_t)B, 1));
   A(&h->ws64, sizeof(double) * (size_t)ws_elems);
   if (mode != RLQR_SEQ_FP64) A(&h->ws32, sizeof(float) * (size_t)ws_elems);
   A((void**)&h->pk, sizeof(double) * (size_t)pk_elems);
@@ -372,7 +384,8 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     }
   }
   if (st == RLQR_OK && B > 0) {
-    bool ok = upload(h->meta, meta) && upload(h->chunks, chunks) && upload(h->whole_off, whole_off);
+    bool ok = upload(h->meta, meta) && upload(h->chunks, chunks) && upload(h->whole_off, whole_off) &&
+              upload(h->chunks_nf, chunks_nf) && upload(h->resfuse, resfuse);
     for (int c = 0; c < TILE_CLASSES && ok; ++c) {
       if (h->count[c] > 0) ok = upload(h->list[c], lists[c]) && upload(h->whole[c].d, whole_d[c]);
       if (ok && scan && h->fseg[c].count > 0) ok = upload(h->fseg[c].d, fseg_d[c]);
@@ -562,12 +575,15 @@ static CheckArgs check_args(rlqr_handle* h, int final_pass, double tol, const in
 // Whole-instance solves, one launch per tile class; run masks select instances.
 // skip (scan mode) leaves the multi-segment instances to the segment solve.
 static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
-                               const double* corr, hipStream_t st, bool fwd_only = false) {
+                               const double* corr, hipStream_t st, bool fwd_only = false, double* res_out = nullptr) {
   for (int c = 0; c < TILE_CLASSES; ++c) {
     if (h->count[c] == 0) continue;
     SolveArgs a = solve_args(h, rhs, out, fp32, run, corr);
     a.list = h->list[c];
     a.fwd_only = (fwd_only && c == TILE_16) ? 1 : 0;
+    if (res_out && c == TILE_16) {
+      a.res = res_out; a.resmax = h->resmax; a.bmax = h->bmax; a.resfuse = h->resfuse;
+    }
     hipError_t e = (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, st)
                                   : launch_solve_mw(c, a, h->count[c], fp32, st);
     if (e != hipSuccess) return RLQR_E_HIP;
@@ -623,14 +639,17 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
       MaskArgs m{};
       m.batch = h->B; m.kind = 4; m.run32 = h->run32; m.multi = h->multi; m.run1 = h->run1;
       RLQR_TRY(launch_masks(m, st));
-      if ((s = solve_whole(h, rhs, out, true, h->run1, corr, st)) != RLQR_OK) return s;
+      if ((s = solve_whole(h, rhs, out, true, h->run1, corr, st, false, res_out)) != RLQR_OK) return s;
       if ((s = solve_segments(h, rhs, out, r32, corr, st)) != RLQR_OK) return s;
-    } else if ((s = solve_whole(h, rhs, out, true, r32, corr, st, fwd_only)) != RLQR_OK) {
+    } else if ((s = solve_whole(h, rhs, out, true, r32, corr, st, fwd_only, res_out)) != RLQR_OK) {
       return s;
     }
   }
-  if ((s = solve_whole(h, rhs, out, false, r64, corr, st, fwd_only)) != RLQR_OK) return s;
+  if ((s = solve_whole(h, rhs, out, false, r64, corr, st, fwd_only, res_out)) != RLQR_OK) return s;
+  // the one-wavefront solves wrote their instances' residuals; the others here
   ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
+  ra.chunks = h->chunks_nf;
+  ra.nchunks = h->nchunks_nf;
   RLQR_TRY(launch_residual(ra, h->shape_all, st));
   RLQR_TRY(launch_check(check_args(h, 0, tol, rres), st));
   return RLQR_OK;

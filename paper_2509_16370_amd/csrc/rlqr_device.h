@@ -202,6 +202,15 @@ __device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane
   if (j1 > j0) ps.minrel = fmin(ps.minrel, dmin / scale);
 }
 
+// X[J][J] of a register tile (wave-uniform)
+template <typename TL, int J>
+__device__ __forceinline__ double tile_diag(const double (&X)[4]) {
+  constexpr bool F32 = trow<TL>(1, 0) == 4;
+  constexpr int GJ = F32 ? (J >> 2) : (J & 3);
+  constexpr int VJ = F32 ? (J & 3) : (J >> 2);
+  return lane_value(X[VJ], 16 * GJ + J);
+}
+
 // Block numbering of a stage tile Z (NZ = 16 TZ) in the multi-wavefront
 // kernels: the TX x TX state blocks first (row-major, numbered like the blocks
 // of the state tiles), then the (x, u) blocks, then the u block-rows.

@@ -122,6 +122,12 @@ struct SolveArgs {
   double *x, *u, *y;
   double* pk;               // p_i / k_i scratch
   int fwd_only;             // whole-instance one-wavefront solves: p_i / k_i already in pk (fused factor)
+  // whole-instance one-wavefront solves: the forward rollout also writes the
+  // float64 residual of the updated solution (layout of k_residual) for the
+  // instances with resfuse[b] != 0, and their maxima to resmax / bmax
+  double* res;
+  unsigned long long *resmax, *bmax;
+  const int32_t* resfuse;
 };
 hipError_t launch_seg_solve(int cls, const SolveArgs& a, int nblocks, hipStream_t st);
 

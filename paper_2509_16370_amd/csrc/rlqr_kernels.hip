@@ -107,14 +107,14 @@ __device__ __forceinline__ void load_hess(double (&o)[4], const double* __restri
 // max |diag| over pivots lo..hi-1 of a register tile (wave-uniform result).
 template <typename TL>
 __device__ __forceinline__ double diag_scale(const double (&X)[4], int lo, int hi, int lane) {
-  const int c = lane & 15, grp = lane >> 4;
+  (void)lane;
   double s = 0.0;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int r = trow<TL>(grp, v);
-    if (r == c && r >= lo && r < hi) s = fmax(s, fabs(X[v]));
-  }
-  return wave_max_rows(s);
+#define RLQR_DIAG(J) \
+  if (J >= lo && J < hi) s = fmax(s, fabs(tile_diag<TL, J>(X)));
+  RLQR_DIAG(0) RLQR_DIAG(1) RLQR_DIAG(2) RLQR_DIAG(3) RLQR_DIAG(4) RLQR_DIAG(5) RLQR_DIAG(6) RLQR_DIAG(7)
+  RLQR_DIAG(8) RLQR_DIAG(9) RLQR_DIAG(10) RLQR_DIAG(11) RLQR_DIAG(12) RLQR_DIAG(13) RLQR_DIAG(14) RLQR_DIAG(15)
+#undef RLQR_DIAG
+  return s;
 }
 
 // ------------------------------------------------------------------ tile-vector helpers
@@ -555,7 +555,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
   __syncthreads();  // p/k written by lanes 0..15 are read by all lanes below
 
-  // ---- forward rollout (k = 0 .. N-1), one step of lookahead
+  // ---- forward rollout (k = 0 .. N-1) with the float64 residual of the
+  // updated solution (Section "Residual Computation") when res is set.
+  // Per step the stage blocks Q, M, R, A, B of step k+1 are copied to LDS
+  // while step k runs (two staging buffers); the tiles and vectors of step
+  // k+1 are loaded into registers one step ahead. The chain of a step is
+  // w = [A_k B_k] z_k -> x_{k+1} -> Z_{k+1} x_{k+1} (which already gives u_{k+1}
+  // and y_{k+1}); the residual rows of stage k hang off it:
+  //   x rows: Q x + M u + A^T y_{k+1} + q - y_k,  u rows: M^T x + R u + B^T y_{k+1} + r,
+  //   dynamics: A x + B u + c_{k+1} - delta y_{k+1} - x_{k+1}   (totals, original rhs)
+  // plus the initial row c_0 - delta y_0 - x_0 and the terminal row
+  // Q_N x_N + q_N - y_N. The instance's maxima go to resmax / bmax directly
+  // (one wavefront per instance).
+  const bool fuse = a.res != nullptr && a.resfuse != nullptr && a.resfuse[b] != 0;
+  double* __restrict__ resg = fuse ? a.res + mt.ores : nullptr;
+  const double* __restrict__ qo = a.q + mt.oq;
+  const double* __restrict__ ro = a.r + mt.or_;
+  const double* __restrict__ co = a.c + mt.oc;
+  __shared__ __align__(16) double stgA[STG_MAX];
+  __shared__ __align__(16) double stgB[STG_MAX];
+  __shared__ double sz[2][16];  // z_k totals (x | u) and y_{k+1} totals
+  int iH[4], iAB[4], iABT[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = 4 * grp + v;
+    iH[v] = stg_hess(j, col, n, m);
+    iAB[v] = stg_ab(j, col, n, m);
+    iABT[v] = stg_ab(col, j, n, m);
+  }
+  const int oZ = 2 * n * n + 2 * n * m + m * m;
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  wave_sync();
+  if (lane == 0) {
+    stgA[oZ] = 0.0;
+    stgB[oZ] = 0.0;
+  }
+  if (N > 0)
+    dma_stage(stgA, a.Q + mt.oQ, a.M + mt.oM, a.R + mt.oR, Ag, Bg, n, m, lane);
+  double rmax = 0.0, bmax = 0.0;
+
+  // x_0, then z_0 = Z_0 x_0 (u_0 and y_0)
   double x;
   {
     double X0[4];
@@ -567,79 +606,170 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     wave_sync();
     x = xr ? -tmatvec<TG>(X0, sv[0], lane) : 0.0;
   }
-  double abt[4];
   tile_load(Zk, ws, lane);
-  tile_load(Xn, ws + (int64_t)(2 * (N > 0 ? 1 : 0) + 1) * 256, lane);
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    abt[v] = N > 0 ? ab_elem(Ag, Bg, n, m, col, trow<TG>(grp, v)) : 0.0;  // [A B][col][j]
-  // step k's vectors, loaded one step ahead like the tiles
-  double pk = 0.0, kk = 0.0, pn = 0.0, cn = 0.0, xold = 0.0, yold = 0.0, uold = 0.0;
-  if (N > 0) {
-    pk = ld_or0(pg, col, xr);
-    kk = ld_or0(kg, col - n, ur);
-    pn = ld_or0(pg, (int64_t)n + col, xr);
-    cn = ld_or0(cb, (int64_t)n + col, xr);
-    if (acc) {
-      xold = ld_or0(xg, col, xr);
-      yold = ld_or0(yg, col, xr);
-      uold = ld_or0(ug, col - n, ur);
-    }
-  }
-  for (int k = 0; k < N; ++k) {
-    double Zk1[4], Xn1[4], abt1[4];
-    const int k1 = k + 1 < N ? k + 1 : k;
-    tile_load(Zk1, ws + (int64_t)(2 * (k + 1)) * 256, lane);  // tile 2N exists (P_N)
-    tile_load(Xn1, ws + (int64_t)(2 * (k1 + 1) + 1) * 256, lane);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      abt1[v] = ab_elem(Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, col, trow<TG>(grp, v));
-    const double pk1 = ld_or0(pg, (int64_t)k1 * n + col, xr);
-    const double kk1 = ld_or0(kg, (int64_t)k1 * m + (col - n), ur);
-    const double pn1 = ld_or0(pg, (int64_t)(k1 + 1) * n + col, xr);
-    const double cn1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
-    const double xold1 = acc ? ld_or0(xg, (int64_t)k1 * n + col, xr) : 0.0;
-    const double yold1 = acc ? ld_or0(yg, (int64_t)k1 * n + col, xr) : 0.0;
-    const double uold1 = acc ? ld_or0(ug, (int64_t)k1 * m + (col - n), ur) : 0.0;
+  double zx;  // Z_k x_k: [P_k x_k; -K_k x_k]
+  {
     wave_sync();
     if (own) sv[0][col] = xr ? x : 0.0;
     wave_sync();
-    const double zx = tmatvec<TG>(Zk, sv[0], lane);   // [P_k x; -K_k x]
+    zx = tmatvec<TG>(Zk, sv[0], lane);
+  }
+  // step k's vectors (loaded one step ahead)
+  double pk = ld_or0(pg, col, xr);
+  double kk = N > 0 ? ld_or0(kg, col - n, ur) : 0.0;
+  double xold = acc ? ld_or0(xg, col, xr) : 0.0;
+  double yold = acc ? ld_or0(yg, col, xr) : 0.0;
+  double uold = (acc && N > 0) ? ld_or0(ug, col - n, ur) : 0.0;
+  {
+    // initial row c_0 - delta y_0 - x_0 (totals, original c_0)
+    const double c0 = ld_or0(co, col, xr);
+    const double xt = x + xold, yt = zx + pk + yold;
+    if (fuse && own && xr) {
+      const double r0 = c0 - delta * yt - xt;
+      resg[(int64_t)N * (n + m) + n + col] = r0;
+      rmax = fmax(rmax, fabs(r0));
+      bmax = fmax(bmax, fabs(c0));
+    }
+  }
+  if (N > 0) tile_load(Xn, ws + (int64_t)3 * 256, lane);
+  double pn = N > 0 ? ld_or0(pg, (int64_t)n + col, xr) : 0.0;
+  double cn = N > 0 ? ld_or0(cb, (int64_t)n + col, xr) : 0.0;
+  double xoldn = (acc && N > 0) ? ld_or0(xg, (int64_t)n + col, xr) : 0.0;
+  double yoldn = (acc && N > 0) ? ld_or0(yg, (int64_t)n + col, xr) : 0.0;
+  double qok = N > 0 ? ld_or0(qo, col, xr) : 0.0;
+  double rok = N > 0 ? ld_or0(ro, col - n, ur) : 0.0;
+  double con = N > 0 ? ld_or0(co, (int64_t)n + col, xr) : 0.0;
+
+  for (int k = 0; k < N; ++k) {
+    double* stgc = (k & 1) ? stgB : stgA;
+    double* stgn = (k & 1) ? stgA : stgB;
+    wait_vmem();  // step k's blocks, tiles and vectors have landed
+    wave_sync();
+    const bool more = k + 1 < N;
+    if (more) {
+      const int k1 = k + 1;
+      dma_stage(stgn, a.Q + mt.oQ + (int64_t)k1 * n * n, a.M + mt.oM + (int64_t)k1 * n * m,
+                a.R + mt.oR + (int64_t)k1 * m * m, Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, lane);
+    }
+    // step k+1's tiles and vectors
+    double Zk1[4], Xn1[4];
+    const int k1 = more ? k + 1 : k;
+    tile_load(Zk1, ws + (int64_t)(2 * (k + 1)) * 256, lane);  // tile 2N exists (P_N)
+    tile_load(Xn1, ws + (int64_t)(2 * (k1 + 1) + 1) * 256, lane);
+    const double kk1 = ld_or0(kg, (int64_t)k1 * m + (col - n), ur);
+    const double uold1 = acc ? ld_or0(ug, (int64_t)k1 * m + (col - n), ur) : 0.0;
+    const double pn1 = ld_or0(pg, (int64_t)(k1 + 1) * n + col, xr);
+    const double cn1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
+    const double xoldn1 = acc ? ld_or0(xg, (int64_t)(k1 + 1) * n + col, xr) : 0.0;
+    const double yoldn1 = acc ? ld_or0(yg, (int64_t)(k1 + 1) * n + col, xr) : 0.0;
+    const double qok1 = ld_or0(qo, (int64_t)k1 * n + col, xr);
+    const double rok1 = ld_or0(ro, (int64_t)k1 * m + (col - n), ur);
+    const double con1 = ld_or0(co, (int64_t)(k1 + 1) * n + col, xr);
+
+    // u_k, y_k from z_k; write the totals
     const double uk = ur ? kk - zx : 0.0;
+    const double xt = x + xold, ut = uk + uold, yt = zx + pk + yold;
     if (own) {
       if (xr) {
-        yg[(int64_t)k * n + col] = zx + pk + yold;
-        xg[(int64_t)k * n + col] = x + xold;
+        yg[(int64_t)k * n + col] = yt;
+        xg[(int64_t)k * n + col] = xt;
       }
-      if (ur) ug[(int64_t)k * m + (col - n)] = uk + uold;
+      if (ur) ug[(int64_t)k * m + (col - n)] = ut;
       sv[1][col] = xr ? x : (ur ? uk : 0.0);
+      sz[0][col] = xr ? xt : (ur ? ut : 0.0);
     }
     wave_sync();
-    const double w = tmatvec<TG>(abt, sv[1], lane);   // A x + B u
+    // w = A x + B u of this pass's z (the chain) and of the totals (residual)
+    double w = 0.0, wt = 0.0, hz = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 4 * grp + v;
+      const double abt = stgc[iABT[v]];
+      w += abt * sv[1][j];
+      wt += abt * sz[0][j];
+      hz += stgc[iH[v]] * sz[0][j];
+    }
+    w = group_sum(w);
     if (own) sv[0][col] = xr ? w + cn - delta * pn : 0.0;
     wave_sync();
-    x = xr ? -tmatvec<TG>(Xn, sv[0], lane) : 0.0;
+    x = xr ? -tmatvec<TG>(Xn, sv[0], lane) : 0.0;  // x_{k+1} of this pass
+    wave_sync();
+    if (own) sv[1][col] = xr ? x : 0.0;
+    wave_sync();
+    zx = tmatvec<TG>(Zk1, sv[1], lane);           // Z_{k+1} x_{k+1}
+    if (fuse) {
+      wt = group_sum(wt);
+      hz = group_sum(hz);
+      const double x1t = x + xoldn, y1t = zx + pn + yoldn;
+      if (own) sz[1][col] = xr ? y1t : 0.0;
+      wave_sync();
+      double g = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) g += stgc[iAB[v]] * sz[1][4 * grp + v];
+      g = group_sum(g);
+      if (own) {
+        const int64_t base = (int64_t)k * (n + m);
+        if (xr) {
+          const double rx = hz + g + qok - yt;
+          const double rd = wt + con - delta * y1t - x1t;
+          resg[base + col] = rx;
+          resg[(int64_t)N * (n + m) + n + (int64_t)(k + 1) * n + col] = rd;
+          rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
+          bmax = fmax(bmax, fmax(fabs(qok), fabs(con)));
+        }
+        if (ur) {
+          const double ru = hz + g + rok;
+          resg[base + col] = ru;
+          rmax = fmax(rmax, fabs(ru));
+          bmax = fmax(bmax, fabs(rok));
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of this step's staging buffer returned before it is refilled
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       Zk[v] = Zk1[v];
       Xn[v] = Xn1[v];
-      abt[v] = abt1[v];
     }
-    pk = pk1; kk = kk1; pn = pn1; cn = cn1;
-    xold = xold1; yold = yold1; uold = uold1;
+    pk = pn; kk = kk1; pn = pn1; cn = cn1;
+    xold = xoldn; yold = yoldn; uold = uold1; xoldn = xoldn1; yoldn = yoldn1;
+    qok = qok1; rok = rok1; con = con1;
   }
   {
-    // y_N = P_N x_N + p_N  (Zk now holds tile 2N)
-    const double pN = ld_or0(pg, (int64_t)N * n + col, xr);
-    const double xold = acc ? ld_or0(xg, (int64_t)N * n + col, xr) : 0.0;
-    const double yold = acc ? ld_or0(yg, (int64_t)N * n + col, xr) : 0.0;
-    wave_sync();
-    if (own) sv[0][col] = xr ? x : 0.0;
-    wave_sync();
-    const double yN = tmatvec<TG>(Zk, sv[0], lane) + pN;
+    // x_N, y_N (zx holds P_N x_N) and the terminal row Q_N x_N + q_N - y_N
+    const double xt = x + xold, yt = zx + pk + yold;
     if (own && xr) {
-      yg[(int64_t)N * n + col] = yN + yold;
-      xg[(int64_t)N * n + col] = x + xold;
+      yg[(int64_t)N * n + col] = yt;
+      xg[(int64_t)N * n + col] = xt;
+    }
+    if (fuse) {
+      const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
+      double Hq[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 4 * grp + v;
+        Hq[v] = ld_or0(QN, j * n + col, j < n && xr);
+      }
+      const double qN = ld_or0(qo, (int64_t)N * n + col, xr);
+      wave_sync();
+      if (own) sz[0][col] = xr ? xt : 0.0;
+      wave_sync();
+      double h = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) h += Hq[v] * sz[0][4 * grp + v];
+      h = group_sum(h);
+      if (own && xr) {
+        const double rt = h + qN - yt;
+        resg[(int64_t)N * (n + m) + col] = rt;
+        rmax = fmax(rmax, fabs(rt));
+        bmax = fmax(bmax, fabs(qN));
+      }
+      rmax = wave_max(rmax);
+      bmax = wave_max(bmax);
+      if (lane == 0) {
+        a.resmax[b] = (unsigned long long)__double_as_longlong(rmax);
+        a.bmax[b] = (unsigned long long)__double_as_longlong(bmax);
+      }
     }
   }
 }

@@ -187,6 +187,10 @@ def test_factor_rhs_matches_factor_then_solve(rl, mode, uniform):
             continue
         ref = dict(zip(("x", "u", "y"), a["sols"][i]))
         compare(inst, b["sols"][i], ref, 1e-12 if mode == "fp64" else 1e-8)
+        # the reported residual is that of the returned solution (float64 residual
+        # of the oracle on the same z, up to the rounding of the residual itself)
+        orel = oracle.rel_residual(inst, *b["sols"][i])
+        assert abs(b["relres"][i] - orel) <= 1e-3 * orel + 2e-15, (i, b["relres"][i], orel)
         oref = oracle.seq(inst)
         ov = oracle.certificate(inst, oref["dS"], oref["dG"])[0]
         if ov and oracle.rel_residual(inst, oref["x"], oref["u"], oref["y"]) < 1e-12:
