@@ -460,7 +460,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // correction with right-hand side corr (the previous residual) and add it to
 // z. The tiles and stage blocks of the next step are loaded one step ahead
 // so that the dependent chain does not wait on memory.
-template <typename TG, int SN, int SM>
+// ACC: correction pass (right-hand side = a.corr, z += dz); otherwise a.corr is NULL
+template <typename TG, int SN, int SM, bool ACC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_solve16(SolveArgs a) {
   const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   double* __restrict__ kg = a.pk + mt.opk + (int64_t)(N + 1) * n;  // k_i at i*m
   const double *qb, *rb, *cb;
   int64_t qs, rs;
-  const bool acc = a.corr != nullptr;
+  constexpr bool acc = ACC;
   if (acc) {
     const double* res = a.corr + mt.ores;
     qb = res; qs = n + m;
@@ -575,13 +576,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   __shared__ __align__(16) double stgA[STG_MAX];
   __shared__ __align__(16) double stgB[STG_MAX];
   __shared__ double sz[2][16];  // z_k totals (x | u) and y_{k+1} totals
-  int iH[4], iAB[4], iABT[4];
+  // staging indices of the lane's Hessian, [A B] and [A B]^T elements, packed
+  // 10 bits each (STG_MAX < 1024) to keep them in one register per element
+  int ipk[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int j = 4 * grp + v;
-    iH[v] = stg_hess(j, col, n, m);
-    iAB[v] = stg_ab(j, col, n, m);
-    iABT[v] = stg_ab(col, j, n, m);
+    ipk[v] = stg_hess(j, col, n, m) | (stg_ab(j, col, n, m) << 10) | (stg_ab(col, j, n, m) << 20);
   }
   const int oZ = 2 * n * n + 2 * n * m + m * m;
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
@@ -684,10 +685,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int j = 4 * grp + v;
-      const double abt = stgc[iABT[v]];
+      const double abt = stgc[ipk[v] >> 20];
       w += abt * sv[1][j];
       wt += abt * sz[0][j];
-      hz += stgc[iH[v]] * sz[0][j];
+      hz += stgc[ipk[v] & 1023] * sz[0][j];
     }
     w = group_sum(w);
     if (own) sv[0][col] = xr ? w + cn - delta * pn : 0.0;
@@ -705,7 +706,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       wave_sync();
       double g = 0.0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) g += stgc[iAB[v]] * sz[1][4 * grp + v];
+      for (int v = 0; v < 4; ++v) g += stgc[(ipk[v] >> 10) & 1023] * sz[1][4 * grp + v];
       g = group_sum(g);
       if (own) {
         const int64_t base = (int64_t)k * (n + m);
@@ -1192,7 +1193,10 @@ hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, i
 
 template <typename TG, int SN, int SM>
 static hipError_t launch_solve_t(const SolveArgs& a, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_solve16<TG, SN, SM>), dim3(nblocks), dim3(64), 0, st, a);
+  if (a.corr)
+    hipLaunchKernelGGL((k_solve16<TG, SN, SM, true>), dim3(nblocks), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_solve16<TG, SN, SM, false>), dim3(nblocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 template <typename TG>
