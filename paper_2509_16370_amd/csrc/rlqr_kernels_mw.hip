@@ -84,12 +84,16 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   auto xtile = [&](int i) { return ws + (int64_t)i * STAGE + (int64_t)TZ * TZ * 256; };
 
   __shared__ __align__(16) unsigned char smem[C::BYTES_U + C::BYTES_AB];
-  __shared__ double colbuf[2 * NZ];
   __shared__ double red[NW];
   TG* sP = reinterpret_cast<TG*>(smem);
   TG* sX = reinterpret_cast<TG*>(smem + C::BYTES_P);
   double* sD = reinterpret_cast<double*>(smem);
   TG* sAB = reinterpret_cast<TG*>(smem + C::BYTES_U);
+  // the blocked sweeps' panel and pivot block overlay the work region, which
+  // is free while a sweep runs
+  double* panel = reinterpret_cast<double*>(smem);
+  double* mbuf = panel + NZ * 17;
+  static_assert((NZ * 17 + 16 * 17) * 8 <= C::BYTES_U, "sweep panel exceeds the work region");
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   int xi[CX], xj[CX], zi[CZ], zj[CZ], ti[CT], tj[CT];
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       }
     {
       const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
-      sweep_mw<TG, CX, TX>(X, xi, xj, xo, 0, n, lane, colbuf, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
+      sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
     }
     {
       TG* xt = xtile(k + 1);
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       }
     {
       const double sc = wg_max<NW>(diag_max<CZ, TG>(Z, zi, zj, zo, n, n + m, lane), red, w, lane);
-      sweep_mw<TG, CZ, TZ>(Z, zi, zj, zo, n, n + m, lane, colbuf, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
+      sweep_blk<TG, CZ, TZ>(Z, zi, zj, zo, n, n + m, w, lane, panel, mbuf, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
     }
     {
       TG* zt = ztile(k);
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + delta * P[t][v];
       }
     const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
-    sweep_mw<TG, CX, TX>(X, xi, xj, xo, 0, n, lane, colbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
+    sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
     TG* xt = xtile(0);
 #pragma unroll
     for (int t = 0; t < CX; ++t)
