@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--nx", type=int, default=12, help="batched_uniform: state size")
     ap.add_argument("--nu", type=int, default=4, help="batched_uniform: control size")
     ap.add_argument("--horizon", type=int, default=128, help="batched_uniform: N")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="scan modes: stages per segment L (0: the library's default)")
     ap.add_argument("--delta", type=float, default=1e-8)
     ap.add_argument("--max-refine", type=int, default=3)
     ap.add_argument("--modes", default=None)
@@ -242,11 +244,12 @@ def main():
         if mode == "tuned":
             from paper_2509_16370_amd import tune
             t1 = time.perf_counter()
-            plan = tune.tune_batch(packed, lhs, rhs, rel_tol=rel_tol, max_refine=max_refine, reps=2)
+            plan = tune.tune_batch(packed, lhs, rhs, rel_tol=rel_tol, max_refine=max_refine, reps=2,
+                                   log=lambda msg: print(msg, file=sys.stderr, flush=True))
             print(f"[bench] tuned {len(plan)} buckets in {time.perf_counter() - t1:.1f}s: "
                   + ", ".join(f"{k}: {c.key()}" for k, c in plan.items()), file=sys.stderr, flush=True)
         results[mode] = run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_tol=rel_tol,
-                                 plan=plan)
+                                 chunk=args.chunk, plan=plan)
         if plan is not None:
             results[mode]["plan"] = {f"{k[0]},{k[1]}": c.key() for k, c in plan.items()}
         print(f"[bench] {mode}: {json.dumps(results[mode])}", file=sys.stderr, flush=True)

@@ -258,8 +258,10 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   std::vector<int32_t> resfuse(B, 0);
   for (int b = 0; b < B; ++b) {
     resfuse[b] = (cls[b] == TILE_16 && nseg[b] == 1) ? 1 : 0;
-    for (int i0 = 0; i0 <= h->N[b]; i0 += RES_CHUNK) {
-      const ResChunk ch{b, i0, std::min(i0 + RES_CHUNK, h->N[b] + 1), 0};
+    // stages with n + m > 16 take one lane per residual row: smaller chunks, more wavefronts
+    const int len = cls[b] == TILE_16 ? RES_CHUNK : 2;
+    for (int i0 = 0; i0 <= h->N[b]; i0 += len) {
+      const ResChunk ch{b, i0, std::min(i0 + len, h->N[b] + 1), 0};
       chunks.push_back(ch);
       if (!resfuse[b]) chunks_nf.push_back(ch);
     }

@@ -783,14 +783,14 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
 }
 
 // Residual of Section "Residual Computation", float64, parallel over
-// (instance, chunk of stages): one wavefront walks RES_CHUNK consecutive
-// stage slots i of one instance (slot N carries the terminal row and the c_0
-// row) and keeps the instance's maxima in registers, so each chunk issues one
-// pair of 64-bit atomic max operations (order-independent). For n + m <= 16 a
-// slot is three tile-vector products on register tiles (Hessian
-// [[Q, M], [M^T, R]], [A B] and its transpose), with the operands of the next
-// slot loaded while the current one is reduced; larger stages use one lane
-// per row.
+// (instance, chunk of stages): one wavefront walks a chunk of consecutive
+// stage slots i of one instance (RES_CHUNK slots for n + m <= 16, two for
+// larger stages; slot N carries the terminal row and the c_0 row) and keeps
+// the instance's maxima in registers, so each chunk issues one pair of 64-bit
+// atomic max operations (order-independent). For n + m <= 16 a slot is three
+// tile-vector products on staged blocks (Hessian [[Q, M], [M^T, R]], [A B] and
+// its transpose), with the blocks of the next slot copied to LDS while the
+// current one is reduced; larger stages use one lane per row.
 struct ResVec {
   double xi, ui, yi, yn, xn, qi, ri, cn;
 };
@@ -924,7 +924,7 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
       int64_t out;
       if (row < n) {
         const int a0 = row;
-        for (int j = 0; j < n; ++j) s = fma(Q[a0 * n + j], xi[j], s);
+        for (int j = 0; j < n; ++j) s = fma(Q[j * n + a0], xi[j], s);  // Q symmetric: lanes read a row
         for (int j = 0; j < m; ++j) s = fma(M[a0 * m + j], ui[j], s);
         for (int j = 0; j < n; ++j) s = fma(A[j * n + a0], yn[j], s);
         bv = q[(int64_t)i * n + a0];
@@ -933,7 +933,7 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
       } else if (row < n + m) {
         const int a0 = row - n;
         for (int j = 0; j < n; ++j) s = fma(M[j * m + a0], xi[j], s);
-        for (int j = 0; j < m; ++j) s = fma(R[a0 * m + j], ui[j], s);
+        for (int j = 0; j < m; ++j) s = fma(R[j * m + a0], ui[j], s);  // R symmetric
         for (int j = 0; j < n; ++j) s = fma(B[j * m + a0], yn[j], s);
         bv = r[(int64_t)i * m + a0];
         s += bv;
@@ -957,7 +957,7 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
       double s = 0.0, bv;
       int64_t out;
       if (row < n) {
-        for (int j = 0; j < n; ++j) s = fma(QN[row * n + j], xN[j], s);
+        for (int j = 0; j < n; ++j) s = fma(QN[j * n + row], xN[j], s);
         bv = q[(int64_t)N * n + row];
         s += bv - y[(int64_t)N * n + row];
         out = (int64_t)N * (n + m) + row;

@@ -395,6 +395,7 @@ template <typename TG, int TX, int TZ, int NW, bool SEG>
 __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   using C = MwCfg<TG, TX, TZ, NW>;
   constexpr int NZ = C::NZ, CX = C::CX, CZ = C::CZ, CT = C::CT;
+  constexpr bool PF = NW <= 9;  // operands of the next step loaded one step ahead
   SegDesc sd{};
   if (SEG) sd = a.segs[blockIdx.x];
   const int b = SEG ? sd.inst : (a.list ? a.list[blockIdx.x] : (int)blockIdx.x);
@@ -501,14 +502,38 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     if (write_pk && xr && hi == N) pg[(int64_t)hi * n + tid] = p;
     double Zp[CZ][4];
     load_tile(Zp, ztile(hi), zo, CZ);
+    // step k's operands, loaded one step ahead
+    double Zk[CZ][4], Xn[CX][4], AB[CT][4];
+    double ck = 0.0, qk = 0.0, rk = 0.0;
+    if (PF && hi > lo) {
+      load_tile(Zk, ztile(hi - 1), zo, CZ);
+      load_tile(Xn, xtile(hi), xo, CX);
+      load_ab(AB, hi - 1, false);
+      ck = xr ? cb[(int64_t)hi * n + tid] : 0.0;
+      qk = xr ? qb[(int64_t)(hi - 1) * qs + tid] : 0.0;
+      rk = ur ? rb[(int64_t)(hi - 1) * rs + (tid - n)] : 0.0;
+    }
     for (int k = hi - 1; k >= lo; --k) {
-      double Zk[CZ][4], Xn[CX][4], AB[CT][4];
-      load_tile(Zk, ztile(k), zo, CZ);
-      load_tile(Xn, xtile(k + 1), xo, CX);
-      load_ab(AB, k, false);
-      const double ck = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
-      const double qk = xr ? qb[(int64_t)k * qs + tid] : 0.0;
-      const double rk = ur ? rb[(int64_t)k * rs + (tid - n)] : 0.0;
+      // PF: the next step's operands are loaded now; otherwise (the 16-wavefront
+      // classes, whose register budget the second set would exceed) this step's
+      const int k1 = k > lo ? k - 1 : k;
+      double Zk1[CZ][4], Xn1[CX][4], AB1[CT][4];
+      double ck1 = 0.0, qk1 = 0.0, rk1 = 0.0;
+      if constexpr (PF) {
+        load_tile(Zk1, ztile(k1), zo, CZ);
+        load_tile(Xn1, xtile(k1 + 1), xo, CX);
+        load_ab(AB1, k1, false);
+        ck1 = xr ? cb[(int64_t)(k1 + 1) * n + tid] : 0.0;
+        qk1 = xr ? qb[(int64_t)k1 * qs + tid] : 0.0;
+        rk1 = ur ? rb[(int64_t)k1 * rs + (tid - n)] : 0.0;
+      } else {
+        load_tile(Zk, ztile(k), zo, CZ);
+        load_tile(Xn, xtile(k + 1), xo, CX);
+        load_ab(AB, k, false);
+        ck = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+        qk = xr ? qb[(int64_t)k * qs + tid] : 0.0;
+        rk = ur ? rb[(int64_t)k * rs + (tid - n)] : 0.0;
+      }
       __syncthreads();
       if (tid < NZ) s0[tid] = xr ? ck : 0.0;
       __syncthreads();
@@ -532,6 +557,21 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       for (int t = 0; t < CZ; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) Zp[t][v] = Zk[t][v];
+      if constexpr (PF) {
+#pragma unroll
+        for (int t = 0; t < CZ; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Zk[t][v] = Zk1[t][v];
+#pragma unroll
+        for (int t = 0; t < CX; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Xn[t][v] = Xn1[t][v];
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) AB[t][v] = AB1[t][v];
+        ck = ck1; qk = qk1; rk = rk1;
+      }
     }
     if (SEG && phase == 1 && xr) a.plo[mt.ovec + (int64_t)sd.s * n + tid] = p;
     __syncthreads();
@@ -553,18 +593,45 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   } else {
     x = xr ? a.xhi[mt.ovec + (int64_t)(sd.s - 1) * n + tid] : 0.0;
   }
-  for (int k = lo; k < hi; ++k) {
-    double Zk[CZ][4], Xn[CX][4], ABt[CT][4];
-    load_tile(Zk, ztile(k), zo, CZ);
-    load_tile(Xn, xtile(k + 1), xo, CX);
-    load_ab(ABt, k, true);
-    const double pk = xr ? pg[(int64_t)k * n + tid] : 0.0;
-    const double kk = ur ? kg[(int64_t)k * m + (tid - n)] : 0.0;
-    // p_{k+1}; at a segment end (k + 1 == hi < N) the boundary value of the chain
+  // p_{k+1}; at a segment end (k + 1 == hi < N) the boundary value of the chain
+  auto pnext = [&](int k) {
     const bool pbound = SEG && k + 1 == hi && hi < N;
     const double* pnp = pbound ? a.plo + mt.ovec + (int64_t)(sd.s + 1) * n : pg + (int64_t)(k + 1) * n;
-    const double pn = xr ? pnp[tid] : 0.0;
-    const double cn = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+    return xr ? pnp[tid] : 0.0;
+  };
+  // step k's operands, loaded one step ahead
+  double Zk[CZ][4], Xn[CX][4], ABt[CT][4];
+  double pk = 0.0, kk = 0.0, pn = 0.0, cn = 0.0;
+  if (PF && hi > lo) {
+    load_tile(Zk, ztile(lo), zo, CZ);
+    load_tile(Xn, xtile(lo + 1), xo, CX);
+    load_ab(ABt, lo, true);
+    pk = xr ? pg[(int64_t)lo * n + tid] : 0.0;
+    kk = ur ? kg[(int64_t)lo * m + (tid - n)] : 0.0;
+    pn = pnext(lo);
+    cn = xr ? cb[(int64_t)(lo + 1) * n + tid] : 0.0;
+  }
+  for (int k = lo; k < hi; ++k) {
+    const int k1 = k + 1 < hi ? k + 1 : k;
+    double Zk1[CZ][4], Xn1[CX][4], ABt1[CT][4];
+    double pk1 = 0.0, kk1 = 0.0, pn1 = 0.0, cn1 = 0.0;
+    if constexpr (PF) {
+      load_tile(Zk1, ztile(k1), zo, CZ);
+      load_tile(Xn1, xtile(k1 + 1), xo, CX);
+      load_ab(ABt1, k1, true);
+      pk1 = xr ? pg[(int64_t)k1 * n + tid] : 0.0;
+      kk1 = ur ? kg[(int64_t)k1 * m + (tid - n)] : 0.0;
+      pn1 = pnext(k1);
+      cn1 = xr ? cb[(int64_t)(k1 + 1) * n + tid] : 0.0;
+    } else {
+      load_tile(Zk, ztile(k), zo, CZ);
+      load_tile(Xn, xtile(k + 1), xo, CX);
+      load_ab(ABt, k, true);
+      pk = xr ? pg[(int64_t)k * n + tid] : 0.0;
+      kk = ur ? kg[(int64_t)k * m + (tid - n)] : 0.0;
+      pn = pnext(k);
+      cn = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+    }
     __syncthreads();
     if (tid < NZ) s0[tid] = xr ? x : 0.0;
     __syncthreads();
@@ -588,6 +655,21 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     __syncthreads();
     tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s0, s1, red, tid, lane);
     x = xr ? -s1[tid] : 0.0;
+    if constexpr (PF) {
+#pragma unroll
+      for (int t = 0; t < CZ; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Zk[t][v] = Zk1[t][v];
+#pragma unroll
+      for (int t = 0; t < CX; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xn[t][v] = Xn1[t][v];
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ABt[t][v] = ABt1[t][v];
+      pk = pk1; kk = kk1; pn = pn1; cn = cn1;
+    }
   }
   if (SEG && phase == 2) {
     if (xr) a.xhi[mt.ovec + (int64_t)sd.s * n + tid] = x;
