@@ -120,7 +120,7 @@ typedef struct { double *x, *u, *y; } rlqr_sol;
    bucket by bucket). */
 typedef struct {
   int32_t scan_chunk;          /* RLQR_SCAN_*: stages per segment L >= 1; 0 picks L
-                                  from the batch (about two segments per compute unit).
+                                  from the batch (about one segment per compute unit).
                                   An instance with N <= L is one segment and skips the
                                   scan. Ignored by the sequential modes. */
   const int32_t *inst_chunk;   /* [host][B] or NULL. RLQR_SCAN_*: per-instance L

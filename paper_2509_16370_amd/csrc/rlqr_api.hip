@@ -188,11 +188,13 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   h->m.assign(s->nu, s->nu + B);
   const bool scan = is_scan(mode);
 
-  // segment length: about two segments per compute unit over the whole batch
+  // segment length: about one segment per compute unit (256) over the whole
+  // batch, so the chunk folds and the segment recursions run in one round and
+  // the boundary chains stay short
   int64_t total_elems = 0;
   for (int b = 0; b < B; ++b) total_elems += h->N[b] + 1;
   const int L = tune && tune->scan_chunk > 0 ? tune->scan_chunk : (int)std::min<int64_t>(
-                                                                      std::max<int64_t>((total_elems + 511) / 512, 8), 1 << 20);
+                                                                      std::max<int64_t>((total_elems + 255) / 256, 8), 1 << 20);
   h->chunk = L;
   std::vector<int32_t> Lb(B, L), pref64(B, 0);
   if (tune && tune->inst_chunk)
