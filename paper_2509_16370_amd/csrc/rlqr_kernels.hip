@@ -141,12 +141,12 @@ __device__ __forceinline__ double tmatvec_r(const double (&X)[4], const double* 
 }
 
 // masked vector element load: v[i] if ok else 0. A masked-off lane reads the
-// zero below instead (an empty block may sit at the end of an array).
+// zero below instead (an empty block may sit at the end of an array); no
+// select follows the load, so the compiler waits for it only at its first use.
 __device__ double g_zero = 0.0;
 __device__ __forceinline__ double ld_or0(const double* __restrict__ v, int64_t i, bool ok) {
   const double* p = ok ? v + i : &g_zero;
-  const double x = *p;
-  return ok ? x : 0.0;
+  return *p;
 }
 
 // ------------------------------------------------------------------ factor
