@@ -111,6 +111,20 @@ __device__ __forceinline__ f4 cgemm_bt(const float* sa, int lda, const float* sb
   else return sgemm_blk_bt<KB>(sa, lda, sb, ldb, I, J, lane);
 }
 
+// max over the 64 lanes (every lane gets it): DPP row rotations, then the
+// four row maxima
+__device__ __forceinline__ float wave_max_f32(float x) {
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x121, 0xf, 0xf, false)));
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x122, 0xf, 0xf, false)));
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x124, 0xf, 0xf, false)));
+  x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x128, 0xf, 0xf, false)));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+  return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+}
+
 // accumulator element (v) of block (I, J): row 16 I + 4 grp + v, column 16 J + col
 __device__ __forceinline__ int arow(int I, int grp, int v) { return 16 * I + 4 * grp + v; }
 
@@ -186,15 +200,10 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
   for (int j = 0; j < n; ++j) {
     if (w == 0) {
       const float a = (lane < NX && lane >= j) ? fabsf(s.W[lane * LDW + j]) : -1.0f;
-      float best = a;
-      int bi = lane;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const float ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int p = bi;
+      // largest |candidate|, lowest row on ties: DPP maxima within 16-lane rows,
+      // the four row maxima by v_readlane, the row by a ballot
+      const float best = wave_max_f32(a);
+      const int p = __builtin_ctzll(__ballot(a == best));
       // swap rows j and p, then publish the scaled pivot row and column j
       for (int c = lane; c < 2 * NX; c += 64) {
         const float vj = s.W[j * LDW + c], vp = s.W[p * LDW + c];

@@ -115,6 +115,7 @@ def test_null_arguments_rejected():
     lib = rlqr._lib
     assert lib.rlqr_create(None, None, 0, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_factor(None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_factor_rhs(None, None, None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_solve(None, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_pivot_inertia(None, None, None, None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_residual(None, None, None, None, None, None) == rlqr.RLQR_E_INVALID
