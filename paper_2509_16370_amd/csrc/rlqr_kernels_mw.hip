@@ -13,7 +13,7 @@
 //
 // Pivot sweeps broadcast each pivot column through LDS with one workgroup
 // barrier per pivot. Workspace per stage: TZ^2 + TX^2 blocks (Z, then X).
-#include "rlqr_device.h"
+#include "rlqr_device_mw.h"
 #include "rlqr_internal.h"
 
 namespace rlqr {
@@ -201,15 +201,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   for (int k = khi - 1; k >= klo; --k) {
     __syncthreads();
     store_ab(ab);
-    double Hc[CZ][4];
-#pragma unroll
-    for (int t = 0; t < CZ; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Hc[t][v] = H[t][v];
-    if (k > klo) {
-      load_ab(ab, k - 1);
-      load_h(H, k - 1);
-    }
+    if (k > klo) load_ab(ab, k - 1);  // the next stage's [A B] (its Hessian after its last use below)
     // X = I + delta P_{k+1}, swept -> -S_hat^{-1}
     double X[CX][4];
 #pragma unroll
@@ -286,8 +278,9 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       if (!zo[t]) continue;
       auto acc = gemm_blk<TG, true, TX>(sAB, LDZ, sX, LDZ, zi[t], zj[t], lane);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Z[t][v] = (double)acc[v] + Hc[t][v];
+      for (int v = 0; v < 4; ++v) Z[t][v] = (double)acc[v] + H[t][v];
     }
+    if (k > klo) load_h(H, k - 1);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < CZ; ++t)

@@ -11,7 +11,7 @@
 // lqr-gpu-combo with X = I + C_ij P_jk inverted by Gauss-Jordan elimination
 // with partial pivoting; p and c are not carried (the p-recurrence recovers p,
 // as the paper recommends).
-#include "rlqr_device.h"
+#include "rlqr_device_mw.h"
 #include "rlqr_internal.h"
 
 namespace rlqr {
