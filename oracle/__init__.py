@@ -12,6 +12,8 @@ Contents
   * dense.py: the plain definition -- the KKT matrix of eqs.
     primal-dual-linear-system / optimal-control-specialization assembled
     densely, solved with numpy, inertia by eigenvalues and by scipy's LDL^T.
+  * crossstage.py: the arrowhead step with cross-stage variables (Section
+    "Cross-Stage Variables"), densely and by the paper's Schur route.
   * certificate(): the pivot test of Theorem
     "riccati-inertia-certification-theorem" from the oracle's pivots.
 """

@@ -29,7 +29,7 @@ exclusive prefix sums of those counts over the batch.
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, List, Sequence
+from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 
@@ -243,6 +243,68 @@ def pack_parallel(specs, workers: int = 8) -> Packed:
     delta = np.concatenate([r[3] for r in res])
     arrays = {k: np.concatenate([r[4][k] for r in res]) for k in ARRAYS_LHS + ARRAYS_RHS}
     return Packed(N, n, m, delta, arrays, layout_offsets(N, n, m))
+
+
+# ---------------------------------------------------------------- cross-stage variables
+
+@dataclasses.dataclass
+class CrossStage:
+    """Data of p cross-stage variables for one instance (no solver arithmetic):
+    the columns of J_theta in the layout of an LQR right-hand side, H_theta_theta
+    and r_theta."""
+    J: List[Tuple[np.ndarray, np.ndarray, np.ndarray]]  # p x (Jq (N+1,n), Jr (N,m), Jc (N+1,n))
+    H: np.ndarray    # (p, p) symmetric
+    rth: np.ndarray  # (p,)
+
+
+def make_cross_stage(inst: Instance, p: int, seed: Sequence[int], indefinite: bool = False) -> CrossStage:
+    """Draw J, H, r_theta for p variables shared by every stage of `inst`.
+
+    Recipe (in this order, from their own seed stream):
+      Jq, Jr ~ 0.5 N(0,1)/sqrt(T), T = (N+1) n + N m (the variables enter
+        every stage's cost; each column has norm about 0.5),
+      Jc ~ 0.05 N(0,1)/sqrt(T) (and, weakly, every step's dynamics),
+      H = W W^T / p + I, W ~ N(0,1) (p x p); with indefinite=True, H <- -H,
+      r_theta ~ N(0,1).
+    The column scale keeps J^T K^{-1} J of order 0.1-1 at any horizon and
+    size: S = H - J^T K^{-1} J is usually, not always, positive definite."""
+    n, m, N = inst.n, inst.m, inst.N
+    rng = _rng(tuple(seed) + (17,))
+    sc = 0.5 / np.sqrt((N + 1.0) * n + N * m)
+    J = []
+    for _ in range(p):
+        Jq = sc * rng.standard_normal((N + 1, n))
+        Jr = sc * rng.standard_normal((N, m))
+        Jc = 0.1 * sc * rng.standard_normal((N + 1, n))
+        J.append((Jq, Jr, Jc))
+    W = rng.standard_normal((p, p))
+    H = W @ W.T / p + np.eye(p)
+    if indefinite:
+        H = -H
+    H = 0.5 * (H + H.T)
+    rth = rng.standard_normal(p)
+    return CrossStage(J, H, rth)
+
+
+def pack_cross_stage(packed: Packed, xs: List[CrossStage]) -> Dict[str, np.ndarray]:
+    """Stack the cross-stage data of a packed batch (all instances share p):
+    column j of J occupies [j*L, (j+1)*L) of Jq / Jr / Jc (L = the batch's
+    q / r / c length, instances at their usual offsets); H is (B, p, p) and
+    r_theta (B, p), flattened."""
+    B = packed.batch
+    p = len(xs[0].J) if B else 0
+    out = {}
+    for k, name in enumerate(("q", "r", "c")):
+        L = int(packed.offsets[name][-1])
+        a = np.zeros(p * L)
+        for b in range(B):
+            o0, o1 = packed.offsets[name][b], packed.offsets[name][b + 1]
+            for j in range(p):
+                a[j * L + o0:j * L + o1] = xs[b].J[j][k].reshape(-1)
+        out["J" + name] = a
+    out["H"] = np.concatenate([x.H.reshape(-1) for x in xs]) if B else np.zeros(0)
+    out["rth"] = np.concatenate([x.rth for x in xs]) if B else np.zeros(0)
+    return out
 
 
 # ---------------------------------------------------------------- constrained trajectory problems
