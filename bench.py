@@ -20,7 +20,10 @@ Other workloads (--workload): long_horizon (one instance, n=64, m=32,
 N=16384, delta=1e-6, refined to 1e-10; the parallel-in-time scan, with float32
 and with bfloat16 combine products, against the float64 sequential recursion) and batched_ragged (1024 instances,
 N ~ U{50..1000}, n in {8,16,32}, m in {2,4,8}, 20% indefinite Q, delta=1e-4;
-the autotuned single-graph launch against the float64 sequential path).
+the autotuned single-graph launch against the float64 sequential path) and
+cross_stage (the uniform batch with p = 4 variables shared by every stage:
+the arrowhead step of Section "Cross-Stage Variables", factor + solve +
+refinement of the whole system, float64 and mixed).
 """
 import argparse
 import json
@@ -121,6 +124,72 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_t
     )
 
 
+def run_xs_mode(torch, rl, packed, lhs, rhs, xsd, mode, steps, warmup, max_refine, rel_tol=REL_TOL):
+    """Cross-stage step: rlqr_xs_factor (LQR factor + p column solves + S) and
+    rlqr_xs_solve (one LQR solve, the p x p step, arrowhead refinement)."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    p = xsd["p"]
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
+    x = rl.CrossStage(s, p)
+    out = {k: s.empty(k) for k in ("x", "u", "y")}
+    out["theta"] = torch.empty(packed.batch * p, dtype=torch.float64, device="cuda:0")
+    J = {k: xsd[k] for k in ("Jq", "Jr", "Jc")}
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        x.factor(lhs, J, xsd["H"], rel_tol=rel_tol, max_refine=max_refine)
+        if ev:
+            ev[1].record(stream)
+        res = x.solve(rhs, xsd["rth"], out=out, rel_tol=rel_tol, max_refine=max_refine)
+        if ev:
+            ev[2].record(stream)
+        return res
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, status, relres = step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = status.cpu().numpy()[:packed.batch]
+    relres = relres.cpu().numpy()[:packed.batch]
+    ok = (relres <= rel_tol) & ((status == rl.INST_OK) | (status == rl.INST_NOT_PD))
+    stages = int(packed.N[ok].sum())
+    ms_per_step = 1e3 * wall / steps
+    return dict(
+        value=stages / (ms_per_step * 1e-3),
+        ms_per_step=ms_per_step,
+        factor_ms=float(np.median([e[0].elapsed_time(e[1]) for e in evs])),
+        solve_ms=float(np.median([e[1].elapsed_time(e[2]) for e in evs])),
+        instances_ok=int(ok.sum()),
+        max_relres=float(relres.max()),
+        median_relres=float(np.median(relres)),
+        status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+        workspace_bytes=s.workspace_bytes + x.workspace_bytes,
+    )
+
+
+def cpu_baseline_xs(insts, xs, count=256):
+    """The cross-stage oracle (the paper's Schur route, p + 2 sequential
+    Riccati solves per instance) on the first `count` instances, one thread."""
+    from oracle import crossstage as ocs
+    t0 = time.perf_counter()
+    stages = 0
+    for inst, x in zip(insts[:count], xs[:count]):
+        ocs.schur(inst, x.J, x.H, (inst.q, inst.r, inst.c), x.rth)
+        stages += inst.N
+    t = time.perf_counter() - t0
+    return dict(value=stages / t, unit="stage-solves/s", cores=1, kind="oracle",
+                sample=f"first {count} instances of the batch, the cross-stage oracle's Schur route "
+                       f"(p + 2 sequential float64 Riccati solves each), one thread",
+                seconds=t)
+
+
 def cpu_baseline(packed, seconds_target=10.0, sample=None):
     """The FP64 oracle, as it stands, over the same batch (or the named sample) on the host cores."""
     import numpy as np
@@ -178,7 +247,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "long_horizon", "batched_ragged"])
+                    choices=["batched_uniform", "long_horizon", "batched_ragged", "cross_stage"])
+    ap.add_argument("--p", type=int, default=4, help="cross_stage: number of cross-stage variables")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--nx", type=int, default=12, help="batched_uniform: state size")
     ap.add_argument("--nu", type=int, default=4, help="batched_uniform: control size")
@@ -225,6 +295,17 @@ def main():
         desc = ("single long-horizon dual-regularized LQR: n=64, m=32, N=16384, delta=1e-6, "
                 "refined to 1e-10 relative KKT residual; parallel-in-time scan vs float64 sequential")
         cfg = {"batch": 1, "nx": 64, "nu": 32, "N": 16384, "delta": 1e-6}
+    elif wk == "cross_stage":
+        n, m, N = args.nx, args.nu, args.horizon
+        insts = wl.batched_uniform(batch=args.batch, n=n, m=m, N=N, delta=args.delta)
+        packed = wl.pack(insts)
+        xs_data = [wl.make_cross_stage(inst, args.p, (1, b, 0)) for b, inst in enumerate(insts)]
+        modes = (args.modes or "fp64,mixed").split(",")
+        head = "fp64"
+        desc = (f"cross-stage Newton step: {args.batch} instances, n={n}, m={m}, N={N}, delta={args.delta:g}, "
+                f"p={args.p} variables shared by all stages (arrowhead Schur route), refined to "
+                f"{REL_TOL:g} relative residual of the whole system")
+        cfg = {"batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta, "p": args.p}
     else:
         insts = wl.batched_ragged()
         packed = wl.pack(insts)
@@ -246,6 +327,13 @@ def main():
         print(f"[bench] calibration copy: {cnt * 4} bytes read, {cnt * 4} bytes written", file=sys.stderr, flush=True)
         del src, dst
 
+    xsd = None
+    if wk == "cross_stage":
+        cs = wl.pack_cross_stage(packed, xs_data)
+        xsd = {k: torch.from_numpy(v).to("cuda:0") for k, v in cs.items()}
+        xsd["p"] = args.p
+        torch.cuda.synchronize()
+
     results = {}
     for mode in modes:
         steps, warmup = args.steps, args.warmup
@@ -259,8 +347,12 @@ def main():
                                    log=lambda msg: print(msg, file=sys.stderr, flush=True))
             print(f"[bench] tuned {len(plan)} buckets in {time.perf_counter() - t1:.1f}s: "
                   + ", ".join(f"{k}: {c.key()}" for k, c in plan.items()), file=sys.stderr, flush=True)
-        results[mode] = run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_tol=rel_tol,
-                                 chunk=args.chunk, plan=plan)
+        if xsd is not None:
+            results[mode] = run_xs_mode(torch, rl, packed, lhs, rhs, xsd, mode, steps, warmup, max_refine,
+                                        rel_tol=rel_tol)
+        else:
+            results[mode] = run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine,
+                                     rel_tol=rel_tol, chunk=args.chunk, plan=plan)
         if plan is not None:
             results[mode]["plan"] = {f"{k[0]},{k[1]}": c.key() for k, c in plan.items()}
         print(f"[bench] {mode}: {json.dumps(results[mode])}", file=sys.stderr, flush=True)
@@ -275,6 +367,24 @@ def main():
                 "traffic": None, "algorithmic_flops_per_stage": scan_factor_flops(64, 32),
                 "launch_ms": r["factor_ms"]}
         dtype = "f32+f64"
+    elif wk == "cross_stage":
+        # the whole step against HBM: factor (LHS read, factorization written),
+        # p + 1 first LQR solve passes (factorization, A, B read; x, u, y written;
+        # the residual re-reads the LHS), the p column and one right-hand side
+        # vectors read, and the cross-stage vector passes (J read three times,
+        # V once, dw written twice)
+        elem = 8 if head == "fp64" else 4
+        p = args.p
+        per_stage = (factor_algorithmic_bytes(n, m, elem, with_rhs=False)
+                     + (p + 1) * (elem * (m * n + n * (n + 1) + m * (m + 1) // 2) + 8 * (n * n + n * m)
+                                  + 8 * (2 * n + m) * 2 + 8 * (2 * n * n + 2 * n * m + m * m))
+                     + 8 * (2 * n + m) * (3 * p + p + 2))
+        alg_bytes = float(per_stage * packed.N.sum())
+        achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+        roof = {"kernel": "whole cross-stage step (all launches)", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes_per_step": alg_bytes, "step_ms": r["ms_per_step"]}
+        dtype = "f64" if head == "fp64" else "f32+f64"
     else:
         elem = 8 if head == "fp64" else 4
         alg_bytes = float(sum(factor_algorithmic_bytes(int(packed.n[b]), int(packed.m[b]), elem) * int(packed.N[b])
@@ -313,7 +423,9 @@ def main():
     if "fp64" in results:
         line[f"{head}_over_fp64"] = results[head]["value"] / results["fp64"]["value"]
     if not args.no_cpu_baseline:
-        if wk == "long_horizon":
+        if wk == "cross_stage":
+            line["cpu_baseline"] = cpu_baseline_xs(insts, xs_data)
+        elif wk == "long_horizon":
             line["cpu_baseline"] = cpu_baseline(wl.pack([wl.make_instance(64, 32, 2048, 1e-6, (3, 0, 0))]),
                                                 sample="one instance of the long-horizon shape at N=2048")
         else:

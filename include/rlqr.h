@@ -197,6 +197,22 @@ rlqr_status rlqr_solve(rlqr_handle *h, const rlqr_rhs *rhs, rlqr_sol *out,
                        int32_t *inst_status, double *inst_relres, rlqr_stream st);
 
 /*
+ * rlqr_solve for nrhs right-hand sides with the same factorization (the
+ * reuse of one factorization for many right-hand sides that Corollary
+ * "p-recurrence" allows). The arrays of rhs and out each hold nrhs vectors
+ * one after another: right-hand side j is (q + j*Lq, r + j*Lr, c + j*Lc) and
+ * its solution (x + j*Lq, u + j*Lr, y + j*Lq), where Lq, Lr, Lc are the batch
+ * lengths of the q, r and c arrays (rlqr_layout_offsets; x and y have the
+ * length of q and c, u that of r). inst_status and inst_relres, when not
+ * NULL, hold [nrhs][B] entries. Each right-hand side is solved and refined
+ * exactly as by rlqr_solve. nrhs = 0 is a no-op. Errors: as rlqr_solve, and
+ * RLQR_E_INVALID for nrhs < 0.
+ */
+rlqr_status rlqr_solve_multi(rlqr_handle *h, int32_t nrhs, const rlqr_rhs *rhs, rlqr_sol *out,
+                             double rel_tol, int32_t max_refine,
+                             int32_t *inst_status, double *inst_relres, rlqr_stream st);
+
+/*
  * Pivot certificate of Theorem "riccati-inertia-certification-theorem":
  * pd_verdict[b] = 1 iff every pivot of every S_hat_i and G_i is positive, i.e.
  * iff the KKT matrix has inertia (N(n+m)+n, (N+1)n, 0). first_bad[b] is the

@@ -704,6 +704,30 @@ extern "C" rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol*
   return RLQR_OK;
 }
 
+namespace rlqr {
+void handle_shapes(const rlqr_handle* h, int* batch, const int32_t** N, const int32_t** n, const int32_t** m) {
+  *batch = h->B;
+  *N = h->N.data(); *n = h->n.data(); *m = h->m.data();
+}
+}  // namespace rlqr
+
+extern "C" rlqr_status rlqr_solve_multi(rlqr_handle* h, int32_t nrhs, const rlqr_rhs* rhs, rlqr_sol* out,
+                                        double rel_tol, int32_t max_refine, int32_t* inst_status,
+                                        double* inst_relres, rlqr_stream stv) {
+  if (!h || !rhs || !out || nrhs < 0) return RLQR_E_INVALID;
+  if (!h->factored) return RLQR_E_STATE;
+  if (h->B == 0 || nrhs == 0) return RLQR_OK;
+  const int64_t Lq = h->off[RLQR_ARR_q][h->B], Lr = h->off[RLQR_ARR_r][h->B], Lc = h->off[RLQR_ARR_c][h->B];
+  for (int32_t j = 0; j < nrhs; ++j) {
+    rlqr_rhs b{rhs->q + j * Lq, rhs->r + j * Lr, rhs->c + j * Lc};
+    rlqr_sol z{out->x + j * Lq, out->u + j * Lr, out->y + j * Lc};
+    rlqr_status s = rlqr_solve(h, &b, &z, rel_tol, max_refine, inst_status ? inst_status + (int64_t)j * h->B : nullptr,
+                               inst_relres ? inst_relres + (int64_t)j * h->B : nullptr, stv);
+    if (s != RLQR_OK) return s;
+  }
+  return RLQR_OK;
+}
+
 extern "C" rlqr_status rlqr_pivot_inertia(rlqr_handle* h, int32_t* pd_verdict, int32_t* first_bad, int64_t* inertia,
                                           rlqr_stream stv) {
   if (!h) return RLQR_E_INVALID;

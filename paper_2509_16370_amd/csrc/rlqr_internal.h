@@ -222,4 +222,8 @@ struct MaskArgs {
 };
 hipError_t launch_masks(const MaskArgs& a, hipStream_t st);
 
+// Shapes of a handle's batch (host arrays owned by the handle), for the
+// cross-stage layer built on the public calls.
+void handle_shapes(const rlqr_handle* h, int* batch, const int32_t** N, const int32_t** n, const int32_t** m);
+
 }  // namespace rlqr

@@ -3,8 +3,9 @@
 Argument marshalling only: every step of the solve runs in the HIP kernels of
 librlqr.so. torch tensors provide device memory and the stream. The functions
 rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_factor_rhs,
-rlqr_solve, rlqr_pivot_inertia, rlqr_residual and rlqr_destroy carry the C
-names; `Solver` wraps one handle.
+rlqr_solve, rlqr_solve_multi, rlqr_pivot_inertia, rlqr_residual and
+rlqr_destroy carry the C names; `Solver` wraps one handle. The cross-stage
+calls of include/rlqr_xs.h (rlqr_xs_*) are wrapped by `CrossStage`.
 
 If librlqr.so is missing this module raises at import: there is no fallback.
 """
@@ -76,6 +77,8 @@ _lib.rlqr_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), _vp]
 _lib.rlqr_factor_rhs.argtypes = [_vp, ctypes.POINTER(_Lhs), ctypes.POINTER(_Rhs), _vp]
 _lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
                             ctypes.c_int32, _vp, _vp, _vp]
+_lib.rlqr_solve_multi.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
+                                  ctypes.c_int32, _vp, _vp, _vp]
 _lib.rlqr_pivot_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.rlqr_residual.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), _vp, _vp, _vp]
 _lib.rlqr_destroy.argtypes = [_vp]
@@ -83,11 +86,11 @@ _lib.rlqr_destroy.restype = None
 _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
 for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-           "rlqr_factor_rhs", "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch"):
+           "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-            "rlqr_factor_rhs", "rlqr_solve", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
+            "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
             "rlqr_destroy", "rlqr_status_string")
 
 
@@ -175,6 +178,15 @@ def rlqr_solve(h, q, r, c, x, u, y, rel_tol, max_refine, inst_status=None, inst_
     sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
     _check(_lib.rlqr_solve(h, ctypes.byref(rhs), ctypes.byref(sol), float(rel_tol), int(max_refine),
                            _ptr(inst_status), _ptr(inst_relres), _stream(stream)), "rlqr_solve")
+
+
+def rlqr_solve_multi(h, nrhs, q, r, c, x, u, y, rel_tol, max_refine, inst_status=None, inst_relres=None,
+                     stream=None):
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
+    _check(_lib.rlqr_solve_multi(h, int(nrhs), ctypes.byref(rhs), ctypes.byref(sol), float(rel_tol),
+                                 int(max_refine), _ptr(inst_status), _ptr(inst_relres), _stream(stream)),
+           "rlqr_solve_multi")
 
 
 def rlqr_pivot_inertia(h, verdict=None, first_bad=None, inertia=None, stream=None):
@@ -274,6 +286,22 @@ class Solver:
                    rel_tol, max_refine, status, relres, stream=stream)
         return out, status, relres
 
+    def solve_multi(self, nrhs: int, rhs, out=None, rel_tol: float = 1e-8, max_refine: int = 0, stream=None):
+        """rlqr_solve_multi: rhs[k] holds nrhs stacked vectors of the batch length of k."""
+        torch = self.torch
+        for k in ("q", "r", "c"):
+            t = rhs[k]
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and \
+                t.numel() >= nrhs * self.size(k), k
+        if out is None:
+            out = {k: torch.empty(max(nrhs * self.size(k), 1), dtype=torch.float64, device=self.device)
+                   for k in ("x", "u", "y")}
+        status = torch.empty(max(nrhs * self.batch, 1), dtype=torch.int32, device=self.device)
+        relres = torch.empty(max(nrhs * self.batch, 1), dtype=torch.float64, device=self.device)
+        rlqr_solve_multi(self.handle, nrhs, rhs["q"], rhs["r"], rhs["c"], out["x"], out["u"], out["y"],
+                         rel_tol, max_refine, status, relres, stream=stream)
+        return out, status, relres
+
     def capture(self, lhs, rhs, out, rel_tol: float = 1e-8, max_refine: int = 0, stream=None):
         """Capture factor + solve on `stream` (a torch.cuda.Stream, not the default
         stream) into the handle's graph; returns (status, relres) tensors that each
@@ -321,6 +349,111 @@ def to_device(packed, device="cuda:0"):
     lhs["delta"] = t(packed.delta)
     rhs = {k: t(packed.arrays[k]) for k in ("q", "r", "c")}
     return lhs, rhs
+
+
+# ------------------------------------------------------------- cross-stage variables (include/rlqr_xs.h)
+
+RLQR_XS_MAX_P = 8
+
+
+class _XsLhs(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("Jq", "Jr", "Jc", "H")]
+
+
+_lib.rlqr_xs_create.argtypes = [ctypes.POINTER(_vp), _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.rlqr_xs_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), ctypes.POINTER(_XsLhs), ctypes.c_double, ctypes.c_int32,
+                                _vp]
+_lib.rlqr_xs_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), _vp, ctypes.POINTER(_Sol), _vp, ctypes.c_double,
+                               ctypes.c_int32, _vp, _vp, _vp]
+_lib.rlqr_xs_inertia.argtypes = [_vp, _vp, _vp, _vp]
+_lib.rlqr_xs_destroy.argtypes = [_vp]
+_lib.rlqr_xs_destroy.restype = None
+for _f in ("rlqr_xs_create", "rlqr_xs_factor", "rlqr_xs_solve", "rlqr_xs_inertia"):
+    getattr(_lib, _f).restype = ctypes.c_int
+XS_EXPORTED = ("rlqr_xs_create", "rlqr_xs_factor", "rlqr_xs_solve", "rlqr_xs_inertia", "rlqr_xs_destroy")
+
+
+def rlqr_xs_create(h, p: int):
+    """Returns (context, workspace_bytes)."""
+    x = _vp()
+    ws = ctypes.c_size_t(0)
+    _check(_lib.rlqr_xs_create(ctypes.byref(x), h, int(p), ctypes.byref(ws)), "rlqr_xs_create")
+    return x, int(ws.value)
+
+
+def rlqr_xs_factor(x, Q, M, R, A, B, delta, Jq, Jr, Jc, H, rel_tol, max_refine, stream=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+    xl = _XsLhs(_ptr(Jq), _ptr(Jr), _ptr(Jc), _ptr(H))
+    _check(_lib.rlqr_xs_factor(x, ctypes.byref(lhs), ctypes.byref(xl), float(rel_tol), int(max_refine),
+                               _stream(stream)), "rlqr_xs_factor")
+
+
+def rlqr_xs_solve(x, q, r, c, rtheta, dx, du, dy, dtheta, rel_tol, max_refine, inst_status=None,
+                  inst_relres=None, stream=None):
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    sol = _Sol(_ptr(dx), _ptr(du), _ptr(dy))
+    _check(_lib.rlqr_xs_solve(x, ctypes.byref(rhs), _ptr(rtheta), ctypes.byref(sol), _ptr(dtheta), float(rel_tol),
+                              int(max_refine), _ptr(inst_status), _ptr(inst_relres), _stream(stream)),
+           "rlqr_xs_solve")
+
+
+def rlqr_xs_inertia(x, verdict=None, inertia=None, stream=None):
+    _check(_lib.rlqr_xs_inertia(x, _ptr(verdict), _ptr(inertia), _stream(stream)), "rlqr_xs_inertia")
+
+
+def rlqr_xs_destroy(x):
+    _lib.rlqr_xs_destroy(x)
+
+
+class CrossStage:
+    """rlqr_xs context over a Solver's handle: p cross-stage variables."""
+
+    def __init__(self, solver: "Solver", p: int):
+        self.solver = solver
+        self.torch = solver.torch
+        self.p = int(p)
+        with self.torch.cuda.device(solver.device):
+            self.ctx, self.workspace_bytes = rlqr_xs_create(solver.handle, self.p)
+
+    def __del__(self):
+        x = getattr(self, "ctx", None)
+        if x is not None and x.value and _lib is not None:
+            try:
+                _lib.rlqr_xs_destroy(x)
+            except Exception:  # interpreter shutdown
+                pass
+            self.ctx = None
+
+    def factor(self, lhs, J, H, rel_tol: float = 1e-8, max_refine: int = 3, stream=None):
+        """J: dict Jq, Jr, Jc of p stacked columns; H: (B*p*p) float64."""
+        s, torch = self.solver, self.torch
+        for k, base in (("Jq", "q"), ("Jr", "r"), ("Jc", "c")):
+            t = J[k]
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and \
+                t.numel() >= self.p * s.size(base), k
+        assert H.dtype == torch.float64 and H.is_contiguous() and H.numel() >= s.batch * self.p * self.p
+        s._lhs = lhs
+        self._keep = (lhs, J, H)  # re-read by every solve
+        rlqr_xs_factor(self.ctx, *(lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")), J["Jq"], J["Jr"], J["Jc"],
+                       H, rel_tol, max_refine, stream=stream)
+
+    def solve(self, rhs, rtheta, out=None, rel_tol: float = 1e-8, max_refine: int = 3, stream=None):
+        s, torch = self.solver, self.torch
+        if out is None:
+            out = {k: s.empty(k) for k in ("x", "u", "y")}
+            out["theta"] = torch.empty(max(s.batch * self.p, 1), dtype=torch.float64, device=s.device)
+        status = torch.empty(max(s.batch, 1), dtype=torch.int32, device=s.device)
+        relres = torch.empty(max(s.batch, 1), dtype=torch.float64, device=s.device)
+        rlqr_xs_solve(self.ctx, rhs["q"], rhs["r"], rhs["c"], rtheta, out["x"], out["u"], out["y"], out["theta"],
+                      rel_tol, max_refine, status, relres, stream=stream)
+        return out, status, relres
+
+    def inertia(self, stream=None):
+        s, torch = self.solver, self.torch
+        verdict = torch.empty(max(s.batch, 1), dtype=torch.int32, device=s.device)
+        inertia = torch.empty(max(3 * s.batch, 1), dtype=torch.int64, device=s.device)
+        rlqr_xs_inertia(self.ctx, verdict, inertia, stream=stream)
+        return verdict, inertia.view(-1, 3) if s.batch else inertia
 
 
 # ------------------------------------------------------------- interior-point driver (include/ripm.h)

@@ -38,6 +38,28 @@ def test_library_exports_every_ipm_symbol():
         assert hasattr(lib, name), name
 
 
+def test_library_exports_every_cross_stage_symbol():
+    from paper_2509_16370_amd import rlqr
+    names = _declared(os.path.join(ROOT, "include", "rlqr_xs.h"), "rlqr_xs_")
+    assert set(names) == set(rlqr.XS_EXPORTED)
+    lib = ctypes.CDLL(rlqr.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_cross_stage_rejects_bad_arguments():
+    from paper_2509_16370_amd import rlqr
+    lib = rlqr._lib
+    x = ctypes.c_void_p()
+    assert lib.rlqr_xs_create(ctypes.byref(x), None, 2, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_xs_create(None, None, 2, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_xs_factor(None, None, None, 1e-8, 0, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_xs_solve(None, None, None, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_xs_inertia(None, None, None, None) == rlqr.RLQR_E_INVALID
+    lib.rlqr_xs_destroy(None)
+    assert lib.rlqr_solve_multi(None, 1, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
+
+
 def test_library_exports_every_network_kernel_symbol():
     from paper_2509_16370_amd import rlqr
     names = _declared(os.path.join(ROOT, "include", "rmlp.h"), "rmlp_")

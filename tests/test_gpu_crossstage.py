@@ -1,0 +1,239 @@
+"""GPU parity of the cross-stage (arrowhead) step and the multi-right-hand-side
+solve, through the C ABI, against the FP64 CPU oracle.
+
+Tolerances as in the LQR parity tests: every instance must reach the relative
+residual it asks for; element-wise the step (dw, dtheta) differs from the
+oracle's by at most cond times that residual, gated at 1e-7 * max(1, |z|) for
+refined results and 1e-10 for the float64 path on tiny instances. Verdicts,
+inertia and statuses must match exactly.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import crossstage as ocs
+from paper_2509_16370_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def rl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2509_16370_amd import rlqr
+    return rlqr
+
+
+def _t(a):
+    import torch
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return torch.from_numpy(a if a.size else np.zeros(1)).cuda()
+
+
+def run_xs(rl, insts, xsd, mode, rel_tol=1e-10, max_refine=4, scan_chunk=0):
+    import torch
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    cs = wl.pack_cross_stage(packed, xsd)
+    p = len(xsd[0].J) if xsd else 1
+    J = {k: _t(cs[k]) for k in ("Jq", "Jr", "Jc")}
+    H, rth = _t(cs["H"]), _t(cs["rth"])
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=scan_chunk)
+    x = rl.CrossStage(s, p)
+    x.factor(lhs, J, H, rel_tol=rel_tol, max_refine=max_refine)
+    out, status, relres = x.solve(rhs, rth, rel_tol=rel_tol, max_refine=max_refine)
+    verdict, inertia = x.inertia()
+    torch.cuda.synchronize()
+    B = packed.batch
+    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
+    theta = out["theta"].cpu().numpy()[:B * p].reshape(B, p)
+    return dict(sols=sols, theta=theta, status=status.cpu().numpy()[:B], relres=relres.cpu().numpy()[:B],
+                verdict=verdict.cpu().numpy()[:B], inertia=inertia.cpu().numpy().reshape(-1, 3)[:B])
+
+
+def check(inst, xs, got_w, got_th, want_w, want_th, tol):
+    scale = max(1.0, max(np.abs(a).max() for a in want_w if a.size), np.abs(want_th).max())
+    err = max(max(np.abs(g - w).max() if w.size else 0.0 for g, w in zip(got_w, want_w)),
+              np.abs(got_th - want_th).max())
+    assert err <= tol * scale, f"max|gpu - oracle| = {err:.3e}, scale {scale:.3e}"
+
+
+# --------------------------------------------------------- hand-derived example
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_hand_example(rl, mode):
+    print(f"[gpu] cross-stage hand example mode={mode}", flush=True)
+    g = json.load(open(os.path.join(GOLD, "example_cross_stage.json")))
+    d = g["lqr"]
+    n, m, N = d["n"], d["m"], d["N"]
+    f = lambda k, s: np.asarray(d[k], float).reshape(s)
+    inst = wl.Instance(n, m, N, float(d["delta"]), f("Q", (N + 1, n, n)), f("M", (N, n, m)), f("R", (N, m, m)),
+                       f("A", (N, n, n)), f("B", (N, n, m)), f("q", (N + 1, n)), f("r", (N, m)), f("c", (N + 1, n)))
+    insts, xsd = [], []
+    for c in g["cases"]:
+        insts.append(inst)
+        xsd.append(wl.CrossStage([(np.asarray(c["Jq"], float), np.asarray(c["Jr"], float),
+                                   np.asarray(c["Jc"], float))], np.asarray(c["H"], float),
+                                 np.asarray(c["rtheta"], float)))
+    r = run_xs(rl, insts, xsd, mode)
+    for b, c in enumerate(g["cases"]):
+        want = (np.asarray(c["x"], float), np.asarray(c["u"], float), np.asarray(c["y"], float))
+        check(inst, xsd[b], r["sols"][b], r["theta"][b], want, np.asarray(c["theta"], float), 1e-10)
+        assert r["relres"][b] <= 1e-10
+        assert r["verdict"][b] == 1 and r["status"][b] == 0
+        assert tuple(r["inertia"][b]) == ocs.target_inertia(inst, 1)
+
+
+# --------------------------------------------------------- random tiny instances vs the dense definition
+
+def _tiny_batch(p, count=16, seed0=0):
+    rng = np.random.default_rng(1234 + p)
+    insts, xsd = [], []
+    for k in range(count):
+        n = int(rng.integers(2, 6)); m = int(rng.integers(1, 4)); N = int(rng.integers(1, 10))
+        delta = [1e-8, 1e-4, 0.1, 1e-6][k % 4]
+        inst = wl.make_instance(n, m, N, delta, (97, seed0 + k, p), indefinite=(k % 5 == 3))
+        insts.append(inst)
+        xsd.append(wl.make_cross_stage(inst, p, (97, seed0 + k, p), indefinite=(k % 7 == 5)))
+    return insts, xsd
+
+
+@pytest.mark.parametrize("mode,chunk", [("fp64", 0), ("mixed", 0), ("scan", 3)])
+@pytest.mark.parametrize("p", [1, 3, 8])
+def test_tiny_vs_dense(rl, mode, chunk, p):
+    print(f"[gpu] cross-stage tiny mode={mode} chunk={chunk} p={p}", flush=True)
+    insts, xsd = _tiny_batch(p)
+    r = run_xs(rl, insts, xsd, mode, scan_chunk=chunk)
+    tol = 1e-10 if mode == "fp64" else 1e-7
+    nbad = 0
+    for b, (inst, xs) in enumerate(zip(insts, xsd)):
+        rw = (inst.q, inst.r, inst.c)
+        w, th = ocs.dense(inst, xs.J, xs.H, rw, xs.rth)
+        check(inst, xs, r["sols"][b], r["theta"][b], w, th, tol)
+        assert r["relres"][b] <= 1e-10
+        want_in = ocs.inertia(inst, xs.J, xs.H)
+        verdict = want_in == ocs.target_inertia(inst, p)
+        nbad += not verdict
+        assert r["verdict"][b] == int(verdict), b
+        assert r["status"][b] == (0 if verdict else 1), b
+        if mode == "fp64":
+            assert tuple(r["inertia"][b]) == want_in, b
+    assert 0 < nbad < len(insts)  # both verdicts occur
+
+
+# --------------------------------------------------------- ragged, both tile classes, vs the Schur oracle
+
+@pytest.mark.parametrize("mode,chunk", [("fp64", 0), ("mixed", 0), ("scan", 16)])
+def test_ragged_vs_schur(rl, mode, chunk):
+    print(f"[gpu] cross-stage ragged mode={mode} chunk={chunk}", flush=True)
+    shapes = [(12, 4, 70), (8, 2, 33), (20, 8, 40), (32, 8, 25), (4, 1, 1), (16, 4, 64), (6, 3, 50), (24, 6, 17)]
+    insts = [wl.make_instance(n, m, N, [1e-8, 1e-4][k % 2], (96, k, 0), indefinite=(k == 2))
+             for k, (n, m, N) in enumerate(shapes)]
+    xsd = [wl.make_cross_stage(inst, 4, (96, k, 0), indefinite=(k == 5)) for k, inst in enumerate(insts)]
+    r = run_xs(rl, insts, xsd, mode, rel_tol=1e-10, max_refine=5, scan_chunk=chunk)
+    for b, (inst, xs) in enumerate(zip(insts, xsd)):
+        w, th, S = ocs.schur(inst, xs.J, xs.H, (inst.q, inst.r, inst.c), xs.rth)
+        check(inst, xs, r["sols"][b], r["theta"][b], w, th, 1e-7)
+        assert r["relres"][b] <= 1e-10, (b, r["relres"][b])
+        s_pd = bool(np.all(np.linalg.eigvalsh(0.5 * (S + S.T)) > 0))
+        o = oracle.seq(inst)
+        k_pd = bool(oracle.certificate(inst, o["dS"], o["dG"])[0])
+        assert r["verdict"][b] == int(k_pd and s_pd), b
+    assert r["verdict"][2] == 0 and r["verdict"][5] == 0  # indefinite Q; negative definite H
+
+
+# --------------------------------------------------------- the benchmark shape, sampled
+
+def test_full_size_sampled(rl):
+    print("[gpu] cross-stage full size: 4096 x (12, 4, 128), p = 4, mixed", flush=True)
+    insts = wl.batched_uniform()
+    xsd = [wl.make_cross_stage(inst, 4, (1, b, 0)) for b, inst in enumerate(insts)]
+    r = run_xs(rl, insts, xsd, "mixed", rel_tol=1e-8, max_refine=3)
+    assert np.all(r["relres"] <= 1e-8)
+    assert np.all(r["status"] == 0) and np.all(r["verdict"] == 1)
+    for b in (0, 1, 2047, 4095):
+        inst, xs = insts[b], xsd[b]
+        w, th, _ = ocs.schur(inst, xs.J, xs.H, (inst.q, inst.r, inst.c), xs.rth)
+        check(inst, xs, r["sols"][b], r["theta"][b], w, th, 1e-6)
+
+
+# --------------------------------------------------------- refinement off, empty batch, argument checks
+
+def test_no_refinement_float64(rl):
+    insts, xsd = _tiny_batch(2, count=6, seed0=50)
+    r = run_xs(rl, insts, xsd, "fp64", rel_tol=1e-8, max_refine=0)
+    assert np.all(r["relres"] <= 1e-12)
+
+
+def test_empty_batch(rl):
+    import torch
+    s = rl.Solver([], [], [], mode="fp64")
+    x = rl.CrossStage(s, 2)
+    z = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lhs = {k: z for k in ("Q", "M", "R", "A", "B", "delta")}
+    x.factor(lhs, {"Jq": z, "Jr": z, "Jc": z}, z)
+    out, status, relres = x.solve({"q": z, "r": z, "c": z}, z)
+    torch.cuda.synchronize()
+
+
+def test_rejects_p_out_of_range(rl):
+    s = rl.Solver([4], [3], [2], mode="fp64")
+    for p in (0, rl.RLQR_XS_MAX_P + 1):
+        with pytest.raises(rl.RlqrError):
+            rl.CrossStage(s, p)
+
+
+def test_solve_before_factor(rl):
+    import torch
+    insts, xsd = _tiny_batch(1, count=2)
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode="fp64")
+    x = rl.CrossStage(s, 1)
+    with pytest.raises(rl.RlqrError) as e:
+        x.solve(rhs, _t(np.zeros(2)))
+    assert e.value.code == rl.RLQR_E_STATE
+
+
+# --------------------------------------------------------- multiple right-hand sides
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "scan"])
+def test_solve_multi_matches_single_solves(rl, mode):
+    import torch
+    print(f"[gpu] solve_multi mode={mode}", flush=True)
+    shapes = [(12, 4, 40), (8, 2, 33), (20, 8, 21), (5, 2, 9)]
+    insts = [wl.make_instance(n, m, N, 1e-6, (95, k, 0)) for k, (n, m, N) in enumerate(shapes)]
+    packed = wl.pack(insts)
+    lhs, _ = rl.to_device(packed)
+    nrhs = 3
+    rng = np.random.default_rng(5)
+    stacks = {k: rng.standard_normal(nrhs * int(packed.offsets[k][-1])) for k in ("q", "r", "c")}
+    rhs = {k: _t(v) for k, v in stacks.items()}
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=8)
+    s.factor(lhs)
+    out, status, relres = s.solve_multi(nrhs, rhs, rel_tol=1e-10, max_refine=4)
+    torch.cuda.synchronize()
+    B = packed.batch
+    assert np.all(relres.cpu().numpy()[:nrhs * B] <= 1e-10)
+    for j in range(nrhs):
+        one = {k: rhs[k][j * s.size(k):(j + 1) * s.size(k)].contiguous() for k in ("q", "r", "c")}
+        o1, st1, rr1 = s.solve(one, rel_tol=1e-10, max_refine=4)
+        torch.cuda.synchronize()
+        for k, base in (("x", "q"), ("u", "r"), ("y", "c")):
+            L = s.size(base)
+            assert torch.equal(out[k][j * L:(j + 1) * L], o1[k][:L]), (j, k)
+        sols = wl.unpack_solution(packed, *(o1[k].cpu().numpy() for k in ("x", "u", "y")))
+        for b, inst in enumerate(insts):
+            sl = lambda k: stacks[k][j * int(packed.offsets[k][-1]):][packed.offsets[k][b]:packed.offsets[k][b + 1]]
+            ib = wl.Instance(inst.n, inst.m, inst.N, inst.delta, inst.Q, inst.M, inst.R, inst.A, inst.B,
+                             sl("q").reshape(inst.N + 1, inst.n), sl("r").reshape(inst.N, inst.m),
+                             sl("c").reshape(inst.N + 1, inst.n))
+            ref = oracle.seq(ib)
+            scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y")))
+            err = max(np.abs(a - ref[k]).max() for a, k in zip(sols[b], ("x", "u", "y")))
+            assert err <= 1e-7 * scale
