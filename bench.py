@@ -130,7 +130,7 @@ def run_xs_mode(torch, rl, packed, lhs, rhs, xsd, mode, steps, warmup, max_refin
     import numpy as np
     stream = torch.cuda.current_stream()
     p = xsd["p"]
-    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, max_rhs=p)  # the p column solves run together
     x = rl.CrossStage(s, p)
     out = {k: s.empty(k) for k in ("x", "u", "y")}
     out["theta"] = torch.empty(packed.batch * p, dtype=torch.float64, device="cuda:0")

@@ -129,6 +129,10 @@ typedef struct {
   const int32_t *inst_fp64;    /* [host][B] or NULL. RLQR_SEQ_MIXED and RLQR_SCAN_*:
                                   1 = factor and solve this instance in float64 only
                                   (no float32 attempt). */
+  int32_t max_rhs;             /* sequential modes: solve state for up to max_rhs
+                                  right-hand sides at once (rlqr_solve_multi); 0 or 1:
+                                  none. Costs max_rhs times the solve workspace
+                                  (right-hand-side-sized vectors, per-instance flags). */
 } rlqr_tuning;
 
 /*
@@ -205,7 +209,12 @@ rlqr_status rlqr_solve(rlqr_handle *h, const rlqr_rhs *rhs, rlqr_sol *out,
  * lengths of the q, r and c arrays (rlqr_layout_offsets; x and y have the
  * length of q and c, u that of r). inst_status and inst_relres, when not
  * NULL, hold [nrhs][B] entries. Each right-hand side is solved and refined
- * exactly as by rlqr_solve. nrhs = 0 is a no-op. Errors: as rlqr_solve, and
+ * exactly as by rlqr_solve, with identical results. In the sequential modes,
+ * when the handle was created with max_rhs >= nrhs, all right-hand sides run
+ * in the same launches (one wavefront or workgroup per instance and
+ * right-hand side, those of one instance placed on one XCD so that its tiles
+ * are read from HBM once and from L2 by the others); otherwise they run one
+ * after another. nrhs = 0 is a no-op. Errors: as rlqr_solve, and
  * RLQR_E_INVALID for nrhs < 0.
  */
 rlqr_status rlqr_solve_multi(rlqr_handle *h, int32_t nrhs, const rlqr_rhs *rhs, rlqr_sol *out,

@@ -108,6 +108,19 @@ struct rlqr_handle {
   int64_t nchunks_nf = 0;
   rlqr_rhs pk_rhs{};
   std::vector<void*> allocs;
+
+  // Stacked right-hand sides (rlqr_solve_multi, sequential modes): mv is a
+  // handle over a virtual batch of max_rhs * B instances, instance j*B + b
+  // being right-hand side j of instance b. It shares this handle's tiles and
+  // left-hand side; its vectors sit at j times the batch lengths. A call
+  // with r right-hand sides uses the first r*B virtual instances.
+  int max_rhs = 1;
+  rlqr_handle* mv = nullptr;
+  int Bbase = 0;                                   // (mv) instances per right-hand side
+  int base_count[TILE_CLASSES] = {};               // (mv) per right-hand side
+  int64_t base_nchunks = 0, base_nchunks_nf = 0;   // (mv) per right-hand side
+  std::vector<int32_t*> mlist[TILE_CLASSES];       // (mv) [r - 1]: launch order for r right-hand sides
+  double* vdelta = nullptr;                        // (mv) delta per virtual instance
 };
 
 static bool is_scan(rlqr_mode m) { return m == RLQR_SCAN_FP32 || m == RLQR_SCAN_BF16; }
@@ -135,6 +148,11 @@ static void release(rlqr_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   drop_graph(h);
+  if (h->mv) {
+    release(h->mv);
+    delete h->mv;
+    h->mv = nullptr;
+  }
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
 }
@@ -149,6 +167,152 @@ static bool upload(T* dst, const std::vector<T>& src) {
   do {                                        \
     if ((x) != hipSuccess) return RLQR_E_HIP; \
   } while (0)
+
+// Virtual instance j*B + b (right-hand side j of instance b) takes b's
+// certificate bookkeeping, float64 flag and delta at the start of each
+// stacked solve (the factorization of b may have changed them).
+struct ReplicateArgs {
+  int B, total;
+  const FactorInfo* info;
+  const int32_t* flag64;
+  const double* delta;
+  FactorInfo* vinfo;
+  int32_t* vflag64;
+  double* vdelta;
+};
+
+__global__ void k_replicate(ReplicateArgs a) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.total) return;
+  const int b = v % a.B;
+  a.vinfo[v] = a.info[b];
+  a.vflag64[v] = a.flag64[b];
+  a.vdelta[v] = a.delta[b];
+}
+
+// The virtual handle of rlqr_handle::mv for R right-hand sides (sequential
+// modes). Launch order of class c for r right-hand sides: the class's
+// instances in groups of 8 consecutive list positions t = 8s + x; right-hand
+// side j of position t goes to launch index (s*r + j)*8 + x, so the r
+// workgroups of one instance are 8 apart, which places them on the same XCD
+// (workgroups are dealt round-robin to the 8 XCDs) at about the same time;
+// the last C mod 8 positions follow in order.
+static rlqr_status build_multi(rlqr_handle* h, int R, const std::vector<InstMeta>& meta,
+                               const std::vector<ResChunk>& chunks, const std::vector<ResChunk>& chunks_nf,
+                               const std::vector<int32_t>& resfuse, const std::vector<std::vector<int32_t>>& lists,
+                               const std::vector<int32_t>& pref64, int64_t pk_elems) {
+  const int B = h->B;
+  if ((int64_t)R * B > (int64_t)INT32_MAX / 2) return RLQR_E_INVALID;
+  const int VB = R * B;
+  rlqr_handle* v = new (std::nothrow) rlqr_handle();
+  if (!v) return RLQR_E_NOMEM;
+  v->B = VB; v->mode = h->mode; v->chunk = h->chunk; v->shape16 = h->shape16; v->shape_all = h->shape_all;
+  v->ws64 = h->ws64; v->ws32 = h->ws32;  // shared, owned by h
+  v->any_pref64 = h->any_pref64;
+  v->Bbase = B;
+  const int64_t Lq = h->off[RLQR_ARR_q][B], Lr = h->off[RLQR_ARR_r][B], Lc = h->off[RLQR_ARR_c][B],
+                Lres = h->off[RLQR_ARR_RES][B];
+  std::vector<InstMeta> vm((size_t)VB);
+  std::vector<int32_t> vres((size_t)VB), vwoff((size_t)VB + 1), vflag((size_t)VB), vpref((size_t)VB);
+  for (int j = 0; j < R; ++j)
+    for (int b = 0; b < B; ++b) {
+      InstMeta mt = meta[b];
+      mt.oq += j * Lq; mt.or_ += j * Lr; mt.oc += j * Lc;
+      mt.ox += j * Lq; mt.ou += j * Lr; mt.oy += j * Lc;
+      mt.ores += j * Lres; mt.opk += j * pk_elems;
+      const int vi = j * B + b;
+      vm[vi] = mt;
+      vres[vi] = resfuse[b];
+      vflag[vi] = (h->mode == RLQR_SEQ_FP64 || pref64[b]) ? 1 : 0;
+      vpref[vi] = pref64[b] ? 0 : 1;
+    }
+  for (int i = 0; i <= VB; ++i) vwoff[i] = i;
+  std::vector<ResChunk> vch, vchnf;
+  for (int j = 0; j < R; ++j) {
+    for (ResChunk c : chunks) { c.inst += j * B; vch.push_back(c); }
+    for (ResChunk c : chunks_nf) { c.inst += j * B; vchnf.push_back(c); }
+  }
+  v->base_nchunks = (int64_t)chunks.size();
+  v->base_nchunks_nf = (int64_t)chunks_nf.size();
+  v->nchunks = (int64_t)vch.size();
+  v->nchunks_nf = (int64_t)vchnf.size();
+
+  rlqr_status st = RLQR_OK;
+  auto A = [&](void** p, size_t bytes) {
+    if (st == RLQR_OK) st = dev_alloc(v, p, bytes);
+  };
+  A((void**)&v->meta, sizeof(InstMeta) * (size_t)VB);
+  A((void**)&v->chunks, sizeof(ResChunk) * std::max<size_t>(vch.size(), 1));
+  A((void**)&v->chunks_nf, sizeof(ResChunk) * std::max<size_t>(vchnf.size(), 1));
+  A((void**)&v->resfuse, sizeof(int32_t) * (size_t)VB);
+  A((void**)&v->pk, sizeof(double) * (size_t)(R * pk_elems));
+  A((void**)&v->res[0], sizeof(double) * (size_t)(R * Lres));
+  A((void**)&v->res[1], sizeof(double) * (size_t)(R * Lres));
+  A((void**)&v->info, sizeof(FactorInfo) * (size_t)VB);
+  A((void**)&v->whole_off, sizeof(int32_t) * (size_t)(VB + 1));
+  A((void**)&v->whole_stats, sizeof(SegStats) * (size_t)VB);
+  A((void**)&v->resmax, sizeof(unsigned long long) * (size_t)VB);
+  A((void**)&v->bmax, sizeof(unsigned long long) * (size_t)VB);
+  int32_t** i32s[] = {&v->flag64, &v->conv, &v->run32, &v->run64, &v->runres, &v->fb, &v->status};
+  for (auto pp : i32s) A((void**)pp, sizeof(int32_t) * (size_t)VB);
+  A((void**)&v->lastrel, sizeof(double) * (size_t)VB);
+  A((void**)&v->relres, sizeof(double) * (size_t)VB);
+  A((void**)&v->vdelta, sizeof(double) * (size_t)VB);
+  if (h->mode != RLQR_SEQ_FP64) A((void**)&v->pref32, sizeof(int32_t) * (size_t)VB);
+  std::vector<std::vector<int32_t>> mlist_h[TILE_CLASSES];
+  std::vector<std::vector<SegDesc>> whole_d(TILE_CLASSES);
+  for (int c = 0; c < TILE_CLASSES; ++c) {
+    const int C = (int)lists[c].size();
+    v->base_count[c] = C;
+    v->count[c] = R * C;
+    v->whole[c].count = R * C;
+    if (C == 0) continue;
+    for (int j = 0; j < R; ++j)
+      for (int b : lists[c]) {
+        SegDesc d{};
+        d.inst = j * B + b; d.lo = 0; d.hi = h->N[b]; d.p0_ld = 0; d.gidx = j * B + b; d.s = 0; d.P0 = nullptr;
+        whole_d[c].push_back(d);
+      }
+    A((void**)&v->whole[c].d, sizeof(SegDesc) * whole_d[c].size());
+    const int S8 = C / 8, T = C % 8;
+    for (int r = 1; r <= R; ++r) {
+      std::vector<int32_t> L((size_t)r * C, -1);
+      for (int t = 0; t < C; ++t) {
+        const int b = lists[c][t];
+        for (int j = 0; j < r; ++j) {
+          const int64_t i = t < 8 * S8 ? ((int64_t)(t / 8) * r + j) * 8 + (t % 8)
+                                       : (int64_t)8 * S8 * r + (int64_t)j * T + (t - 8 * S8);
+          L[(size_t)i] = j * B + b;
+        }
+      }
+      mlist_h[c].push_back(L);
+      int32_t* d = nullptr;
+      A((void**)&d, sizeof(int32_t) * L.size());
+      v->mlist[c].push_back(d);
+    }
+    v->list[c] = v->mlist[c][R - 1];
+  }
+  if (st == RLQR_OK) {
+    bool ok = upload(v->meta, vm) && upload(v->chunks, vch) && upload(v->chunks_nf, vchnf) &&
+              upload(v->resfuse, vres) && upload(v->whole_off, vwoff) && upload(v->flag64, vflag);
+    if (ok && h->mode != RLQR_SEQ_FP64) ok = upload(v->pref32, vpref);
+    for (int c = 0; c < TILE_CLASSES && ok; ++c) {
+      if (lists[c].empty()) continue;
+      ok = upload(v->whole[c].d, whole_d[c]);
+      for (int r = 0; r < R && ok; ++r) ok = upload(v->mlist[c][r], mlist_h[c][r]);
+    }
+    if (!ok) st = RLQR_E_HIP;
+  }
+  if (st != RLQR_OK) {
+    release(v);
+    delete v;
+    return st;
+  }
+  h->bytes += v->bytes;
+  h->mv = v;
+  h->max_rhs = R;
+  return RLQR_OK;
+}
 
 extern "C" {
 
@@ -171,7 +335,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   if (!s || s->batch < 0) return RLQR_E_INVALID;
   if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED && mode != RLQR_SCAN_FP32 && mode != RLQR_SCAN_BF16)
     return RLQR_E_INVALID;
-  if (tune && tune->scan_chunk < 0) return RLQR_E_INVALID;
+  if (tune && (tune->scan_chunk < 0 || tune->max_rhs < 0)) return RLQR_E_INVALID;
   const int B = s->batch;
   if (B > 0 && (!s->N || !s->nx || !s->nu)) return RLQR_E_INVALID;
   for (int b = 0; b < B; ++b) {
@@ -414,6 +578,8 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     if (ok && scan && scan_prepare() != hipSuccess) ok = false;
     if (!ok) st = RLQR_E_HIP;
   }
+  if (st == RLQR_OK && tune && tune->max_rhs > 1 && !scan && B > 0)
+    st = build_multi(h, tune->max_rhs, meta, chunks, chunks_nf, resfuse, lists, pref64, pk_elems);
   if (st != RLQR_OK) {
     release(h);
     delete h;
@@ -659,14 +825,8 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
   return RLQR_OK;
 }
 
-extern "C" rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, double rel_tol,
-                                  int32_t max_refine, int32_t* inst_status, double* inst_relres, rlqr_stream stv) {
-  if (!h || !rhs || !out) return RLQR_E_INVALID;
-  if (!h->factored) return RLQR_E_STATE;
-  if (h->B == 0) return RLQR_OK;
-  if (!rhs->q || !rhs->r || !rhs->c || !out->x || !out->u || !out->y) return RLQR_E_INVALID;
-  if (!(rel_tol >= 0.0) || max_refine < 0) return RLQR_E_INVALID;
-  hipStream_t st = (hipStream_t)stv;
+static rlqr_status solve_impl(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, double rel_tol, int32_t max_refine,
+                              int32_t* inst_status, double* inst_relres, hipStream_t st) {
   rlqr_status s;
 
   RLQR_TRY(launch_fill_i32(h->conv, h->B, 0, st));
@@ -704,6 +864,16 @@ extern "C" rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol*
   return RLQR_OK;
 }
 
+extern "C" rlqr_status rlqr_solve(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, double rel_tol,
+                                  int32_t max_refine, int32_t* inst_status, double* inst_relres, rlqr_stream stv) {
+  if (!h || !rhs || !out) return RLQR_E_INVALID;
+  if (!h->factored) return RLQR_E_STATE;
+  if (h->B == 0) return RLQR_OK;
+  if (!rhs->q || !rhs->r || !rhs->c || !out->x || !out->u || !out->y) return RLQR_E_INVALID;
+  if (!(rel_tol >= 0.0) || max_refine < 0) return RLQR_E_INVALID;
+  return solve_impl(h, rhs, out, rel_tol, max_refine, inst_status, inst_relres, (hipStream_t)stv);
+}
+
 namespace rlqr {
 void handle_shapes(const rlqr_handle* h, int* batch, const int32_t** N, const int32_t** n, const int32_t** m) {
   *batch = h->B;
@@ -717,6 +887,31 @@ extern "C" rlqr_status rlqr_solve_multi(rlqr_handle* h, int32_t nrhs, const rlqr
   if (!h || !rhs || !out || nrhs < 0) return RLQR_E_INVALID;
   if (!h->factored) return RLQR_E_STATE;
   if (h->B == 0 || nrhs == 0) return RLQR_OK;
+  if (nrhs >= 2 && h->mv && nrhs <= h->max_rhs) {
+    if (!rhs->q || !rhs->r || !rhs->c || !out->x || !out->u || !out->y) return RLQR_E_INVALID;
+    if (!(rel_tol >= 0.0) || max_refine < 0) return RLQR_E_INVALID;
+    hipStream_t st = (hipStream_t)stv;
+    rlqr_handle* v = h->mv;
+    const int B = h->B;
+    v->B = nrhs * B;
+    for (int c = 0; c < TILE_CLASSES; ++c) {
+      v->count[c] = nrhs * v->base_count[c];
+      v->whole[c].count = v->count[c];
+      if (v->base_count[c] > 0) v->list[c] = v->mlist[c][nrhs - 1];
+    }
+    v->nchunks = nrhs * v->base_nchunks;
+    v->nchunks_nf = nrhs * v->base_nchunks_nf;
+    ReplicateArgs ra{};
+    ra.B = B; ra.total = v->B; ra.info = h->info; ra.flag64 = h->flag64; ra.delta = h->lhs.delta;
+    ra.vinfo = v->info; ra.vflag64 = v->flag64; ra.vdelta = v->vdelta;
+    hipLaunchKernelGGL(k_replicate, dim3((v->B + 255) / 256), dim3(256), 0, st, ra);
+    RLQR_TRY(hipGetLastError());
+    v->lhs = h->lhs;
+    v->lhs.delta = v->vdelta;
+    v->factored = true;
+    v->pk_fused = false;
+    return solve_impl(v, rhs, out, rel_tol, max_refine, inst_status, inst_relres, st);
+  }
   const int64_t Lq = h->off[RLQR_ARR_q][h->B], Lr = h->off[RLQR_ARR_r][h->B], Lc = h->off[RLQR_ARR_c][h->B];
   for (int32_t j = 0; j < nrhs; ++j) {
     rlqr_rhs b{rhs->q + j * Lq, rhs->r + j * Lr, rhs->c + j * Lc};

@@ -43,7 +43,7 @@ def run_xs(rl, insts, xsd, mode, rel_tol=1e-10, max_refine=4, scan_chunk=0):
     p = len(xsd[0].J) if xsd else 1
     J = {k: _t(cs[k]) for k in ("Jq", "Jr", "Jc")}
     H, rth = _t(cs["H"]), _t(cs["rth"])
-    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=scan_chunk)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=scan_chunk, max_rhs=p)
     x = rl.CrossStage(s, p)
     x.factor(lhs, J, H, rel_tol=rel_tol, max_refine=max_refine)
     out, status, relres = x.solve(rhs, rth, rel_tol=rel_tol, max_refine=max_refine)
@@ -202,19 +202,22 @@ def test_solve_before_factor(rl):
 
 # --------------------------------------------------------- multiple right-hand sides
 
-@pytest.mark.parametrize("mode", ["fp64", "mixed", "scan"])
-def test_solve_multi_matches_single_solves(rl, mode):
+@pytest.mark.parametrize("mode,max_rhs", [("fp64", 3), ("mixed", 3), ("fp64", 0), ("scan", 3), ("fp64", 5)])
+def test_solve_multi_matches_single_solves(rl, mode, max_rhs):
+    """Stacked solves (in one set of launches when max_rhs allows, else one
+    after another) equal single solves bit for bit and match the oracle."""
     import torch
-    print(f"[gpu] solve_multi mode={mode}", flush=True)
-    shapes = [(12, 4, 40), (8, 2, 33), (20, 8, 21), (5, 2, 9)]
-    insts = [wl.make_instance(n, m, N, 1e-6, (95, k, 0)) for k, (n, m, N) in enumerate(shapes)]
+    print(f"[gpu] solve_multi mode={mode} max_rhs={max_rhs}", flush=True)
+    shapes = [(12, 4, 40), (8, 2, 33), (20, 8, 21), (5, 2, 9), (12, 4, 1), (3, 1, 60), (32, 8, 12), (12, 4, 17),
+              (6, 2, 25), (16, 4, 30), (12, 4, 5)]
+    insts = [wl.make_instance(n, m, N, 1e-6, (95, k, 0), indefinite=(k == 3)) for k, (n, m, N) in enumerate(shapes)]
     packed = wl.pack(insts)
     lhs, _ = rl.to_device(packed)
     nrhs = 3
     rng = np.random.default_rng(5)
     stacks = {k: rng.standard_normal(nrhs * int(packed.offsets[k][-1])) for k in ("q", "r", "c")}
     rhs = {k: _t(v) for k, v in stacks.items()}
-    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=8)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=8, max_rhs=max_rhs)
     s.factor(lhs)
     out, status, relres = s.solve_multi(nrhs, rhs, rel_tol=1e-10, max_refine=4)
     torch.cuda.synchronize()
