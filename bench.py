@@ -368,17 +368,21 @@ def main():
                 "launch_ms": r["factor_ms"]}
         dtype = "f32+f64"
     elif wk == "cross_stage":
-        # the whole step against HBM: factor (LHS read, factorization written),
-        # p + 1 first LQR solve passes (factorization, A, B read; x, u, y written;
-        # the residual re-reads the LHS), the p column and one right-hand side
-        # vectors read, and the cross-stage vector passes (J read three times,
-        # V once, dw written twice)
+        # the whole step against HBM, per stage: the factorization (LHS read,
+        # factorization written); two solve passes (the p stacked column
+        # solves, then the r_w solve), each reading the factorization and A, B
+        # twice (backward and forward) and Q, M, R once (its residual), plus
+        # per right-hand side its q, r, c read and x, u, y written; the
+        # arrowhead residual re-reading the LHS; the cross-stage vector passes
+        # (6p + 10 vectors of the right-hand-side length read or written)
         elem = 8 if head == "fp64" else 4
         p = args.p
+        handoff = elem * (m * n + n * (n + 1) + m * (m + 1) // 2)
+        lhs_b = 8 * (2 * n * n + 2 * n * m + m * m)
+        vec_b = 8 * (2 * n + m)
         per_stage = (factor_algorithmic_bytes(n, m, elem, with_rhs=False)
-                     + (p + 1) * (elem * (m * n + n * (n + 1) + m * (m + 1) // 2) + 8 * (n * n + n * m)
-                                  + 8 * (2 * n + m) * 2 + 8 * (2 * n * n + 2 * n * m + m * m))
-                     + 8 * (2 * n + m) * (3 * p + p + 2))
+                     + 2 * (2 * handoff + 16 * (n * n + n * m) + 8 * (n * n + n * m + m * m))
+                     + (p + 1) * 2 * vec_b + lhs_b + (6 * p + 10) * vec_b)
         alg_bytes = float(per_stage * packed.N.sum())
         achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
         roof = {"kernel": "whole cross-stage step (all launches)", "bound": "hbm", "achieved": achieved,
