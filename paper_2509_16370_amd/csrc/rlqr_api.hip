@@ -100,6 +100,15 @@ struct rlqr_handle {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
 
+  // Batches with instances in two or more tile classes run the classes'
+  // factor and solve launches side by side: class c > first on side[c],
+  // forked from and joined back to the caller's stream with events (the same
+  // in graph capture). Each class launch is bound by its longest instance's
+  // sequential stage loop, so one after another they would add up.
+  hipStream_t side[TILE_CLASSES] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[TILE_CLASSES] = {};
+  bool owns_streams = false;
+
   rlqr_lhs lhs{};
   bool factored = false;
   bool pk_fused = false;  // pk holds the backward vector pass for pk_rhs (rlqr_factor_rhs)
@@ -148,6 +157,16 @@ static void release(rlqr_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   drop_graph(h);
+  if (h->owns_streams) {
+    for (int c = 0; c < TILE_CLASSES; ++c) {
+      if (h->side[c]) (void)hipStreamDestroy(h->side[c]);
+      if (h->ev_join[c]) (void)hipEventDestroy(h->ev_join[c]);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  }
+  for (int c = 0; c < TILE_CLASSES; ++c) { h->side[c] = nullptr; h->ev_join[c] = nullptr; }
+  h->ev_fork = nullptr;
+  h->owns_streams = false;
   if (h->mv) {
     release(h->mv);
     delete h->mv;
@@ -208,6 +227,8 @@ static rlqr_status build_multi(rlqr_handle* h, int R, const std::vector<InstMeta
   if (!v) return RLQR_E_NOMEM;
   v->B = VB; v->mode = h->mode; v->chunk = h->chunk; v->shape16 = h->shape16; v->shape_all = h->shape_all;
   v->ws64 = h->ws64; v->ws32 = h->ws32;  // shared, owned by h
+  for (int c = 0; c < TILE_CLASSES; ++c) { v->side[c] = h->side[c]; v->ev_join[c] = h->ev_join[c]; }
+  v->ev_fork = h->ev_fork;  // shared, owned by h (v->owns_streams stays false)
   v->any_pref64 = h->any_pref64;
   v->Bbase = B;
   const int64_t Lq = h->off[RLQR_ARR_q][B], Lr = h->off[RLQR_ARR_r][B], Lc = h->off[RLQR_ARR_c][B],
@@ -578,6 +599,20 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     if (ok && scan && scan_prepare() != hipSuccess) ok = false;
     if (!ok) st = RLQR_E_HIP;
   }
+  if (st == RLQR_OK) {
+    int nclass = 0;
+    for (int c = 0; c < TILE_CLASSES; ++c) nclass += lists[c].empty() ? 0 : 1;
+    if (nclass > 1) {
+      h->owns_streams = true;
+      bool ok = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess;
+      for (int c = 0; c < TILE_CLASSES && ok; ++c) {
+        if (lists[c].empty()) continue;
+        ok = hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming) == hipSuccess;
+      }
+      if (!ok) st = RLQR_E_HIP;
+    }
+  }
   if (st == RLQR_OK && tune && tune->max_rhs > 1 && !scan && B > 0)
     st = build_multi(h, tune->max_rhs, meta, chunks, chunks_nf, resfuse, lists, pref64, pk_elems);
   if (st != RLQR_OK) {
@@ -612,11 +647,51 @@ rlqr_status rlqr_layout_offsets(const rlqr_handle* h, int32_t array, int64_t* of
 
 // One factor launch per tile class over the given segment lists, then the
 // per-instance merge of the segments' pivot statistics.
+// Run launch(c, stream) for every class c with count[c] > 0: the first on st,
+// the others on their side streams between a fork and a join event.
+template <class F>
+static hipError_t per_class(rlqr_handle* h, const int* count, hipStream_t st, F&& launch) {
+  int first = -1, nclass = 0;
+  for (int c = 0; c < TILE_CLASSES; ++c)
+    if (count[c] > 0) {
+      if (first < 0) first = c;
+      ++nclass;
+    }
+  if (nclass <= 1 || !h->ev_fork) {
+    for (int c = 0; c < TILE_CLASSES; ++c) {
+      if (count[c] <= 0) continue;
+      hipError_t e = launch(c, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t e = hipEventRecord(h->ev_fork, st);
+  if (e != hipSuccess) return e;
+  for (int c = 0; c < TILE_CLASSES; ++c) {
+    if (count[c] <= 0) continue;
+    if (c == first) {
+      e = launch(c, st);
+    } else {
+      e = hipStreamWaitEvent(h->side[c], h->ev_fork, 0);
+      if (e == hipSuccess) e = launch(c, h->side[c]);
+      if (e == hipSuccess) e = hipEventRecord(h->ev_join[c], h->side[c]);
+    }
+    if (e != hipSuccess) return e;
+  }
+  for (int c = 0; c < TILE_CLASSES; ++c) {
+    if (count[c] <= 0 || c == first) continue;
+    e = hipStreamWaitEvent(st, h->ev_join[c], 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const int32_t* off, SegStats* stats,
                                   void* ws, const int32_t* run, bool fp32, hipStream_t st,
                                   const rlqr_rhs* rhs = nullptr) {
-  for (int c = 0; c < TILE_CLASSES; ++c) {
-    if (lists[c].count == 0) continue;
+  int count[TILE_CLASSES];
+  for (int c = 0; c < TILE_CLASSES; ++c) count[c] = lists[c].count;
+  hipError_t e = per_class(h, count, st, [&](int c, hipStream_t s2) {
     FactorArgs a{};
     a.meta = h->meta; a.segs = lists[c].d; a.run = run;
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
@@ -624,10 +699,10 @@ static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const in
     if (rhs && c == TILE_16) {
       a.q = rhs->q; a.r = rhs->r; a.c = rhs->c; a.pk = h->pk;
     }
-    hipError_t e = (c == TILE_16) ? launch_factor(a, lists[c].count, fp32, h->shape16, st)
-                                  : launch_factor_mw(c, a, lists[c].count, fp32, st);
-    if (e != hipSuccess) return e;
-  }
+    return (c == TILE_16) ? launch_factor(a, lists[c].count, fp32, h->shape16, s2)
+                          : launch_factor_mw(c, a, lists[c].count, fp32, s2);
+  });
+  if (e != hipSuccess) return e;
   MergeArgs m{};
   m.batch = h->B; m.meta = h->meta; m.seg_off = off; m.run = run; m.stats = stats; m.info = h->info;
   return launch_merge(m, st);
@@ -746,19 +821,17 @@ static CheckArgs check_args(rlqr_handle* h, int final_pass, double tol, const in
 // skip (scan mode) leaves the multi-segment instances to the segment solve.
 static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
                                const double* corr, hipStream_t st, bool fwd_only = false, double* res_out = nullptr) {
-  for (int c = 0; c < TILE_CLASSES; ++c) {
-    if (h->count[c] == 0) continue;
+  hipError_t e = per_class(h, h->count, st, [&](int c, hipStream_t s2) {
     SolveArgs a = solve_args(h, rhs, out, fp32, run, corr);
     a.list = h->list[c];
     a.fwd_only = (fwd_only && c == TILE_16) ? 1 : 0;
     if (res_out && c == TILE_16) {
       a.res = res_out; a.resmax = h->resmax; a.bmax = h->bmax; a.resfuse = h->resfuse;
     }
-    hipError_t e = (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, st)
-                                  : launch_solve_mw(c, a, h->count[c], fp32, st);
-    if (e != hipSuccess) return RLQR_E_HIP;
-  }
-  return RLQR_OK;
+    return (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, s2)
+                          : launch_solve_mw(c, a, h->count[c], fp32, s2);
+  });
+  return e == hipSuccess ? RLQR_OK : RLQR_E_HIP;
 }
 
 // Scan mode: the segments of multi-segment instances in three phases joined
