@@ -222,6 +222,21 @@ rlqr_status rlqr_solve_multi(rlqr_handle *h, int32_t nrhs, const rlqr_rhs *rhs, 
                              int32_t *inst_status, double *inst_relres, rlqr_stream st);
 
 /*
+ * Leave the instances with skip[b] != 0 out of the following rlqr_factor,
+ * rlqr_factor_rhs and rlqr_solve calls (sequential modes): their tiles,
+ * certificate, solution, status and relative residual keep their previous
+ * values, and they cost nothing but a flag test. skip is a DEVICE array [B]
+ * owned by the caller, read by each of those calls when it runs (so a
+ * captured graph reads its contents at replay); NULL clears the mask.
+ * rlqr_solve_multi and rlqr_residual ignore it. For drivers whose instances
+ * finish at different iterations (an interior-point batch, where converged
+ * problems drop out and only those whose certificate failed are refactored
+ * with a larger inertia correction). Errors: RLQR_E_INVALID (NULL h),
+ * RLQR_E_UNSUPPORTED (scan modes, when skip is not NULL).
+ */
+rlqr_status rlqr_set_skip(rlqr_handle *h, const int32_t *skip);
+
+/*
  * Pivot certificate of Theorem "riccati-inertia-certification-theorem":
  * pd_verdict[b] = 1 iff every pivot of every S_hat_i and G_i is positive, i.e.
  * iff the KKT matrix has inertia (N(n+m)+n, (N+1)n, 0). first_bad[b] is the

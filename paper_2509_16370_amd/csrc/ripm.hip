@@ -45,6 +45,11 @@ struct IpmArgs {
   double *Q, *M, *R, *Al, *Bl, *q, *r, *c;
   const double *dx, *du, *dy;
   const int32_t* verdict;
+  // LQR instances left out of the factor and solve (rlqr_set_skip):
+  // converged problems, and in later inertia-correction rounds also those
+  // whose certificate already holds; k_ipm_build skips them too when set
+  int32_t* skip;
+  const int32_t* build_skip;
 };
 
 __device__ __forceinline__ const double* mA(const IpmArgs& a) { return a.model; }
@@ -145,7 +150,7 @@ __global__ void k_ipm_init(IpmArgs a, const double* warm) {
 __global__ __launch_bounds__(256) void k_ipm_build(IpmArgs a) {
   const Dims d = a.d;
   const int i = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-  if (a.conv[b]) return;
+  if (a.conv[b] || (a.build_skip && a.build_skip[b])) return;
   const int n = d.n, m = d.m, ng = d.ng, N = d.N, nz = n + m;
   const double mu = a.mu[b], rho = a.rho[b];
   __shared__ double xs[MAXD], us[MAXD], yi[MAXD], yn[MAXD], th[MAXD], se[MAXD], wdd[MAXD];
@@ -544,6 +549,14 @@ __global__ void k_ipm_reset_steps(IpmArgs a) {
 
 __global__ void k_ipm_zero(int32_t* p) { *p = 0; }
 
+// skip = conv (mode 0), or conv || verdict (mode 1: later inertia-correction
+// rounds refactor only the problems whose certificate failed)
+__global__ void k_ipm_skip(IpmArgs a, int mode) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.d.B) return;
+  a.skip[b] = (a.conv[b] || (mode == 1 && a.verdict[b])) ? 1 : 0;
+}
+
 __global__ void k_ipm_count_active(const int32_t* conv, int B, int32_t* out) {
   __shared__ int red[256];
   int c = 0;
@@ -661,8 +674,11 @@ rlqr_status ripm_create(ripm_handle** hp, const ripm_problem* p, size_t* workspa
   A(&h->duv, D * B * N * m);
   A(&h->dyv, D * B * (N + 1) * n);
   A(&h->verdict, 4 * B);
+  A(&a.skip, 4 * B);
   if (st == RLQR_OK) {
     a.dx = h->dxv; a.du = h->duv; a.dy = h->dyv; a.verdict = h->verdict; a.fail = h->counter;
+    a.build_skip = nullptr;
+    if (rlqr_set_skip(h->lqr, a.skip) != RLQR_OK) st = RLQR_E_HIP;
     std::vector<double> model;
     model.insert(model.end(), p->A, p->A + n * n);
     model.insert(model.end(), p->B, p->B + n * m);
@@ -707,9 +723,14 @@ rlqr_status ripm_iterate(ripm_handle* h, int32_t* active, rlqr_stream stv) {
   rlqr_rhs rhs{a.q, a.r, a.c};
   rlqr_sol sol{h->dxv, h->duv, h->dyv};
   rlqr_status s;
-  // Newton direction with the inertia correction
+  // Newton direction with the inertia correction; converged problems are left
+  // out of the LQR calls, and after the first round only the problems whose
+  // certificate failed are rebuilt (with their larger rho) and refactored
   for (int round = 0; round < 60; ++round) {
-    hipLaunchKernelGGL(k_ipm_build, stages, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ipm_skip, small, dim3(256), 0, st, a, round > 0 ? 1 : 0);
+    IpmArgs ab = a;
+    ab.build_skip = round > 0 ? a.skip : nullptr;
+    hipLaunchKernelGGL(k_ipm_build, stages, dim3(256), 0, st, ab);
     IPM_TRY(hipGetLastError());
     if ((s = rlqr_factor_rhs(h->lqr, &lhs, &rhs, stv)) != RLQR_OK) return s;
     if ((s = rlqr_pivot_inertia(h->lqr, h->verdict, nullptr, nullptr, stv)) != RLQR_OK) return s;
@@ -721,6 +742,8 @@ rlqr_status ripm_iterate(ripm_handle* h, int32_t* active, rlqr_stream stv) {
     IPM_TRY(hipStreamSynchronize(st));
     if (fails == 0) break;
   }
+  hipLaunchKernelGGL(k_ipm_skip, small, dim3(256), 0, st, a, 0);
+  IPM_TRY(hipGetLastError());
   if ((s = rlqr_solve(h->lqr, &rhs, &sol, 1e-10, 4, nullptr, nullptr, stv)) != RLQR_OK) return s;
   hipLaunchKernelGGL(k_ipm_reset_steps, small, dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_ipm_recover, stages, dim3(64), 0, st, a);

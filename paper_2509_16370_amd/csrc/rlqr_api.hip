@@ -95,6 +95,8 @@ struct rlqr_handle {
   double *lastrel = nullptr, *relres = nullptr;
 
   int32_t* pref32 = nullptr;     // [B] float32 attempt allowed (mixed and scan modes)
+  const int32_t* skip = nullptr;  // [B] caller's mask of instances left out (rlqr_set_skip)
+  int32_t *runf = nullptr, *runf2 = nullptr;  // [B] factor run masks under the skip mask
   bool any_pref64 = false;
 
   hipGraph_t graph = nullptr;
@@ -509,6 +511,10 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   A((void**)&h->lastrel, sizeof(double) * (size_t)B);
   A((void**)&h->relres, sizeof(double) * (size_t)B);
   if (mode != RLQR_SEQ_FP64) A((void**)&h->pref32, sizeof(int32_t) * (size_t)B);
+  if (!scan) {
+    A((void**)&h->runf, sizeof(int32_t) * (size_t)B);
+    A((void**)&h->runf2, sizeof(int32_t) * (size_t)B);
+  }
   if (scan) {
     A((void**)&h->seg_off, sizeof(int32_t) * (size_t)(B + 1));
     A((void**)&h->seg_stats, sizeof(SegStats) * (size_t)std::max(seg_off[B], 1));
@@ -750,21 +756,35 @@ static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_r
   h->pk_fused = false;
   if (h->B == 0) return RLQR_OK;
   if (is_scan(h->mode)) rhs = nullptr;  // the segment recursions do not carry the vector pass
+  // run mask of a factor launch under the skip mask: !skip && in
+  auto masked = [&](const int32_t* in, int32_t* out, const int32_t** run) -> hipError_t {
+    *run = in;
+    if (!h->skip) return hipSuccess;
+    MaskArgs k{};
+    k.batch = h->B; k.kind = 5; k.skip = h->skip; k.in = in; k.out = out;
+    *run = out;
+    return launch_masks(k, st);
+  };
+  const int32_t* run = nullptr;
   if (h->mode == RLQR_SEQ_FP64) {
-    RLQR_TRY(factor_whole(h, h->ws64, nullptr, false, st, rhs));
+    RLQR_TRY(masked(nullptr, h->runf, &run));
+    RLQR_TRY(factor_whole(h, h->ws64, run, false, st, rhs));
   } else {
     // float32 products everywhere, then float64 for instances whose pivots fall
     // inside the guard band (or whose scan failed)
-    if (h->mode == RLQR_SEQ_MIXED)
-      RLQR_TRY(factor_whole(h, h->ws32, h->any_pref64 ? h->pref32 : nullptr, true, st, rhs));
-    else
+    if (h->mode == RLQR_SEQ_MIXED) {
+      RLQR_TRY(masked(h->any_pref64 ? h->pref32 : nullptr, h->runf, &run));
+      RLQR_TRY(factor_whole(h, h->ws32, run, true, st, rhs));
+    } else {
       RLQR_TRY(factor_scan(h, st));
+    }
     MaskArgs m{};
     m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
     m.bad = is_scan(h->mode) ? h->bad : nullptr;
     m.pref32 = h->any_pref64 ? h->pref32 : nullptr;
     RLQR_TRY(launch_masks(m, st));
-    RLQR_TRY(factor_whole(h, h->ws64, h->flag64, false, st, rhs));
+    RLQR_TRY(masked(h->flag64, h->runf2, &run));
+    RLQR_TRY(factor_whole(h, h->ws64, run, false, st, rhs));
   }
   if (rhs) {
     h->pk_fused = true;
@@ -902,7 +922,13 @@ static rlqr_status solve_impl(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
                               int32_t* inst_status, double* inst_relres, hipStream_t st) {
   rlqr_status s;
 
-  RLQR_TRY(launch_fill_i32(h->conv, h->B, 0, st));
+  if (h->skip) {  // left-out instances start converged: no pass touches them
+    MaskArgs k{};
+    k.batch = h->B; k.kind = 6; k.skip = h->skip; k.conv = h->conv;
+    RLQR_TRY(launch_masks(k, st));
+  } else {
+    RLQR_TRY(launch_fill_i32(h->conv, h->B, 0, st));
+  }
   // per-instance residual maxima start at zero (the check kernel clears resmax after each pass)
   RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->resmax), 2 * h->B, 0, st));
   RLQR_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(h->bmax), 2 * h->B, 0, st));
@@ -917,6 +943,7 @@ static rlqr_status solve_impl(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
     // instances that did not converge from float32 tiles: redo them in float64
     MaskArgs m{};
     m.batch = h->B; m.kind = 2; m.flag64 = h->flag64; m.conv = h->conv; m.status = h->status; m.fb = h->fb;
+    m.skip = h->skip;
     RLQR_TRY(launch_masks(m, st));
     RLQR_TRY(factor_whole(h, h->ws64, h->fb, false, st));
     const int extra = std::min<int32_t>(max_refine, 2);
@@ -993,6 +1020,13 @@ extern "C" rlqr_status rlqr_solve_multi(rlqr_handle* h, int32_t nrhs, const rlqr
                                inst_relres ? inst_relres + (int64_t)j * h->B : nullptr, stv);
     if (s != RLQR_OK) return s;
   }
+  return RLQR_OK;
+}
+
+extern "C" rlqr_status rlqr_set_skip(rlqr_handle* h, const int32_t* skip) {
+  if (!h) return RLQR_E_INVALID;
+  if (skip && is_scan(h->mode)) return RLQR_E_UNSUPPORTED;
+  h->skip = skip;
   return RLQR_OK;
 }
 

@@ -211,13 +211,17 @@ hipError_t launch_fill_i32(int32_t* p, int count, int32_t v, hipStream_t st);
 struct MaskArgs {
   int batch;
   int kind;               // 0: run masks, 1: guard band, 2: pick fallback instances, 3: fallback run mask,
-                          // 4: single-segment float32 run mask
+                          // 4: single-segment float32 run mask, 5: out = !skip && in (in NULL: 1),
+                          // 6: conv = skip
   double guard;
   const FactorInfo* info;
   const int32_t* status;
   const int32_t* bad;     // kind 1: instances whose scan failed also go to float64
   const int32_t* pref32;  // kind 1: if set, instances with pref32[b] == 0 always use float64
   const int32_t* multi;   // kind 4: instances with two or more segments
+  const int32_t* skip;    // kinds 2, 5, 6: instances left out (rlqr_set_skip)
+  const int32_t* in;      // kind 5
+  int32_t* out;           // kind 5
   int32_t *flag64, *conv, *run32, *run64, *runres, *fb, *run1;
 };
 hipError_t launch_masks(const MaskArgs& a, hipStream_t st);

@@ -1191,7 +1191,7 @@ __global__ void k_masks(MaskArgs a) {
     const bool fp64_only = a.pref32 && !a.pref32[b];
     a.flag64[b] = (fp64_only || fi.singular || !(fi.minrel >= a.guard) || (a.bad && a.bad[b])) ? 1 : 0;
   } else if (a.kind == 2) {
-    const int f = (!a.flag64[b] && a.status[b] == RLQR_INST_NOT_CONVERGED) ? 1 : 0;
+    const int f = (!a.flag64[b] && a.status[b] == RLQR_INST_NOT_CONVERGED && !(a.skip && a.skip[b])) ? 1 : 0;
     a.fb[b] = f;
     if (f) {
       a.flag64[b] = 1;
@@ -1199,6 +1199,10 @@ __global__ void k_masks(MaskArgs a) {
     }
   } else if (a.kind == 3) {
     a.run64[b] = (a.fb[b] && !a.conv[b]) ? 1 : 0;
+  } else if (a.kind == 5) {
+    a.out[b] = (!a.skip[b] && (a.in == nullptr || a.in[b])) ? 1 : 0;
+  } else if (a.kind == 6) {
+    a.conv[b] = a.skip[b] ? 1 : 0;
   } else {
     a.run1[b] = (a.run32[b] && !a.multi[b]) ? 1 : 0;
   }

@@ -81,17 +81,20 @@ _lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), cty
 _lib.rlqr_solve_multi.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
                                   ctypes.c_int32, _vp, _vp, _vp]
 _lib.rlqr_pivot_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.rlqr_set_skip.argtypes = [_vp, _vp]
 _lib.rlqr_residual.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), _vp, _vp, _vp]
 _lib.rlqr_destroy.argtypes = [_vp]
 _lib.rlqr_destroy.restype = None
 _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
 for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
-           "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch"):
+           "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
+           "rlqr_set_skip"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
             "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
+            "rlqr_set_skip",
             "rlqr_destroy", "rlqr_status_string")
 
 
@@ -188,6 +191,10 @@ def rlqr_solve_multi(h, nrhs, q, r, c, x, u, y, rel_tol, max_refine, inst_status
     _check(_lib.rlqr_solve_multi(h, int(nrhs), ctypes.byref(rhs), ctypes.byref(sol), float(rel_tol),
                                  int(max_refine), _ptr(inst_status), _ptr(inst_relres), _stream(stream)),
            "rlqr_solve_multi")
+
+
+def rlqr_set_skip(h, skip=None):
+    _check(_lib.rlqr_set_skip(h, _ptr(skip)), "rlqr_set_skip")
 
 
 def rlqr_pivot_inertia(h, verdict=None, first_bad=None, inertia=None, stream=None):
@@ -320,6 +327,13 @@ class Solver:
 
     def replay(self, stream=None):
         rlqr_graph_launch(self.handle, stream=stream)
+
+    def set_skip(self, skip=None):
+        """rlqr_set_skip: int32 device tensor [B] (nonzero = leave out), or None."""
+        if skip is not None:
+            assert skip.dtype == self.torch.int32 and skip.is_cuda and skip.numel() >= self.batch
+        self._skip = skip  # read by later calls: keep it alive
+        rlqr_set_skip(self.handle, skip)
 
     def pivot_inertia(self, stream=None):
         torch = self.torch
@@ -488,7 +502,7 @@ IPM_ETA = 1.0e3
 class IPM:
     """Batched regularized interior-point driver over a workloads.TrajectorySet."""
 
-    def __init__(self, ts, lqr: str = "mixed", eta: float = IPM_ETA, tol: float = 1e-6, device: str = "cuda:0"):
+    def __init__(self, ts, lqr: str = "fp64", eta: float = IPM_ETA, tol: float = 1e-6, device: str = "cuda:0"):
         import torch
         self.torch = torch
         self.ts = ts

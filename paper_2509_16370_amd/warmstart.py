@@ -128,7 +128,7 @@ def features(ts):
     return np.concatenate([ts.x0, ts.goal], axis=1).astype(np.float32)
 
 
-def solve_batch(ts, lqr="mixed", max_iter=200, warm=None):
+def solve_batch(ts, lqr="fp64", max_iter=200, warm=None):
     """Run the GPU interior-point driver; returns (iters, converged, x, u, y, z, seconds)."""
     import torch
     drv = rl.IPM(ts, lqr=lqr)
