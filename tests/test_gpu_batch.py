@@ -104,3 +104,43 @@ def test_autotuned_ragged_batch_matches_oracle(rl):
             scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y")))
             err = max(np.abs(a - ref[k]).max() for a, k in zip(sols[b], ("x", "u", "y")))
             assert err <= 1e-7 * scale, (b, err)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_full_size_ragged_batch(rl, mode):
+    """The ragged benchmark batch at full size (1024 instances, N up to 1000,
+    205 indefinite, delta = 1e-4), tile classes on their concurrent streams:
+    every instance meets 1e-8; certificate parity on a sample against the
+    oracle's pivots; every positive definite instance element-wise against
+    the oracle's batch solve."""
+    import torch
+    print(f"[gpu] full-size ragged batch mode={mode}", flush=True)
+    insts = wl.batched_ragged()
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
+    s.factor(lhs)
+    out, status, relres = s.solve(rhs, rel_tol=1e-8, max_refine=3)
+    verdict, first_bad, _ = s.pivot_inertia()
+    torch.cuda.synchronize()
+    B = packed.batch
+    rr = relres.cpu().numpy()[:B]
+    assert (rr <= 1e-8).all(), rr.max()
+    vd, fb = verdict.cpu().numpy()[:B], first_bad.cpu().numpy()[:B]
+    st = status.cpu().numpy()[:B]
+    assert (vd[[b for b, i in enumerate(insts) if i.indefinite]] == 0).all()
+    rng = np.random.default_rng(11)
+    for b in rng.choice(B, 48, replace=False):
+        ref = oracle.seq(insts[b])
+        ov, ofb, _ = oracle.certificate(insts[b], ref["dS"], ref["dG"])
+        assert vd[b] == int(ov) and fb[b] == ofb, b
+        assert st[b] == (0 if ov else 1), b
+    x, u, y, ost, _ = oracle.seq_batch(packed)
+    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
+    refs = wl.unpack_solution(packed, x, u, y)
+    for b, inst in enumerate(insts):
+        if inst.indefinite:
+            continue
+        scale = max(1.0, *(np.abs(a).max() for a in refs[b] if a.size))
+        err = max(np.abs(a - c).max() if a.size else 0.0 for a, c in zip(sols[b], refs[b]))
+        assert err <= 1e-7 * scale, (b, err)
