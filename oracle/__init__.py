@@ -64,8 +64,12 @@ def _load():
         lib.rlqr_oracle_residual.restype = None
         lib.rlqr_oracle_combine.argtypes = [i] + [dp] * 15
         lib.rlqr_oracle_combine.restype = i
+        lib.rlqr_oracle_seq_diag.argtypes = [i, i, i, dp] + [dp] * 8 + [dp] * 3 + [dp] * 6
+        lib.rlqr_oracle_seq_diag.restype = i
+        lib.rlqr_oracle_residual_diag.argtypes = [i, i, i, dp] + [dp] * 8 + [dp] * 3 + [dp]
+        lib.rlqr_oracle_residual_diag.restype = None
         lib.rlqr_oracle_seq_batch.argtypes = ([i, ip, ip, ip, dp] + [dp] * 8 + [llp] * 11
-                                              + [dp] * 3 + [ip, i])
+                                              + [dp] * 3 + [ip, i, dp])
         lib.rlqr_oracle_seq_batch.restype = i
         _lib = lib
     return _lib
@@ -91,17 +95,32 @@ def _outputs(n, m, N):
         dS=np.zeros((N + 1, n)), dG=np.zeros((N, m)))
 
 
+def _diag(inst) -> Optional[np.ndarray]:
+    """The instance's per-stage diagonals Delta_i, (N+1, n), or None (delta I)."""
+    dd = getattr(inst, "delta_diag", None)
+    if dd is None:
+        return None
+    dd = np.ascontiguousarray(dd, dtype=np.float64)
+    assert dd.shape == (inst.N + 1, inst.n) and (dd > 0).all()
+    return dd
+
+
 def seq(inst) -> Dict[str, np.ndarray]:
     """Sequential dual-regularized Riccati (FP64). Returns x, u, y, P, p, K, k,
-    state pivots dS, control pivots dG and `status` (0, or 1 on a zero pivot)."""
+    state pivots dS, control pivots dG and `status` (0, or 1 on a zero pivot).
+    With `inst.delta_diag` set, Delta_i = diag(delta_diag[i]) and dS holds the
+    pivots of I + Delta_i^{1/2} P_i Delta_i^{1/2}."""
     lib = _load()
     n, m, N = inst.n, inst.m, inst.N
     data = _data(inst)
     o = _outputs(n, m, N)
-    st = lib.rlqr_oracle_seq(n, m, N, float(inst.delta), *[_p(a) for a in data],
-                             _p(o["x"]), _p(o["u"]), _p(o["y"]),
-                             _p(o["P"]), _p(o["p"]), _p(o["K"]), _p(o["k"]),
-                             _p(o["dS"]), _p(o["dG"]))
+    dd = _diag(inst)
+    outs = (_p(o["x"]), _p(o["u"]), _p(o["y"]), _p(o["P"]), _p(o["p"]), _p(o["K"]), _p(o["k"]),
+            _p(o["dS"]), _p(o["dG"]))
+    if dd is None:
+        st = lib.rlqr_oracle_seq(n, m, N, float(inst.delta), *[_p(a) for a in data], *outs)
+    else:
+        st = lib.rlqr_oracle_seq_diag(n, m, N, _p(dd), *[_p(a) for a in data], *outs)
     o["status"] = st
     return o
 
@@ -142,8 +161,13 @@ def residual(inst, x, u, y) -> np.ndarray:
     data = _data(inst)
     res = np.zeros(N * (n + m) + n + (N + 1) * n)
     xs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, u, y)]
-    lib.rlqr_oracle_residual(n, m, N, float(inst.delta), *[_p(a) for a in data],
-                             *[_p(v) for v in xs], _p(res))
+    dd = _diag(inst)
+    if dd is None:
+        lib.rlqr_oracle_residual(n, m, N, float(inst.delta), *[_p(a) for a in data],
+                                 *[_p(v) for v in xs], _p(res))
+    else:
+        lib.rlqr_oracle_residual_diag(n, m, N, _p(dd), *[_p(a) for a in data],
+                                      *[_p(v) for v in xs], _p(res))
     return res
 
 
@@ -161,7 +185,8 @@ def rel_residual(inst, x, u, y) -> float:
 def certificate(inst, dS: np.ndarray, dG: np.ndarray):
     """Pivot test of Theorem "riccati-inertia-certification-theorem".
 
-    dS: (N+1, n) LDL^T pivots of S_hat_i = I + delta P_i; dG: (N, m) pivots of G_i.
+    dS: (N+1, n) LDL^T pivots of S_hat_i = I + delta P_i (with a per-stage
+    diagonal Delta_i: I + Delta_i^{1/2} P_i Delta_i^{1/2}); dG: (N, m) pivots of G_i.
     Returns (verdict, first_bad, inertia) where verdict is True iff every pivot
     is positive, first_bad is the code of the first failing pivot in the order
     the backward pass meets them (S_hat_N, G_{N-1}, S_hat_{N-1}, ..., G_0,
@@ -206,10 +231,12 @@ def seq_batch(packed, nthreads: int = 0):
     nu = np.ascontiguousarray(packed.m, dtype=np.int32)
     offs = [np.ascontiguousarray(o[k], dtype=np.int64) for k in
             ("Q", "M", "R", "A", "B", "q", "r", "c", "x", "u", "y")]
+    dd = packed.arrays.get("delta_diag")
     used = lib.rlqr_oracle_seq_batch(
         packed.batch, N.ctypes.data_as(ip), nx.ctypes.data_as(ip), nu.ctypes.data_as(ip),
         _p(np.ascontiguousarray(packed.delta)),
         *[_p(a[k]) for k in ("Q", "M", "R", "A", "B", "q", "r", "c")],
         *[v.ctypes.data_as(llp) for v in offs],
-        _p(x), _p(u), _p(y), status.ctypes.data_as(ip), int(nthreads))
+        _p(x), _p(u), _p(y), status.ctypes.data_as(ip), int(nthreads),
+        None if dd is None else _p(np.ascontiguousarray(dd, dtype=np.float64)))
     return x, u, y, status, used

@@ -6,6 +6,10 @@ with the block layout of eq. optimal-control-specialization,
 
     [[P, C^T], [C, -Delta]] [x; y] = -[s; c],
 
+with Delta = blockdiag(Delta_0, ..., Delta_N): delta I, or the instance's
+per-stage diagonals when it carries them (Definition "dual-regularized LQR"
+lets every Delta_i be any SPD matrix),
+
 assembled as a dense matrix and solved with numpy. Inertia comes from the
 eigenvalues (numpy.linalg.eigvalsh) and, independently, from the block
 diagonal of scipy's symmetric-indefinite LDL^T. Small sizes only.
@@ -46,7 +50,8 @@ def assemble(inst):
         C[(i + 1) * n:(i + 2) * n, xo[i]:xo[i] + n] = inst.A[i]
         C[(i + 1) * n:(i + 2) * n, uo[i]:uo[i] + m] = inst.B[i]
         C[(i + 1) * n:(i + 2) * n, xo[i + 1]:xo[i + 1] + n] = -np.eye(n)
-    Delta = d * np.eye(ny)
+    dd = getattr(inst, "delta_diag", None)
+    Delta = d * np.eye(ny) if dd is None else np.diag(np.asarray(dd, dtype=np.float64).reshape(-1))
     K = np.block([[P, C.T], [C, -Delta]])
     rhs = -np.concatenate([s, inst.c.reshape(-1)])
     return K, rhs

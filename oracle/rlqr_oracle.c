@@ -13,6 +13,11 @@
  *     K, k before eq. control-law, eq. value-fn-formulas, eqs. recover-x0,
  *     recover-x, control-law and the y = P x + p rewriting at the end of the
  *     proof), with Delta_i = delta * I.
+ *   - rlqr_oracle_seq_diag: the same recursion with a positive diagonal
+ *     Delta_i per stage (Definition "dual-regularized LQR" allows any SPD
+ *     Delta_i): the Riccati formulas with I + Delta_i P_i, and the state
+ *     pivots taken from the symmetric representative S_hat_i = I +
+ *     Delta_i^{1/2} P_i Delta_i^{1/2} of Section "Inertia Certification".
  *   - rlqr_oracle_par: the parallel algorithm of Section "Parallel
  *     Algorithm" run serially: u-elimination (eqs. lqr-gpu-init-running,
  *     lqr-gpu-init-terminal), reverse associative scan with the
@@ -30,6 +35,11 @@
  *   - (I + delta P)^{-1} is applied through an unpivoted LDL^T of the
  *     symmetric S_hat = I + delta P; its D entries are the state pivots of the
  *     certificate (Section "Inertia Certification", inverse-free form).
+ *   - With a diagonal Delta_i, I + Delta_i P_i is not symmetric: it is
+ *     applied through LU with partial pivoting of that matrix itself, and the
+ *     state pivots come from a separate unpivoted LDL^T of S_hat_i = I +
+ *     Delta_i^{1/2} P_i Delta_i^{1/2} (similar to I + Delta_i P_i, so it is
+ *     invertible exactly when I + Delta_i P_i is).
  *   - G_k is factored by unpivoted LDL^T; its D entries are the control pivots.
  *   - W, G and P are symmetrized after being formed (the paper proves them
  *     symmetric; rounding does not keep them so).
@@ -220,7 +230,8 @@ static void fill_nan(double *p, size_t cnt) {
  * dG N m      = D of LDL^T(G_i)            (control pivots, i = 0..N-1).
  * Returns 0, or 1 if a pivot was zero (solution then NaN).
  */
-int rlqr_oracle_seq(int n, int m, int N, double delta,
+/* dd == NULL: Delta_i = delta I; otherwise Delta_i = diag(dd + i n), i = 0..N */
+static int seq_core(int n, int m, int N, double delta, const double *dd,
                     const double *Q, const double *M, const double *R,
                     const double *A, const double *B,
                     const double *q, const double *r, const double *c,
@@ -228,6 +239,9 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
                     double *Pout, double *pout, double *Kout, double *kout,
                     double *dS, double *dG) {
   const int nn = n * n, nm = n * m, mm = m * m;
+  /* with dd: LU factors of I + Delta_i P_i and their row pivots */
+  double *LUs = dd ? malloc(sizeof(double) * (size_t)(N + 1) * nn) : NULL;
+  int *pivs = dd ? malloc(sizeof(int) * (size_t)(N + 1) * n) : NULL;
   double *P = malloc(sizeof(double) * (size_t)(N + 1) * nn);
   double *p = malloc(sizeof(double) * (size_t)(N + 1) * n);
   double *K = malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * nm);
@@ -253,13 +267,30 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
     const double *Qk = Q + (size_t)k * nn, *Mk = M + (size_t)k * nm, *Rk = R + (size_t)k * mm;
     const double *qk = q + (size_t)k * n, *rk = r + (size_t)k * m, *cn = c + (size_t)(k + 1) * n;
 
-    /* S_hat_{k+1} = I + delta P_{k+1}, factored */
-    for (int i = 0; i < nn; ++i) Sh[i] = delta * Pn[i];
-    for (int i = 0; i < n; ++i) Sh[i * n + i] += 1.0;
-    if (ldlt(n, Sh, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n)) { status = 1; break; }
-    /* W_{k+1} = P_{k+1} (I + delta P_{k+1})^{-1} = ((I + delta P)^{-1} P)^T */
-    memcpy(tmp, Pn, sizeof(double) * nn);
-    ldlt_solve(n, n, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n, tmp);
+    const double *dn = dd ? dd + (size_t)(k + 1) * n : NULL;
+    if (!dd) {
+      /* S_hat_{k+1} = I + delta P_{k+1}, factored */
+      for (int i = 0; i < nn; ++i) Sh[i] = delta * Pn[i];
+      for (int i = 0; i < n; ++i) Sh[i * n + i] += 1.0;
+      if (ldlt(n, Sh, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n)) { status = 1; break; }
+      /* W_{k+1} = P_{k+1} (I + delta P_{k+1})^{-1} = ((I + delta P)^{-1} P)^T */
+      memcpy(tmp, Pn, sizeof(double) * nn);
+      ldlt_solve(n, n, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n, tmp);
+    } else {
+      /* state pivots: S_hat_{k+1} = I + Delta^{1/2} P_{k+1} Delta^{1/2} */
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Sh[i * n + j] = sqrt(dn[i]) * Pn[i * n + j] * sqrt(dn[j]);
+      for (int i = 0; i < n; ++i) Sh[i * n + i] += 1.0;
+      if (ldlt(n, Sh, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n)) { status = 1; break; }
+      /* I + Delta P_{k+1} by LU; W_{k+1} = P (I + Delta P)^{-1}, whose
+         transpose solves (I + Delta P)^T W^T = P */
+      double *LU = LUs + (size_t)(k + 1) * nn;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) LU[i * n + j] = (i == j ? 1.0 : 0.0) + dn[i] * Pn[i * n + j];
+      if (lu_factor(n, LU, pivs + (size_t)(k + 1) * n)) { status = 1; break; }
+      memcpy(tmp, Pn, sizeof(double) * nn);
+      lu_solve_t(n, n, LU, pivs + (size_t)(k + 1) * n, tmp);
+    }
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) W[i * n + j] = tmp[j * n + i];
     symmetrize(n, W);
@@ -274,8 +305,8 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < n; ++j) H[i * n + j] += Mk[j * m + i];
 
-    /* g_{k+1} = p_{k+1} + W (c_{k+1} - delta p_{k+1}),  h_k = r_k + B^T g */
-    for (int i = 0; i < n; ++i) v[i] = cn[i] - delta * pn[i];
+    /* g_{k+1} = p_{k+1} + W (c_{k+1} - Delta p_{k+1}),  h_k = r_k + B^T g */
+    for (int i = 0; i < n; ++i) v[i] = cn[i] - (dd ? dn[i] : delta) * pn[i];
     mat_vec(n, n, W, v, g);
     for (int i = 0; i < n; ++i) g[i] += pn[i];
     mat_tvec(n, m, Bk, g, h);
@@ -303,10 +334,17 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
   }
 
   if (!status) {
-    /* S_hat_0 = I + delta P_0 */
-    for (int i = 0; i < nn; ++i) Sh[i] = delta * P[i];
+    /* S_hat_0 = I + delta P_0 (with dd: I + Delta_0^{1/2} P_0 Delta_0^{1/2},
+       and the LU of I + Delta_0 P_0) */
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) Sh[i * n + j] = (dd ? sqrt(dd[i]) * sqrt(dd[j]) : delta) * P[i * n + j];
     for (int i = 0; i < n; ++i) Sh[i * n + i] += 1.0;
     if (ldlt(n, Sh, SL, SD)) status = 1;
+    if (!status && dd) {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) LUs[i * n + j] = (i == j ? 1.0 : 0.0) + dd[i] * P[i * n + j];
+      if (lu_factor(n, LUs, pivs)) status = 1;
+    }
   }
 
   if (!status) {
@@ -314,8 +352,10 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
        u_k = K_k x_k + k_k,
        x_{k+1} = S_hat_{k+1}^{-1}(A x + B u + c_{k+1} - delta p_{k+1}),
        y_k = P_k x_k + p_k */
-    for (int i = 0; i < n; ++i) x[i] = c[i] - delta * p[i];
-    ldlt_solve(n, 1, SL, SD, x);
+    /* (with dd: Delta_i in place of delta and (I + Delta_i P_i)^{-1} by its LU) */
+    for (int i = 0; i < n; ++i) x[i] = c[i] - (dd ? dd[i] : delta) * p[i];
+    if (dd) lu_solve(n, 1, LUs, pivs, x);
+    else ldlt_solve(n, 1, SL, SD, x);
     for (int k = 0; k < N; ++k) {
       const double *xk = x + (size_t)k * n;
       double *uk = u + (size_t)k * m, *xn = x + (size_t)(k + 1) * n;
@@ -324,8 +364,10 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
       mat_vec(n, n, A + (size_t)k * nn, xk, v);
       mat_vec(n, m, B + (size_t)k * nm, uk, w);
       for (int i = 0; i < n; ++i)
-        xn[i] = v[i] + w[i] + c[(size_t)(k + 1) * n + i] - delta * p[(size_t)(k + 1) * n + i];
-      ldlt_solve(n, 1, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n, xn);
+        xn[i] = v[i] + w[i] + c[(size_t)(k + 1) * n + i] -
+                (dd ? dd[(size_t)(k + 1) * n + i] : delta) * p[(size_t)(k + 1) * n + i];
+      if (dd) lu_solve(n, 1, LUs + (size_t)(k + 1) * nn, pivs + (size_t)(k + 1) * n, xn);
+      else ldlt_solve(n, 1, SL + (size_t)(k + 1) * nn, SD + (size_t)(k + 1) * n, xn);
     }
     for (int k = 0; k <= N; ++k) {
       mat_vec(n, n, P + (size_t)k * nn, x + (size_t)k * n, y + (size_t)k * n);
@@ -345,7 +387,31 @@ int rlqr_oracle_seq(int n, int m, int N, double delta,
   free(P); free(p); free(K); free(kk); free(SL); free(SD); free(GD);
   free(Sh); free(W); free(WA); free(WB); free(G); free(GL); free(H); free(tmp);
   free(g); free(h); free(v); free(w);
+  free(LUs); free(pivs);
   return status;
+}
+
+int rlqr_oracle_seq(int n, int m, int N, double delta,
+                    const double *Q, const double *M, const double *R,
+                    const double *A, const double *B,
+                    const double *q, const double *r, const double *c,
+                    double *x, double *u, double *y,
+                    double *Pout, double *pout, double *Kout, double *kout,
+                    double *dS, double *dG) {
+  return seq_core(n, m, N, delta, NULL, Q, M, R, A, B, q, r, c, x, u, y, Pout, pout, Kout, kout, dS, dG);
+}
+
+/* As rlqr_oracle_seq with Delta_i = diag(dd[i n .. i n + n - 1]), i = 0..N,
+ * every entry > 0; dS then holds the LDL^T pivots of
+ * I + Delta_i^{1/2} P_i Delta_i^{1/2}. */
+int rlqr_oracle_seq_diag(int n, int m, int N, const double *dd,
+                         const double *Q, const double *M, const double *R,
+                         const double *A, const double *B,
+                         const double *q, const double *r, const double *c,
+                         double *x, double *u, double *y,
+                         double *Pout, double *pout, double *Kout, double *kout,
+                         double *dS, double *dG) {
+  return seq_core(n, m, N, 0.0, dd, Q, M, R, A, B, q, r, c, x, u, y, Pout, pout, Kout, kout, dS, dG);
 }
 
 /* --------------------------------------------------------- parallel algorithm */
@@ -730,7 +796,7 @@ int rlqr_oracle_combine(int n,
  *   A_i x_i + B_i u_i + c_{i+1} - delta y_{i+1} - x_{i+1}, i = 0..N-1       (n each)
  * Length N(n+m) + n + (N+1)n.
  */
-void rlqr_oracle_residual(int n, int m, int N, double delta,
+static void residual_core(int n, int m, int N, double delta, const double *dd,
                           const double *Q, const double *M, const double *R,
                           const double *A, const double *B,
                           const double *q, const double *r, const double *c,
@@ -761,16 +827,36 @@ void rlqr_oracle_residual(int n, int m, int N, double delta,
     for (int b = 0; b < n; ++b) s += Q[(size_t)N * nn + a * n + b] * x[(size_t)N * n + b];
     res[o++] = s;
   }
-  for (int a = 0; a < n; ++a) res[o++] = c[a] - delta * y[a] - x[a];
+  for (int a = 0; a < n; ++a) res[o++] = c[a] - (dd ? dd[a] : delta) * y[a] - x[a];
   for (int i = 0; i < N; ++i) {
     const double *xi = x + (size_t)i * n, *ui = u + (size_t)i * m;
     for (int a = 0; a < n; ++a) {
-      double s = c[(size_t)(i + 1) * n + a] - delta * y[(size_t)(i + 1) * n + a] - x[(size_t)(i + 1) * n + a];
+      const size_t j = (size_t)(i + 1) * n + a;
+      double s = c[j] - (dd ? dd[j] : delta) * y[j] - x[j];
       for (int b = 0; b < n; ++b) s += A[(size_t)i * nn + a * n + b] * xi[b];
       for (int b = 0; b < m; ++b) s += B[(size_t)i * nm + a * m + b] * ui[b];
       res[o++] = s;
     }
   }
+}
+
+void rlqr_oracle_residual(int n, int m, int N, double delta,
+                          const double *Q, const double *M, const double *R,
+                          const double *A, const double *B,
+                          const double *q, const double *r, const double *c,
+                          const double *x, const double *u, const double *y,
+                          double *res) {
+  residual_core(n, m, N, delta, NULL, Q, M, R, A, B, q, r, c, x, u, y, res);
+}
+
+/* As rlqr_oracle_residual with Delta_i = diag(dd + i n) in the dual rows. */
+void rlqr_oracle_residual_diag(int n, int m, int N, const double *dd,
+                               const double *Q, const double *M, const double *R,
+                               const double *A, const double *B,
+                               const double *q, const double *r, const double *c,
+                               const double *x, const double *u, const double *y,
+                               double *res) {
+  residual_core(n, m, N, 0.0, dd, Q, M, R, A, B, q, r, c, x, u, y, res);
 }
 
 /* ------------------------------------------------------------- batch driver */
@@ -779,6 +865,7 @@ void rlqr_oracle_residual(int n, int m, int N, double delta,
  * Runs rlqr_oracle_seq over a packed batch (offsets are the exclusive
  * prefix sums of the per-instance element counts, one int64[B+1] per array),
  * instances spread over threads. status[b] receives the per-instance return.
+ * dd: NULL (Delta_i = delta[b] I), or per-stage diagonals laid out like x.
  * Returns the number of threads used.
  */
 int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
@@ -790,7 +877,8 @@ int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
                           const long long *oA, const long long *oB,
                           const long long *oq, const long long *or_, const long long *oc,
                           const long long *ox, const long long *ou, const long long *oy,
-                          double *x, double *u, double *y, int *status, int nthreads) {
+                          double *x, double *u, double *y, int *status, int nthreads,
+                          const double *dd) {
   int used = 1;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -800,7 +888,7 @@ int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
     used = omp_get_num_threads();
 #pragma omp for schedule(dynamic, 1)
     for (int b = 0; b < batch; ++b)
-      status[b] = rlqr_oracle_seq(nx[b], nu[b], N[b], delta[b],
+      status[b] = seq_core(nx[b], nu[b], N[b], delta[b], dd ? dd + ox[b] : NULL,
                                   Q + oQ[b], M + oM[b], R + oR[b], A + oA[b], B + oB[b],
                                   q + oq[b], r + or_[b], c + oc[b],
                                   x + ox[b], u + ou[b], y + oy[b],
@@ -809,7 +897,7 @@ int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
 #else
   (void)nthreads;
   for (int b = 0; b < batch; ++b)
-    status[b] = rlqr_oracle_seq(nx[b], nu[b], N[b], delta[b],
+    status[b] = seq_core(nx[b], nu[b], N[b], delta[b], dd ? dd + ox[b] : NULL,
                                 Q + oQ[b], M + oM[b], R + oR[b], A + oA[b], B + oB[b],
                                 q + oq[b], r + or_[b], c + oc[b],
                                 x + ox[b], u + ou[b], y + oy[b],

@@ -8,7 +8,8 @@ path and the oracle can share it without sharing any of the method.
 Problem data follow the dual-regularized LQR definition (Section "Dual-Regularized
 LQR", Definition 1): stage blocks Q_i (n x n), M_i (n x m), R_i (m x m),
 q_i, r_i, dynamics A_i (n x n), B_i (n x m), offsets c_0 .. c_N and the
-regularization Delta_i = delta * I.
+regularization Delta_i = delta * I, or a positive diagonal Delta_i per stage
+(`delta_diag`, (N+1, n); the definition allows any SPD Delta_i).
 
 Flat layout (per instance, instances packed one after another, float64):
 
@@ -22,6 +23,8 @@ Flat layout (per instance, instances packed one after another, float64):
     c : (N+1) * n         c[0] is the initial-state target c_0,
                           c[i+1] the offset of the dynamics of step i
     x : (N+1) * n,  u : N * m,  y : (N+1) * n      (solution)
+    delta_diag : (N+1) * n  (optional; laid out like x: the diagonal of Delta_i
+                 at i * n; instances without one contribute delta repeated)
 
 The element counts per instance are given by `counts(N, n, m)`; offsets are
 exclusive prefix sums of those counts over the batch.
@@ -29,7 +32,7 @@ exclusive prefix sums of those counts over the batch.
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, List, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -65,6 +68,7 @@ class Instance:
     r: np.ndarray  # (N, m)
     c: np.ndarray  # (N+1, n)
     indefinite: bool = False
+    delta_diag: Optional[np.ndarray] = None  # (N+1, n): Delta_i = diag(delta_diag[i]); None: delta I
 
 
 def _rng(seed: Sequence[int]) -> np.random.Generator:
@@ -80,7 +84,7 @@ def _haar_orthogonal(rng: np.random.Generator, N: int, n: int) -> np.ndarray:
 
 
 def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
-                  indefinite: bool = False) -> Instance:
+                  indefinite: bool = False, diag_spread: Optional[float] = None) -> Instance:
     """Draw one instance with the stage recipe of the small single-instance workload.
 
     Recipe (all draws independent per stage, in this order):
@@ -92,6 +96,9 @@ def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
       q_i ~ N(0,1) (i = 0..N),  r_i ~ N(0,1)
       c_0 ~ N(0,1),  c_1..c_N ~ N(0, 0.1^2)
     With indefinite=True every Q_i is shifted by -0.5 * lambda_max(Q_i) I.
+    With diag_spread = s, Delta_i is diagonal with entries delta * 10^U(-s, s),
+    drawn after everything else (the other data do not depend on s); they
+    stand for separate penalty parameters per constraint.
     """
     rng = _rng(seed)
     A = 0.95 * _haar_orthogonal(rng, N, n) + 0.05 * rng.standard_normal((N, n, n)) / np.sqrt(n)
@@ -112,7 +119,10 @@ def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
     # exact symmetry of the symmetric blocks
     Q = 0.5 * (Q + np.swapaxes(Q, 1, 2))
     R = 0.5 * (R + np.swapaxes(R, 1, 2))
-    return Instance(n, m, N, float(delta), Q, M, R, A, B, q, r, c, indefinite)
+    dd = None
+    if diag_spread is not None:
+        dd = float(delta) * 10.0 ** rng.uniform(-diag_spread, diag_spread, size=(N + 1, n))
+    return Instance(n, m, N, float(delta), Q, M, R, A, B, q, r, c, indefinite, dd)
 
 
 # ---------------------------------------------------------------- workloads
@@ -199,7 +209,16 @@ def pack(instances: List[Instance]) -> Packed:
         arrays[name] = np.concatenate(
             [getattr(i, name).reshape(-1) for i in instances]).astype(np.float64)
         assert arrays[name].shape[0] == offs[name][-1]
+    if any(i.delta_diag is not None for i in instances):
+        arrays["delta_diag"] = _pack_diag(instances)
+        assert arrays["delta_diag"].shape[0] == offs["x"][-1]
     return Packed(N, n, m, delta, arrays, offs)
+
+
+def _pack_diag(instances: List[Instance]) -> np.ndarray:
+    return np.concatenate([
+        (i.delta_diag if i.delta_diag is not None else np.full((i.N + 1, i.n), i.delta)).reshape(-1)
+        for i in instances]).astype(np.float64)
 
 
 def unpack_solution(p: Packed, x: np.ndarray, u: np.ndarray, y: np.ndarray):
@@ -241,7 +260,12 @@ def pack_parallel(specs, workers: int = 8) -> Packed:
     n = np.concatenate([r[1] for r in res])
     m = np.concatenate([r[2] for r in res])
     delta = np.concatenate([r[3] for r in res])
-    arrays = {k: np.concatenate([r[4][k] for r in res]) for k in ARRAYS_LHS + ARRAYS_RHS}
+    keys = list(ARRAYS_LHS + ARRAYS_RHS)
+    if any("delta_diag" in r[4] for r in res):
+        if not all("delta_diag" in r[4] for r in res):
+            raise ValueError("pack_parallel: mix of chunks with and without delta_diag")
+        keys.append("delta_diag")
+    arrays = {k: np.concatenate([r[4][k] for r in res]) for k in keys}
     return Packed(N, n, m, delta, arrays, layout_offsets(N, n, m))
 
 
