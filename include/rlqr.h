@@ -8,7 +8,10 @@
  *     [[P, C^T], [C, -Delta]] [x; y] = -[s; c]       (eq. primal-dual-linear-system)
  *
  * with the stagewise blocks of eq. optimal-control-specialization and
- * Delta_i = delta * I for i = 0..N. The call split follows the paper's
+ * Delta_i = delta * I for i = 0..N, or a positive diagonal Delta_i per stage
+ * (rlqr_lhs.delta_diag; the definition allows any SPD Delta_i, and the
+ * paper's per-constraint penalties Delta_C, Delta_G give diagonal ones).
+ * The call split follows the paper's
  * factorization / solve / residual callbacks (Section "Software
  * Contributions"): one factorization serves any number of right-hand sides.
  *
@@ -22,6 +25,7 @@
  *     Q (N+1)*n*n   M N*n*m   R N*m*m   A N*n*n   B N*n*m
  *     q (N+1)*n     r N*m     c (N+1)*n   (c[0] = c_0, c[i+1] offset of step i)
  *     x (N+1)*n     u N*m     y (N+1)*n
+ *     delta_diag (N+1)*n  (optional; like x: Delta_i's diagonal at i*n)
  *     residual  N*(n+m) + n + (N+1)*n  (order given at rlqr_residual)
  * Instance b's block of array k starts at the exclusive prefix sum of the
  * per-instance element counts; rlqr_layout_offsets returns those offsets.
@@ -107,6 +111,16 @@ typedef struct {
 typedef struct {        /* left-hand side: stage blocks and regularization       */
   const double *Q, *M, *R, *A, *B;
   const double *delta;  /* [B] delta_b >= 0; Delta_i = delta_b * I, i = 0..N    */
+  /* Optional per-stage diagonal regularization (NULL: Delta_i = delta_b I).
+   * Laid out like x: instance b's Delta_i = diag(delta_diag[off_x(b) + i n_b
+   * .. + n_b - 1]), i = 0..N_b. Every entry must be > 0 and finite (Delta_i
+   * SPD, Definition "dual-regularized LQR"); other values give undefined
+   * (non-finite) results. When set, delta is not read and may be NULL. The
+   * state pivots are then those of the symmetric representative S_hat_i =
+   * I + Delta_i^{1/2} P_i Delta_i^{1/2} (Section "Inertia Certification"),
+   * which is similar to I + Delta_i P_i. Sequential modes only: the scan
+   * modes return RLQR_E_UNSUPPORTED from rlqr_factor. */
+  const double *delta_diag;
 } rlqr_lhs;
 
 typedef struct { const double *q, *r, *c; } rlqr_rhs;   /* s = (q_0, r_0, ..., q_N), c */
@@ -164,9 +178,13 @@ rlqr_status rlqr_layout_offsets(const rlqr_handle *h, int32_t array, int64_t *of
  * P_{k+1} S_hat_{k+1}^{-1}, G_k = R_k + B_k^T W B_k, H_k = B_k^T W A_k + M_k^T,
  * K_k = -G_k^{-1} H_k, P_k = A_k^T W A_k + Q_k + H_k^T K_k, P_N = Q_N) for every
  * instance, recording the pivots of S_hat_i (i = 0..N) and G_i (i = 0..N-1)
- * for the certificate. The lhs arrays must stay valid and unchanged until the
- * last rlqr_solve/rlqr_residual on this factorization, which re-read them.
- * Errors: RLQR_E_INVALID (NULL pointer), RLQR_E_HIP.
+ * for the certificate. With lhs->delta_diag (Delta_i = D_i^2 diagonal) the
+ * swept matrix is S_hat_{k+1} = I + D P_{k+1} D and W_{k+1} = P_{k+1} D
+ * S_hat_{k+1}^{-1} D^{-1} = P_{k+1} (I + Delta_{k+1} P_{k+1})^{-1}. The lhs
+ * arrays must stay valid and unchanged until the last rlqr_solve/rlqr_residual
+ * on this factorization, which re-read them.
+ * Errors: RLQR_E_INVALID (NULL pointer), RLQR_E_UNSUPPORTED (delta_diag in a
+ * scan mode), RLQR_E_HIP.
  */
 rlqr_status rlqr_factor(rlqr_handle *h, const rlqr_lhs *lhs, rlqr_stream st);
 

@@ -208,7 +208,7 @@ __global__ void k_replicate(ReplicateArgs a) {
   const int b = v % a.B;
   a.vinfo[v] = a.info[b];
   a.vflag64[v] = a.flag64[b];
-  a.vdelta[v] = a.delta[b];
+  a.vdelta[v] = a.delta ? a.delta[b] : 0.0;  // NULL with a per-stage diagonal
 }
 
 // The virtual handle of rlqr_handle::mv for R right-hand sides (sequential
@@ -418,6 +418,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     mt.oA = h->off[RLQR_ARR_A][b]; mt.oB = h->off[RLQR_ARR_B][b];
     mt.oq = h->off[RLQR_ARR_q][b]; mt.or_ = h->off[RLQR_ARR_r][b]; mt.oc = h->off[RLQR_ARR_c][b];
     mt.ox = h->off[RLQR_ARR_x][b]; mt.ou = h->off[RLQR_ARR_u][b]; mt.oy = h->off[RLQR_ARR_y][b];
+    mt.od = mt.ox;
     mt.ores = h->off[RLQR_ARR_RES][b];
     mt.ows = ws_elems;
     mt.opk = pk_elems;
@@ -701,6 +702,7 @@ static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const in
     FactorArgs a{};
     a.meta = h->meta; a.segs = lists[c].d; a.run = run;
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
+    a.dd = h->lhs.delta_diag;
     a.ws = ws; a.stats = stats;
     if (rhs && c == TILE_16) {
       a.q = rhs->q; a.r = rhs->r; a.c = rhs->c; a.pk = h->pk;
@@ -749,7 +751,9 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
 
 static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_rhs* rhs, hipStream_t st) {
   if (!h || !lhs) return RLQR_E_INVALID;
-  if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || !lhs->delta)) return RLQR_E_INVALID;
+  if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || (!lhs->delta && !lhs->delta_diag)))
+    return RLQR_E_INVALID;
+  if (lhs->delta_diag && is_scan(h->mode)) return RLQR_E_UNSUPPORTED;
   if (rhs && h->B > 0 && (!rhs->q || !rhs->r || !rhs->c)) return RLQR_E_INVALID;
   h->lhs = *lhs;
   h->factored = true;
@@ -807,6 +811,7 @@ static SolveArgs solve_args(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, 
   SolveArgs a{};
   a.meta = h->meta; a.run = run;
   a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
+  a.dd = h->lhs.delta_diag;
   a.ws = fp32 ? h->ws32 : h->ws64;
   a.info = h->info;
   a.q = rhs->q; a.r = rhs->r; a.c = rhs->c;
@@ -823,6 +828,7 @@ static ResidualArgs residual_args(rlqr_handle* h, const rlqr_rhs* rhs, const rlq
   a.batch = h->B; a.meta = h->meta; a.chunks = h->chunks; a.nchunks = h->nchunks;
   a.run = run; a.skip = nullptr; a.info = h->info;
   a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
+  a.dd = h->lhs.delta_diag;
   a.q = rhs->q; a.r = rhs->r; a.c = rhs->c;
   a.x = z->x; a.u = z->u; a.y = z->y;
   a.res = res; a.resmax = h->resmax; a.bmax = h->bmax;
@@ -1066,8 +1072,8 @@ extern "C" rlqr_status rlqr_graph_capture(rlqr_handle* h, const rlqr_lhs* lhs, c
                                           double rel_tol, int32_t max_refine, int32_t* inst_status,
                                           double* inst_relres, rlqr_stream stv) {
   if (!h || !lhs || !rhs || !out || !stv) return RLQR_E_INVALID;
-  if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || !lhs->delta || !rhs->q || !rhs->r ||
-                   !rhs->c || !out->x || !out->u || !out->y))
+  if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || (!lhs->delta && !lhs->delta_diag) ||
+                   !rhs->q || !rhs->r || !rhs->c || !out->x || !out->u || !out->y))
     return RLQR_E_INVALID;
   if (!(rel_tol >= 0.0) || max_refine < 0) return RLQR_E_INVALID;
   hipStream_t st = (hipStream_t)stv;

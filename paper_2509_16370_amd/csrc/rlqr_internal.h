@@ -11,11 +11,12 @@ namespace rlqr {
 // (ows in workspace elements, opk in float64 elements of the p/k scratch).
 // Scan mode only: nseg stage segments, ovec the first boundary vector (n
 // float64 per segment), opsi the first transfer matrix pair (2 n^2 float64
-// per segment).
+// per segment). od: offset of the instance's per-stage diagonals Delta_i
+// (laid out like x; a stacked right-hand side keeps its base instance's).
 struct InstMeta {
   int32_t N, n, m, nseg;
   int32_t chunk, pad;  // scan mode: stages per segment and per scan chunk
-  int64_t oQ, oM, oR, oA, oB, oq, or_, oc, ox, ou, oy, ores, ows, opk, ovec, opsi;
+  int64_t oQ, oM, oR, oA, oB, oq, or_, oc, ox, ou, oy, ores, ows, opk, ovec, opsi, od;
 };
 
 // Certificate bookkeeping written by the factor kernels.
@@ -46,6 +47,7 @@ struct FactorArgs {
   const SegDesc* segs;    // block -> segment
   const int32_t* run;     // if set, only instances with run[b] != 0 are touched
   const double *Q, *M, *R, *A, *B, *delta;
+  const double* dd;       // if set: per-stage diagonal Delta_i (at InstMeta::od), delta unused
   void* ws;
   SegStats* stats;        // one per segment (indexed like segs)
   // optional right-hand side (one-wavefront kernels, whole instances): the
@@ -115,6 +117,7 @@ struct SolveArgs {
   double *plo, *xhi;      // segment boundary vectors (n per segment, at InstMeta::ovec)
   const int32_t* run;     // if set, only instances with run[b] != 0 are touched
   const double *Q, *M, *R, *A, *B, *delta;
+  const double* dd;       // if set: per-stage diagonal Delta_i (at InstMeta::od), delta unused
   const void* ws;
   const FactorInfo* info;
   const double *q, *r, *c;  // the original right-hand side
@@ -146,6 +149,7 @@ struct ResidualArgs {
   const int32_t* skip;       // if set, instances with skip[b] != 0 are left alone
   const FactorInfo* info;
   const double *Q, *M, *R, *A, *B, *delta;
+  const double* dd;          // if set: per-stage diagonal Delta_i (at InstMeta::od), delta unused
   const double *q, *r, *c;
   const double *x, *u, *y;
   double* res;

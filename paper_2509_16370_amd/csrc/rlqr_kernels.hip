@@ -239,17 +239,21 @@ __device__ __forceinline__ double ld_or0(const double* __restrict__ v, int64_t i
 // from the tiles Zp = Z_{k+1} (P_{k+1}), Xn = X_{k+1} = -S_hat_{k+1}^{-1},
 // Zk = Z_k and ab = [A_k B_k] (all in the register layout trow<TG>); p holds
 // p_{k+1} on entry and p_k on exit (x lanes), the return value is k_k (u lanes).
-template <typename TG>
+// DG (diagonal Delta_{k+1} = D^2): g = (I + P Delta)^{-1} v = D^{-1} S_hat^{-1} D v
+// with S_hat = I + D P D; sd, isd are D and D^{-1} of the lane's column.
+template <typename TG, bool DG = false>
 __device__ __forceinline__ double bwd_vec_step(const double (&Zp)[4], const double (&Xn)[4], const double (&ab)[4],
                                                const double (&Zk)[4], double& p, double ck, double qk, double rk,
-                                               double (*sv)[16], bool xr, bool ur, bool own, int col, int lane) {
+                                               double (*sv)[16], bool xr, bool ur, bool own, int col, int lane,
+                                               double sd = 1.0, double isd = 1.0) {
   wave_sync();
   if (own) sv[0][col] = ck;
   wave_sync();
   const double vv = xr ? p + tmatvec<TG>(Zp, sv[0], lane) : 0.0;  // p + P_{k+1} c_{k+1}
-  if (own) sv[1][col] = vv;
+  if (own) sv[1][col] = DG ? sd * vv : vv;
   wave_sync();
-  const double g = -tmatvec<TG>(Xn, sv[1], lane);                  // S_hat^{-1} v
+  const double g = DG ? -isd * tmatvec<TG>(Xn, sv[1], lane)        // D^{-1} S_hat^{-1} D v
+                      : -tmatvec<TG>(Xn, sv[1], lane);             // S_hat^{-1} v
   if (own) sv[0][col] = xr ? g : 0.0;
   wave_sync();
   const double abg = tmatvec<TG>(ab, sv[0], lane);                 // [A^T g; B^T g]
@@ -331,7 +335,11 @@ __device__ __forceinline__ typename AccT<T>::type gemm_abt_t(const double* stg, 
 
 // SN, SM > 0: stage shape fixed at compile time (every instance of the launch
 // has n = SN, m = SM); 0: taken from the instance.
-template <typename TG, int SN, int SM>
+// DG: per-stage diagonal Delta_i = D_i^2 (a.dd): the swept matrix is the
+// symmetric representative S_hat = I + D P D of Section "Inertia
+// Certification", and since I + Delta P = D S_hat D^{-1},
+// W = P (I + Delta P)^{-1} = -P (D X D^{-1}) with X = -S_hat^{-1}.
+template <typename TG, int SN, int SM, bool DG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_factor16(FactorArgs a) {
   constexpr bool CP = sizeof(TG) == 8;  // compact tiles in float64 (TileLayout)
   const SegDesc sd = a.segs[blockIdx.x];
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
   const int klo = sd.lo, khi = sd.hi;
-  const double delta = a.delta[b];
+  const double delta = DG ? 0.0 : a.delta[b];
   const double* __restrict__ Qg = a.Q + mt.oQ;
   const double* __restrict__ Mg = a.M + mt.oM;
   const double* __restrict__ Rg = a.R + mt.oR;
@@ -382,6 +390,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     pv = ld_or0(qg, (int64_t)N * n + col, xr);
     if (own && xr) pg[(int64_t)N * n + col] = pv;
   }
+  // DG: the lane's diagonal entry of Delta_{k+1}, loaded one stage ahead, and
+  // D of every row of the stage in LDS (0 outside the state block)
+  const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
+  __shared__ double sdl[16];
+  double dnx = DG ? ld_or0(ddg, (int64_t)khi * n + col, xr) : 0.0;
+  auto diag_scales = [&](double dcur, double& sdc, double& isdc, double (&sdr)[4]) {
+    sdc = xr ? sqrt(dcur) : 0.0;
+    isdc = xr ? 1.0 / sdc : 0.0;
+    wave_sync();
+    if (own) sdl[col] = sdc;
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sdr[v] = sdl[trow<TG>(grp, v)];
+  };
 
   // P_hi: Q_N at the top of the horizon, else the boundary tile of the scan
   double P[4];
@@ -423,10 +445,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       qk = ld_or0(qg, (int64_t)k * n + col, xr);
       rk = ld_or0(rg, (int64_t)k * m + (col - n), ur);
     }
-    // X = I + delta P_{k+1}; sweep -> -S_hat_{k+1}^{-1}  (no stage data needed)
+    // X = I + delta P_{k+1} (DG: I + D P D); sweep -> -S_hat_{k+1}^{-1}  (no stage data needed)
+    double sdc = 1.0, isdc = 1.0, sdr[4] = {1.0, 1.0, 1.0, 1.0};
+    if constexpr (DG) {
+      const double dcur = dnx;
+      dnx = ld_or0(ddg, (int64_t)k * n + col, xr);
+      diag_scales(dcur, sdc, isdc, sdr);
+    }
     double X[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
+    for (int v = 0; v < 4; ++v)
+      X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + (DG ? sdr[v] * sdc * P[v] : delta * P[v]);
     {
       const double sc = diag_scale<TG>(X, 0, n, lane_s);
       sweep16<TG>(X, 0, n, lane_s, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
@@ -437,13 +466,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       if (own) sv[0][col] = ck;
       wave_sync();
       const double vv = xr ? pv + tmatvec_r<TG>(P, sv[0], lane) : 0.0;
-      if (own) sv[1][col] = vv;
+      if (own) sv[1][col] = DG ? sdc * vv : vv;
       wave_sync();
-      const double g = -tmatvec_r<TG>(X, sv[1], lane);
+      const double g = DG ? -isdc * tmatvec_r<TG>(X, sv[1], lane) : -tmatvec_r<TG>(X, sv[1], lane);
       if (own) sv[0][col] = xr ? g : 0.0;
     }
     tile_to_lds<TG>(sP, P, lane);
-    tile_to_lds<TG>(sX, X, lane);
+    if constexpr (DG) {  // the product takes D X D^{-1}; the stored tile stays X
+      double Xs[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xs[v] = sdr[v] * X[v] * isdc;
+      tile_to_lds<TG>(sX, Xs, lane);
+    } else {
+      tile_to_lds<TG>(sX, X, lane);
+    }
     wave_sync();
     // W = -P X, symmetrized (sD overlays sP)
     double W[4];
@@ -519,9 +555,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
   // S_hat_0
   if (klo == 0) {
+    double sdc = 1.0, isdc = 1.0, sdr[4] = {1.0, 1.0, 1.0, 1.0};
+    if constexpr (DG) diag_scales(dnx, sdc, isdc, sdr);
     double X[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + delta * P[v];
+    for (int v = 0; v < 4; ++v)
+      X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + (DG ? sdr[v] * sdc * P[v] : delta * P[v]);
     const double sc = diag_scale<TG>(X, 0, n, lane);
     sweep16<TG>(X, 0, n, lane, ps, 0, 1.0e3 * n * eps * sc, sc);
     tile_store_as<TG, CP>(ws + tl.x(0), X, lane, n);
@@ -545,7 +584,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // z. The tiles and stage blocks of the next step are loaded one step ahead
 // so that the dependent chain does not wait on memory.
 // ACC: correction pass (right-hand side = a.corr, z += dz); otherwise a.corr is NULL
-template <typename TG, int SN, int SM, bool ACC>
+// DG: per-stage diagonal Delta_i = D_i^2 (a.dd); (I + Delta P)^{-1} = D S_hat^{-1} D^{-1}
+// and (I + P Delta)^{-1} = D^{-1} S_hat^{-1} D with the stored X = -S_hat^{-1}.
+template <typename TG, int SN, int SM, bool ACC, bool DG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_solve16(SolveArgs a) {
   constexpr bool CP = sizeof(TG) == 8;  // compact tiles in float64 (TileLayout)
   const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
@@ -553,7 +594,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
-  const double delta = a.delta[b];
+  const double delta = DG ? 0.0 : a.delta[b];
+  const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
   const double* __restrict__ Ag = a.A + mt.oA;
   const double* __restrict__ Bg = a.B + mt.oB;
   const TG* __restrict__ ws = reinterpret_cast<const TG*>(a.ws) + mt.ows;
@@ -609,11 +651,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       for (int v = 0; v < 4; ++v)
         ab[v] = ab_elem(Ag + (int64_t)(N - 1) * n * n, Bg + (int64_t)(N - 1) * n * m, n, m, trow<TG>(grp, v), col);
     }
-    double ck = 0.0, qk = 0.0, rk = 0.0;
+    double ck = 0.0, qk = 0.0, rk = 0.0, dk = 0.0;
     if (N > 0) {
       ck = ld_or0(cb, (int64_t)N * n + col, xr);
       qk = ld_or0(qb, (int64_t)(N - 1) * qs + col, xr);
       rk = ld_or0(rb, (int64_t)(N - 1) * rs + (col - n), ur);
+      if (DG) dk = ld_or0(ddg, (int64_t)N * n + col, xr);
     }
     for (int k = N - 1; k >= 0; --k) {
       if constexpr (CP) asm volatile("" : "+v"(pz), "+v"(px));
@@ -628,7 +671,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const double ck1 = ld_or0(cb, (int64_t)(k1 + 1) * n + col, xr);
       const double qk1 = ld_or0(qb, (int64_t)k1 * qs + col, xr);
       const double rk1 = ld_or0(rb, (int64_t)k1 * rs + (col - n), ur);
-      const double zh = bwd_vec_step<TG>(Zp, Xn, ab, Zk, p, ck, qk, rk, sv, xr, ur, own, col, lane);
+      const double dk1 = DG ? ld_or0(ddg, (int64_t)(k1 + 1) * n + col, xr) : 0.0;
+      double sdk = 1.0, isdk = 1.0;
+      if constexpr (DG) {
+        sdk = xr ? sqrt(dk) : 0.0;
+        isdk = xr ? 1.0 / sdk : 0.0;
+      }
+      const double zh = bwd_vec_step<TG, DG>(Zp, Xn, ab, Zk, p, ck, qk, rk, sv, xr, ur, own, col, lane, sdk, isdk);
       if (own) {
         if (xr) pg[(int64_t)k * n + col] = p;
         if (ur) kg[(int64_t)k * m + (col - n)] = zh;
@@ -643,6 +692,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       ck = ck1;
       qk = qk1;
       rk = rk1;
+      dk = dk1;
     }
   }
   __syncthreads();  // p/k written by lanes 0..15 are read by all lanes below
@@ -687,6 +737,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   double rmax = 0.0, bmax = 0.0;
 
   // x_0, then z_0 = Z_0 x_0 (u_0 and y_0)
+  // DG: Delta_0's entry of the lane (d0) and Delta_{k+1}'s (dn, one step ahead)
+  const double d0 = DG ? ld_or0(ddg, col, xr) : delta;
   double x;
   {
     double X0[4];
@@ -694,9 +746,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double p0 = ld_or0(pg, col, xr);
     const double c00 = ld_or0(cb, col, xr);
     wave_sync();
-    if (own) sv[0][col] = xr ? c00 - delta * p0 : 0.0;
-    wave_sync();
-    x = xr ? -tmatvec<TG>(X0, sv[0], lane) : 0.0;
+    if constexpr (DG) {  // x_0 = D S_hat_0^{-1} D^{-1} (c_0 - Delta_0 p_0)
+      const double s0 = xr ? sqrt(d0) : 0.0;
+      if (own) sv[0][col] = xr ? (c00 - d0 * p0) / s0 : 0.0;
+      wave_sync();
+      x = xr ? -s0 * tmatvec<TG>(X0, sv[0], lane) : 0.0;
+    } else {
+      if (own) sv[0][col] = xr ? c00 - delta * p0 : 0.0;
+      wave_sync();
+      x = xr ? -tmatvec<TG>(X0, sv[0], lane) : 0.0;
+    }
   }
   tile_load_pk<CP>(Zk, ws + tl.z(0), lane, pz);
   double zx;  // Z_k x_k: [P_k x_k; -K_k x_k]
@@ -717,7 +776,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double c0 = ld_or0(co, col, xr);
     const double xt = x + xold, yt = zx + pk + yold;
     if (fuse && own && xr) {
-      const double r0 = c0 - delta * yt - xt;
+      const double r0 = c0 - d0 * yt - xt;
       resg[(int64_t)N * (n + m) + n + col] = r0;
       rmax = fmax(rmax, fabs(r0));
       bmax = fmax(bmax, fabs(c0));
@@ -731,6 +790,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   double qok = N > 0 ? ld_or0(qo, col, xr) : 0.0;
   double rok = N > 0 ? ld_or0(ro, col - n, ur) : 0.0;
   double con = N > 0 ? ld_or0(co, (int64_t)n + col, xr) : 0.0;
+  double dn = (DG && N > 0) ? ld_or0(ddg, (int64_t)n + col, xr) : delta;
 
   for (int k = 0; k < N; ++k) {
     if constexpr (CP) asm volatile("" : "+v"(pz), "+v"(px));
@@ -758,6 +818,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double qok1 = ld_or0(qo, (int64_t)k1 * n + col, xr);
     const double rok1 = ld_or0(ro, (int64_t)k1 * m + (col - n), ur);
     const double con1 = ld_or0(co, (int64_t)(k1 + 1) * n + col, xr);
+    const double dn1 = DG ? ld_or0(ddg, (int64_t)(k1 + 1) * n + col, xr) : delta;
 
     // u_k, y_k from z_k; write the totals
     const double uk = ur ? kk - zx : 0.0;
@@ -783,9 +844,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       hz += stgc[ipk[v] & 1023] * sz[0][j];
     }
     w = group_sum(w);
-    if (own) sv[0][col] = xr ? w + cn - delta * pn : 0.0;
-    wave_sync();
-    x = xr ? -tmatvec<TG>(Xn, sv[0], lane) : 0.0;  // x_{k+1} of this pass
+    if constexpr (DG) {  // x_{k+1} = D S_hat^{-1} D^{-1} (w + c - Delta p)
+      const double s1 = xr ? sqrt(dn) : 0.0;
+      if (own) sv[0][col] = xr ? (w + cn - dn * pn) / s1 : 0.0;
+      wave_sync();
+      x = xr ? -s1 * tmatvec<TG>(Xn, sv[0], lane) : 0.0;
+    } else {
+      if (own) sv[0][col] = xr ? w + cn - delta * pn : 0.0;
+      wave_sync();
+      x = xr ? -tmatvec<TG>(Xn, sv[0], lane) : 0.0;  // x_{k+1} of this pass
+    }
     wave_sync();
     if (own) sv[1][col] = xr ? x : 0.0;
     wave_sync();
@@ -804,7 +872,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const int64_t base = (int64_t)k * (n + m);
         if (xr) {
           const double rx = hz + g + qok - yt;
-          const double rd = wt + con - delta * y1t - x1t;
+          const double rd = wt + con - dn * y1t - x1t;
           resg[base + col] = rx;
           resg[(int64_t)N * (n + m) + n + (int64_t)(k + 1) * n + col] = rd;
           rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
@@ -824,7 +892,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       Zk[v] = Zk1[v];
       Xn[v] = Xn1[v];
     }
-    pk = pn; kk = kk1; pn = pn1; cn = cn1;
+    pk = pn; kk = kk1; pn = pn1; cn = cn1; dn = dn1;
     xold = xoldn; yold = yoldn; uold = uold1; xoldn = xoldn1; yoldn = yoldn1;
     qok = qok1; rok = rok1; con = con1;
   }
@@ -885,10 +953,12 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
 // current one is reduced; larger stages use one lane per row.
 struct ResVec {
   double xi, ui, yi, yn, xn, qi, ri, cn;
+  double dn;  // the lane's entry of the per-stage diagonal Delta_{i+1} (unused with delta I)
 };
 
+// dd: the per-stage diagonals (a.dd) or NULL (delta I); likewise below
 __device__ __forceinline__ void res_load_vec(const ResidualArgs& a, const InstMeta& mt, int n, int m, int i, int lane,
-                                             ResVec& o) {
+                                             double delta, const double* dd, ResVec& o) {
   const int col = lane & 15;
   const bool xr = col < n, ur = col >= n && col < n + m;
   o.xi = ld_or0(a.x + mt.ox, (int64_t)i * n + col, xr);
@@ -899,6 +969,7 @@ __device__ __forceinline__ void res_load_vec(const ResidualArgs& a, const InstMe
   o.qi = ld_or0(a.q + mt.oq, (int64_t)i * n + col, xr);
   o.ri = ld_or0(a.r + mt.or_, (int64_t)i * m + (col - n), ur);
   o.cn = ld_or0(a.c + mt.oc, (int64_t)(i + 1) * n + col, xr);
+  o.dn = dd ? ld_or0(dd + mt.od, (int64_t)(i + 1) * n + col, xr) : 0.0;
 }
 
 __device__ __forceinline__ void res_stage_dma(const ResidualArgs& a, const InstMeta& mt, int n, int m, int i,
@@ -911,7 +982,7 @@ __device__ __forceinline__ void res_stage_dma(const ResidualArgs& a, const InstM
 // Residual rows of stage i < N from the staged blocks (Hessian, [A B], [A B]^T
 // read at the per-lane staging indices) and the stage vectors.
 __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMeta& mt, int n, int m, double delta,
-                                            int i, const double* stg, const int (&iH)[4], const int (&iAB)[4],
+                                            const double* dd, int i, const double* stg, const int (&iH)[4], const int (&iAB)[4],
                                             const int (&iABT)[4], const ResVec& o, double* sv, double& rmax,
                                             double& bmax, int lane) {
   const int N = mt.N;
@@ -939,7 +1010,7 @@ __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMet
     const int64_t base = (int64_t)i * (n + m);
     if (xr) {
       const double rx = h + g + o.qi - o.yi;
-      const double rd = w + o.cn - delta * o.yn - o.xn;
+      const double rd = w + o.cn - (dd ? o.dn : delta) * o.yn - o.xn;
       if (res) {
         res[base + col] = rx;
         res[(int64_t)N * (n + m) + 2 * n + (int64_t)i * n + col] = rd;
@@ -958,7 +1029,7 @@ __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMet
 
 // slot N of an instance with n + m <= 16: terminal row and c_0 row
 __device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMeta& mt, int n, int m, double delta,
-                                             double* sv, double& rmax, double& bmax, int lane) {
+                                             const double* dd, double* sv, double& rmax, double& bmax, int lane) {
   const int N = mt.N;
   const int col = lane & 15, grp = lane >> 4;
   const bool xr = col < n, own = grp == 0;
@@ -978,6 +1049,7 @@ __device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMe
   const double c0 = ld_or0(c, col, xr);
   const double x0 = ld_or0(x, col, xr);
   const double y0 = ld_or0(y, col, xr);
+  const double d0 = dd ? ld_or0(dd + mt.od, col, xr) : delta;
   wave_sync();
   if (own) sv[col] = xr ? xN : 0.0;
   wave_sync();
@@ -987,7 +1059,7 @@ __device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMe
   h = group_sum(h);
   if (own && xr) {
     const double rt = h + qN - yN;
-    const double ri = c0 - delta * y0 - x0;
+    const double ri = c0 - d0 * y0 - x0;
     if (res) {
       res[(int64_t)N * (n + m) + col] = rt;
       res[(int64_t)N * (n + m) + n + col] = ri;
@@ -998,10 +1070,11 @@ __device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMe
 }
 
 __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const InstMeta& mt, int b, int i,
-                                                   double& rmax, double& bmax, int lane) {
+                                                   const double* ddall, double& rmax, double& bmax, int lane) {
   const int N = mt.N, n = mt.n, m = mt.m;
   const int nn = n * n, nm = n * m, mm = m * m;
-  const double delta = a.delta[b];
+  const double delta = ddall ? 0.0 : a.delta[b];
+  const double* dd = ddall ? ddall + mt.od : nullptr;  // per-stage diagonal Delta_i, laid out like x
   const double* q = a.q + mt.oq; const double* r = a.r + mt.or_; const double* c = a.c + mt.oc;
   const double* x = a.x + mt.ox; const double* u = a.u + mt.ou; const double* y = a.y + mt.oy;
   double* res = a.res ? a.res + mt.ores : nullptr;
@@ -1035,7 +1108,7 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
         for (int j = 0; j < n; ++j) s = fma(A[a0 * n + j], xi[j], s);
         for (int j = 0; j < m; ++j) s = fma(B[a0 * m + j], ui[j], s);
         bv = c[(int64_t)(i + 1) * n + a0];
-        s += bv - delta * yn[a0] - x[(int64_t)(i + 1) * n + a0];
+        s += bv - (dd ? dd[(int64_t)(i + 1) * n + a0] : delta) * yn[a0] - x[(int64_t)(i + 1) * n + a0];
         out = (int64_t)N * (n + m) + 2 * n + (int64_t)i * n + a0;
       }
       if (res) res[out] = s;
@@ -1056,7 +1129,7 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
       } else {
         const int a0 = row - n;
         bv = c[a0];
-        s = bv - delta * y[a0] - x[a0];
+        s = bv - (dd ? dd[a0] : delta) * y[a0] - x[a0];
         out = (int64_t)N * (n + m) + n + a0;
       }
       if (res) res[out] = s;
@@ -1067,8 +1140,10 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
 }
 
 // SN, SM > 0: every instance of the batch has n = SN, m = SM (n + m <= 16).
-template <int SN, int SM>
+// DG: per-stage diagonal Delta_i (a.dd) in the dual rows.
+template <int SN, int SM, bool DG>
 __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
+  const double* dd = DG ? a.dd : nullptr;
   __shared__ double sv[32];
   // two distinct staging arrays: a direct global-to-LDS copy into one never
   // aliases the reads of the other, so no wait is inserted before the reads
@@ -1083,7 +1158,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
     if (a.info && a.info[b].singular) continue;
     const InstMeta mt = a.meta[b];
     const int n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
-    const double delta = a.delta[b];
+    const double delta = DG ? 0.0 : a.delta[b];
     double rmax = 0.0, bmax = 0.0;
     if (n + m <= 16) {
       int iH[4], iAB[4], iABT[4];
@@ -1105,30 +1180,30 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
       ResVec v0, v1;
       if (ch.i0 < iend) {
         res_stage_dma(a, mt, n, m, ch.i0, stgA, lane);
-        res_load_vec(a, mt, n, m, ch.i0, lane, v0);
+        res_load_vec(a, mt, n, m, ch.i0, lane, delta, dd, v0);
       }
       for (int i = ch.i0; i < iend; i += 2) {
         wait_vmem();
         wave_sync();
         if (i + 1 < iend) {
           res_stage_dma(a, mt, n, m, i + 1, stgB, lane);
-          res_load_vec(a, mt, n, m, i + 1, lane, v1);
+          res_load_vec(a, mt, n, m, i + 1, lane, delta, dd, v1);
         }
-        res_compute(a, mt, n, m, delta, i, stgA, iH, iAB, iABT, v0, sv, rmax, bmax, lane);
+        res_compute(a, mt, n, m, delta, dd, i, stgA, iH, iAB, iABT, v0, sv, rmax, bmax, lane);
         if (i + 1 >= iend) break;
         __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgA returned before it is refilled
         wait_vmem();
         wave_sync();
         if (i + 2 < iend) {
           res_stage_dma(a, mt, n, m, i + 2, stgA, lane);
-          res_load_vec(a, mt, n, m, i + 2, lane, v0);
+          res_load_vec(a, mt, n, m, i + 2, lane, delta, dd, v0);
         }
-        res_compute(a, mt, n, m, delta, i + 1, stgB, iH, iAB, iABT, v1, sv, rmax, bmax, lane);
+        res_compute(a, mt, n, m, delta, dd, i + 1, stgB, iH, iAB, iABT, v1, sv, rmax, bmax, lane);
         __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgB returned before it is refilled
       }
-      if (ch.i1 > mt.N) res_terminal(a, mt, n, m, delta, sv, rmax, bmax, lane);
+      if (ch.i1 > mt.N) res_terminal(a, mt, n, m, delta, dd, sv, rmax, bmax, lane);
     } else {
-      for (int i = ch.i0; i < ch.i1; ++i) residual_slot_rows(a, mt, b, i, rmax, bmax, lane);
+      for (int i = ch.i0; i < ch.i1; ++i) residual_slot_rows(a, mt, b, i, dd, rmax, bmax, lane);
     }
     rmax = wave_max(rmax);
     bmax = wave_max(bmax);
@@ -1268,13 +1343,15 @@ __global__ void k_fill_i32(int32_t* p, int count, int32_t v) {
 
 // ------------------------------------------------------------------ launchers
 
-template <typename TG, int SN, int SM>
+template <typename TG, int SN, int SM, bool DG = false>
 static hipError_t launch_factor_t(const FactorArgs& a, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_factor16<TG, SN, SM>), dim3(nblocks), dim3(64), 0, st, a);
+  hipLaunchKernelGGL((k_factor16<TG, SN, SM, DG>), dim3(nblocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
+// a per-stage diagonal Delta_i takes the general-shape kernel
 template <typename TG>
 static hipError_t launch_factor_s(const FactorArgs& a, int nblocks, int shape, hipStream_t st) {
+  if (a.dd) return launch_factor_t<TG, 0, 0, true>(a, nblocks, st);
   switch (shape) {
     case SHAPE_4_1: return launch_factor_t<TG, 4, 1>(a, nblocks, st);
     case SHAPE_8_2: return launch_factor_t<TG, 8, 2>(a, nblocks, st);
@@ -1287,16 +1364,17 @@ hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, i
   return fp32_products ? launch_factor_s<float>(a, nblocks, shape, st) : launch_factor_s<double>(a, nblocks, shape, st);
 }
 
-template <typename TG, int SN, int SM>
+template <typename TG, int SN, int SM, bool DG = false>
 static hipError_t launch_solve_t(const SolveArgs& a, int nblocks, hipStream_t st) {
   if (a.corr)
-    hipLaunchKernelGGL((k_solve16<TG, SN, SM, true>), dim3(nblocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_solve16<TG, SN, SM, true, DG>), dim3(nblocks), dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_solve16<TG, SN, SM, false>), dim3(nblocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_solve16<TG, SN, SM, false, DG>), dim3(nblocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 template <typename TG>
 static hipError_t launch_solve_s(const SolveArgs& a, int nblocks, int shape, hipStream_t st) {
+  if (a.dd) return launch_solve_t<TG, 0, 0, true>(a, nblocks, st);
   switch (shape) {
     case SHAPE_4_1: return launch_solve_t<TG, 4, 1>(a, nblocks, st);
     case SHAPE_8_2: return launch_solve_t<TG, 8, 2>(a, nblocks, st);
@@ -1312,11 +1390,15 @@ hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, int sh
 hipError_t launch_residual(const ResidualArgs& a, int shape, hipStream_t st) {
   if (a.nchunks <= 0) return hipSuccess;
   const dim3 grid((unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20)));
+  if (a.dd) {
+    hipLaunchKernelGGL((k_residual<0, 0, true>), grid, dim3(64), 0, st, a);
+    return hipGetLastError();
+  }
   switch (shape) {
-    case SHAPE_4_1: hipLaunchKernelGGL((k_residual<4, 1>), grid, dim3(64), 0, st, a); break;
-    case SHAPE_8_2: hipLaunchKernelGGL((k_residual<8, 2>), grid, dim3(64), 0, st, a); break;
-    case SHAPE_12_4: hipLaunchKernelGGL((k_residual<12, 4>), grid, dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_residual<0, 0>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_4_1: hipLaunchKernelGGL((k_residual<4, 1, false>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_8_2: hipLaunchKernelGGL((k_residual<8, 2, false>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_12_4: hipLaunchKernelGGL((k_residual<12, 4, false>), grid, dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_residual<0, 0, false>), grid, dim3(64), 0, st, a); break;
   }
   return hipGetLastError();
 }

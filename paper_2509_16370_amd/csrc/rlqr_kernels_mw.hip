@@ -61,7 +61,8 @@ struct MwCfg {
   static constexpr int BLOCKS_PER_STAGE = TZ * TZ + TX * TX;
 };
 
-template <typename TG, int TX, int TZ, int NW>
+// DG: per-stage diagonal Delta_i (a.dd); the instantiations without it carry none of its code
+template <typename TG, int TX, int TZ, int NW, bool DG>
 __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   using C = MwCfg<TG, TX, TZ, NW>;
   constexpr int NX = C::NX, NZ = C::NZ, LDX = C::LDX, LDZ = C::LDZ;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
   const int klo = sd.lo, khi = sd.hi;
-  const double delta = a.delta[b];
+  const double delta = DG ? 0.0 : a.delta[b];
   const double* __restrict__ Qg = a.Q + mt.oQ;
   const double* __restrict__ Mg = a.M + mt.oM;
   const double* __restrict__ Rg = a.R + mt.oR;
@@ -122,6 +123,21 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   PivStats ps;
   ps.init();
   const double eps = 2.220446049250313e-16;
+
+  // per-stage diagonal Delta_{k+1} = D^2 (a.dd): the swept matrix is
+  // S_hat = I + D P D and the product takes D X D^{-1} (W = P (I + Delta P)^{-1});
+  // D and D^{-1} of the stage sit in LDS (0 outside the state block), the
+  // thread's entry of the next stage is loaded one stage ahead
+  const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
+  __shared__ double sdl[DG ? NX : 1], isdl[DG ? NX : 1];
+  double dpre = (DG && tid < n) ? ddg[(int64_t)khi * n + tid] : 0.0;
+  auto put_diag = [&](double d) {
+    if (tid < NX) {
+      const double sq = tid < n ? sqrt(d) : 0.0;
+      sdl[tid] = sq;
+      isdl[tid] = tid < n ? 1.0 / sq : 0.0;
+    }
+  };
 
   auto load_ab = [&](double (&o)[NAB], int k) {
     const double* A = Ag + (int64_t)k * n * n;
@@ -199,17 +215,23 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   }
 
   for (int k = khi - 1; k >= klo; --k) {
+    // (the previous stage's reads of sdl / isdl are behind its barriers)
+    if constexpr (DG) {
+      put_diag(dpre);
+      dpre = tid < n ? ddg[(int64_t)k * n + tid] : 0.0;
+    }
     __syncthreads();
     store_ab(ab);
     if (k > klo) load_ab(ab, k - 1);  // the next stage's [A B] (its Hessian after its last use below)
-    // X = I + delta P_{k+1}, swept -> -S_hat^{-1}
+    // X = I + delta P_{k+1} (per-stage diagonal: I + D P D), swept -> -S_hat^{-1}
     double X[CX][4];
 #pragma unroll
     for (int t = 0; t < CX; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
-        X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + delta * P[t][v];
+        const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
+        X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
     {
       const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
@@ -227,7 +249,17 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     for (int t = 0; t < CX; ++t)
       if (xo[t]) {
         blk_to_lds<TG>(sP, LDX, xi[t], xj[t], P[t], lane);
-        blk_to_lds<TG>(sX, LDX, xi[t], xj[t], X[t], lane);
+        if constexpr (DG) {  // the product takes D X D^{-1}; the stored tile stays X
+          double Xs[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+            Xs[v] = sdl[r] * X[t][v] * isdl[c];
+          }
+          blk_to_lds<TG>(sX, LDX, xi[t], xj[t], Xs, lane);
+        } else {
+          blk_to_lds<TG>(sX, LDX, xi[t], xj[t], X[t], lane);
+        }
       }
     __syncthreads();
     // W = -P X, symmetrized through sD (sD overlaps sP/sX: barrier between)
@@ -316,13 +348,19 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   }
   // S_hat_0
   if (klo == 0) {
+    if constexpr (DG) {
+      __syncthreads();
+      put_diag(dpre);
+      __syncthreads();
+    }
     double X[CX][4];
 #pragma unroll
     for (int t = 0; t < CX; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
-        X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + delta * P[t][v];
+        const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
+        X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
     const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
     sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
@@ -384,7 +422,7 @@ __device__ __forceinline__ void tmatvec_mw(const double (&X)[Cn][4], const int (
 //            x_hi -> xhi
 //   phase 3: forward from the true x_lo (the previous segment's xhi), x, u, y
 //            written (x_N, y_N by the last segment)
-template <typename TG, int TX, int TZ, int NW, bool SEG>
+template <typename TG, int TX, int TZ, int NW, bool SEG, bool DG = false>
 __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   using C = MwCfg<TG, TX, TZ, NW>;
   constexpr int NZ = C::NZ, CX = C::CX, CZ = C::CZ, CT = C::CT;
@@ -400,7 +438,10 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   const int phase = SEG ? a.phase : 0;
   const bool do_bwd = !SEG || phase <= 2, do_fwd = !SEG || phase >= 2;
   const bool write_pk = !SEG || phase == 2, write_z = !SEG || phase == 3;
-  const double delta = a.delta[b];
+  const double delta = DG ? 0.0 : a.delta[b];
+  // DG: per-stage diagonal Delta_i = D_i^2 (a.dd, laid out like x): (I + P Delta)^{-1}
+  // = D^{-1} S_hat^{-1} D and (I + Delta P)^{-1} = D S_hat^{-1} D^{-1}
+  const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
   const double* __restrict__ Ag = a.A + mt.oA;
   const double* __restrict__ Bg = a.B + mt.oB;
   const TG* __restrict__ ws = reinterpret_cast<const TG*>(a.ws) + mt.ows;
@@ -497,12 +538,13 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     load_tile(Zp, ztile(hi), zo, CZ);
     // step k's operands, loaded one step ahead
     double Zk[CZ][4], Xn[CX][4], AB[CT][4];
-    double ck = 0.0, qk = 0.0, rk = 0.0;
+    double ck = 0.0, qk = 0.0, rk = 0.0, dk = 0.0;
     if (PF && hi > lo) {
       load_tile(Zk, ztile(hi - 1), zo, CZ);
       load_tile(Xn, xtile(hi), xo, CX);
       load_ab(AB, hi - 1, false);
       ck = xr ? cb[(int64_t)hi * n + tid] : 0.0;
+      dk = (DG && xr) ? ddg[(int64_t)hi * n + tid] : 0.0;
       qk = xr ? qb[(int64_t)(hi - 1) * qs + tid] : 0.0;
       rk = ur ? rb[(int64_t)(hi - 1) * rs + (tid - n)] : 0.0;
     }
@@ -511,12 +553,13 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       // classes, whose register budget the second set would exceed) this step's
       const int k1 = k > lo ? k - 1 : k;
       double Zk1[CZ][4], Xn1[CX][4], AB1[CT][4];
-      double ck1 = 0.0, qk1 = 0.0, rk1 = 0.0;
+      double ck1 = 0.0, qk1 = 0.0, rk1 = 0.0, dk1 = 0.0;
       if constexpr (PF) {
         load_tile(Zk1, ztile(k1), zo, CZ);
         load_tile(Xn1, xtile(k1 + 1), xo, CX);
         load_ab(AB1, k1, false);
         ck1 = xr ? cb[(int64_t)(k1 + 1) * n + tid] : 0.0;
+        dk1 = (DG && xr) ? ddg[(int64_t)(k1 + 1) * n + tid] : 0.0;
         qk1 = xr ? qb[(int64_t)k1 * qs + tid] : 0.0;
         rk1 = ur ? rb[(int64_t)k1 * rs + (tid - n)] : 0.0;
       } else {
@@ -524,6 +567,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
         load_tile(Xn, xtile(k + 1), xo, CX);
         load_ab(AB, k, false);
         ck = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+        dk = (DG && xr) ? ddg[(int64_t)(k + 1) * n + tid] : 0.0;
         qk = xr ? qb[(int64_t)k * qs + tid] : 0.0;
         rk = ur ? rb[(int64_t)k * rs + (tid - n)] : 0.0;
       }
@@ -531,10 +575,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       if (tid < NZ) s0[tid] = xr ? ck : 0.0;
       __syncthreads();
       tmatvec_mw<TG, CZ, TZ, TZ>(Zp, zi, zj, zo, s0, s1, red, tid, lane);   // s1 = Z_{k+1} c (x rows = P c)
-      if (tid < NZ) s2[tid] = xr ? p + s1[tid] : 0.0;                      // v
+      const double sdk = (DG && xr) ? sqrt(dk) : 1.0;
+      if (tid < NZ) s2[tid] = xr ? sdk * (p + s1[tid]) : 0.0;              // v (per-stage diagonal: D v)
       __syncthreads();
       tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s2, s1, red, tid, lane);   // s1 = -S_hat^{-1} v
-      if (tid < NZ) s0[tid] = xr ? -s1[tid] : 0.0;                          // g
+      if (tid < NZ) s0[tid] = xr ? (DG ? -s1[tid] / sdk : -s1[tid]) : 0.0;  // g
       __syncthreads();
       tmatvec_mw<TG, CT, TX, TZ>(AB, ai, aj, ao, s0, s1, red, tid, lane);   // s1 = [A^T g; B^T g]
       const double abg = tid < NZ ? s1[tid] : 0.0;
@@ -563,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
         for (int t = 0; t < CT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) AB[t][v] = AB1[t][v];
-        ck = ck1; qk = qk1; rk = rk1;
+        ck = ck1; qk = qk1; rk = rk1; dk = dk1;
       }
     }
     if (SEG && phase == 1 && xr) a.plo[mt.ovec + (int64_t)sd.s * n + tid] = p;
@@ -577,10 +622,12 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     double X0[CX][4];
     load_tile(X0, xtile(0), xo, CX);
     const double p0 = xr ? pg[tid] : 0.0;
-    if (tid < NZ) s0[tid] = xr ? cb[tid] - delta * p0 : 0.0;
+    const double d0 = (DG && xr) ? ddg[tid] : delta;
+    const double sd0 = (DG && xr) ? sqrt(d0) : 1.0;
+    if (tid < NZ) s0[tid] = xr ? (DG ? (cb[tid] - d0 * p0) / sd0 : cb[tid] - delta * p0) : 0.0;
     __syncthreads();
     tmatvec_mw<TG, CX, TX, TX>(X0, xi, xj, xo, s0, s1, red, tid, lane);
-    x = xr ? -s1[tid] : 0.0;
+    x = xr ? -sd0 * s1[tid] : 0.0;
   } else if (phase == 2) {
     x = 0.0;
   } else {
@@ -594,8 +641,9 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   };
   // step k's operands, loaded one step ahead
   double Zk[CZ][4], Xn[CX][4], ABt[CT][4];
-  double pk = 0.0, kk = 0.0, pn = 0.0, cn = 0.0;
+  double pk = 0.0, kk = 0.0, pn = 0.0, cn = 0.0, dn = delta;
   if (PF && hi > lo) {
+    if constexpr (DG) dn = xr ? ddg[(int64_t)(lo + 1) * n + tid] : 0.0;
     load_tile(Zk, ztile(lo), zo, CZ);
     load_tile(Xn, xtile(lo + 1), xo, CX);
     load_ab(ABt, lo, true);
@@ -607,8 +655,9 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   for (int k = lo; k < hi; ++k) {
     const int k1 = k + 1 < hi ? k + 1 : k;
     double Zk1[CZ][4], Xn1[CX][4], ABt1[CT][4];
-    double pk1 = 0.0, kk1 = 0.0, pn1 = 0.0, cn1 = 0.0;
+    double pk1 = 0.0, kk1 = 0.0, pn1 = 0.0, cn1 = 0.0, dn1 = delta;
     if constexpr (PF) {
+      if constexpr (DG) dn1 = xr ? ddg[(int64_t)(k1 + 1) * n + tid] : 0.0;
       load_tile(Zk1, ztile(k1), zo, CZ);
       load_tile(Xn1, xtile(k1 + 1), xo, CX);
       load_ab(ABt1, k1, true);
@@ -624,6 +673,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       kk = ur ? kg[(int64_t)k * m + (tid - n)] : 0.0;
       pn = pnext(k);
       cn = xr ? cb[(int64_t)(k + 1) * n + tid] : 0.0;
+      if constexpr (DG) dn = xr ? ddg[(int64_t)(k + 1) * n + tid] : 0.0;
     }
     __syncthreads();
     if (tid < NZ) s0[tid] = xr ? x : 0.0;
@@ -644,10 +694,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     if (tid < NZ) s2[tid] = xr ? x : (ur ? uk : 0.0);
     __syncthreads();
     tmatvec_mw<TG, CT, TZ, TX>(ABt, ati, atj, ao, s2, s1, red, tid, lane); // [A B] z
-    if (tid < NZ) s0[tid] = xr ? s1[tid] + cn - delta * pn : 0.0;
+    const double sdn = (DG && xr) ? sqrt(dn) : 1.0;
+    if (tid < NZ) s0[tid] = xr ? (DG ? (s1[tid] + cn - dn * pn) / sdn : s1[tid] + cn - delta * pn) : 0.0;
     __syncthreads();
     tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s0, s1, red, tid, lane);
-    x = xr ? -s1[tid] : 0.0;
+    x = xr ? -sdn * s1[tid] : 0.0;
     if constexpr (PF) {
 #pragma unroll
       for (int t = 0; t < CZ; ++t)
@@ -661,7 +712,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       for (int t = 0; t < CT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) ABt[t][v] = ABt1[t][v];
-      pk = pk1; kk = kk1; pn = pn1; cn = cn1;
+      pk = pk1; kk = kk1; pn = pn1; cn = cn1; dn = dn1;
     }
   }
   if (SEG && phase == 2) {
@@ -689,12 +740,19 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
 
 template <typename TG, int TX, int TZ, int NW>
 static hipError_t launch_mw_pair(bool factor, const void* args, int nblocks, hipStream_t st) {
-  if (factor)
-    hipLaunchKernelGGL((k_factor_mw<TG, TX, TZ, NW>), dim3(nblocks), dim3(64 * NW), 0, st,
-                       *reinterpret_cast<const FactorArgs*>(args));
-  else
-    hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false>), dim3(nblocks), dim3(64 * NW), 0, st,
-                       *reinterpret_cast<const SolveArgs*>(args));
+  if (factor) {
+    const FactorArgs& a = *reinterpret_cast<const FactorArgs*>(args);
+    if (a.dd)
+      hipLaunchKernelGGL((k_factor_mw<TG, TX, TZ, NW, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_factor_mw<TG, TX, TZ, NW, false>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+  } else {
+    const SolveArgs& a = *reinterpret_cast<const SolveArgs*>(args);
+    if (a.dd)
+      hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false, false>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ class _Shape(ctypes.Structure):
 
 
 class _Lhs(ctypes.Structure):
-    _fields_ = [(k, _vp) for k in ("Q", "M", "R", "A", "B", "delta")]
+    _fields_ = [(k, _vp) for k in ("Q", "M", "R", "A", "B", "delta", "delta_diag")]
 
 
 class _Rhs(ctypes.Structure):
@@ -166,13 +166,13 @@ def rlqr_layout_offsets(h, array: int, batch: int) -> np.ndarray:
     return off
 
 
-def rlqr_factor(h, Q, M, R, A, B, delta, stream=None):
-    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+def rlqr_factor(h, Q, M, R, A, B, delta, stream=None, delta_diag=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta, delta_diag)])
     _check(_lib.rlqr_factor(h, ctypes.byref(lhs), _stream(stream)), "rlqr_factor")
 
 
-def rlqr_factor_rhs(h, Q, M, R, A, B, delta, q, r, c, stream=None):
-    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+def rlqr_factor_rhs(h, Q, M, R, A, B, delta, q, r, c, stream=None, delta_diag=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta, delta_diag)])
     rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
     _check(_lib.rlqr_factor_rhs(h, ctypes.byref(lhs), ctypes.byref(rhs), _stream(stream)), "rlqr_factor_rhs")
 
@@ -210,8 +210,8 @@ def rlqr_residual(h, q, r, c, x, u, y, res=None, inst_relres=None, stream=None):
 
 
 def rlqr_graph_capture(h, Q, M, R, A, B, delta, q, r, c, x, u, y, rel_tol, max_refine,
-                       inst_status=None, inst_relres=None, stream=None):
-    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+                       inst_status=None, inst_relres=None, stream=None, delta_diag=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta, delta_diag)])
     rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
     sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
     _check(_lib.rlqr_graph_capture(h, ctypes.byref(lhs), ctypes.byref(rhs), ctypes.byref(sol), float(rel_tol),
@@ -270,16 +270,20 @@ class Solver:
             t = lhs[k]
             assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() >= self.size(k), k
         assert lhs["delta"].numel() >= self.batch and lhs["delta"].dtype == self.torch.float64
+        dd = lhs.get("delta_diag")
+        if dd is not None:  # per-stage diagonal Delta_i, laid out like x
+            assert dd.dtype == self.torch.float64 and dd.is_cuda and dd.is_contiguous() and \
+                dd.numel() >= self.size("x")
         self._lhs = lhs  # the library re-reads the lhs during refinement: keep it alive
         args = [lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")]
         if rhs is None:
-            rlqr_factor(self.handle, *args, stream=stream)
+            rlqr_factor(self.handle, *args, stream=stream, delta_diag=dd)
             return
         for k in ("q", "r", "c"):
             t = rhs[k]
             assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() >= self.size(k), k
         self._rhs = rhs
-        rlqr_factor_rhs(self.handle, *args, rhs["q"], rhs["r"], rhs["c"], stream=stream)
+        rlqr_factor_rhs(self.handle, *args, rhs["q"], rhs["r"], rhs["c"], stream=stream, delta_diag=dd)
 
     def solve(self, rhs, out=None, rel_tol: float = 1e-8, max_refine: int = 0, stream=None):
         torch = self.torch
@@ -322,7 +326,7 @@ class Solver:
         self._graph_out = (status, relres)
         rlqr_graph_capture(self.handle, *(lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")),
                            rhs["q"], rhs["r"], rhs["c"], out["x"], out["u"], out["y"], rel_tol, max_refine,
-                           status, relres, stream=stream)
+                           status, relres, stream=stream, delta_diag=lhs.get("delta_diag"))
         return status, relres
 
     def replay(self, stream=None):
@@ -362,6 +366,8 @@ def to_device(packed, device="cuda:0"):
         return torch.from_numpy(a if a.size else np.zeros(1)).to(dev)
     lhs = {k: t(packed.arrays[k]) for k in ("Q", "M", "R", "A", "B")}
     lhs["delta"] = t(packed.delta)
+    if "delta_diag" in packed.arrays:
+        lhs["delta_diag"] = t(packed.arrays["delta_diag"])
     rhs = {k: t(packed.arrays[k]) for k in ("q", "r", "c")}
     return lhs, rhs
 
@@ -396,8 +402,8 @@ def rlqr_xs_create(h, p: int):
     return x, int(ws.value)
 
 
-def rlqr_xs_factor(x, Q, M, R, A, B, delta, Jq, Jr, Jc, H, rel_tol, max_refine, stream=None):
-    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta)])
+def rlqr_xs_factor(x, Q, M, R, A, B, delta, Jq, Jr, Jc, H, rel_tol, max_refine, stream=None, delta_diag=None):
+    lhs = _Lhs(*[_ptr(t) for t in (Q, M, R, A, B, delta, delta_diag)])
     xl = _XsLhs(_ptr(Jq), _ptr(Jr), _ptr(Jc), _ptr(H))
     _check(_lib.rlqr_xs_factor(x, ctypes.byref(lhs), ctypes.byref(xl), float(rel_tol), int(max_refine),
                                _stream(stream)), "rlqr_xs_factor")
@@ -451,7 +457,7 @@ class CrossStage:
         s._lhs = lhs
         self._keep = (lhs, J, H)  # re-read by every solve
         rlqr_xs_factor(self.ctx, *(lhs[k] for k in ("Q", "M", "R", "A", "B", "delta")), J["Jq"], J["Jr"], J["Jc"],
-                       H, rel_tol, max_refine, stream=stream)
+                       H, rel_tol, max_refine, stream=stream, delta_diag=lhs.get("delta_diag"))
 
     def solve(self, rhs, rtheta, out=None, rel_tol: float = 1e-8, max_refine: int = 3, stream=None):
         s, torch = self.solver, self.torch

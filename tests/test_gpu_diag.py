@@ -1,0 +1,177 @@
+"""GPU parity with a per-stage diagonal regularization Delta_i (rlqr_lhs.delta_diag).
+
+The definition of a dual-regularized LQR problem allows any SPD Delta_i;
+separate penalty parameters per constraint give diagonal ones. Every case
+runs through the C ABI and is checked against the oracle's diagonal path
+(pinned on the CPU against the dense KKT system, a diagonal change of
+variables to Delta = I, the KKT inertia and a determinant identity):
+element-wise at 1e-10 (float64 path) or 1e-7 (refined), the relative KKT
+residual at 1e-8, and verdict / first failing pivot / inertia exactly.
+Tile classes covered: the one-wavefront kernel (n + m <= 16) and four
+multi-wavefront classes; horizons include N = 0 and 1.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_16370_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2509_16370_amd import rlqr
+    return rlqr
+
+
+def _batch(shapes, spread, delta=1e-3, tag=0):
+    out = []
+    for b, (n, m, N) in enumerate(shapes):
+        out.append(wl.make_instance(n, m, N, delta, (41, tag, b), indefinite=(b % 4 == 3),
+                                    diag_spread=spread))
+    return out
+
+
+def _run(rl, insts, mode, max_refine=3, fused=False, drop_delta=False):
+    import torch
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    if drop_delta:  # delta is not read when delta_diag is given
+        lhs = dict(lhs)
+        lhs["delta"] = torch.full_like(lhs["delta"], float("nan"))
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
+    s.factor(lhs, rhs if fused else None)
+    out, status, relres = s.solve(rhs, rel_tol=1e-8, max_refine=max_refine)
+    verdict, first_bad, inertia = s.pivot_inertia()
+    torch.cuda.synchronize()
+    B = packed.batch
+    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
+    return dict(sols=sols, status=status.cpu().numpy()[:B], relres=relres.cpu().numpy()[:B],
+                verdict=verdict.cpu().numpy()[:B], first_bad=first_bad.cpu().numpy()[:B],
+                inertia=inertia.cpu().numpy().reshape(-1, 3)[:B], solver=s, lhs=lhs, rhs=rhs, out=out,
+                packed=packed)
+
+
+def _check(insts, r, tol):
+    for b, inst in enumerate(insts):
+        ref = oracle.seq(inst)
+        assert ref["status"] == 0
+        ok, fb, inertia = oracle.certificate(inst, ref["dS"], ref["dG"])
+        assert r["verdict"][b] == int(ok) and r["first_bad"][b] == fb, b
+        assert tuple(r["inertia"][b]) == inertia, b
+        assert r["relres"][b] <= 1e-8, (b, r["relres"][b])
+        scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y") if ref[k].size))
+        err = max(np.abs(a - ref[k]).max() if a.size else 0.0 for a, k in zip(r["sols"][b], ("x", "u", "y")))
+        assert err <= tol * scale, (b, err, scale)
+
+
+ONE_WAVE = [(4, 1, 40), (12, 4, 33), (5, 3, 1), (8, 2, 0), (12, 4, 70), (3, 2, 17), (10, 6, 25), (12, 4, 9)]
+MULTI_WAVE = [(20, 8, 12), (24, 7, 1), (36, 10, 9), (64, 32, 6), (17, 3, 0), (30, 2, 21), (14, 9, 7)]
+
+
+@pytest.mark.parametrize("spread", [0.0, 1.0, 3.0])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_diag_one_wavefront_matches_oracle(rl, mode, spread):
+    print(f"[gpu] diag one-wavefront mode={mode} spread={spread}", flush=True)
+    insts = _batch(ONE_WAVE, spread, tag=int(10 * spread))
+    r = _run(rl, insts, mode)
+    _check(insts, r, 1e-10 if mode == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_diag_multi_wavefront_matches_oracle(rl, mode):
+    print(f"[gpu] diag multi-wavefront mode={mode}", flush=True)
+    insts = _batch(MULTI_WAVE, 1.5, delta=1e-2, tag=5)
+    r = _run(rl, insts, mode)
+    _check(insts, r, 1e-10 if mode == "fp64" else 1e-7)
+
+
+def test_diag_mixed_classes_fused_and_delta_not_read(rl):
+    """One batch over both kinds of kernel, the backward vector pass fused into
+    the factorization, and delta set to NaN (it must not be read)."""
+    print("[gpu] diag mixed classes fused", flush=True)
+    insts = _batch(ONE_WAVE[:4] + MULTI_WAVE[:3], 2.0, delta=1e-4, tag=7)
+    r = _run(rl, insts, "fp64", fused=True, drop_delta=True)
+    _check(insts, r, 1e-10)
+
+
+def test_equal_diagonal_matches_scalar_path(rl):
+    """delta_diag = delta everywhere reproduces the scalar-delta kernels."""
+    print("[gpu] diag equal entries vs scalar", flush=True)
+    insts = _batch(ONE_WAVE + MULTI_WAVE[:2], 0.0, delta=1e-3, tag=9)
+    plain = [wl.Instance(*[getattr(i, f) for f in ("n", "m", "N", "delta", "Q", "M", "R", "A", "B", "q", "r",
+                                                   "c", "indefinite")]) for i in insts]
+    a = _run(rl, insts, "fp64", max_refine=0)
+    b = _run(rl, plain, "fp64", max_refine=0)
+    assert (a["verdict"] == b["verdict"]).all() and (a["first_bad"] == b["first_bad"]).all()
+    assert (a["inertia"] == b["inertia"]).all()
+    for sa, sb in zip(a["sols"], b["sols"]):
+        for x, y in zip(sa, sb):
+            if y.size:
+                assert np.abs(x - y).max() <= 1e-11 * max(1.0, np.abs(y).max())
+
+
+def test_diag_residual_call_matches_oracle(rl):
+    import torch
+    print("[gpu] diag residual call", flush=True)
+    insts = _batch(ONE_WAVE[:3] + MULTI_WAVE[:2], 1.0, tag=11)
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode="fp64")
+    s.factor(lhs)
+    rng = np.random.default_rng(5)
+    z = {k: rng.standard_normal(max(int(packed.offsets[k][-1]), 1)) for k in ("x", "u", "y")}
+    zt = {k: torch.from_numpy(v).cuda() for k, v in z.items()}
+    res, relres = s.residual(rhs, zt)
+    torch.cuda.synchronize()
+    res = res.cpu().numpy()
+    roff = s.offsets["res"]
+    sols = wl.unpack_solution(packed, z["x"], z["u"], z["y"])
+    for b, inst in enumerate(insts):
+        ref = oracle.residual(inst, *sols[b])
+        got = res[roff[b]:roff[b + 1]]
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-13 * max(1, np.abs(ref).max())), b
+        rel = np.abs(ref).max() / oracle.rhs_norm(inst)
+        assert np.isclose(float(relres[b]), rel, rtol=1e-12), b
+
+
+def test_diag_stacked_right_hand_sides(rl):
+    """rlqr_solve_multi with the fused stacked launch: every right-hand side
+    matches its own rlqr_solve (the stacked instances read their base
+    instance's Delta_i)."""
+    import torch
+    print("[gpu] diag stacked right-hand sides", flush=True)
+    insts = _batch(ONE_WAVE[:4] + MULTI_WAVE[:2], 1.0, tag=13)
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    p = 3
+    s = rl.Solver(packed.N, packed.n, packed.m, mode="fp64", max_rhs=p)
+    s.factor(lhs)
+    rng = np.random.default_rng(3)
+    stacked = {k: torch.from_numpy(rng.standard_normal(p * s.size(k))).to(lhs["Q"].device) for k in ("q", "r", "c")}
+    out, status, relres = s.solve_multi(p, stacked, rel_tol=1e-8, max_refine=3)
+    torch.cuda.synchronize()
+    assert (relres.cpu().numpy()[:p * s.batch] <= 1e-8).all()
+    for j in range(p):
+        one = {k: stacked[k][j * s.size(k):(j + 1) * s.size(k)].contiguous() for k in ("q", "r", "c")}
+        o1, _, _ = s.solve(one, rel_tol=1e-8, max_refine=3)
+        torch.cuda.synchronize()
+        for k in ("x", "u", "y"):
+            a = out[k][j * s.size(k):(j + 1) * s.size(k)].cpu().numpy()
+            b = o1[k][:s.size(k)].cpu().numpy()
+            assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), (j, k)
+
+
+@pytest.mark.parametrize("mode", ["scan", "scan_bf16"])
+def test_diag_scan_modes_unsupported(rl, mode):
+    print(f"[gpu] diag scan unsupported mode={mode}", flush=True)
+    insts = _batch(ONE_WAVE[:2], 1.0, tag=15)
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
+    with pytest.raises(rl.RlqrError) as e:
+        s.factor(lhs)
+    assert "UNSUPPORTED" in str(e.value) or "-5" in str(e.value)
