@@ -23,7 +23,9 @@ N ~ U{50..1000}, n in {8,16,32}, m in {2,4,8}, 20% indefinite Q, delta=1e-4;
 the autotuned single-graph launch against the float64 sequential path) and
 cross_stage (the uniform batch with p = 4 variables shared by every stage:
 the arrowhead step of Section "Cross-Stage Variables", factor + solve +
-refinement of the whole system, float64 and mixed).
+refinement of the whole system, float64 and mixed). --diag-spread s gives the
+uniform batch a per-stage diagonal Delta_i (entries delta * 10^U(-s, s), the
+separate per-constraint penalties the definition allows).
 """
 import argparse
 import json
@@ -40,13 +42,14 @@ HBM_PEAK_GBS = 8000.0
 REL_TOL = 1e-8
 
 
-def factor_algorithmic_bytes(n, m, elem_bytes, with_rhs=True):
+def factor_algorithmic_bytes(n, m, elem_bytes, with_rhs=True, diag=False):
     """Per stage: read Q, M, R, A, B (float64) and write the minimal
     factorization a solve needs -- K (m x n), the symmetric P and S_hat^{-1}
     (n(n+1)/2 each) and the symmetric G^{-1} (m(m+1)/2) -- in the working
     precision; with the right-hand side (rlqr_factor_rhs) also read q, r, c
-    and write p, k (float64)."""
-    lhs = 8 * (n * n + n * m + m * m + n * n + n * m)
+    and write p, k (float64); with a per-stage diagonal Delta_i also read its
+    n entries (float64)."""
+    lhs = 8 * (n * n + n * m + m * m + n * n + n * m) + (8 * n if diag else 0)
     handoff = elem_bytes * (m * n + n * (n + 1) + m * (m + 1) // 2)
     vec = 8 * ((2 * n + m) + (n + m)) if with_rhs else 0
     return lhs + handoff + vec
@@ -256,6 +259,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0,
                     help="scan modes: stages per segment L (0: the library's default)")
     ap.add_argument("--delta", type=float, default=1e-8)
+    ap.add_argument("--diag-spread", type=float, default=None,
+                    help="batched_uniform: per-stage diagonal Delta_i with entries delta * 10^U(-s, s)")
     ap.add_argument("--max-refine", type=int, default=3)
     ap.add_argument("--modes", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -277,15 +282,25 @@ def main():
     wk = args.workload
     t0 = time.perf_counter()
     rel_tol, max_refine = REL_TOL, args.max_refine
+    diag = args.diag_spread is not None
+    if diag and wk != "batched_uniform":
+        print("--diag-spread applies to the batched_uniform workload only", file=sys.stderr)
+        sys.exit(2)
     if wk == "batched_uniform":
         n, m, N = args.nx, args.nu, args.horizon
-        packed = wl.pack_parallel(wl.uniform_specs(batch=args.batch, n=n, m=m, N=N, delta=args.delta),
-                                  workers=args.workers)
+        specs = wl.uniform_specs(batch=args.batch, n=n, m=m, N=N, delta=args.delta)
+        if diag:
+            specs = [s + (False, args.diag_spread) for s in specs]
+        packed = wl.pack_parallel(specs, workers=args.workers)
         modes = (args.modes or "fp64,mixed").split(",")
         head = "mixed"
+        reg = (f"per-stage diagonal Delta_i with entries delta * 10^U(-{args.diag_spread:g}, {args.diag_spread:g}), "
+               f"delta={args.delta:g}") if diag else f"delta={args.delta:g}"
         desc = (f"batched uniform dual-regularized LQR: {args.batch} instances, n={n}, m={m}, N={N}, "
-                f"delta={args.delta:g}, refined to {REL_TOL:g} relative KKT residual")
+                f"{reg}, refined to {REL_TOL:g} relative KKT residual")
         cfg = {"batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta}
+        if diag:
+            cfg["delta_diag_spread"] = args.diag_spread
     elif wk == "long_horizon":
         inst = wl.long_horizon()[0]
         packed = wl.pack([inst])
@@ -391,13 +406,14 @@ def main():
         dtype = "f64" if head == "fp64" else "f32+f64"
     else:
         elem = 8 if head == "fp64" else 4
-        alg_bytes = float(sum(factor_algorithmic_bytes(int(packed.n[b]), int(packed.m[b]), elem) * int(packed.N[b])
-                              for b in range(packed.batch)))
+        alg_bytes = float(sum(factor_algorithmic_bytes(int(packed.n[b]), int(packed.m[b]), elem, diag=diag)
+                              * int(packed.N[b]) for b in range(packed.batch)))
         achieved = alg_bytes / (r["factor_ms"] * 1e-3) / 1e9
-        default_uniform = wk == "batched_uniform" and (args.nx, args.nu, args.horizon, args.batch) == (12, 4, 128, 4096)
+        default_uniform = (wk == "batched_uniform" and not diag
+                           and (args.nx, args.nu, args.horizon, args.batch) == (12, 4, 128, 4096))
         if wk == "batched_uniform":
             kern = ("k_factor16<%s>" if args.nx + args.nu <= 16 else "k_factor_mw<%s>") % (
-                "double" if head == "fp64" else "float")
+                ("double" if head == "fp64" else "float") + (", diagonal Delta" if diag else ""))
         else:
             kern = "rlqr_factor (all tile classes)"
         traffic = (load_counters("k_factor16_float.batched_uniform.counters.txt")

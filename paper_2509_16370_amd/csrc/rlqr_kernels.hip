@@ -239,20 +239,21 @@ __device__ __forceinline__ double ld_or0(const double* __restrict__ v, int64_t i
 // from the tiles Zp = Z_{k+1} (P_{k+1}), Xn = X_{k+1} = -S_hat_{k+1}^{-1},
 // Zk = Z_k and ab = [A_k B_k] (all in the register layout trow<TG>); p holds
 // p_{k+1} on entry and p_k on exit (x lanes), the return value is k_k (u lanes).
-// DG (diagonal Delta_{k+1} = D^2): g = (I + P Delta)^{-1} v = D^{-1} S_hat^{-1} D v
-// with S_hat = I + D P D; sd, isd are D and D^{-1} of the lane's column.
+// DG (diagonal Delta_{k+1}): the stored tile is X~ = -D S_hat^{-1} D (S_hat = I +
+// D P D, D = Delta^{1/2}), so g = (I + P Delta)^{-1} v = -Delta^{-1} X~ v; id is
+// 1 / Delta's entry of the lane's column.
 template <typename TG, bool DG = false>
 __device__ __forceinline__ double bwd_vec_step(const double (&Zp)[4], const double (&Xn)[4], const double (&ab)[4],
                                                const double (&Zk)[4], double& p, double ck, double qk, double rk,
                                                double (*sv)[16], bool xr, bool ur, bool own, int col, int lane,
-                                               double sd = 1.0, double isd = 1.0) {
+                                               double id = 1.0) {
   wave_sync();
   if (own) sv[0][col] = ck;
   wave_sync();
   const double vv = xr ? p + tmatvec<TG>(Zp, sv[0], lane) : 0.0;  // p + P_{k+1} c_{k+1}
-  if (own) sv[1][col] = DG ? sd * vv : vv;
+  if (own) sv[1][col] = vv;
   wave_sync();
-  const double g = DG ? -isd * tmatvec<TG>(Xn, sv[1], lane)        // D^{-1} S_hat^{-1} D v
+  const double g = DG ? -id * tmatvec<TG>(Xn, sv[1], lane)         // -Delta^{-1} X~ v
                       : -tmatvec<TG>(Xn, sv[1], lane);             // S_hat^{-1} v
   if (own) sv[0][col] = xr ? g : 0.0;
   wave_sync();
@@ -337,8 +338,9 @@ __device__ __forceinline__ typename AccT<T>::type gemm_abt_t(const double* stg, 
 // has n = SN, m = SM); 0: taken from the instance.
 // DG: per-stage diagonal Delta_i = D_i^2 (a.dd): the swept matrix is the
 // symmetric representative S_hat = I + D P D of Section "Inertia
-// Certification", and since I + Delta P = D S_hat D^{-1},
-// W = P (I + Delta P)^{-1} = -P (D X D^{-1}) with X = -S_hat^{-1}.
+// Certification". Since I + Delta P = D S_hat D^{-1}, the tile stored is the
+// symmetric X~ = D X D (X = -S_hat^{-1}), with (I + Delta P)^{-1} = -X~ Delta^{-1}
+// and W = P (I + Delta P)^{-1} = -P X~ Delta^{-1}.
 template <typename TG, int SN, int SM, bool DG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_factor16(FactorArgs a) {
   constexpr bool CP = sizeof(TG) == 8;  // compact tiles in float64 (TileLayout)
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       rk = ld_or0(rg, (int64_t)k * m + (col - n), ur);
     }
     // X = I + delta P_{k+1} (DG: I + D P D); sweep -> -S_hat_{k+1}^{-1}  (no stage data needed)
-    double sdc = 1.0, isdc = 1.0, sdr[4] = {1.0, 1.0, 1.0, 1.0};
+    double sdc = 1.0, isdc = 1.0, sdr[4] = {1.0, 1.0, 1.0, 1.0};  // DG: D of the column, of the rows
     if constexpr (DG) {
       const double dcur = dnx;
       dnx = ld_or0(ddg, (int64_t)k * n + col, xr);
@@ -460,22 +462,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const double sc = diag_scale<TG>(X, 0, n, lane_s);
       sweep16<TG>(X, 0, n, lane_s, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
     }
+    const double idc = isdc * isdc;  // DG: 1 / Delta's entry of the column
+    if constexpr (DG) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[v] = sdr[v] * X[v] * sdc;  // X~ = D X D
+    }
     tile_store_as<TG, CP>(ws + tl.x(k + 1), X, lane, n);
     if (vec) {  // vector pass, first part: g = S_hat_{k+1}^{-1} (p_{k+1} + P_{k+1} c_{k+1})
       wave_sync();
       if (own) sv[0][col] = ck;
       wave_sync();
       const double vv = xr ? pv + tmatvec_r<TG>(P, sv[0], lane) : 0.0;
-      if (own) sv[1][col] = DG ? sdc * vv : vv;
+      if (own) sv[1][col] = vv;
       wave_sync();
-      const double g = DG ? -isdc * tmatvec_r<TG>(X, sv[1], lane) : -tmatvec_r<TG>(X, sv[1], lane);
+      const double g = DG ? -idc * tmatvec_r<TG>(X, sv[1], lane) : -tmatvec_r<TG>(X, sv[1], lane);
       if (own) sv[0][col] = xr ? g : 0.0;
     }
     tile_to_lds<TG>(sP, P, lane);
-    if constexpr (DG) {  // the product takes D X D^{-1}; the stored tile stays X
+    if constexpr (DG) {  // the product takes X~ Delta^{-1}
       double Xs[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Xs[v] = sdr[v] * X[v] * isdc;
+      for (int v = 0; v < 4; ++v) Xs[v] = X[v] * idc;
       tile_to_lds<TG>(sX, Xs, lane);
     } else {
       tile_to_lds<TG>(sX, X, lane);
@@ -563,6 +570,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + (DG ? sdr[v] * sdc * P[v] : delta * P[v]);
     const double sc = diag_scale<TG>(X, 0, n, lane);
     sweep16<TG>(X, 0, n, lane, ps, 0, 1.0e3 * n * eps * sc, sc);
+    if constexpr (DG) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[v] = sdr[v] * X[v] * sdc;  // X~_0 = D_0 X_0 D_0
+    }
     tile_store_as<TG, CP>(ws + tl.x(0), X, lane, n);
   }
   if (lane == 0) {
@@ -584,8 +595,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // z. The tiles and stage blocks of the next step are loaded one step ahead
 // so that the dependent chain does not wait on memory.
 // ACC: correction pass (right-hand side = a.corr, z += dz); otherwise a.corr is NULL
-// DG: per-stage diagonal Delta_i = D_i^2 (a.dd); (I + Delta P)^{-1} = D S_hat^{-1} D^{-1}
-// and (I + P Delta)^{-1} = D^{-1} S_hat^{-1} D with the stored X = -S_hat^{-1}.
+// DG: per-stage diagonal Delta_i (a.dd); with the stored X~ = -D S_hat^{-1} D,
+// (I + Delta P)^{-1} = -X~ Delta^{-1} and (I + P Delta)^{-1} = -Delta^{-1} X~.
 template <typename TG, int SN, int SM, bool ACC, bool DG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_solve16(SolveArgs a) {
   constexpr bool CP = sizeof(TG) == 8;  // compact tiles in float64 (TileLayout)
@@ -672,12 +683,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const double qk1 = ld_or0(qb, (int64_t)k1 * qs + col, xr);
       const double rk1 = ld_or0(rb, (int64_t)k1 * rs + (col - n), ur);
       const double dk1 = DG ? ld_or0(ddg, (int64_t)(k1 + 1) * n + col, xr) : 0.0;
-      double sdk = 1.0, isdk = 1.0;
-      if constexpr (DG) {
-        sdk = xr ? sqrt(dk) : 0.0;
-        isdk = xr ? 1.0 / sdk : 0.0;
-      }
-      const double zh = bwd_vec_step<TG, DG>(Zp, Xn, ab, Zk, p, ck, qk, rk, sv, xr, ur, own, col, lane, sdk, isdk);
+      const double idk = (DG && xr) ? 1.0 / dk : 0.0;
+      const double zh = bwd_vec_step<TG, DG>(Zp, Xn, ab, Zk, p, ck, qk, rk, sv, xr, ur, own, col, lane, idk);
       if (own) {
         if (xr) pg[(int64_t)k * n + col] = p;
         if (ur) kg[(int64_t)k * m + (col - n)] = zh;
@@ -746,11 +753,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double p0 = ld_or0(pg, col, xr);
     const double c00 = ld_or0(cb, col, xr);
     wave_sync();
-    if constexpr (DG) {  // x_0 = D S_hat_0^{-1} D^{-1} (c_0 - Delta_0 p_0)
-      const double s0 = xr ? sqrt(d0) : 0.0;
-      if (own) sv[0][col] = xr ? (c00 - d0 * p0) / s0 : 0.0;
+    if constexpr (DG) {  // x_0 = -X~_0 Delta_0^{-1} (c_0 - Delta_0 p_0)
+      if (own) sv[0][col] = xr ? (c00 - d0 * p0) / d0 : 0.0;
       wave_sync();
-      x = xr ? -s0 * tmatvec<TG>(X0, sv[0], lane) : 0.0;
+      x = xr ? -tmatvec<TG>(X0, sv[0], lane) : 0.0;
     } else {
       if (own) sv[0][col] = xr ? c00 - delta * p0 : 0.0;
       wave_sync();
@@ -798,6 +804,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     double* stgn = (k & 1) ? stgA : stgB;
     wait_vmem();  // step k's blocks, tiles and vectors have landed
     wave_sync();
+    // DG: 1 / Delta_{k+1}'s entry, off the step's dependent chain
+    const double idn = (DG && xr) ? 1.0 / dn : 0.0;
     const bool more = k + 1 < N;
     if (more) {
       const int k1 = k + 1;
@@ -844,11 +852,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       hz += stgc[ipk[v] & 1023] * sz[0][j];
     }
     w = group_sum(w);
-    if constexpr (DG) {  // x_{k+1} = D S_hat^{-1} D^{-1} (w + c - Delta p)
-      const double s1 = xr ? sqrt(dn) : 0.0;
-      if (own) sv[0][col] = xr ? (w + cn - dn * pn) / s1 : 0.0;
+    if constexpr (DG) {  // x_{k+1} = -X~ Delta^{-1} (w + c - Delta p)
+      if (own) sv[0][col] = xr ? (w + cn - dn * pn) * idn : 0.0;
       wave_sync();
-      x = xr ? -s1 * tmatvec<TG>(Xn, sv[0], lane) : 0.0;
+      x = xr ? -tmatvec<TG>(Xn, sv[0], lane) : 0.0;
     } else {
       if (own) sv[0][col] = xr ? w + cn - delta * pn : 0.0;
       wave_sync();
@@ -1348,10 +1355,16 @@ static hipError_t launch_factor_t(const FactorArgs& a, int nblocks, hipStream_t 
   hipLaunchKernelGGL((k_factor16<TG, SN, SM, DG>), dim3(nblocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
-// a per-stage diagonal Delta_i takes the general-shape kernel
 template <typename TG>
 static hipError_t launch_factor_s(const FactorArgs& a, int nblocks, int shape, hipStream_t st) {
-  if (a.dd) return launch_factor_t<TG, 0, 0, true>(a, nblocks, st);
+  if (a.dd) {  // per-stage diagonal Delta_i
+    switch (shape) {
+      case SHAPE_4_1: return launch_factor_t<TG, 4, 1, true>(a, nblocks, st);
+      case SHAPE_8_2: return launch_factor_t<TG, 8, 2, true>(a, nblocks, st);
+      case SHAPE_12_4: return launch_factor_t<TG, 12, 4, true>(a, nblocks, st);
+      default: return launch_factor_t<TG, 0, 0, true>(a, nblocks, st);
+    }
+  }
   switch (shape) {
     case SHAPE_4_1: return launch_factor_t<TG, 4, 1>(a, nblocks, st);
     case SHAPE_8_2: return launch_factor_t<TG, 8, 2>(a, nblocks, st);
@@ -1374,7 +1387,14 @@ static hipError_t launch_solve_t(const SolveArgs& a, int nblocks, hipStream_t st
 }
 template <typename TG>
 static hipError_t launch_solve_s(const SolveArgs& a, int nblocks, int shape, hipStream_t st) {
-  if (a.dd) return launch_solve_t<TG, 0, 0, true>(a, nblocks, st);
+  if (a.dd) {  // per-stage diagonal Delta_i
+    switch (shape) {
+      case SHAPE_4_1: return launch_solve_t<TG, 4, 1, true>(a, nblocks, st);
+      case SHAPE_8_2: return launch_solve_t<TG, 8, 2, true>(a, nblocks, st);
+      case SHAPE_12_4: return launch_solve_t<TG, 12, 4, true>(a, nblocks, st);
+      default: return launch_solve_t<TG, 0, 0, true>(a, nblocks, st);
+    }
+  }
   switch (shape) {
     case SHAPE_4_1: return launch_solve_t<TG, 4, 1>(a, nblocks, st);
     case SHAPE_8_2: return launch_solve_t<TG, 8, 2>(a, nblocks, st);

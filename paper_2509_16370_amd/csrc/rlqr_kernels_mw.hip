@@ -125,18 +125,25 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   const double eps = 2.220446049250313e-16;
 
   // per-stage diagonal Delta_{k+1} = D^2 (a.dd): the swept matrix is
-  // S_hat = I + D P D and the product takes D X D^{-1} (W = P (I + Delta P)^{-1});
-  // D and D^{-1} of the stage sit in LDS (0 outside the state block), the
+  // S_hat = I + D P D, the stored tile X~ = D X D (symmetric) and the product
+  // takes X~ Delta^{-1} (W = P (I + Delta P)^{-1} = -P X~ Delta^{-1}); D and
+  // Delta^{-1} of the stage sit in LDS (0 outside the state block), the
   // thread's entry of the next stage is loaded one stage ahead
   const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
-  __shared__ double sdl[DG ? NX : 1], isdl[DG ? NX : 1];
+  __shared__ double sdl[DG ? NX : 1], idl[DG ? NX : 1];
   double dpre = (DG && tid < n) ? ddg[(int64_t)khi * n + tid] : 0.0;
   auto put_diag = [&](double d) {
     if (tid < NX) {
-      const double sq = tid < n ? sqrt(d) : 0.0;
-      sdl[tid] = sq;
-      isdl[tid] = tid < n ? 1.0 / sq : 0.0;
+      sdl[tid] = tid < n ? sqrt(d) : 0.0;
+      idl[tid] = tid < n ? 1.0 / d : 0.0;
     }
+  };
+  auto scale_x = [&](double (&X)[CX][4]) {
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t])
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[t][v] *= sdl[16 * xi[t] + trow<TG>(grp, v)] * sdl[16 * xj[t] + col];
   };
 
   auto load_ab = [&](double (&o)[NAB], int k) {
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   }
 
   for (int k = khi - 1; k >= klo; --k) {
-    // (the previous stage's reads of sdl / isdl are behind its barriers)
+    // (the previous stage's reads of sdl / idl are behind its barriers)
     if constexpr (DG) {
       put_diag(dpre);
       dpre = tid < n ? ddg[(int64_t)k * n + tid] : 0.0;
@@ -237,6 +244,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
       sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
     }
+    if constexpr (DG) scale_x(X);  // X~ = D X D
     {
       TG* xt = xtile(k + 1);
 #pragma unroll
@@ -249,13 +257,10 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     for (int t = 0; t < CX; ++t)
       if (xo[t]) {
         blk_to_lds<TG>(sP, LDX, xi[t], xj[t], P[t], lane);
-        if constexpr (DG) {  // the product takes D X D^{-1}; the stored tile stays X
+        if constexpr (DG) {  // the product takes X~ Delta^{-1}
           double Xs[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
-            Xs[v] = sdl[r] * X[t][v] * isdl[c];
-          }
+          for (int v = 0; v < 4; ++v) Xs[v] = X[t][v] * idl[16 * xj[t] + col];
           blk_to_lds<TG>(sX, LDX, xi[t], xj[t], Xs, lane);
         } else {
           blk_to_lds<TG>(sX, LDX, xi[t], xj[t], X[t], lane);
@@ -364,6 +369,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       }
     const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
     sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
+    if constexpr (DG) scale_x(X);  // X~_0 = D_0 X_0 D_0
     TG* xt = xtile(0);
 #pragma unroll
     for (int t = 0; t < CX; ++t)
@@ -439,8 +445,8 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   const bool do_bwd = !SEG || phase <= 2, do_fwd = !SEG || phase >= 2;
   const bool write_pk = !SEG || phase == 2, write_z = !SEG || phase == 3;
   const double delta = DG ? 0.0 : a.delta[b];
-  // DG: per-stage diagonal Delta_i = D_i^2 (a.dd, laid out like x): (I + P Delta)^{-1}
-  // = D^{-1} S_hat^{-1} D and (I + Delta P)^{-1} = D S_hat^{-1} D^{-1}
+  // DG: per-stage diagonal Delta_i (a.dd, laid out like x); with the stored
+  // X~ = -D S_hat^{-1} D: (I + P Delta)^{-1} = -Delta^{-1} X~, (I + Delta P)^{-1} = -X~ Delta^{-1}
   const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
   const double* __restrict__ Ag = a.A + mt.oA;
   const double* __restrict__ Bg = a.B + mt.oB;
@@ -575,11 +581,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       if (tid < NZ) s0[tid] = xr ? ck : 0.0;
       __syncthreads();
       tmatvec_mw<TG, CZ, TZ, TZ>(Zp, zi, zj, zo, s0, s1, red, tid, lane);   // s1 = Z_{k+1} c (x rows = P c)
-      const double sdk = (DG && xr) ? sqrt(dk) : 1.0;
-      if (tid < NZ) s2[tid] = xr ? sdk * (p + s1[tid]) : 0.0;              // v (per-stage diagonal: D v)
+      const double idk = (DG && xr) ? 1.0 / dk : 1.0;
+      if (tid < NZ) s2[tid] = xr ? p + s1[tid] : 0.0;                      // v
       __syncthreads();
-      tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s2, s1, red, tid, lane);   // s1 = -S_hat^{-1} v
-      if (tid < NZ) s0[tid] = xr ? (DG ? -s1[tid] / sdk : -s1[tid]) : 0.0;  // g
+      tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s2, s1, red, tid, lane);   // s1 = -S_hat^{-1} v (DG: X~ v)
+      if (tid < NZ) s0[tid] = xr ? (DG ? -idk * s1[tid] : -s1[tid]) : 0.0;  // g
       __syncthreads();
       tmatvec_mw<TG, CT, TX, TZ>(AB, ai, aj, ao, s0, s1, red, tid, lane);   // s1 = [A^T g; B^T g]
       const double abg = tid < NZ ? s1[tid] : 0.0;
@@ -623,11 +629,10 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     load_tile(X0, xtile(0), xo, CX);
     const double p0 = xr ? pg[tid] : 0.0;
     const double d0 = (DG && xr) ? ddg[tid] : delta;
-    const double sd0 = (DG && xr) ? sqrt(d0) : 1.0;
-    if (tid < NZ) s0[tid] = xr ? (DG ? (cb[tid] - d0 * p0) / sd0 : cb[tid] - delta * p0) : 0.0;
+    if (tid < NZ) s0[tid] = xr ? (DG ? (cb[tid] - d0 * p0) / d0 : cb[tid] - delta * p0) : 0.0;
     __syncthreads();
     tmatvec_mw<TG, CX, TX, TX>(X0, xi, xj, xo, s0, s1, red, tid, lane);
-    x = xr ? -sd0 * s1[tid] : 0.0;
+    x = xr ? -s1[tid] : 0.0;
   } else if (phase == 2) {
     x = 0.0;
   } else {
@@ -694,11 +699,11 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     if (tid < NZ) s2[tid] = xr ? x : (ur ? uk : 0.0);
     __syncthreads();
     tmatvec_mw<TG, CT, TZ, TX>(ABt, ati, atj, ao, s2, s1, red, tid, lane); // [A B] z
-    const double sdn = (DG && xr) ? sqrt(dn) : 1.0;
-    if (tid < NZ) s0[tid] = xr ? (DG ? (s1[tid] + cn - dn * pn) / sdn : s1[tid] + cn - delta * pn) : 0.0;
+    const double idn = (DG && xr) ? 1.0 / dn : 1.0;
+    if (tid < NZ) s0[tid] = xr ? (DG ? (s1[tid] + cn - dn * pn) * idn : s1[tid] + cn - delta * pn) : 0.0;
     __syncthreads();
     tmatvec_mw<TG, CX, TX, TX>(Xn, xi, xj, xo, s0, s1, red, tid, lane);
-    x = xr ? -sdn * s1[tid] : 0.0;
+    x = xr ? -s1[tid] : 0.0;
     if constexpr (PF) {
 #pragma unroll
       for (int t = 0; t < CZ; ++t)

@@ -175,3 +175,16 @@ def test_diag_scan_modes_unsupported(rl, mode):
     with pytest.raises(rl.RlqrError) as e:
         s.factor(lhs)
     assert "UNSUPPORTED" in str(e.value) or "-5" in str(e.value)
+
+
+@pytest.mark.parametrize("shape", [(4, 1), (8, 2), (12, 4)])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_diag_fixed_shape_kernels(rl, shape, mode):
+    """A batch whose instances share one of the compiled stage shapes takes the
+    fixed-shape kernels with the diagonal; fused factorization as in the
+    benchmark step."""
+    n, m = shape
+    print(f"[gpu] diag fixed shape {shape} mode={mode}", flush=True)
+    insts = _batch([(n, m, N) for N in (0, 1, 7, 30, 64, 128)], 1.0, delta=1e-8, tag=20 + n)
+    r = _run(rl, insts, mode, fused=True)
+    _check(insts, r, 1e-10 if mode == "fp64" else 1e-7)
