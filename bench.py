@@ -18,7 +18,8 @@ baseline are reported beside it.
 
 Other workloads (--workload): long_horizon (one instance, n=64, m=32,
 N=16384, delta=1e-6, refined to 1e-10; the parallel-in-time scan, with float32
-and with bfloat16 combine products, against the float64 sequential recursion) and batched_ragged (1024 instances,
+and with bfloat16 combine products, and with p and c carried through the scan
+(scan_pc) instead of the p-recurrence, against the float64 sequential recursion) and batched_ragged (1024 instances,
 N ~ U{50..1000}, n in {8,16,32}, m in {2,4,8}, 20% indefinite Q, delta=1e-4;
 the autotuned single-graph launch against the float64 sequential path) and
 cross_stage (the uniform batch with p = 4 variables shared by every stage:
@@ -71,7 +72,9 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_t
                 ev[2].record(stream)
             return out, st, rr
     else:
-        s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=chunk)
+        # scan_pc: the scan mode carrying p and c through the reverse scan
+        s = rl.Solver(packed.N, packed.n, packed.m, mode="scan" if mode == "scan_pc" else mode,
+                      scan_chunk=chunk, scan_carry_pc=mode == "scan_pc")
         out = {k: s.empty(k) for k in ("x", "u", "y")}
 
         def step(ev=None):
@@ -305,7 +308,7 @@ def main():
         inst = wl.long_horizon()[0]
         packed = wl.pack([inst])
         rel_tol, max_refine = 1e-10, 6
-        modes = (args.modes or "fp64,scan,scan_bf16").split(",")
+        modes = (args.modes or "fp64,scan,scan_pc,scan_bf16").split(",")
         head = "scan"
         desc = ("single long-horizon dual-regularized LQR: n=64, m=32, N=16384, delta=1e-6, "
                 "refined to 1e-10 relative KKT residual; parallel-in-time scan vs float64 sequential")

@@ -147,6 +147,16 @@ typedef struct {
                                   right-hand sides at once (rlqr_solve_multi); 0 or 1:
                                   none. Costs max_rhs times the solve workspace
                                   (right-hand-side-sized vectors, per-instance flags). */
+  int32_t scan_carry_pc;       /* RLQR_SCAN_*: nonzero = rlqr_factor_rhs also carries
+                                  p and c through the reverse scan (eq. lqr-gpu-combo,
+                                  the alternative the paper sets beside the
+                                  p-recurrence), and the next rlqr_solve with the same
+                                  rhs pointers takes every segment's boundary p from
+                                  the scan instead of a backward pass over the
+                                  segments and the sequential boundary chain; its
+                                  refinement passes use the p-recurrence. Float32
+                                  vectors, 2 n_pad floats per element. Ignored by the
+                                  sequential modes and by rlqr_factor. */
 } rlqr_tuning;
 
 /*

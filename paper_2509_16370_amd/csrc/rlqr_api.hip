@@ -46,6 +46,8 @@ struct ScanGroup {
   int64_t *eoff = nullptr, *aoff = nullptr;
   float* elems = nullptr;
   float* aggr[2] = {nullptr, nullptr};
+  float* pce = nullptr;                  // carried p, c (scan_carry_pc)
+  float* pca[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -118,6 +120,10 @@ struct rlqr_handle {
   ResChunk* chunks_nf = nullptr;     // residual chunks of the other instances
   int64_t nchunks_nf = 0;
   rlqr_rhs pk_rhs{};
+  // scan_carry_pc: the last rlqr_factor_rhs carried p through the scan and
+  // wrote the segments' boundary p for this right-hand side into plo
+  bool carry_pc = false, pc_valid = false;
+  rlqr_rhs pc_rhs{};
   std::vector<void*> allocs;
 
   // Stacked right-hand sides (rlqr_solve_multi, sequential modes): mv is a
@@ -374,6 +380,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   h->n.assign(s->nx, s->nx + B);
   h->m.assign(s->nu, s->nu + B);
   const bool scan = is_scan(mode);
+  h->carry_pc = scan && tune && tune->scan_carry_pc != 0;
 
   // segment length: about one segment per compute unit (256) over the whole
   // batch, so the chunk folds and the segment recursions run in one round and
@@ -540,6 +547,12 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
       A((void**)&G.elems, sizeof(float) * elem * (size_t)g_elem[g]);
       A((void**)&G.aggr[0], sizeof(float) * elem * (size_t)g_aggr[g]);
       A((void**)&G.aggr[1], sizeof(float) * elem * (size_t)g_aggr[g]);
+      if (h->carry_pc) {
+        const size_t vec = 2ull * (16 * G.tx);
+        A((void**)&G.pce, sizeof(float) * vec * (size_t)g_elem[g]);
+        A((void**)&G.pca[0], sizeof(float) * vec * (size_t)g_aggr[g]);
+        A((void**)&G.pca[1], sizeof(float) * vec * (size_t)g_aggr[g]);
+      }
     }
   }
   // segment descriptors (device pointers into the scan buffers are known now)
@@ -641,6 +654,8 @@ rlqr_status rlqr_get_tuning(const rlqr_handle* h, rlqr_tuning* t) {
   t->scan_chunk = h->chunk;
   t->inst_chunk = nullptr;
   t->inst_fp64 = nullptr;
+  t->max_rhs = h->max_rhs;
+  t->scan_carry_pc = h->carry_pc ? 1 : 0;
   return RLQR_OK;
 }
 
@@ -723,9 +738,13 @@ static hipError_t factor_whole(rlqr_handle* h, void* ws, const int32_t* run, boo
 
 // Scan mode: elements, chunk reduce and suffix scan per group, then every
 // segment factored from its boundary cost-to-go, then the transfer matrices.
-static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
+// With rhs (scan_carry_pc) the scan also carries p and c, and the segments'
+// boundary p for that right-hand side goes to plo.
+static hipError_t factor_scan(rlqr_handle* h, hipStream_t st, const rlqr_rhs* rhs = nullptr) {
   hipError_t e = launch_fill_i32(h->bad, h->B, 0, st);
   if (e != hipSuccess) return e;
+  const bool pc = h->carry_pc && rhs != nullptr;
+  h->pc_valid = false;
   for (int g = 0; g < 3; ++g) {
     ScanGroup& G = h->grp[g];
     if (G.ninst == 0) continue;
@@ -734,8 +753,20 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st) {
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
     a.elems = G.elems; a.aggr[0] = G.aggr[0]; a.aggr[1] = G.aggr[1];
     a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
+    if (pc) {
+      a.pc = 1; a.q = rhs->q; a.r = rhs->r; a.c = rhs->c;
+      a.pce = G.pce; a.pca[0] = G.pca[0]; a.pca[1] = G.pca[1];
+    }
     if ((e = launch_scan_elements(a, G.ninst, G.tx, G.tm, st)) != hipSuccess) return e;
     if ((e = launch_scan_tree(a, G.ninst, G.tx, h->mode == RLQR_SCAN_BF16, st)) != hipSuccess) return e;
+    if (pc) {
+      a.pca_in = G.pca[scan_result_buffer(G.maxchunks)];
+      if ((e = launch_scan_pc_boundary(a, G.ninst, G.tx, h->plo, st)) != hipSuccess) return e;
+    }
+  }
+  if (pc) {
+    h->pc_valid = true;
+    h->pc_rhs = *rhs;
   }
   const int32_t* run32 = h->any_pref64 ? h->pref32 : nullptr;
   if ((e = factor_segments(h, h->fseg, h->seg_off, h->seg_stats, h->ws32, run32, true, st)) != hipSuccess)
@@ -759,6 +790,7 @@ static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_r
   h->factored = true;
   h->pk_fused = false;
   if (h->B == 0) return RLQR_OK;
+  const rlqr_rhs* scan_rhs = rhs;       // scan_carry_pc: the scan carries p and c for it
   if (is_scan(h->mode)) rhs = nullptr;  // the segment recursions do not carry the vector pass
   // run mask of a factor launch under the skip mask: !skip && in
   auto masked = [&](const int32_t* in, int32_t* out, const int32_t** run) -> hipError_t {
@@ -780,7 +812,7 @@ static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_r
       RLQR_TRY(masked(h->any_pref64 ? h->pref32 : nullptr, h->runf, &run));
       RLQR_TRY(factor_whole(h, h->ws32, run, true, st, rhs));
     } else {
-      RLQR_TRY(factor_scan(h, st));
+      RLQR_TRY(factor_scan(h, st, scan_rhs));
     }
     MaskArgs m{};
     m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
@@ -865,7 +897,12 @@ static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* ou
 static rlqr_status solve_segments(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, const int32_t* run,
                                   const double* corr, hipStream_t st) {
   if (h->nmulti == 0) return RLQR_OK;
-  for (int phase = 1; phase <= 3; ++phase) {
+  // the boundary p carried by the scan serves the first solve of its
+  // right-hand side; phase 1 and the backward chain overwrite it
+  const bool use_pc = h->pc_valid && corr == nullptr && rhs->q == h->pc_rhs.q && rhs->r == h->pc_rhs.r &&
+                      rhs->c == h->pc_rhs.c;
+  h->pc_valid = false;
+  for (int phase = use_pc ? 2 : 1; phase <= 3; ++phase) {
     for (int c = 0; c < TILE_CLASSES; ++c) {
       if (h->sseg[c].count == 0) continue;
       SolveArgs a = solve_args(h, rhs, out, true, run, corr);

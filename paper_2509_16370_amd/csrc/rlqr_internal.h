@@ -78,9 +78,22 @@ struct ScanArgs {
   float* aggr_out;
   int dist, maxN, maxchunks;
   int32_t* bad;            // per instance: set when the scan cannot be used
+  // pc != 0: the elements also carry p and c (eq. lqr-gpu-combo), built from
+  // the right-hand side q, r, c; 2 NX floats per element / aggregate (p at 0,
+  // c at NX), indexed like elems / aggr
+  int pc;
+  const double *q, *r, *c;
+  float* pce;
+  float* pca[2];
+  const float* pca_in;
+  float* pca_out;
 };
 hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tm, hipStream_t st);
 hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, bool bf16, hipStream_t st);
+// Carried p: write p_{lo(s)} of every segment s >= 1 of the launch's
+// multi-segment instances into the boundary vectors (InstMeta::ovec) from the
+// finished suffix scan (the pca buffer given as pca_in).
+hipError_t launch_scan_pc_boundary(const ScanArgs& a, int ninst, int tx, double* plo, hipStream_t st);
 int scan_result_buffer(int maxchunks);
 hipError_t scan_prepare();  // once per device before the first scan launch
 hipError_t launch_merge(const MergeArgs& a, hipStream_t st);

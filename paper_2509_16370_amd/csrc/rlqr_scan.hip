@@ -9,8 +9,10 @@
 //     P at 0, A at NX^2, C at 2 NX^2.
 // The combine (i->j) (+) (j->k) is the single-inversion form of eq.
 // lqr-gpu-combo with X = I + C_ij P_jk inverted by Gauss-Jordan elimination
-// with partial pivoting; p and c are not carried (the p-recurrence recovers p,
-// as the paper recommends).
+// with partial pivoting. By default p and c are not carried (the p-recurrence
+// recovers p, as the paper recommends); with ScanArgs::pc they are carried as
+// float32 vectors beside the elements (the paper's alternative), built from
+// one right-hand side.
 #include "rlqr_device_mw.h"
 #include "rlqr_internal.h"
 
@@ -148,8 +150,27 @@ struct ScanLds {
   float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
   float YA[C::TILE], YC[C::TILE];
   float rowbuf[2 * C::NX], colbuf[C::NX];
+  float pv1[C::NX], cv1[C::NX], pv2[C::NX], cv2[C::NX], tv[C::NX], tw[C::NX];  // carried p, c
   int piv;
 };
+
+// carried vectors of an element / aggregate (2 NX floats: p, then c)
+template <int TX, int NW>
+__device__ __forceinline__ void load_pc(float* p, float* c, const float* __restrict__ g, int tid) {
+  constexpr int NX = 16 * TX;
+  if (tid < NX) {
+    p[tid] = g[tid];
+    c[tid] = g[NX + tid];
+  }
+}
+template <int TX, int NW>
+__device__ __forceinline__ void store_pc(float* __restrict__ g, const float* p, const float* c, int tid) {
+  constexpr int NX = 16 * TX;
+  if (tid < NX) {
+    g[tid] = p[tid];
+    g[NX + tid] = c[tid];
+  }
+}
 
 // copy an element's P, A (and C if withC) from global into LDS tiles
 template <int TX, int NW>
@@ -174,9 +195,10 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
 }
 
 // acc (P1, A1, C1 in LDS) <- acc (+) next (P2, A2 in LDS, C2 in global).
+// pc: also the carried vectors (p1, c1) <- (+) (p2, c2), all in LDS.
 // Returns false if X = I + C1 P2 is singular (no pivot above tol).
 template <int TX, int NW, bool BF>
-__device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid) {
+__device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid, bool pc) {
   using C = ScanCfg<TX, NW>;
   constexpr int NX = C::NX, LDX = C::LDX, LDW = C::LDW, CB = C::CB;
   const int w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
@@ -244,6 +266,44 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
     }
   }
   __syncthreads();
+  if (pc) {
+    // while W still holds X^{-1} (eq. lqr-gpu-combo; X^{-T} = (I + P2 C1)^{-1}):
+    //   p = (X^{-1} A1)^T (p2 + P2 c1) + p1,   c = A2 X^{-1} (c1 - C1 p2) + c2
+    // one thread per row; rows >= n stay zero (the tiles are zero there and
+    // X^{-1} is the identity)
+    if (tid < NX) {
+      float v1 = s.pv2[tid], v2 = s.cv1[tid];
+      for (int j = 0; j < n; ++j) {
+        v1 = fmaf(s.P2[tid * LDX + j], s.cv1[j], v1);
+        v2 = fmaf(-s.C1[tid * LDX + j], s.pv2[j], v2);
+      }
+      s.tv[tid] = v1;
+      s.tw[tid] = v2;
+    }
+    __syncthreads();
+    float pn = 0.0f, wn = 0.0f;
+    if (tid < NX) {
+      pn = s.pv1[tid];
+      for (int j = 0; j < n; ++j) {
+        pn = fmaf(s.YA[j * LDX + tid], s.tv[j], pn);
+        wn = fmaf(s.W[tid * LDW + NX + j], s.tw[j], wn);
+      }
+    }
+    __syncthreads();
+    if (tid < NX) {
+      s.pv1[tid] = pn;
+      s.tv[tid] = wn;  // X^{-1} (c1 - C1 p2)
+    }
+    __syncthreads();
+    float cn = 0.0f;
+    if (tid < NX) {
+      cn = s.cv2[tid];
+      for (int j = 0; j < n; ++j) cn = fmaf(s.A2[tid * LDX + j], s.tv[j], cn);
+    }
+    __syncthreads();
+    if (tid < NX) s.cv1[tid] = cn;
+    __syncthreads();
+  }
   // T1 = P2 Y_A (into W left half), T2 = Y_C A2^T (into W right half)
 #pragma unroll
   for (int t = 0; t < CB; ++t) {
@@ -345,13 +405,18 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
   if (i > N) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   float* __restrict__ e = a.elems + (a.eoff[blockIdx.y] + i) * 3 * NX * NX;
-  if (i == N) {  // terminal element
+  float* __restrict__ epc = a.pc ? a.pce + (a.eoff[blockIdx.y] + i) * 2 * NX : nullptr;
+  if (i == N) {  // terminal element (eq. lqr-gpu-init-terminal): (Q_N, q_N, 0, 0, 0)
     const double* QN = a.Q + mt.oQ + (int64_t)N * n * n;
     for (int x = tid; x < NX * NX; x += 64 * NW) {
       const int r = x / NX, c = x % NX;
       e[x] = (r < n && c < n) ? (float)QN[r * n + c] : 0.0f;
       e[NX * NX + x] = 0.0f;
       e[2 * NX * NX + x] = 0.0f;
+    }
+    if (epc && tid < NX) {
+      epc[tid] = tid < n ? (float)a.q[mt.oq + (int64_t)N * n + tid] : 0.0f;
+      epc[NX + tid] = 0.0f;
     }
     return;
   }
@@ -408,6 +473,32 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
         sRi[r * LDM + c] = (r < m && c < m) ? (float)X[t][v] : 0.0f;
       }
   __syncthreads();
+  if (epc) {
+    // carried vectors of the running element: with t = -R^{-1} r_i,
+    // p = q_i + M t, c = c_{i+1} + B t
+    __shared__ float tvec[NM];
+    const double* ri = a.r + mt.or_ + (int64_t)i * m;
+    if (tid < NM) {
+      float acc = 0.0f;
+      for (int k = 0; k < m; ++k) acc = fmaf(sRi[tid * LDM + k], (float)ri[k], acc);
+      tvec[tid] = tid < m ? acc : 0.0f;
+    }
+    __syncthreads();
+    if (tid < NX) {
+      float pv = 0.0f, cv = 0.0f;
+      if (tid < n) {
+        double ps = a.q[mt.oq + (int64_t)i * n + tid], cs = a.c[mt.oc + (int64_t)(i + 1) * n + tid];
+        for (int k = 0; k < m; ++k) {
+          ps += M[tid * m + k] * (double)tvec[k];
+          cs += B[tid * m + k] * (double)tvec[k];
+        }
+        pv = (float)ps;
+        cv = (float)cs;
+      }
+      epc[tid] = pv;
+      epc[NX + tid] = cv;
+    }
+  }
   // Y = (-R^{-1}) S  (TM x 2TX blocks, inner TM)
 #pragma unroll
   for (int t = 0; t < CY; ++t) {
@@ -457,16 +548,21 @@ __global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
   const float* elems = a.elems + a.eoff[blockIdx.y] * C::ELEM;
   const int tid = threadIdx.x;
   if (tid == 0) s.piv = 0;
+  const bool pc = a.pc != 0;
+  const float* pce = pc ? a.pce + a.eoff[blockIdx.y] * 2 * C::NX : nullptr;
   load_elem<TX, NW>(s.P1, s.A1, s.C1, elems + (int64_t)e0 * C::ELEM, tid);
+  if (pc) load_pc<TX, NW>(s.pv1, s.cv1, pce + (int64_t)e0 * 2 * C::NX, tid);
   __syncthreads();
   bool ok = true;
   for (int k = e0 + 1; k < e1; ++k) {
     const float* en = elems + (int64_t)k * C::ELEM;
     load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
+    if (pc) load_pc<TX, NW>(s.pv2, s.cv2, pce + (int64_t)k * 2 * C::NX, tid);
     __syncthreads();
-    ok &= combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid);
+    ok &= combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid, pc);
   }
   store_elem<TX, NW>(a.aggr_out + (a.aoff[blockIdx.y] + c) * C::ELEM, s.P1, s.A1, s.C1, tid);
+  if (pc) store_pc<TX, NW>(a.pca_out + (a.aoff[blockIdx.y] + c) * 2 * C::NX, s.pv1, s.cv1, tid);
   if (!ok && tid == 0) a.bad[b] = 1;
 }
 
@@ -487,15 +583,36 @@ __global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
   float* out = a.aggr_out + a.aoff[blockIdx.y] * C::ELEM;
   const int tid = threadIdx.x;
   if (tid == 0) s.piv = 0;
+  const bool pc = a.pc != 0;
+  const float* pin = pc ? a.pca_in + a.aoff[blockIdx.y] * 2 * C::NX : nullptr;
   load_elem<TX, NW>(s.P1, s.A1, s.C1, in + (int64_t)c * C::ELEM, tid);
+  if (pc) load_pc<TX, NW>(s.pv1, s.cv1, pin + (int64_t)c * 2 * C::NX, tid);
   __syncthreads();
   if (c + d < nch) {
     const float* en = in + (int64_t)(c + d) * C::ELEM;
     load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
+    if (pc) load_pc<TX, NW>(s.pv2, s.cv2, pin + (int64_t)(c + d) * 2 * C::NX, tid);
     __syncthreads();
-    if (!combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid) && tid == 0) a.bad[b] = 1;
+    if (!combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid, pc) && tid == 0) a.bad[b] = 1;
   }
   store_elem<TX, NW>(out + (int64_t)c * C::ELEM, s.P1, s.A1, s.C1, tid);
+  if (pc) store_pc<TX, NW>(a.pca_out + a.aoff[blockIdx.y] * 2 * C::NX + (int64_t)c * 2 * C::NX, s.pv1, s.cv1, tid);
+}
+
+// Carried p: the suffix aggregate of chunk s is e_{lo(s) -> N+1}, whose p is
+// p_{lo(s)}; write it (float64) into segment s's boundary vector for s >= 1.
+template <int TX>
+__global__ __launch_bounds__(256) void k_scan_pc_boundary(ScanArgs a, double* __restrict__ plo) {
+  constexpr int NX = 16 * TX;
+  const int b = a.insts[blockIdx.x];
+  const InstMeta mt = a.meta[b];
+  if (mt.nseg <= 1) return;
+  const float* __restrict__ res = a.pca_in + a.aoff[blockIdx.x] * 2 * NX;
+  const int64_t cnt = (int64_t)(mt.nseg - 1) * mt.n;  // segments 1 .. nseg-1, n entries each
+  for (int64_t x = threadIdx.x; x < cnt; x += 256) {
+    const int64_t s = 1 + x / mt.n, j = x % mt.n;
+    plo[mt.ovec + s * mt.n + j] = (double)res[s * 2 * NX + j];
+  }
 }
 
 template <int TX, int NW>
@@ -535,12 +652,15 @@ static hipError_t launch_scan_tree_t(ScanArgs a, int ninst, hipStream_t st) {
   const size_t lds = scan_lds_bytes<TX, NW>();
   hipError_t e;
   a.aggr_out = a.aggr[0];
+  a.pca_out = a.pca[0];
   hipLaunchKernelGGL((k_scan_reduce<TX, NW, BF>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int d = 1; d < a.maxchunks; d *= 2) {
     a.aggr_in = a.aggr[cur];
     a.aggr_out = a.aggr[cur ^ 1];
+    a.pca_in = a.pca[cur];
+    a.pca_out = a.pca[cur ^ 1];
     a.dist = d;
     hipLaunchKernelGGL((k_scan_level<TX, NW, BF>), dim3(a.maxchunks, ninst), dim3(64 * NW), lds, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -590,6 +710,16 @@ hipError_t launch_scan_tree(const ScanArgs& a, int ninst, int tx, bool bf16, hip
     if (tx == 4) return launch_scan_tree_t<4, 16, false>(a, ninst, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_scan_pc_boundary(const ScanArgs& a, int ninst, int tx, double* plo, hipStream_t st) {
+  if (ninst <= 0) return hipSuccess;
+  if (!plo || !a.pca_in) return hipErrorInvalidValue;
+  if (tx == 1) hipLaunchKernelGGL(k_scan_pc_boundary<1>, dim3(ninst), dim3(256), 0, st, a, plo);
+  else if (tx == 2) hipLaunchKernelGGL(k_scan_pc_boundary<2>, dim3(ninst), dim3(256), 0, st, a, plo);
+  else if (tx == 4) hipLaunchKernelGGL(k_scan_pc_boundary<4>, dim3(ninst), dim3(256), 0, st, a, plo);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ segment transfer
