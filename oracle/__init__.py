@@ -14,6 +14,9 @@ Contents
     densely, solved with numpy, inertia by eigenvalues and by scipy's LDL^T.
   * crossstage.py: the arrowhead step with cross-stage variables (Section
     "Cross-Stage Variables"), densely and by the paper's Schur route.
+  * eqstep.py: stagewise equality rows eliminated into a dual-regularized
+    LQR (Section "Applying the regularized IPM to optimal control"),
+    densely and by the elimination route.
   * certificate(): the pivot test of Theorem
     "riccati-inertia-certification-theorem" from the oracle's pivots.
 """

@@ -269,6 +269,58 @@ def pack_parallel(specs, workers: int = 8) -> Packed:
     return Packed(N, n, m, delta, arrays, layout_offsets(N, n, m))
 
 
+# ---------------------------------------------------------------- stagewise equality constraints
+
+@dataclasses.dataclass
+class StageEq:
+    """ne equality rows per stage for one instance (no solver arithmetic):
+    Jacobians E_i = [Ex_i | Eu_i] (stage N: Ex only), residuals r_e and the
+    penalties eta (the dual regularization is 1 / eta)."""
+    ne: int
+    Ex: np.ndarray   # (N+1, ne, n)
+    Eu: np.ndarray   # (N, ne, m)
+    r: np.ndarray    # (N+1, ne)
+    eta: np.ndarray  # (N+1, ne) > 0
+
+
+def make_stage_eq(inst: Instance, ne: int, seed: Sequence[int], eta: float = 1e3) -> StageEq:
+    """Draw ne stagewise equality rows for every stage of `inst`.
+
+    Recipe (in this order, from their own seed stream): Ex_i ~ N(0,1)/sqrt(n+m),
+    Eu_i ~ N(0,1)/sqrt(n+m), r_e ~ N(0, 0.1^2), penalties eta * 10^U(-1, 1)
+    (one penalty per constraint, as the regularized IPM allows).
+    """
+    rng = _rng(list(seed) + [5])
+    n, m, N = inst.n, inst.m, inst.N
+    Ex = rng.standard_normal((N + 1, ne, n)) / np.sqrt(n + m)
+    Eu = rng.standard_normal((N, ne, m)) / np.sqrt(n + m)
+    r = 0.1 * rng.standard_normal((N + 1, ne))
+    pen = eta * 10.0 ** rng.uniform(-1.0, 1.0, size=(N + 1, ne))
+    return StageEq(ne, Ex, Eu, r, pen)
+
+
+def pack_stage_eq(packed: Packed, eqs: List[StageEq]) -> Dict[str, np.ndarray]:
+    """Flat arrays of the batch's equality rows. Per instance: E stage-stacked
+    (stage i < N an ne x (n+m) row-major block [Ex_i | Eu_i], stage N an
+    ne x n block), r and eta (N+1) * ne each; offsets by exclusive prefix
+    sums (`E_off`, `v_off`)."""
+    E, r, eta = [], [], []
+    e_off = [0]
+    v_off = [0]
+    for b, eq in enumerate(eqs):
+        N = int(packed.N[b])
+        blocks = [np.concatenate([eq.Ex[i], eq.Eu[i]], axis=1).reshape(-1) for i in range(N)]
+        blocks.append(eq.Ex[N].reshape(-1))
+        E.append(np.concatenate(blocks) if blocks else np.zeros(0))
+        r.append(eq.r.reshape(-1))
+        eta.append(eq.eta.reshape(-1))
+        e_off.append(e_off[-1] + E[-1].size)
+        v_off.append(v_off[-1] + r[-1].size)
+    return {"E": np.concatenate(E).astype(np.float64), "r": np.concatenate(r).astype(np.float64),
+            "eta": np.concatenate(eta).astype(np.float64),
+            "E_off": np.asarray(e_off, dtype=np.int64), "v_off": np.asarray(v_off, dtype=np.int64)}
+
+
 # ---------------------------------------------------------------- cross-stage variables
 
 @dataclasses.dataclass
