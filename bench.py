@@ -26,7 +26,9 @@ cross_stage (the uniform batch with p = 4 variables shared by every stage:
 the arrowhead step of Section "Cross-Stage Variables", factor + solve +
 refinement of the whole system, float64 and mixed). --diag-spread s gives the
 uniform batch a per-stage diagonal Delta_i (entries delta * 10^U(-s, s), the
-separate per-constraint penalties the definition allows).
+separate per-constraint penalties the definition allows). stage_eq: the
+uniform batch with --ne equality rows per stage eliminated into the LQR
+(rlqr_eq_reduce, factor, solve, rlqr_eq_recover).
 """
 import argparse
 import json
@@ -180,6 +182,84 @@ def run_xs_mode(torch, rl, packed, lhs, rhs, xsd, mode, steps, warmup, max_refin
     )
 
 
+def run_eq_mode(torch, rl, packed, lhs, rhs, eqd, ne, mode, steps, warmup, max_refine, rel_tol=REL_TOL):
+    """Newton step with stagewise equality rows: rlqr_eq_reduce (into
+    preallocated reduced blocks), rlqr_factor_rhs + rlqr_solve on the reduced
+    LQR, rlqr_eq_recover. Events: reduce | factor | solve + recover."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
+    st = rl.StageEquality(s, [ne] * packed.batch)
+    red = {k: torch.empty_like(lhs[k]) for k in ("Q", "M", "R")}
+    red.update({k: torch.empty_like(rhs[k]) for k in ("q", "r")})
+    out = {k: s.empty(k) for k in ("x", "u", "y")}
+    w = torch.empty(max(int(st.offsets["v"][-1]), 1), dtype=torch.float64, device="cuda:0")
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        lhs2, rhs2 = st.reduce(lhs, rhs, eqd, out=red)
+        if ev:
+            ev[1].record(stream)
+        s.factor(lhs2, rhs2)
+        if ev:
+            ev[2].record(stream)
+        res = s.solve(rhs2, out=out, rel_tol=rel_tol, max_refine=max_refine)
+        st.recover(eqd, out, w=w)
+        if ev:
+            ev[3].record(stream)
+        return res
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, status, relres = step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = status.cpu().numpy()[:packed.batch]
+    relres = relres.cpu().numpy()[:packed.batch]
+    ok = (relres <= rel_tol) & ((status == rl.INST_OK) | (status == rl.INST_NOT_PD))
+    stages = int(packed.N[ok].sum())
+    ms_per_step = 1e3 * wall / steps
+    return dict(
+        value=stages / (ms_per_step * 1e-3),
+        ms_per_step=ms_per_step,
+        reduce_ms=float(np.median([e[0].elapsed_time(e[1]) for e in evs])),
+        factor_ms=float(np.median([e[1].elapsed_time(e[2]) for e in evs])),
+        solve_ms=float(np.median([e[2].elapsed_time(e[3]) for e in evs])),
+        instances_ok=int(ok.sum()),
+        max_relres=float(relres.max()),
+        median_relres=float(np.median(relres)),
+        status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+        workspace_bytes=s.workspace_bytes + st.workspace_bytes,
+    )
+
+
+def cpu_baseline_eq(insts, eqs, count=512):
+    """The elimination oracle (reduce in numpy, the sequential C oracle over
+    the reduced batch on all host threads, recover) on the first `count`
+    instances."""
+    import oracle
+    from oracle import eqstep
+    from paper_2509_16370_amd import workloads as wl
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+    t0 = time.perf_counter()
+    red = [eqstep.reduce(i, e) for i, e in zip(insts[:count], eqs[:count])]
+    packed = wl.pack(red)
+    x, u, y, st, used = oracle.seq_batch(packed, nthreads=threads)
+    for b, (xb, ub, yb) in enumerate(wl.unpack_solution(packed, x, u, y)):
+        eqstep.recover(red[b], eqs[b], xb, ub)
+    t = time.perf_counter() - t0
+    stages = int(packed.N.sum())
+    return dict(value=stages / t, unit="stage-solves/s", cores=int(used), kind="oracle",
+                sample=f"first {count} instances of the batch: numpy reduction, the sequential FP64 oracle "
+                       f"over the reduced batch on {used} threads, numpy recovery of w",
+                seconds=t)
+
+
 def cpu_baseline_xs(insts, xs, count=256):
     """The cross-stage oracle (the paper's Schur route, p + 2 sequential
     Riccati solves per instance) on the first `count` instances, one thread."""
@@ -253,7 +333,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "long_horizon", "batched_ragged", "cross_stage"])
+                    choices=["batched_uniform", "long_horizon", "batched_ragged", "cross_stage", "stage_eq"])
+    ap.add_argument("--ne", type=int, default=2, help="stage_eq: equality rows per stage")
     ap.add_argument("--p", type=int, default=4, help="cross_stage: number of cross-stage variables")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--nx", type=int, default=12, help="batched_uniform: state size")
@@ -304,6 +385,17 @@ def main():
         cfg = {"batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta}
         if diag:
             cfg["delta_diag_spread"] = args.diag_spread
+    elif wk == "stage_eq":
+        n, m, N = args.nx, args.nu, args.horizon
+        insts = wl.batched_uniform(batch=args.batch, n=n, m=m, N=N, delta=args.delta)
+        packed = wl.pack(insts)
+        eqs = [wl.make_stage_eq(inst, args.ne, (1, b, 0)) for b, inst in enumerate(insts)]
+        modes = (args.modes or "fp64,mixed").split(",")
+        head = "fp64"
+        desc = (f"Newton step with stagewise equality rows: {args.batch} instances, n={n}, m={m}, N={N}, "
+                f"delta={args.delta:g}, {args.ne} equality rows per stage (penalties 1e3 * 10^U(-1, 1)), "
+                f"eliminated into the LQR, refined to {REL_TOL:g} relative KKT residual, multipliers recovered")
+        cfg = {"batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta, "ne": args.ne}
     elif wk == "long_horizon":
         inst = wl.long_horizon()[0]
         packed = wl.pack([inst])
@@ -345,6 +437,11 @@ def main():
         print(f"[bench] calibration copy: {cnt * 4} bytes read, {cnt * 4} bytes written", file=sys.stderr, flush=True)
         del src, dst
 
+    eqd = None
+    if wk == "stage_eq":
+        cs = wl.pack_stage_eq(packed, eqs)
+        eqd = {k: torch.from_numpy(cs[k]).to("cuda:0") for k in ("E", "r", "eta")}
+        torch.cuda.synchronize()
     xsd = None
     if wk == "cross_stage":
         cs = wl.pack_cross_stage(packed, xs_data)
@@ -365,7 +462,10 @@ def main():
                                    log=lambda msg: print(msg, file=sys.stderr, flush=True))
             print(f"[bench] tuned {len(plan)} buckets in {time.perf_counter() - t1:.1f}s: "
                   + ", ".join(f"{k}: {c.key()}" for k, c in plan.items()), file=sys.stderr, flush=True)
-        if xsd is not None:
+        if eqd is not None:
+            results[mode] = run_eq_mode(torch, rl, packed, lhs, rhs, eqd, args.ne, mode, steps, warmup,
+                                        max_refine, rel_tol=rel_tol)
+        elif xsd is not None:
             results[mode] = run_xs_mode(torch, rl, packed, lhs, rhs, xsd, mode, steps, warmup, max_refine,
                                         rel_tol=rel_tol)
         else:
@@ -414,7 +514,7 @@ def main():
         achieved = alg_bytes / (r["factor_ms"] * 1e-3) / 1e9
         default_uniform = (wk == "batched_uniform" and not diag
                            and (args.nx, args.nu, args.horizon, args.batch) == (12, 4, 128, 4096))
-        if wk == "batched_uniform":
+        if wk in ("batched_uniform", "stage_eq"):
             kern = ("k_factor16<%s>" if args.nx + args.nu <= 16 else "k_factor_mw<%s>") % (
                 ("double" if head == "fp64" else "float") + (", diagonal Delta" if diag else ""))
         else:
@@ -424,6 +524,15 @@ def main():
         roof = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": r["factor_ms"]}
+        if wk == "stage_eq":
+            # the elimination kernel beside it: per stage Q, M, R, q, r read and
+            # written, E (ne x (n + m)), r_e and eta read
+            n, m, ne = args.nx, args.nu, args.ne
+            red_b = 8 * (2 * (n * n + n * m + m * m + n + m) + ne * (n + m) + 2 * ne)
+            roof["reduce_kernel"] = "k_eq_reduce"
+            roof["reduce_algorithmic_bytes_per_launch"] = float(red_b * packed.N.sum())
+            roof["reduce_gbs"] = red_b * float(packed.N.sum()) / (r["reduce_ms"] * 1e-3) / 1e9
+            roof["reduce_ms"] = r["reduce_ms"]
         dtype = "f64" if head == "fp64" else "f32+f64"
     cfg.update({"workload": desc, "rel_tol": rel_tol, "max_refine": max_refine, "path": head})
     line = {
@@ -448,6 +557,8 @@ def main():
     if not args.no_cpu_baseline:
         if wk == "cross_stage":
             line["cpu_baseline"] = cpu_baseline_xs(insts, xs_data)
+        elif wk == "stage_eq":
+            line["cpu_baseline"] = cpu_baseline_eq(insts, eqs)
         elif wk == "long_horizon":
             line["cpu_baseline"] = cpu_baseline(wl.pack([wl.make_instance(64, 32, 2048, 1e-6, (3, 0, 0))]),
                                                 sample="one instance of the long-horizon shape at N=2048")

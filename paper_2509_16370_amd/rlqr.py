@@ -395,6 +395,88 @@ for _f in ("rlqr_xs_create", "rlqr_xs_factor", "rlqr_xs_solve", "rlqr_xs_inertia
     getattr(_lib, _f).restype = ctypes.c_int
 XS_EXPORTED = ("rlqr_xs_create", "rlqr_xs_factor", "rlqr_xs_solve", "rlqr_xs_inertia", "rlqr_xs_destroy")
 
+# ------------------------------------------------------------- stagewise equality rows (include/rlqr_eq.h)
+
+class _EqData(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("E", "r", "eta")]
+
+
+_lib.rlqr_eq_create.argtypes = [ctypes.POINTER(_vp), _vp, _i32p, ctypes.POINTER(ctypes.c_size_t)]
+_lib.rlqr_eq_create.restype = ctypes.c_int
+_lib.rlqr_eq_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+_lib.rlqr_eq_offsets.restype = ctypes.c_int
+_lib.rlqr_eq_reduce.argtypes = [_vp, ctypes.POINTER(_Lhs), ctypes.POINTER(_Rhs), ctypes.POINTER(_EqData)] + [_vp] * 5 + [_vp]
+_lib.rlqr_eq_reduce.restype = ctypes.c_int
+_lib.rlqr_eq_recover.argtypes = [_vp, ctypes.POINTER(_EqData), ctypes.POINTER(_Sol), _vp, _vp]
+_lib.rlqr_eq_recover.restype = ctypes.c_int
+_lib.rlqr_eq_destroy.argtypes = [_vp]
+_lib.rlqr_eq_destroy.restype = None
+EQ_EXPORTED = ("rlqr_eq_create", "rlqr_eq_offsets", "rlqr_eq_reduce", "rlqr_eq_recover", "rlqr_eq_destroy")
+RLQR_EQ_ARR_E, RLQR_EQ_ARR_V = 0, 1
+
+
+class StageEquality:
+    """rlqr_eq context over a Solver's batch: ne[b] equality rows per stage.
+    reduce() gives the reduced lhs / rhs dicts for the Solver, recover() the
+    equality multipliers w."""
+
+    def __init__(self, solver: "Solver", ne):
+        self.solver = solver
+        self.torch = solver.torch
+        self.ne = np.ascontiguousarray(ne, dtype=np.int32)
+        assert self.ne.shape[0] == solver.batch
+        ctx = _vp()
+        ws = ctypes.c_size_t(0)
+        with self.torch.cuda.device(solver.device):
+            _check(_lib.rlqr_eq_create(ctypes.byref(ctx), solver.handle, self.ne.ctypes.data_as(_i32p),
+                                       ctypes.byref(ws)), "rlqr_eq_create")
+        self.ctx, self.workspace_bytes = ctx, int(ws.value)
+        self.offsets = {}
+        for name, arr in (("E", RLQR_EQ_ARR_E), ("v", RLQR_EQ_ARR_V)):
+            off = np.zeros(solver.batch + 1, dtype=np.int64)
+            _check(_lib.rlqr_eq_offsets(self.ctx, arr, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                   "rlqr_eq_offsets")
+            self.offsets[name] = off
+
+    def __del__(self):
+        x = getattr(self, "ctx", None)
+        if x is not None and x.value and _lib is not None:
+            try:
+                _lib.rlqr_eq_destroy(x)
+            except Exception:  # interpreter shutdown
+                pass
+            self.ctx = None
+
+    def reduce(self, lhs, rhs, eq, out=None, stream=None):
+        """eq: dict of device tensors E, r, eta. Returns (lhs', rhs') with the
+        reduced Q, M, R, q, r (new tensors unless `out` is given; `out` may
+        be lhs / rhs themselves: in place) and A, B, c, delta(, delta_diag)
+        shared with the inputs."""
+        if out is None:
+            out = {k: self.torch.empty_like(lhs[k]) for k in ("Q", "M", "R")}
+            out.update({k: self.torch.empty_like(rhs[k]) for k in ("q", "r")})
+        L = _Lhs(*[_ptr(lhs.get(k)) for k in ("Q", "M", "R", "A", "B", "delta", "delta_diag")])
+        Rh = _Rhs(_ptr(rhs["q"]), _ptr(rhs["r"]), _ptr(rhs["c"]))
+        D = _EqData(_ptr(eq["E"]), _ptr(eq["r"]), _ptr(eq["eta"]))
+        _check(_lib.rlqr_eq_reduce(self.ctx, ctypes.byref(L), ctypes.byref(Rh), ctypes.byref(D),
+                                   *[_ptr(out[k]) for k in ("Q", "M", "R", "q", "r")], _stream(stream)),
+               "rlqr_eq_reduce")
+        lhs2 = dict(lhs)
+        lhs2.update({k: out[k] for k in ("Q", "M", "R")})
+        rhs2 = dict(rhs)
+        rhs2.update({k: out[k] for k in ("q", "r")})
+        return lhs2, rhs2
+
+    def recover(self, eq, sol, w=None, stream=None):
+        if w is None:
+            w = self.torch.empty(max(int(self.offsets["v"][-1]), 1), dtype=self.torch.float64,
+                                 device=self.solver.device)
+        D = _EqData(_ptr(eq["E"]), _ptr(eq["r"]), _ptr(eq["eta"]))
+        S = _Sol(_ptr(sol["x"]), _ptr(sol["u"]), _ptr(sol["y"]))
+        _check(_lib.rlqr_eq_recover(self.ctx, ctypes.byref(D), ctypes.byref(S), _ptr(w), _stream(stream)),
+               "rlqr_eq_recover")
+        return w
+
 
 def rlqr_xs_create(h, p: int):
     """Returns (context, workspace_bytes)."""

@@ -60,6 +60,28 @@ def test_cross_stage_rejects_bad_arguments():
     assert lib.rlqr_solve_multi(None, 1, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
 
 
+def test_library_exports_every_stage_equality_symbol():
+    from paper_2509_16370_amd import rlqr
+    names = _declared(os.path.join(ROOT, "include", "rlqr_eq.h"), "rlqr_eq_")
+    assert set(names) == set(rlqr.EQ_EXPORTED)
+    lib = ctypes.CDLL(rlqr.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_stage_equality_rejects_bad_arguments():
+    from paper_2509_16370_amd import rlqr
+    lib = rlqr._lib
+    x = ctypes.c_void_p()
+    assert lib.rlqr_eq_create(ctypes.byref(x), None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_eq_create(None, None, None, None) == rlqr.RLQR_E_INVALID
+    off = (ctypes.c_int64 * 2)()
+    assert lib.rlqr_eq_offsets(None, 0, off) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_eq_reduce(None, None, None, None, None, None, None, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_eq_recover(None, None, None, None, None) == rlqr.RLQR_E_INVALID
+    lib.rlqr_eq_destroy(None)
+
+
 def test_library_exports_every_network_kernel_symbol():
     from paper_2509_16370_amd import rlqr
     names = _declared(os.path.join(ROOT, "include", "rmlp.h"), "rmlp_")
