@@ -30,6 +30,7 @@ struct EqRecoverArgs {
   const EqMeta* meta;
   const double *E, *re, *eta, *x, *u;
   double* w;
+  int lds_e;  // as in EqReduceArgs
 };
 
 // Four stages per workgroup, one wavefront each: stage i = 4 blockIdx.x + w
@@ -106,23 +107,39 @@ __global__ __launch_bounds__(64 * EQ_SPB) void k_eq_reduce(EqReduceArgs a) {
   }
 }
 
-// Thread t of instance blockIdx.y: stage t / 16, row t % 16.
-__global__ __launch_bounds__(256) void k_eq_recover(EqRecoverArgs a) {
+// Sixteen lanes per stage, four stages per workgroup (one wavefront): stage
+// i = 4 blockIdx.x + g (g = lane / 16) of instance blockIdx.y. The sixteen
+// lanes copy E_i and z_i = (x_i, u_i) into their LDS slice with contiguous
+// loads, then lane 16 g + k, k < ne, forms row k's multiplier. LDS: four
+// slices of at most 16 * 96 + 96 doubles (52 KB).
+constexpr int EQ_RSPB = 4;  // stages per workgroup
+__global__ __launch_bounds__(64) void k_eq_recover(EqRecoverArgs a) {
   const EqMeta mt = a.meta[blockIdx.y];
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const int i = t >> 4, k = t & 15;
-  if (i > mt.N || k >= mt.ne) return;
+  const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+  const int i = blockIdx.x * EQ_RSPB + g;
   const int N = mt.N, n = mt.n, m = mt.m, ne = mt.ne;
+  extern __shared__ double sRec[];  // per stage: lds_e doubles of E, then RLQR_MAX_NXU of z
+  double* sE = sRec + (size_t)g * (a.lds_e + RLQR_MAX_NXU);
+  double* sz = sE + a.lds_e;
+  const bool live = i <= N && ne > 0;
   const int s = i < N ? n + m : n;
-  const double* __restrict__ Er = a.E + mt.oE + (int64_t)i * ne * (n + m) + (int64_t)k * s;
-  const double* __restrict__ xi = a.x + mt.ox + (int64_t)i * n;
-  const int64_t v = mt.ov + (int64_t)i * ne + k;
-  double acc = a.re[v];
-  for (int j = 0; j < n; ++j) acc = fma(Er[j], xi[j], acc);
-  if (i < N) {
-    const double* __restrict__ ui = a.u + mt.ou + (int64_t)i * m;
-    for (int j = 0; j < m; ++j) acc = fma(Er[n + j], ui[j], acc);
+  if (live) {
+    const double* __restrict__ E = a.E + mt.oE + (int64_t)i * ne * (n + m);
+    for (int x = l; x < ne * s; x += 16) sE[x] = E[x];
+    const double* __restrict__ xi = a.x + mt.ox + (int64_t)i * n;
+    for (int x = l; x < n; x += 16) sz[x] = xi[x];
+    if (i < N) {
+      const double* __restrict__ ui = a.u + mt.ou + (int64_t)i * m;
+      for (int x = l; x < m; x += 16) sz[n + x] = ui[x];
+    }
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!live || l >= ne) return;
+  const int64_t v = mt.ov + (int64_t)i * ne + l;
+  double acc = a.re[v];
+  for (int j = 0; j < s; ++j) acc = fma(sE[l * s + j], sz[j], acc);
   a.w[v] = a.eta[v] * acc;
 }
 
@@ -134,6 +151,7 @@ using namespace rlqr;
 struct rlqr_eq {
   const rlqr_handle* h = nullptr;
   int B = 0, maxN = 0, lds_e = 1;
+  int64_t max_rows = 0;  // max over the batch of (N + 1) ne
   std::vector<int64_t> offE, offV;
   EqMeta* meta = nullptr;
   size_t bytes = 0;
@@ -177,6 +195,8 @@ rlqr_status rlqr_eq_create(rlqr_eq** ctx, const rlqr_handle* h, const int32_t* n
     c->offE[b + 1] = c->offE[b] + (int64_t)ne[b] * ((int64_t)N[b] * (n[b] + m[b]) + n[b]);
     c->offV[b + 1] = c->offV[b] + (int64_t)ne[b] * (N[b] + 1);
     c->maxN = N[b] > c->maxN ? N[b] : c->maxN;
+    const int64_t rows = (int64_t)(N[b] + 1) * ne[b];
+    c->max_rows = rows > c->max_rows ? rows : c->max_rows;
     const int le = ne[b] * (n[b] + m[b]);
     c->lds_e = le > c->lds_e ? le : c->lds_e;
   }
@@ -231,8 +251,11 @@ rlqr_status rlqr_eq_recover(rlqr_eq* ctx, const rlqr_eq_data* eq, const rlqr_sol
   EqRecoverArgs a{};
   a.meta = ctx->meta;
   a.E = eq->E; a.re = eq->r; a.eta = eq->eta; a.x = z->x; a.u = z->u; a.w = w;
-  const unsigned gx = (unsigned)(((int64_t)(ctx->maxN + 1) * 16 + 255) / 256);
-  hipLaunchKernelGGL(k_eq_recover, dim3(gx, ctx->B), dim3(256), 0, (hipStream_t)stv, a);
+  if (ctx->max_rows == 0) return RLQR_OK;
+  a.lds_e = ctx->lds_e;
+  const unsigned gx = (unsigned)((ctx->maxN + 1 + EQ_RSPB - 1) / EQ_RSPB);
+  const size_t lds = sizeof(double) * (size_t)EQ_RSPB * (size_t)(ctx->lds_e + RLQR_MAX_NXU);  // <= 52 KB
+  hipLaunchKernelGGL(k_eq_recover, dim3(gx, ctx->B), dim3(64), lds, (hipStream_t)stv, a);
   return hipGetLastError() == hipSuccess ? RLQR_OK : RLQR_E_HIP;
 }
 
