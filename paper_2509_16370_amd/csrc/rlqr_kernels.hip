@@ -739,12 +739,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     stgA[oZ] = 0.0;
     stgB[oZ] = 0.0;
   }
-  if (N > 0)
+  // DG: Delta_{k+1}'s diagonal rides with step k's staged blocks (after the zero cell)
+  const int oD = oZ + 1;
+  if (N > 0) {
     dma_stage(stgA, a.Q + mt.oQ, a.M + mt.oM, a.R + mt.oR, Ag, Bg, n, m, lane);
+    if constexpr (DG) dma_block(ddg + n, stgA + oD, n, lane);
+  }
   double rmax = 0.0, bmax = 0.0;
 
   // x_0, then z_0 = Z_0 x_0 (u_0 and y_0)
-  // DG: Delta_0's entry of the lane (d0) and Delta_{k+1}'s (dn, one step ahead)
+  // DG: Delta_0's entry of the lane (d0); Delta_{k+1}'s (dn) is staged with step k's blocks
   const double d0 = DG ? ld_or0(ddg, col, xr) : delta;
   double x;
   {
@@ -796,7 +800,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   double qok = N > 0 ? ld_or0(qo, col, xr) : 0.0;
   double rok = N > 0 ? ld_or0(ro, col - n, ur) : 0.0;
   double con = N > 0 ? ld_or0(co, (int64_t)n + col, xr) : 0.0;
-  double dn = (DG && N > 0) ? ld_or0(ddg, (int64_t)n + col, xr) : delta;
+  double dn = delta;
 
   for (int k = 0; k < N; ++k) {
     if constexpr (CP) asm volatile("" : "+v"(pz), "+v"(px));
@@ -804,13 +808,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     double* stgn = (k & 1) ? stgA : stgB;
     wait_vmem();  // step k's blocks, tiles and vectors have landed
     wave_sync();
-    // DG: 1 / Delta_{k+1}'s entry, off the step's dependent chain
+    // DG: Delta_{k+1}'s entry from the staging buffer and its reciprocal, off
+    // the step's dependent chain
+    if constexpr (DG) dn = xr ? stgc[oD + col] : 0.0;
     const double idn = (DG && xr) ? 1.0 / dn : 0.0;
     const bool more = k + 1 < N;
     if (more) {
       const int k1 = k + 1;
       dma_stage(stgn, a.Q + mt.oQ + (int64_t)k1 * n * n, a.M + mt.oM + (int64_t)k1 * n * m,
                 a.R + mt.oR + (int64_t)k1 * m * m, Ag + (int64_t)k1 * n * n, Bg + (int64_t)k1 * n * m, n, m, lane);
+      if constexpr (DG) dma_block(ddg + (int64_t)(k1 + 1) * n, stgn + oD, n, lane);
     }
     // step k+1's tiles and vectors
     double Zk1[4], Xn1[4];
@@ -826,7 +833,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double qok1 = ld_or0(qo, (int64_t)k1 * n + col, xr);
     const double rok1 = ld_or0(ro, (int64_t)k1 * m + (col - n), ur);
     const double con1 = ld_or0(co, (int64_t)(k1 + 1) * n + col, xr);
-    const double dn1 = DG ? ld_or0(ddg, (int64_t)(k1 + 1) * n + col, xr) : delta;
 
     // u_k, y_k from z_k; write the totals
     const double uk = ur ? kk - zx : 0.0;
@@ -899,7 +905,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       Zk[v] = Zk1[v];
       Xn[v] = Xn1[v];
     }
-    pk = pn; kk = kk1; pn = pn1; cn = cn1; dn = dn1;
+    pk = pn; kk = kk1; pn = pn1; cn = cn1;
     xold = xoldn; yold = yoldn; uold = uold1; xoldn = xoldn1; yoldn = yoldn1;
     qok = qok1; rok = rok1; con = con1;
   }
