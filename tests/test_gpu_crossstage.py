@@ -240,3 +240,27 @@ def test_solve_multi_matches_single_solves(rl, mode, max_rhs):
             scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y")))
             err = max(np.abs(a - ref[k]).max() for a, k in zip(sols[b], ("x", "u", "y")))
             assert err <= 1e-7 * scale
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_cross_stage_with_per_stage_diagonal(rl, mode):
+    """The arrowhead step over an LQR with a per-stage diagonal Delta_i
+    (rlqr_lhs.delta_diag): the Schur route rides on the diagonal kernels;
+    checked against the dense arrowhead definition (whose LQR block carries
+    the -Delta_i blocks)."""
+    print(f"[gpu] cross-stage with a per-stage diagonal mode={mode}", flush=True)
+    rng = np.random.default_rng(4321)
+    insts, xsd = [], []
+    for k in range(10):
+        n = int(rng.integers(2, 6)); m = int(rng.integers(1, 4)); N = int(rng.integers(1, 12))
+        inst = wl.make_instance(n, m, N, 1e-3, (98, k, 0), indefinite=(k % 5 == 3), diag_spread=1.5)
+        insts.append(inst)
+        xsd.append(wl.make_cross_stage(inst, 3, (98, k, 0)))
+    r = run_xs(rl, insts, xsd, mode)
+    tol = 1e-10 if mode == "fp64" else 1e-7
+    for b, (inst, xs) in enumerate(zip(insts, xsd)):
+        w, th = ocs.dense(inst, xs.J, xs.H, (inst.q, inst.r, inst.c), xs.rth)
+        check(inst, xs, r["sols"][b], r["theta"][b], w, th, tol)
+        assert r["relres"][b] <= 1e-10
+        want_in = ocs.inertia(inst, xs.J, xs.H)
+        assert r["verdict"][b] == int(want_in == ocs.target_inertia(inst, 3)), b

@@ -176,3 +176,17 @@ def test_stage_equality_full_size_sampled(rl):
     sub["w"] = np.concatenate([r["w"][v[i]:v[i + 1]] for i in idx])
     sub["cs"] = wl.pack_stage_eq(sp, sub_eqs)
     check(sub_insts, sub_eqs, sub, tol=1e-6, rel_tol=1e-8)
+
+
+def test_stage_equality_with_per_stage_diagonal(rl):
+    """Equality rows eliminated into an LQR whose dynamics carry a per-stage
+    diagonal Delta_i: the reduced lhs keeps delta_diag, the diagonal kernels
+    run the step."""
+    print("[gpu] stage equality with a per-stage diagonal", flush=True)
+    insts, eqs = [], []
+    for b, (n, m, N) in enumerate(SHAPES):
+        inst = wl.make_instance(n, m, N, 1e-3, (96, 0, b), indefinite=(b % 4 == 3), diag_spread=1.0)
+        insts.append(inst)
+        eqs.append(wl.make_stage_eq(inst, 1 + b % 3, (96, 0, b)))
+    r = step(rl, insts, eqs)
+    check(insts, eqs, r, inertia_full=True)
