@@ -118,8 +118,8 @@ typedef struct {        /* left-hand side: stage blocks and regularization      
    * (non-finite) results. When set, delta is not read and may be NULL. The
    * state pivots are then those of the symmetric representative S_hat_i =
    * I + Delta_i^{1/2} P_i Delta_i^{1/2} (Section "Inertia Certification"),
-   * which is similar to I + Delta_i P_i. Sequential modes only: the scan
-   * modes return RLQR_E_UNSUPPORTED from rlqr_factor. */
+   * which is similar to I + Delta_i P_i. All modes (in the scan modes the
+   * interval elements' C carries Delta_{i+1}). */
   const double *delta_diag;
 } rlqr_lhs;
 
@@ -193,8 +193,7 @@ rlqr_status rlqr_layout_offsets(const rlqr_handle *h, int32_t array, int64_t *of
  * S_hat_{k+1}^{-1} D^{-1} = P_{k+1} (I + Delta_{k+1} P_{k+1})^{-1}. The lhs
  * arrays must stay valid and unchanged until the last rlqr_solve/rlqr_residual
  * on this factorization, which re-read them.
- * Errors: RLQR_E_INVALID (NULL pointer), RLQR_E_UNSUPPORTED (delta_diag in a
- * scan mode), RLQR_E_HIP.
+ * Errors: RLQR_E_INVALID (NULL pointer), RLQR_E_HIP.
  */
 rlqr_status rlqr_factor(rlqr_handle *h, const rlqr_lhs *lhs, rlqr_stream st);
 

@@ -751,6 +751,7 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st, const rlqr_rhs* rh
     ScanArgs a{};
     a.meta = h->meta; a.insts = G.insts; a.eoff = G.eoff; a.aoff = G.aoff;
     a.Q = h->lhs.Q; a.M = h->lhs.M; a.R = h->lhs.R; a.A = h->lhs.A; a.B = h->lhs.B; a.delta = h->lhs.delta;
+    a.dd = h->lhs.delta_diag;
     a.elems = G.elems; a.aggr[0] = G.aggr[0]; a.aggr[1] = G.aggr[1];
     a.maxN = G.maxN; a.maxchunks = G.maxchunks; a.bad = h->bad;
     if (pc) {
@@ -775,6 +776,7 @@ static hipError_t factor_scan(rlqr_handle* h, hipStream_t st, const rlqr_rhs* rh
     if (h->sseg[c].count == 0) continue;
     TransferArgs t{};
     t.meta = h->meta; t.segs = h->sseg[c].d; t.A = h->lhs.A; t.B = h->lhs.B; t.ws = h->ws32; t.psi = h->psi;
+    t.dd = h->lhs.delta_diag;
     if ((e = launch_transfer(c, t, h->sseg[c].count, st)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -784,7 +786,6 @@ static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_r
   if (!h || !lhs) return RLQR_E_INVALID;
   if (h->B > 0 && (!lhs->Q || !lhs->M || !lhs->R || !lhs->A || !lhs->B || (!lhs->delta && !lhs->delta_diag)))
     return RLQR_E_INVALID;
-  if (lhs->delta_diag && is_scan(h->mode)) return RLQR_E_UNSUPPORTED;
   if (rhs && h->B > 0 && (!rhs->q || !rhs->r || !rhs->c)) return RLQR_E_INVALID;
   h->lhs = *lhs;
   h->factored = true;

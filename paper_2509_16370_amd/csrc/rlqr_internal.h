@@ -72,6 +72,7 @@ struct ScanArgs {
   const int64_t* eoff;     // per instance: element offset (in elements) into elems
   const int64_t* aoff;     // per instance: chunk-aggregate offset (in elements) into aggr
   const double *Q, *M, *R, *A, *B, *delta;
+  const double* dd;        // if set: per-stage diagonal Delta_i (at InstMeta::od), delta unused
   float* elems;            // N + 1 interval elements per instance
   float* aggr[2];          // chunk aggregates, ping-pong
   const float* aggr_in;
@@ -106,6 +107,7 @@ struct TransferArgs {
   const double *A, *B;
   const void* ws;          // float32 factor tiles
   double* psi;             // per segment: Psi (row-major n x n), then Psi^T
+  const double* dd;        // if set: per-stage diagonal Delta_i; the X tiles then hold D X D
 };
 hipError_t launch_transfer(int cls, const TransferArgs& a, int nblocks, hipStream_t st);
 

@@ -788,7 +788,10 @@ hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, 
 // same kernel with a single 16 x 16 block (its workspace layout is identical).
 template <int TX, int TZ, int NW>
 static hipError_t launch_seg_t(const SolveArgs& a, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_solve_mw<float, TX, TZ, NW, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+  if (a.dd)
+    hipLaunchKernelGGL((k_solve_mw<float, TX, TZ, NW, true, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_solve_mw<float, TX, TZ, NW, true, false>), dim3(nblocks), dim3(64 * NW), 0, st, a);
   return hipGetLastError();
 }
 

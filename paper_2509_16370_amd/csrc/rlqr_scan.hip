@@ -420,7 +420,9 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
     }
     return;
   }
-  const double delta = a.delta[b];
+  const double delta = a.dd ? 0.0 : a.delta[b];
+  // per-stage diagonal: C takes Delta_{i+1} (the regularization of the row defining x_{i+1})
+  const double* ddn = a.dd ? a.dd + mt.od + (int64_t)(i + 1) * n : nullptr;
   const double* Q = a.Q + mt.oQ + (int64_t)i * n * n;
   const double* M = a.M + mt.oM + (int64_t)i * n * m;
   const double* R = a.R + mt.oR + (int64_t)i * m * m;
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
       float val = 0.0f;
       if (part == 0) val = in ? (float)(Q[r * n + c] + (double)acc[v]) : 0.0f;             // P
       else if (part == 1) val = in ? (float)(A[r * n + c] + (double)acc[v]) : 0.0f;        // A
-      else val = in ? (float)((r == c ? delta : 0.0) - (double)acc[v]) : 0.0f;             // C
+      else val = in ? (float)((r == c ? (ddn ? ddn[r] : delta) : 0.0) - (double)acc[v]) : 0.0f;  // C
       e[part * NX * NX + r * NX + c] = val;
     }
   }
@@ -726,7 +728,9 @@ hipError_t launch_scan_pc_boundary(const ScanArgs& a, int ninst, int tx, double*
 
 // Psi = F_{hi-1} ... F_lo for the segment [lo, hi) of blockIdx.x, with
 // F_k = S_hat_{k+1}^{-1} (A_k + B_k K_k) taken from the float32 factor tiles
-// (Z_k holds -K_k in its (u, x) block, X_{k+1} holds -S_hat_{k+1}^{-1}).
+// (Z_k holds -K_k in its (u, x) block, X_{k+1} holds -S_hat_{k+1}^{-1}; with a
+// per-stage diagonal X~ = D X D, and F_k = (I + Delta P)^{-1}(A + B K) takes
+// X~ Delta^{-1} in place of X).
 // Per stage: V = [Psi; K Psi], T = [A B] V, Psi <- -X T, float32 MFMA.
 // The last segment of an instance is skipped: no boundary chain uses it.
 template <int TX, int TZ, int NW>
@@ -763,10 +767,19 @@ __global__ __launch_bounds__(64 * NW) void k_transfer(TransferArgs a) {
       if (r >= n && r < n + m && c < n) sK[r * LX + c] = -zt[x];
     }
     const float* xt = ws + (int64_t)(k + 1) * STAGE + TZ * TZ * 256;
-    for (int x = tid; x < TX * TX * 256; x += 64 * NW) {
-      const int bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
-      const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
-      sX[r * LX + c] = (r < n && c < n) ? xt[x] : 0.0f;
+    if (a.dd) {
+      const double* dn = a.dd + mt.od + (int64_t)(k + 1) * n;
+      for (int x = tid; x < TX * TX * 256; x += 64 * NW) {
+        const int bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+        const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
+        sX[r * LX + c] = (r < n && c < n) ? (float)((double)xt[x] / dn[c]) : 0.0f;
+      }
+    } else {
+      for (int x = tid; x < TX * TX * 256; x += 64 * NW) {
+        const int bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+        const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
+        sX[r * LX + c] = (r < n && c < n) ? xt[x] : 0.0f;
+      }
     }
     const double* A = Ag + (int64_t)k * n * n;
     const double* B = Bg + (int64_t)k * n * m;

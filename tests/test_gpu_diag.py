@@ -165,16 +165,58 @@ def test_diag_stacked_right_hand_sides(rl):
             assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max()), (j, k)
 
 
-@pytest.mark.parametrize("mode", ["scan", "scan_bf16"])
-def test_diag_scan_modes_unsupported(rl, mode):
-    print(f"[gpu] diag scan unsupported mode={mode}", flush=True)
-    insts = _batch(ONE_WAVE[:2], 1.0, tag=15)
+@pytest.mark.parametrize("mode,chunk", [("scan", 3), ("scan", 8), ("scan_bf16", 5)])
+def test_diag_scan_modes_match_oracle(rl, mode, chunk):
+    """Scan modes: the interval elements' C carries Delta_{i+1}, the segment
+    recursions and the transfer matrices take X~ Delta^{-1}; one-wavefront
+    and multi-wavefront classes cut into segments of `chunk` stages."""
+    print(f"[gpu] diag scan mode={mode} chunk={chunk}", flush=True)
+    shapes = [(4, 1, 40), (12, 4, 33), (5, 3, 1), (8, 2, 0), (20, 8, 29), (36, 10, 17), (64, 32, 12), (3, 2, 64)]
+    insts = _batch(shapes, 1.0, delta=1e-4, tag=30 + chunk)
+    import torch
     packed = wl.pack(insts)
     lhs, rhs = rl.to_device(packed)
-    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
-    with pytest.raises(rl.RlqrError) as e:
-        s.factor(lhs)
-    assert "UNSUPPORTED" in str(e.value) or "-5" in str(e.value)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, scan_chunk=chunk)
+    s.factor(lhs)
+    out, status, relres = s.solve(rhs, rel_tol=1e-8, max_refine=10)
+    verdict, first_bad, inertia = s.pivot_inertia()
+    torch.cuda.synchronize()
+    B = packed.batch
+    r = dict(sols=wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y"))),
+             relres=relres.cpu().numpy()[:B], verdict=verdict.cpu().numpy()[:B],
+             first_bad=first_bad.cpu().numpy()[:B], inertia=inertia.cpu().numpy().reshape(-1, 3)[:B])
+    for b, inst in enumerate(insts):
+        ref = oracle.seq(inst)
+        ok, fb, inr = oracle.certificate(inst, ref["dS"], ref["dG"])
+        assert r["verdict"][b] == int(ok) and r["first_bad"][b] == fb, b
+        if ok:
+            assert tuple(r["inertia"][b]) == inr, b
+        assert r["relres"][b] <= 1e-8, (b, r["relres"][b])
+        if ok:
+            scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y") if ref[k].size))
+            err = max(np.abs(a - ref[k]).max() if a.size else 0.0 for a, k in zip(r["sols"][b], ("x", "u", "y")))
+            assert err <= 1e-7 * scale, (b, err)
+
+
+def test_diag_scan_carrying_p_and_c(rl):
+    """The scan carrying p and c over a per-stage diagonal."""
+    import torch
+    print("[gpu] diag scan carrying p and c", flush=True)
+    insts = _batch([(12, 4, 40), (4, 1, 64), (20, 8, 33), (12, 4, 9)], 1.0, delta=1e-4, tag=40)
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    s = rl.Solver(packed.N, packed.n, packed.m, mode="scan", scan_chunk=4, scan_carry_pc=True)
+    s.factor(lhs, rhs)
+    out, status, relres = s.solve(rhs, rel_tol=1e-8, max_refine=10)
+    torch.cuda.synchronize()
+    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
+    for b, inst in enumerate(insts):
+        ref = oracle.seq(inst)
+        assert float(relres[b]) <= 1e-8
+        if not inst.indefinite:
+            scale = max(1.0, *(np.abs(ref[k]).max() for k in ("x", "u", "y")))
+            err = max(np.abs(a - ref[k]).max() for a, k in zip(sols[b], ("x", "u", "y")))
+            assert err <= 1e-7 * scale, (b, err)
 
 
 @pytest.mark.parametrize("shape", [(4, 1), (8, 2), (12, 4)])
