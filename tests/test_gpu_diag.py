@@ -8,7 +8,9 @@ variables to Delta = I, the KKT inertia and a determinant identity):
 element-wise at 1e-10 (float64 path) or 1e-7 (refined), the relative KKT
 residual at 1e-8, and verdict / first failing pivot / inertia exactly.
 Tile classes covered: the one-wavefront kernel (n + m <= 16) and four
-multi-wavefront classes; horizons include N = 0 and 1.
+multi-wavefront classes; horizons include N = 0 and 1; the sequential modes,
+the scan modes (float32 and bfloat16 combine products) and the scan carrying
+p and c.
 """
 import numpy as np
 import pytest
