@@ -26,6 +26,14 @@ mu <- max(mu / 10, 1e-9) when the barrier error is <= 10 mu; converged when
 |grad_x L|_inf, |c|_inf, |g + s|_inf and |s z|_inf are all <= 1e-6; at most
 200 iterations. Cold start: x_i = x0, u_i = 0, y = 0, s = max(-g, 1e-2),
 z = mu0 / s.
+
+Optional stagewise equality rows e_i(u) = E_u u_i - b_i = 0 (i < N), ne rows
+per stage with multipliers y_e: their rows of the Newton-KKT system carry the
+same -1/eta dual regularization and are eliminated into the LQR (Section
+"Applying the regularized IPM to optimal control"): R_i += eta E_u^T E_u,
+r_i += eta E_u^T e_i, then dy_e = eta (E_u du_i + e_i) with the full step
+y_e <- y_e + dy_e; the merit gains y_e^T e + eta/2 |e|^2 and the
+convergence test |e|_inf.
 """
 from __future__ import annotations
 
@@ -52,13 +60,17 @@ class State:
     z: np.ndarray   # (N+1, ng)
     mu: float
     rho: float = 0.0
+    ye: Optional[np.ndarray] = None  # (N, ne) multipliers of the stagewise equality rows
 
 
 class Problem:
     """One problem b of a TrajectorySet: f, c, g and their derivatives."""
 
-    def __init__(self, ts, b: int):
+    def __init__(self, ts, b: int, eq=None):
+        """eq: optional (E_u (ne, m), b (N, ne)) stagewise equality rows E_u u_i = b_i."""
         self.ts = ts
+        self.Eu = None if eq is None else np.atleast_2d(np.asarray(eq[0], dtype=float))
+        self.eb = None if eq is None else np.asarray(eq[1], dtype=float).reshape(ts.N, -1)
         self.n, self.m, self.N = ts.n, ts.m, ts.N
         self.ng = 2 + 2 * ts.m
         self.x0 = ts.x0[b].astype(float)
@@ -130,11 +142,18 @@ class Problem:
         return w @ self.Gx, w[:-1] @ self.Gu
 
     # ---- IPM quantities
+    def e(self, u):
+        """Stagewise equality residuals E_u u_i - b_i, (N, ne)."""
+        return u @ self.Eu.T - self.eb
+
     def grad_L(self, st: State):
         gx, gu = self.grad_f(st.x, st.u)
         cx, cu = self.jac_c_T(st.x, st.u, st.y)
         zx, zu = self.jac_g_T(st.z)
-        return gx + cx + zx, gu + cu + zu
+        gu = gu + cu + zu
+        if self.Eu is not None:
+            gu = gu + st.ye @ self.Eu
+        return gx + cx + zx, gu
 
     def errors(self, st: State, mu: Optional[float] = None):
         """(|grad L|, |c|, |g + s|, |s z - mu|) in the inf-norm; mu = 0 gives |s z|."""
@@ -142,15 +161,22 @@ class Problem:
         c = self.c(st.x, st.u)
         gs = (self.g(st.x, st.u) + st.s) * self.mask
         sz = (st.s * st.z - (mu or 0.0)) * self.mask
-        return (max(np.abs(gx).max(), np.abs(gu).max() if gu.size else 0.0), np.abs(c).max(),
-                np.abs(gs).max(), np.abs(sz).max())
+        err = (max(np.abs(gx).max(), np.abs(gu).max() if gu.size else 0.0), np.abs(c).max(),
+               np.abs(gs).max(), np.abs(sz).max())
+        if self.Eu is not None and self.N:
+            err = err + (np.abs(self.e(st.u)).max(),)
+        return err
 
     def merit(self, x, u, s, st: State, mu: float):
         c = self.c(x, u)
         gs = (self.g(x, u) + s) * self.mask
         logs = np.sum(np.log(np.where(self.mask > 0, s, 1.0)))
-        return (self.f(x, u) - mu * logs + np.sum(st.y * c) + np.sum(st.z * gs)
-                + 0.5 * ETA * (np.sum(c * c) + np.sum(gs * gs)))
+        val = (self.f(x, u) - mu * logs + np.sum(st.y * c) + np.sum(st.z * gs)
+               + 0.5 * ETA * (np.sum(c * c) + np.sum(gs * gs)))
+        if self.Eu is not None:
+            e = self.e(u)
+            val += np.sum(st.ye * e) + 0.5 * ETA * np.sum(e * e)
+        return val
 
     def merit_slope(self, st: State, mu, dx, du, ds):
         """Directional derivative of the merit along (dx, du, ds) at st (y, z fixed)."""
@@ -160,7 +186,10 @@ class Problem:
         cx, cu = self.jac_c_T(st.x, st.u, st.y + ETA * c)
         zx, zu = self.jac_g_T(st.z + ETA * gs)
         dsg = (-mu / np.where(self.mask > 0, st.s, 1.0) + st.z + ETA * gs) * self.mask
-        return np.sum((gx + cx + zx) * dx) + np.sum((gu + cu + zu) * du) + np.sum(dsg * ds)
+        eu = 0.0
+        if self.Eu is not None:
+            eu = (st.ye + ETA * self.e(st.u)) @ self.Eu
+        return np.sum((gx + cx + zx) * dx) + np.sum((gu + cu + zu + eu) * du) + np.sum(dsg * ds)
 
     def newton_lqr(self, st: State, mu: float, rho: float):
         """The dual-regularized LQR of the reduced Newton-KKT system, as an
@@ -192,6 +221,9 @@ class Problem:
         Bdyn = ts.dt * sech2[:, :, None] * ts.B[None]
         q = gx + (Sig * rz) @ self.Gx
         r = gu + (Sig[:N] * rz[:N]) @ self.Gu
+        if self.Eu is not None:  # the equality rows, eliminated through their -1/eta block
+            R = R + ETA * (self.Eu.T @ self.Eu)[None]
+            r = r + ETA * self.e(u) @ self.Eu
         c = self.c(x, u)
         inst = Instance(n, m, N, 1.0 / ETA, Q, M, R, Adyn, Bdyn, q, r, c)
         return inst, Sig, rz
@@ -203,7 +235,8 @@ def cold_start(p: Problem, mu0: float = 0.1) -> State:
     u = np.zeros((N, m))
     s = np.maximum(-p.g(x, u), 1e-2) * p.mask + (1 - p.mask)
     z = (mu0 / s) * p.mask
-    return State(x, u, np.zeros((N + 1, n)), s, z, mu0)
+    ye = None if p.Eu is None else np.zeros((N, p.Eu.shape[0]))
+    return State(x, u, np.zeros((N + 1, n)), s, z, mu0, ye=ye)
 
 
 def warm_start(p: Problem, x, u, y, logz) -> State:
@@ -212,7 +245,8 @@ def warm_start(p: Problem, x, u, y, logz) -> State:
     s = np.maximum(-p.g(x, u), 1e-2) * p.mask + (1 - p.mask)
     z = np.exp(logz) * p.mask
     mu0 = float(np.clip(np.sum(s * z) / np.sum(p.mask), 1e-9, 0.1))
-    return State(x.copy(), u.copy(), y.copy(), s, z, mu0)
+    ye = None if p.Eu is None else np.zeros((p.N, p.Eu.shape[0]))
+    return State(x.copy(), u.copy(), y.copy(), s, z, mu0, ye=ye)
 
 
 def frac_to_boundary(v, dv, tau, mask):
@@ -245,6 +279,7 @@ def step(p: Problem, st: State, log=None) -> Dict:
     """One IPM iteration in place. Returns diagnostics."""
     mu = st.mu
     dx, du, dy, ds, dz, rho = direction(p, st, mu, st.rho)
+    dye = None if p.Eu is None else ETA * (du @ p.Eu.T + p.e(st.u))
     tau = max(0.99, 1.0 - mu)
     a_s = frac_to_boundary(st.s, ds, tau, p.mask)
     a_z = frac_to_boundary(st.z, dz, tau, p.mask)
@@ -259,6 +294,8 @@ def step(p: Problem, st: State, log=None) -> Dict:
     st.u = st.u + a * du
     st.s = (st.s + a * ds) * p.mask + (1 - p.mask)
     st.y = st.y + dy
+    if dye is not None:
+        st.ye = st.ye + dye
     st.z = (st.z + a_z * dz) * p.mask
     st.rho = rho / 3.0
     err = p.errors(st, mu)

@@ -188,3 +188,62 @@ def test_full_size_problems_converge():
     for b in range(3):
         st, it, ok = ipm.solve(ipm.Problem(ts, b))
         assert ok and it <= 40, (b, it)
+
+
+# ---- stagewise equality rows E_u u_i = b_i, eliminated through their -1/eta block
+
+def _eq(ts, ne=1, bval=0.1):
+    Eu = np.zeros((ne, ts.m))
+    for k in range(ne):
+        Eu[k, k], Eu[k, k + 1] = 1.0 / np.sqrt(2), -1.0 / np.sqrt(2)
+    return Eu, np.full((ts.N, ne), bval)
+
+
+def test_ipm_with_stage_equalities_matches_scipy_slsqp():
+    from scipy.optimize import minimize
+    ts = wl.trajectory_problems(1, N=6, n=3, m=2, xmax=0.3)
+    Eu, eb = _eq(ts)
+    p = ipm.Problem(ts, 0, eq=(Eu, eb))
+    st, it, ok = ipm.solve(p)
+    assert ok
+    w0 = _pack(p, ipm.cold_start(p).x, ipm.cold_start(p).u)
+    obj = lambda w: p.f(*_unpack(p, w))
+    cons = [dict(type="eq", fun=lambda w: p.c(*_unpack(p, w)).ravel()),
+            dict(type="eq", fun=lambda w: p.e(_unpack(p, w)[1]).ravel()),
+            dict(type="ineq", fun=lambda w: -p.g(*_unpack(p, w))[p.mask > 0])]
+    res = minimize(obj, w0, constraints=cons, method="SLSQP", options=dict(ftol=1e-14, maxiter=500))
+    assert res.success, res.message
+    x, u = _unpack(p, res.x)
+    assert np.allclose(st.x, x, atol=1e-5) and np.allclose(st.u, u, atol=1e-5)
+    assert np.abs(p.e(st.u)).max() <= 1e-6
+
+
+def test_stage_equalities_first_order_conditions():
+    """Full-width model at N = 24 with two equality rows per stage:
+    stationarity of f + y^T c + y_e^T e + z^T g by finite differences,
+    feasibility of c, e and g, and complementarity."""
+    ts = wl.trajectory_problems(1, N=24)
+    p = ipm.Problem(ts, 0, eq=_eq(ts, ne=2, bval=0.05))
+    st, it, ok = ipm.solve(p)
+    assert ok and it < 60
+    w = _pack(p, st.x, st.u)
+
+    def lag(v):
+        x, u = _unpack(p, v)
+        return (p.f(x, u) + np.sum(st.y * p.c(x, u)) + np.sum(st.ye * p.e(u))
+                + np.sum((st.z * p.g(x, u))[p.mask > 0]))
+
+    assert np.abs(_fd_grad(lag, w)).max() <= 1e-5
+    assert np.abs(p.c(st.x, st.u)).max() <= 1e-6 and np.abs(p.e(st.u)).max() <= 1e-6
+    g = p.g(st.x, st.u)[p.mask > 0]
+    assert g.max() <= 1e-6 and st.z[p.mask > 0].min() >= 0.0
+    assert np.abs(g * st.z[p.mask > 0]).max() <= 1e-6
+
+
+def test_stage_equalities_full_size_converge():
+    """Cold starts on the full trajectory shape (N = 256, n = 12, m = 4) with
+    one equality row per stage: as fast as without it."""
+    ts = wl.trajectory_problems(2, N=256)
+    for b in range(2):
+        st, it, ok = ipm.solve(ipm.Problem(ts, b, eq=_eq(ts)))
+        assert ok and it <= 40, (b, it)
