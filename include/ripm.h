@@ -19,6 +19,14 @@
  *        a_j^T x_i <= xmax (j = 1, 2; i = 0..N),  |u_i| <= umax componentwise
  * Inequalities per stage i < N: [a_1^T x - xmax, a_2^T x - xmax, u - umax,
  * -u - umax] (ng = 2 + 2m rows); stage N: the two state rows.
+ * Optional stagewise equality rows E_u u_i = b_i (i < N; ne rows per stage,
+ * E_u shared, b per problem and stage) with multipliers y_e: like the
+ * dynamics rows they carry the -1/eta dual-regularization block, and they are
+ * eliminated into the Newton LQR (Section "Applying the regularized IPM to
+ * optimal control": the other equality rows go "in the same fashion"):
+ * R_i += eta E_u^T E_u, r_i += E_u^T (y_e + eta e_i) with e_i = E_u u_i - b_i,
+ * then dy_e = eta (E_u du_i + e_i) and the full step y_e <- y_e + dy_e; the
+ * merit gains y_e^T e + eta/2 |e|^2 and the convergence test |e|.
  *
  * Iteration rules (where the paper leaves them open): exact Lagrangian
  * Hessian; rho = 0 at start, rho <- max(1e-8, 10 rho) while the certificate
@@ -51,6 +59,8 @@ typedef struct {
   double eta;                  /* Delta_C = Delta_G = eta I; LQR delta = 1 / eta */
   double tol;                  /* convergence tolerance (inf-norms) */
   int32_t lqr_mode;            /* RLQR_SEQ_FP64 or RLQR_SEQ_MIXED for the Newton LQR */
+  int32_t ne;                  /* stagewise equality rows per stage, 0 <= ne <= min(m, 8) */
+  const double *Eu;            /* [host] E_u (ne x m), full row rank; NULL when ne = 0 */
 } ripm_problem;
 
 /* Allocate the driver (iterates, Newton-LQR handle and workspace).
@@ -58,7 +68,9 @@ typedef struct {
 rlqr_status ripm_create(ripm_handle **h, const ripm_problem *p, size_t *workspace_bytes);
 
 /*
- * Set the problems and the starting point. x0, goal: [batch][n].
+ * Set the problems and the starting point. x0, goal: [batch][n]; eb: the
+ * equality rows' right-hand sides [batch][N][ne] (NULL when ne = 0; their
+ * multipliers start at 0).
  * warm == NULL: cold start x_i = x0, u_i = 0, y = 0, s = max(-g, 1e-2),
  * z = mu0 / s, mu0 = 0.1. Otherwise warm = [batch][(N+1)n + Nm + (N+1)n +
  * (N+1)ng] holding x, u, y and log z per problem (rows of stage N beyond its
@@ -66,7 +78,7 @@ rlqr_status ripm_create(ripm_handle **h, const ripm_problem *p, size_t *workspac
  * mu0 = mean(s z) clipped to [1e-9, 0.1].
  */
 rlqr_status ripm_start(ripm_handle *h, const double *x0, const double *goal, const double *warm,
-                       rlqr_stream st);
+                       const double *eb, rlqr_stream st);
 
 /* One iteration for every problem not yet converged. *active [host] receives
  * the number of problems still running afterwards (this call synchronizes
@@ -79,8 +91,10 @@ rlqr_status ripm_solve(ripm_handle *h, int32_t max_iter, int32_t *iters, int32_t
                        rlqr_stream st);
 
 /* Copy the current iterate: x [batch][(N+1)n], u [batch][Nm], y [batch][(N+1)n],
- * z [batch][(N+1)ng] (any may be NULL). */
-rlqr_status ripm_solution(ripm_handle *h, double *x, double *u, double *y, double *z, rlqr_stream st);
+ * z [batch][(N+1)ng], ye [batch][N][ne] (any may be NULL; ye is not written
+ * when ne = 0). */
+rlqr_status ripm_solution(ripm_handle *h, double *x, double *u, double *y, double *z, double *ye,
+                          rlqr_stream st);
 
 void ripm_destroy(ripm_handle *h);
 

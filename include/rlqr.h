@@ -91,7 +91,26 @@ enum {
   RLQR_INST_OK = 0,             /* solved to rel_tol, pivot certificate holds  */
   RLQR_INST_NOT_PD = 1,         /* solved to rel_tol, certificate fails (wrong inertia) */
   RLQR_INST_SINGULAR = 2,       /* a pivot is zero; x, u, y are NaN             */
-  RLQR_INST_NOT_CONVERGED = 3   /* relative residual above rel_tol after max_refine steps */
+  RLQR_INST_NOT_CONVERGED = 3,  /* relative residual above rel_tol after max_refine steps */
+  /* A NaN or +-Inf reached the computation: in the data (||[s; c]||_inf is
+     not finite, or a pivot of the factorization is), or arising in the
+     recursion itself (a non-finite residual with finite pivots). Detected
+     from the pivots and the residual, which every non-finite entry of the
+     data reaches; no separate pass over the inputs is made. x, u, y hold
+     whatever non-finite values arose; the certificate reports the instance
+     as failed. */
+  RLQR_INST_NONFINITE = 4
+};
+
+/* Precision path of each instance (rlqr_precision_path). */
+enum {
+  RLQR_PATH_FP32 = 0,        /* served from float32 tiles (RLQR_SEQ_MIXED, RLQR_SCAN_*) */
+  RLQR_PATH_FP64 = 1,        /* float64 by mode (RLQR_SEQ_FP64) or by rlqr_tuning.inst_fp64 */
+  RLQR_PATH_FP64_GUARD = 2,  /* float32 factorization, then refactored in float64 before any
+                                solve: a pivot fell inside the guard band (|d| < 1e-4 max|diag|),
+                                a pivot was zero, or the scan met a singular I + C P */
+  RLQR_PATH_FP64_REDO = 3    /* refinement from float32 tiles did not reach rel_tol; the
+                                instance was refactored and solved again in float64 */
 };
 
 /* array identifiers for rlqr_layout_offsets */
@@ -275,6 +294,20 @@ rlqr_status rlqr_set_skip(rlqr_handle *h, const int32_t *skip);
  */
 rlqr_status rlqr_pivot_inertia(rlqr_handle *h, int32_t *pd_verdict, int32_t *first_bad,
                                int64_t *inertia, rlqr_stream st);
+
+/*
+ * Which precision served each instance in the last rlqr_factor /
+ * rlqr_factor_rhs and the rlqr_solve calls after it: path[b] = RLQR_PATH_*
+ * (DEVICE array [B], written on stream st). In RLQR_SEQ_FP64 every instance
+ * is RLQR_PATH_FP64. The mixed and scan modes decide per instance: a
+ * float32 attempt that a pivot, the scan or refinement rejects is finished
+ * in float64, and this call reports which instances that was (so a float32
+ * result is not float64 work in disguise). Instances left out by
+ * rlqr_set_skip keep their previous path. Errors: RLQR_E_INVALID (NULL h,
+ * or NULL path for a non-empty batch), RLQR_E_STATE (no factorization),
+ * RLQR_E_HIP.
+ */
+rlqr_status rlqr_precision_path(rlqr_handle *h, int32_t *path, rlqr_stream st);
 
 /*
  * Float64 residual of the first-order conditions at z = (x, u, y) (Section

@@ -72,7 +72,7 @@ def _load():
         lib.rlqr_oracle_residual_diag.argtypes = [i, i, i, dp] + [dp] * 8 + [dp] * 3 + [dp]
         lib.rlqr_oracle_residual_diag.restype = None
         lib.rlqr_oracle_seq_batch.argtypes = ([i, ip, ip, ip, dp] + [dp] * 8 + [llp] * 11
-                                              + [dp] * 3 + [ip, i, dp])
+                                              + [dp] * 3 + [ip, i, dp, dp, dp])
         lib.rlqr_oracle_seq_batch.restype = i
         _lib = lib
     return _lib
@@ -217,15 +217,18 @@ def certificate(inst, dS: np.ndarray, dG: np.ndarray):
     return first_bad < 0, first_bad, (npos, nneg, nzero)
 
 
-def seq_batch(packed, nthreads: int = 0):
+def seq_batch(packed, nthreads: int = 0, pivots: bool = False):
     """Sequential oracle over a packed batch, instances spread over threads.
-    Returns (x, u, y, status, threads_used)."""
+    Returns (x, u, y, status, threads_used); with pivots=True also (dS, dG),
+    the pivots of every instance laid out like x and u (see certificate_batch)."""
     lib = _load()
     a = packed.arrays
     o = packed.offsets
     x = np.zeros(o["x"][-1])
     u = np.zeros(o["u"][-1])
     y = np.zeros(o["y"][-1])
+    dS = np.zeros(o["x"][-1]) if pivots else None
+    dG = np.zeros(o["u"][-1]) if pivots else None
     status = np.zeros(packed.batch, dtype=np.int32)
     ip = ctypes.POINTER(ctypes.c_int)
     llp = ctypes.POINTER(ctypes.c_longlong)
@@ -241,5 +244,20 @@ def seq_batch(packed, nthreads: int = 0):
         *[_p(a[k]) for k in ("Q", "M", "R", "A", "B", "q", "r", "c")],
         *[v.ctypes.data_as(llp) for v in offs],
         _p(x), _p(u), _p(y), status.ctypes.data_as(ip), int(nthreads),
-        None if dd is None else _p(np.ascontiguousarray(dd, dtype=np.float64)))
+        None if dd is None else _p(np.ascontiguousarray(dd, dtype=np.float64)), _p(dS), _p(dG))
+    if pivots:
+        return x, u, y, status, used, dS, dG
     return x, u, y, status, used
+
+
+def certificate_batch(packed, insts, dS, dG):
+    """certificate() of every instance of a packed batch from the pivots
+    seq_batch(..., pivots=True) returned: lists of (verdict, first_bad, inertia)."""
+    o = packed.offsets
+    out = []
+    for b, inst in enumerate(insts):
+        n, m, N = inst.n, inst.m, inst.N
+        s = dS[o["x"][b]:o["x"][b + 1]].reshape(N + 1, n)
+        g = dG[o["u"][b]:o["u"][b + 1]].reshape(N, m)
+        out.append(certificate(inst, s, g))
+    return out

@@ -866,6 +866,9 @@ void rlqr_oracle_residual_diag(int n, int m, int N, const double *dd,
  * prefix sums of the per-instance element counts, one int64[B+1] per array),
  * instances spread over threads. status[b] receives the per-instance return.
  * dd: NULL (Delta_i = delta[b] I), or per-stage diagonals laid out like x.
+ * dS, dG: NULL, or the pivots of every instance (dS laid out like x: the n
+ * pivots of S_hat_i at i n; dG laid out like u: the m pivots of G_i at i m),
+ * for the certificate of every instance of a batch.
  * Returns the number of threads used.
  */
 int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
@@ -878,7 +881,7 @@ int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
                           const long long *oq, const long long *or_, const long long *oc,
                           const long long *ox, const long long *ou, const long long *oy,
                           double *x, double *u, double *y, int *status, int nthreads,
-                          const double *dd) {
+                          const double *dd, double *dS, double *dG) {
   int used = 1;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -892,7 +895,7 @@ int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
                                   Q + oQ[b], M + oM[b], R + oR[b], A + oA[b], B + oB[b],
                                   q + oq[b], r + or_[b], c + oc[b],
                                   x + ox[b], u + ou[b], y + oy[b],
-                                  NULL, NULL, NULL, NULL, NULL, NULL);
+                                  NULL, NULL, NULL, NULL, dS ? dS + ox[b] : NULL, dG ? dG + ou[b] : NULL);
   }
 #else
   (void)nthreads;
@@ -901,7 +904,7 @@ int rlqr_oracle_seq_batch(int batch, const int *N, const int *nx, const int *nu,
                                 Q + oQ[b], M + oM[b], R + oR[b], A + oA[b], B + oB[b],
                                 q + oq[b], r + or_[b], c + oc[b],
                                 x + ox[b], u + ou[b], y + oy[b],
-                                NULL, NULL, NULL, NULL, NULL, NULL);
+                                NULL, NULL, NULL, NULL, dS ? dS + ox[b] : NULL, dG ? dG + ou[b] : NULL);
 #endif
   return used;
 }

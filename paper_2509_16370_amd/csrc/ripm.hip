@@ -26,17 +26,21 @@ namespace {
 constexpr int LADDER = 12;    // step ladder alpha_max 2^-k, k = 0..LADDER-1
 constexpr double C1 = 1.0e-4;  // Armijo constant
 constexpr int MAXD = 32;      // n + m bound of the driver
+constexpr int MAXE = 8;       // stagewise equality rows bound
 
 struct Dims {
   int B, N, n, m, ng;
+  int ne;                     // stagewise equality rows E_u u_i = b_i per stage (0: none)
   double dt, wx, wu, wN, xmax, umax, eta;
 };
 
 // Problem and iterate pointers handed to every kernel.
 struct IpmArgs {
   Dims d;
-  const double* model;  // A (n x n), B (n x m), a (2 x n)
+  const double* model;  // A (n x n), B (n x m), a (2 x n), E_u (ne x m)
   const double *x0, *goal;
+  const double* eb;     // [B][N][ne] right-hand sides b_i of the equality rows
+  double* ye;           // [B][N][ne] their multipliers
   double *x, *u, *y, *s, *z, *ds, *dz;
   double *mu, *rho, *merit, *slope, *alpha, *err;
   unsigned long long *amax_s, *amax_z;  // fraction-to-boundary steps (bit patterns of positive doubles)
@@ -55,6 +59,24 @@ struct IpmArgs {
 __device__ __forceinline__ const double* mA(const IpmArgs& a) { return a.model; }
 __device__ __forceinline__ const double* mB(const IpmArgs& a) { return a.model + a.d.n * a.d.n; }
 __device__ __forceinline__ const double* ma(const IpmArgs& a) { return a.model + a.d.n * a.d.n + a.d.n * a.d.m; }
+__device__ __forceinline__ const double* mE(const IpmArgs& a) { return ma(a) + 2 * a.d.n; }
+
+// equality row k of stage i at u: e_k = E_u[k] u - b_k  (Section "Applying
+// the regularized IPM to optimal control": stagewise rows other than the
+// dynamics, eliminated through their -1/eta block like the dynamics duals)
+__device__ __forceinline__ double e_row(const IpmArgs& a, int b, int i, int k, const double* u) {
+  const double* E = mE(a) + k * a.d.m;
+  double v = 0.0;
+  for (int j = 0; j < a.d.m; ++j) v = fma(E[j], u[j], v);
+  return v - a.eb[((int64_t)b * a.d.N + i) * a.d.ne + k];
+}
+// (E_u v)_k
+__device__ __forceinline__ double e_lin(const IpmArgs& a, int k, const double* v) {
+  const double* E = mE(a) + k * a.d.m;
+  double s = 0.0;
+  for (int j = 0; j < a.d.m; ++j) s = fma(E[j], v[j], s);
+  return s;
+}
 
 // inequality row l of stage i at (x, u): rows 0, 1: a_l^T x - xmax; 2..2+m: u - umax; 2+m..: -u - umax
 __device__ __forceinline__ double g_row(const IpmArgs& a, int l, const double* x, const double* u) {
@@ -118,8 +140,10 @@ __global__ void k_ipm_init(IpmArgs a, const double* warm) {
     x[k] = w ? w[(int64_t)i * n + k] : a.x0[(int64_t)b * n + k];
     y[k] = w ? w[(int64_t)(d.N + 1) * n + (int64_t)d.N * m + (int64_t)i * n + k] : 0.0;
   }
-  if (i < d.N)
+  if (i < d.N) {
     for (int k = t; k < m; k += blockDim.x) u[k] = w ? w[(int64_t)(d.N + 1) * n + (int64_t)i * m + k] : 0.0;
+    for (int k = t; k < d.ne; k += blockDim.x) a.ye[((int64_t)b * d.N + i) * d.ne + k] = 0.0;
+  }
   __syncthreads();
   const double mu0 = 0.1;
   for (int l = t; l < ng; l += blockDim.x) {
@@ -155,6 +179,7 @@ __global__ __launch_bounds__(256) void k_ipm_build(IpmArgs a) {
   const double mu = a.mu[b], rho = a.rho[b];
   __shared__ double xs[MAXD], us[MAXD], yi[MAXD], yn[MAXD], th[MAXD], se[MAXD], wdd[MAXD];
   __shared__ double sig[2 + 2 * MAXD], rz[2 + 2 * MAXD];
+  __shared__ double ev[MAXE], yev[MAXE];  // equality residuals and multipliers of the stage
   const double* xg = a.x + ((int64_t)b * (N + 1) + i) * n;
   const double* yg = a.y + (int64_t)b * (N + 1) * n;
   const double* sg = a.s + ((int64_t)b * (N + 1) + i) * ng;
@@ -177,6 +202,11 @@ __global__ __launch_bounds__(256) void k_ipm_build(IpmArgs a) {
     th[t] = tv;
     se[t] = sv;
     wdd[t] = d.dt * yn[t] * (-2.0 * tv * sv);
+  }
+  if (t >= 192 && t < 192 + d.ne && i < N) {
+    const int k = t - 192;
+    ev[k] = e_row(a, b, i, k, us);
+    yev[k] = a.ye[((int64_t)b * N + i) * d.ne + k];
   }
   const int rows = rows_of(d, i);
   for (int l = t; l < 2 + 2 * m; l += 256) {
@@ -210,7 +240,10 @@ __global__ __launch_bounds__(256) void k_ipm_build(IpmArgs a) {
         M[rr * m + (cc - n)] = h;
       } else {
         const int k = rr - n;
-        R[k * m + (cc - n)] = (rr == cc ? d.wu + rho + sig[2 + k] + sig[2 + m + k] : 0.0) + h;
+        // eliminated equality rows: + eta E_u^T E_u
+        double ee = 0.0;
+        for (int l = 0; l < d.ne; ++l) ee = fma(mE(a)[l * m + k], mE(a)[l * m + (cc - n)], ee);
+        R[k * m + (cc - n)] = (rr == cc ? d.wu + rho + sig[2 + k] + sig[2 + m + k] : 0.0) + h + d.eta * ee;
       }
     }
     double* Al = a.Al + ((int64_t)b * N + i) * n * n;
@@ -237,6 +270,8 @@ __global__ __launch_bounds__(256) void k_ipm_build(IpmArgs a) {
       const int k = t - n;
       double gu = d.wu * us[k] + zg[2 + k] - zg[2 + m + k];
       for (int j = 0; j < n; ++j) gu = fma(d.dt * se[j] * yn[j], Bm[j * m + k], gu);
+      // E_u^T y_e (gradient of the Lagrangian) + eta E_u^T e (the eliminated rows' right-hand side)
+      for (int l = 0; l < d.ne; ++l) gu = fma(mE(a)[l * m + k], yev[l] + d.eta * ev[l], gu);
       a.r[((int64_t)b * N + i) * m + k] = gu + sig[2 + k] * rz[2 + k] - sig[2 + m + k] * rz[2 + m + k];
     }
   } else {
@@ -357,6 +392,14 @@ __global__ __launch_bounds__(256) void k_ipm_merit(IpmArgs a) {
         mer += 0.5 * d.wu * ut[j] * ut[j];
         if (k < 0) slope += d.wu * ut[j] * a.du[((int64_t)b * N + i) * m + j];
       }
+    // stagewise equality rows: y_e^T e + eta/2 |e|^2
+    if (i < N)
+      for (int l = 0; l < d.ne; ++l) {
+        const double ev = e_row(a, b, i, l, ut);
+        const double yv = a.ye[((int64_t)b * N + i) * d.ne + l];
+        mer += yv * ev + 0.5 * d.eta * ev * ev;
+        if (k < 0) slope += (yv + d.eta * ev) * e_lin(a, l, a.du + ((int64_t)b * N + i) * m);
+      }
     // inequalities with slacks
     const int rows = rows_of(d, i);
     for (int l = 0; l < rows; ++l) {
@@ -449,6 +492,12 @@ __global__ __launch_bounds__(64) void k_ipm_update(IpmArgs a) {
   }
   if (i < N) {
     const int64_t ou = ((int64_t)b * N + i) * m;
+    // equality multipliers, full step: dy_e = eta (E_u du + e(u)) at the u before the update
+    if (t < d.ne) {
+      const double dye = d.eta * (e_lin(a, t, a.du + ou) + e_row(a, b, i, t, a.u + ou));
+      a.ye[((int64_t)b * N + i) * d.ne + t] += dye;
+    }
+    __syncthreads();
     for (int j = t; j < m; j += 64) a.u[ou + j] += al * a.du[ou + j];
   }
   const int64_t o = ((int64_t)b * (N + 1) + i) * ng;
@@ -505,12 +554,16 @@ __global__ __launch_bounds__(256) void k_ipm_errors(IpmArgs a, int mode, int war
       }
       eg = fmax(eg, fabs(gx));
     }
-    if (i < N)
+    if (i < N) {
+      const double* ye = a.ye + ((int64_t)b * N + i) * d.ne;
       for (int k = 0; k < m; ++k) {
         double gu = d.wu * u[k] + z[2 + k] - z[2 + m + k];
         for (int j = 0; j < n; ++j) gu = fma(d.dt * sev[j] * y[(int64_t)(i + 1) * n + j], Bm[j * m + k], gu);
+        for (int l = 0; l < d.ne; ++l) gu = fma(ye[l], mE(a)[l * m + k], gu);
         eg = fmax(eg, fabs(gu));
       }
+      for (int l = 0; l < d.ne; ++l) ec = fmax(ec, fabs(e_row(a, b, i, l, u)));
+    }
     for (int l = 0; l < rows; ++l) {
       egs = fmax(egs, fabs(g_row(a, l, x, u) + s[l]));
       esz_mu = fmax(esz_mu, fabs(s[l] * z[l] - mu));
@@ -622,10 +675,11 @@ rlqr_status ripm_create(ripm_handle** hp, const ripm_problem* p, size_t* workspa
     return RLQR_E_INVALID;
   if (!(p->eta > 0) || !(p->dt > 0) || !(p->tol > 0) || !(p->umax > 0)) return RLQR_E_INVALID;
   if (p->lqr_mode != RLQR_SEQ_FP64 && p->lqr_mode != RLQR_SEQ_MIXED) return RLQR_E_INVALID;
+  if (p->ne < 0 || p->ne > MAXE || p->ne > p->m || (p->ne > 0 && !p->Eu)) return RLQR_E_INVALID;
   ripm_handle* h = new (std::nothrow) ripm_handle();
   if (!h) return RLQR_E_NOMEM;
   Dims& d = h->d;
-  d.B = p->batch; d.N = p->N; d.n = p->n; d.m = p->m; d.ng = 2 + 2 * p->m;
+  d.B = p->batch; d.N = p->N; d.n = p->n; d.m = p->m; d.ng = 2 + 2 * p->m; d.ne = p->ne;
   d.dt = p->dt; d.wx = p->wx; d.wu = p->wu; d.wN = p->wN; d.xmax = p->xmax; d.umax = p->umax; d.eta = p->eta;
   h->tol = p->tol;
   h->lqr_mode = p->lqr_mode;
@@ -640,8 +694,11 @@ rlqr_status ripm_create(ripm_handle** hp, const ripm_problem* p, size_t* workspa
   IpmArgs& a = h->a;
   a.d = d;
   const size_t D = sizeof(double);
-  A(&a.model, D * (size_t)(n * n + n * m + 2 * n));
+  const int64_t ne = d.ne;
+  A(&a.model, D * (size_t)(n * n + n * m + 2 * n + ne * m));
   A(&a.x0, D * B * n);
+  A(&a.eb, D * B * N * ne);
+  A(&a.ye, D * B * N * ne);
   A(&a.goal, D * B * n);
   A(&a.x, D * B * (N + 1) * n);
   A(&a.u, D * B * N * m);
@@ -683,6 +740,7 @@ rlqr_status ripm_create(ripm_handle** hp, const ripm_problem* p, size_t* workspa
     model.insert(model.end(), p->A, p->A + n * n);
     model.insert(model.end(), p->B, p->B + n * m);
     model.insert(model.end(), p->a, p->a + 2 * n);
+    if (ne > 0) model.insert(model.end(), p->Eu, p->Eu + ne * m);
     std::vector<double> dl(B, 1.0 / d.eta);
     if (hipMemcpy((void*)a.model, model.data(), D * model.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->delta, dl.data(), D * B, hipMemcpyHostToDevice) != hipSuccess)
@@ -698,10 +756,14 @@ rlqr_status ripm_create(ripm_handle** hp, const ripm_problem* p, size_t* workspa
   return RLQR_OK;
 }
 
-rlqr_status ripm_start(ripm_handle* h, const double* x0, const double* goal, const double* warm, rlqr_stream stv) {
+rlqr_status ripm_start(ripm_handle* h, const double* x0, const double* goal, const double* warm, const double* eb,
+                       rlqr_stream stv) {
   if (!h || !x0 || !goal) return RLQR_E_INVALID;
+  if (h->d.ne > 0 && !eb) return RLQR_E_INVALID;
   hipStream_t st = (hipStream_t)stv;
   const Dims& d = h->d;
+  if (d.ne > 0)
+    IPM_TRY(hipMemcpyAsync((void*)h->a.eb, eb, sizeof(double) * d.B * d.N * d.ne, hipMemcpyDeviceToDevice, st));
   IPM_TRY(hipMemcpyAsync((void*)h->a.x0, x0, sizeof(double) * d.B * d.n, hipMemcpyDeviceToDevice, st));
   IPM_TRY(hipMemcpyAsync((void*)h->a.goal, goal, sizeof(double) * d.B * d.n, hipMemcpyDeviceToDevice, st));
   h->warm = warm != nullptr;
@@ -779,7 +841,8 @@ rlqr_status ripm_solve(ripm_handle* h, int32_t max_iter, int32_t* iters, int32_t
   return RLQR_OK;
 }
 
-rlqr_status ripm_solution(ripm_handle* h, double* x, double* u, double* y, double* z, rlqr_stream stv) {
+rlqr_status ripm_solution(ripm_handle* h, double* x, double* u, double* y, double* z, double* ye,
+                          rlqr_stream stv) {
   if (!h) return RLQR_E_INVALID;
   hipStream_t st = (hipStream_t)stv;
   const Dims& d = h->d;
@@ -789,6 +852,7 @@ rlqr_status ripm_solution(ripm_handle* h, double* x, double* u, double* y, doubl
   if (u) IPM_TRY(hipMemcpyAsync(u, h->a.u, D * B * N * m, hipMemcpyDeviceToDevice, st));
   if (y) IPM_TRY(hipMemcpyAsync(y, h->a.y, D * B * (N + 1) * n, hipMemcpyDeviceToDevice, st));
   if (z) IPM_TRY(hipMemcpyAsync(z, h->a.z, D * B * (N + 1) * ng, hipMemcpyDeviceToDevice, st));
+  if (ye && d.ne > 0) IPM_TRY(hipMemcpyAsync(ye, h->a.ye, D * B * N * d.ne, hipMemcpyDeviceToDevice, st));
   return RLQR_OK;
 }
 

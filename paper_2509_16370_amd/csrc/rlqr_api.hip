@@ -96,6 +96,7 @@ struct rlqr_handle {
           *runres = nullptr, *fb = nullptr, *status = nullptr;
   double *lastrel = nullptr, *relres = nullptr;
 
+  int32_t* path = nullptr;       // [B] precision path of the last factor / solve (RLQR_PATH_*)
   int32_t* pref32 = nullptr;     // [B] float32 attempt allowed (mixed and scan modes)
   const int32_t* skip = nullptr;  // [B] caller's mask of instances left out (rlqr_set_skip)
   int32_t *runf = nullptr, *runf2 = nullptr;  // [B] factor run masks under the skip mask
@@ -519,6 +520,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   A((void**)&h->lastrel, sizeof(double) * (size_t)B);
   A((void**)&h->relres, sizeof(double) * (size_t)B);
   if (mode != RLQR_SEQ_FP64) A((void**)&h->pref32, sizeof(int32_t) * (size_t)B);
+  A((void**)&h->path, sizeof(int32_t) * (size_t)B);
   if (!scan) {
     A((void**)&h->runf, sizeof(int32_t) * (size_t)B);
     A((void**)&h->runf2, sizeof(int32_t) * (size_t)B);
@@ -611,6 +613,11 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     std::vector<int32_t> f(B, mode == RLQR_SEQ_FP64 ? 1 : 0);
     for (int b = 0; b < B; ++b) f[b] = f[b] || pref64[b];
     if (ok) ok = upload(h->flag64, f);
+    if (ok) {  // before the first factorization: the float64-only instances are known
+      std::vector<int32_t> pth(B);
+      for (int b = 0; b < B; ++b) pth[b] = f[b] ? RLQR_PATH_FP64 : RLQR_PATH_FP32;
+      ok = upload(h->path, pth);
+    }
     if (ok && mode != RLQR_SEQ_FP64) {
       std::vector<int32_t> p32(B);
       for (int b = 0; b < B; ++b) p32[b] = pref64[b] ? 0 : 1;
@@ -817,6 +824,7 @@ static rlqr_status factor_impl(rlqr_handle* h, const rlqr_lhs* lhs, const rlqr_r
     }
     MaskArgs m{};
     m.batch = h->B; m.kind = 1; m.guard = kGuard; m.info = h->info; m.flag64 = h->flag64;
+    m.path = h->path; m.skip = h->skip;
     m.bad = is_scan(h->mode) ? h->bad : nullptr;
     m.pref32 = h->any_pref64 ? h->pref32 : nullptr;
     RLQR_TRY(launch_masks(m, st));
@@ -987,7 +995,7 @@ static rlqr_status solve_impl(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
     // instances that did not converge from float32 tiles: redo them in float64
     MaskArgs m{};
     m.batch = h->B; m.kind = 2; m.flag64 = h->flag64; m.conv = h->conv; m.status = h->status; m.fb = h->fb;
-    m.skip = h->skip;
+    m.skip = h->skip; m.path = h->path;
     RLQR_TRY(launch_masks(m, st));
     RLQR_TRY(factor_whole(h, h->ws64, h->fb, false, st));
     const int extra = std::min<int32_t>(max_refine, 2);
@@ -1081,6 +1089,15 @@ extern "C" rlqr_status rlqr_pivot_inertia(rlqr_handle* h, int32_t* pd_verdict, i
   InertiaArgs a{};
   a.batch = h->B; a.info = h->info; a.verdict = pd_verdict; a.first_bad = first_bad; a.inertia = inertia;
   RLQR_TRY(launch_inertia(a, (hipStream_t)stv));
+  return RLQR_OK;
+}
+
+extern "C" rlqr_status rlqr_precision_path(rlqr_handle* h, int32_t* path, rlqr_stream stv) {
+  if (!h) return RLQR_E_INVALID;
+  if (!h->factored) return RLQR_E_STATE;
+  if (h->B == 0) return RLQR_OK;
+  if (!path) return RLQR_E_INVALID;
+  RLQR_TRY(hipMemcpyAsync(path, h->path, sizeof(int32_t) * h->B, hipMemcpyDeviceToDevice, (hipStream_t)stv));
   return RLQR_OK;
 }
 

@@ -56,8 +56,9 @@ __device__ __forceinline__ typename AccT<T>::type gemm16(const T* sa, const T* s
 // Per-instance pivot bookkeeping for the certificate.
 struct PivStats {
   int npos, nneg, nzero, first_bad;
+  int nonfinite;  // a pivot was NaN or +-Inf (it also counts as zero)
   double minrel;
-  __device__ void init() { npos = nneg = nzero = 0; first_bad = -1; minrel = 1.0e300; }
+  __device__ void init() { npos = nneg = nzero = nonfinite = 0; first_bad = -1; minrel = 1.0e300; }
 };
 
 // A value every lane holds identically, moved to scalar registers.
@@ -75,9 +76,13 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// max that keeps a NaN (fmax drops it): residual maxima must not hide a
+// non-finite residual entry
+__device__ __forceinline__ double maxnan(double a, double b) { return (b > a || b != b) ? b : a; }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  for (int o = 32; o > 0; o >>= 1) v = maxnan(v, __shfl_xor(v, o));
   return v;
 }
 
@@ -193,6 +198,7 @@ __device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane
   const bool pos = mine && !zero && dsave > 0;
   const bool neg = mine && !zero && dsave < 0;
   const int nz = __popcll(__ballot(zero)), np = __popcll(__ballot(pos)), nn = __popcll(__ballot(neg));
+  if (__ballot(mine && !__builtin_isfinite(dsave))) ps.nonfinite = 1;
   ps.nzero += nz;
   ps.npos += np;
   ps.nneg += nn;

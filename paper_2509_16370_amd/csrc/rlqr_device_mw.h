@@ -62,6 +62,7 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
     __syncthreads();
     const double d = cb[j];
     const bool zero = !(fabs(d) > tol);
+    if (!__builtin_isfinite(d)) ps.nonfinite = 1;
     if (zero) ps.nzero++;
     else if (d > 0) ps.npos++;
     else ps.nneg++;

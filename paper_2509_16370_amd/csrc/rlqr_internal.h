@@ -21,7 +21,8 @@ struct InstMeta {
 
 // Certificate bookkeeping written by the factor kernels.
 struct FactorInfo {
-  int32_t verdict, first_bad, singular, pad;
+  int32_t verdict, first_bad, singular;
+  int32_t nonfinite;  // a pivot was NaN or +-Inf (non-finite data reached the factorization)
   int64_t npos, nneg, nzero;
   double minrel;  // min |pivot| / max|diag| over all pivots
 };
@@ -40,6 +41,7 @@ struct SegStats {
   int32_t first_bad, nzero;
   int32_t npos, nneg;
   double minrel;
+  int32_t nonfinite, pad;
 };
 
 struct FactorArgs {
@@ -242,6 +244,7 @@ struct MaskArgs {
   const int32_t* in;      // kind 5
   int32_t* out;           // kind 5
   int32_t *flag64, *conv, *run32, *run64, *runres, *fb, *run1;
+  int32_t* path;          // kinds 1, 2: if set, the precision path (RLQR_PATH_*) of each instance
 };
 hipError_t launch_masks(const MaskArgs& a, hipStream_t st);
 

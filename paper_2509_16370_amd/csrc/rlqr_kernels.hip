@@ -583,6 +583,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     st.npos = ps.npos;
     st.nneg = ps.nneg;
     st.minrel = ps.minrel;
+    st.nonfinite = ps.nonfinite;
+    st.pad = 0;
     a.stats[sd.gidx] = st;
   }
 }
@@ -788,8 +790,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     if (fuse && own && xr) {
       const double r0 = c0 - d0 * yt - xt;
       resg[(int64_t)N * (n + m) + n + col] = r0;
-      rmax = fmax(rmax, fabs(r0));
-      bmax = fmax(bmax, fabs(c0));
+      rmax = maxnan(rmax, fabs(r0));
+      bmax = maxnan(bmax, fabs(c0));
     }
   }
   if (N > 0) tile_load_pk<CP>(Xn, ws + tl.x(1), lane, px);
@@ -888,14 +890,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
           const double rd = wt + con - dn * y1t - x1t;
           resg[base + col] = rx;
           resg[(int64_t)N * (n + m) + n + (int64_t)(k + 1) * n + col] = rd;
-          rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
-          bmax = fmax(bmax, fmax(fabs(qok), fabs(con)));
+          rmax = maxnan(rmax, maxnan(fabs(rx), fabs(rd)));
+          bmax = maxnan(bmax, maxnan(fabs(qok), fabs(con)));
         }
         if (ur) {
           const double ru = hz + g + rok;
           resg[base + col] = ru;
-          rmax = fmax(rmax, fabs(ru));
-          bmax = fmax(bmax, fabs(rok));
+          rmax = maxnan(rmax, fabs(ru));
+          bmax = maxnan(bmax, fabs(rok));
         }
       }
     }
@@ -935,8 +937,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       if (own && xr) {
         const double rt = h + qN - yt;
         resg[(int64_t)N * (n + m) + col] = rt;
-        rmax = fmax(rmax, fabs(rt));
-        bmax = fmax(bmax, fabs(qN));
+        rmax = maxnan(rmax, fabs(rt));
+        bmax = maxnan(bmax, fabs(qN));
       }
       rmax = wave_max(rmax);
       bmax = wave_max(bmax);
@@ -1028,14 +1030,14 @@ __device__ __forceinline__ void res_compute(const ResidualArgs& a, const InstMet
         res[base + col] = rx;
         res[(int64_t)N * (n + m) + 2 * n + (int64_t)i * n + col] = rd;
       }
-      rmax = fmax(rmax, fmax(fabs(rx), fabs(rd)));
-      bmax = fmax(bmax, fmax(fabs(o.qi), fabs(o.cn)));
+      rmax = maxnan(rmax, maxnan(fabs(rx), fabs(rd)));
+      bmax = maxnan(bmax, maxnan(fabs(o.qi), fabs(o.cn)));
     }
     if (ur) {
       const double ru = h + g + o.ri;
       if (res) res[base + col] = ru;
-      rmax = fmax(rmax, fabs(ru));
-      bmax = fmax(bmax, fabs(o.ri));
+      rmax = maxnan(rmax, fabs(ru));
+      bmax = maxnan(bmax, fabs(o.ri));
     }
   }
 }
@@ -1077,8 +1079,8 @@ __device__ __forceinline__ void res_terminal(const ResidualArgs& a, const InstMe
       res[(int64_t)N * (n + m) + col] = rt;
       res[(int64_t)N * (n + m) + n + col] = ri;
     }
-    rmax = fmax(rmax, fmax(fabs(rt), fabs(ri)));
-    bmax = fmax(bmax, fmax(fabs(qN), fabs(c0)));
+    rmax = maxnan(rmax, maxnan(fabs(rt), fabs(ri)));
+    bmax = maxnan(bmax, maxnan(fabs(qN), fabs(c0)));
   }
 }
 
@@ -1125,8 +1127,8 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
         out = (int64_t)N * (n + m) + 2 * n + (int64_t)i * n + a0;
       }
       if (res) res[out] = s;
-      rmax = fmax(rmax, fabs(s));
-      bmax = fmax(bmax, fabs(bv));
+      rmax = maxnan(rmax, fabs(s));
+      bmax = maxnan(bmax, fabs(bv));
     }
   } else {
     const double* QN = a.Q + mt.oQ + (int64_t)N * nn;
@@ -1146,8 +1148,8 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
         out = (int64_t)N * (n + m) + n + a0;
       }
       if (res) res[out] = s;
-      rmax = fmax(rmax, fabs(s));
-      bmax = fmax(bmax, fabs(bv));
+      rmax = maxnan(rmax, fabs(s));
+      bmax = maxnan(bmax, fabs(bv));
     }
   }
 }
@@ -1242,8 +1244,10 @@ __global__ void k_check(CheckArgs a) {
     return;
   }
   const FactorInfo fi = a.info[b];
+  // a non-finite right-hand side (||b|| is NaN or Inf) or a non-finite pivot
+  const bool nonfinite_in = fi.nonfinite || !(bm <= 1.7976931348623157e308);
   if (!a.final_pass) {
-    if (fi.singular) {
+    if (fi.singular || nonfinite_in) {
       a.conv[b] = 1;
       a.lastrel[b] = __builtin_nan("");
     } else {
@@ -1258,7 +1262,10 @@ __global__ void k_check(CheckArgs a) {
   if (a.relres) a.relres[b] = rel;
   if (a.status) {
     int st = RLQR_INST_OK;
-    if (fi.singular) st = RLQR_INST_SINGULAR;
+    // a residual that is NaN or Inf with finite data and nonzero pivots:
+    // a non-finite value arose in the recursion itself
+    if (nonfinite_in || (!fi.singular && !(fabs(rel) <= 1.7976931348623157e308))) st = RLQR_INST_NONFINITE;
+    else if (fi.singular) st = RLQR_INST_SINGULAR;
     else if (!(rel <= a.tol)) st = RLQR_INST_NOT_CONVERGED;
     else if (!fi.verdict) st = RLQR_INST_NOT_PD;
     a.status[b] = st;
@@ -1275,15 +1282,19 @@ __global__ void k_masks(MaskArgs a) {
     a.run64[b] = (f && !c) ? 1 : 0;
     a.runres[b] = (!c) ? 1 : 0;
   } else if (a.kind == 1) {
+    if (a.skip && a.skip[b]) return;  // left out of this factorization: keeps its path
     const FactorInfo fi = a.info[b];
     const bool fp64_only = a.pref32 && !a.pref32[b];
-    a.flag64[b] = (fp64_only || fi.singular || !(fi.minrel >= a.guard) || (a.bad && a.bad[b])) ? 1 : 0;
+    const bool guard = fi.singular || !(fi.minrel >= a.guard) || (a.bad && a.bad[b]);
+    a.flag64[b] = (fp64_only || guard) ? 1 : 0;
+    if (a.path) a.path[b] = fp64_only ? RLQR_PATH_FP64 : (guard ? RLQR_PATH_FP64_GUARD : RLQR_PATH_FP32);
   } else if (a.kind == 2) {
     const int f = (!a.flag64[b] && a.status[b] == RLQR_INST_NOT_CONVERGED && !(a.skip && a.skip[b])) ? 1 : 0;
     a.fb[b] = f;
     if (f) {
       a.flag64[b] = 1;
       a.conv[b] = 0;
+      if (a.path) a.path[b] = RLQR_PATH_FP64_REDO;
     }
   } else if (a.kind == 3) {
     a.run64[b] = (a.fb[b] && !a.conv[b]) ? 1 : 0;
@@ -1302,12 +1313,13 @@ __global__ void k_merge_stats(MergeArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.batch) return;
   if (a.run && !a.run[b]) return;
-  int first_bad = -1, nzero = 0;
+  int first_bad = -1, nzero = 0, nonfinite = 0;
   long long npos = 0, nneg = 0;
   double minrel = 1.0e300;
   for (int s = a.seg_off[b]; s < a.seg_off[b + 1]; ++s) {
     const SegStats st = a.stats[s];
     first_bad = max(first_bad, st.first_bad);
+    nonfinite |= st.nonfinite;
     nzero += st.nzero;
     npos += st.npos;
     nneg += st.nneg;
@@ -1318,7 +1330,7 @@ __global__ void k_merge_stats(MergeArgs a) {
   fi.verdict = first_bad < 0 ? 1 : 0;
   fi.first_bad = first_bad;
   fi.singular = nzero > 0 ? 1 : 0;
-  fi.pad = 0;
+  fi.nonfinite = nonfinite ? 1 : 0;
   fi.npos = npos;
   fi.nneg = nneg + (long long)(mt.N + 1) * mt.n;
   fi.nzero = nzero;

@@ -384,6 +384,8 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     st.npos = ps.npos;
     st.nneg = ps.nneg;
     st.minrel = ps.minrel;
+    st.nonfinite = ps.nonfinite;
+    st.pad = 0;
     a.stats[sd.gidx] = st;
   }
 }

@@ -225,7 +225,10 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
       // largest |candidate|, lowest row on ties: DPP maxima within 16-lane rows,
       // the four row maxima by v_readlane, the row by a ballot
       const float best = wave_max_f32(a);
-      const int p = __builtin_ctzll(__ballot(a == best));
+      // only candidate rows j..NX-1; with no match (every candidate NaN) the
+      // row stays j and the zero test below marks the scan singular
+      const unsigned long long bal = __ballot(lane < NX && lane >= j && a == best);
+      const int p = bal ? __builtin_ctzll(bal) : j;
       // swap rows j and p, then publish the scaled pivot row and column j
       for (int c = lane; c < 2 * NX; c += 64) {
         const float vj = s.W[j * LDW + c], vp = s.W[p * LDW + c];

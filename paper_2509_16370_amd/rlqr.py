@@ -3,8 +3,8 @@
 Argument marshalling only: every step of the solve runs in the HIP kernels of
 librlqr.so. torch tensors provide device memory and the stream. The functions
 rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_factor_rhs,
-rlqr_solve, rlqr_solve_multi, rlqr_pivot_inertia, rlqr_residual and
-rlqr_destroy carry the C names; `Solver` wraps one handle. The cross-stage
+rlqr_solve, rlqr_solve_multi, rlqr_pivot_inertia, rlqr_precision_path,
+rlqr_residual and rlqr_destroy carry the C names; `Solver` wraps one handle. The cross-stage
 calls of include/rlqr_xs.h (rlqr_xs_*) are wrapped by `CrossStage`.
 
 If librlqr.so is missing this module raises at import: there is no fallback.
@@ -36,7 +36,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 RLQR_OK, RLQR_E_INVALID, RLQR_E_NOMEM, RLQR_E_HIP, RLQR_E_STATE, RLQR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 RLQR_SEQ_FP64, RLQR_SEQ_MIXED, RLQR_SCAN_FP32, RLQR_SCAN_BF16 = 0, 1, 2, 3
-INST_OK, INST_NOT_PD, INST_SINGULAR, INST_NOT_CONVERGED = 0, 1, 2, 3
+INST_OK, INST_NOT_PD, INST_SINGULAR, INST_NOT_CONVERGED, INST_NONFINITE = 0, 1, 2, 3, 4
+PATH_FP32, PATH_FP64, PATH_FP64_GUARD, PATH_FP64_REDO = 0, 1, 2, 3
 ARRAYS = ("Q", "M", "R", "A", "B", "q", "r", "c", "x", "u", "y", "res")
 MODES = {"fp64": RLQR_SEQ_FP64, "mixed": RLQR_SEQ_MIXED, "scan": RLQR_SCAN_FP32, "scan_bf16": RLQR_SCAN_BF16}
 
@@ -81,6 +82,7 @@ _lib.rlqr_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), cty
 _lib.rlqr_solve_multi.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double,
                                   ctypes.c_int32, _vp, _vp, _vp]
 _lib.rlqr_pivot_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.rlqr_precision_path.argtypes = [_vp, _vp, _vp]
 _lib.rlqr_set_skip.argtypes = [_vp, _vp]
 _lib.rlqr_residual.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), _vp, _vp, _vp]
 _lib.rlqr_destroy.argtypes = [_vp]
@@ -89,12 +91,12 @@ _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
 for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
            "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
-           "rlqr_set_skip"):
+           "rlqr_set_skip", "rlqr_precision_path"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
             "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
-            "rlqr_set_skip",
+            "rlqr_set_skip", "rlqr_precision_path",
             "rlqr_destroy", "rlqr_status_string")
 
 
@@ -201,6 +203,10 @@ def rlqr_set_skip(h, skip=None):
 def rlqr_pivot_inertia(h, verdict=None, first_bad=None, inertia=None, stream=None):
     _check(_lib.rlqr_pivot_inertia(h, _ptr(verdict), _ptr(first_bad), _ptr(inertia), _stream(stream)),
            "rlqr_pivot_inertia")
+
+
+def rlqr_precision_path(h, path, stream=None):
+    _check(_lib.rlqr_precision_path(h, _ptr(path), _stream(stream)), "rlqr_precision_path")
 
 
 def rlqr_residual(h, q, r, c, x, u, y, res=None, inst_relres=None, stream=None):
@@ -348,6 +354,12 @@ class Solver:
         inertia = torch.empty(max(3 * self.batch, 1), dtype=torch.int64, device=self.device)
         rlqr_pivot_inertia(self.handle, verdict, first_bad, inertia, stream=stream)
         return verdict, first_bad, inertia.view(-1, 3) if self.batch else inertia
+
+    def precision_path(self, stream=None):
+        """rlqr_precision_path: int32 device tensor [B] of PATH_* values."""
+        path = self.torch.empty(max(self.batch, 1), dtype=self.torch.int32, device=self.device)
+        rlqr_precision_path(self.handle, path, stream=stream)
+        return path
 
     def residual(self, rhs, sol, stream=None):
         torch = self.torch
@@ -572,14 +584,14 @@ class _IpmProblem(ctypes.Structure):
                 ("dt", ctypes.c_double), ("wx", ctypes.c_double), ("wu", ctypes.c_double),
                 ("wN", ctypes.c_double), ("xmax", ctypes.c_double), ("umax", ctypes.c_double),
                 ("A", _dp), ("B", _dp), ("a", _dp), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
-                ("lqr_mode", ctypes.c_int32)]
+                ("lqr_mode", ctypes.c_int32), ("ne", ctypes.c_int32), ("Eu", _dp)]
 
 
 _lib.ripm_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_IpmProblem), ctypes.POINTER(ctypes.c_size_t)]
-_lib.ripm_start.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.ripm_start.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 _lib.ripm_iterate.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _vp]
 _lib.ripm_solve.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp]
-_lib.ripm_solution.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.ripm_solution.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.ripm_destroy.argtypes = [_vp]
 _lib.ripm_destroy.restype = None
 for _f in ("ripm_create", "ripm_start", "ripm_iterate", "ripm_solve", "ripm_solution"):
@@ -590,9 +602,11 @@ IPM_ETA = 1.0e3
 
 
 class IPM:
-    """Batched regularized interior-point driver over a workloads.TrajectorySet."""
+    """Batched regularized interior-point driver over a workloads.TrajectorySet.
+    eq: optional stagewise equality rows (E_u (ne, m), b (batch, N, ne)), E_u u_i = b_i."""
 
-    def __init__(self, ts, lqr: str = "fp64", eta: float = IPM_ETA, tol: float = 1e-6, device: str = "cuda:0"):
+    def __init__(self, ts, lqr: str = "fp64", eta: float = IPM_ETA, tol: float = 1e-6, device: str = "cuda:0",
+                 eq=None):
         import torch
         self.torch = torch
         self.ts = ts
@@ -601,8 +615,15 @@ class IPM:
         self.ng = 2 + 2 * ts.m
         self.batch = ts.batch
         self._model = [np.ascontiguousarray(v, dtype=np.float64) for v in (ts.A, ts.B, ts.a)]
+        self.ne = 0
+        self._Eu = None
+        if eq is not None:
+            self._Eu = np.ascontiguousarray(np.atleast_2d(eq[0]), dtype=np.float64)
+            self.ne = int(self._Eu.shape[0])
+            assert self._Eu.shape == (self.ne, ts.m)
         p = _IpmProblem(self.batch, ts.N, ts.n, ts.m, ts.dt, ts.wx, ts.wu, ts.wN, ts.xmax, ts.umax,
-                        *(v.ctypes.data_as(_dp) for v in self._model), float(eta), float(tol), MODES[lqr])
+                        *(v.ctypes.data_as(_dp) for v in self._model), float(eta), float(tol), MODES[lqr],
+                        self.ne, None if self._Eu is None else self._Eu.ctypes.data_as(_dp))
         self.handle = _vp()
         ws = ctypes.c_size_t(0)
         with torch.cuda.device(self.device):
@@ -610,6 +631,10 @@ class IPM:
         self.workspace_bytes = int(ws.value)
         self.x0 = torch.from_numpy(np.ascontiguousarray(ts.x0, dtype=np.float64)).to(self.device)
         self.goal = torch.from_numpy(np.ascontiguousarray(ts.goal, dtype=np.float64)).to(self.device)
+        self.eb = None
+        if eq is not None:
+            eb = np.ascontiguousarray(np.broadcast_to(eq[1], (self.batch, ts.N, self.ne)), dtype=np.float64)
+            self.eb = torch.from_numpy(eb).to(self.device)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -629,8 +654,8 @@ class IPM:
         if warm is not None:
             assert warm.dtype == self.torch.float64 and warm.is_cuda and warm.is_contiguous()
             assert warm.numel() == self.batch * self.warm_size()
-        _check(_lib.ripm_start(self.handle, _ptr(self.x0), _ptr(self.goal), _ptr(warm), _stream(stream)),
-               "ripm_start")
+        _check(_lib.ripm_start(self.handle, _ptr(self.x0), _ptr(self.goal), _ptr(warm), _ptr(self.eb),
+                               _stream(stream)), "ripm_start")
 
     def iterate(self, stream=None) -> int:
         act = ctypes.c_int32(0)
@@ -651,7 +676,11 @@ class IPM:
         u = torch.empty(B, N, m, dtype=torch.float64, device=self.device)
         y = torch.empty(B, N + 1, n, dtype=torch.float64, device=self.device)
         z = torch.empty(B, N + 1, ng, dtype=torch.float64, device=self.device)
-        _check(_lib.ripm_solution(self.handle, _ptr(x), _ptr(u), _ptr(y), _ptr(z), _stream(stream)), "ripm_solution")
+        ye = torch.empty(B, N, max(self.ne, 1), dtype=torch.float64, device=self.device) if self.ne else None
+        _check(_lib.ripm_solution(self.handle, _ptr(x), _ptr(u), _ptr(y), _ptr(z), _ptr(ye), _stream(stream)),
+               "ripm_solution")
+        if self.ne:
+            self.ye = ye
         return x, u, y, z
 
 

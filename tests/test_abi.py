@@ -119,6 +119,15 @@ def test_ipm_create_rejects_bad_problems():
                              kw["eta"], kw["tol"], kw["lqr_mode"])
         h = rlqr._vp()
         assert lib.ripm_create(ctypes.byref(h), ctypes.byref(p), None) == rlqr.RLQR_E_INVALID, bad
+    # stagewise equality rows: more rows than controls, or no E_u
+    kw = good
+    Eu = np.ones((2, 1))
+    for ne, E in ((2, Eu), (1, None), (9, Eu), (-1, Eu)):
+        p = rlqr._IpmProblem(kw["batch"], kw["N"], kw["n"], kw["m"], kw["dt"], kw["wx"], kw["wu"], kw["wN"],
+                             kw["xmax"], kw["umax"], A.ctypes.data_as(dp), B.ctypes.data_as(dp), a.ctypes.data_as(dp),
+                             kw["eta"], kw["tol"], kw["lqr_mode"], ne, None if E is None else E.ctypes.data_as(dp))
+        h = rlqr._vp()
+        assert lib.ripm_create(ctypes.byref(h), ctypes.byref(p), None) == rlqr.RLQR_E_INVALID, ne
     lib.ripm_destroy(None)
 
 
@@ -166,6 +175,7 @@ def test_null_arguments_rejected():
     assert lib.rlqr_graph_capture(None, None, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_graph_launch(None, None) == rlqr.RLQR_E_INVALID
     assert lib.rlqr_get_tuning(None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_precision_path(None, None, None) == rlqr.RLQR_E_INVALID
     lib.rlqr_destroy(None)
 
 

@@ -88,3 +88,66 @@ def test_warm_start_from_solution_converges_at_once(rl):
     it1, conv1 = drv2.solve(max_iter=200)
     assert conv1.all()
     assert (it1 <= 8).all() and it1.mean() < it0.mean(), (it1, it0)
+
+
+# ---- stagewise equality rows E_u u_i = b_i (eliminated into the Newton LQR)
+
+def _eq(ts, ne=1, bval=0.1):
+    Eu = np.zeros((ne, ts.m))
+    for k in range(ne):
+        Eu[k, k], Eu[k, k + 1] = 1.0 / np.sqrt(2), -1.0 / np.sqrt(2)
+    return Eu, np.full((ts.N, ne), bval)
+
+
+def _check_kkt_eq(p, x, u, y, z, ye, tol):
+    gx, gu = p.grad_L(oipm.State(x, u, y, np.ones_like(z), z * p.mask, 0.0, ye=ye))
+    assert max(np.abs(gx).max(), np.abs(gu).max()) <= tol
+    assert np.abs(p.c(x, u)).max() <= tol and np.abs(p.e(u)).max() <= tol
+    g = p.g(x, u)[p.mask > 0]
+    zz = z[p.mask > 0]
+    assert g.max() <= tol and zz.min() >= 0.0
+    assert np.abs(g * zz).max() <= 2 * tol
+
+
+@pytest.mark.parametrize("lqr,ne", [("fp64", 1), ("mixed", 1), ("fp64", 2)])
+def test_ipm_stage_equalities_match_oracle(rl, lqr, ne):
+    """Equality rows carried through the whole GPU loop: iterations within
+    two of the CPU oracle's, the converged x, u and y_e equal the oracle's,
+    and the point meets the NLP's first-order conditions."""
+    print(f"[gpu] ipm stage equalities lqr={lqr} ne={ne}", flush=True)
+    ts = wl.trajectory_problems(6, N=32, n=6, m=3)
+    Eu, eb = _eq(ts, ne=ne, bval=0.05)
+    drv = rl.IPM(ts, lqr=lqr, eta=oipm.ETA, tol=oipm.TOL, eq=(Eu, eb))
+    drv.start()
+    iters, conv = drv.solve(max_iter=oipm.MAX_ITER)
+    x, u, y, z = (t.cpu().numpy() for t in drv.solution())
+    ye = drv.ye.cpu().numpy()
+    assert conv.all(), conv
+    for b in range(ts.batch):
+        p = oipm.Problem(ts, b, eq=(Eu, eb))
+        st, it, ok = oipm.solve(p)
+        assert ok
+        assert abs(int(iters[b]) - it) <= 2, (b, int(iters[b]), it)
+        _check_kkt_eq(p, x[b], u[b], y[b], z[b], ye[b], 1e-6)
+        assert np.allclose(x[b], st.x, atol=1e-5) and np.allclose(u[b], st.u, atol=1e-5)
+        assert np.allclose(ye[b], st.ye, atol=1e-4 * max(1.0, np.abs(st.ye).max()))
+
+
+def test_ipm_stage_equalities_full_shape(rl):
+    """N = 256, n = 12, m = 4 with one equality row per stage: every problem
+    converges to a first-order point; two of them against the oracle."""
+    print("[gpu] ipm stage equalities full shape", flush=True)
+    ts = wl.trajectory_problems(32, N=256)
+    Eu, eb = _eq(ts)
+    drv = rl.IPM(ts, lqr="fp64", eq=(Eu, eb))
+    drv.start()
+    iters, conv = drv.solve(max_iter=200)
+    assert conv.all(), (conv == 0).sum()
+    x, u, y, z = (t.cpu().numpy() for t in drv.solution())
+    ye = drv.ye.cpu().numpy()
+    for b in range(ts.batch):
+        _check_kkt_eq(oipm.Problem(ts, b, eq=(Eu, eb)), x[b], u[b], y[b], z[b], ye[b], 1e-6)
+    for b in (0, 21):
+        st, it, ok = oipm.solve(oipm.Problem(ts, b, eq=(Eu, eb)))
+        assert ok and abs(int(iters[b]) - it) <= 2, (b, int(iters[b]), it)
+        assert np.allclose(x[b], st.x, atol=1e-5) and np.allclose(u[b], st.u, atol=1e-5)

@@ -331,3 +331,34 @@ def test_delta_to_zero_continuity():
         o = oracle.seq(inst)
         err = max(np.abs(o[k] - o0[k]).max() for k in ("x", "u", "y"))
         assert err <= 1e3 * d + 1e-12
+
+
+def test_batch_pivots_give_dense_inertia():
+    """The batch driver's pivots (every instance of a ragged batch, PD and
+    indefinite, delta = 0 included) give the eigenvalue inertia of each
+    instance's dense KKT matrix, and equal the single-instance pivots."""
+    rng = np.random.default_rng(23)
+    insts = []
+    for i in range(24):
+        n, m = int(rng.integers(2, 5)), int(rng.integers(1, 4))
+        N = int(rng.integers(0, 7))
+        delta = float(rng.choice([0.0, 1e-4, 0.1]))
+        insts.append(wl.make_instance(n, m, N, delta, (94, i, 0), indefinite=bool(i % 2 == 1)))
+    packed = wl.pack(insts)
+    x, u, y, st, _, dS, dG = oracle.seq_batch(packed, nthreads=2, pivots=True)
+    certs = oracle.certificate_batch(packed, insts, dS, dG)
+    nfalse = 0
+    for b, inst in enumerate(insts):
+        ref = oracle.seq(inst)
+        assert st[b] == ref["status"]
+        o = packed.offsets
+        assert np.array_equal(dS[o["x"][b]:o["x"][b + 1]], ref["dS"].ravel())
+        assert np.array_equal(dG[o["u"][b]:o["u"][b + 1]], ref["dG"].ravel())
+        if ref["status"]:
+            continue
+        verdict, first_bad, inertia = certs[b]
+        K, _ = dense.assemble(inst)
+        assert inertia == dense.inertia_eig(K), b
+        assert verdict == (inertia == dense.target_inertia(inst))
+        nfalse += not verdict
+    assert nfalse >= 3
