@@ -28,7 +28,12 @@ refinement of the whole system, float64 and mixed). --diag-spread s gives the
 uniform batch a per-stage diagonal Delta_i (entries delta * 10^U(-s, s), the
 separate per-constraint penalties the definition allows). stage_eq: the
 uniform batch with --ne equality rows per stage eliminated into the LQR
-(rlqr_eq_reduce, factor, solve, rlqr_eq_recover).
+(rlqr_eq_reduce, factor, solve, rlqr_eq_recover). single_small: one instance
+n=4, m=2, N=32, delta=1e-6 (a latency measurement: float64 and mixed).
+ipm: the regularized interior-point method on 2048 trajectory problems
+(n=12, m=4, N=256, tolerance 1e-6), cold start against the learned warm
+start (network trained first on --train method-generated solutions); the
+line reports both runs' iterations and wall times.
 """
 import argparse
 import json
@@ -118,7 +123,14 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_t
     stages = int(packed.N[ok].sum())
     ms_per_step = 1e3 * wall / steps
     import numpy as np
+    path = s.precision_path()
+    torch.cuda.synchronize()
+    path = path.cpu().numpy()[:packed.batch]
+    paths = {name: int((path == code).sum()) for name, code in
+             (("fp32", rl.PATH_FP32), ("fp64", rl.PATH_FP64), ("fp64_guard", rl.PATH_FP64_GUARD),
+              ("fp64_redo", rl.PATH_FP64_REDO))}
     return dict(
+        precision_paths=paths,
         value=stages / (ms_per_step * 1e-3),
         ms_per_step=ms_per_step,
         factor_ms=float(np.median(factor_ms)),
@@ -238,6 +250,18 @@ def run_eq_mode(torch, rl, packed, lhs, rhs, eqd, ne, mode, steps, warmup, max_r
     )
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline_eq(insts, eqs, count=512):
     """The elimination oracle (reduce in numpy, the sequential C oracle over
     the reduced batch on all host threads, recover) on the first `count`
@@ -254,7 +278,7 @@ def cpu_baseline_eq(insts, eqs, count=512):
         eqstep.recover(red[b], eqs[b], xb, ub)
     t = time.perf_counter() - t0
     stages = int(packed.N.sum())
-    return dict(value=stages / t, unit="stage-solves/s", cores=int(used), kind="oracle",
+    return dict(value=stages / t, unit="stage-solves/s", cores=int(used), kind="oracle", cpu_model=cpu_model(),
                 sample=f"first {count} instances of the batch: numpy reduction, the sequential FP64 oracle "
                        f"over the reduced batch on {used} threads, numpy recovery of w",
                 seconds=t)
@@ -270,17 +294,17 @@ def cpu_baseline_xs(insts, xs, count=256):
         ocs.schur(inst, x.J, x.H, (inst.q, inst.r, inst.c), x.rth)
         stages += inst.N
     t = time.perf_counter() - t0
-    return dict(value=stages / t, unit="stage-solves/s", cores=1, kind="oracle",
+    return dict(value=stages / t, unit="stage-solves/s", cores=1, kind="oracle", cpu_model=cpu_model(),
                 sample=f"first {count} instances of the batch, the cross-stage oracle's Schur route "
                        f"(p + 2 sequential float64 Riccati solves each), one thread",
                 seconds=t)
 
 
-def cpu_baseline(packed, seconds_target=10.0, sample=None):
+def cpu_baseline(packed, seconds_target=10.0, sample=None, threads=0):
     """The FP64 oracle, as it stands, over the same batch (or the named sample) on the host cores."""
     import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+    threads = threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
     times = []
     used = 1
     t_start = time.perf_counter()
@@ -288,15 +312,68 @@ def cpu_baseline(packed, seconds_target=10.0, sample=None):
         t0 = time.perf_counter()
         x, u, y, st, used = oracle.seq_batch(packed, nthreads=threads)
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > seconds_target or len(times) >= 5:
+        if time.perf_counter() - t_start > seconds_target or len(times) >= (5 if packed.batch > 1 else 200):
             break
     t = float(np.median(times))
     stages = int(packed.N.sum())
     what = sample or f"full batch ({packed.batch} instances, {stages} stages)"
-    return dict(value=stages / t, unit="stage-solves/s", cores=int(used), kind="oracle",
+    return dict(value=stages / t, unit="stage-solves/s", cores=int(used), kind="oracle", cpu_model=cpu_model(),
                 sample=f"{what}, median of {len(times)} runs of the sequential FP64 oracle, instances spread "
                        f"over {used} threads",
                 seconds=t)
+
+
+def run_ipm(torch, rl, args):
+    """Interior-point workload: train the warm-start network on method-generated
+    solutions (untimed), then solve the 2048 evaluation problems cold and warm.
+    Returns the JSON line's fields."""
+    import numpy as np
+    from paper_2509_16370_amd import warmstart as wsm
+    from paper_2509_16370_amd import workloads as wl
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    F, T = wsm.make_dataset(args.train, log=log)
+    log(f"[bench] {F.shape[0]} training solutions in {time.perf_counter() - t0:.1f} s")
+    net = wsm.WarmStart(F.shape[1], T.shape[1], dtype="bf16")
+    t0 = time.perf_counter()
+    hist = net.fit(F, T, epochs=args.epochs, log=log)
+    train_s = time.perf_counter() - t0
+    ts = wl.trajectory_problems(2048, stream=0)
+    wsm.solve_batch(ts, max_iter=3)  # warm the driver and the library up (untimed)
+    torch.cuda.synchronize()
+    ic, cc, _, _, _, _, tc = wsm.solve_batch(ts)
+    Fe = torch.from_numpy(wsm.features(ts)).cuda()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    warm = net.predict(Fe)
+    torch.cuda.synchronize()
+    tpred = time.perf_counter() - t1
+    iw, cw, _, _, _, _, tw = wsm.solve_batch(ts, warm=warm)
+    tw += tpred
+    both = (cc > 0) & (cw > 0)
+    N = ts.N
+    res = dict(
+        problems=int(ts.batch), cold_converged=int(cc.sum()), warm_converged=int(cw.sum()),
+        cold_mean_iterations=float(ic[both].mean()), warm_mean_iterations=float(iw[both].mean()),
+        cold_seconds=tc, warm_seconds=tw, predict_seconds=tpred, train_solutions=int(F.shape[0]),
+        train_epochs=args.epochs, train_seconds=train_s, final_loss=float(hist[-1]),
+        cold_stage_solves_per_s=float(ic.sum()) * N / tc, warm_stage_solves_per_s=float(iw.sum()) * N / tw)
+    return res, ts
+
+
+def cpu_baseline_ipm(ts, count=8):
+    """The CPU interior-point oracle (numpy, the sequential C oracle for each
+    Newton step's LQR) on the first `count` problems, cold start, one thread."""
+    from oracle import ipm as oipm
+    t0 = time.perf_counter()
+    stage_solves = 0
+    for b in range(count):
+        st, it, ok = oipm.solve(oipm.Problem(ts, b))
+        stage_solves += it * ts.N
+    t = time.perf_counter() - t0
+    return dict(value=stage_solves / t, unit="stage-solves/s", cores=1, kind="oracle", cpu_model=cpu_model(),
+                sample=f"first {count} of the 2048 problems, the CPU interior-point oracle from a cold start "
+                       f"(Newton-step LQR stage-solves per second), one thread", seconds=t)
 
 
 def scan_factor_flops(n, m):
@@ -333,7 +410,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "long_horizon", "batched_ragged", "cross_stage", "stage_eq"])
+                    choices=["batched_uniform", "long_horizon", "batched_ragged", "cross_stage", "stage_eq",
+                             "single_small", "ipm"])
+    ap.add_argument("--train", type=int, default=50000, help="ipm: training problems for the warm start")
+    ap.add_argument("--epochs", type=int, default=40, help="ipm: training epochs")
     ap.add_argument("--ne", type=int, default=2, help="stage_eq: equality rows per stage")
     ap.add_argument("--p", type=int, default=4, help="cross_stage: number of cross-stage variables")
     ap.add_argument("--batch", type=int, default=4096)
@@ -396,6 +476,38 @@ def main():
                 f"delta={args.delta:g}, {args.ne} equality rows per stage (penalties 1e3 * 10^U(-1, 1)), "
                 f"eliminated into the LQR, refined to {REL_TOL:g} relative KKT residual, multipliers recovered")
         cfg = {"batch": args.batch, "nx": n, "nu": m, "N": N, "delta": args.delta, "ne": args.ne}
+    elif wk == "single_small":
+        insts = wl.single_small()
+        packed = wl.pack(insts)
+        args.delta = 1e-6
+        modes = (args.modes or "fp64,mixed").split(",")
+        head = "fp64"
+        desc = ("single small dual-regularized LQR: n=4, m=2, N=32, delta=1e-6, refined to 1e-8 "
+                "(one instance: a latency measurement)")
+        cfg = {"batch": 1, "nx": 4, "nu": 2, "N": 32, "delta": 1e-6}
+    elif wk == "ipm":
+        res, ts = run_ipm(torch, rl, args)
+        fb = factor_algorithmic_bytes(ts.n, ts.m, 8)
+        achieved = res["warm_stage_solves_per_s"] * fb / 1e9
+        line = {
+            "metric": METRIC, "value": res["warm_stage_solves_per_s"], "unit": "stage-solves/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": 1e3 * res["warm_seconds"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "regularized interior-point method, 2048 trajectory problems (n=12, m=4, "
+                                   "N=256, x+ = x + 0.05 tanh(A x + B u), |u| <= 1, 2 state rows per stage), "
+                                   "tolerance 1e-6, learned warm start vs cold start; value = Newton-step "
+                                   "LQR stage-solves per second of the warm run",
+                       "batch": 2048, "nx": ts.n, "nu": ts.m, "N": ts.N, "tol": 1e-6},
+            "ipm": res,
+            "roofline": {"kernel": "interior-point loop (all launches; factorization bytes per stage-solve)",
+                         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_stage_solve": fb},
+        }
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline_ipm(ts)
+        print(json.dumps(line), flush=True)
+        return
     elif wk == "long_horizon":
         inst = wl.long_horizon()[0]
         packed = wl.pack([inst])
@@ -562,6 +674,9 @@ def main():
         elif wk == "long_horizon":
             line["cpu_baseline"] = cpu_baseline(wl.pack([wl.make_instance(64, 32, 2048, 1e-6, (3, 0, 0))]),
                                                 sample="one instance of the long-horizon shape at N=2048")
+        elif wk == "single_small":
+            line["cpu_baseline"] = cpu_baseline(packed, seconds_target=2.0, threads=1,
+                                                sample="the same single instance")
         else:
             line["cpu_baseline"] = cpu_baseline(packed)
     print(json.dumps(line), flush=True)
