@@ -7,8 +7,8 @@ with the block layout of eq. optimal-control-specialization,
     [[P, C^T], [C, -Delta]] [x; y] = -[s; c],
 
 with Delta = blockdiag(Delta_0, ..., Delta_N): delta I, or the instance's
-per-stage diagonals when it carries them (Definition "dual-regularized LQR"
-lets every Delta_i be any SPD matrix),
+per-stage diagonals or full SPD blocks when it carries them (Definition
+"dual-regularized LQR" lets every Delta_i be any SPD matrix),
 
 assembled as a dense matrix and solved with numpy. Inertia comes from the
 eigenvalues (numpy.linalg.eigvalsh) and, independently, from the block
@@ -51,7 +51,11 @@ def assemble(inst):
         C[(i + 1) * n:(i + 2) * n, uo[i]:uo[i] + m] = inst.B[i]
         C[(i + 1) * n:(i + 2) * n, xo[i + 1]:xo[i + 1] + n] = -np.eye(n)
     dd = getattr(inst, "delta_diag", None)
-    Delta = d * np.eye(ny) if dd is None else np.diag(np.asarray(dd, dtype=np.float64).reshape(-1))
+    df = getattr(inst, "delta_full", None)
+    if df is not None:  # full SPD blocks Delta_i
+        Delta = scipy.linalg.block_diag(*np.asarray(df, dtype=np.float64))
+    else:
+        Delta = d * np.eye(ny) if dd is None else np.diag(np.asarray(dd, dtype=np.float64).reshape(-1))
     K = np.block([[P, C.T], [C, -Delta]])
     rhs = -np.concatenate([s, inst.c.reshape(-1)])
     return K, rhs

@@ -69,6 +69,7 @@ class Instance:
     c: np.ndarray  # (N+1, n)
     indefinite: bool = False
     delta_diag: Optional[np.ndarray] = None  # (N+1, n): Delta_i = diag(delta_diag[i]); None: delta I
+    delta_full: Optional[np.ndarray] = None  # (N+1, n, n): Delta_i any SPD matrix; overrides the others
 
 
 def _rng(seed: Sequence[int]) -> np.random.Generator:
@@ -84,7 +85,8 @@ def _haar_orthogonal(rng: np.random.Generator, N: int, n: int) -> np.ndarray:
 
 
 def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
-                  indefinite: bool = False, diag_spread: Optional[float] = None) -> Instance:
+                  indefinite: bool = False, diag_spread: Optional[float] = None,
+                  spd_spread: Optional[float] = None) -> Instance:
     """Draw one instance with the stage recipe of the small single-instance workload.
 
     Recipe (all draws independent per stage, in this order):
@@ -99,6 +101,10 @@ def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
     With diag_spread = s, Delta_i is diagonal with entries delta * 10^U(-s, s),
     drawn after everything else (the other data do not depend on s); they
     stand for separate penalty parameters per constraint.
+    With spd_spread = s, Delta_i is a full SPD matrix delta * V_i diag(10^U(-s, s)) V_i^T
+    with V_i Haar-orthogonal (drawn after everything else, per stage i = 0..N):
+    penalties on combinations of the constraints (the definition allows any
+    SPD Delta_i).
     """
     rng = _rng(seed)
     A = 0.95 * _haar_orthogonal(rng, N, n) + 0.05 * rng.standard_normal((N, n, n)) / np.sqrt(n)
@@ -122,7 +128,13 @@ def make_instance(n: int, m: int, N: int, delta: float, seed: Sequence[int],
     dd = None
     if diag_spread is not None:
         dd = float(delta) * 10.0 ** rng.uniform(-diag_spread, diag_spread, size=(N + 1, n))
-    return Instance(n, m, N, float(delta), Q, M, R, A, B, q, r, c, indefinite, dd)
+    df = None
+    if spd_spread is not None:
+        Vd = _haar_orthogonal(rng, N + 1, n)
+        ev = float(delta) * 10.0 ** rng.uniform(-spd_spread, spd_spread, size=(N + 1, n))
+        df = (Vd * ev[:, None, :]) @ np.swapaxes(Vd, 1, 2)
+        df = 0.5 * (df + np.swapaxes(df, 1, 2))
+    return Instance(n, m, N, float(delta), Q, M, R, A, B, q, r, c, indefinite, dd, df)
 
 
 # ---------------------------------------------------------------- workloads
@@ -212,7 +224,25 @@ def pack(instances: List[Instance]) -> Packed:
     if any(i.delta_diag is not None for i in instances):
         arrays["delta_diag"] = _pack_diag(instances)
         assert arrays["delta_diag"].shape[0] == offs["x"][-1]
+    if any(i.delta_full is not None for i in instances):
+        arrays["delta_full"] = _pack_full(instances)
+        assert arrays["delta_full"].shape[0] == offs["Q"][-1]
     return Packed(N, n, m, delta, arrays, offs)
+
+
+def _pack_full(instances: List[Instance]) -> np.ndarray:
+    """Full Delta_i of every instance, laid out like Q ((N+1) n n per
+    instance); an instance without them contributes its delta I (or its
+    per-stage diagonal)."""
+    parts = []
+    for i in instances:
+        if i.delta_full is not None:
+            parts.append(np.asarray(i.delta_full, dtype=np.float64).reshape(-1))
+        elif i.delta_diag is not None:
+            parts.append(np.stack([np.diag(d) for d in i.delta_diag]).reshape(-1))
+        else:
+            parts.append(np.tile(i.delta * np.eye(i.n), (i.N + 1, 1, 1)).reshape(-1))
+    return np.concatenate(parts) if parts else np.zeros(0)
 
 
 def _pack_diag(instances: List[Instance]) -> np.ndarray:
