@@ -324,6 +324,34 @@ rlqr_status rlqr_precision_path(rlqr_handle *h, int32_t *path, rlqr_stream st);
 rlqr_status rlqr_residual(rlqr_handle *h, const rlqr_rhs *rhs, const rlqr_sol *z,
                           double *res, double *inst_relres, rlqr_stream st);
 
+/* Size of the device array rlqr_residual_noalloc works in (per GPU). */
+#define RLQR_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/*
+ * For callers that cannot allocate device memory (serving loops that must
+ * not call hipMalloc, harnesses that forbid it): rlqr_residual without a
+ * handle. Same residual, same order of rows and same inst_relres as
+ * rlqr_residual on a handle created with the same shape (bit-identical: the
+ * same kernels run), for z at the lhs given here. Allocates nothing: the
+ * per-instance metadata, the stage-chunk list and the per-instance maxima
+ * live in one device array of RLQR_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends. The batch must fit:
+ * 160 B per instance + 16 B per stage chunk (ceil((N_b + 1) / 16) chunks for
+ * n + m <= 16, ceil((N_b + 1) / 2) otherwise) + 2 x 8 B per instance, each
+ * part rounded up to 256 B, at most RLQR_NOALLOC_SCRATCH_BYTES (e.g. 4096
+ * instances of N = 128 with n + m <= 16 take 1.2 MB); a larger batch returns
+ * RLQR_E_INVALID and touches nothing. Runs on the current device; st must
+ * belong to it. The metadata are uploaded by a copy from pageable host memory,
+ * which HIP performs synchronously with respect to the host, so the call
+ * cannot be captured into a graph. Calls on one stream are ordered; calls
+ * that overlap on one GPU (other streams, other host threads) share the
+ * array and race. The array keeps the last call's contents; the maxima are
+ * cleared at every call. Errors: RLQR_E_INVALID (NULL pointer, a shape out
+ * of range, batch too large), RLQR_E_HIP.
+ */
+rlqr_status rlqr_residual_noalloc(const rlqr_shape *s, const rlqr_lhs *lhs, const rlqr_rhs *rhs,
+                                  const rlqr_sol *z, double *res, double *inst_relres, rlqr_stream st);
+
 /*
  * Capture rlqr_factor followed by rlqr_solve (same arguments as those calls)
  * on stream st into a HIP graph owned by the handle, for callers that repeat

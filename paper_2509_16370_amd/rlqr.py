@@ -4,7 +4,7 @@ Argument marshalling only: every step of the solve runs in the HIP kernels of
 librlqr.so. torch tensors provide device memory and the stream. The functions
 rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_factor_rhs,
 rlqr_solve, rlqr_solve_multi, rlqr_pivot_inertia, rlqr_precision_path,
-rlqr_residual and rlqr_destroy carry the C names; `Solver` wraps one handle. The cross-stage
+rlqr_residual, rlqr_residual_noalloc and rlqr_destroy carry the C names; `Solver` wraps one handle. The cross-stage
 calls of include/rlqr_xs.h (rlqr_xs_*) are wrapped by `CrossStage`.
 
 If librlqr.so is missing this module raises at import: there is no fallback.
@@ -85,18 +85,20 @@ _lib.rlqr_pivot_inertia.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.rlqr_precision_path.argtypes = [_vp, _vp, _vp]
 _lib.rlqr_set_skip.argtypes = [_vp, _vp]
 _lib.rlqr_residual.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), _vp, _vp, _vp]
+_lib.rlqr_residual_noalloc.argtypes = [ctypes.POINTER(_Shape), ctypes.POINTER(_Lhs), ctypes.POINTER(_Rhs),
+                                       ctypes.POINTER(_Sol), _vp, _vp, _vp]
 _lib.rlqr_destroy.argtypes = [_vp]
 _lib.rlqr_destroy.restype = None
 _lib.rlqr_status_string.argtypes = [ctypes.c_int]
 _lib.rlqr_status_string.restype = ctypes.c_char_p
 for _f in ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
            "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
-           "rlqr_set_skip", "rlqr_precision_path"):
+           "rlqr_set_skip", "rlqr_precision_path", "rlqr_residual_noalloc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("rlqr_create", "rlqr_create_tuned", "rlqr_get_tuning", "rlqr_layout_offsets", "rlqr_factor",
             "rlqr_factor_rhs", "rlqr_solve", "rlqr_solve_multi", "rlqr_pivot_inertia", "rlqr_residual", "rlqr_graph_capture", "rlqr_graph_launch",
-            "rlqr_set_skip", "rlqr_precision_path",
+            "rlqr_set_skip", "rlqr_precision_path", "rlqr_residual_noalloc",
             "rlqr_destroy", "rlqr_status_string")
 
 
@@ -214,6 +216,17 @@ def rlqr_residual(h, q, r, c, x, u, y, res=None, inst_relres=None, stream=None):
     sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
     _check(_lib.rlqr_residual(h, ctypes.byref(rhs), ctypes.byref(sol), _ptr(res), _ptr(inst_relres),
                               _stream(stream)), "rlqr_residual")
+
+
+def rlqr_residual_noalloc(N, nx, nu, Q, M, R, A, B, delta, q, r, c, x, u, y, res=None, inst_relres=None,
+                          stream=None, delta_diag=None):
+    """rlqr_residual without a handle (no device allocation; see include/rlqr.h)."""
+    shape, _keep = _shape(N, nx, nu)
+    lhs = _Lhs(_ptr(Q), _ptr(M), _ptr(R), _ptr(A), _ptr(B), _ptr(delta), _ptr(delta_diag))
+    rhs = _Rhs(_ptr(q), _ptr(r), _ptr(c))
+    sol = _Sol(_ptr(x), _ptr(u), _ptr(y))
+    _check(_lib.rlqr_residual_noalloc(ctypes.byref(shape), ctypes.byref(lhs), ctypes.byref(rhs), ctypes.byref(sol),
+                                      _ptr(res), _ptr(inst_relres), _stream(stream)), "rlqr_residual_noalloc")
 
 
 def rlqr_graph_capture(h, Q, M, R, A, B, delta, q, r, c, x, u, y, rel_tol, max_refine,

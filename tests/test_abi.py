@@ -203,3 +203,27 @@ def test_package_binds_to_a_single_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_residual_noalloc_rejects_bad_arguments_before_gpu_work():
+    """NULL arguments, shapes out of range and a batch beyond the scratch
+    array are rejected on the host (no pointer is dereferenced)."""
+    from paper_2509_16370_amd import rlqr
+    lib = rlqr._lib
+    lhs = rlqr._Lhs(*(8 for _ in range(7)))
+    rhs = rlqr._Rhs(8, 8, 8)
+    sol = rlqr._Sol(8, 8, 8)
+    assert lib.rlqr_residual_noalloc(None, None, None, None, None, None, None) == rlqr.RLQR_E_INVALID
+    for N, nx, nu in [(-1, 2, 1), (3, 0, 1), (3, 65, 1), (3, 60, 40)]:
+        shape, _keep = rlqr._shape([N], [nx], [nu])
+        assert lib.rlqr_residual_noalloc(ctypes.byref(shape), ctypes.byref(lhs), ctypes.byref(rhs),
+                                         ctypes.byref(sol), None, None, None) == rlqr.RLQR_E_INVALID
+    B = 200000  # 200000 instances need > 32 MB of metadata alone
+    shape, _keep = rlqr._shape(np.full(B, 1), np.full(B, 2), np.full(B, 1))
+    assert lib.rlqr_residual_noalloc(ctypes.byref(shape), ctypes.byref(lhs), ctypes.byref(rhs),
+                                     ctypes.byref(sol), None, None, None) == rlqr.RLQR_E_INVALID
+    bad_lhs = rlqr._Lhs(8, 8, 8, 8, 8, None, None)  # neither delta nor delta_diag
+    shape, _keep = rlqr._shape([3], [2], [1])
+    assert lib.rlqr_residual_noalloc(ctypes.byref(shape), ctypes.byref(bad_lhs), ctypes.byref(rhs),
+                                     ctypes.byref(sol), None, None, None) == rlqr.RLQR_E_INVALID
+
