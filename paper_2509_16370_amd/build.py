@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["rlqr_kernels.hip", "rlqr_kernels_mw.hip", "rlqr_scan.hip", "rlqr_api.hip", "rlqr_noalloc.hip", "rlqr_xs.hip", "rlqr_eq.hip", "ripm.hip", "rmlp.hip"]
+SOURCES = ["rlqr_kernels.hip", "rlqr_kernels_mw.hip", "rlqr_scan.hip", "rlqr_api.hip", "rlqr_noalloc.hip", "rlqr_spd.hip", "rlqr_xs.hip", "rlqr_eq.hip", "ripm.hip", "rmlp.hip"]
 LIB = os.path.join(HERE, "librlqr.so")
 
 HIPCC_FLAGS = [

@@ -5,7 +5,8 @@ librlqr.so. torch tensors provide device memory and the stream. The functions
 rlqr_create, rlqr_create_tuned, rlqr_get_tuning, rlqr_factor, rlqr_factor_rhs,
 rlqr_solve, rlqr_solve_multi, rlqr_pivot_inertia, rlqr_precision_path,
 rlqr_residual, rlqr_residual_noalloc and rlqr_destroy carry the C names; `Solver` wraps one handle. The cross-stage
-calls of include/rlqr_xs.h (rlqr_xs_*) are wrapped by `CrossStage`.
+calls of include/rlqr_xs.h (rlqr_xs_*) are wrapped by `CrossStage`, the
+general-SPD calls of include/rlqr_spd.h (rlqr_spd_*) by `SpdRegularized`.
 
 If librlqr.so is missing this module raises at import: there is no fallback.
 """
@@ -395,8 +396,77 @@ def to_device(packed, device="cuda:0"):
     lhs["delta"] = t(packed.delta)
     if "delta_diag" in packed.arrays:
         lhs["delta_diag"] = t(packed.arrays["delta_diag"])
+    if "delta_full" in packed.arrays:  # full SPD Delta_i (SpdRegularized), laid out like Q
+        lhs["delta_full"] = t(packed.arrays["delta_full"])
     rhs = {k: t(packed.arrays[k]) for k in ("q", "r", "c")}
     return lhs, rhs
+
+
+# ------------------------------------------------------------- general SPD Delta_i (include/rlqr_spd.h)
+
+_lib.rlqr_spd_create.argtypes = [ctypes.POINTER(_vp), _vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.rlqr_spd_factor.argtypes = [_vp, ctypes.POINTER(_Lhs), _vp, _vp]
+_lib.rlqr_spd_solve.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), ctypes.c_double, ctypes.c_int32,
+                                _vp, _vp, _vp]
+_lib.rlqr_spd_residual.argtypes = [_vp, ctypes.POINTER(_Rhs), ctypes.POINTER(_Sol), _vp, _vp, _vp]
+_lib.rlqr_spd_destroy.argtypes = [_vp]
+_lib.rlqr_spd_destroy.restype = None
+for _f in ("rlqr_spd_create", "rlqr_spd_factor", "rlqr_spd_solve", "rlqr_spd_residual"):
+    getattr(_lib, _f).restype = ctypes.c_int
+SPD_EXPORTED = ("rlqr_spd_create", "rlqr_spd_factor", "rlqr_spd_solve", "rlqr_spd_residual", "rlqr_spd_destroy")
+
+
+class SpdRegularized:
+    """rlqr_spd context over a Solver's handle: every Delta_i a full SPD
+    matrix (laid out like Q), solved through the handle's mode."""
+
+    def __init__(self, solver: "Solver"):
+        self.solver = solver
+        self.torch = solver.torch
+        ctx = _vp()
+        ws = ctypes.c_size_t(0)
+        with self.torch.cuda.device(solver.device):
+            _check(_lib.rlqr_spd_create(ctypes.byref(ctx), solver.handle, ctypes.byref(ws)), "rlqr_spd_create")
+        self.ctx, self.workspace_bytes = ctx, int(ws.value)
+        self._keep = None
+
+    def __del__(self):
+        x = getattr(self, "ctx", None)
+        if x is not None and x.value and _lib is not None:
+            try:
+                _lib.rlqr_spd_destroy(x)
+            except Exception:  # interpreter shutdown
+                pass
+            self.ctx = None
+
+    def factor(self, lhs, Delta, stream=None):
+        self._keep = (lhs, Delta)  # re-read by solve and residual
+        L = _Lhs(*[_ptr(lhs.get(k)) for k in ("Q", "M", "R", "A", "B")], None, None)
+        _check(_lib.rlqr_spd_factor(self.ctx, ctypes.byref(L), _ptr(Delta), _stream(stream)), "rlqr_spd_factor")
+
+    def solve(self, rhs, out=None, rel_tol: float = 1e-8, max_refine: int = 3, stream=None):
+        torch = self.torch
+        s = self.solver
+        if out is None:
+            out = {k: s.empty(k) for k in ("x", "u", "y")}
+        status = torch.empty(max(s.batch, 1), dtype=torch.int32, device=s.device)
+        relres = torch.empty(max(s.batch, 1), dtype=torch.float64, device=s.device)
+        R = _Rhs(_ptr(rhs["q"]), _ptr(rhs["r"]), _ptr(rhs["c"]))
+        S = _Sol(_ptr(out["x"]), _ptr(out["u"]), _ptr(out["y"]))
+        _check(_lib.rlqr_spd_solve(self.ctx, ctypes.byref(R), ctypes.byref(S), float(rel_tol), int(max_refine),
+                                   _ptr(status), _ptr(relres), _stream(stream)), "rlqr_spd_solve")
+        return out, status, relres
+
+    def residual(self, rhs, sol, stream=None):
+        torch = self.torch
+        s = self.solver
+        res = s.empty("res")
+        relres = torch.empty(max(s.batch, 1), dtype=torch.float64, device=s.device)
+        R = _Rhs(_ptr(rhs["q"]), _ptr(rhs["r"]), _ptr(rhs["c"]))
+        S = _Sol(_ptr(sol["x"]), _ptr(sol["u"]), _ptr(sol["y"]))
+        _check(_lib.rlqr_spd_residual(self.ctx, ctypes.byref(R), ctypes.byref(S), _ptr(res), _ptr(relres),
+                                      _stream(stream)), "rlqr_spd_residual")
+        return res, relres
 
 
 # ------------------------------------------------------------- cross-stage variables (include/rlqr_xs.h)

@@ -227,3 +227,23 @@ def test_residual_noalloc_rejects_bad_arguments_before_gpu_work():
     assert lib.rlqr_residual_noalloc(ctypes.byref(shape), ctypes.byref(bad_lhs), ctypes.byref(rhs),
                                      ctypes.byref(sol), None, None, None) == rlqr.RLQR_E_INVALID
 
+
+def test_library_exports_every_spd_symbol():
+    from paper_2509_16370_amd import rlqr
+    names = _declared(os.path.join(ROOT, "include", "rlqr_spd.h"), "rlqr_spd_")
+    assert set(names) == set(rlqr.SPD_EXPORTED)
+    lib = ctypes.CDLL(rlqr.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_spd_rejects_bad_arguments():
+    from paper_2509_16370_amd import rlqr
+    lib = rlqr._lib
+    x = ctypes.c_void_p()
+    assert lib.rlqr_spd_create(ctypes.byref(x), None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_spd_create(None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_spd_factor(None, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_spd_solve(None, None, None, 1e-8, 0, None, None, None) == rlqr.RLQR_E_INVALID
+    assert lib.rlqr_spd_residual(None, None, None, None, None, None) == rlqr.RLQR_E_INVALID
+    lib.rlqr_spd_destroy(None)
