@@ -106,41 +106,104 @@ def test_autotuned_ragged_batch_matches_oracle(rl):
             assert err <= 1e-7 * scale, (b, err)
 
 
+_RAGGED = {}
+
+
+def _full_ragged():
+    """The ragged benchmark batch and the oracle's solution, certificate and
+    residual of every instance (computed once per module)."""
+    if not _RAGGED:
+        insts = wl.batched_ragged()
+        packed = wl.pack(insts)
+        x, u, y, ost, _, dS, dG = oracle.seq_batch(packed, pivots=True)
+        certs = oracle.certificate_batch(packed, insts, dS, dG)
+        refs = wl.unpack_solution(packed, x, u, y)
+        orel = np.array([oracle.rel_residual(inst, *refs[b]) for b, inst in enumerate(insts)])
+        _RAGGED.update(insts=insts, packed=packed, certs=certs, refs=refs, orel=orel, ost=ost)
+    return _RAGGED
+
+
+def _check_full_ragged(rl, out, status, relres, verdict, first_bad, inertia):
+    """Every instance of the full ragged batch: certificate (verdict, first
+    failing pivot, inertia) equal to the oracle's, status, relative residual
+    <= 1e-8, and the solution element-wise within max(1e-7, 1e4 * (gpu +
+    oracle relative residual)) * max(1, |z|) of the oracle's -- indefinite
+    instances included (their KKT system has one solution; the oracle's own
+    residual on the worst of them is ~4e-7, which the bound accounts for)."""
+    import torch
+    torch.cuda.synchronize()
+    R = _full_ragged()
+    insts, packed = R["insts"], R["packed"]
+    B = packed.batch
+    rr = relres.cpu().numpy()[:B]
+    st = status.cpu().numpy()[:B]
+    vd, fb = verdict.cpu().numpy()[:B], first_bad.cpu().numpy()[:B]
+    ine = inertia.cpu().numpy().reshape(-1, 3)[:B]
+    assert (rr <= 1e-8).all(), rr.max()
+    assert (R["ost"] == 0).all()
+    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
+    nfalse = 0
+    for b, inst in enumerate(insts):
+        ov, ofb, oin = R["certs"][b]
+        assert vd[b] == int(ov) and fb[b] == ofb, (b, vd[b], ofb)
+        assert tuple(ine[b]) == oin, (b, tuple(ine[b]), oin)
+        assert st[b] == (rl.INST_OK if ov else rl.INST_NOT_PD), (b, st[b])
+        nfalse += 0 if ov else 1
+        ref = R["refs"][b]
+        scale = max(1.0, *(np.abs(a).max() for a in ref if a.size))
+        err = max(np.abs(a - c).max() if a.size else 0.0 for a, c in zip(sols[b], ref))
+        assert err <= max(1e-7, 1e4 * (rr[b] + R["orel"][b])) * scale, (b, err, scale)
+    # every indefinite instance fails the certificate (the parity is not vacuous)
+    assert nfalse >= sum(1 for i in insts if i.indefinite)
+
+
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_full_size_ragged_batch(rl, mode):
     """The ragged benchmark batch at full size (1024 instances, N up to 1000,
-    205 indefinite, delta = 1e-4), tile classes on their concurrent streams:
-    every instance meets 1e-8; certificate parity on a sample against the
-    oracle's pivots; every positive definite instance element-wise against
-    the oracle's batch solve."""
+    205 indefinite, delta = 1e-4), tile classes on their concurrent streams,
+    every instance checked against the oracle (see _check_full_ragged)."""
     import torch
     print(f"[gpu] full-size ragged batch mode={mode}", flush=True)
-    insts = wl.batched_ragged()
-    packed = wl.pack(insts)
+    R = _full_ragged()
+    packed = R["packed"]
     lhs, rhs = rl.to_device(packed)
     s = rl.Solver(packed.N, packed.n, packed.m, mode=mode)
     s.factor(lhs)
     out, status, relres = s.solve(rhs, rel_tol=1e-8, max_refine=3)
-    verdict, first_bad, _ = s.pivot_inertia()
-    torch.cuda.synchronize()
-    B = packed.batch
-    rr = relres.cpu().numpy()[:B]
-    assert (rr <= 1e-8).all(), rr.max()
-    vd, fb = verdict.cpu().numpy()[:B], first_bad.cpu().numpy()[:B]
-    st = status.cpu().numpy()[:B]
-    assert (vd[[b for b, i in enumerate(insts) if i.indefinite]] == 0).all()
-    rng = np.random.default_rng(11)
-    for b in rng.choice(B, 48, replace=False):
-        ref = oracle.seq(insts[b])
-        ov, ofb, _ = oracle.certificate(insts[b], ref["dS"], ref["dG"])
-        assert vd[b] == int(ov) and fb[b] == ofb, b
-        assert st[b] == (0 if ov else 1), b
-    x, u, y, ost, _ = oracle.seq_batch(packed)
-    sols = wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y")))
-    refs = wl.unpack_solution(packed, x, u, y)
-    for b, inst in enumerate(insts):
-        if inst.indefinite:
-            continue
-        scale = max(1.0, *(np.abs(a).max() for a in refs[b] if a.size))
-        err = max(np.abs(a - c).max() if a.size else 0.0 for a, c in zip(sols[b], refs[b]))
-        assert err <= 1e-7 * scale, (b, err)
+    verdict, first_bad, inertia = s.pivot_inertia()
+    _check_full_ragged(rl, out, status, relres, verdict, first_bad, inertia)
+    del s
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("source", ["tuner", "mixed_paths"])
+def test_full_size_tuned_graph(rl, source):
+    """The ragged benchmark batch at full size through one captured graph of
+    one handle under a tuning plan: the plan the coordinate-descent tuner
+    picks (one round, candidates float64 / mixed / scan with L = 64), and a
+    fixed plan that puts every path into the one graph (float64 for n = 32,
+    the float32-product recursion for n = 16, the scan with L = 32 for n = 8).
+    Two replays with the graph's own eager synchronizations between them;
+    every instance checked against the oracle."""
+    import torch
+    from paper_2509_16370_amd import tune
+    print(f"[gpu] full-size tuned graph source={source}", flush=True)
+    R = _full_ragged()
+    packed = R["packed"]
+    lhs, rhs = rl.to_device(packed)
+    if source == "tuner":
+        plan = tune.tune_batch(packed, lhs, rhs, rel_tol=1e-8, max_refine=3, reps=1, lengths=(64,), rounds=1,
+                               log=print)
+    else:
+        plan = {bk: (tune.Choice("fp64") if bk[0] == 32 else
+                     tune.Choice("mixed") if bk[0] == 16 else tune.Choice("scan", 32))
+                for bk in tune.buckets(packed)}
+    print(f"[gpu] plan: { {f'{k[0]},{k[1]}': c.key() for k, c in plan.items()} }", flush=True)
+    tb = tune.TunedBatch(packed, plan, lhs, rhs, rel_tol=1e-8, max_refine=3)
+    for rep in range(2):
+        out, status, relres = tb.run()
+        torch.cuda.synchronize()
+    verdict, first_bad, inertia = tb.solver.pivot_inertia()
+    _check_full_ragged(rl, out, status, relres, verdict, first_bad, inertia)
+    del tb
+    torch.cuda.empty_cache()
