@@ -208,6 +208,73 @@ __device__ __forceinline__ void sweep16(double (&X)[4], int j0, int j1, int lane
   if (j1 > j0) ps.minrel = fmin(ps.minrel, dmin / scale);
 }
 
+// sum over the 16 lanes of each row (DPP row rotations), then over the rows
+__device__ __forceinline__ double wave_sum_rows(double s) {
+#pragma unroll
+  for (int k = 1; k < 16; k <<= 1) {
+    const long long b = __double_as_longlong(s);
+    int lo, hi;
+    switch (k) {
+      case 1: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x121, 0xf, 0xf, false);
+              hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x121, 0xf, 0xf, false); break;
+      case 2: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x122, 0xf, 0xf, false);
+              hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x122, 0xf, 0xf, false); break;
+      case 4: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x124, 0xf, 0xf, false);
+              hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x124, 0xf, 0xf, false); break;
+      default: lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x128, 0xf, 0xf, false);
+               hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x128, 0xf, 0xf, false); break;
+    }
+    s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  return (lane_value(s, 0) + lane_value(s, 16)) + (lane_value(s, 32) + lane_value(s, 48));
+}
+
+// Inverse of a state pivot S_hat = I + E close to the identity, without its
+// pivot sweep. E (= delta P, or D P D with a per-stage diagonal) is symmetric,
+// so ||E||_2 <= ||E||_F = e. When e < 1, every eigenvalue of S_hat lies in
+// [1 - e, 1 + e]: S_hat is positive definite, every pivot of its LDL^T lies
+// in the same interval (a pivot is a Schur complement of a leading block,
+// bounded by that block's extreme eigenvalues), and
+//     S_hat^{-1} = I - E + E^2 - ... = Y_k + O(e^{k+1} / (1 - e)),
+// Y_1 = I - E, Y_j = I - E Y_{j-1}. neumann_terms returns the number of
+// terms k (<= 13) for which e^{k+1} stays below the unit roundoff of the
+// precision TG the tile is stored and multiplied in (a quarter of it), or 0
+// when e is too large (or not finite) and the sweep must run.
+template <typename TG>
+__device__ __forceinline__ int neumann_terms(double e) {
+  constexpr double tau = sizeof(TG) == 8 ? 0x1p-55 : 0x1p-26;
+  if (!(e <= 0.0625)) return 0;
+  int k = 1;
+  double t = e * e;
+  while (t > tau && k < 13) {
+    t *= e;
+    ++k;
+  }
+  return t <= tau ? k : 0;
+}
+
+// ||X - I||_F of a register tile X (wave-uniform), rows trow<TL>.
+template <typename TL>
+__device__ __forceinline__ double dist_identity(const double (&X)[4], int lane) {
+  const int col = lane & 15, grp = lane >> 4;
+  double s = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double d = X[v] - (trow<TL>(grp, v) == col ? 1.0 : 0.0);
+    s = __fma_rn(d, d, s);
+  }
+  return sqrt(wave_sum_rows(s));
+}
+
+// Certificate bookkeeping of a state pivot certified by the norm bound
+// (pivots j0..j1-1, all in [1 - e, 1 + e], hence positive and nonzero):
+// the counts the pivot sweep would give, and the bound (1 - e) / (1 + e) on
+// min |pivot| / max |diag|.
+__device__ __forceinline__ void neumann_stats(PivStats& ps, int j0, int j1, double e) {
+  ps.npos += j1 - j0;
+  if (j1 > j0) ps.minrel = fmin(ps.minrel, (1.0 - e) / (1.0 + e));
+}
+
 // X[J][J] of a register tile (wave-uniform)
 template <typename TL, int J>
 __device__ __forceinline__ double tile_diag(const double (&X)[4]) {

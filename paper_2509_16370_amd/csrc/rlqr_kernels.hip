@@ -334,6 +334,65 @@ __device__ __forceinline__ typename AccT<T>::type gemm_abt_t(const double* stg, 
   return acc;
 }
 
+// State pivot S_hat (register tile X, rows trow<TG>) -> X = -S_hat^{-1}, with
+// its certificate bookkeeping in ps (code: the pivot's certificate code).
+// When ||S_hat - I||_F is small enough (neumann_terms: always the case for a
+// small delta, where the Riccati recursion spends most of its time) the
+// inverse is the truncated Neumann series in the tile's precision TG -- Y_1 =
+// I - E elementwise, each further term one 16 x 16 MFMA product through LDS
+// (sE, sY: free TG tiles; sD: a float64 tile that may overlay them) -- and
+// the norm bound certifies every pivot positive; otherwise the pivot sweep
+// runs. Either way X is exactly symmetric on return (the compact float64
+// tiles keep one triangle). PROD = false (the kernels with a per-stage
+// diagonal, short of registers): only the one-term series (no product) is
+// taken, anything longer goes to the sweep.
+template <typename TG, bool PROD = true>
+__device__ __forceinline__ void shat_inverse(double (&X)[4], int n, int lane, PivStats& ps, int code, TG* sE,
+                                             TG* sY, double* sD) {
+  const double e = dist_identity<TG>(X, lane);
+  int terms = neumann_terms<TG>(e);
+  if (!PROD && terms > 1) terms = 0;
+  if (terms == 0) {
+    const double sc = diag_scale<TG>(X, 0, n, lane);
+    sweep16<TG>(X, 0, n, lane, ps, code, 1.0e3 * n * 2.220446049250313e-16 * sc, sc);
+    return;
+  }
+  const int col = lane & 15, grp = lane >> 4;
+  // X holds Y (the partial sums) from here on: no extra register tiles
+  if (PROD && terms > 1) {
+    double E[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) E[v] = X[v] - (trow<TG>(grp, v) == col ? 1.0 : 0.0);
+    wave_sync();
+    tile_to_lds<TG>(sE, E, lane);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double id = trow<TG>(grp, v) == col ? 1.0 : 0.0;
+    X[v] = id - (X[v] - id);  // Y_1 = I - E
+  }
+  if (PROD && terms > 1) {
+    for (int j = 2; j <= terms; ++j) {
+      wave_sync();
+      tile_to_lds<TG>(sY, X, lane);
+      wave_sync();
+      auto acc = gemm16<TG, false>(sE, sY, lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) - (double)acc[v];
+    }
+    // E Y is symmetric only up to rounding: Y <- (Y + Y^T) / 2
+    wave_sync();
+    tile_to_lds<TG>(sD, X, lane);
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[v] = 0.5 * (X[v] + sD[col * LD + trow<TG>(grp, v)]);
+    wave_sync();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[v] = -X[v];
+  neumann_stats(ps, 0, n, e);
+}
+
 // SN, SM > 0: stage shape fixed at compile time (every instance of the launch
 // has n = SN, m = SM); 0: taken from the instance.
 // DG: per-stage diagonal Delta_i = D_i^2 (a.dd): the swept matrix is the
@@ -458,10 +517,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + (DG ? sdr[v] * sdc * P[v] : delta * P[v]);
-    {
-      const double sc = diag_scale<TG>(X, 0, n, lane_s);
-      sweep16<TG>(X, 0, n, lane_s, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
-    }
+    shat_inverse<TG, !DG>(X, n, lane_s, ps, 2 * (k + 1), sP, sX, sD);
     const double idc = isdc * isdc;  // DG: 1 / Delta's entry of the column
     if constexpr (DG) {
 #pragma unroll
@@ -568,8 +624,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       X[v] = (trow<TG>(grp, v) == col ? 1.0 : 0.0) + (DG ? sdr[v] * sdc * P[v] : delta * P[v]);
-    const double sc = diag_scale<TG>(X, 0, n, lane);
-    sweep16<TG>(X, 0, n, lane, ps, 0, 1.0e3 * n * eps * sc, sc);
+    shat_inverse<TG, !DG>(X, n, lane, ps, 0, sP, sX, sD);
     if constexpr (DG) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) X[v] = sdr[v] * X[v] * sdc;  // X~_0 = D_0 X_0 D_0

@@ -61,6 +61,102 @@ struct MwCfg {
   static constexpr int BLOCKS_PER_STAGE = TZ * TZ + TX * TX;
 };
 
+// State pivot S_hat over a distributed NX x NX tile (owned blocks X[t] at
+// (xi[t], xj[t])) -> X = -S_hat^{-1}, certificate bookkeeping in ps. As in the
+// one-wavefront kernels: when ||S_hat - I||_F is small (neumann_terms), the
+// truncated Neumann series Y_1 = I - E, Y_j = I - E Y_{j-1} (one blocked MFMA
+// product and two workgroup barriers per further term, E and Y through the
+// LDS tiles sE and sY, stride LDX) replaces the pivot sweep and the norm bound
+// certifies every pivot positive; the result is symmetrized through sD (a
+// float64 tile that may overlay sE and sY). Otherwise the blocked sweep runs.
+template <typename TG, int TX, int CX, int NW>
+__device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&xi)[CX], const int (&xj)[CX],
+                                                const bool (&xo)[CX], int n, int w, int lane, double* red,
+                                                double* panel, double* mbuf, PivStats& ps, int code, TG* sE,
+                                                TG* sY, double* sD) {
+  constexpr int NX = 16 * TX, LDX = NX + 1;
+  const int col = lane & 15, grp = lane >> 4;
+  double s2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < CX; ++t)
+    if (xo[t])
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double d = X[t][v] - (16 * xi[t] + trow<TG>(grp, v) == 16 * xj[t] + col ? 1.0 : 0.0);
+        s2 = __fma_rn(d, d, s2);
+      }
+  s2 = wave_sum_rows(s2);
+  __syncthreads();
+  if (lane == 0) red[w] = s2;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) tot += red[i];  // same order in every thread: uniform
+  const double e = sqrt(tot);
+  const int terms = neumann_terms<TG>(e);
+  if (terms == 0) {
+    const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
+    sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, code,
+                          1.0e3 * n * 2.220446049250313e-16 * sc, sc);
+    return;
+  }
+  if (terms > 1) {
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t]) {
+        double E[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          E[v] = X[t][v] - (16 * xi[t] + trow<TG>(grp, v) == 16 * xj[t] + col ? 1.0 : 0.0);
+        blk_to_lds<TG>(sE, LDX, xi[t], xj[t], E, lane);
+      }
+  }
+  // X holds Y from here on
+#pragma unroll
+  for (int t = 0; t < CX; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double id = (16 * xi[t] + trow<TG>(grp, v) == 16 * xj[t] + col) ? 1.0 : 0.0;
+      X[t][v] = xo[t] ? id - (X[t][v] - id) : 0.0;
+    }
+  if (terms > 1) {
+    for (int j = 2; j <= terms; ++j) {
+#pragma unroll
+      for (int t = 0; t < CX; ++t)
+        if (xo[t]) blk_to_lds<TG>(sY, LDX, xi[t], xj[t], X[t], lane);
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < CX; ++t) {
+        if (!xo[t]) continue;
+        auto acc = gemm_blk<TG, false, TX>(sE, LDX, sY, LDX, xi[t], xj[t], lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          X[t][v] = (16 * xi[t] + trow<TG>(grp, v) == 16 * xj[t] + col ? 1.0 : 0.0) - (double)acc[v];
+      }
+      __syncthreads();
+    }
+    // E Y is symmetric only up to rounding: Y <- (Y + Y^T) / 2
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t]) blk_to_lds<TG>(sD, LDX, xi[t], xj[t], X[t], lane);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < CX; ++t)
+      if (xo[t])
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
+          X[t][v] = 0.5 * (X[t][v] + sD[c * LDX + r]);
+        }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < CX; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[t][v] = -X[t][v];
+  neumann_stats(ps, 0, n, e);
+}
+
 // DG: per-stage diagonal Delta_i (a.dd); the instantiations without it carry none of its code
 template <typename TG, int TX, int TZ, int NW, bool DG>
 __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
@@ -240,10 +336,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
-    {
-      const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
-      sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 2 * (k + 1), 1.0e3 * n * eps * sc, sc);
-    }
+    shat_inverse_mw<TG, TX, CX, NW>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 2 * (k + 1), sP, sX, sD);
     if constexpr (DG) scale_x(X);  // X~ = D X D
     {
       TG* xt = xtile(k + 1);
@@ -367,8 +460,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
-    const double sc = wg_max<NW>(diag_max<CX, TG>(X, xi, xj, xo, 0, n, lane), red, w, lane);
-    sweep_blk<TG, CX, TX>(X, xi, xj, xo, 0, n, w, lane, panel, mbuf, ps, 0, 1.0e3 * n * eps * sc, sc);
+    shat_inverse_mw<TG, TX, CX, NW>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 0, sP, sX, sD);
     if constexpr (DG) scale_x(X);  // X~_0 = D_0 X_0 D_0
     TG* xt = xtile(0);
 #pragma unroll
