@@ -46,6 +46,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "dual-reg LQR stage-solves/s at 1e-8 KKT residual, mixed vs FP64 plain"
+MW_WAVES = 0  # --mw-waves: wavefronts per instance for 16 < n + m <= 48 (0: the library's default)
 HBM_PEAK_GBS = 8000.0
 REL_TOL = 1e-8
 
@@ -81,7 +82,7 @@ def run_mode(torch, rl, packed, lhs, rhs, mode, steps, warmup, max_refine, rel_t
     else:
         # scan_pc: the scan mode carrying p and c through the reverse scan
         s = rl.Solver(packed.N, packed.n, packed.m, mode="scan" if mode == "scan_pc" else mode,
-                      scan_chunk=chunk, scan_carry_pc=mode == "scan_pc")
+                      scan_chunk=chunk, scan_carry_pc=mode == "scan_pc", mw_waves=MW_WAVES)
         out = {k: s.empty(k) for k in ("x", "u", "y")}
 
         def step(ev=None):
@@ -427,11 +428,15 @@ def main():
                     help="batched_uniform: per-stage diagonal Delta_i with entries delta * 10^U(-s, s)")
     ap.add_argument("--max-refine", type=int, default=3)
     ap.add_argument("--modes", default=None)
+    ap.add_argument("--mw-waves", type=int, default=0,
+                    help="wavefronts per instance of the kernels for 16 < n + m <= 48 (4 or 8; 0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch one plain 1 GiB float32 copy kernel (rmlp_cast) for counter calibration")
     args = ap.parse_args()
+    global MW_WAVES
+    MW_WAVES = args.mw_waves
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batch is "
               "independent instances and would shard by instance across GPUs, which this "
@@ -573,7 +578,8 @@ def main():
             plan = tune.tune_batch(packed, lhs, rhs, rel_tol=rel_tol, max_refine=max_refine, reps=2,
                                    log=lambda msg: print(msg, file=sys.stderr, flush=True))
             print(f"[bench] tuned {len(plan)} buckets in {time.perf_counter() - t1:.1f}s: "
-                  + ", ".join(f"{k}: {c.key()}" for k, c in plan.items()), file=sys.stderr, flush=True)
+                  + ", ".join(f"{k}: {c.key()}" for k, c in plan.items())
+                  + f"; waves per instance {plan.mw_waves or 4}", file=sys.stderr, flush=True)
         if eqd is not None:
             results[mode] = run_eq_mode(torch, rl, packed, lhs, rhs, eqd, args.ne, mode, steps, warmup,
                                         max_refine, rel_tol=rel_tol)
@@ -585,6 +591,7 @@ def main():
                                      rel_tol=rel_tol, chunk=args.chunk, plan=plan)
         if plan is not None:
             results[mode]["plan"] = {f"{k[0]},{k[1]}": c.key() for k, c in plan.items()}
+            results[mode]["plan"]["waves_per_instance"] = plan.mw_waves or 4
         print(f"[bench] {mode}: {json.dumps(results[mode])}", file=sys.stderr, flush=True)
 
     head = head if head in results else modes[0]

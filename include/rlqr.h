@@ -176,6 +176,12 @@ typedef struct {
                                   refinement passes use the p-recurrence. Float32
                                   vectors, 2 n_pad floats per element. Ignored by the
                                   sequential modes and by rlqr_factor. */
+  int32_t mw_waves;            /* wavefronts per instance (one workgroup) in the kernels
+                                  of instances with 16 < n + m <= 48 and n <= 32: 0 or 4
+                                  (default) or 8. More wavefronts shorten each stage's
+                                  dependent chain of block products at the price of
+                                  more workgroup slots; results are identical. Larger
+                                  stages keep their fixed counts. */
 } rlqr_tuning;
 
 /*

@@ -133,6 +133,7 @@ struct rlqr_handle {
   // left-hand side; its vectors sit at j times the batch lengths. A call
   // with r right-hand sides uses the first r*B virtual instances.
   int max_rhs = 1;
+  int mw_waves = 4;  // wavefronts per workgroup of the multi-wavefront classes up to 32 x 48 (4 or 8)
   rlqr_handle* mv = nullptr;
   int Bbase = 0;                                   // (mv) instances per right-hand side
   int base_count[TILE_CLASSES] = {};               // (mv) per right-hand side
@@ -235,6 +236,7 @@ static rlqr_status build_multi(rlqr_handle* h, int R, const std::vector<InstMeta
   rlqr_handle* v = new (std::nothrow) rlqr_handle();
   if (!v) return RLQR_E_NOMEM;
   v->B = VB; v->mode = h->mode; v->chunk = h->chunk; v->shape16 = h->shape16; v->shape_all = h->shape_all;
+  v->mw_waves = h->mw_waves;
   v->ws64 = h->ws64; v->ws32 = h->ws32;  // shared, owned by h
   for (int c = 0; c < TILE_CLASSES; ++c) { v->side[c] = h->side[c]; v->ev_join[c] = h->ev_join[c]; }
   v->ev_fork = h->ev_fork;  // shared, owned by h (v->owns_streams stays false)
@@ -366,6 +368,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED && mode != RLQR_SCAN_FP32 && mode != RLQR_SCAN_BF16)
     return RLQR_E_INVALID;
   if (tune && (tune->scan_chunk < 0 || tune->max_rhs < 0)) return RLQR_E_INVALID;
+  if (tune && tune->mw_waves != 0 && tune->mw_waves != 4 && tune->mw_waves != 8) return RLQR_E_INVALID;
   const int B = s->batch;
   if (B > 0 && (!s->N || !s->nx || !s->nu)) return RLQR_E_INVALID;
   for (int b = 0; b < B; ++b) {
@@ -382,6 +385,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   h->m.assign(s->nu, s->nu + B);
   const bool scan = is_scan(mode);
   h->carry_pc = scan && tune && tune->scan_carry_pc != 0;
+  h->mw_waves = (tune && tune->mw_waves == 8) ? 8 : 4;
 
   // segment length: about one segment per compute unit (256) over the whole
   // batch, so the chunk folds and the segment recursions run in one round and
@@ -663,6 +667,7 @@ rlqr_status rlqr_get_tuning(const rlqr_handle* h, rlqr_tuning* t) {
   t->inst_fp64 = nullptr;
   t->max_rhs = h->max_rhs;
   t->scan_carry_pc = h->carry_pc ? 1 : 0;
+  t->mw_waves = h->mw_waves;
   return RLQR_OK;
 }
 
@@ -730,7 +735,7 @@ static hipError_t factor_segments(rlqr_handle* h, const SegList* lists, const in
       a.q = rhs->q; a.r = rhs->r; a.c = rhs->c; a.pk = h->pk;
     }
     return (c == TILE_16) ? launch_factor(a, lists[c].count, fp32, h->shape16, s2)
-                          : launch_factor_mw(c, a, lists[c].count, fp32, s2);
+                          : launch_factor_mw(c, a, lists[c].count, fp32, s2, h->mw_waves);
   });
   if (e != hipSuccess) return e;
   MergeArgs m{};
@@ -896,7 +901,7 @@ static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* ou
       a.res = res_out; a.resmax = h->resmax; a.bmax = h->bmax; a.resfuse = h->resfuse;
     }
     return (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, s2)
-                          : launch_solve_mw(c, a, h->count[c], fp32, s2);
+                          : launch_solve_mw(c, a, h->count[c], fp32, s2, h->mw_waves);
   });
   return e == hipSuccess ? RLQR_OK : RLQR_E_HIP;
 }

@@ -221,8 +221,11 @@ inline int fixed_shape(int n, int m) {
   return SHAPE_ANY;
 }
 hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, int shape, hipStream_t st);
-hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st);
-hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st);
+// waves: wavefronts per workgroup of the multi-wavefront kernels for the tile
+// classes up to 32 x 48 (TILE_X1_Z2, TILE_X2_Z2, TILE_X2_Z3): 4 or 8; the
+// larger classes have their own fixed counts (9, 16)
+hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st, int waves = 4);
+hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st, int waves = 4);
 hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, int shape, hipStream_t st);
 hipError_t launch_residual(const ResidualArgs& a, int shape, hipStream_t st);
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);

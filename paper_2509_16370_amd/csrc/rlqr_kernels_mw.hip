@@ -856,11 +856,15 @@ static hipError_t launch_mw_pair(bool factor, const void* args, int nblocks, hip
 }
 
 template <typename TG>
-static hipError_t launch_mw_t(int cls, bool factor, const void* args, int nblocks, hipStream_t st) {
+static hipError_t launch_mw_t(int cls, bool factor, const void* args, int nblocks, hipStream_t st, int waves) {
+  const bool w8 = waves == 8;
   switch (cls) {
-    case TILE_X1_Z2: return launch_mw_pair<TG, 1, 2, 4>(factor, args, nblocks, st);
-    case TILE_X2_Z2: return launch_mw_pair<TG, 2, 2, 4>(factor, args, nblocks, st);
-    case TILE_X2_Z3: return launch_mw_pair<TG, 2, 3, 4>(factor, args, nblocks, st);
+    case TILE_X1_Z2: return w8 ? launch_mw_pair<TG, 1, 2, 8>(factor, args, nblocks, st)
+                               : launch_mw_pair<TG, 1, 2, 4>(factor, args, nblocks, st);
+    case TILE_X2_Z2: return w8 ? launch_mw_pair<TG, 2, 2, 8>(factor, args, nblocks, st)
+                               : launch_mw_pair<TG, 2, 2, 4>(factor, args, nblocks, st);
+    case TILE_X2_Z3: return w8 ? launch_mw_pair<TG, 2, 3, 8>(factor, args, nblocks, st)
+                               : launch_mw_pair<TG, 2, 3, 4>(factor, args, nblocks, st);
     case TILE_X3_Z3: return launch_mw_pair<TG, 3, 3, 9>(factor, args, nblocks, st);
     case TILE_X4_Z4: return launch_mw_pair<TG, 4, 4, 16>(factor, args, nblocks, st);
     case TILE_X4_Z6: return launch_mw_pair<TG, 4, 6, 16>(factor, args, nblocks, st);
@@ -868,14 +872,16 @@ static hipError_t launch_mw_t(int cls, bool factor, const void* args, int nblock
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st) {
+hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st, int waves) {
   if (nblocks <= 0) return hipSuccess;
-  return fp32 ? launch_mw_t<float>(cls, true, &a, nblocks, st) : launch_mw_t<double>(cls, true, &a, nblocks, st);
+  return fp32 ? launch_mw_t<float>(cls, true, &a, nblocks, st, waves)
+              : launch_mw_t<double>(cls, true, &a, nblocks, st, waves);
 }
 
-hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st) {
+hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st, int waves) {
   if (nblocks <= 0) return hipSuccess;
-  return fp32 ? launch_mw_t<float>(cls, false, &a, nblocks, st) : launch_mw_t<double>(cls, false, &a, nblocks, st);
+  return fp32 ? launch_mw_t<float>(cls, false, &a, nblocks, st, waves)
+              : launch_mw_t<double>(cls, false, &a, nblocks, st, waves);
 }
 
 // Segment solves (scan mode, float32 tiles); the one-wavefront class uses the

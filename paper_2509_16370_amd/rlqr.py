@@ -64,7 +64,7 @@ class _Sol(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("scan_chunk", ctypes.c_int32), ("inst_chunk", _i32p), ("inst_fp64", _i32p),
-                ("max_rhs", ctypes.c_int32), ("scan_carry_pc", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("scan_carry_pc", ctypes.c_int32), ("mw_waves", ctypes.c_int32)]
 
 
 _lib.rlqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Shape), ctypes.c_int,
@@ -145,7 +145,7 @@ def rlqr_create(N: Sequence[int], nx: Sequence[int], nu: Sequence[int], mode: in
 
 
 def rlqr_create_tuned(N, nx, nu, mode: int, scan_chunk: int = 0, inst_chunk=None, inst_fp64=None, max_rhs: int = 0,
-                      scan_carry_pc: bool = False):
+                      scan_carry_pc: bool = False, mw_waves: int = 0):
     """Returns (handle, workspace_bytes). inst_chunk / inst_fp64: optional per-instance arrays."""
     shape, _keep = _shape(N, nx, nu)
     h = _vp()
@@ -153,7 +153,8 @@ def rlqr_create_tuned(N, nx, nu, mode: int, scan_chunk: int = 0, inst_chunk=None
     ic = None if inst_chunk is None else np.ascontiguousarray(inst_chunk, dtype=np.int32)
     i64 = None if inst_fp64 is None else np.ascontiguousarray(inst_fp64, dtype=np.int32)
     t = _Tuning(int(scan_chunk), ic.ctypes.data_as(_i32p) if ic is not None else None,
-                i64.ctypes.data_as(_i32p) if i64 is not None else None, int(max_rhs), int(bool(scan_carry_pc)))
+                i64.ctypes.data_as(_i32p) if i64 is not None else None, int(max_rhs), int(bool(scan_carry_pc)),
+                int(mw_waves))
     _check(_lib.rlqr_create_tuned(ctypes.byref(h), ctypes.byref(shape), int(mode), ctypes.byref(t),
                                   ctypes.byref(ws)), "rlqr_create_tuned")
     return h, int(ws.value)
@@ -162,7 +163,8 @@ def rlqr_create_tuned(N, nx, nu, mode: int, scan_chunk: int = 0, inst_chunk=None
 def rlqr_get_tuning(h) -> Dict[str, int]:
     t = _Tuning(0)
     _check(_lib.rlqr_get_tuning(h, ctypes.byref(t)), "rlqr_get_tuning")
-    return {"scan_chunk": int(t.scan_chunk), "max_rhs": int(t.max_rhs), "scan_carry_pc": int(t.scan_carry_pc)}
+    return {"scan_chunk": int(t.scan_chunk), "max_rhs": int(t.max_rhs), "scan_carry_pc": int(t.scan_carry_pc),
+            "mw_waves": int(t.mw_waves)}
 
 
 def rlqr_layout_offsets(h, array: int, batch: int) -> np.ndarray:
@@ -254,7 +256,7 @@ class Solver:
     """One handle over a fixed batch of shapes; tensors are torch CUDA float64."""
 
     def __init__(self, N, nx, nu, mode: str = "fp64", device: str = "cuda:0", scan_chunk: int = 0,
-                 inst_chunk=None, inst_fp64=None, max_rhs: int = 0, scan_carry_pc: bool = False):
+                 inst_chunk=None, inst_fp64=None, max_rhs: int = 0, scan_carry_pc: bool = False, mw_waves: int = 0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -266,7 +268,7 @@ class Solver:
         with torch.cuda.device(self.device):
             self.handle, self.workspace_bytes = rlqr_create_tuned(self.N, self.nx, self.nu, MODES[mode],
                                                                   scan_chunk, inst_chunk, inst_fp64, max_rhs,
-                                                                  scan_carry_pc)
+                                                                  scan_carry_pc, mw_waves)
         self.tuning = rlqr_get_tuning(self.handle)
         self.offsets = {name: rlqr_layout_offsets(self.handle, i, self.batch) for i, name in enumerate(ARRAYS)}
         self._lhs = None

@@ -34,6 +34,16 @@ from . import workloads as wl
 Bucket = Tuple[int, int]
 
 
+class Plan(dict):
+    """Bucket -> Choice, plus the batch-level schedule: mw_waves, the
+    wavefronts per instance of the multi-wavefront kernels for stages with
+    16 < n + m <= 48 (0: the library's default of four, or 8)."""
+
+    def __init__(self, *args, mw_waves: int = 0, **kw):
+        super().__init__(*args, **kw)
+        self.mw_waves = mw_waves
+
+
 @dataclasses.dataclass
 class Choice:
     path: str          # "fp64", "mixed" or "scan"
@@ -110,7 +120,7 @@ def tune(packed: wl.Packed, rel_tol: float = 1e-8, max_refine: int = 3, reps: in
     """Time every candidate on each bucket's instances; return the plan."""
     import torch
     from . import rlqr as rl
-    plan: Dict[Bucket, Choice] = {}
+    plan = Plan()
     for bk, ids in buckets(packed).items():
         sub = subset(packed, ids)
         lhs, rhs = rl.to_device(sub, device)
@@ -154,7 +164,7 @@ def tune_batch(packed: wl.Packed, lhs, rhs, rel_tol: float = 1e-8, max_refine: i
     """Coordinate descent over the buckets with whole-batch timing (see module doc)."""
     bks = buckets(packed)
     work = {bk: float(sum(int(packed.N[b]) * (bk[0] + bk[1]) ** 3 for b in ids)) for bk, ids in bks.items()}
-    plan = {bk: Choice("fp64") for bk in bks}
+    plan = Plan({bk: Choice("fp64") for bk in bks})
     best = time_plan(packed, plan, lhs, rhs, rel_tol, max_refine, reps, device)
     if log:
         log(f"[tune] all-fp64: {best:.3f} ms")
@@ -164,7 +174,7 @@ def tune_batch(packed: wl.Packed, lhs, rhs, rel_tol: float = 1e-8, max_refine: i
             for c in candidates(bk[0], bk[1], Nmax, lengths):
                 if c.key() == plan[bk].key():
                     continue
-                trial = dict(plan)
+                trial = Plan(plan, mw_waves=plan.mw_waves)
                 trial[bk] = c
                 t = time_plan(packed, trial, lhs, rhs, rel_tol, max_refine, reps, device)
                 if log:
@@ -172,16 +182,27 @@ def tune_batch(packed: wl.Packed, lhs, rhs, rel_tol: float = 1e-8, max_refine: i
                 if t < 0.98 * best:
                     best, plan = t, trial
                     plan[bk].ms = t
+    # schedule: eight wavefronts per instance for the stages with 16 < n + m <= 48
+    if any(16 < n + m <= 48 and n <= 32 for n, m in bks):
+        trial = Plan(plan, mw_waves=8)
+        t = time_plan(packed, trial, lhs, rhs, rel_tol, max_refine, reps, device)
+        if log:
+            log(f"[tune] eight wavefronts per instance: {t:.3f} ms (best {best:.3f})")
+        if t < 0.98 * best:
+            best, plan = t, trial
     return plan
 
 
 def save_plan(plan: Dict[Bucket, Choice], path: str) -> None:
-    json.dump({f"{n},{m}": dataclasses.asdict(c) for (n, m), c in plan.items()}, open(path, "w"), indent=1)
+    d = {f"{n},{m}": dataclasses.asdict(c) for (n, m), c in plan.items()}
+    d["mw_waves"] = int(getattr(plan, "mw_waves", 0))
+    json.dump(d, open(path, "w"), indent=1)
 
 
-def load_plan(path: str) -> Dict[Bucket, Choice]:
+def load_plan(path: str) -> "Plan":
     d = json.load(open(path))
-    return {tuple(int(v) for v in k.split(",")): Choice(**c) for k, c in d.items()}
+    w = int(d.pop("mw_waves", 0))
+    return Plan({tuple(int(v) for v in k.split(",")): Choice(**c) for k, c in d.items()}, mw_waves=w)
 
 
 class TunedBatch:
@@ -195,7 +216,7 @@ class TunedBatch:
         self.torch = torch
         chunk, fp64 = plan_arrays(packed, plan)
         self.solver = rl.Solver(packed.N, packed.n, packed.m, mode="scan", device=device,
-                                inst_chunk=chunk, inst_fp64=fp64)
+                                inst_chunk=chunk, inst_fp64=fp64, mw_waves=getattr(plan, "mw_waves", 0))
         self.lhs, self.rhs = lhs, rhs
         self.out = {k: self.solver.empty(k) for k in ("x", "u", "y")}
         self.stream = torch.cuda.Stream(device=device)

@@ -330,3 +330,37 @@ def test_multiwave_tile_classes_match_oracle(rl, mode):
     res = run(rl, insts, mode)
     for b, inst in enumerate(insts):
         check_instance(rl, inst, res, b, 1e-10 if mode == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_eight_wavefronts_per_instance_match_four(rl, mode):
+    """rlqr_tuning.mw_waves = 8 (stages with 16 < n + m <= 48) gives the
+    results of the default four wavefronts: identical certificates, solutions
+    within float64 rounding of each other, and the oracle's gates."""
+    import torch
+    print(f"[gpu] eight wavefronts mode={mode}", flush=True)
+    insts = []
+    for ci, (n, m) in enumerate([(10, 12), (16, 8), (20, 10), (24, 20), (32, 8), (32, 2)]):
+        for j, (N, delta, indef) in enumerate([(0, 1e-6, False), (9, 1e-4, False), (13, 1e-2, True), (40, 1e-8, False)]):
+            insts.append(wl.make_instance(n, m, N, delta, (61, ci, j), indefinite=indef))
+    packed = wl.pack(insts)
+    lhs, rhs = rl.to_device(packed)
+    res = {}
+    for w in (4, 8):
+        s = rl.Solver(packed.N, packed.n, packed.m, mode=mode, mw_waves=w)
+        assert s.tuning["mw_waves"] == w
+        s.factor(lhs)
+        out, status, relres = s.solve(rhs, rel_tol=1e-8, max_refine=3)
+        verdict, first_bad, inertia = s.pivot_inertia()
+        torch.cuda.synchronize()
+        B = packed.batch
+        res[w] = dict(sols=wl.unpack_solution(packed, *(out[k].cpu().numpy() for k in ("x", "u", "y"))),
+                      status=status.cpu().numpy()[:B], relres=relres.cpu().numpy()[:B],
+                      verdict=verdict.cpu().numpy()[:B], first_bad=first_bad.cpu().numpy()[:B],
+                      inertia=inertia.cpu().numpy().reshape(-1, 3)[:B])
+    for k in ("status", "verdict", "first_bad", "inertia"):
+        assert np.array_equal(res[4][k], res[8][k]), k
+    for b, inst in enumerate(insts):
+        compare(inst, res[8]["sols"][b], dict(zip(("x", "u", "y"), res[4]["sols"][b])),
+                1e-12 if mode == "fp64" else 1e-8)
+        check_instance(rl, inst, res[8], b, 1e-10 if mode == "fp64" else 1e-7)

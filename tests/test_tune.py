@@ -50,3 +50,11 @@ def test_plan_round_trip(tmp_path):
     tune.save_plan(plan, str(p))
     back = tune.load_plan(str(p))
     assert back == plan
+
+
+def test_plan_round_trip_keeps_the_schedule(tmp_path):
+    plan = tune.Plan({(16, 4): tune.Choice("fp64", 0, 2.0)}, mw_waves=8)
+    p = tmp_path / "plan.json"
+    tune.save_plan(plan, str(p))
+    back = tune.load_plan(str(p))
+    assert back == plan and back.mw_waves == 8
