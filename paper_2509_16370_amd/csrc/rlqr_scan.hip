@@ -149,7 +149,7 @@ struct ScanLds {
   float P2[C::TILE], A2[C::TILE];               // next (j -> k)
   float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
   float YA[C::TILE], YC[C::TILE];
-  float rowbuf[2 * C::NX], colbuf[C::NX];
+  float rowbuf[2 * C::NX], colbuf[2 * C::NX];  // Gauss-Jordan pivot row; pivot column (two slots)
   float pv1[C::NX], cv1[C::NX], pv2[C::NX], cv2[C::NX], tv[C::NX], tw[C::NX];  // carried p, c
   int piv;
 };
@@ -203,7 +203,7 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
   constexpr int NX = C::NX, LDX = C::LDX, LDW = C::LDW, CB = C::CB;
   const int w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   bool ok = true;
-  // X = I + C1 P2, W = [X | I]
+  // X = I + C1 P2 into the left half of W
 #pragma unroll
   for (int t = 0; t < CB; ++t) {
     const int bx = w + NW * t;
@@ -213,45 +213,82 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
-      s.W[r * LDW + c] = acc[v] + (r == c ? 1.0f : 0.0f);
-      s.W[r * LDW + NX + c] = (r == c) ? 1.0f : 0.0f;
+      s.W[r * LDW + c] = acc[v] + (r == c ? 1.0f : 0.0f);  // the identity half is built in registers below
     }
   }
   __syncthreads();
-  // Gauss-Jordan with partial pivoting on the first n pivots
-  for (int j = 0; j < n; ++j) {
-    if (w == 0) {
-      const float a = (lane < NX && lane >= j) ? fabsf(s.W[lane * LDW + j]) : -1.0f;
+  // Gauss-Jordan with partial pivoting on the first n pivots, [X | I] held in
+  // registers: thread tid owns KPT consecutive entries of row r (columns c0
+  // .. c0 + KPT - 1 of the NX x 2NX matrix). Rows are never swapped: pivot j
+  // is the unused row p_j with the largest |column j| entry (lowest row on
+  // ties), the row is scaled and column j eliminated from every other row, and
+  // at the end row p_j of the right half is row j of X^{-1}. Per pivot two
+  // workgroup barriers: one publishes the column (written by its owners at
+  // the end of the previous pivot, two slots), after which every wavefront
+  // finds the same pivot row; one publishes the scaled pivot row. Only the
+  // pivot column and row pass through LDS.
+  {
+    constexpr int KPT = (2 * NX * NX) / (64 * NW);  // entries per thread
+    constexpr int TPR = 2 * NX / KPT;                // threads per row
+    static_assert(KPT * 64 * NW == 2 * NX * NX && TPR * KPT == 2 * NX, "Gauss-Jordan thread map");
+    const int r = tid / TPR, c0 = (tid % TPR) * KPT;
+    float g[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int c = c0 + k;
+      g[k] = c < NX ? s.W[r * LDW + c] : (c - NX == r ? 1.0f : 0.0f);
+    }
+    if (n > 0 && c0 == 0) s.colbuf[r] = g[0];  // column 0, slot 0
+    unsigned long long used = 0ull;
+    int myq = r;  // row of X^{-1} this thread's right half becomes (rows beyond n: themselves)
+    bool sing = false;
+    for (int j = 0; j < n; ++j) {
+      const float* cb = s.colbuf + NX * (j & 1);
+      __syncthreads();  // column j published; the previous pivot row read by all
+      const bool cand = lane < NX && !((used >> lane) & 1ull);
+      const float a = cand ? fabsf(cb[lane]) : -1.0f;
       // largest |candidate|, lowest row on ties: DPP maxima within 16-lane rows,
-      // the four row maxima by v_readlane, the row by a ballot
+      // the four row maxima by v_readlane, the row by a ballot (the same in
+      // every wavefront); with no match (every candidate NaN) the lowest unused
+      // row is taken and the zero test marks the scan singular
       const float best = wave_max_f32(a);
-      // only candidate rows j..NX-1; with no match (every candidate NaN) the
-      // row stays j and the zero test below marks the scan singular
-      const unsigned long long bal = __ballot(lane < NX && lane >= j && a == best);
-      const int p = bal ? __builtin_ctzll(bal) : j;
-      // swap rows j and p, then publish the scaled pivot row and column j
-      for (int c = lane; c < 2 * NX; c += 64) {
-        const float vj = s.W[j * LDW + c], vp = s.W[p * LDW + c];
-        s.W[j * LDW + c] = vp;
-        s.W[p * LDW + c] = vj;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const float d = s.W[j * LDW + j];
+      const unsigned long long bal = __ballot(cand && a == best);
+      const unsigned long long freer = ~used & (NX == 64 ? ~0ull : ((1ull << NX) - 1ull));
+      const int p = bal ? __builtin_ctzll(bal) : __builtin_ctzll(freer);
+      used |= 1ull << p;
+      sing = sing || !(best > 0.0f);
+      const float d = cb[p];
       const float rd = (best > 0.0f) ? 1.0f / d : 0.0f;
-      if (lane == 0 && !(best > 0.0f)) s.piv = -1;
-      for (int c = lane; c < 2 * NX; c += 64) s.rowbuf[c] = s.W[j * LDW + c] * rd;
-      if (lane < NX) s.colbuf[lane] = s.W[lane * LDW + j];
+      const float cr = cb[r];
+      if (r == p) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) s.rowbuf[c0 + k] = g[k] * rd;
+        myq = j;
+      }
+      __syncthreads();  // pivot row published
+#pragma unroll
+      for (int k = 0; k < KPT; ++k) {
+        const float rv = s.rowbuf[c0 + k];
+        g[k] = (r == p) ? rv : fmaf(-cr, rv, g[k]);
+      }
+      // the next pivot column, published by its owners into the other slot
+      const int jn = j + 1;
+      if (jn < n && jn >= c0 && jn < c0 + KPT) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k)
+          if (c0 + k == jn) s.colbuf[NX * (jn & 1) + r] = g[k];
+      }
     }
-    __syncthreads();
-    for (int x = tid; x < NX * 2 * NX; x += 64 * NW) {
-      const int r = x / (2 * NX), c = x % (2 * NX);
-      const float rv = s.rowbuf[c];
-      s.W[r * LDW + c] = (r == j) ? rv : fmaf(-s.colbuf[r], rv, s.W[r * LDW + c]);
+    if (tid == 0 && sing) s.piv = -1;
+    __syncthreads();  // every read of W's left half and of the buffers is done
+    // X^{-1}: row p_j of the right half is row j
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int c = c0 + k;
+      if (c >= NX) s.W[myq * LDW + c] = g[k];
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (s.piv < 0) ok = false;
   // Y_A = X^{-1} A1, Y_C = X^{-1} C1
 #pragma unroll
