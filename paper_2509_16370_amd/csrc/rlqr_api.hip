@@ -445,6 +445,11 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
     seg_off[b + 1] = seg_off[b] + nseg[b];
     whole_off[b + 1] = b + 1;
   }
+  // Longest first: a class launch whose workgroups do not all fit on the GPU
+  // at once dispatches them in list order, and a workgroup's time is its
+  // instance's sequential stage loop, so the longest loops start first.
+  for (auto& l : lists)
+    std::stable_sort(l.begin(), l.end(), [&](int32_t x, int32_t y) { return h->N[x] > h->N[y]; });
   // one fixed-shape kernel serves the one-wavefront class if all its instances share the shape
   {
     int sn = -1, sm = -1;
@@ -564,11 +569,14 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   // segment descriptors (device pointers into the scan buffers are known now)
   std::vector<std::vector<SegDesc>> whole_d(TILE_CLASSES), fseg_d(TILE_CLASSES), sseg_d(TILE_CLASSES);
   if (st == RLQR_OK) {
+    for (int c = 0; c < TILE_CLASSES; ++c)
+      for (int b : lists[c]) {
+        SegDesc d{};
+        d.inst = b; d.lo = 0; d.hi = h->N[b]; d.p0_ld = 0; d.gidx = b; d.s = 0; d.P0 = nullptr;
+        whole_d[c].push_back(d);
+      }
     for (int b = 0; b < B; ++b) {
-      SegDesc d{};
-      d.inst = b; d.lo = 0; d.hi = h->N[b]; d.p0_ld = 0; d.gidx = b; d.s = 0; d.P0 = nullptr;
-      whole_d[cls[b]].push_back(d);
-      if (!scan) continue;
+      if (!scan) break;
       const int N = h->N[b];
       const ScanGroup* G = nseg[b] > 1 ? &h->grp[scan_group(h->n[b])] : nullptr;
       for (int s2 = 0; s2 < nseg[b]; ++s2) {

@@ -157,6 +157,14 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
   neumann_stats(ps, 0, n, e);
 }
 
+// Makes the lane coordinates opaque at this point of a stage loop, so that
+// the compiler re-derives the lane-dependent addresses after it instead of
+// hoisting all of them out of the loop: hoisted, they stay live across every
+// stage and the large tile classes spill them.
+__device__ __forceinline__ void lane_fence(int& tid, int& lane, int& col, int& grp) {
+  asm volatile("" : "+v"(tid), "+v"(lane), "+v"(col), "+v"(grp));
+}
+
 // DG: per-stage diagonal Delta_i (a.dd); the instantiations without it carry none of its code
 template <typename TG, int TX, int TZ, int NW, bool DG>
 __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
@@ -192,7 +200,8 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   double* mbuf = panel + NZ * 17;
   static_assert((NZ * 17 + 16 * 17) * 8 <= C::BYTES_U, "sweep panel exceeds the work region");
 
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  const int w = tid >> 6;
   int xi[CX], xj[CX], zi[CZ], zj[CZ], ti[CT], tj[CT];
   bool xo[CX], zo[CZ], to[CT];
 #pragma unroll
@@ -312,12 +321,11 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   }
 
   double ab[NAB], H[CZ][4];
-  if (khi > klo) {
-    load_ab(ab, khi - 1);
-    load_h(H, khi - 1);
-  }
+  if (khi > klo) load_ab(ab, khi - 1);
 
   for (int k = khi - 1; k >= klo; --k) {
+    lane_fence(tid, lane, col, grp);
+    load_h(H, k);  // consumed by the Z product, after the state pivot and two products
     // (the previous stage's reads of sdl / idl are behind its barriers)
     if constexpr (DG) {
       put_diag(dpre);
@@ -360,6 +368,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         }
       }
     __syncthreads();
+    lane_fence(tid, lane, col, grp);
     // W = -P X, symmetrized through sD (sD overlaps sP/sX: barrier between)
     double W[CX][4];
 #pragma unroll
@@ -388,6 +397,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     for (int t = 0; t < CX; ++t)
       if (xo[t]) blk_to_lds<TG>(sP, LDX, xi[t], xj[t], W[t], lane);
     __syncthreads();
+    lane_fence(tid, lane, col, grp);
     // T = W [A B]  (NX x NZ)
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
@@ -399,6 +409,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       blk_to_lds<TG>(sX, LDZ, ti[t], tj[t], Tb, lane);
     }
     __syncthreads();
+    lane_fence(tid, lane, col, grp);
     // Z = [A B]^T T + Hessian, symmetrized
     double Z[CZ][4];
 #pragma unroll
@@ -410,7 +421,6 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) Z[t][v] = (double)acc[v] + H[t][v];
     }
-    if (k > klo) load_h(H, k - 1);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < CZ; ++t)
@@ -423,6 +433,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const int r = 16 * zi[t] + trow<TG>(grp, v), c = 16 * zj[t] + col;
         if (zo[t]) Z[t][v] = 0.5 * (Z[t][v] + sD[c * LDZ + r]);
       }
+    lane_fence(tid, lane, col, grp);
     {
       const double sc = wg_max<NW>(diag_max<CZ, TG>(Z, zi, zj, zo, n, n + m, lane), red, w, lane);
       sweep_blk<TG, CZ, TZ>(Z, zi, zj, zo, n, n + m, w, lane, panel, mbuf, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
@@ -530,7 +541,8 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   SegDesc sd{};
   if (SEG) sd = a.segs[blockIdx.x];
   const int b = SEG ? sd.inst : (a.list ? a.list[blockIdx.x] : (int)blockIdx.x);
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  const int w = tid >> 6;
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
@@ -649,6 +661,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       rk = ur ? rb[(int64_t)(hi - 1) * rs + (tid - n)] : 0.0;
     }
     for (int k = hi - 1; k >= lo; --k) {
+      lane_fence(tid, lane, col, grp);
       // PF: the next step's operands are loaded now; otherwise (the 16-wavefront
       // classes, whose register budget the second set would exceed) this step's
       const int k1 = k > lo ? k - 1 : k;
@@ -752,6 +765,7 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
     cn = xr ? cb[(int64_t)(lo + 1) * n + tid] : 0.0;
   }
   for (int k = lo; k < hi; ++k) {
+    lane_fence(tid, lane, col, grp);
     const int k1 = k + 1 < hi ? k + 1 : k;
     double Zk1[CZ][4], Xn1[CX][4], ABt1[CT][4];
     double pk1 = 0.0, kk1 = 0.0, pn1 = 0.0, cn1 = 0.0, dn1 = delta;
