@@ -157,6 +157,11 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
   neumann_stats(ps, 0, n, e);
 }
 
+// One zero in global memory (never written): the padding elements of the
+// branch-free stage loads read it. Not const: a constant-address-space
+// operand would turn the selected pointers into generic ones (flat loads).
+__device__ double kZeroPad[1];
+
 // Makes the lane coordinates opaque at this point of a stage loop, so that
 // the compiler re-derives the lane-dependent addresses after it instead of
 // hoisting all of them out of the loop: hoisted, they stay live across every
@@ -251,18 +256,17 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         for (int v = 0; v < 4; ++v) X[t][v] *= sdl[16 * xi[t] + trow<TG>(grp, v)] * sdl[16 * xj[t] + col];
   };
 
+  // The stage loads below are branch-free: a padding element reads the zero
+  // kZeroPad. Loads issued under divergent branches, or masked right after
+  // they are issued, make the compiler wait for every outstanding load.
   auto load_ab = [&](double (&o)[NAB], int k) {
     const double* A = Ag + (int64_t)k * n * n;
     const double* B = Bg + (int64_t)k * n * m;
 #pragma unroll
     for (int t = 0; t < NAB; ++t) {
       const int e = tid + 64 * NW * t, r = e / NZ, c = e % NZ;
-      double v = 0.0;
-      if (e < NX * NZ && r < n) {
-        if (c < n) v = A[r * n + c];
-        else if (c < n + m) v = B[r * m + (c - n)];
-      }
-      o[t] = v;
+      const bool inA = e < NX * NZ && r < n && c < n, inB = e < NX * NZ && r < n && c >= n && c < n + m;
+      o[t] = *(inA ? A + r * n + c : (inB ? B + r * m + (c - n) : kZeroPad));
     }
   };
   auto load_h = [&](double (&o)[CZ][4], int k) {
@@ -274,17 +278,13 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * zi[t] + trow<TG>(grp, v), c = 16 * zj[t] + col;
-        double x = 0.0;
-        if (zo[t]) {
-          if (r < n) {
-            if (c < n) x = Q[r * n + c];
-            else if (c < n + m) x = M[r * m + (c - n)];
-          } else if (r < n + m) {
-            if (c < n) x = M[c * m + (r - n)];
-            else if (c < n + m) x = R[(r - n) * m + (c - n)];
-          }
-        }
-        o[t][v] = x;
+        const bool rx = zo[t] && r < n, ru = zo[t] && r >= n && r < n + m;
+        const bool cx = c < n, cu = c >= n && c < n + m;
+        const double* src = (rx && cx) ? Q + r * n + c
+                          : (rx && cu) ? M + r * m + (c - n)
+                          : (ru && cx) ? M + c * m + (r - n)
+                          : (ru && cu) ? R + (r - n) * m + (c - n) : kZeroPad;
+        o[t][v] = *src;
       }
   };
   auto store_ab = [&](const double (&o)[NAB]) {
@@ -320,20 +320,32 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     }
   }
 
+  // [A B] of stage k is staged in sAB after the Z product of stage k + 1
+  // (sAB is free once that product has read it), from registers loaded at
+  // the end of stage k + 2: the loads have the state pivot and three
+  // products to arrive, their registers are not live across a control
+  // sweep, and no wait at the top of a stage covers the tile stores of the
+  // stage before it. Stage khi - 1 is staged before the loop.
   double ab[NAB], H[CZ][4];
-  if (khi > klo) load_ab(ab, khi - 1);
+  if (khi > klo) {
+    load_ab(ab, khi - 1);
+    store_ab(ab);
+    if (khi - 2 >= klo) load_ab(ab, khi - 2);
+  }
+  // every load so far has been consumed: say so before the stage loop, or the
+  // compiler's wait analysis, merging the loop entry with its back edge,
+  // waits for all outstanding memory operations inside every stage
+  __builtin_amdgcn_s_waitcnt(0);
 
   for (int k = khi - 1; k >= klo; --k) {
     lane_fence(tid, lane, col, grp);
-    load_h(H, k);  // consumed by the Z product, after the state pivot and two products
     // (the previous stage's reads of sdl / idl are behind its barriers)
     if constexpr (DG) {
       put_diag(dpre);
       dpre = tid < n ? ddg[(int64_t)k * n + tid] : 0.0;
     }
     __syncthreads();
-    store_ab(ab);
-    if (k > klo) load_ab(ab, k - 1);  // the next stage's [A B] (its Hessian after its last use below)
+    load_h(H, k);  // consumed by the Z product, after the state pivot and two products
     // X = I + delta P_{k+1} (per-stage diagonal: I + D P D), swept -> -S_hat^{-1}
     double X[CX][4];
 #pragma unroll
@@ -422,6 +434,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       for (int v = 0; v < 4; ++v) Z[t][v] = (double)acc[v] + H[t][v];
     }
     __syncthreads();
+    if (k > klo) store_ab(ab);  // stage k - 1; every wavefront is past its last read of sAB for stage k
 #pragma unroll
     for (int t = 0; t < CZ; ++t)
       if (zo[t]) blk_to_lds<TG>(sD, LDZ, zi[t], zj[t], Z[t], lane);
@@ -454,6 +467,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
         P[t][v] = (xo[t] && r < n && c < n) ? Z[t < CZ ? t : 0][v] : 0.0;
       }
+    if (k - 2 >= klo) load_ab(ab, k - 2);  // staged after the next stage's Z product
   }
   // S_hat_0
   if (klo == 0) {

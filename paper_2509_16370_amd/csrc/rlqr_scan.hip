@@ -149,7 +149,9 @@ struct ScanLds {
   float P2[C::TILE], A2[C::TILE];               // next (j -> k)
   float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
   float YA[C::TILE], YC[C::TILE];
-  float rowbuf[2 * C::NX], colbuf[2 * C::NX];  // Gauss-Jordan pivot row; pivot column (two slots)
+  int invp[C::NX];  // Gauss-Jordan: right-half row r ends as row invp[r] of X^{-1}
+  int pv[16];       // Gauss-Jordan: pivot rows of the current block of columns
+  float dinv[16 * 17];  // Gauss-Jordan: D^{-1} of the current block (row stride 17)
   float pv1[C::NX], cv1[C::NX], pv2[C::NX], cv2[C::NX], tv[C::NX], tw[C::NX];  // carried p, c
   int piv;
 };
@@ -198,7 +200,10 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
 // pc: also the carried vectors (p1, c1) <- (+) (p2, c2), all in LDS.
 // Returns false if X = I + C1 P2 is singular (no pivot above tol).
 template <int TX, int NW, bool BF>
-__device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid, bool pc) {
+__device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid, bool pc) {
+  // opaque thread index: in the chunk fold's loop the lane-dependent offsets
+  // are re-derived in every combine instead of being hoisted out of the loop
+  asm volatile("" : "+v"(tid));
   using C = ScanCfg<TX, NW>;
   constexpr int NX = C::NX, LDX = C::LDX, LDW = C::LDW, CB = C::CB;
   const int w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
@@ -217,76 +222,163 @@ __device__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n
     }
   }
   __syncthreads();
-  // Gauss-Jordan with partial pivoting on the first n pivots, [X | I] held in
-  // registers: thread tid owns KPT consecutive entries of row r (columns c0
-  // .. c0 + KPT - 1 of the NX x 2NX matrix). Rows are never swapped: pivot j
-  // is the unused row p_j with the largest |column j| entry (lowest row on
-  // ties), the row is scaled and column j eliminated from every other row, and
-  // at the end row p_j of the right half is row j of X^{-1}. Per pivot two
-  // workgroup barriers: one publishes the column (written by its owners at
-  // the end of the previous pivot, two slots), after which every wavefront
-  // finds the same pivot row; one publishes the scaled pivot row. Only the
-  // pivot column and row pass through LDS.
+  // Blocked Gauss-Jordan with partial pivoting on the first n pivots of
+  // M = [X | I] (W; rows are never swapped). Per block of 16 pivot columns C:
+  //  1. wavefront 0 factors the NX x 16 panel M[:, C] in registers (one row
+  //     per lane, unused rows only) with partial pivoting, which picks the
+  //     pivot rows P in order, and inverts D = M[P, C] by an in-wavefront
+  //     Gauss-Jordan elimination (no pivoting: the order of P is a pivoting
+  //     order); P and D^{-1} go to LDS;
+  //  2. every wavefront forms U_J = D^{-1} M[P, J] (MFMA) for its column
+  //     block J; rows outside P take M[i, J] - M[i, C] U_J (MFMA), rows P
+  //     take U_J.
+  // This is the same elimination as 16 single pivot steps, with three
+  // workgroup barriers per block in place of two per pivot; the serial part
+  // runs in one wavefront, which then has its SIMD to itself. At the end row
+  // p_j of the right half is row j of X^{-1}; one permutation pass puts it there.
   {
-    constexpr int KPT = (2 * NX * NX) / (64 * NW);  // entries per thread
-    constexpr int TPR = 2 * NX / KPT;                // threads per row
-    static_assert(KPT * 64 * NW == 2 * NX * NX && TPR * KPT == 2 * NX, "Gauss-Jordan thread map");
-    const int r = tid / TPR, c0 = (tid % TPR) * KPT;
-    float g[KPT];
-#pragma unroll
-    for (int k = 0; k < KPT; ++k) {
-      const int c = c0 + k;
-      g[k] = c < NX ? s.W[r * LDW + c] : (c - NX == r ? 1.0f : 0.0f);
+    constexpr int NJ = 2 * TX;         // column blocks of M
+    constexpr int WJ = NW / NJ;        // wavefronts per column block
+    constexpr int RB = (TX + WJ - 1) / WJ;  // row blocks per wavefront (some may be past TX)
+    static_assert(WJ >= 1 && WJ * NJ == NW, "blocked Gauss-Jordan wavefront map");
+    const int J = w / WJ, i0 = w % WJ, i = lane & 15, kq = lane >> 4;
+    for (int x = tid; x < NX * NX; x += 64 * NW) {
+      const int r = x / NX, c = x % NX;
+      s.W[r * LDW + NX + c] = (r == c) ? 1.0f : 0.0f;
     }
-    if (n > 0 && c0 == 0) s.colbuf[r] = g[0];  // column 0, slot 0
-    unsigned long long used = 0ull;
-    int myq = r;  // row of X^{-1} this thread's right half becomes (rows beyond n: themselves)
+    if (tid < NX) s.invp[tid] = tid;
+    __syncthreads();
+    const unsigned long long rows = NX == 64 ? ~0ull : ((1ull << NX) - 1ull);
+    unsigned long long used = 0ull;  // pivot rows so far (wavefront 0)
     bool sing = false;
-    for (int j = 0; j < n; ++j) {
-      const float* cb = s.colbuf + NX * (j & 1);
-      __syncthreads();  // column j published; the previous pivot row read by all
-      const bool cand = lane < NX && !((used >> lane) & 1ull);
-      const float a = cand ? fabsf(cb[lane]) : -1.0f;
-      // largest |candidate|, lowest row on ties: DPP maxima within 16-lane rows,
-      // the four row maxima by v_readlane, the row by a ballot (the same in
-      // every wavefront); with no match (every candidate NaN) the lowest unused
-      // row is taken and the zero test marks the scan singular
-      const float best = wave_max_f32(a);
-      const unsigned long long bal = __ballot(cand && a == best);
-      const unsigned long long freer = ~used & (NX == 64 ? ~0ull : ((1ull << NX) - 1ull));
-      const int p = bal ? __builtin_ctzll(bal) : __builtin_ctzll(freer);
-      used |= 1ull << p;
-      sing = sing || !(best > 0.0f);
-      const float d = cb[p];
-      const float rd = (best > 0.0f) ? 1.0f / d : 0.0f;
-      const float cr = cb[r];
-      if (r == p) {
+    for (int K = 0; 16 * K < n; ++K) {
+      const int kn = min(16, n - 16 * K);
+      if (w == 0) {
+        // 1. panel factorization; rows >= NX are padding
+        float v[16];
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) s.rowbuf[c0 + k] = g[k] * rd;
-        myq = j;
-      }
-      __syncthreads();  // pivot row published
+        for (int c = 0; c < 16; ++c) v[c] = lane < NX ? s.W[lane * LDW + 16 * K + c] : 0.0f;
+        int pl = 0;  // lanes with (lane & 15) == j hold the pivot row of column 16 K + j
 #pragma unroll
-      for (int k = 0; k < KPT; ++k) {
-        const float rv = s.rowbuf[c0 + k];
-        g[k] = (r == p) ? rv : fmaf(-cr, rv, g[k]);
-      }
-      // the next pivot column, published by its owners into the other slot
-      const int jn = j + 1;
-      if (jn < n && jn >= c0 && jn < c0 + KPT) {
+        for (int jj = 0; jj < 16; ++jj) {
+          if (jj < kn) {
+            // largest |candidate| (lowest row on ties); with no match (every
+            // candidate NaN) the lowest unused row, and the scan is marked singular
+            const bool cand = lane < NX && !((used >> lane) & 1ull);
+            const float a = cand ? fabsf(v[jj]) : -1.0f;
+            const float best = wave_max_f32(a);
+            const unsigned long long bal = __ballot(cand && a == best);
+            const int p = bal ? __builtin_ctzll(bal) : __builtin_ctzll(~used & rows);
+            used |= 1ull << p;
+            sing = sing || !(best > 0.0f);
+            if ((lane & 15) == jj) pl = p;
+            const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[jj]), p));
+            const float mlt = (best > 0.0f && !((used >> lane) & 1ull)) ? v[jj] / d : 0.0f;
 #pragma unroll
-        for (int k = 0; k < KPT; ++k)
-          if (c0 + k == jn) s.colbuf[NX * (jn & 1) + r] = g[k];
+            for (int c = jj + 1; c < 16; ++c)
+              v[c] = fmaf(-mlt, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[c]), p)), v[c]);
+          }
+        }
+        // D = M[P, C] in the accumulator layout (row 4 kq + e, column i),
+        // identity past kn; [D | I] -> [I | D^{-1}]
+        float D[4], Di[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 4 * kq + e, pr = __shfl(pl, r);
+          D[e] = r < kn ? (i < kn ? s.W[pr * LDW + 16 * K + i] : 0.0f) : (r == i ? 1.0f : 0.0f);
+          Di[e] = r == i ? 1.0f : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j < kn) {
+            const int src = 16 * (j >> 2) + i;
+            const float prD = __shfl(D[j & 3], src), prI = __shfl(Di[j & 3], src);  // row j at column i
+            const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prD), j));
+            const float rd = (d != 0.0f) ? 1.0f / d : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float cj = __shfl(D[e], 16 * kq + j);  // D[4 kq + e][j]
+              if (4 * kq + e == j) {
+                D[e] = prD * rd;
+                Di[e] = prI * rd;
+              } else {
+                const float f = cj * rd;
+                D[e] = fmaf(-f, prD, D[e]);
+                Di[e] = fmaf(-f, prI, Di[e]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s.dinv[(4 * kq + e) * 17 + i] = Di[e];
+        if (lane < 16) s.pv[lane] = pl;
+        if (lane < kn) s.invp[pl] = 16 * K + lane;
       }
+      __syncthreads();  // P and D^{-1} published
+      // 2. U_J = D^{-1} M[P, J] (rows past kn zero), the owned blocks M[I, J]
+      // and the A operands M[I, C] (k = 4 kq + kk, the order the B
+      // operand's accumulator rows come in); everything read before the barrier
+      int prow[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) prow[e] = s.pv[4 * kq + e];
+      f4 U = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kk + kq;
+        const float av = k < kn ? s.dinv[i * 17 + k] : 0.0f;
+        const float bv = k < kn ? s.W[s.pv[k] * LDW + 16 * J + i] : 0.0f;
+        U = mfma16(av, bv, U);
+      }
+      float Mo[RB][4], La[RB][4];
+#pragma unroll
+      for (int t = 0; t < RB; ++t) {
+        const int I = i0 + WJ * t;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          Mo[t][e] = I < TX ? s.W[(16 * I + 4 * kq + e) * LDW + 16 * J + i] : 0.0f;
+          La[t][e] = (I < TX && 4 * kq + e < kn) ? s.W[(16 * I + i) * LDW + 16 * K + 4 * kq + e] : 0.0f;
+        }
+      }
+      unsigned long long cur = 0ull;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj)
+        if (jj < kn) cur |= 1ull << s.pv[jj];
+      __syncthreads();  // every read of this block's M is done
+#pragma unroll
+      for (int t = 0; t < RB; ++t) {
+        const int I = i0 + WJ * t;
+        if (I >= TX) break;
+        f4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = mfma16(La[t][kk], U[kk], acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * I + 4 * kq + e;
+          if (!((cur >> r) & 1ull)) s.W[r * LDW + 16 * J + i] = Mo[t][e] - acc[e];
+        }
+      }
+      if (i0 == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * kq + e < kn) s.W[prow[e] * LDW + 16 * J + i] = U[e];
+      }
+      __syncthreads();
     }
     if (tid == 0 && sing) s.piv = -1;
-    __syncthreads();  // every read of W's left half and of the buffers is done
-    // X^{-1}: row p_j of the right half is row j
+    // X^{-1}: right-half row r is row invp[r]
+    constexpr int KP = (NX * NX + 64 * NW - 1) / (64 * NW);
+    float tmp[KP];
+    int dst[KP];
 #pragma unroll
-    for (int k = 0; k < KPT; ++k) {
-      const int c = c0 + k;
-      if (c >= NX) s.W[myq * LDW + c] = g[k];
+    for (int q = 0; q < KP; ++q) {
+      const int x = tid + 64 * NW * q, r = x / NX, c = x % NX;
+      tmp[q] = x < NX * NX ? s.W[r * LDW + NX + c] : 0.0f;
+      dst[q] = x < NX * NX ? s.invp[r] * LDW + NX + c : -1;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KP; ++q)
+      if (dst[q] >= 0) s.W[dst[q]] = tmp[q];
   }
   __syncthreads();
   if (s.piv < 0) ok = false;
