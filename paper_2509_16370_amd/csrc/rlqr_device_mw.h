@@ -103,7 +103,8 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
 // Three workgroup barriers per 16 pivots instead of one per pivot. The A
 // operands are read with their rows permuted so that the float64 MFMA
 // accumulator comes out in the register layout TL of the blocks.
-// panel: 16 TT x 17 doubles, mbuf: 16 x 17 doubles (LDS, free during the call).
+// panel: 16 TT x 17 doubles, mbuf: 2 x 16 x 17 doubles (LDS, free during the call).
+// Only wavefront 0's PivStats receive the pivots.
 template <typename TL>
 __device__ __forceinline__ int blk_row(int i) { return trow<TL>(i & 3, i >> 2); }
 
@@ -125,18 +126,24 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
         for (int v = 0; v < 4; ++v) panel[(16 * bi[t] + trow<TL>(grp, v)) * LP + col] = X[t][v];
       }
     __syncthreads();
-    // the diagonal block, swept by every wavefront
-    double D[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) D[v] = panel[(16 * K + trow<TL>(grp, v)) * LP + col];
-    int lane_s = lane;  // opaque: the per-pivot lane masks stay inside the loop
-    asm volatile("" : "+v"(lane_s));
-    sweep16<TL>(D, s0, s1, lane_s, ps, code, tol, scale);
+    // the diagonal block, swept by wavefront 0 alone: the others wait at the
+    // barrier, so the serial sweep has its SIMD to itself (run by every
+    // wavefront it is issue-bound, several copies per SIMD). mbuf receives
+    // M (zero outside S), dbuf the whole swept block. The pivot counts land
+    // in wavefront 0's PivStats, the ones the kernels report.
+    double* dbuf = mbuf + 16 * LP;
     if (w == 0) {
+      double D[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) D[v] = panel[(16 * K + trow<TL>(grp, v)) * LP + col];
+      int lane_s = lane;  // opaque: the per-pivot lane masks stay inside the loop
+      asm volatile("" : "+v"(lane_s));
+      sweep16<TL>(D, s0, s1, lane_s, ps, code, tol, scale);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = trow<TL>(grp, v);
         mbuf[r * LP + col] = (r >= s0 && r < s1 && col >= s0 && col < s1) ? D[v] : 0.0;
+        dbuf[r * LP + col] = D[v];
       }
     }
     __syncthreads();
@@ -146,7 +153,7 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
       const int I = bi[t], J = bj[t];
       if (I == K && J == K) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) X[t][v] = D[v];
+        for (int v = 0; v < 4; ++v) X[t][v] = dbuf[trow<TL>(grp, v) * LP + col];
         continue;
       }
       // F = M U_J^T (accumulator rows grp + 4v feed the next product as its B operand)

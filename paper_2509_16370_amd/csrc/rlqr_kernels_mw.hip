@@ -55,7 +55,9 @@ struct MwCfg {
   static constexpr int BYTES_P = (int)sizeof(TG) * NX * LDX;
   static constexpr int BYTES_X = (int)sizeof(TG) * NX * LDZ;
   static constexpr int BYTES_D = 8 * NZ * LDZ;
-  static constexpr int BYTES_U0 = BYTES_P + BYTES_X > BYTES_D ? BYTES_P + BYTES_X : BYTES_D;
+  static constexpr int BYTES_SW = 8 * (NZ * 17 + 2 * 16 * 17);  // blocked sweep: panel, M and the swept block
+  static constexpr int BYTES_U1 = BYTES_P + BYTES_X > BYTES_D ? BYTES_P + BYTES_X : BYTES_D;
+  static constexpr int BYTES_U0 = BYTES_U1 > BYTES_SW ? BYTES_U1 : BYTES_SW;
   static constexpr int BYTES_U = (BYTES_U0 + 15) / 16 * 16;
   static constexpr int BYTES_AB = (int)sizeof(TG) * NX * LDZ;
   static constexpr int BLOCKS_PER_STAGE = TZ * TZ + TX * TX;
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   // is free while a sweep runs
   double* panel = reinterpret_cast<double*>(smem);
   double* mbuf = panel + NZ * 17;
-  static_assert((NZ * 17 + 16 * 17) * 8 <= C::BYTES_U, "sweep panel exceeds the work region");
+  static_assert((NZ * 17 + 2 * 16 * 17) * 8 <= C::BYTES_U, "sweep panel exceeds the work region");
 
   int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   const int w = tid >> 6;
