@@ -681,7 +681,10 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
       // PF: the next step's operands are loaded now; otherwise (the 16-wavefront
       // classes, whose register budget the second set would exceed) this step's
       const int k1 = k > lo ? k - 1 : k;
-      double Zk1[CZ][4], Xn1[CX][4], AB1[CT][4];
+      // the tiles of the next step stay in their stored precision until they are
+      // used (a conversion at the load would wait for it)
+      TG Zk1[CZ][4], Xn1[CX][4];
+      double AB1[CT][4];
       double ck1 = 0.0, qk1 = 0.0, rk1 = 0.0, dk1 = 0.0;
       if constexpr (PF) {
         load_tile(Zk1, ztile(k1), zo, CZ);
@@ -783,7 +786,8 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   for (int k = lo; k < hi; ++k) {
     lane_fence(tid, lane, col, grp);
     const int k1 = k + 1 < hi ? k + 1 : k;
-    double Zk1[CZ][4], Xn1[CX][4], ABt1[CT][4];
+    TG Zk1[CZ][4], Xn1[CX][4];  // stored precision until used
+    double ABt1[CT][4];
     double pk1 = 0.0, kk1 = 0.0, pn1 = 0.0, cn1 = 0.0, dn1 = delta;
     if constexpr (PF) {
       if constexpr (DG) dn1 = xr ? ddg[(int64_t)(k1 + 1) * n + tid] : 0.0;

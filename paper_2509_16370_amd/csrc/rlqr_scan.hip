@@ -563,7 +563,7 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
   __shared__ float sRi[NM * LDM];     // -R^{-1}
   __shared__ float sS[NM * LDS2];     // S = [M^T | B^T], columns x at 0.., z at NX..
   __shared__ float sY[NM * LDS2];     // Y = -R^{-1} S
-  __shared__ double colbuf[2 * NM];
+  __shared__ double swbuf[NM * 17 + 2 * 16 * 17];  // blocked sweep: panel, M, swept block
   __shared__ double red[NW];
   // S, zero-padded
   for (int x = tid; x < NM * 2 * NX; x += 64 * NW) {
@@ -595,7 +595,8 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
   ps.init();
   {
     const double sc = wg_max<NW>(diag_max<CR, float>(X, ri, rj, ro, 0, m, lane), red, w, lane);
-    sweep_mw<float, CR, TM>(X, ri, rj, ro, 0, m, lane, colbuf, ps, 0, 1.0e3 * m * 2.220446049250313e-16 * sc, sc);
+    sweep_blk<float, CR, TM>(X, ri, rj, ro, 0, m, w, lane, swbuf, swbuf + NM * 17, ps, 0,
+                             1.0e3 * m * 2.220446049250313e-16 * sc, sc);
   }
   if (ps.nzero && tid == 0) a.bad[b] = 1;
 #pragma unroll
@@ -817,8 +818,8 @@ hipError_t launch_scan_elements(const ScanArgs& a, int ninst, int tx, int tm, hi
     if (tm <= 2) return launch_scan_init_t<2, 2, 8>(a, ninst, st);
     if (tm <= 5) return launch_scan_init_t<2, 5, 8>(a, ninst, st);
   } else if (tx == 4) {
-    if (tm <= 1) return launch_scan_init_t<4, 1, 16>(a, ninst, st);
-    if (tm <= 2) return launch_scan_init_t<4, 2, 16>(a, ninst, st);
+    if (tm <= 1) return launch_scan_init_t<4, 1, 8>(a, ninst, st);
+    if (tm <= 2) return launch_scan_init_t<4, 2, 8>(a, ninst, st);
     if (tm <= 4) return launch_scan_init_t<4, 4, 16>(a, ninst, st);
   }
   return hipErrorInvalidValue;
