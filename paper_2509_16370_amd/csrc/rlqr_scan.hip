@@ -196,6 +196,34 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
   }
 }
 
+// Pivot J of an in-wavefront Gauss-Jordan elimination [D | Di] over a 16 x 16
+// tile in the float32 accumulator layout (lane holds rows 4 kq + e of column
+// i): row J is scaled by 1 / D[J][J], column J eliminated from the others.
+// No pivoting (the caller's row order is a pivoting order). The pivot row
+// crosses 16-lane rows by ds_bpermute; column J stays within each 16-lane row
+// (DPP row broadcast of lane J).
+template <int J>
+__device__ __forceinline__ void gj_pivot(float (&D)[4], float (&Di)[4], int i, int kq) {
+  const int src = 16 * (J >> 2) + i;
+  const float prD = __shfl(D[J & 3], src), prI = __shfl(Di[J & 3], src);  // row J at column i
+  const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prD), J));
+  // 1 / d: hardware estimate and one Newton step, r + r (1 - d r)
+  const float r0 = __builtin_amdgcn_rcpf(d);
+  const float rd = (d != 0.0f) ? fmaf(r0, fmaf(-d, r0, 1.0f), r0) : 0.0f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float cj = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(D[e]), 0x150 + J, 0xf, 0xf, false));
+    if (4 * kq + e == J) {
+      D[e] = prD * rd;
+      Di[e] = prI * rd;
+    } else {
+      const float f = cj * rd;
+      D[e] = fmaf(-f, prD, D[e]);
+      Di[e] = fmaf(-f, prI, Di[e]);
+    }
+  }
+}
+
 // acc (P1, A1, C1 in LDS) <- acc (+) next (P2, A2 in LDS, C2 in global).
 // pc: also the carried vectors (p1, c1) <- (+) (p2, c2), all in LDS.
 // Returns false if X = I + C1 P2 is singular (no pivot above tol).
@@ -248,7 +276,7 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
     }
     if (tid < NX) s.invp[tid] = tid;
     __syncthreads();
-    const unsigned long long rows = NX == 64 ? ~0ull : ((1ull << NX) - 1ull);
+    const unsigned long long rows = NX >= 64 ? ~0ull : ((1ull << (NX & 63)) - 1ull);
     unsigned long long used = 0ull;  // pivot rows so far (wavefront 0)
     bool sing = false;
     for (int K = 0; 16 * K < n; ++K) {
@@ -272,8 +300,9 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
             used |= 1ull << p;
             sing = sing || !(best > 0.0f);
             if ((lane & 15) == jj) pl = p;
+            // the factorization only picks the rows: the hardware reciprocal will do
             const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[jj]), p));
-            const float mlt = (best > 0.0f && !((used >> lane) & 1ull)) ? v[jj] / d : 0.0f;
+            const float mlt = (best > 0.0f && !((used >> lane) & 1ull)) ? v[jj] * __builtin_amdgcn_rcpf(d) : 0.0f;
 #pragma unroll
             for (int c = jj + 1; c < 16; ++c)
               v[c] = fmaf(-mlt, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[c]), p)), v[c]);
@@ -288,27 +317,12 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
           D[e] = r < kn ? (i < kn ? s.W[pr * LDW + 16 * K + i] : 0.0f) : (r == i ? 1.0f : 0.0f);
           Di[e] = r == i ? 1.0f : 0.0f;
         }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (j < kn) {
-            const int src = 16 * (j >> 2) + i;
-            const float prD = __shfl(D[j & 3], src), prI = __shfl(Di[j & 3], src);  // row j at column i
-            const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prD), j));
-            const float rd = (d != 0.0f) ? 1.0f / d : 0.0f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const float cj = __shfl(D[e], 16 * kq + j);  // D[4 kq + e][j]
-              if (4 * kq + e == j) {
-                D[e] = prD * rd;
-                Di[e] = prI * rd;
-              } else {
-                const float f = cj * rd;
-                D[e] = fmaf(-f, prD, D[e]);
-                Di[e] = fmaf(-f, prI, Di[e]);
-              }
-            }
-          }
-        }
+#define RLQR_GJ_PIVOT(J) \
+        if (J < kn) gj_pivot<J>(D, Di, i, kq);
+        RLQR_GJ_PIVOT(0) RLQR_GJ_PIVOT(1) RLQR_GJ_PIVOT(2) RLQR_GJ_PIVOT(3) RLQR_GJ_PIVOT(4) RLQR_GJ_PIVOT(5)
+        RLQR_GJ_PIVOT(6) RLQR_GJ_PIVOT(7) RLQR_GJ_PIVOT(8) RLQR_GJ_PIVOT(9) RLQR_GJ_PIVOT(10) RLQR_GJ_PIVOT(11)
+        RLQR_GJ_PIVOT(12) RLQR_GJ_PIVOT(13) RLQR_GJ_PIVOT(14) RLQR_GJ_PIVOT(15)
+#undef RLQR_GJ_PIVOT
 #pragma unroll
         for (int e = 0; e < 4; ++e) s.dinv[(4 * kq + e) * 17 + i] = Di[e];
         if (lane < 16) s.pv[lane] = pl;
