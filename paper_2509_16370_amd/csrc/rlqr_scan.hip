@@ -54,32 +54,39 @@ __device__ __forceinline__ f4 sgemm_blk_bt(const float* sa, int lda, const float
 }
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
-// float32 -> bfloat16 bits, round to nearest even (a NaN stays a quiet NaN)
-__device__ __forceinline__ short bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (short)((u >> 16) | 0x0040u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
-
-// The same block products with bfloat16 operands and float32 accumulation:
-// one 16x16x16 MFMA per 16-block of the inner dimension, lane l holding
-// op(A)[i][4 kq .. 4 kq + 3] and B[4 kq .. 4 kq + 3][j] (i, j = l & 15, kq = l >> 4).
+// The same block products with bfloat16 operands (float32 -> bfloat16 by the
+// hardware conversion, round to nearest even) and float32 accumulation, on
+// gfx950's 16x16x32 MFMA: lane l supplies op(A)[i][32 kb + 8 kq + j] and
+// B[32 kb + 8 kq + j][i] (i = l & 15, kq = l >> 4, j = 0..7), the accumulator
+// layout being that of the float32 instruction. An odd last 16-block of the
+// inner dimension takes the 16x16x16 instruction (4 per lane).
 template <bool TRANS_A, int KB>
 __device__ __forceinline__ f4 bgemm_blk(const float* sa, int lda, const float* sb, int ldb, int I, int J, int lane) {
   f4 acc = {0, 0, 0, 0};
   const int i = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    s4 av, bv;
+  for (int kb = 0; kb + 1 < KB; kb += 2) {
+    bf8 av, bv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 16 * kb + 8 * kq + j;
+      av[j] = (__bf16)(TRANS_A ? sa[k * lda + 16 * I + i] : sa[(16 * I + i) * lda + k]);
+      bv[j] = (__bf16)sb[k * ldb + 16 * J + i];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+  if constexpr (KB % 2) {
+    bf4 av, bv;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = 16 * kb + 4 * kq + j;
-      av[j] = bf16_bits(TRANS_A ? sa[k * lda + 16 * I + i] : sa[(16 * I + i) * lda + k]);
-      bv[j] = bf16_bits(sb[k * ldb + 16 * J + i]);
+      const int k = 16 * (KB - 1) + 4 * kq + j;
+      av[j] = (__bf16)(TRANS_A ? sa[k * lda + 16 * I + i] : sa[(16 * I + i) * lda + k]);
+      bv[j] = (__bf16)sb[k * ldb + 16 * J + i];
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, av), __builtin_bit_cast(s4, bv), acc, 0, 0, 0);
   }
   return acc;
 }
@@ -88,15 +95,25 @@ __device__ __forceinline__ f4 bgemm_blk_bt(const float* sa, int lda, const float
   f4 acc = {0, 0, 0, 0};
   const int i = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    s4 av, bv;
+  for (int kb = 0; kb + 1 < KB; kb += 2) {
+    bf8 av, bv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 16 * kb + 8 * kq + j;
+      av[j] = (__bf16)sa[(16 * I + i) * lda + k];
+      bv[j] = (__bf16)sb[(16 * J + i) * ldb + k];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+  if constexpr (KB % 2) {
+    bf4 av, bv;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = 16 * kb + 4 * kq + j;
-      av[j] = bf16_bits(sa[(16 * I + i) * lda + k]);
-      bv[j] = bf16_bits(sb[(16 * J + i) * ldb + k]);
+      const int k = 16 * (KB - 1) + 4 * kq + j;
+      av[j] = (__bf16)sa[(16 * I + i) * lda + k];
+      bv[j] = (__bf16)sb[(16 * J + i) * ldb + k];
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, av), __builtin_bit_cast(s4, bv), acc, 0, 0, 0);
   }
   return acc;
 }

@@ -2,11 +2,12 @@
 //
 // GEMM: one 256-thread workgroup per 64 x 64 tile of C, four wavefronts of
 // 32 x 32 (2 x 2 blocks of 16 x 16). op(A) and op(B) tiles of depth 16 are
-// staged in LDS in the operand type (zero-filled outside the matrices). The
-// products use v_mfma_f32_16x16x16_bf16 for bfloat16 operands (lane l holds
-// A[l & 15][4 (l >> 4) .. +3] and B[4 (l >> 4) .. +3][l & 15]) and
-// v_mfma_f32_16x16x4_f32 for float32 operands; both accumulate in float32
-// with the result of lane l in rows 4 (l >> 4) + v, column l & 15.
+// staged in LDS in the operand type (zero-filled outside the matrices), 32
+// deep. The products use gfx950's v_mfma_f32_16x16x32_bf16 for bfloat16
+// operands (lane l holds A[l & 15][8 (l >> 4) .. +7] and
+// B[8 (l >> 4) .. +7][l & 15]) and v_mfma_f32_16x16x4_f32 for float32
+// operands; both accumulate in float32 with the result of lane l in rows
+// 4 (l >> 4) + v, column l & 15.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,7 +15,8 @@
 
 namespace {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // float32 -> bfloat16 bits, round to nearest even (NaN kept quiet)
@@ -40,7 +42,7 @@ template <> struct Op<uint16_t> {
   }
 };
 
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64, TK = 32;
 
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* __restrict__ A, int lda,
@@ -58,9 +60,9 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f4{0, 0, 0, 0};
   for (int k0 = 0; k0 < K; k0 += TK) {
-    // stage op(A) (TM x TK) and op(B) (TK x TN), 4 elements per thread each
+    // stage op(A) (TM x TK) and op(B) (TK x TN), 8 elements per thread each
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < 8; ++e) {
       const int idx = tid + 256 * e;
       const int ai = idx / TK, ak = idx % TK;
       const int gi = row0 + ai, gk = k0 + ak;
@@ -80,16 +82,17 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
       for (int bj = 0; bj < 2; ++bj) {
         const int r = wr + 16 * bi + (lane & 15), c = wc + 16 * bj + (lane & 15), kq = lane >> 4;
         if constexpr (sizeof(T) == 2) {
-          s4 a, b;
+          s8 a, b;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            a[j] = (short)As[r][4 * kq + j];
-            b[j] = (short)Bs[4 * kq + j][c];
+          for (int j = 0; j < 8; ++j) {
+            a[j] = (short)As[r][8 * kq + j];
+            b[j] = (short)Bs[8 * kq + j][c];
           }
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b),
+                                                                 acc[bi][bj], 0, 0, 0);
         } else {
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk)
+          for (int kk = 0; kk < 8; ++kk)
             acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)As[r][4 * kk + kq], (float)Bs[4 * kk + kq][c],
                                                                 acc[bi][bj], 0, 0, 0);
         }
