@@ -1154,28 +1154,38 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
     const double* B = a.B + mt.oB + (int64_t)i * nm;
     const double* xi = x + (int64_t)i * n; const double* ui = u + (int64_t)i * m;
     const double* yn = y + (int64_t)(i + 1) * n;
+    // the inner products are unrolled by 8: eight loads in flight per lane
+    // instead of one memory round trip per term
     for (int row = lane; row < 2 * n + m; row += 64) {
       double s = 0.0, bv;
       int64_t out;
       if (row < n) {
         const int a0 = row;
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(Q[j * n + a0], xi[j], s);  // Q symmetric: lanes read a row
+#pragma unroll 8
         for (int j = 0; j < m; ++j) s = fma(M[a0 * m + j], ui[j], s);
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(A[j * n + a0], yn[j], s);
         bv = q[(int64_t)i * n + a0];
         s += bv - y[(int64_t)i * n + a0];
         out = (int64_t)i * (n + m) + a0;
       } else if (row < n + m) {
         const int a0 = row - n;
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(M[j * m + a0], xi[j], s);
+#pragma unroll 8
         for (int j = 0; j < m; ++j) s = fma(R[j * m + a0], ui[j], s);  // R symmetric
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(B[j * m + a0], yn[j], s);
         bv = r[(int64_t)i * m + a0];
         s += bv;
         out = (int64_t)i * (n + m) + n + a0;
       } else {
         const int a0 = row - n - m;
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(A[a0 * n + j], xi[j], s);
+#pragma unroll 8
         for (int j = 0; j < m; ++j) s = fma(B[a0 * m + j], ui[j], s);
         bv = c[(int64_t)(i + 1) * n + a0];
         s += bv - (dd ? dd[(int64_t)(i + 1) * n + a0] : delta) * yn[a0] - x[(int64_t)(i + 1) * n + a0];
@@ -1192,6 +1202,7 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
       double s = 0.0, bv;
       int64_t out;
       if (row < n) {
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(QN[j * n + row], xN[j], s);
         bv = q[(int64_t)N * n + row];
         s += bv - y[(int64_t)N * n + row];
@@ -1211,7 +1222,10 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
 
 // SN, SM > 0: every instance of the batch has n = SN, m = SM (n + m <= 16).
 // DG: per-stage diagonal Delta_i (a.dd) in the dual rows.
-template <int SN, int SM, bool DG>
+// PART 1: only the chunks of stages with n + m <= 16, PART 2: only the
+// others (the general launch runs both: the large-stage path's unrolled
+// products need registers the small-stage path would pay for in occupancy).
+template <int SN, int SM, bool DG, int PART>
 __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
   const double* dd = DG ? a.dd : nullptr;
   __shared__ double sv[32];
@@ -1228,9 +1242,10 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
     if (a.info && a.info[b].singular) continue;
     const InstMeta mt = a.meta[b];
     const int n = SN > 0 ? SN : mt.n, m = SN > 0 ? SM : mt.m;
+    if ((PART == 1 && n + m > 16) || (PART == 2 && n + m <= 16)) continue;
     const double delta = DG ? 0.0 : a.delta[b];
     double rmax = 0.0, bmax = 0.0;
-    if (n + m <= 16) {
+    if (PART != 2 && n + m <= 16) {
       int iH[4], iAB[4], iABT[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1272,7 +1287,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
         __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of stgB returned before it is refilled
       }
       if (ch.i1 > mt.N) res_terminal(a, mt, n, m, delta, dd, sv, rmax, bmax, lane);
-    } else {
+    } else if (PART != 1) {
       for (int i = ch.i0; i < ch.i1; ++i) residual_slot_rows(a, mt, b, i, dd, rmax, bmax, lane);
     }
     rmax = wave_max(rmax);
@@ -1484,14 +1499,18 @@ hipError_t launch_residual(const ResidualArgs& a, int shape, hipStream_t st) {
   if (a.nchunks <= 0) return hipSuccess;
   const dim3 grid((unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20)));
   if (a.dd) {
-    hipLaunchKernelGGL((k_residual<0, 0, true>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_residual<0, 0, true, 1>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_residual<0, 0, true, 2>), grid, dim3(64), 0, st, a);
     return hipGetLastError();
   }
   switch (shape) {
-    case SHAPE_4_1: hipLaunchKernelGGL((k_residual<4, 1, false>), grid, dim3(64), 0, st, a); break;
-    case SHAPE_8_2: hipLaunchKernelGGL((k_residual<8, 2, false>), grid, dim3(64), 0, st, a); break;
-    case SHAPE_12_4: hipLaunchKernelGGL((k_residual<12, 4, false>), grid, dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_residual<0, 0, false>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_4_1: hipLaunchKernelGGL((k_residual<4, 1, false, 1>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_8_2: hipLaunchKernelGGL((k_residual<8, 2, false, 1>), grid, dim3(64), 0, st, a); break;
+    case SHAPE_12_4: hipLaunchKernelGGL((k_residual<12, 4, false, 1>), grid, dim3(64), 0, st, a); break;
+    default:
+      hipLaunchKernelGGL((k_residual<0, 0, false, 1>), grid, dim3(64), 0, st, a);
+      hipLaunchKernelGGL((k_residual<0, 0, false, 2>), grid, dim3(64), 0, st, a);
+      break;
   }
   return hipGetLastError();
 }
