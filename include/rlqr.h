@@ -178,10 +178,12 @@ typedef struct {
                                   sequential modes and by rlqr_factor. */
   int32_t mw_waves;            /* wavefronts per instance (one workgroup) in the kernels
                                   of instances with 16 < n + m <= 48 and n <= 32: 0 or 4
-                                  (default) or 8. More wavefronts shorten each stage's
-                                  dependent chain of block products at the price of
-                                  more workgroup slots; results are identical. Larger
-                                  stages keep their fixed counts. */
+                                  (default), 1, 2 or 8 (instances with n > 16 take at
+                                  least 2). More wavefronts shorten each stage's
+                                  dependent chain of block products; fewer make its
+                                  workgroup barriers cheaper. Certificates are identical
+                                  and solutions agree to rounding. Larger stages keep
+                                  their fixed counts. Other values: RLQR_E_INVALID. */
 } rlqr_tuning;
 
 /*

@@ -133,7 +133,7 @@ struct rlqr_handle {
   // left-hand side; its vectors sit at j times the batch lengths. A call
   // with r right-hand sides uses the first r*B virtual instances.
   int max_rhs = 1;
-  int mw_waves = 4;  // wavefronts per workgroup of the multi-wavefront classes up to 32 x 48 (4 or 8)
+  int mw_waves = 4;  // wavefronts per workgroup of the multi-wavefront classes up to 32 x 48 (1, 2, 4 or 8)
   rlqr_handle* mv = nullptr;
   int Bbase = 0;                                   // (mv) instances per right-hand side
   int base_count[TILE_CLASSES] = {};               // (mv) per right-hand side
@@ -368,7 +368,9 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   if (mode != RLQR_SEQ_FP64 && mode != RLQR_SEQ_MIXED && mode != RLQR_SCAN_FP32 && mode != RLQR_SCAN_BF16)
     return RLQR_E_INVALID;
   if (tune && (tune->scan_chunk < 0 || tune->max_rhs < 0)) return RLQR_E_INVALID;
-  if (tune && tune->mw_waves != 0 && tune->mw_waves != 4 && tune->mw_waves != 8) return RLQR_E_INVALID;
+  if (tune && tune->mw_waves != 0 && tune->mw_waves != 1 && tune->mw_waves != 2 && tune->mw_waves != 4 &&
+      tune->mw_waves != 8)
+    return RLQR_E_INVALID;
   const int B = s->batch;
   if (B > 0 && (!s->N || !s->nx || !s->nu)) return RLQR_E_INVALID;
   for (int b = 0; b < B; ++b) {
@@ -385,7 +387,7 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   h->m.assign(s->nu, s->nu + B);
   const bool scan = is_scan(mode);
   h->carry_pc = scan && tune && tune->scan_carry_pc != 0;
-  h->mw_waves = (tune && tune->mw_waves == 8) ? 8 : 4;
+  h->mw_waves = (tune && tune->mw_waves != 0) ? tune->mw_waves : 4;
 
   // segment length: about one segment per compute unit (256) over the whole
   // batch, so the chunk folds and the segment recursions run in one round and

@@ -222,8 +222,9 @@ inline int fixed_shape(int n, int m) {
 }
 hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, int shape, hipStream_t st);
 // waves: wavefronts per workgroup of the multi-wavefront kernels for the tile
-// classes up to 32 x 48 (TILE_X1_Z2, TILE_X2_Z2, TILE_X2_Z3): 4 or 8; the
-// larger classes have their own fixed counts (9, 16)
+// classes up to 32 x 48 (TILE_X1_Z2, TILE_X2_Z2, TILE_X2_Z3): 1, 2, 4 or 8
+// (the 32-wide classes take at least 2); the larger classes have their own
+// fixed counts (9, 16)
 hipError_t launch_factor_mw(int cls, const FactorArgs& a, int nblocks, bool fp32, hipStream_t st, int waves = 4);
 hipError_t launch_solve_mw(int cls, const SolveArgs& a, int nblocks, bool fp32, hipStream_t st, int waves = 4);
 hipError_t launch_solve(const SolveArgs& a, int nblocks, bool fp32_tiles, int shape, hipStream_t st);

@@ -889,16 +889,32 @@ static hipError_t launch_mw_pair(bool factor, const void* args, int nblocks, hip
   return hipGetLastError();
 }
 
+// waves: wavefronts per instance of the classes up to 32 x 48 (1, 2, 4 or 8;
+// the 32-wide classes take at least 2). With fewer wavefronts each owns more
+// blocks and the stage's workgroup barriers get cheaper (one wavefront:
+// none to wait for).
 template <typename TG>
 static hipError_t launch_mw_t(int cls, bool factor, const void* args, int nblocks, hipStream_t st, int waves) {
-  const bool w8 = waves == 8;
   switch (cls) {
-    case TILE_X1_Z2: return w8 ? launch_mw_pair<TG, 1, 2, 8>(factor, args, nblocks, st)
-                               : launch_mw_pair<TG, 1, 2, 4>(factor, args, nblocks, st);
-    case TILE_X2_Z2: return w8 ? launch_mw_pair<TG, 2, 2, 8>(factor, args, nblocks, st)
-                               : launch_mw_pair<TG, 2, 2, 4>(factor, args, nblocks, st);
-    case TILE_X2_Z3: return w8 ? launch_mw_pair<TG, 2, 3, 8>(factor, args, nblocks, st)
-                               : launch_mw_pair<TG, 2, 3, 4>(factor, args, nblocks, st);
+    case TILE_X1_Z2:
+      switch (waves) {
+        case 1: return launch_mw_pair<TG, 1, 2, 1>(factor, args, nblocks, st);
+        case 2: return launch_mw_pair<TG, 1, 2, 2>(factor, args, nblocks, st);
+        case 8: return launch_mw_pair<TG, 1, 2, 8>(factor, args, nblocks, st);
+        default: return launch_mw_pair<TG, 1, 2, 4>(factor, args, nblocks, st);
+      }
+    case TILE_X2_Z2:
+      switch (waves) {
+        case 1: case 2: return launch_mw_pair<TG, 2, 2, 2>(factor, args, nblocks, st);
+        case 8: return launch_mw_pair<TG, 2, 2, 8>(factor, args, nblocks, st);
+        default: return launch_mw_pair<TG, 2, 2, 4>(factor, args, nblocks, st);
+      }
+    case TILE_X2_Z3:
+      switch (waves) {
+        case 1: case 2: return launch_mw_pair<TG, 2, 3, 2>(factor, args, nblocks, st);
+        case 8: return launch_mw_pair<TG, 2, 3, 8>(factor, args, nblocks, st);
+        default: return launch_mw_pair<TG, 2, 3, 4>(factor, args, nblocks, st);
+      }
     case TILE_X3_Z3: return launch_mw_pair<TG, 3, 3, 9>(factor, args, nblocks, st);
     case TILE_X4_Z4: return launch_mw_pair<TG, 4, 4, 16>(factor, args, nblocks, st);
     case TILE_X4_Z6: return launch_mw_pair<TG, 4, 6, 16>(factor, args, nblocks, st);

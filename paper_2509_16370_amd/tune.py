@@ -182,14 +182,16 @@ def tune_batch(packed: wl.Packed, lhs, rhs, rel_tol: float = 1e-8, max_refine: i
                 if t < 0.98 * best:
                     best, plan = t, trial
                     plan[bk].ms = t
-    # schedule: eight wavefronts per instance for the stages with 16 < n + m <= 48
+    # schedule: wavefronts per instance for the stages with 16 < n + m <= 48
+    # (one for the 16-wide states, two for the 32-wide ones; or eight)
     if any(16 < n + m <= 48 and n <= 32 for n, m in bks):
-        trial = Plan(plan, mw_waves=8)
-        t = time_plan(packed, trial, lhs, rhs, rel_tol, max_refine, reps, device)
-        if log:
-            log(f"[tune] eight wavefronts per instance: {t:.3f} ms (best {best:.3f})")
-        if t < 0.98 * best:
-            best, plan = t, trial
+        for w in (1, 8):
+            trial = Plan(plan, mw_waves=w)
+            t = time_plan(packed, trial, lhs, rhs, rel_tol, max_refine, reps, device)
+            if log:
+                log(f"[tune] {w} wavefront(s) per instance: {t:.3f} ms (best {best:.3f})")
+            if t < 0.98 * best:
+                best, plan = t, trial
     return plan
 
 
