@@ -56,8 +56,15 @@ struct MwCfg {
   static constexpr int BYTES_X = (int)sizeof(TG) * NX * LDZ;
   static constexpr int BYTES_D = 8 * NZ * LDZ;
   static constexpr int BYTES_SW = 8 * (NZ * 17 + 2 * 16 * 17);  // blocked sweep: panel, M and the swept block
+  static constexpr int BYTES_Q = 4 * (int)sizeof(TG) * NX * LDX;  // Neumann by squaring: four state tiles
   static constexpr int BYTES_U1 = BYTES_P + BYTES_X > BYTES_D ? BYTES_P + BYTES_X : BYTES_D;
-  static constexpr int BYTES_U0 = BYTES_U1 > BYTES_SW ? BYTES_U1 : BYTES_SW;
+  static constexpr int BYTES_U2 = BYTES_U1 > BYTES_SW ? BYTES_U1 : BYTES_SW;
+  // the squaring form of the Neumann series needs four state tiles; it is
+  // built for states up to 32 wide (where many terms occur and the registers
+  // are there) if the tiles fit in 160 KB of LDS with [A B] beside them
+  static constexpr bool SQ =
+      TX <= 2 && (BYTES_Q > BYTES_U2 ? BYTES_Q : BYTES_U2) + (int)sizeof(TG) * NX * LDZ <= 160 * 1024;
+  static constexpr int BYTES_U0 = SQ && BYTES_Q > BYTES_U2 ? BYTES_Q : BYTES_U2;
   static constexpr int BYTES_U = (BYTES_U0 + 15) / 16 * 16;
   static constexpr int BYTES_AB = (int)sizeof(TG) * NX * LDZ;
   static constexpr int BLOCKS_PER_STAGE = TZ * TZ + TX * TX;
@@ -70,8 +77,10 @@ struct MwCfg {
 // product and two workgroup barriers per further term, E and Y through the
 // LDS tiles sE and sY, stride LDX) replaces the pivot sweep and the norm bound
 // certifies every pivot positive; the result is symmetrized through sD (a
-// float64 tile that may overlay sE and sY). Otherwise the blocked sweep runs.
-template <typename TG, int TX, int CX, int NW>
+// float64 tile that may overlay sE and sY). With SQ (four state tiles from sE
+// on) four or more terms are summed by squaring instead. Otherwise the
+// blocked sweep runs.
+template <typename TG, int TX, int CX, int NW, bool SQ>
 __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&xi)[CX], const int (&xj)[CX],
                                                 const bool (&xo)[CX], int n, int w, int lane, double* red,
                                                 double* panel, double* mbuf, PivStats& ps, int code, TG* sE,
@@ -121,7 +130,76 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
       const double id = (16 * xi[t] + trow<TG>(grp, v) == 16 * xj[t] + col) ? 1.0 : 0.0;
       X[t][v] = xo[t] ? id - (X[t][v] - id) : 0.0;
     }
-  if (terms > 1) {
+  if (SQ && terms >= 4) {
+    // the same series by squaring: with F = -E, (I + F)(I + F^2)(I + F^4)...
+    // over L factors sums F^0 .. F^(2^L - 1), 2^L - 1 >= terms; products
+    // that do not depend on each other share a phase (two barriers), so
+    // terms <= 7 take 3 phases and terms <= 15 take 4 (Horner: terms - 1).
+    // Tiles (stride LDX): 0 = E, then E^8; 1 = E^2; 2 = E^4; 3 = partial sum S.
+    constexpr int NXX = 16 * TX * (16 * TX + 1);
+    TG* t0 = sE;
+    TG* t1 = sE + NXX;
+    TG* t2 = sE + 2 * NXX;
+    TG* t3 = sE + 3 * NXX;
+    __syncthreads();  // E in t0
+    double E2[CX][4];
+#pragma unroll
+    for (int t = 0; t < CX; ++t) {
+      if (!xo[t]) continue;
+      auto acc = gemm_blk<TG, false, TX>(t0, LDX, t0, LDX, xi[t], xj[t], lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) E2[t][v] = (double)acc[v];
+      blk_to_lds<TG>(t1, LDX, xi[t], xj[t], E2[t], lane);
+    }
+    __syncthreads();  // E^2 in t1
+    // S = I - E + E^2 - E^3 (X holds I - E), E^4 = E^2 E^2
+#pragma unroll
+    for (int t = 0; t < CX; ++t) {
+      if (!xo[t]) continue;
+      auto e3 = gemm_blk<TG, false, TX>(t0, LDX, t1, LDX, xi[t], xj[t], lane);
+      auto e4 = gemm_blk<TG, false, TX>(t1, LDX, t1, LDX, xi[t], xj[t], lane);
+      double E4[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        X[t][v] = X[t][v] + E2[t][v] - (double)e3[v];
+        E4[v] = (double)e4[v];
+      }
+      blk_to_lds<TG>(t2, LDX, xi[t], xj[t], E4, lane);
+      blk_to_lds<TG>(t3, LDX, xi[t], xj[t], X[t], lane);
+    }
+    __syncthreads();  // E^4 in t2, S in t3
+    // S <- S + S E^4 (8 terms); with more terms also E^8 = E^4 E^4 into t0
+#pragma unroll
+    for (int t = 0; t < CX; ++t) {
+      if (!xo[t]) continue;
+      auto se = gemm_blk<TG, false, TX>(t3, LDX, t2, LDX, xi[t], xj[t], lane);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[t][v] += (double)se[v];
+      if (terms > 7) {
+        auto e8 = gemm_blk<TG, false, TX>(t2, LDX, t2, LDX, xi[t], xj[t], lane);
+        double E8[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) E8[v] = (double)e8[v];
+        blk_to_lds<TG>(t0, LDX, xi[t], xj[t], E8, lane);
+      }
+    }
+    __syncthreads();  // every read of t3 done (and E^8 in t0)
+    if (terms > 7) {
+      // S <- S + S E^8 (16 terms)
+#pragma unroll
+      for (int t = 0; t < CX; ++t)
+        if (xo[t]) blk_to_lds<TG>(t3, LDX, xi[t], xj[t], X[t], lane);
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < CX; ++t) {
+        if (!xo[t]) continue;
+        auto se = gemm_blk<TG, false, TX>(t3, LDX, t0, LDX, xi[t], xj[t], lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[t][v] += (double)se[v];
+      }
+      __syncthreads();
+    }
+  } else if (terms > 1) {
     for (int j = 2; j <= terms; ++j) {
 #pragma unroll
       for (int t = 0; t < CX; ++t)
@@ -137,6 +215,8 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
       }
       __syncthreads();
     }
+  }
+  if (terms > 1) {
     // E Y is symmetric only up to rounding: Y <- (Y + Y^T) / 2
 #pragma unroll
     for (int t = 0; t < CX; ++t)
@@ -358,7 +438,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
-    shat_inverse_mw<TG, TX, CX, NW>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 2 * (k + 1), sP, sX, sD);
+    shat_inverse_mw<TG, TX, CX, NW, C::SQ>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 2 * (k + 1), sP, sX, sD);
     if constexpr (DG) scale_x(X);  // X~ = D X D
     {
       TG* xt = xtile(k + 1);
@@ -487,7 +567,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
-    shat_inverse_mw<TG, TX, CX, NW>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 0, sP, sX, sD);
+    shat_inverse_mw<TG, TX, CX, NW, C::SQ>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 0, sP, sX, sD);
     if constexpr (DG) scale_x(X);  // X~_0 = D_0 X_0 D_0
     TG* xt = xtile(0);
 #pragma unroll
