@@ -120,6 +120,11 @@ struct rlqr_handle {
   int32_t* resfuse = nullptr;        // [B] residual computed by the one-wavefront solve (n + m <= 16, one segment)
   ResChunk* chunks_nf = nullptr;     // residual chunks of the other instances
   int64_t nchunks_nf = 0;
+  // the same chunks by tile class: in float64 mode each class's residual runs
+  // on its own stream right after its solve, beside the other classes' solves
+  ResChunk* cls_chunks[TILE_CLASSES] = {};
+  int64_t cls_nchunks[TILE_CLASSES] = {};
+  bool cls_res = false;
   rlqr_rhs pk_rhs{};
   // scan_carry_pc: the last rlqr_factor_rhs carried p through the scan and
   // wrote the segments' boundary p for this right-hand side into plo
@@ -467,8 +472,9 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   std::vector<int32_t> resfuse(B, 0);
   for (int b = 0; b < B; ++b) {
     resfuse[b] = (cls[b] == TILE_16 && nseg[b] == 1) ? 1 : 0;
-    // stages with n + m > 16 take one lane per residual row: smaller chunks, more wavefronts
-    const int len = cls[b] == TILE_16 ? RES_CHUNK : 2;
+    // stages with n + m > 16 take one lane per (stage, row) of each kind of
+    // row: 64 / n stages per chunk fill a wavefront
+    const int len = cls[b] == TILE_16 ? RES_CHUNK : std::max(1, 64 / h->n[b]);
     for (int i0 = 0; i0 <= h->N[b]; i0 += len) {
       const ResChunk ch{b, i0, std::min(i0 + len, h->N[b] + 1), 0};
       chunks.push_back(ch);
@@ -477,6 +483,8 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   }
   h->nchunks = (int64_t)chunks.size();
   h->nchunks_nf = (int64_t)chunks_nf.size();
+  std::vector<std::vector<ResChunk>> cls_chunks(TILE_CLASSES);
+  for (const ResChunk& ch : chunks_nf) cls_chunks[cls[ch.inst]].push_back(ch);
 
   // scan groups: instances with two or more segments, by element tile size
   std::vector<int32_t> g_insts[3];
@@ -507,6 +515,10 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   A((void**)&h->meta, sizeof(InstMeta) * (size_t)B);
   A((void**)&h->chunks, sizeof(ResChunk) * std::max<size_t>(chunks.size(), 1));
   A((void**)&h->chunks_nf, sizeof(ResChunk) * std::max<size_t>(chunks_nf.size(), 1));
+  for (int c = 0; c < TILE_CLASSES; ++c) {
+    h->cls_nchunks[c] = (int64_t)cls_chunks[c].size();
+    if (h->cls_nchunks[c] > 0) A((void**)&h->cls_chunks[c], sizeof(ResChunk) * cls_chunks[c].size());
+  }
   A((void**)&h->resfuse, sizeof(int32_t) * std::max<size_t>((size_t)B, 1));
   A(&h->ws64, sizeof(double) * (size_t)ws_elems);
   if (mode != RLQR_SEQ_FP64) A(&h->ws32, sizeof(float) * (size_t)ws_elems);
@@ -611,6 +623,9 @@ rlqr_status rlqr_create_tuned(rlqr_handle** hp, const rlqr_shape* s, rlqr_mode m
   if (st == RLQR_OK && B > 0) {
     bool ok = upload(h->meta, meta) && upload(h->chunks, chunks) && upload(h->whole_off, whole_off) &&
               upload(h->chunks_nf, chunks_nf) && upload(h->resfuse, resfuse);
+    for (int c = 0; c < TILE_CLASSES && ok; ++c)
+      if (h->cls_nchunks[c] > 0) ok = upload(h->cls_chunks[c], cls_chunks[c]);
+    h->cls_res = ok;
     for (int c = 0; c < TILE_CLASSES && ok; ++c) {
       if (h->count[c] > 0) ok = upload(h->list[c], lists[c]) && upload(h->whole[c].d, whole_d[c]);
       if (ok && scan && h->fseg[c].count > 0) ok = upload(h->fseg[c].d, fseg_d[c]);
@@ -901,8 +916,15 @@ static CheckArgs check_args(rlqr_handle* h, int final_pass, double tol, const in
 
 // Whole-instance solves, one launch per tile class; run masks select instances.
 // skip (scan mode) leaves the multi-segment instances to the segment solve.
+static ResidualArgs residual_args(rlqr_handle* h, const rlqr_rhs* rhs, const rlqr_sol* z, double* res,
+                                  const int32_t* run);
+
+// res_run: if set, each class's residual (its instances outside the fused
+// one-wavefront residual, run mask res_run) follows its solve on the class's
+// stream, beside the other classes' solves, instead of one launch after all.
 static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out, bool fp32, const int32_t* run,
-                               const double* corr, hipStream_t st, bool fwd_only = false, double* res_out = nullptr) {
+                               const double* corr, hipStream_t st, bool fwd_only = false, double* res_out = nullptr,
+                               const int32_t* res_run = nullptr) {
   hipError_t e = per_class(h, h->count, st, [&](int c, hipStream_t s2) {
     SolveArgs a = solve_args(h, rhs, out, fp32, run, corr);
     a.list = h->list[c];
@@ -910,8 +932,15 @@ static rlqr_status solve_whole(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* ou
     if (res_out && c == TILE_16) {
       a.res = res_out; a.resmax = h->resmax; a.bmax = h->bmax; a.resfuse = h->resfuse;
     }
-    return (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, s2)
-                          : launch_solve_mw(c, a, h->count[c], fp32, s2, h->mw_waves);
+    hipError_t e2 = (c == TILE_16) ? launch_solve(a, h->count[c], fp32, h->shape16, s2)
+                                   : launch_solve_mw(c, a, h->count[c], fp32, s2, h->mw_waves);
+    if (e2 == hipSuccess && res_run && h->cls_nchunks[c] > 0) {
+      ResidualArgs ra = residual_args(h, rhs, out, res_out, res_run);
+      ra.chunks = h->cls_chunks[c];
+      ra.nchunks = h->cls_nchunks[c];
+      e2 = launch_residual(ra, c == TILE_16 ? h->shape16 : SHAPE_LARGE, s2);
+    }
+    return e2;
   });
   return e == hipSuccess ? RLQR_OK : RLQR_E_HIP;
 }
@@ -975,12 +1004,18 @@ static rlqr_status solve_pass(rlqr_handle* h, const rlqr_rhs* rhs, rlqr_sol* out
       return s;
     }
   }
-  if ((s = solve_whole(h, rhs, out, false, r64, corr, st, fwd_only, res_out)) != RLQR_OK) return s;
-  // the one-wavefront solves wrote their instances' residuals; the others here
-  ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
-  ra.chunks = h->chunks_nf;
-  ra.nchunks = h->nchunks_nf;
-  RLQR_TRY(launch_residual(ra, h->shape_all, st));
+  // float64 mode: every instance is solved by this one call, so each class's
+  // residual can follow its own solve (the one-wavefront solves write theirs)
+  const bool cls_res = h->cls_res && h->mode == RLQR_SEQ_FP64 && !run64_override;
+  if ((s = solve_whole(h, rhs, out, false, r64, corr, st, fwd_only, res_out, cls_res ? rres : nullptr)) != RLQR_OK)
+    return s;
+  if (!cls_res) {
+    // the one-wavefront solves wrote their instances' residuals; the others here
+    ResidualArgs ra = residual_args(h, rhs, out, res_out, rres);
+    ra.chunks = h->chunks_nf;
+    ra.nchunks = h->nchunks_nf;
+    RLQR_TRY(launch_residual(ra, h->shape_all, st));
+  }
   RLQR_TRY(launch_check(check_args(h, 0, tol, rres), st));
   return RLQR_OK;
 }

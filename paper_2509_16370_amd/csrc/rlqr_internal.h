@@ -214,6 +214,8 @@ int tile_blocks_per_stage(int cls);  // 16x16 blocks of workspace per stage
 // launch over instances that all share one of them takes the fixed-shape
 // kernel, any other launch the general one (SHAPE_ANY).
 enum { SHAPE_ANY = 0, SHAPE_4_1, SHAPE_8_2, SHAPE_12_4 };
+// launch_residual only: every chunk of the launch has n + m > 16
+constexpr int SHAPE_LARGE = -1;
 inline int fixed_shape(int n, int m) {
   if (n == 4 && m == 1) return SHAPE_4_1;
   if (n == 8 && m == 2) return SHAPE_8_2;

@@ -1014,13 +1014,14 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
 
 // Residual of Section "Residual Computation", float64, parallel over
 // (instance, chunk of stages): one wavefront walks a chunk of consecutive
-// stage slots i of one instance (RES_CHUNK slots for n + m <= 16, two for
+// stage slots i of one instance (RES_CHUNK slots for n + m <= 16, 64 / n for
 // larger stages; slot N carries the terminal row and the c_0 row) and keeps
 // the instance's maxima in registers, so each chunk issues one pair of 64-bit
 // atomic max operations (order-independent). For n + m <= 16 a slot is three
 // tile-vector products on staged blocks (Hessian [[Q, M], [M^T, R]], [A B] and
 // its transpose), with the blocks of the next slot copied to LDS while the
-// current one is reduced; larger stages use one lane per row.
+// current one is reduced; larger stages use one lane per (stage, row) of
+// each kind of row (residual_chunk_rows).
 struct ResVec {
   double xi, ui, yi, yn, xn, qi, ri, cn;
   double dn;  // the lane's entry of the per-stage diagonal Delta_{i+1} (unused with delta I)
@@ -1220,6 +1221,78 @@ __device__ __forceinline__ void residual_slot_rows(const ResidualArgs& a, const 
   }
 }
 
+// The stage slots [i0, min(i1, N)) of one instance with n + m > 16: the rows
+// are taken by kind (primal x rows, primal u rows, dual rows), each kind over
+// all the chunk's stages at once with one lane per (stage, row), so that the
+// lanes of a wavefront run the same products (no divergence between kinds)
+// and a chunk of 64 / n stages fills the wavefront. The inner products are
+// unrolled by 8: eight loads in flight per lane.
+__device__ __forceinline__ void residual_chunk_rows(const ResidualArgs& a, const InstMeta& mt, int b, int i0, int i1,
+                                                    const double* ddall, double& rmax, double& bmax, int lane) {
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m, mm = (int64_t)m * m;
+  const double delta = ddall ? 0.0 : a.delta[b];
+  const double* dd = ddall ? ddall + mt.od : nullptr;
+  const double* q = a.q + mt.oq; const double* r = a.r + mt.or_; const double* c = a.c + mt.oc;
+  const double* x = a.x + mt.ox; const double* u = a.u + mt.ou; const double* y = a.y + mt.oy;
+  double* res = a.res ? a.res + mt.ores : nullptr;
+  const int nst = min(i1, N) - i0;
+  for (int t = lane; t < nst * n; t += 64) {  // Q x + M u + A^T y_{i+1} + q - y_i
+    const int i = i0 + t / n, a0 = t % n;
+    const double* Q = a.Q + mt.oQ + i * nn; const double* M = a.M + mt.oM + i * nm;
+    const double* A = a.A + mt.oA + i * nn;
+    const double* xi = x + (int64_t)i * n; const double* ui = u + (int64_t)i * m;
+    const double* yn = y + (int64_t)(i + 1) * n;
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) s = fma(Q[j * n + a0], xi[j], s);  // Q symmetric: lanes read a row
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) s = fma(M[a0 * m + j], ui[j], s);
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) s = fma(A[j * n + a0], yn[j], s);
+    const double bv = q[(int64_t)i * n + a0];
+    s += bv - y[(int64_t)i * n + a0];
+    if (res) res[(int64_t)i * (n + m) + a0] = s;
+    rmax = maxnan(rmax, fabs(s));
+    bmax = maxnan(bmax, fabs(bv));
+  }
+  for (int t = lane; t < nst * m; t += 64) {  // M^T x + R u + B^T y_{i+1} + r
+    const int i = i0 + t / m, a0 = t % m;
+    const double* M = a.M + mt.oM + i * nm; const double* R = a.R + mt.oR + i * mm;
+    const double* B = a.B + mt.oB + i * nm;
+    const double* xi = x + (int64_t)i * n; const double* ui = u + (int64_t)i * m;
+    const double* yn = y + (int64_t)(i + 1) * n;
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) s = fma(M[j * m + a0], xi[j], s);
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) s = fma(R[j * m + a0], ui[j], s);  // R symmetric
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) s = fma(B[j * m + a0], yn[j], s);
+    const double bv = r[(int64_t)i * m + a0];
+    s += bv;
+    if (res) res[(int64_t)i * (n + m) + n + a0] = s;
+    rmax = maxnan(rmax, fabs(s));
+    bmax = maxnan(bmax, fabs(bv));
+  }
+  for (int t = lane; t < nst * n; t += 64) {  // A x + B u + c_{i+1} - Delta y_{i+1} - x_{i+1}
+    const int i = i0 + t / n, a0 = t % n;
+    const double* A = a.A + mt.oA + i * nn; const double* B = a.B + mt.oB + i * nm;
+    const double* xi = x + (int64_t)i * n; const double* ui = u + (int64_t)i * m;
+    const double* yn = y + (int64_t)(i + 1) * n;
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) s = fma(A[a0 * n + j], xi[j], s);
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) s = fma(B[a0 * m + j], ui[j], s);
+    const double bv = c[(int64_t)(i + 1) * n + a0];
+    s += bv - (dd ? dd[(int64_t)(i + 1) * n + a0] : delta) * yn[a0] - x[(int64_t)(i + 1) * n + a0];
+    if (res) res[(int64_t)N * (n + m) + 2 * n + (int64_t)i * n + a0] = s;
+    rmax = maxnan(rmax, fabs(s));
+    bmax = maxnan(bmax, fabs(bv));
+  }
+}
+
 // SN, SM > 0: every instance of the batch has n = SN, m = SM (n + m <= 16).
 // DG: per-stage diagonal Delta_i (a.dd) in the dual rows.
 // PART 1: only the chunks of stages with n + m <= 16, PART 2: only the
@@ -1288,7 +1361,8 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs a) {
       }
       if (ch.i1 > mt.N) res_terminal(a, mt, n, m, delta, dd, sv, rmax, bmax, lane);
     } else if (PART != 1) {
-      for (int i = ch.i0; i < ch.i1; ++i) residual_slot_rows(a, mt, b, i, dd, rmax, bmax, lane);
+      residual_chunk_rows(a, mt, b, ch.i0, ch.i1, dd, rmax, bmax, lane);
+      if (ch.i1 > mt.N) residual_slot_rows(a, mt, b, mt.N, dd, rmax, bmax, lane);  // terminal rows
     }
     rmax = wave_max(rmax);
     bmax = wave_max(bmax);
@@ -1499,11 +1573,12 @@ hipError_t launch_residual(const ResidualArgs& a, int shape, hipStream_t st) {
   if (a.nchunks <= 0) return hipSuccess;
   const dim3 grid((unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20)));
   if (a.dd) {
-    hipLaunchKernelGGL((k_residual<0, 0, true, 1>), grid, dim3(64), 0, st, a);
+    if (shape != SHAPE_LARGE) hipLaunchKernelGGL((k_residual<0, 0, true, 1>), grid, dim3(64), 0, st, a);
     hipLaunchKernelGGL((k_residual<0, 0, true, 2>), grid, dim3(64), 0, st, a);
     return hipGetLastError();
   }
   switch (shape) {
+    case SHAPE_LARGE: hipLaunchKernelGGL((k_residual<0, 0, false, 2>), grid, dim3(64), 0, st, a); break;
     case SHAPE_4_1: hipLaunchKernelGGL((k_residual<4, 1, false, 1>), grid, dim3(64), 0, st, a); break;
     case SHAPE_8_2: hipLaunchKernelGGL((k_residual<8, 2, false, 1>), grid, dim3(64), 0, st, a); break;
     case SHAPE_12_4: hipLaunchKernelGGL((k_residual<12, 4, false, 1>), grid, dim3(64), 0, st, a); break;

@@ -108,8 +108,8 @@ extern "C" rlqr_status rlqr_residual_noalloc(const rlqr_shape* s, const rlqr_lhs
     } else {
       same16 = false;
     }
-    // stages with n + m > 16 take one lane per residual row: two-stage chunks
-    const int len = cls == TILE_16 ? RES_CHUNK : 2;
+    // stages with n + m > 16: 64 / n stages per chunk (one lane per stage and row)
+    const int64_t len = cls == TILE_16 ? RES_CHUNK : std::max<int64_t>(1, 64 / n);
     for (int64_t i0 = 0; i0 <= N; i0 += len)
       chunks.push_back(ResChunk{b, (int32_t)i0, (int32_t)std::min<int64_t>(i0 + len, N + 1), 0});
   }
