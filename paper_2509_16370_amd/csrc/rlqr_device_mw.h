@@ -105,13 +105,21 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
 // accumulator comes out in the register layout TL of the blocks.
 // panel: 16 TT x 17 doubles, mbuf: 2 x 16 x 17 doubles (LDS, free during the call).
 // Only wavefront 0's PivStats receive the pivots.
+// pscale: the pivots j0..j1-1 lie in one block column and the caller passes
+// the tolerance as a multiple of the scale (tol = coefficient, scale unused):
+// wavefront 0 takes the scale, max |X_jj| over the pivots, from the panel's
+// diagonal block (the same values a workgroup reduction over the tile would
+// find), which saves that reduction's barriers.
+// TAIL = false: no barrier after the last update; the caller's next barrier
+// must come before anything is written to the panel's LDS region.
 template <typename TL>
 __device__ __forceinline__ int blk_row(int i) { return trow<TL>(i & 3, i >> 2); }
 
-template <typename TL, int C, int TT>
+template <typename TL, int C, int TT, bool TAIL = true>
 __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C], const int (&bj)[C],
                                           const bool (&ok)[C], int j0, int j1, int w, int lane, double* panel,
-                                          double* mbuf, PivStats& ps, int code, double tol, double scale) {
+                                          double* mbuf, PivStats& ps, int code, double tol, double scale,
+                                          bool pscale = false) {
   constexpr int LP = 17;
   const int col = lane & 15, grp = lane >> 4;
   const int ia = lane & 15, kq = lane >> 4;  // MFMA operand coordinates
@@ -138,7 +146,18 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
       for (int v = 0; v < 4; ++v) D[v] = panel[(16 * K + trow<TL>(grp, v)) * LP + col];
       int lane_s = lane;  // opaque: the per-pivot lane masks stay inside the loop
       asm volatile("" : "+v"(lane_s));
-      sweep16<TL>(D, s0, s1, lane_s, ps, code, tol, scale);
+      double t = tol, sc = scale;
+      if (pscale) {
+        double dm = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = trow<TL>(grp, v);
+          if (r == col && r >= s0 && r < s1) dm = fmax(dm, fabs(D[v]));
+        }
+        sc = wave_max(dm);
+        t = tol * sc;
+      }
+      sweep16<TL>(D, s0, s1, lane_s, ps, code, t, sc);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = trow<TL>(grp, v);
@@ -196,7 +215,7 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
       __builtin_amdgcn_sched_barrier(0);  // one block at a time: bounds the live accumulators
     }
   }
-  __syncthreads();  // the panel is read until here; the caller may reuse the region
+  if constexpr (TAIL) __syncthreads();  // the panel is read until here; the caller may reuse the region
 }
 
 template <int C, typename TL>

@@ -3,7 +3,8 @@
 // Factor: the backward recursion of Section "Sequential Algorithm"
 // (arXiv 2509.16370), one wavefront per instance, 16 x 16 tiles. Per stage k:
 //   X   = I + delta P_{k+1}                 sweep all n pivots -> X = -S_hat^{-1}
-//   W   = -P_{k+1} X = P S_hat^{-1}         MFMA, then symmetrized
+//   W   = -P_{k+1} X = P S_hat^{-1}         MFMA (symmetric to rounding; Z's
+//                                           symmetrization below covers it)
 //   T   = W [A_k B_k]                       MFMA
 //   Z   = [A_k B_k]^T T + [[Q_k, M_k], [M_k^T, R_k]]   MFMA, symmetrized
 //       = [[A^T W A + Q, H^T], [H, G]]      (G = R + B^T W B, H = B^T W A + M^T)
@@ -544,17 +545,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       tile_to_lds<TG>(sX, X, lane);
     }
     wave_sync();
-    // W = -P X, symmetrized (sD overlays sP)
+    // W = -P X. Symmetric only up to rounding, and left so: Z = [A B]^T W [A B]
+    // + Hess is symmetrized below, which symmetrizes W's share of it as well
     double W[4];
     {
       auto acc = gemm16<TG, false>(sP, sX, lane);
       acc_to_regs<TG>(W, acc, -1.0);
     }
-    wave_sync();
-    tile_to_lds<TG>(sD, W, lane);
-    wave_sync();
-#pragma unroll
-    for (int v = 0; v < 4; ++v) W[v] = 0.5 * (W[v] + sD[col * LD + trow<TG>(grp, v)]);
     wave_sync();
     tile_to_lds<TG>(sP, W, lane);
     // the stage blocks of step k must have landed

@@ -66,6 +66,8 @@ struct MwCfg {
       TX <= 2 && (BYTES_Q > BYTES_U2 ? BYTES_Q : BYTES_U2) + (int)sizeof(TG) * NX * LDZ <= 160 * 1024;
   static constexpr int BYTES_U0 = SQ && BYTES_Q > BYTES_U2 ? BYTES_Q : BYTES_U2;
   static constexpr int BYTES_U = (BYTES_U0 + 15) / 16 * 16;
+  // W in a tile of its own after the X tile, where the work region has room
+  static constexpr bool WSEP = 2 * BYTES_P + BYTES_X <= BYTES_U;
   static constexpr int BYTES_AB = (int)sizeof(TG) * NX * LDZ;
   static constexpr int BLOCKS_PER_STAGE = TZ * TZ + TX * TX;
 };
@@ -76,15 +78,19 @@ struct MwCfg {
 // truncated Neumann series Y_1 = I - E, Y_j = I - E Y_{j-1} (one blocked MFMA
 // product and two workgroup barriers per further term, E and Y through the
 // LDS tiles sE and sY, stride LDX) replaces the pivot sweep and the norm bound
-// certifies every pivot positive; the result is symmetrized through sD (a
-// float64 tile that may overlay sE and sY). With SQ (four state tiles from sE
-// on) four or more terms are summed by squaring instead. Otherwise the
-// blocked sweep runs.
+// certifies every pivot positive. The series is a polynomial in the symmetric
+// E, symmetric up to the rounding of its products, and is not symmetrized:
+// the tiles built from it (W, then Z) are symmetrized where the symmetric
+// sweep needs it. With SQ (four state tiles from sE on) four or more terms
+// are summed by squaring instead. Otherwise the blocked sweep runs.
+// rnorm: NW doubles of LDS used by nothing else (its previous readers, the
+// call before, are behind the caller's barriers, so no barrier precedes its
+// stores); red: NW doubles for the sweep's scale.
 template <typename TG, int TX, int CX, int NW, bool SQ>
 __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&xi)[CX], const int (&xj)[CX],
                                                 const bool (&xo)[CX], int n, int w, int lane, double* red,
-                                                double* panel, double* mbuf, PivStats& ps, int code, TG* sE,
-                                                TG* sY, double* sD) {
+                                                double* rnorm, double* panel, double* mbuf, PivStats& ps,
+                                                int code, TG* sE) {
   constexpr int NX = 16 * TX, LDX = NX + 1;
   const int col = lane & 15, grp = lane >> 4;
   double s2 = 0.0;
@@ -97,12 +103,11 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
         s2 = __fma_rn(d, d, s2);
       }
   s2 = wave_sum_rows(s2);
-  __syncthreads();
-  if (lane == 0) red[w] = s2;
+  if (lane == 0) rnorm[w] = s2;
   __syncthreads();
   double tot = 0.0;
 #pragma unroll
-  for (int i = 0; i < NW; ++i) tot += red[i];  // same order in every thread: uniform
+  for (int i = 0; i < NW; ++i) tot += rnorm[i];  // same order in every thread: uniform
   const double e = sqrt(tot);
   const int terms = neumann_terms<TG>(e);
   if (terms == 0) {
@@ -200,6 +205,7 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
       __syncthreads();
     }
   } else if (terms > 1) {
+    TG* sY = sE + NX * LDX;
     for (int j = 2; j <= terms; ++j) {
 #pragma unroll
       for (int t = 0; t < CX; ++t)
@@ -216,22 +222,7 @@ __device__ __forceinline__ void shat_inverse_mw(double (&X)[CX][4], const int (&
       __syncthreads();
     }
   }
-  if (terms > 1) {
-    // E Y is symmetric only up to rounding: Y <- (Y + Y^T) / 2
-#pragma unroll
-    for (int t = 0; t < CX; ++t)
-      if (xo[t]) blk_to_lds<TG>(sD, LDX, xi[t], xj[t], X[t], lane);
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < CX; ++t)
-      if (xo[t])
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
-          X[t][v] = 0.5 * (X[t][v] + sD[c * LDX + r]);
-        }
-    __syncthreads();
-  }
+  // (both forms end with a barrier: the caller may overwrite sE onwards)
 #pragma unroll
   for (int t = 0; t < CX; ++t)
 #pragma unroll
@@ -276,9 +267,10 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   auto xtile = [&](int i) { return ws + (int64_t)i * STAGE + (int64_t)TZ * TZ * 256; };
 
   __shared__ __align__(16) unsigned char smem[C::BYTES_U + C::BYTES_AB];
-  __shared__ double red[NW];
+  __shared__ double red[NW], rnorm[NW];
   TG* sP = reinterpret_cast<TG*>(smem);
   TG* sX = reinterpret_cast<TG*>(smem + C::BYTES_P);
+  TG* sW = C::WSEP ? reinterpret_cast<TG*>(smem + C::BYTES_P + C::BYTES_X) : sP;
   double* sD = reinterpret_cast<double*>(smem);
   TG* sAB = reinterpret_cast<TG*>(smem + C::BYTES_U);
   // the blocked sweeps' panel and pivot block overlay the work region, which
@@ -438,7 +430,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
-    shat_inverse_mw<TG, TX, CX, NW, C::SQ>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 2 * (k + 1), sP, sX, sD);
+    shat_inverse_mw<TG, TX, CX, NW, C::SQ>(X, xi, xj, xo, n, w, lane, red, rnorm, panel, mbuf, ps, 2 * (k + 1), sP);
     if constexpr (DG) scale_x(X);  // X~ = D X D
     {
       TG* xt = xtile(k + 1);
@@ -463,7 +455,10 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       }
     __syncthreads();
     lane_fence(tid, lane, col, grp);
-    // W = -P X, symmetrized through sD (sD overlaps sP/sX: barrier between)
+    // W = -P X, symmetric only up to rounding and left so: Z = [A B]^T W [A B]
+    // + Hessian is symmetrized below, which symmetrizes W's share of it as
+    // well. W goes to its own tile sW where the work region has room for one
+    // (no barrier before its stores), else over P once every product has read it.
     double W[CX][4];
 #pragma unroll
     for (int t = 0; t < CX; ++t) {
@@ -474,29 +469,17 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) W[t][v] = -(double)acc[v];
     }
-    __syncthreads();
+    if constexpr (!C::WSEP) __syncthreads();
 #pragma unroll
     for (int t = 0; t < CX; ++t)
-      if (xo[t]) blk_to_lds<TG>(sD, LDX, xi[t], xj[t], W[t], lane);
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < CX; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * xi[t] + trow<TG>(grp, v), c = 16 * xj[t] + col;
-        if (xo[t]) W[t][v] = 0.5 * (W[t][v] + sD[c * LDX + r]);
-      }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < CX; ++t)
-      if (xo[t]) blk_to_lds<TG>(sP, LDX, xi[t], xj[t], W[t], lane);
+      if (xo[t]) blk_to_lds<TG>(sW, LDX, xi[t], xj[t], W[t], lane);
     __syncthreads();
     lane_fence(tid, lane, col, grp);
     // T = W [A B]  (NX x NZ)
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
       if (!to[t]) continue;
-      auto acc = gemm_blk<TG, false, TX>(sP, LDX, sAB, LDZ, ti[t], tj[t], lane);
+      auto acc = gemm_blk<TG, false, TX>(sW, LDX, sAB, LDZ, ti[t], tj[t], lane);
       double Tb[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) Tb[v] = (double)acc[v];
@@ -530,8 +513,15 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
       }
     lane_fence(tid, lane, col, grp);
     {
-      const double sc = wg_max<NW>(diag_max<CZ, TG>(Z, zi, zj, zo, n, n + m, lane), red, w, lane);
-      sweep_blk<TG, CZ, TZ>(Z, zi, zj, zo, n, n + m, w, lane, panel, mbuf, ps, 2 * k + 1, 1.0e3 * m * eps * sc, sc);
+      // control pivots within one block column: wavefront 0 takes their scale
+      // from the sweep's panel; else a workgroup reduction over the tile. No
+      // barrier after the sweep: the next one is at the top of the stage (or
+      // in the state pivot after the loop), before any store to its region.
+      const bool one = m > 0 && (n >> 4) == ((n + m - 1) >> 4);
+      const double sc = one ? 0.0 : wg_max<NW>(diag_max<CZ, TG>(Z, zi, zj, zo, n, n + m, lane), red, w, lane);
+      const double coef = 1.0e3 * m * eps;
+      sweep_blk<TG, CZ, TZ, false>(Z, zi, zj, zo, n, n + m, w, lane, panel, mbuf, ps, 2 * k + 1,
+                                   one ? coef : coef * sc, sc, one);
     }
     {
       TG* zt = ztile(k);
@@ -567,7 +557,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const double sc = DG ? (xo[t] ? sdl[r] * sdl[c] : 0.0) : delta;
         X[t][v] = (xo[t] && r == c ? 1.0 : 0.0) + sc * P[t][v];
       }
-    shat_inverse_mw<TG, TX, CX, NW, C::SQ>(X, xi, xj, xo, n, w, lane, red, panel, mbuf, ps, 0, sP, sX, sD);
+    shat_inverse_mw<TG, TX, CX, NW, C::SQ>(X, xi, xj, xo, n, w, lane, red, rnorm, panel, mbuf, ps, 0, sP);
     if constexpr (DG) scale_x(X);  // X~_0 = D_0 X_0 D_0
     TG* xt = xtile(0);
 #pragma unroll
@@ -949,6 +939,298 @@ __global__ __launch_bounds__(64 * NW) void k_solve_mw(SolveArgs a) {
   }
 }
 
+// Column-owned whole-instance solve for the stage tiles up to 48 wide (TZ <= 3):
+// the passes of k_solve_mw (SEG = false; Theorem "main-seq-theorem") with one
+// wavefront per block column, TZ in all. Wavefront J holds block column J of
+// every tile it multiplies, so a product y = T^T v is a sum over the block
+// rows in registers and over the four lane groups (group_sum), and entry
+// y_i lands in the thread that owns index i (wavefront i / 16, the lanes of
+// column i % 16), the thread that holds every other per-index quantity of
+// the step as well. Each product costs one workgroup barrier (its operand
+// vector goes through LDS): three per step in each direction. The backward
+// pass forms P_k c_k for the next step from the same tile Z_k, in the same
+// phase as [-K_k^T h; -G_k^{-1} h].
+template <int TX, int TZ>
+__device__ __forceinline__ int zblock(int I, int J) {
+  if (I < TX && J < TX) return I * TX + J;
+  if (I < TX) return TX * TX + I * (TZ - TX) + (J - TX);
+  return TX * TX + TX * (TZ - TX) + (I - TX) * TZ + J;
+}
+
+// sum over the rows of R blocks of one block column: sum_r T[r][c] vec[r]
+template <typename TL, typename T, int R>
+__device__ __forceinline__ double col_dot(const T (&X)[R][4], const double* vec, int grp) {
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int I = 0; I < R; ++I) {
+    s0 = __fma_rn((double)X[I][0], vec[16 * I + trow<TL>(grp, 0)], s0);
+    s1 = __fma_rn((double)X[I][1], vec[16 * I + trow<TL>(grp, 1)], s1);
+    s0 = __fma_rn((double)X[I][2], vec[16 * I + trow<TL>(grp, 2)], s0);
+    s1 = __fma_rn((double)X[I][3], vec[16 * I + trow<TL>(grp, 3)], s1);
+  }
+  return group_sum(s0 + s1);
+}
+
+template <typename TG, int TX, int TZ, bool DG>
+__global__ __launch_bounds__(64 * TZ) void k_solve_col(SolveArgs a) {
+  using C = MwCfg<TG, TX, TZ, TZ>;
+  constexpr int NX = C::NX, NZ = C::NZ;
+  const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  const int J = tid >> 6;  // the wavefront's block column
+  if (a.run && !a.run[b]) return;
+  const InstMeta mt = a.meta[b];
+  const int N = mt.N, n = mt.n, m = mt.m;
+  const double delta = DG ? 0.0 : a.delta[b];
+  const double* __restrict__ ddg = DG ? a.dd + mt.od : nullptr;
+  const double* __restrict__ Ag = a.A + mt.oA;
+  const double* __restrict__ Bg = a.B + mt.oB;
+  const TG* __restrict__ ws = reinterpret_cast<const TG*>(a.ws) + mt.ows;
+  constexpr int64_t STAGE = (int64_t)C::BLOCKS_PER_STAGE * 256;
+  auto ztile = [&](int i) { return ws + (int64_t)i * STAGE; };
+  auto xtile = [&](int i) { return ws + (int64_t)i * STAGE + (int64_t)TZ * TZ * 256; };
+  double* __restrict__ pg = a.pk + mt.opk;
+  double* __restrict__ kg = a.pk + mt.opk + (int64_t)(N + 1) * n;
+  const double *qb, *rb, *cb;
+  int64_t qs, rs;
+  const bool accum = a.corr != nullptr;
+  if (accum) {
+    const double* res = a.corr + mt.ores;
+    qb = res; qs = n + m;
+    rb = res + n; rs = n + m;
+    cb = res + (int64_t)N * (n + m) + n;
+  } else {
+    qb = a.q + mt.oq; qs = n;
+    rb = a.r + mt.or_; rs = m;
+    cb = a.c + mt.oc;
+  }
+  double* __restrict__ xg = a.x + mt.ox;
+  double* __restrict__ ug = a.u + mt.ou;
+  double* __restrict__ yg = a.y + mt.oy;
+  if (a.info[b].singular) {
+    if (!accum) {
+      const double nanv = __builtin_nan("");
+      for (int i = tid; i < (N + 1) * n; i += 64 * TZ) { xg[i] = nanv; yg[i] = nanv; }
+      for (int i = tid; i < N * m; i += 64 * TZ) ug[i] = nanv;
+    }
+    return;
+  }
+
+  // operand vectors, one per product of a step (a buffer is rewritten only
+  // after a barrier that every reader of its previous contents has passed)
+  __shared__ double bv[NZ], bg[NZ], bh[NZ], bc[NZ], bx[NZ], bz[NZ], bw[NZ];
+  const int vi = 16 * J + col;  // the vector index this thread owns
+  const bool xr = vi < n, ur = vi >= n && vi < n + m, own = grp == 0;
+  const bool wx = J < TX;  // the wavefront holds state indices (and X, [A B]^T columns)
+
+  // tile loads in the stored precision (converted where used); padding
+  // elements of [A B] read the zero kZeroPad (branch-free)
+  auto load_z = [&](TG (&R)[TZ][4], const TG* zt) {
+#pragma unroll
+    for (int I = 0; I < TZ; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R[I][v] = zt[(int64_t)zblock<TX, TZ>(I, J) * 256 + v * 64 + lane];
+  };
+  const int Jx = wx ? J : 0;  // the other wavefronts load a state column too (unused): no masked loads
+  auto load_x = [&](TG (&R)[TX][4], const TG* xt) {
+#pragma unroll
+    for (int I = 0; I < TX; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R[I][v] = xt[(int64_t)(I * TX + Jx) * 256 + v * 64 + lane];
+  };
+  auto ab_ptr = [&](int k, int r, int c) {  // &[A_k B_k][r][c], or the zero
+    const double* A = Ag + (int64_t)k * n * n;
+    const double* B = Bg + (int64_t)k * n * m;
+    const bool inA = r < n && c < n, inB = r < n && c >= n && c < n + m;
+    return inA ? A + r * n + c : (inB ? B + r * m + (c - n) : kZeroPad);
+  };
+  auto load_ab = [&](double (&R)[TX][4], int k) {  // column J of [A B]
+#pragma unroll
+    for (int I = 0; I < TX; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R[I][v] = *ab_ptr(k, 16 * I + trow<TG>(grp, v), 16 * J + col);
+  };
+  auto load_abt = [&](double (&R)[TZ][4], int k) {  // column J of [A B]^T (J < TX)
+#pragma unroll
+    for (int I = 0; I < TZ; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) R[I][v] = *ab_ptr(k, wx ? 16 * J + col : NX, 16 * I + trow<TG>(grp, v));
+  };
+  auto ldv = [&](const double* p, int64_t i, bool ok) { return *(ok ? p + i : kZeroPad); };
+
+  // ---- backward vector pass, k = N-1 .. 0. p_k and k_k go to pk from every
+  // lane group (the same value): each thread reads back only its own stores.
+  double p = ldv(qb, (int64_t)N * qs + vi, xr);  // p_{k+1}
+  if (xr) pg[(int64_t)N * n + vi] = p;
+  double pc;  // (P_{k+1} c_{k+1})_vi
+  {
+    TG ZN[TZ][4];
+    load_z(ZN, ztile(N));
+    const double cN = ldv(cb, (int64_t)N * n + vi, xr);
+    if (own) bc[vi] = cN;
+    __syncthreads();
+    pc = col_dot<TG, TG, TX>(reinterpret_cast<const TG(&)[TX][4]>(ZN), bc, grp);
+  }
+  // A step's operands are loaded two steps ahead (the loads are in flight for
+  // two steps of products and barriers): three operand sets in rotation,
+  // the loop unrolled by three so that no set is copied.
+  struct BwdOps {
+    TG Z[TZ][4];      // column J of Z_k
+    TG X[TX][4];      // column J of X_{k+1}
+    double AB[TX][4]; // column J of [A_k B_k]
+    double q, r, c, d;
+  };
+  auto load_bwd = [&](BwdOps& o, int k) {
+    k = k > 0 ? k : 0;
+    load_z(o.Z, ztile(k));
+    load_x(o.X, xtile(k + 1));
+    load_ab(o.AB, k);
+    o.q = ldv(qb, (int64_t)k * qs + vi, xr);
+    o.r = ldv(rb, (int64_t)k * rs + (vi - n), ur);
+    o.c = ldv(cb, (int64_t)k * n + vi, xr);
+    o.d = DG ? ldv(ddg, (int64_t)(k + 1) * n + vi, xr) : 0.0;
+  };
+  auto bwd_step = [&](const BwdOps& o, int k) {
+    // g = S_hat_{k+1}^{-1} (p_{k+1} + P_{k+1} c_{k+1})  (DG: -Delta^{-1} X~ v)
+    if (own && wx) bv[vi] = xr ? p + pc : 0.0;
+    __syncthreads();
+    double g = 0.0;
+    if (wx) {
+      const double t = col_dot<TG, TG, TX>(o.X, bv, grp);
+      g = xr ? (DG ? -t / o.d : -t) : 0.0;
+    }
+    // [A^T g; B^T g]
+    if (own && wx) bg[vi] = g;
+    __syncthreads();
+    const double abg = col_dot<TG, double, TX>(o.AB, bg, grp);
+    // h = r_k + B^T g; [-K^T h; -G^{-1} h] and P_k c_k, both from Z_k
+    if (own) {
+      bh[vi] = ur ? o.r + abg : 0.0;
+      bc[vi] = xr ? o.c : 0.0;
+    }
+    __syncthreads();
+    const double zh = col_dot<TG, TG, TZ>(o.Z, bh, grp);
+    pc = wx ? col_dot<TG, TG, TX>(reinterpret_cast<const TG(&)[TX][4]>(o.Z), bc, grp) : 0.0;
+    if (xr) {
+      p = o.q + abg - zh;
+      pg[(int64_t)k * n + vi] = p;
+    }
+    if (ur) kg[(int64_t)k * m + (vi - n)] = zh;
+  };
+  if (N > 0) {
+    BwdOps S0, S1, S2;
+    load_bwd(S0, N - 1);
+    load_bwd(S1, N - 2);
+    int k = N - 1;
+    for (;;) {
+      load_bwd(S2, k - 2);
+      bwd_step(S0, k);
+      if (--k < 0) break;
+      load_bwd(S0, k - 2);
+      bwd_step(S1, k);
+      if (--k < 0) break;
+      load_bwd(S1, k - 2);
+      bwd_step(S2, k);
+      if (--k < 0) break;
+    }
+  }
+
+  // ---- forward rollout, k = 0 .. N-1
+  double x;
+  {
+    TG X0[TX][4];
+    load_x(X0, xtile(0));
+    const double p0 = ldv(pg, vi, xr);
+    const double c0 = ldv(cb, vi, xr);
+    const double d0 = DG ? ldv(ddg, vi, xr) : delta;
+    if (own && wx) bw[vi] = xr ? (DG ? (c0 - d0 * p0) / d0 : c0 - delta * p0) : 0.0;
+    __syncthreads();
+    x = (wx && xr) ? -col_dot<TG, TG, TX>(X0, bw, grp) : 0.0;
+  }
+  struct FwdOps {
+    TG Z[TX][4];       // column J of Z_k, state rows
+    TG X[TX][4];       // column J of X_{k+1}
+    double ABt[TZ][4]; // column J of [A_k B_k]^T
+    double pk, kk, pn, cn, dn;
+  };
+  auto load_fwd = [&](FwdOps& o, int k) {
+    k = k < N - 1 ? k : N - 1;
+#pragma unroll
+    for (int I = 0; I < TX; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o.Z[I][v] = ztile(k)[(int64_t)zblock<TX, TZ>(I, J) * 256 + v * 64 + lane];
+    load_x(o.X, xtile(k + 1));
+    load_abt(o.ABt, k);
+    o.pk = ldv(pg, (int64_t)k * n + vi, xr);
+    o.kk = ldv(kg, (int64_t)k * m + (vi - n), ur);
+    o.pn = ldv(pg, (int64_t)(k + 1) * n + vi, xr);
+    o.cn = ldv(cb, (int64_t)(k + 1) * n + vi, xr);
+    o.dn = DG ? ldv(ddg, (int64_t)(k + 1) * n + vi, xr) : delta;
+  };
+  auto fwd_step = [&](const FwdOps& o, int k) {
+    // [P_k x_k; -K_k x_k]: y_k and u_k
+    if (own && wx) bx[vi] = x;
+    __syncthreads();
+    const double zx = col_dot<TG, TG, TX>(o.Z, bx, grp);
+    double uk = 0.0;
+    if (own && xr) {
+      const int64_t i = (int64_t)k * n + vi;
+      const double yk = zx + o.pk;
+      yg[i] = accum ? yg[i] + yk : yk;
+      xg[i] = accum ? xg[i] + x : x;
+    }
+    if (ur) {
+      uk = o.kk - zx;
+      const int64_t i = (int64_t)k * m + (vi - n);
+      if (own) ug[i] = accum ? ug[i] + uk : uk;
+    }
+    // [A_k B_k] z_k
+    if (own) bz[vi] = xr ? x : uk;
+    __syncthreads();
+    double wv = 0.0;
+    if (wx) {
+      const double t = col_dot<TG, double, TZ>(o.ABt, bz, grp);
+      wv = xr ? (DG ? (t + o.cn - o.dn * o.pn) / o.dn : t + o.cn - delta * o.pn) : 0.0;
+    }
+    // x_{k+1} = S_hat_{k+1}^{-1} (...)  (DG: -X~ Delta^{-1} (...))
+    if (own && wx) bw[vi] = wv;
+    __syncthreads();
+    x = (wx && xr) ? -col_dot<TG, TG, TX>(o.X, bw, grp) : 0.0;
+  };
+  if (N > 0) {
+    FwdOps S0, S1, S2;
+    load_fwd(S0, 0);
+    load_fwd(S1, 1);
+    int k = 0;
+    for (;;) {
+      load_fwd(S2, k + 2);
+      fwd_step(S0, k);
+      if (++k >= N) break;
+      load_fwd(S0, k + 2);
+      fwd_step(S1, k);
+      if (++k >= N) break;
+      load_fwd(S1, k + 2);
+      fwd_step(S2, k);
+      if (++k >= N) break;
+    }
+  }
+  // x_N, y_N = P_N x_N + p_N
+  {
+    TG ZN[TZ][4];
+    load_z(ZN, ztile(N));
+    const double pN = ldv(pg, (int64_t)N * n + vi, xr);
+    if (own && wx) bx[vi] = x;
+    __syncthreads();
+    const double zx = col_dot<TG, TG, TX>(reinterpret_cast<const TG(&)[TX][4]>(ZN), bx, grp);
+    if (own && xr) {
+      const int64_t i = (int64_t)N * n + vi;
+      const double yN = zx + pN;
+      yg[i] = accum ? yg[i] + yN : yN;
+      xg[i] = accum ? xg[i] + x : x;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ dispatch
 
 template <typename TG, int TX, int TZ, int NW>
@@ -960,11 +1242,19 @@ static hipError_t launch_mw_pair(bool factor, const void* args, int nblocks, hip
     else
       hipLaunchKernelGGL((k_factor_mw<TG, TX, TZ, NW, false>), dim3(nblocks), dim3(64 * NW), 0, st, a);
   } else {
+    // whole-instance solves: one wavefront per block column up to 48-wide tiles
     const SolveArgs& a = *reinterpret_cast<const SolveArgs*>(args);
-    if (a.dd)
-      hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false, false>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+    if constexpr (TZ <= 3) {
+      if (a.dd)
+        hipLaunchKernelGGL((k_solve_col<TG, TX, TZ, true>), dim3(nblocks), dim3(64 * TZ), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_solve_col<TG, TX, TZ, false>), dim3(nblocks), dim3(64 * TZ), 0, st, a);
+    } else {
+      if (a.dd)
+        hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false, true>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_solve_mw<TG, TX, TZ, NW, false, false>), dim3(nblocks), dim3(64 * NW), 0, st, a);
+    }
   }
   return hipGetLastError();
 }
