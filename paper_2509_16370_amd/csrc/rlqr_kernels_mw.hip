@@ -280,7 +280,7 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   static_assert((NZ * 17 + 2 * 16 * 17) * 8 <= C::BYTES_U, "sweep panel exceeds the work region");
 
   int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
-  const int w = tid >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   int xi[CX], xj[CX], zi[CZ], zj[CZ], ti[CT], tj[CT];
   bool xo[CX], zo[CZ], to[CT];
 #pragma unroll
@@ -977,7 +977,7 @@ __global__ __launch_bounds__(64 * TZ) void k_solve_col(SolveArgs a) {
   constexpr int NX = C::NX, NZ = C::NZ;
   const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
-  const int J = tid >> 6;  // the wavefront's block column
+  const int J = __builtin_amdgcn_readfirstlane(tid >> 6);  // the wavefront's block column (uniform)
   if (a.run && !a.run[b]) return;
   const InstMeta mt = a.meta[b];
   const int N = mt.N, n = mt.n, m = mt.m;
@@ -1075,14 +1075,28 @@ __global__ __launch_bounds__(64 * TZ) void k_solve_col(SolveArgs a) {
   // two steps of products and barriers): three operand sets in rotation,
   // the loop unrolled by three so that no set is copied.
   struct BwdOps {
-    TG Z[TZ][4];      // column J of Z_k
+    TG Z[TZ][4];      // column J of Z_k (state rows only in the state columns)
     TG X[TX][4];      // column J of X_{k+1}
     double AB[TX][4]; // column J of [A_k B_k]
     double q, r, c, d;
   };
+  // the backward products take Z_k's state block (P_k c_k) and its control
+  // rows (h only has control entries, rows n .. n+m-1): in the control
+  // columns the block rows above row n are not read, and their registers are
+  // zero
+  const int hrow0 = n >> 4;  // first block row holding a control row
   auto load_bwd = [&](BwdOps& o, int k) {
     k = k > 0 ? k : 0;
-    load_z(o.Z, ztile(k));
+#pragma unroll
+    for (int I = 0; I < TZ; ++I) {
+      if (wx || I >= hrow0) {  // uniform branch
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o.Z[I][v] = ztile(k)[(int64_t)zblock<TX, TZ>(I, J) * 256 + v * 64 + lane];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o.Z[I][v] = (TG)0;
+      }
+    }
     load_x(o.X, xtile(k + 1));
     load_ab(o.AB, k);
     o.q = ldv(qb, (int64_t)k * qs + vi, xr);

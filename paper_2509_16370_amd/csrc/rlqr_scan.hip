@@ -251,7 +251,7 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
   asm volatile("" : "+v"(tid));
   using C = ScanCfg<TX, NW>;
   constexpr int NX = C::NX, LDX = C::LDX, LDW = C::LDW, CB = C::CB;
-  const int w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, col = lane & 15, grp = lane >> 4;
   bool ok = true;
   // X = I + C1 P2 into the left half of W
 #pragma unroll
@@ -566,7 +566,8 @@ __global__ __launch_bounds__(64 * NW) void k_scan_init(ScanArgs a) {
   const int N = mt.N, n = mt.n, m = mt.m;
   const int i = blockIdx.x;
   if (i > N) return;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, col = lane & 15,
+            grp = lane >> 4;
   float* __restrict__ e = a.elems + (a.eoff[blockIdx.y] + i) * 3 * NX * NX;
   float* __restrict__ epc = a.pc ? a.pce + (a.eoff[blockIdx.y] + i) * 2 * NX : nullptr;
   if (i == N) {  // terminal element (eq. lqr-gpu-init-terminal): (Q_N, q_N, 0, 0, 0)
@@ -912,7 +913,8 @@ __global__ __launch_bounds__(64 * NW) void k_transfer(TransferArgs a) {
   __shared__ float sPsi[NX * LX], sX[NX * LX], sT[NX * LX];
   __shared__ float sK[NZ * LX], sV[NZ * LX];
   __shared__ float sAB[NX * LZ];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, col = lane & 15,
+            grp = lane >> 4;
   for (int x = tid; x < NX * LX; x += 64 * NW) {
     const int r = x / LX, c = x % LX;
     sPsi[x] = (r == c && r < n) ? 1.0f : 0.0f;
