@@ -166,6 +166,10 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
       }
     }
     __syncthreads();
+    // M is zero outside the pivots s0..s1-1 (rows and columns): the products'
+    // inner dimension runs over the 4-wide chunks that hold pivots only (the
+    // skipped chunks would add exact zeros)
+    const int kb0 = s0 >> 2, kb1 = (s1 + 3) >> 2;
 #pragma unroll
     for (int t = 0; t < C; ++t) {
       if (!ok[t]) continue;
@@ -179,20 +183,24 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
       d4 F = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
+        if (kk < kb0 || kk >= kb1) continue;  // uniform
         const int k = 4 * kk + kq;
         F = mfma16(mbuf[ia * LP + k], panel[(16 * J + ia) * LP + k], F);
       }
       // E = U_I M U_J^T, rows permuted into the layout TL
       d4 E = {0, 0, 0, 0};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
+      for (int kk = 0; kk < 4; ++kk) {
+        if (kk < kb0 || kk >= kb1) continue;
         E = mfma16(panel[(16 * I + blk_row<TL>(ia)) * LP + 4 * kk + kq], F[kk], E);
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) X[t][v] += E[v];
       if (J == K) {
         d4 V = {0, 0, 0, 0};  // U_I M
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
+          if (kk < kb0 || kk >= kb1) continue;
           const int k = 4 * kk + kq;
           V = mfma16(panel[(16 * I + blk_row<TL>(ia)) * LP + k], mbuf[k * LP + ia], V);
         }
@@ -203,6 +211,7 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
         d4 F2 = {0, 0, 0, 0};  // M U_J^T, rows permuted into the layout TL
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
+          if (kk < kb0 || kk >= kb1) continue;
           const int k = 4 * kk + kq;
           F2 = mfma16(mbuf[blk_row<TL>(ia) * LP + k], panel[(16 * J + ia) * LP + k], F2);
         }

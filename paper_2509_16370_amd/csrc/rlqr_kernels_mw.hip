@@ -333,20 +333,25 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   // The stage loads below are branch-free: a padding element reads the zero
   // kZeroPad. Loads issued under divergent branches, or masked right after
   // they are issued, make the compiler wait for every outstanding load.
+  // (the element's array and offset are chosen as integers: a choice between
+  // address computations is compiled to branches, one per element)
+  const uint64_t uzero = reinterpret_cast<uint64_t>(kZeroPad);
   auto load_ab = [&](double (&o)[NAB], int k) {
-    const double* A = Ag + (int64_t)k * n * n;
-    const double* B = Bg + (int64_t)k * n * m;
+    const uint64_t ua = reinterpret_cast<uint64_t>(Ag + (int64_t)k * n * n);
+    const uint64_t ub = reinterpret_cast<uint64_t>(Bg + (int64_t)k * n * m);
 #pragma unroll
     for (int t = 0; t < NAB; ++t) {
       const int e = tid + 64 * NW * t, r = e / NZ, c = e % NZ;
       const bool inA = e < NX * NZ && r < n && c < n, inB = e < NX * NZ && r < n && c >= n && c < n + m;
-      o[t] = *(inA ? A + r * n + c : (inB ? B + r * m + (c - n) : kZeroPad));
+      const int o1 = r * n + c, o2 = r * m + (c - n);
+      const int off = inA ? o1 : (inB ? o2 : 0);
+      o[t] = reinterpret_cast<const double*>(inA ? ua : (inB ? ub : uzero))[off];
     }
   };
   auto load_h = [&](double (&o)[CZ][4], int k) {
-    const double* Q = Qg + (int64_t)k * n * n;
-    const double* M = Mg + (int64_t)k * n * m;
-    const double* R = Rg + (int64_t)k * m * m;
+    const uint64_t uq0 = reinterpret_cast<uint64_t>(Qg + (int64_t)k * n * n);
+    const uint64_t um0 = reinterpret_cast<uint64_t>(Mg + (int64_t)k * n * m);
+    const uint64_t ur0 = reinterpret_cast<uint64_t>(Rg + (int64_t)k * m * m);
 #pragma unroll
     for (int t = 0; t < CZ; ++t)
 #pragma unroll
@@ -354,11 +359,12 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const int r = 16 * zi[t] + trow<TG>(grp, v), c = 16 * zj[t] + col;
         const bool rx = zo[t] && r < n, ru = zo[t] && r >= n && r < n + m;
         const bool cx = c < n, cu = c >= n && c < n + m;
-        const double* src = (rx && cx) ? Q + r * n + c
-                          : (rx && cu) ? M + r * m + (c - n)
-                          : (ru && cx) ? M + c * m + (r - n)
-                          : (ru && cu) ? R + (r - n) * m + (c - n) : kZeroPad;
-        o[t][v] = *src;
+        const bool uq = rx && cx, um = (rx && cu) || (ru && cx), ur = ru && cu;
+        // M holds the (x, u) block; the (u, x) block reads it transposed.
+        // Every candidate offset is formed first, then chosen.
+        const int o1 = r * n + c, o2 = r * m + (c - n), o3 = c * m + (r - n), o4 = (r - n) * m + (c - n);
+        const int off = uq ? o1 : ((rx && cu) ? o2 : ((ru && cx) ? o3 : (ur ? o4 : 0)));
+        o[t][v] = reinterpret_cast<const double*>(uq ? uq0 : (um ? um0 : (ur ? ur0 : uzero)))[off];
       }
   };
   auto store_ab = [&](const double (&o)[NAB]) {
@@ -1038,11 +1044,17 @@ __global__ __launch_bounds__(64 * TZ) void k_solve_col(SolveArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) R[I][v] = xt[(int64_t)(I * TX + Jx) * 256 + v * 64 + lane];
   };
-  auto ab_ptr = [&](int k, int r, int c) {  // &[A_k B_k][r][c], or the zero
-    const double* A = Ag + (int64_t)k * n * n;
-    const double* B = Bg + (int64_t)k * n * m;
+  // &[A_k B_k][r][c]; outside the n x (n+m) block the first element of A_k
+  // (any finite value does: the products below multiply such entries only by
+  // zero vector entries or write only outputs that are discarded). Integer
+  // choices only: a choice between address computations becomes a branch.
+  auto ab_ptr = [&](int k, int r, int c) {
+    const uint64_t ua = reinterpret_cast<uint64_t>(Ag + (int64_t)k * n * n);
+    const uint64_t ub = reinterpret_cast<uint64_t>(Bg + (int64_t)k * n * m);
     const bool inA = r < n && c < n, inB = r < n && c >= n && c < n + m;
-    return inA ? A + r * n + c : (inB ? B + r * m + (c - n) : kZeroPad);
+    const int o1 = r * n + c, o2 = r * m + (c - n);
+    const int off = inA ? o1 : (inB ? o2 : 0);
+    return reinterpret_cast<const double*>(inB ? ub : ua) + off;
   };
   auto load_ab = [&](double (&R)[TX][4], int k) {  // column J of [A B]
 #pragma unroll
