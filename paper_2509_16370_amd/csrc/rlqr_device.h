@@ -69,11 +69,55 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over the four 16-lane groups (lanes l, l^16, l^32, l^48).
+// gfx950's lane-permute swaps, each 32-bit half separately (old = src = x):
+// permlane16_swap gives [0] = rows (0, 0, 2, 2) and [1] = rows (1, 1, 3, 3)
+// of x (rows = 16-lane groups, same lane within the row), permlane32_swap
+// [0] = rows (0, 1, 0, 1) and [1] = rows (2, 3, 2, 3). VALU operations: no
+// LDS round trip as with ds_bpermute.
+__device__ __forceinline__ double mk_double(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ void pl16(double x, double& a, double& b) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, true, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), true, false);
+  a = mk_double(l[0], h[0]);
+  b = mk_double(l[1], h[1]);
+}
+__device__ __forceinline__ void pl32(double x, double& a, double& b) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, true, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), true, false);
+  a = mk_double(l[0], h[0]);
+  b = mk_double(l[1], h[1]);
+}
+
+// Sum over the four 16-lane groups (lanes l, l^16, l^32, l^48): (r0 + r1) +
+// (r2 + r3) in every lane, the same value a butterfly over lane xor 16, 32
+// gives (the additions commute exactly).
 __device__ __forceinline__ double group_sum(double v) {
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+  double a, b;
+  pl16(v, a, b);
+  const double s = a + b;  // rows 0, 1: r0 + r1; rows 2, 3: r2 + r3
+  pl32(s, a, b);
+  return a + b;
+}
+
+// x of row group G (lane 16 G + (lane & 15)), in every row group
+template <int G>
+__device__ __forceinline__ double group_bcast(double x) {
+  double a, b;
+  pl16(x, a, b);
+  pl32((G & 1) ? b : a, a, b);
+  return (G & 2) ? b : a;
+}
+template <int G>
+__device__ __forceinline__ float group_bcast_f(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto a = __builtin_amdgcn_permlane16_swap(u, u, true, false);
+  const unsigned y = (G & 1) ? a[1] : a[0];
+  const auto b = __builtin_amdgcn_permlane32_swap(y, y, true, false);
+  return __uint_as_float((G & 2) ? b[1] : b[0]);
 }
 
 // max that keeps a NaN (fmax drops it): residual maxima must not hide a
@@ -152,7 +196,7 @@ __device__ __forceinline__ void sweep_pivot(double (&X)[4], int lane, double tol
   constexpr int VJ = F32 ? (J & 3) : (J >> 2);
   const int col = lane & 15, grp = lane >> 4;
   const double d = lane_value(X[VJ], 16 * GJ + J);        // X[J][J]
-  const double cc = __shfl(X[VJ], 16 * GJ + col);          // X[J][col] = X[col][J]
+  const double cc = group_bcast<GJ>(X[VJ]);                // X[J][col] = X[col][J]
   double ci[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) ci[v] = row_bcast<J>(X[v]);  // X[row(v)][J]
@@ -180,7 +224,7 @@ __device__ __forceinline__ void sweep_pivot(double (&X)[4], int lane, double tol
 // The pivots met are the D entries of the unpivoted LDL^T of X_SS.
 // Every update is written so that exact symmetry is preserved bit for bit
 // (the product ci * cc is formed before the scaling). The pivot column moves
-// between lanes by DPP row broadcasts, the pivot row by one ds_bpermute; the
+// between lanes by DPP row broadcasts, the pivot row by two lane-permute swaps; the
 // pivots are counted once per sweep from a ballot.
 // code: certificate code shared by all pivots of the block. TL selects the row map.
 template <typename TL>

@@ -651,8 +651,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // ACC: correction pass (right-hand side = a.corr, z += dz); otherwise a.corr is NULL
 // DG: per-stage diagonal Delta_i (a.dd); with the stored X~ = -D S_hat^{-1} D,
 // (I + Delta P)^{-1} = -X~ Delta^{-1} and (I + P Delta)^{-1} = -Delta^{-1} X~.
-template <typename TG, int SN, int SM, bool ACC, bool DG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_solve16(SolveArgs a) {
+// WPE: wavefronts per SIMD the register budget is sized for: 4 for full
+// batches (occupancy hides the memory latency), 1 for small launches (the
+// longest instance's step chain is the launch: no spills, registers to spare).
+template <typename TG, int SN, int SM, bool ACC, bool DG, int WPE = 4>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_solve16(SolveArgs a) {
   constexpr bool CP = sizeof(TG) == 8;  // compact tiles in float64 (TileLayout)
   const int b = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
@@ -1536,8 +1539,17 @@ hipError_t launch_factor(const FactorArgs& a, int nblocks, bool fp32_products, i
   return fp32_products ? launch_factor_s<float>(a, nblocks, shape, st) : launch_factor_s<double>(a, nblocks, shape, st);
 }
 
+// fewer instances than SIMDs: the register-rich build of the generic shape
+constexpr int SOLVE16_FEW = 1024;
 template <typename TG, int SN, int SM, bool DG = false>
 static hipError_t launch_solve_t(const SolveArgs& a, int nblocks, hipStream_t st) {
+  if (SN == 0 && nblocks < SOLVE16_FEW) {
+    if (a.corr)
+      hipLaunchKernelGGL((k_solve16<TG, SN, SM, true, DG, 1>), dim3(nblocks), dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_solve16<TG, SN, SM, false, DG, 1>), dim3(nblocks), dim3(64), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.corr)
     hipLaunchKernelGGL((k_solve16<TG, SN, SM, true, DG>), dim3(nblocks), dim3(64), 0, st, a);
   else

@@ -333,25 +333,20 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   // The stage loads below are branch-free: a padding element reads the zero
   // kZeroPad. Loads issued under divergent branches, or masked right after
   // they are issued, make the compiler wait for every outstanding load.
-  // (the element's array and offset are chosen as integers: a choice between
-  // address computations is compiled to branches, one per element)
-  const uint64_t uzero = reinterpret_cast<uint64_t>(kZeroPad);
   auto load_ab = [&](double (&o)[NAB], int k) {
-    const uint64_t ua = reinterpret_cast<uint64_t>(Ag + (int64_t)k * n * n);
-    const uint64_t ub = reinterpret_cast<uint64_t>(Bg + (int64_t)k * n * m);
+    const double* A = Ag + (int64_t)k * n * n;
+    const double* B = Bg + (int64_t)k * n * m;
 #pragma unroll
     for (int t = 0; t < NAB; ++t) {
       const int e = tid + 64 * NW * t, r = e / NZ, c = e % NZ;
       const bool inA = e < NX * NZ && r < n && c < n, inB = e < NX * NZ && r < n && c >= n && c < n + m;
-      const int o1 = r * n + c, o2 = r * m + (c - n);
-      const int off = inA ? o1 : (inB ? o2 : 0);
-      o[t] = reinterpret_cast<const double*>(inA ? ua : (inB ? ub : uzero))[off];
+      o[t] = *(inA ? A + r * n + c : (inB ? B + r * m + (c - n) : kZeroPad));
     }
   };
   auto load_h = [&](double (&o)[CZ][4], int k) {
-    const uint64_t uq0 = reinterpret_cast<uint64_t>(Qg + (int64_t)k * n * n);
-    const uint64_t um0 = reinterpret_cast<uint64_t>(Mg + (int64_t)k * n * m);
-    const uint64_t ur0 = reinterpret_cast<uint64_t>(Rg + (int64_t)k * m * m);
+    const double* Q = Qg + (int64_t)k * n * n;
+    const double* M = Mg + (int64_t)k * n * m;
+    const double* R = Rg + (int64_t)k * m * m;
 #pragma unroll
     for (int t = 0; t < CZ; ++t)
 #pragma unroll
@@ -359,12 +354,11 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
         const int r = 16 * zi[t] + trow<TG>(grp, v), c = 16 * zj[t] + col;
         const bool rx = zo[t] && r < n, ru = zo[t] && r >= n && r < n + m;
         const bool cx = c < n, cu = c >= n && c < n + m;
-        const bool uq = rx && cx, um = (rx && cu) || (ru && cx), ur = ru && cu;
-        // M holds the (x, u) block; the (u, x) block reads it transposed.
-        // Every candidate offset is formed first, then chosen.
-        const int o1 = r * n + c, o2 = r * m + (c - n), o3 = c * m + (r - n), o4 = (r - n) * m + (c - n);
-        const int off = uq ? o1 : ((rx && cu) ? o2 : ((ru && cx) ? o3 : (ur ? o4 : 0)));
-        o[t][v] = reinterpret_cast<const double*>(uq ? uq0 : (um ? um0 : (ur ? ur0 : uzero)))[off];
+        const double* src = (rx && cx) ? Q + r * n + c
+                          : (rx && cu) ? M + r * m + (c - n)
+                          : (ru && cx) ? M + c * m + (r - n)
+                          : (ru && cu) ? R + (r - n) * m + (c - n) : kZeroPad;
+        o[t][v] = *src;
       }
   };
   auto store_ab = [&](const double (&o)[NAB]) {

@@ -217,12 +217,11 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
 // tile in the float32 accumulator layout (lane holds rows 4 kq + e of column
 // i): row J is scaled by 1 / D[J][J], column J eliminated from the others.
 // No pivoting (the caller's row order is a pivoting order). The pivot row
-// crosses 16-lane rows by ds_bpermute; column J stays within each 16-lane row
-// (DPP row broadcast of lane J).
+// crosses 16-lane rows by two lane-permute swaps; column J stays within each
+// 16-lane row (DPP row broadcast of lane J).
 template <int J>
 __device__ __forceinline__ void gj_pivot(float (&D)[4], float (&Di)[4], int i, int kq) {
-  const int src = 16 * (J >> 2) + i;
-  const float prD = __shfl(D[J & 3], src), prI = __shfl(Di[J & 3], src);  // row J at column i
+  const float prD = group_bcast_f<J / 4>(D[J & 3]), prI = group_bcast_f<J / 4>(Di[J & 3]);  // row J at column i
   const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prD), J));
   // 1 / d: hardware estimate and one Newton step, r + r (1 - d r)
   const float r0 = __builtin_amdgcn_rcpf(d);
