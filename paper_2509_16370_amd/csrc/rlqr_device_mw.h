@@ -112,10 +112,12 @@ __device__ __forceinline__ void sweep_mw(double (&X)[C][4], const int (&bi)[C], 
 // find), which saves that reduction's barriers.
 // TAIL = false: no barrier after the last update; the caller's next barrier
 // must come before anything is written to the panel's LDS region.
+// LEAD = false: no barrier before the first block's panel stores; every
+// earlier reader of the panel region must be behind a barrier already.
 template <typename TL>
 __device__ __forceinline__ int blk_row(int i) { return trow<TL>(i & 3, i >> 2); }
 
-template <typename TL, int C, int TT, bool TAIL = true>
+template <typename TL, int C, int TT, bool TAIL = true, bool LEAD = true>
 __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C], const int (&bj)[C],
                                           const bool (&ok)[C], int j0, int j1, int w, int lane, double* panel,
                                           double* mbuf, PivStats& ps, int code, double tol, double scale,
@@ -126,7 +128,7 @@ __device__ __forceinline__ void sweep_blk(double (&X)[C][4], const int (&bi)[C],
   for (int K = j0 >> 4; 16 * K < j1; ++K) {
     const int s0 = j0 > 16 * K ? j0 - 16 * K : 0;
     const int s1 = j1 < 16 * K + 16 ? j1 - 16 * K : 16;
-    __syncthreads();  // earlier readers of the panel / LDS region are done
+    if (LEAD || K != (j0 >> 4)) __syncthreads();  // earlier readers of the panel / LDS region are done
 #pragma unroll
     for (int t = 0; t < C; ++t)
       if (ok[t] && bj[t] == K) {

@@ -65,7 +65,13 @@ struct MwCfg {
   static constexpr bool SQ =
       TX <= 2 && (BYTES_Q > BYTES_U2 ? BYTES_Q : BYTES_U2) + (int)sizeof(TG) * NX * LDZ <= 160 * 1024;
   static constexpr int BYTES_U0 = SQ && BYTES_Q > BYTES_U2 ? BYTES_Q : BYTES_U2;
-  static constexpr int BYTES_U = (BYTES_U0 + 15) / 16 * 16;
+  // up to 48-wide states the control sweep's panel and pivot block sit after
+  // Z's symmetrization tile (the sweep's first panel stores need no barrier
+  // after its reads); the 64-wide classes keep them at the start of the work
+  // region (a second panel address costs them registers)
+  static constexpr bool CSEP = TX <= 3;
+  static constexpr int BYTES_U3 = !CSEP || BYTES_U0 > BYTES_D + BYTES_SW ? BYTES_U0 : BYTES_D + BYTES_SW;
+  static constexpr int BYTES_U = (BYTES_U3 + 15) / 16 * 16;
   // W in a tile of its own after the X tile, where the work region has room
   static constexpr bool WSEP = 2 * BYTES_P + BYTES_X <= BYTES_U;
   static constexpr int BYTES_AB = (int)sizeof(TG) * NX * LDZ;
@@ -278,6 +284,9 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   double* panel = reinterpret_cast<double*>(smem);
   double* mbuf = panel + NZ * 17;
   static_assert((NZ * 17 + 2 * 16 * 17) * 8 <= C::BYTES_U, "sweep panel exceeds the work region");
+  static_assert(C::BYTES_U + C::BYTES_AB + 8 * (2 * NW + 2 * NX) <= 160 * 1024, "LDS exceeds 160 KB");
+  double* cpanel = C::CSEP ? reinterpret_cast<double*>(smem + C::BYTES_D) : panel;  // the control sweep's
+  double* cmbuf = cpanel + NZ * 17;
 
   int tid = threadIdx.x, lane = tid & 63, col = lane & 15, grp = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
@@ -414,11 +423,14 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
   for (int k = khi - 1; k >= klo; --k) {
     lane_fence(tid, lane, col, grp);
     // (the previous stage's reads of sdl / idl are behind its barriers)
+    // Without a per-stage diagonal no barrier is needed here: nothing is
+    // stored to LDS before the state pivot's norm barrier, which also orders
+    // the previous stage's sweep reads before the stores after it.
     if constexpr (DG) {
       put_diag(dpre);
       dpre = tid < n ? ddg[(int64_t)k * n + tid] : 0.0;
+      __syncthreads();
     }
-    __syncthreads();
     load_h(H, k);  // consumed by the Z product, after the state pivot and two products
     // X = I + delta P_{k+1} (per-stage diagonal: I + D P D), swept -> -S_hat^{-1}
     double X[CX][4];
@@ -514,14 +526,16 @@ __global__ __launch_bounds__(64 * NW) void k_factor_mw(FactorArgs a) {
     lane_fence(tid, lane, col, grp);
     {
       // control pivots within one block column: wavefront 0 takes their scale
-      // from the sweep's panel; else a workgroup reduction over the tile. No
-      // barrier after the sweep: the next one is at the top of the stage (or
-      // in the state pivot after the loop), before any store to its region.
+      // from the sweep's panel; else a workgroup reduction over the tile. Up
+      // to 48-wide states the panel lies outside Z's symmetrization tile (no
+      // barrier before its first stores), and no barrier follows the sweep:
+      // the next one (the state pivot's norm, or the top of the stage with a
+      // per-stage diagonal) comes before any store to its region.
       const bool one = m > 0 && (n >> 4) == ((n + m - 1) >> 4);
       const double sc = one ? 0.0 : wg_max<NW>(diag_max<CZ, TG>(Z, zi, zj, zo, n, n + m, lane), red, w, lane);
       const double coef = 1.0e3 * m * eps;
-      sweep_blk<TG, CZ, TZ, false>(Z, zi, zj, zo, n, n + m, w, lane, panel, mbuf, ps, 2 * k + 1,
-                                   one ? coef : coef * sc, sc, one);
+      sweep_blk<TG, CZ, TZ, false, !C::CSEP>(Z, zi, zj, zo, n, n + m, w, lane, cpanel, cmbuf, ps, 2 * k + 1,
+                                             one ? coef : coef * sc, sc, one);
     }
     {
       TG* zt = ztile(k);
