@@ -482,8 +482,12 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
     }
   }
   __syncthreads();
-  // P = A1^T T1 + P1,  A = A2 Y_A,  C = A2 T2 + C2
-  float Pn[CB][4], An[CB][4], Cn[CB][4];
+  // P = A1^T T1 + P1,  A = A2 Y_A,  C = A2 T2 + C2. The new P and C go to the
+  // tiles YC and P2, which no product of this phase reads (no barrier before
+  // the stores); after one barrier every wavefront symmetrizes its blocks from
+  // them (the products keep P and C symmetric only up to rounding) and writes
+  // the accumulated element.
+  float An[CB][4];
 #pragma unroll
   for (int t = 0; t < CB; ++t) {
     const int bx = w + NW * t;
@@ -495,9 +499,9 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
-      Pn[t][v] = pa[v] + s.P1[r * LDX + c];
+      s.YC[r * LDX + c] = pa[v] + s.P1[r * LDX + c];
       An[t][v] = aa[v];
-      Cn[t][v] = ca[v] + C2g[r * NX + c];
+      s.P2[r * LDX + c] = ca[v] + C2g[r * NX + c];
     }
   }
   __syncthreads();
@@ -509,36 +513,9 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
-      s.P1[r * LDX + c] = Pn[t][v];
+      s.P1[r * LDX + c] = 0.5f * (s.YC[r * LDX + c] + s.YC[c * LDX + r]);
+      s.C1[r * LDX + c] = 0.5f * (s.P2[r * LDX + c] + s.P2[c * LDX + r]);
       s.A1[r * LDX + c] = An[t][v];
-      s.C1[r * LDX + c] = Cn[t][v];
-    }
-  }
-  __syncthreads();
-  // symmetrize P and C (the products keep them symmetric only up to rounding)
-#pragma unroll
-  for (int t = 0; t < CB; ++t) {
-    const int bx = w + NW * t;
-    if (bx >= C::NB) break;
-    const int I = bx / TX, J = bx % TX;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = arow(I, grp, v), c = 16 * J + col;
-      Pn[t][v] = 0.5f * (s.P1[r * LDX + c] + s.P1[c * LDX + r]);
-      Cn[t][v] = 0.5f * (s.C1[r * LDX + c] + s.C1[c * LDX + r]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < CB; ++t) {
-    const int bx = w + NW * t;
-    if (bx >= C::NB) break;
-    const int I = bx / TX, J = bx % TX;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = arow(I, grp, v), c = 16 * J + col;
-      s.P1[r * LDX + c] = Pn[t][v];
-      s.C1[r * LDX + c] = Cn[t][v];
     }
   }
   __syncthreads();
