@@ -167,8 +167,8 @@ struct ScanLds {
   float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
   float YA[C::TILE], YC[C::TILE];
   int invp[C::NX];  // Gauss-Jordan: right-half row r ends as row invp[r] of X^{-1}
-  int pv[16];       // Gauss-Jordan: pivot rows of the current block of columns
-  float dinv[16 * 17];  // Gauss-Jordan: D^{-1} of the current block (row stride 17)
+  int pv[2][16];         // Gauss-Jordan: pivot rows of a block of columns (by its parity)
+  float dinv[2][16 * 17];  // Gauss-Jordan: D^{-1} of a block (row stride 17, by its parity)
   float pv1[C::NX], cv1[C::NX], pv2[C::NX], cv2[C::NX], tv[C::NX], tw[C::NX];  // carried p, c
   int piv;
 };
@@ -229,13 +229,70 @@ __device__ __forceinline__ void gj_pivot(float (&D)[4], float (&Di)[4], int i, i
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const float cj = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(D[e]), 0x150 + J, 0xf, 0xf, false));
-    if (4 * kq + e == J) {
-      D[e] = prD * rd;
-      Di[e] = prI * rd;
-    } else {
-      const float f = cj * rd;
-      D[e] = fmaf(-f, prD, D[e]);
-      Di[e] = fmaf(-f, prI, Di[e]);
+    const float f = cj * rd;
+    const float dn = fmaf(-f, prD, D[e]), in = fmaf(-f, prI, Di[e]);
+    // only element J & 3 of the lanes with kq == J / 4 holds row J (a select, no branch)
+    const bool prow = e == (J & 3) && kq == J / 4;
+    D[e] = prow ? prD * rd : dn;
+    Di[e] = prow ? prI * rd : in;
+  }
+}
+
+// Gauss-Jordan inversion of the 16 x 16 tile [D | Di] (the first kn pivots;
+// FULL: kn == 16, so every pivot is taken with no run-time test and the steps
+// form one straight-line block the scheduler can interleave).
+template <bool FULL>
+__device__ __forceinline__ void gj_block(float (&D)[4], float (&Di)[4], int kn, int i, int kq) {
+#define RLQR_GJ_PIVOT(J) \
+  if (FULL || J < kn) gj_pivot<J>(D, Di, i, kq);
+  RLQR_GJ_PIVOT(0) RLQR_GJ_PIVOT(1) RLQR_GJ_PIVOT(2) RLQR_GJ_PIVOT(3) RLQR_GJ_PIVOT(4) RLQR_GJ_PIVOT(5)
+  RLQR_GJ_PIVOT(6) RLQR_GJ_PIVOT(7) RLQR_GJ_PIVOT(8) RLQR_GJ_PIVOT(9) RLQR_GJ_PIVOT(10) RLQR_GJ_PIVOT(11)
+  RLQR_GJ_PIVOT(12) RLQR_GJ_PIVOT(13) RLQR_GJ_PIVOT(14) RLQR_GJ_PIVOT(15)
+#undef RLQR_GJ_PIVOT
+}
+
+// Partial-pivoting elimination of one 16-column panel held one row per lane
+// (v; rows past the matrix are zero and never candidates): for each of the
+// first kn columns the largest unused |entry| (lowest row on ties) is the
+// pivot row p, and every other unused row subtracts its multiple of row p
+// from the later columns. used gains the pivot rows, lane j gets the pivot
+// row of column j in pl, and sing is set if a
+// column has no nonzero candidate. FULL: kn == 16 (no run-time test per column).
+template <bool FULL>
+__device__ __forceinline__ void panel_lu(float (&v)[16], int kn, int lane, unsigned long long rows,
+                                         unsigned long long& used, bool& sing, int& pl) {
+  // opaque lane index: the 16 lane tests below are made in place, not kept as
+  // loop-invariant scalar masks for the whole panel loop
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    if (FULL || jj < kn) {
+      // |entry| of a candidate as its bit pattern (ordered like the values for
+      // non-negative floats), -1 for non-candidates and NaN; the maximum over the
+      // wavefront is a DPP row reduction and a scalar max of the four rows. With
+      // no valid candidate the lowest unused row is taken.
+      const bool cand = ((rows & ~used) >> lane) & 1ull;
+      const float a = fabsf(v[jj]);
+      const int key = (cand && !__builtin_isnan(a)) ? __float_as_int(a) : -1;
+      int k = key;
+      k = max(k, __builtin_amdgcn_mov_dpp(k, 0x121, 0xf, 0xf, false));
+      k = max(k, __builtin_amdgcn_mov_dpp(k, 0x122, 0xf, 0xf, false));
+      k = max(k, __builtin_amdgcn_mov_dpp(k, 0x124, 0xf, 0xf, false));
+      k = max(k, __builtin_amdgcn_mov_dpp(k, 0x128, 0xf, 0xf, false));
+      const int best = max(max(__builtin_amdgcn_readlane(k, 0), __builtin_amdgcn_readlane(k, 16)),
+                           max(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
+      const unsigned long long bal = __ballot(best >= 0 && key == best);
+      const int p = bal ? __builtin_ctzll(bal) : __builtin_ctzll(~used & rows);
+      used |= 1ull << p;
+      sing = sing || best <= 0;
+      if (ln == jj) pl = p;
+      // the factorization only picks the rows: the hardware reciprocal will do
+      const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[jj]), p));
+      const float mlt = (best > 0 && !((used >> lane) & 1ull)) ? v[jj] * __builtin_amdgcn_rcpf(d) : 0.0f;
+#pragma unroll
+      for (int c = jj + 1; c < 16; ++c)
+        v[c] = fmaf(-mlt, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[c]), p)), v[c]);
     }
   }
 }
@@ -262,137 +319,120 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
-      s.W[r * LDW + c] = acc[v] + (r == c ? 1.0f : 0.0f);  // the identity half is built in registers below
+      s.W[r * LDW + c] = acc[v] + (r == c ? 1.0f : 0.0f);  // the identity half is written below
     }
   }
   __syncthreads();
   // Blocked Gauss-Jordan with partial pivoting on the first n pivots of
-  // M = [X | I] (W; rows are never swapped). Per block of 16 pivot columns C:
-  //  1. wavefront 0 factors the NX x 16 panel M[:, C] in registers (one row
-  //     per lane, unused rows only) with partial pivoting, which picks the
-  //     pivot rows P in order, and inverts D = M[P, C] by an in-wavefront
-  //     Gauss-Jordan elimination (no pivoting: the order of P is a pivoting
-  //     order); P and D^{-1} go to LDS;
-  //  2. every wavefront forms U_J = D^{-1} M[P, J] (MFMA) for its column
-  //     block J; rows outside P take M[i, J] - M[i, C] U_J (MFMA), rows P
-  //     take U_J.
-  // This is the same elimination as 16 single pivot steps, with three
-  // workgroup barriers per block in place of two per pivot; the serial part
-  // runs in one wavefront, which then has its SIMD to itself. At the end row
-  // p_j of the right half is row j of X^{-1}; one permutation pass puts it there.
+  // M = [X | I] (W; rows are never swapped), 16 pivot columns C_K per block K:
+  //  * wavefront 0 factors the panel M[:, C_K] in registers (one row per lane,
+  //    unused rows only) with partial pivoting, which picks the pivot rows P_K
+  //    in order, and inverts D = M[P_K, C_K] by an in-wavefront Gauss-Jordan
+  //    elimination (no pivoting: the order of P_K is a pivoting order); P_K and
+  //    D^{-1} go to LDS (two buffers, by the parity of K);
+  //  * each live column block J is then updated by one wavefront, which reads
+  //    all it needs (its own column block, the panel, P_K, D^{-1}) before it
+  //    writes: rows P_K take U_J = D^{-1} M[P_K, J] (MFMA), the other rows
+  //    M[i, J] - M[i, C_K] U_J (MFMA).
+  // This is the same elimination as 16 single pivot steps. A left-half column
+  // block is dead once it has been a panel (only the right half is read
+  // afterwards) and is not updated. Wavefront 0 updates the next panel's
+  // column block itself and factors it in the same phase (one block of
+  // lookahead), so a block takes one workgroup barrier and the serial panel
+  // overlaps the other column updates. At the end row p_j of the right half is
+  // row j of X^{-1}; one permutation pass puts it there.
   {
-    constexpr int NJ = 2 * TX;         // column blocks of M
-    constexpr int WJ = NW / NJ;        // wavefronts per column block
-    constexpr int RB = (TX + WJ - 1) / WJ;  // row blocks per wavefront (some may be past TX)
-    static_assert(WJ >= 1 && WJ * NJ == NW, "blocked Gauss-Jordan wavefront map");
-    const int J = w / WJ, i0 = w % WJ, i = lane & 15, kq = lane >> 4;
+    constexpr int NJ = 2 * TX;  // column blocks of M
+    static_assert(NJ <= NW, "one wavefront per column block");
+    const int i = lane & 15, kq = lane >> 4;
+    const int nk = (n + 15) >> 4;  // blocks of pivot columns
     for (int x = tid; x < NX * NX; x += 64 * NW) {
       const int r = x / NX, c = x % NX;
       s.W[r * LDW + NX + c] = (r == c) ? 1.0f : 0.0f;
     }
     if (tid < NX) s.invp[tid] = tid;
-    __syncthreads();
     const unsigned long long rows = NX >= 64 ? ~0ull : ((1ull << (NX & 63)) - 1ull);
     unsigned long long used = 0ull;  // pivot rows so far (wavefront 0)
     bool sing = false;
-    for (int K = 0; 16 * K < n; ++K) {
-      const int kn = min(16, n - 16 * K);
-      if (w == 0) {
-        // 1. panel factorization; rows >= NX are padding
-        float v[16];
+    for (int K = -1; K < nk; ++K) {
+      // this wavefront's column block after the pivots of block K: wavefront 0
+      // takes the next panel's, wavefront J the later left-half ones and the
+      // right half
+      int J = -1;
+      if (K >= 0) {
+        if (w == 0) J = K + 1 < nk ? K + 1 : -1;
+        else if ((w < TX && w > K + 1 && w < nk) || (w >= TX && w < NJ)) J = w;
+      }
+      if (J >= 0) {
+        const int kn = min(16, n - 16 * K), b = K & 1;
+        f4 U = {0, 0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < 16; ++c) v[c] = lane < NX ? s.W[lane * LDW + 16 * K + c] : 0.0f;
-        int pl = 0;  // lanes with (lane & 15) == j hold the pivot row of column 16 K + j
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + kq;
+          const float av = k < kn ? s.dinv[b][i * 17 + k] : 0.0f;
+          const float bv = k < kn ? s.W[s.pv[b][k] * LDW + 16 * J + i] : 0.0f;
+          U = mfma16(av, bv, U);
+        }
+        // the owned blocks M[I, J] and the A operands M[I, C_K] (k = 4 kq + kk,
+        // the order the B operand's accumulator rows come in)
+        float Mo[TX][4], La[TX][4];
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
-          if (jj < kn) {
-            // largest |candidate| (lowest row on ties); with no match (every
-            // candidate NaN) the lowest unused row, and the scan is marked singular
-            const bool cand = lane < NX && !((used >> lane) & 1ull);
-            const float a = cand ? fabsf(v[jj]) : -1.0f;
-            const float best = wave_max_f32(a);
-            const unsigned long long bal = __ballot(cand && a == best);
-            const int p = bal ? __builtin_ctzll(bal) : __builtin_ctzll(~used & rows);
-            used |= 1ull << p;
-            sing = sing || !(best > 0.0f);
-            if ((lane & 15) == jj) pl = p;
-            // the factorization only picks the rows: the hardware reciprocal will do
-            const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[jj]), p));
-            const float mlt = (best > 0.0f && !((used >> lane) & 1ull)) ? v[jj] * __builtin_amdgcn_rcpf(d) : 0.0f;
+        for (int I = 0; I < TX; ++I) {
 #pragma unroll
-            for (int c = jj + 1; c < 16; ++c)
-              v[c] = fmaf(-mlt, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[c]), p)), v[c]);
+          for (int e = 0; e < 4; ++e) {
+            Mo[I][e] = s.W[(16 * I + 4 * kq + e) * LDW + 16 * J + i];
+            La[I][e] = 4 * kq + e < kn ? s.W[(16 * I + i) * LDW + 16 * K + 4 * kq + e] : 0.0f;
           }
         }
+        int prow[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) prow[e] = s.pv[b][4 * kq + e];
+        unsigned long long cur = 0ull;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+          if (jj < kn) cur |= 1ull << s.pv[b][jj];
+#pragma unroll
+        for (int I = 0; I < TX; ++I) {
+          f4 acc = {0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) acc = mfma16(La[I][kk], U[kk], acc);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 16 * I + 4 * kq + e;
+            if (!((cur >> r) & 1ull)) s.W[r * LDW + 16 * J + i] = Mo[I][e] - acc[e];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * kq + e < kn) s.W[prow[e] * LDW + 16 * J + i] = U[e];
+      }
+      if (w == 0 && K + 1 < nk) {
+        // the panel of block K + 1 (its column block was just updated by this
+        // wavefront); rows >= NX are padding
+        const int Kp = K + 1, kn = min(16, n - 16 * Kp), b = Kp & 1;
+        float v[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = lane < NX ? s.W[lane * LDW + 16 * Kp + c] : 0.0f;
+        int pl = 0;  // lane j holds the pivot row of column 16 Kp + j
+        if (kn == 16) panel_lu<true>(v, kn, lane, rows, used, sing, pl);
+        else panel_lu<false>(v, kn, lane, rows, used, sing, pl);
         // D = M[P, C] in the accumulator layout (row 4 kq + e, column i),
         // identity past kn; [D | I] -> [I | D^{-1}]
         float D[4], Di[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int r = 4 * kq + e, pr = __shfl(pl, r);
-          D[e] = r < kn ? (i < kn ? s.W[pr * LDW + 16 * K + i] : 0.0f) : (r == i ? 1.0f : 0.0f);
+          D[e] = r < kn ? (i < kn ? s.W[pr * LDW + 16 * Kp + i] : 0.0f) : (r == i ? 1.0f : 0.0f);
           Di[e] = r == i ? 1.0f : 0.0f;
         }
-#define RLQR_GJ_PIVOT(J) \
-        if (J < kn) gj_pivot<J>(D, Di, i, kq);
-        RLQR_GJ_PIVOT(0) RLQR_GJ_PIVOT(1) RLQR_GJ_PIVOT(2) RLQR_GJ_PIVOT(3) RLQR_GJ_PIVOT(4) RLQR_GJ_PIVOT(5)
-        RLQR_GJ_PIVOT(6) RLQR_GJ_PIVOT(7) RLQR_GJ_PIVOT(8) RLQR_GJ_PIVOT(9) RLQR_GJ_PIVOT(10) RLQR_GJ_PIVOT(11)
-        RLQR_GJ_PIVOT(12) RLQR_GJ_PIVOT(13) RLQR_GJ_PIVOT(14) RLQR_GJ_PIVOT(15)
-#undef RLQR_GJ_PIVOT
+        if (kn == 16) gj_block<true>(D, Di, kn, i, kq);
+        else gj_block<false>(D, Di, kn, i, kq);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) s.dinv[(4 * kq + e) * 17 + i] = Di[e];
-        if (lane < 16) s.pv[lane] = pl;
-        if (lane < kn) s.invp[pl] = 16 * K + lane;
+        for (int e = 0; e < 4; ++e) s.dinv[b][(4 * kq + e) * 17 + i] = Di[e];
+        if (lane < 16) s.pv[b][lane] = pl;
+        if (lane < kn) s.invp[pl] = 16 * Kp + lane;
       }
-      __syncthreads();  // P and D^{-1} published
-      // 2. U_J = D^{-1} M[P, J] (rows past kn zero), the owned blocks M[I, J]
-      // and the A operands M[I, C] (k = 4 kq + kk, the order the B
-      // operand's accumulator rows come in); everything read before the barrier
-      int prow[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) prow[e] = s.pv[4 * kq + e];
-      f4 U = {0, 0, 0, 0};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int k = 4 * kk + kq;
-        const float av = k < kn ? s.dinv[i * 17 + k] : 0.0f;
-        const float bv = k < kn ? s.W[s.pv[k] * LDW + 16 * J + i] : 0.0f;
-        U = mfma16(av, bv, U);
-      }
-      float Mo[RB][4], La[RB][4];
-#pragma unroll
-      for (int t = 0; t < RB; ++t) {
-        const int I = i0 + WJ * t;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          Mo[t][e] = I < TX ? s.W[(16 * I + 4 * kq + e) * LDW + 16 * J + i] : 0.0f;
-          La[t][e] = (I < TX && 4 * kq + e < kn) ? s.W[(16 * I + i) * LDW + 16 * K + 4 * kq + e] : 0.0f;
-        }
-      }
-      unsigned long long cur = 0ull;
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj)
-        if (jj < kn) cur |= 1ull << s.pv[jj];
-      __syncthreads();  // every read of this block's M is done
-#pragma unroll
-      for (int t = 0; t < RB; ++t) {
-        const int I = i0 + WJ * t;
-        if (I >= TX) break;
-        f4 acc = {0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc = mfma16(La[t][kk], U[kk], acc);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = 16 * I + 4 * kq + e;
-          if (!((cur >> r) & 1ull)) s.W[r * LDW + 16 * J + i] = Mo[t][e] - acc[e];
-        }
-      }
-      if (i0 == 0) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (4 * kq + e < kn) s.W[prow[e] * LDW + 16 * J + i] = U[e];
-      }
-      __syncthreads();
+      __syncthreads();  // block K's columns, P_{K+1} and its D^{-1} published
     }
     if (tid == 0 && sing) s.piv = -1;
     // X^{-1}: right-half row r is row invp[r]
