@@ -167,8 +167,9 @@ struct ScanLds {
   float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
   float YA[C::TILE], YC[C::TILE];
   int invp[C::NX];  // Gauss-Jordan: right-half row r ends as row invp[r] of X^{-1}
-  int pv[2][16];         // Gauss-Jordan: pivot rows of a block of columns (by its parity)
-  float dinv[2][16 * 17];  // Gauss-Jordan: D^{-1} of a block (row stride 17, by its parity)
+  int pv[2][16];                // Gauss-Jordan: pivot rows of a block of columns (by its parity)
+  float G[2][C::NX * 17];       // Gauss-Jordan: a block's row coefficients (row stride 17, by its parity)
+  unsigned long long pm[2];     // Gauss-Jordan: the pivot rows of a block as a row mask (by its parity)
   float pv1[C::NX], cv1[C::NX], pv2[C::NX], cv2[C::NX], tv[C::NX], tw[C::NX];  // carried p, c
   int piv;
 };
@@ -213,58 +214,27 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
   }
 }
 
-// Pivot J of an in-wavefront Gauss-Jordan elimination [D | Di] over a 16 x 16
-// tile in the float32 accumulator layout (lane holds rows 4 kq + e of column
-// i): row J is scaled by 1 / D[J][J], column J eliminated from the others.
-// No pivoting (the caller's row order is a pivoting order). The pivot row
-// crosses 16-lane rows by two lane-permute swaps; column J stays within each
-// 16-lane row (DPP row broadcast of lane J).
-template <int J>
-__device__ __forceinline__ void gj_pivot(float (&D)[4], float (&Di)[4], int i, int kq) {
-  const float prD = group_bcast_f<J / 4>(D[J & 3]), prI = group_bcast_f<J / 4>(Di[J & 3]);  // row J at column i
-  const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prD), J));
-  // 1 / d: hardware estimate and one Newton step, r + r (1 - d r)
-  const float r0 = __builtin_amdgcn_rcpf(d);
-  const float rd = (d != 0.0f) ? fmaf(r0, fmaf(-d, r0, 1.0f), r0) : 0.0f;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const float cj = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(D[e]), 0x150 + J, 0xf, 0xf, false));
-    const float f = cj * rd;
-    const float dn = fmaf(-f, prD, D[e]), in = fmaf(-f, prI, Di[e]);
-    // only element J & 3 of the lanes with kq == J / 4 holds row J (a select, no branch)
-    const bool prow = e == (J & 3) && kq == J / 4;
-    D[e] = prow ? prD * rd : dn;
-    Di[e] = prow ? prI * rd : in;
-  }
-}
-
-// Gauss-Jordan inversion of the 16 x 16 tile [D | Di] (the first kn pivots;
-// FULL: kn == 16, so every pivot is taken with no run-time test and the steps
-// form one straight-line block the scheduler can interleave).
-template <bool FULL>
-__device__ __forceinline__ void gj_block(float (&D)[4], float (&Di)[4], int kn, int i, int kq) {
-#define RLQR_GJ_PIVOT(J) \
-  if (FULL || J < kn) gj_pivot<J>(D, Di, i, kq);
-  RLQR_GJ_PIVOT(0) RLQR_GJ_PIVOT(1) RLQR_GJ_PIVOT(2) RLQR_GJ_PIVOT(3) RLQR_GJ_PIVOT(4) RLQR_GJ_PIVOT(5)
-  RLQR_GJ_PIVOT(6) RLQR_GJ_PIVOT(7) RLQR_GJ_PIVOT(8) RLQR_GJ_PIVOT(9) RLQR_GJ_PIVOT(10) RLQR_GJ_PIVOT(11)
-  RLQR_GJ_PIVOT(12) RLQR_GJ_PIVOT(13) RLQR_GJ_PIVOT(14) RLQR_GJ_PIVOT(15)
-#undef RLQR_GJ_PIVOT
-}
-
-// Partial-pivoting elimination of one 16-column panel held one row per lane
-// (v; rows past the matrix are zero and never candidates): for each of the
-// first kn columns the largest unused |entry| (lowest row on ties) is the
-// pivot row p, and every other unused row subtracts its multiple of row p
-// from the later columns. used gains the pivot rows, lane j gets the pivot
-// row of column j in pl, and sing is set if a
+// Gauss-Jordan elimination with partial pivoting of one 16-column panel held
+// one row per lane (v; rows past the matrix are zero and never candidates),
+// first kn columns: for column j the largest unused |entry| (lowest row on
+// ties) is the pivot row p_j, and every other row subtracts its multiple of
+// row p_j (pivot rows are not scaled on the way). g carries each row as a
+// combination of the pivot rows' original rows: on return row l of the
+// eliminated panel matrix is (l not a pivot row of this panel ? M[l] : 0)
+// + sum_j g[j] M[p_j], which is the update every other column block takes.
+// used gains the pivot rows, lane j gets p_j in pl, and sing is set if a
 // column has no nonzero candidate. FULL: kn == 16 (no run-time test per column).
 template <bool FULL>
-__device__ __forceinline__ void panel_lu(float (&v)[16], int kn, int lane, unsigned long long rows,
+__device__ __forceinline__ void panel_gj(float (&v)[16], float (&g)[16], int kn, int lane, unsigned long long rows,
                                          unsigned long long& used, bool& sing, int& pl) {
-  // opaque lane index: the 16 lane tests below are made in place, not kept as
+  // opaque lane index: the lane tests below are made in place, not kept as
   // loop-invariant scalar masks for the whole panel loop
   int ln = lane;
   asm volatile("" : "+v"(ln));
+  const unsigned long long u0 = used;
+  float dme = 1.0f;  // a pivot row's own pivot
+#pragma unroll
+  for (int c = 0; c < 16; ++c) g[c] = 0.0f;
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) {
     if (FULL || jj < kn) {
@@ -287,13 +257,29 @@ __device__ __forceinline__ void panel_lu(float (&v)[16], int kn, int lane, unsig
       used |= 1ull << p;
       sing = sing || best <= 0;
       if (ln == jj) pl = p;
-      // the factorization only picks the rows: the hardware reciprocal will do
       const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[jj]), p));
-      const float mlt = (best > 0 && !((used >> lane) & 1ull)) ? v[jj] * __builtin_amdgcn_rcpf(d) : 0.0f;
+      // 1 / d: hardware estimate and one Newton step, r + r (1 - d r); no
+      // elimination without a nonzero pivot
+      const float r0 = __builtin_amdgcn_rcpf(d);
+      const float rd = best > 0 ? fmaf(r0, fmaf(-d, r0, 1.0f), r0) : 0.0f;
+      const bool me = ln == p;
+      if (me) dme = d;
+      const float f = me ? 0.0f : v[jj] * rd;
 #pragma unroll
       for (int c = jj + 1; c < 16; ++c)
-        v[c] = fmaf(-mlt, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[c]), p)), v[c]);
+        v[c] = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[c]), p)), v[c]);
+#pragma unroll
+      for (int c = 0; c < jj; ++c)
+        g[c] = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[c]), p)), g[c]);
+      g[jj] = me ? 1.0f : -f;
     }
+  }
+  // scale this panel's pivot rows by their pivots
+  const float r0 = __builtin_amdgcn_rcpf(dme);
+  const float rs = dme != 0.0f ? fmaf(r0, fmaf(-dme, r0, 1.0f), r0) : 0.0f;
+  if (((used & ~u0) >> lane) & 1ull) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) g[c] *= rs;
   }
 }
 
@@ -325,15 +311,13 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
   __syncthreads();
   // Blocked Gauss-Jordan with partial pivoting on the first n pivots of
   // M = [X | I] (W; rows are never swapped), 16 pivot columns C_K per block K:
-  //  * wavefront 0 factors the panel M[:, C_K] in registers (one row per lane,
-  //    unused rows only) with partial pivoting, which picks the pivot rows P_K
-  //    in order, and inverts D = M[P_K, C_K] by an in-wavefront Gauss-Jordan
-  //    elimination (no pivoting: the order of P_K is a pivoting order); P_K and
-  //    D^{-1} go to LDS (two buffers, by the parity of K);
+  //  * wavefront 0 eliminates the panel M[:, C_K] in registers (one row per
+  //    lane) with partial pivoting, which picks the pivot rows P_K in order, and
+  //    carries every row as a combination G of the rows P_K; P_K and G go to
+  //    LDS (two buffers, by the parity of K);
   //  * each live column block J is then updated by one wavefront, which reads
-  //    all it needs (its own column block, the panel, P_K, D^{-1}) before it
-  //    writes: rows P_K take U_J = D^{-1} M[P_K, J] (MFMA), the other rows
-  //    M[i, J] - M[i, C_K] U_J (MFMA).
+  //    all it needs (its own column block, P_K, G) before it writes:
+  //    M[i, J] <- (i in P_K ? 0 : M[i, J]) + G[i, :] M[P_K, J] (MFMA).
   // This is the same elimination as 16 single pivot steps. A left-half column
   // block is dead once it has been a panel (only the right half is read
   // afterwards) and is not updated. Wavefront 0 updates the next panel's
@@ -343,7 +327,9 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
   // row j of X^{-1}; one permutation pass puts it there.
   {
     constexpr int NJ = 2 * TX;  // column blocks of M
-    static_assert(NJ <= NW, "one wavefront per column block");
+    // column block J >= 1 goes to the J-th wavefront w with w % 4 != 0, so no
+    // other update shares wavefront 0's SIMD (wavefronts are dealt round-robin)
+    static_assert(NJ - 1 <= (NW - 1) - (NW - 1) / 4, "one wavefront per column block");
     const int i = lane & 15, kq = lane >> 4;
     const int nk = (n + 15) >> 4;  // blocks of pivot columns
     for (int x = tid; x < NX * NX; x += 64 * NW) {
@@ -356,83 +342,66 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
     bool sing = false;
     for (int K = -1; K < nk; ++K) {
       // this wavefront's column block after the pivots of block K: wavefront 0
-      // takes the next panel's, wavefront J the later left-half ones and the
+      // takes the next panel's, the others the later left-half ones and the
       // right half
       int J = -1;
       if (K >= 0) {
+        const int Jw = w - (w >> 2);
         if (w == 0) J = K + 1 < nk ? K + 1 : -1;
-        else if ((w < TX && w > K + 1 && w < nk) || (w >= TX && w < NJ)) J = w;
+        else if ((w & 3) && ((Jw < TX && Jw > K + 1 && Jw < nk) || (Jw >= TX && Jw < NJ))) J = Jw;
       }
       if (J >= 0) {
         const int kn = min(16, n - 16 * K), b = K & 1;
-        f4 U = {0, 0, 0, 0};
+        // B operand M[P_K, J] (k = 4 kk + kq, rows past kn zero), the owned
+        // blocks M[I, J] and the A operands G[I, :]
+        float Bv[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k = 4 * kk + kq;
-          const float av = k < kn ? s.dinv[b][i * 17 + k] : 0.0f;
-          const float bv = k < kn ? s.W[s.pv[b][k] * LDW + 16 * J + i] : 0.0f;
-          U = mfma16(av, bv, U);
+          Bv[kk] = k < kn ? s.W[s.pv[b][k] * LDW + 16 * J + i] : 0.0f;
         }
-        // the owned blocks M[I, J] and the A operands M[I, C_K] (k = 4 kq + kk,
-        // the order the B operand's accumulator rows come in)
-        float Mo[TX][4], La[TX][4];
+        float Mo[TX][4], Ga[TX][4];
 #pragma unroll
         for (int I = 0; I < TX; ++I) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             Mo[I][e] = s.W[(16 * I + 4 * kq + e) * LDW + 16 * J + i];
-            La[I][e] = 4 * kq + e < kn ? s.W[(16 * I + i) * LDW + 16 * K + 4 * kq + e] : 0.0f;
+            Ga[I][e] = s.G[b][(16 * I + i) * 17 + 4 * e + kq];
           }
         }
-        int prow[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) prow[e] = s.pv[b][4 * kq + e];
-        unsigned long long cur = 0ull;
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj)
-          if (jj < kn) cur |= 1ull << s.pv[b][jj];
+        const unsigned long long cur = s.pm[b];
 #pragma unroll
         for (int I = 0; I < TX; ++I) {
           f4 acc = {0, 0, 0, 0};
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) acc = mfma16(La[I][kk], U[kk], acc);
+          for (int kk = 0; kk < 4; ++kk) acc = mfma16(Ga[I][kk], Bv[kk], acc);
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int r = 16 * I + 4 * kq + e;
-            if (!((cur >> r) & 1ull)) s.W[r * LDW + 16 * J + i] = Mo[I][e] - acc[e];
+            s.W[r * LDW + 16 * J + i] = ((cur >> r) & 1ull) ? acc[e] : Mo[I][e] + acc[e];
           }
         }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (4 * kq + e < kn) s.W[prow[e] * LDW + 16 * J + i] = U[e];
       }
       if (w == 0 && K + 1 < nk) {
         // the panel of block K + 1 (its column block was just updated by this
         // wavefront); rows >= NX are padding
         const int Kp = K + 1, kn = min(16, n - 16 * Kp), b = Kp & 1;
-        float v[16];
+        float v[16], g[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) v[c] = lane < NX ? s.W[lane * LDW + 16 * Kp + c] : 0.0f;
         int pl = 0;  // lane j holds the pivot row of column 16 Kp + j
-        if (kn == 16) panel_lu<true>(v, kn, lane, rows, used, sing, pl);
-        else panel_lu<false>(v, kn, lane, rows, used, sing, pl);
-        // D = M[P, C] in the accumulator layout (row 4 kq + e, column i),
-        // identity past kn; [D | I] -> [I | D^{-1}]
-        float D[4], Di[4];
+        const unsigned long long u0 = used;
+        if (kn == 16) panel_gj<true>(v, g, kn, lane, rows, used, sing, pl);
+        else panel_gj<false>(v, g, kn, lane, rows, used, sing, pl);
+        if (lane < NX) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = 4 * kq + e, pr = __shfl(pl, r);
-          D[e] = r < kn ? (i < kn ? s.W[pr * LDW + 16 * Kp + i] : 0.0f) : (r == i ? 1.0f : 0.0f);
-          Di[e] = r == i ? 1.0f : 0.0f;
+          for (int c = 0; c < 16; ++c) s.G[b][lane * 17 + c] = g[c];
         }
-        if (kn == 16) gj_block<true>(D, Di, kn, i, kq);
-        else gj_block<false>(D, Di, kn, i, kq);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) s.dinv[b][(4 * kq + e) * 17 + i] = Di[e];
         if (lane < 16) s.pv[b][lane] = pl;
+        if (lane == 0) s.pm[b] = used & ~u0;
         if (lane < kn) s.invp[pl] = 16 * Kp + lane;
       }
-      __syncthreads();  // block K's columns, P_{K+1} and its D^{-1} published
+      __syncthreads();  // block K's columns, P_{K+1} and its G published
     }
     if (tid == 0 && sing) s.piv = -1;
     // X^{-1}: right-half row r is row invp[r]
