@@ -216,14 +216,15 @@ __device__ __forceinline__ void store_elem(float* __restrict__ e, const float* P
 
 // Gauss-Jordan elimination with partial pivoting of one 16-column panel held
 // one row per lane (v; rows past the matrix are zero and never candidates),
-// first kn columns: for column j the largest unused |entry| (lowest row on
-// ties) is the pivot row p_j, and every other row subtracts its multiple of
-// row p_j (pivot rows are not scaled on the way). g carries each row as a
-// combination of the pivot rows' original rows: on return row l of the
-// eliminated panel matrix is (l not a pivot row of this panel ? M[l] : 0)
-// + sum_j g[j] M[p_j], which is the update every other column block takes.
-// used gains the pivot rows, lane j gets p_j in pl, and sing is set if a
-// column has no nonzero candidate. FULL: kn == 16 (no run-time test per column).
+// first kn columns: for column j the largest unused |entry| (to a relative
+// 2^-17, lowest row among those) is the pivot row p_j, and every other row
+// subtracts its multiple of row p_j (pivot rows are not scaled on the way).
+// g carries each row as a combination of the pivot rows' original rows: on
+// return row l of the eliminated panel matrix is (l not a pivot row of this
+// panel ? M[l] : 0) + sum_j g[j] M[p_j], which is the update every other
+// column block takes. used gains the pivot rows, lane j gets p_j in pl, and
+// sing is set if a column has no nonzero candidate. FULL: kn == 16 (no
+// run-time test per column).
 template <bool FULL>
 __device__ __forceinline__ void panel_gj(float (&v)[16], float (&g)[16], int kn, int lane, unsigned long long rows,
                                          unsigned long long& used, bool& sing, int& pl) {
@@ -239,12 +240,14 @@ __device__ __forceinline__ void panel_gj(float (&v)[16], float (&g)[16], int kn,
   for (int jj = 0; jj < 16; ++jj) {
     if (FULL || jj < kn) {
       // |entry| of a candidate as its bit pattern (ordered like the values for
-      // non-negative floats), -1 for non-candidates and NaN; the maximum over the
-      // wavefront is a DPP row reduction and a scalar max of the four rows. With
-      // no valid candidate the lowest unused row is taken.
+      // non-negative floats) with the 6 low mantissa bits replaced by 63 - lane,
+      // -1 for non-candidates and NaN: the wavefront maximum (a DPP row reduction
+      // and a scalar max of the four rows) names the pivot row itself, the
+      // largest |entry| to a relative 2^-17, the lowest row among those. With no
+      // valid candidate the lowest unused row is taken.
       const bool cand = ((rows & ~used) >> lane) & 1ull;
       const float a = fabsf(v[jj]);
-      const int key = (cand && !__builtin_isnan(a)) ? __float_as_int(a) : -1;
+      const int key = (cand && !__builtin_isnan(a)) ? ((__float_as_int(a) & ~63) | (63 - lane)) : -1;
       int k = key;
       k = max(k, __builtin_amdgcn_mov_dpp(k, 0x121, 0xf, 0xf, false));
       k = max(k, __builtin_amdgcn_mov_dpp(k, 0x122, 0xf, 0xf, false));
@@ -252,16 +255,16 @@ __device__ __forceinline__ void panel_gj(float (&v)[16], float (&g)[16], int kn,
       k = max(k, __builtin_amdgcn_mov_dpp(k, 0x128, 0xf, 0xf, false));
       const int best = max(max(__builtin_amdgcn_readlane(k, 0), __builtin_amdgcn_readlane(k, 16)),
                            max(__builtin_amdgcn_readlane(k, 32), __builtin_amdgcn_readlane(k, 48)));
-      const unsigned long long bal = __ballot(best >= 0 && key == best);
-      const int p = bal ? __builtin_ctzll(bal) : __builtin_ctzll(~used & rows);
+      const bool piv = best >= 64;  // a nonzero pivot (|entry| above 64 times the smallest subnormal)
+      const int p = best >= 0 ? 63 - (best & 63) : __builtin_ctzll(~used & rows);
       used |= 1ull << p;
-      sing = sing || best <= 0;
+      sing = sing || !piv;
       if (ln == jj) pl = p;
       const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[jj]), p));
       // 1 / d: hardware estimate and one Newton step, r + r (1 - d r); no
       // elimination without a nonzero pivot
       const float r0 = __builtin_amdgcn_rcpf(d);
-      const float rd = best > 0 ? fmaf(r0, fmaf(-d, r0, 1.0f), r0) : 0.0f;
+      const float rd = piv ? fmaf(r0, fmaf(-d, r0, 1.0f), r0) : 0.0f;
       const bool me = ln == p;
       if (me) dme = d;
       const float f = me ? 0.0f : v[jj] * rd;
