@@ -156,6 +156,7 @@ struct ScanCfg {
   static constexpr int CB = (NB + NW - 1) / NW;        // blocks per wavefront
   static constexpr int TILE = NX * LDX;                // floats of an LDS tile
   static constexpr int ELEM = 3 * NX * NX;             // floats of a stored element
+  static constexpr int KE = (NX * NX + 64 * NW - 1) / (64 * NW);  // tile floats per thread
 };
 
 // LDS working set of one combine
@@ -166,7 +167,7 @@ struct ScanLds {
   float P2[C::TILE], A2[C::TILE];               // next (j -> k)
   float W[C::NX * C::LDW];                      // [X | X^{-1}], later temporaries
   float YA[C::TILE], YC[C::TILE];
-  int invp[C::NX];  // Gauss-Jordan: right-half row r ends as row invp[r] of X^{-1}
+  int xrow[C::NX];  // Gauss-Jordan: row r of X^{-1} ends as right-half row xrow[r]
   int pv[2][16];                // Gauss-Jordan: pivot rows of a block of columns (by its parity)
   float G[2][C::NX * 17];       // Gauss-Jordan: a block's row coefficients (row stride 17, by its parity)
   unsigned long long pm[2];     // Gauss-Jordan: the pivot rows of a block as a row mask (by its parity)
@@ -288,9 +289,12 @@ __device__ __forceinline__ void panel_gj(float (&v)[16], float (&g)[16], int kn,
 
 // acc (P1, A1, C1 in LDS) <- acc (+) next (P2, A2 in LDS, C2 in global).
 // pc: also the carried vectors (p1, c1) <- (+) (p2, c2), all in LDS.
+// nxt (or null): the element after next, whose P and A are read into pf
+// (the thread's share, as load_elem lays it out) while the products run.
 // Returns false if X = I + C1 P2 is singular (no pivot above tol).
 template <int TX, int NW, bool BF>
-__device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid, bool pc) {
+__device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restrict__ C2g, int n, int tid, bool pc,
+                                        const float* __restrict__ nxt, float (&pf)[2 * ScanCfg<TX, NW>::KE]) {
   // opaque thread index: in the chunk fold's loop the lane-dependent offsets
   // are re-derived in every combine instead of being hoisted out of the loop
   asm volatile("" : "+v"(tid));
@@ -326,8 +330,8 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
   // afterwards) and is not updated. Wavefront 0 updates the next panel's
   // column block itself and factors it in the same phase (one block of
   // lookahead), so a block takes one workgroup barrier and the serial panel
-  // overlaps the other column updates. At the end row p_j of the right half is
-  // row j of X^{-1}; one permutation pass puts it there.
+  // overlaps the other column updates. At the end row j of X^{-1} is the right
+  // half's row p_j (xrow), which the products read in place.
   {
     constexpr int NJ = 2 * TX;  // column blocks of M
     // column block J >= 1 goes to the J-th wavefront w with w % 4 != 0, so no
@@ -339,7 +343,7 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
       const int r = x / NX, c = x % NX;
       s.W[r * LDW + NX + c] = (r == c) ? 1.0f : 0.0f;
     }
-    if (tid < NX) s.invp[tid] = tid;
+    if (tid < NX) s.xrow[tid] = tid;
     const unsigned long long rows = NX >= 64 ? ~0ull : ((1ull << (NX & 63)) - 1ull);
     unsigned long long used = 0ull;  // pivot rows so far (wavefront 0)
     bool sing = false;
@@ -402,36 +406,33 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
         }
         if (lane < 16) s.pv[b][lane] = pl;
         if (lane == 0) s.pm[b] = used & ~u0;
-        if (lane < kn) s.invp[pl] = 16 * Kp + lane;
+        if (lane < kn) s.xrow[16 * Kp + lane] = pl;
+        if (lane == 0 && sing) s.piv = -1;
       }
       __syncthreads();  // block K's columns, P_{K+1} and its G published
     }
-    if (tid == 0 && sing) s.piv = -1;
-    // X^{-1}: right-half row r is row invp[r]
-    constexpr int KP = (NX * NX + 64 * NW - 1) / (64 * NW);
-    float tmp[KP];
-    int dst[KP];
-#pragma unroll
-    for (int q = 0; q < KP; ++q) {
-      const int x = tid + 64 * NW * q, r = x / NX, c = x % NX;
-      tmp[q] = x < NX * NX ? s.W[r * LDW + NX + c] : 0.0f;
-      dst[q] = x < NX * NX ? s.invp[r] * LDW + NX + c : -1;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < KP; ++q)
-      if (dst[q] >= 0) s.W[dst[q]] = tmp[q];
   }
-  __syncthreads();
   if (s.piv < 0) ok = false;
-  // Y_A = X^{-1} A1, Y_C = X^{-1} C1
+  if (nxt) {
+#pragma unroll
+    for (int q = 0; q < C::KE; ++q) {
+      const int x = tid + 64 * NW * q;
+      if (x < NX * NX) {
+        pf[q] = nxt[x];
+        pf[C::KE + q] = nxt[NX * NX + x];
+      }
+    }
+  }
+  // Y_A = X^{-1} A1, Y_C = X^{-1} C1; a lane reads one row of the A operand,
+  // X^{-1} row r = right-half row xrow[r], so its row base is shifted there
 #pragma unroll
   for (int t = 0; t < CB; ++t) {
     const int bx = w + NW * t;
     if (bx >= C::NB) break;
-    const int I = bx / TX, J = bx % TX;
-    f4 ya = cgemm<BF, false, TX>(s.W + NX, LDW, s.A1, LDX, I, J, lane);
-    f4 yc = cgemm<BF, false, TX>(s.W + NX, LDW, s.C1, LDX, I, J, lane);
+    const int I = bx / TX, J = bx % TX, ra = 16 * I + col;
+    const float* xa = s.W + NX + (s.xrow[ra] - ra) * LDW;
+    f4 ya = cgemm<BF, false, TX>(xa, LDW, s.A1, LDX, I, J, lane);
+    f4 yc = cgemm<BF, false, TX>(xa, LDW, s.C1, LDX, I, J, lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = arow(I, grp, v), c = 16 * J + col;
@@ -460,7 +461,7 @@ __device__ __forceinline__ bool combine(ScanLds<TX, NW>& s, const float* __restr
       pn = s.pv1[tid];
       for (int j = 0; j < n; ++j) {
         pn = fmaf(s.YA[j * LDX + tid], s.tv[j], pn);
-        wn = fmaf(s.W[tid * LDW + NX + j], s.tw[j], wn);
+        wn = fmaf(s.W[s.xrow[tid] * LDW + NX + j], s.tw[j], wn);
       }
     }
     __syncthreads();
@@ -707,14 +708,28 @@ __global__ __launch_bounds__(64 * NW) void k_scan_reduce(ScanArgs a) {
   const float* pce = pc ? a.pce + a.eoff[blockIdx.y] * 2 * C::NX : nullptr;
   load_elem<TX, NW>(s.P1, s.A1, s.C1, elems + (int64_t)e0 * C::ELEM, tid);
   if (pc) load_pc<TX, NW>(s.pv1, s.cv1, pce + (int64_t)e0 * 2 * C::NX, tid);
+  if (e0 + 1 < e1) load_elem<TX, NW>(s.P2, s.A2, nullptr, elems + (int64_t)(e0 + 1) * C::ELEM, tid);
   __syncthreads();
   bool ok = true;
+  float pf[2 * C::KE];  // P and A of the element after next, read during a combine
   for (int k = e0 + 1; k < e1; ++k) {
     const float* en = elems + (int64_t)k * C::ELEM;
-    load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
     if (pc) load_pc<TX, NW>(s.pv2, s.cv2, pce + (int64_t)k * 2 * C::NX, tid);
     __syncthreads();
-    ok &= combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid, pc);
+    const bool more = k + 1 < e1;
+    ok &= combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid, pc, more ? en + C::ELEM : nullptr, pf);
+    if (more) {
+      // the combine has ended with a barrier: P2 and A2 are free
+#pragma unroll
+      for (int q = 0; q < C::KE; ++q) {
+        const int x = tid + 64 * NW * q;
+        if (x < C::NX * C::NX) {
+          const int r = x / C::NX, c = x % C::NX;
+          s.P2[r * C::LDX + c] = pf[q];
+          s.A2[r * C::LDX + c] = pf[C::KE + q];
+        }
+      }
+    }
   }
   store_elem<TX, NW>(a.aggr_out + (a.aoff[blockIdx.y] + c) * C::ELEM, s.P1, s.A1, s.C1, tid);
   if (pc) store_pc<TX, NW>(a.pca_out + (a.aoff[blockIdx.y] + c) * 2 * C::NX, s.pv1, s.cv1, tid);
@@ -748,7 +763,8 @@ __global__ __launch_bounds__(64 * NW) void k_scan_level(ScanArgs a) {
     load_elem<TX, NW>(s.P2, s.A2, nullptr, en, tid);
     if (pc) load_pc<TX, NW>(s.pv2, s.cv2, pin + (int64_t)(c + d) * 2 * C::NX, tid);
     __syncthreads();
-    if (!combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid, pc) && tid == 0) a.bad[b] = 1;
+    float pf[2 * C::KE];
+    if (!combine<TX, NW, BF>(s, en + 2 * C::NX * C::NX, n, tid, pc, nullptr, pf) && tid == 0) a.bad[b] = 1;
   }
   store_elem<TX, NW>(out + (int64_t)c * C::ELEM, s.P1, s.A1, s.C1, tid);
   if (pc) store_pc<TX, NW>(a.pca_out + a.aoff[blockIdx.y] * 2 * C::NX + (int64_t)c * 2 * C::NX, s.pv1, s.cv1, tid);
