@@ -925,39 +925,70 @@ __global__ __launch_bounds__(64 * NW) void k_transfer(TransferArgs a) {
   }
   for (int x = tid; x < NZ * LX; x += 64 * NW) sK[x] = 0.0f;
   for (int x = tid; x < NX * LZ; x += 64 * NW) sAB[x] = 0.0f;
-  __syncthreads();
-  for (int k = sd.lo; k < sd.hi; ++k) {
-    // K_k = -(Z_k)_ux from the (u, x) entries of the stage tile
+  // A stage's operands are read into registers (this thread's share) while
+  // the previous stage's products run, and written to LDS after them:
+  // K_k = -(Z_k)_ux from the (u, x) entries of the stage tile, X_{k+1}
+  // (scaled by the stage diagonal when there is one), [A_k B_k].
+  constexpr int KZ = (TZ * TZ * 256 + 64 * NW - 1) / (64 * NW);
+  constexpr int KX = (TX * TX * 256 + 64 * NW - 1) / (64 * NW);
+  constexpr int KAB = (NX * NZ + 64 * NW - 1) / (64 * NW);
+  float rz[KZ], rx[KX];
+  double rd[KX], rab[KAB];
+  auto fetch = [&](int k) {
     const float* zt = ws + (int64_t)k * STAGE;
-    for (int x = tid; x < TZ * TZ * 256; x += 64 * NW) {
-      const int bz = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
-      int I, J;
-      zmap<TX, TZ>(bz, I, J);
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+      const int x = tid + 64 * NW * q, bz = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+      int I = 0, J = 0;
+      if (x < TZ * TZ * 256) zmap<TX, TZ>(bz, I, J);
       const int r = 16 * I + 4 * (l >> 4) + v, c = 16 * J + (l & 15);
-      if (r >= n && r < n + m && c < n) sK[r * LX + c] = -zt[x];
+      rz[q] = (x < TZ * TZ * 256 && r >= n && r < n + m && c < n) ? zt[x] : 0.0f;
     }
     const float* xt = ws + (int64_t)(k + 1) * STAGE + TZ * TZ * 256;
-    if (a.dd) {
-      const double* dn = a.dd + mt.od + (int64_t)(k + 1) * n;
-      for (int x = tid; x < TX * TX * 256; x += 64 * NW) {
-        const int bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
-        const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
-        sX[r * LX + c] = (r < n && c < n) ? (float)((double)xt[x] / dn[c]) : 0.0f;
-      }
-    } else {
-      for (int x = tid; x < TX * TX * 256; x += 64 * NW) {
-        const int bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
-        const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
-        sX[r * LX + c] = (r < n && c < n) ? xt[x] : 0.0f;
-      }
+    const double* dn = a.dd ? a.dd + mt.od + (int64_t)(k + 1) * n : nullptr;
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+      const int x = tid + 64 * NW * q, bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+      const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
+      const bool in = x < TX * TX * 256 && r < n && c < n;
+      rx[q] = in ? xt[x] : 0.0f;
+      rd[q] = in && dn ? dn[c] : 1.0;
     }
     const double* A = Ag + (int64_t)k * n * n;
     const double* B = Bg + (int64_t)k * n * m;
-    for (int x = tid; x < n * (n + m); x += 64 * NW) {
-      const int r = x / (n + m), c = x % (n + m);
-      sAB[r * LZ + c] = (float)(c < n ? A[r * n + c] : B[r * m + (c - n)]);
+#pragma unroll
+    for (int q = 0; q < KAB; ++q) {
+      const int x = tid + 64 * NW * q, r = x / (n + m), c = x % (n + m);
+      rab[q] = x < n * (n + m) ? (c < n ? A[r * n + c] : B[r * m + (c - n)]) : 0.0;
     }
-    __syncthreads();
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+      const int x = tid + 64 * NW * q, bz = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+      int I = 0, J = 0;
+      if (x < TZ * TZ * 256) zmap<TX, TZ>(bz, I, J);
+      const int r = 16 * I + 4 * (l >> 4) + v, c = 16 * J + (l & 15);
+      if (x < TZ * TZ * 256 && r >= n && r < n + m && c < n) sK[r * LX + c] = -rz[q];
+    }
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+      const int x = tid + 64 * NW * q, bx = x >> 8, e = x & 255, v = e >> 6, l = e & 63;
+      const int r = 16 * (bx / TX) + 4 * (l >> 4) + v, c = 16 * (bx % TX) + (l & 15);
+      if (x < TX * TX * 256) sX[r * LX + c] = a.dd ? (float)((double)rx[q] / rd[q]) : rx[q];
+    }
+#pragma unroll
+    for (int q = 0; q < KAB; ++q) {
+      const int x = tid + 64 * NW * q, r = x / (n + m), c = x % (n + m);
+      if (x < n * (n + m)) sAB[r * LZ + c] = (float)rab[q];
+    }
+  };
+  __syncthreads();  // the zero fills are done before any operand lands
+  fetch(sd.lo);
+  store();
+  for (int k = sd.lo; k < sd.hi; ++k) {
+    __syncthreads();  // stage k's operands in LDS
+    if (k + 1 < sd.hi) fetch(k + 1);
     // V = K Psi (rows n .. n+m-1) + Psi (rows < n)
 #pragma unroll
     for (int t = 0; t < CV; ++t) {
@@ -994,6 +1025,7 @@ __global__ __launch_bounds__(64 * NW) void k_transfer(TransferArgs a) {
       for (int v = 0; v < 4; ++v) sPsi[arow(I, grp, v) * LX + 16 * J + col] = -acc[v];
     }
     __syncthreads();
+    if (k + 1 < sd.hi) store();  // every reader of sK, sX, sAB has passed the barrier
   }
   double* out = a.psi + mt.opsi + (int64_t)sd.s * 2 * n * n;
   for (int x = tid; x < n * n; x += 64 * NW) {
